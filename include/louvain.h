@@ -1,0 +1,218 @@
+/*
+ * louvain.h -- C ABI of the MI355X (gfx950) synchronous parallel Louvain
+ * library (R. Forster, "Parallel Louvain Community Detection Optimized for
+ * GPUs", arXiv 1805.10904).
+ *
+ * Graph model (paper, Section 2 "Problem statement and notation"):
+ *   G(V, E, w) is undirected with positive integer weights, loops allowed,
+ *   no multi-edges.  It is passed as a symmetric CSR adjacency matrix A:
+ *   row i lists the neighbours j of i with A_ij; an edge {i, j}, i != j,
+ *   appears in rows i and j with the same weight; a loop appears once, as
+ *   A_ii.  delta_i = sum_j A_ij, TW = 2W = sum_i delta_i.
+ *   Communities are labelled by vertex IDs in [0, n).
+ *
+ * Modularity (eq. 3) is reported exactly as the 128-bit integer
+ *   Q_int = TW^2 * Q = TW * sum_i e_{i->C(i)} - sum_C deg_C^2
+ * (e_{i->C} from eq. 1 including loops, deg_C from eq. 2), and as a double.
+ *
+ * Conventions for every call:
+ *   - Return value: LOUVAIN_OK (0) or a negative LOUVAIN_E* status.  On an
+ *     error the caller's output buffers are left untouched, nothing leaks,
+ *     and louvain_last_error(ctx) describes the failure.  No call aborts.
+ *   - Pointer arguments marked "host or device" are device pointers when
+ *     LOUVAIN_DEVICE_PTRS is set in `flags`, host pointers otherwise.
+ *     Device pointers must be device memory of the context's device.
+ *   - All device work is enqueued on the context's HIP stream; a call
+ *     returns after its outputs are complete (host outputs copied back,
+ *     device outputs written, stream synchronised).
+ *   - A context is not thread-safe: use one context per host thread.
+ */
+#ifndef LOUVAIN_H
+#define LOUVAIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define LOUVAIN_OK         0
+#define LOUVAIN_EINVAL    (-1)  /* invalid argument or malformed graph          */
+#define LOUVAIN_ENOMEM    (-2)  /* device or host allocation failed             */
+#define LOUVAIN_EDEVICE   (-3)  /* HIP runtime error                            */
+#define LOUVAIN_ELIMIT    (-6)  /* max_sweeps / max_levels reached; result valid */
+#define LOUVAIN_EOVERFLOW (-7)  /* n >= 2^31 or TW >= 2^62                      */
+
+/* flags */
+#define LOUVAIN_DEVICE_PTRS    0x1u  /* pointer arguments are device pointers        */
+#define LOUVAIN_CHECK_SYMMETRY 0x2u  /* graph_create: also verify A_ij == A_ji       */
+#define LOUVAIN_NO_SINGLET     0x4u  /* local_move: disable the singlet minimum-label
+                                        heuristic (paper Section 3.1.1)               */
+#define LOUVAIN_WEIGHTS_I64    0x8u  /* graph_create: weights are int64 (else int32) */
+
+typedef struct louvain_ctx_s *louvain_ctx;
+typedef struct louvain_graph_s *louvain_graph;
+
+/* 128-bit two's-complement integer as two words. */
+typedef struct {
+    uint64_t lo;
+    int64_t hi;
+} louvain_i128;
+
+/* Parameters of louvain_run (Alg. 2 driving Alg. 1 phases). */
+typedef struct {
+    int64_t theta_num;     /* a sweep is kept iff                                   */
+    int64_t theta_den;     /*   theta_den*(Q_new-Q_prev) > theta_num*|Q_prev|      */
+                           /* (Alg. 1's relative threshold theta, exact); default 1/10^6 */
+    int32_t max_sweeps;    /* kept sweeps per phase, default 1000                   */
+    int32_t max_levels;    /* phases (dendrogram levels), default 64                */
+    int32_t singlet_rule;  /* 1 = singlet minimum-label heuristic on (default)      */
+    int32_t pass_batch;    /* sweep passes enqueued between host checks of the
+                              device's convergence flag (0 = library default);
+                              passes past the end of a phase exit at once      */
+} louvain_params;
+
+/* Per-level record filled by louvain_run. */
+typedef struct {
+    int64_t n, nnz;               /* the level's graph                                   */
+    int32_t sweeps_executed;      /* sweeps of the method incl. the final discarded one   */
+    int32_t sweeps_accepted;      /* sweeps kept                                          */
+    int32_t gpu_passes;           /* sweep passes the device ran for this phase           */
+    int32_t reserved;
+    louvain_i128 q_int;           /* Q_int after the phase, on this level's graph         */
+    double ms_sweep;              /* device time of the phase's sweep kernels (stats mode) */
+    double ms_contract;           /* device time of renumber + contraction (stats mode)    */
+} louvain_level_stats;
+
+#define LOUVAIN_MAX_KERNEL_STATS 24
+
+/* Per-kernel device-time record (stats mode): one per kernel family. */
+typedef struct {
+    char name[40];
+    int64_t launches;
+    double ms;                    /* summed device time (HIP events around each launch)   */
+    double alg_bytes;             /* summed algorithmic HBM bytes of those launches        */
+} louvain_kernel_stats;
+
+/* Statistics of a run.  Set `timing` to 1 before the call to record
+ * per-kernel device times with HIP events (adds a little overhead). */
+typedef struct {
+    int32_t timing;               /* in: 1 = record kernel times                          */
+    int32_t levels;               /* out: phases executed                                  */
+    int32_t status;               /* out: LOUVAIN_OK or LOUVAIN_ELIMIT                     */
+    int32_t n_kernels;            /* out: entries used in kernels[]                        */
+    int64_t total_edges_swept;    /* out: sum over device passes of the level's nnz        */
+    double ms_total;              /* out: device time of the whole run (stats mode)        */
+    louvain_level_stats level[64];
+    louvain_kernel_stats kernels[LOUVAIN_MAX_KERNEL_STATS];
+} louvain_run_stats;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device` that enqueues its work on
+ * `hip_stream` (a hipStream_t; NULL = the null stream).  The stream must
+ * outlive the context.  *out receives the handle. */
+int louvain_ctx_create(int device, void *hip_stream, louvain_ctx *out);
+int louvain_ctx_destroy(louvain_ctx ctx);
+
+/* Message of the last failed call on ctx (never NULL; "" if none).  The
+ * string is owned by ctx and valid until the next call on it. */
+const char *louvain_last_error(louvain_ctx ctx);
+
+/* ---- graphs --------------------------------------------------------------- */
+
+/*
+ * Copy a symmetric CSR graph into device memory owned by the library,
+ * validate it, and compute delta_i and TW (paper Section 2).
+ *   row_ptr: int64[n+1], host or device; row_ptr[0] == 0, nondecreasing,
+ *            row_ptr[n] == nnz.
+ *   col_idx: int32[nnz], host or device; every column in [0, n) and strictly
+ *            ascending inside a row (no multi-edges).
+ *   weight:  int32[nnz] (int64 with LOUVAIN_WEIGHTS_I64), host or device;
+ *            every weight >= 1 (an unweighted graph uses weight 1).
+ *   flags:   LOUVAIN_DEVICE_PTRS, LOUVAIN_CHECK_SYMMETRY, LOUVAIN_WEIGHTS_I64.
+ * The inputs are copied; the caller may release them on return.
+ * Errors: EINVAL (malformed CSR, weight < 1, asymmetric with
+ * CHECK_SYMMETRY), EOVERFLOW (n >= 2^31, nnz >= 2^40 or TW >= 2^62),
+ * ENOMEM, EDEVICE.
+ */
+int louvain_graph_create(louvain_ctx ctx, int64_t n, int64_t nnz, const int64_t *row_ptr,
+                         const int32_t *col_idx, const void *weight, uint32_t flags,
+                         louvain_graph *out);
+int louvain_graph_destroy(louvain_graph g);
+
+/* n, nnz and TW = 2W of a graph (any pointer may be NULL). */
+int louvain_graph_info(louvain_graph g, int64_t *n, int64_t *nnz, int64_t *total_weight);
+
+/* Copy a graph out as CSR with int64 weights (host or device pointers per
+ * flags): row_ptr int64[n+1], col_idx int32[nnz], weight int64[nnz]. */
+int louvain_graph_export(louvain_graph g, int64_t *row_ptr, int32_t *col_idx, int64_t *weight,
+                         uint32_t flags);
+
+/* ---- the method's steps ------------------------------------------------------ */
+
+/*
+ * One synchronous local-moving sweep (the parallel loop of Alg. 1; gains
+ * of eq. 4 compared as exact integers, argmax of eq. 5, minimum-label
+ * heuristics of Section 3.1).  Every vertex decides from labels_in and the
+ * community degrees and sizes of labels_in; loops do not enter the move
+ * scores.
+ *   labels_in:  int32[n] in [0, n), host or device; NULL = singletons.
+ *   labels_out: int32[n], host or device: every vertex's new community.
+ *   deg_c_out:  optional int64[n], host or device: deg_C of labels_out
+ *               (eq. 2), indexed by label.
+ *   e_own_out:  optional int64[n], host or device: e_{i->labels_in[i]}
+ *               (eq. 1) including i's loop.
+ *   flags:      LOUVAIN_DEVICE_PTRS, LOUVAIN_NO_SINGLET.
+ * Errors: EINVAL (NULL graph or output, label out of range), ENOMEM, EDEVICE.
+ */
+int louvain_local_move(louvain_ctx ctx, louvain_graph g, const int32_t *labels_in,
+                       int32_t *labels_out, int64_t *deg_c_out, int64_t *e_own_out,
+                       uint32_t flags);
+
+/* Modularity of a labelling (eq. 3): labels int32[n] in [0, n), host or
+ * device per flags.  q_int receives TW^2*Q exactly, q (optional) the double
+ * Q_int / TW^2 (0 when TW == 0). */
+int louvain_modularity(louvain_ctx ctx, louvain_graph g, const int32_t *labels,
+                       louvain_i128 *q_int, double *q, uint32_t flags);
+
+/*
+ * Renumbering and graph rebuilding (Section 5.1, "Renumbering nodes" and
+ * "Inducing new graph"): community labels are mapped to consecutive IDs in
+ * ascending label order, and the graph is contracted so that super-vertex a
+ * holds A'_ab = sum of A_ij over members i of a and j of b (loops included;
+ * a super-vertex's loop counts each internal edge in both directions).  The
+ * result has ascending columns in every row and int64 weights.
+ *   labels:       int32[n] in [0, n), host or device.
+ *   renumber_out: optional int32[n], host or device: new ID of each vertex's
+ *                 community.
+ *   out:          receives a new graph handle owned by the caller.
+ * Errors: EINVAL, ENOMEM, EDEVICE.
+ */
+int louvain_aggregate(louvain_ctx ctx, louvain_graph g, const int32_t *labels,
+                      int32_t *renumber_out, louvain_graph *out, uint32_t flags);
+
+/*
+ * The whole method (Alg. 2 over Alg. 1 phases) on device-resident state:
+ * per phase, singleton initialisation, synchronous sweeps kept while the
+ * exact relative gain test passes, then renumbering and contraction; stop
+ * after a phase that keeps no sweep.
+ *   params:     NULL = defaults (theta 1/10^6, 1000 sweeps, 64 levels,
+ *               singlet rule on).
+ *   labels_out: int32[n], host or device: final dense community IDs.
+ *   q_int, q:   optional: modularity of the final partition on g.
+ *   stats:      optional run statistics (see louvain_run_stats).
+ * Returns LOUVAIN_OK, LOUVAIN_ELIMIT (a cap cut the run short; outputs are
+ * valid), or an error (outputs untouched).
+ */
+int louvain_run(louvain_ctx ctx, louvain_graph g, const louvain_params *params,
+                int32_t *labels_out, louvain_i128 *q_int, double *q,
+                louvain_run_stats *stats, uint32_t flags);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LOUVAIN_H */

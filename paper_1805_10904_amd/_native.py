@@ -1,0 +1,306 @@
+"""ctypes binding of the C ABI in include/louvain.h (marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import NamedTuple, Optional
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblouvain_hip.so")
+
+LOUVAIN_OK = 0
+LOUVAIN_EINVAL = -1
+LOUVAIN_ENOMEM = -2
+LOUVAIN_EDEVICE = -3
+LOUVAIN_ELIMIT = -6
+LOUVAIN_EOVERFLOW = -7
+
+LOUVAIN_DEVICE_PTRS = 0x1
+LOUVAIN_CHECK_SYMMETRY = 0x2
+LOUVAIN_NO_SINGLET = 0x4
+LOUVAIN_WEIGHTS_I64 = 0x8
+
+# Every symbol the header declares (checked by the CPU test-suite).
+ABI_SYMBOLS = (
+    "louvain_ctx_create", "louvain_ctx_destroy", "louvain_last_error",
+    "louvain_graph_create", "louvain_graph_destroy", "louvain_graph_info", "louvain_graph_export",
+    "louvain_local_move", "louvain_modularity", "louvain_aggregate", "louvain_run",
+)
+
+
+class louvain_i128(C.Structure):
+    _fields_ = [("lo", C.c_uint64), ("hi", C.c_int64)]
+
+    def value(self) -> int:
+        return (int(self.hi) << 64) | int(self.lo)
+
+
+class louvain_params(C.Structure):
+    _fields_ = [("theta_num", C.c_int64), ("theta_den", C.c_int64), ("max_sweeps", C.c_int32),
+                ("max_levels", C.c_int32), ("singlet_rule", C.c_int32), ("pass_batch", C.c_int32)]
+
+
+class louvain_level_stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("sweeps_executed", C.c_int32),
+                ("sweeps_accepted", C.c_int32), ("gpu_passes", C.c_int32), ("reserved", C.c_int32),
+                ("q_int", louvain_i128), ("ms_sweep", C.c_double), ("ms_contract", C.c_double)]
+
+
+class louvain_kernel_stats(C.Structure):
+    _fields_ = [("name", C.c_char * 40), ("launches", C.c_int64), ("ms", C.c_double),
+                ("alg_bytes", C.c_double)]
+
+
+class louvain_run_stats(C.Structure):
+    _fields_ = [("timing", C.c_int32), ("levels", C.c_int32), ("status", C.c_int32),
+                ("n_kernels", C.c_int32), ("total_edges_swept", C.c_int64), ("ms_total", C.c_double),
+                ("level", louvain_level_stats * 64), ("kernels", louvain_kernel_stats * 24)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing "
+                           "(run paper_1805_10904_amd/build.py or __graft_entry__.build())")
+    lib = C.CDLL(path)
+    p, i64, u32, i32 = C.c_void_p, C.c_int64, C.c_uint32, C.c_int
+    lib.louvain_ctx_create.argtypes = [i32, p, C.POINTER(p)]
+    lib.louvain_ctx_destroy.argtypes = [p]
+    lib.louvain_last_error.argtypes = [p]
+    lib.louvain_last_error.restype = C.c_char_p
+    lib.louvain_graph_create.argtypes = [p, i64, i64, p, p, p, u32, C.POINTER(p)]
+    lib.louvain_graph_destroy.argtypes = [p]
+    lib.louvain_graph_info.argtypes = [p, p, p, p]
+    lib.louvain_graph_export.argtypes = [p, p, p, p, u32]
+    lib.louvain_local_move.argtypes = [p, p, p, p, p, p, u32]
+    lib.louvain_modularity.argtypes = [p, p, p, C.POINTER(louvain_i128), p, u32]
+    lib.louvain_aggregate.argtypes = [p, p, p, p, C.POINTER(p), u32]
+    lib.louvain_run.argtypes = [p, p, C.POINTER(louvain_params), p, C.POINTER(louvain_i128), p,
+                                C.POINTER(louvain_run_stats), u32]
+    for f in ABI_SYMBOLS:
+        if f != "louvain_last_error":
+            getattr(lib, f).restype = C.c_int
+    if path == LIB_PATH:
+        _lib = lib
+    return lib
+
+
+def exported_symbols(path: str = LIB_PATH):
+    """Names of the ABI functions the library exports (via the dynamic loader)."""
+    lib = C.CDLL(path)
+    return [f for f in ABI_SYMBOLS if hasattr(lib, f)]
+
+
+class LouvainError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"louvain error {code}: {msg}")
+        self.code = code
+
+
+# ------------------------------------------------------------- marshalling --
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if _is_torch(x):
+        return C.c_void_p(x.data_ptr())
+    return x.ctypes.data_as(C.c_void_p)
+
+
+def _host(x, dtype):
+    return np.ascontiguousarray(x, dtype=dtype)
+
+
+def _empty_like_kind(ref_is_dev, n, dtype_np, device=None):
+    if ref_is_dev:
+        import torch
+        tdt = {np.int32: torch.int32, np.int64: torch.int64}[dtype_np]
+        return torch.empty(max(n, 0), dtype=tdt, device=device)
+    return np.empty(max(n, 0), dtype=dtype_np)
+
+
+class RunResult(NamedTuple):
+    labels: object       # int32[n] final dense community IDs (numpy or torch)
+    q_int: int           # TW^2 * Q, exact
+    q: float
+    status: int          # LOUVAIN_OK or LOUVAIN_ELIMIT
+    stats: dict
+
+
+class Graph:
+    """A device-resident graph handle (louvain_graph)."""
+
+    def __init__(self, ctx: "Context", handle: C.c_void_p, device_kind: bool):
+        self.ctx = ctx
+        self.h = handle
+        self.dev = device_kind
+
+    def info(self):
+        n, m, tw = C.c_int64(), C.c_int64(), C.c_int64()
+        self.ctx._check(self.ctx.lib.louvain_graph_info(self.h, C.byref(n), C.byref(m), C.byref(tw)))
+        return n.value, m.value, tw.value
+
+    def export(self, device: bool = False):
+        n, m, _ = self.info()
+        rp = _empty_like_kind(device, n + 1, np.int64, self.ctx.torch_device)
+        col = _empty_like_kind(device, m, np.int32, self.ctx.torch_device)
+        w = _empty_like_kind(device, m, np.int64, self.ctx.torch_device)
+        self.ctx._check(self.ctx.lib.louvain_graph_export(
+            self.h, _ptr(rp), _ptr(col), _ptr(w), LOUVAIN_DEVICE_PTRS if device else 0))
+        return rp, col, w
+
+    def destroy(self):
+        if self.h:
+            self.ctx.lib.louvain_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Context:
+    """A louvain_ctx on one HIP device, enqueuing on the given stream handle
+    (default: torch's current stream on that device when torch has a GPU,
+    else the null stream)."""
+
+    def __init__(self, device: int = 0, stream: Optional[int] = None):
+        self.lib = load_library()
+        self.device = device
+        self.torch_device = None
+        try:
+            import torch
+            self.torch_device = torch.device("cuda", device)
+            if stream is None and torch.cuda.is_available():
+                stream = torch.cuda.current_stream(self.torch_device).cuda_stream
+        except ImportError:
+            pass
+        h = C.c_void_p()
+        rc = self.lib.louvain_ctx_create(device, C.c_void_p(stream or 0), C.byref(h))
+        if rc != LOUVAIN_OK:
+            raise LouvainError(rc, "louvain_ctx_create failed")
+        self.h = h
+
+    def _check(self, rc: int, ok=(LOUVAIN_OK,)):
+        if rc not in ok:
+            msg = self.lib.louvain_last_error(self.h)
+            raise LouvainError(rc, msg.decode() if msg else "")
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.louvain_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- calls ---------------------------------------------------------------
+
+    def graph_create(self, row_ptr, col, w, check_symmetry: bool = False) -> Graph:
+        dev = _is_torch(row_ptr) and row_ptr.is_cuda
+        if dev:
+            n = row_ptr.shape[0] - 1
+            nnz = col.shape[0]
+            wide = str(w.dtype) == "torch.int64"
+            keep = (row_ptr, col, w)
+        else:
+            row_ptr = _host(row_ptr, np.int64)
+            col = _host(col, np.int32)
+            wide = np.asarray(w).dtype == np.int64
+            w = _host(w, np.int64 if wide else np.int32)
+            n = row_ptr.shape[0] - 1
+            nnz = col.shape[0]
+            keep = (row_ptr, col, w)
+        flags = (LOUVAIN_DEVICE_PTRS if dev else 0) | (LOUVAIN_CHECK_SYMMETRY if check_symmetry else 0) \
+            | (LOUVAIN_WEIGHTS_I64 if wide else 0)
+        h = C.c_void_p()
+        self._check(self.lib.louvain_graph_create(self.h, n, nnz, _ptr(keep[0]), _ptr(keep[1]),
+                                                  _ptr(keep[2]), flags, C.byref(h)))
+        return Graph(self, h, dev)
+
+    def _labels(self, labels, dev):
+        if labels is None:
+            return None
+        return labels if dev else _host(labels, np.int32)
+
+    def local_move(self, g: Graph, labels=None, singlet_rule: bool = True, device: Optional[bool] = None):
+        """One synchronous sweep: (labels_out, deg_C of labels_out, e_own)."""
+        dev = g.dev if device is None else device
+        n, _, _ = g.info()
+        lab = self._labels(labels, dev)
+        out = _empty_like_kind(dev, n, np.int32, self.torch_device)
+        deg = _empty_like_kind(dev, n, np.int64, self.torch_device)
+        eown = _empty_like_kind(dev, n, np.int64, self.torch_device)
+        flags = (LOUVAIN_DEVICE_PTRS if dev else 0) | (0 if singlet_rule else LOUVAIN_NO_SINGLET)
+        self._check(self.lib.louvain_local_move(self.h, g.h, _ptr(lab), _ptr(out), _ptr(deg), _ptr(eown), flags))
+        return out, deg, eown
+
+    def modularity(self, g: Graph, labels, device: Optional[bool] = None):
+        """(Q_int, Q) of a labelling (eq. 3)."""
+        dev = g.dev if device is None else device
+        lab = self._labels(labels, dev)
+        qi = louvain_i128()
+        q = C.c_double()
+        self._check(self.lib.louvain_modularity(self.h, g.h, _ptr(lab), C.byref(qi), C.byref(q),
+                                                LOUVAIN_DEVICE_PTRS if dev else 0))
+        return qi.value(), q.value
+
+    def aggregate(self, g: Graph, labels, device: Optional[bool] = None):
+        """(contracted Graph, renumbered community of every vertex)."""
+        dev = g.dev if device is None else device
+        n, _, _ = g.info()
+        lab = self._labels(labels, dev)
+        ren = _empty_like_kind(dev, n, np.int32, self.torch_device)
+        h = C.c_void_p()
+        self._check(self.lib.louvain_aggregate(self.h, g.h, _ptr(lab), _ptr(ren), C.byref(h),
+                                               LOUVAIN_DEVICE_PTRS if dev else 0))
+        return Graph(self, h, dev), ren
+
+    def run(self, g: Graph, theta_num: int = 1, theta_den: int = 1_000_000, max_sweeps: int = 1000,
+            max_levels: int = 64, singlet_rule: bool = True, pass_batch: int = 0, timing: bool = False,
+            device: Optional[bool] = None, labels_out=None) -> RunResult:
+        """The whole method (Alg. 2 over Alg. 1 phases)."""
+        dev = g.dev if device is None else device
+        n, _, _ = g.info()
+        out = labels_out if labels_out is not None else _empty_like_kind(dev, n, np.int32, self.torch_device)
+        prm = louvain_params(theta_num, theta_den, max_sweeps, max_levels, 1 if singlet_rule else 0, pass_batch)
+        qi = louvain_i128()
+        q = C.c_double()
+        st = louvain_run_stats()
+        st.timing = 1 if timing else 0
+        rc = self._check(self.lib.louvain_run(self.h, g.h, C.byref(prm), _ptr(out), C.byref(qi), C.byref(q),
+                                              C.byref(st), LOUVAIN_DEVICE_PTRS if dev else 0),
+                         ok=(LOUVAIN_OK, LOUVAIN_ELIMIT))
+        return RunResult(out, qi.value(), q.value, rc, stats_dict(st))
+
+
+def stats_dict(st: louvain_run_stats) -> dict:
+    levels = []
+    for k in range(st.levels):
+        lv = st.level[k]
+        levels.append(dict(n=lv.n, nnz=lv.nnz, sweeps_executed=lv.sweeps_executed,
+                           sweeps_accepted=lv.sweeps_accepted, gpu_passes=lv.gpu_passes,
+                           q_int=lv.q_int.value(), ms_sweep=lv.ms_sweep, ms_contract=lv.ms_contract))
+    kernels = {}
+    for k in range(st.n_kernels):
+        kk = st.kernels[k]
+        kernels[kk.name.decode()] = dict(launches=kk.launches, ms=kk.ms, alg_bytes=kk.alg_bytes)
+    return dict(levels=levels, kernels=kernels, total_edges_swept=st.total_edges_swept,
+                ms_total=st.ms_total, status=st.status)

@@ -1,0 +1,201 @@
+// Internal definitions shared by the HIP sources of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "louvain.h"
+
+namespace lv {
+
+typedef __int128 i128;
+typedef unsigned __int128 u128;
+
+// ---------------------------------------------------------------- errors --
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+inline void hip_check(hipError_t e, const char *what, const char *file, int line) {
+    if (e != hipSuccess) {
+        char buf[512];
+        snprintf(buf, sizeof buf, "%s failed at %s:%d: %s", what, file, line, hipGetErrorString(e));
+        throw Error(e == hipErrorOutOfMemory ? LOUVAIN_ENOMEM : LOUVAIN_EDEVICE, buf);
+    }
+}
+#define LV_HIP(call) ::lv::hip_check((call), #call, __FILE__, __LINE__)
+#define LV_LAUNCHED(name) ::lv::hip_check(hipGetLastError(), name, __FILE__, __LINE__)
+
+inline void require(bool ok, int code, const std::string &msg) {
+    if (!ok) throw Error(code, msg);
+}
+
+// ---------------------------------------------------------- device buffers --
+
+// Owning device allocation (hipMalloc / hipFree).
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t count) { alloc(count); }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        return *this;
+    }
+    ~DevBuf() { release(); }
+    void alloc(size_t count) {
+        release();
+        size_t bytes = (count ? count : 1) * sizeof(T);
+        hipError_t e = hipMalloc((void **)&p, bytes);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            throw Error(LOUVAIN_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        }
+        n = count;
+    }
+    // grow-only reallocation (contents are not preserved)
+    void reserve(size_t count) { if (count > n || !p) alloc(count); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    T *get() const { return p; }
+};
+
+// -------------------------------------------------------------- timing --
+
+// Groups of kernels for per-level time accounting.
+enum TimerGroup { TG_INGEST = 0, TG_LEVEL, TG_SWEEP, TG_CONTRACT, TG_OTHER };
+
+// Optional per-launch device timing with HIP events (run statistics).
+struct Timer {
+    bool on = false;
+    hipStream_t stream = nullptr;
+    struct Rec {
+        std::string name;
+        int group;
+        hipEvent_t a, b;
+        double bytes;   // algorithmic HBM bytes of the launch
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    hipEvent_t next_event() {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            LV_HIP(hipEventCreate(&e));
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    int begin(int group, const char *name, const char *suffix, double bytes) {
+        if (!on) return -1;
+        Rec r{std::string(name) + (suffix ? suffix : ""), group, next_event(), next_event(), bytes};
+        LV_HIP(hipEventRecord(r.a, stream));
+        recs.push_back(std::move(r));
+        return (int)recs.size() - 1;
+    }
+    void end(int id) {
+        if (id < 0) return;
+        LV_HIP(hipEventRecord(recs[id].b, stream));
+    }
+    void reset() { recs.clear(); used = 0; }
+    ~Timer() {
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+// RAII scope around one launch.
+struct TimedLaunch {
+    Timer *t;
+    int id;
+    TimedLaunch(Timer *t_, int group, const char *name, double bytes, const char *suffix = nullptr)
+        : t(t_), id(t_ ? t_->begin(group, name, suffix, bytes) : -1) {}
+    ~TimedLaunch() {
+        if (t && id >= 0) t->end(id);
+    }
+};
+
+// Type names as they appear in demangled kernel names.
+template <typename T> inline const char *type_name();
+template <> inline const char *type_name<int32_t>() { return "int"; }
+template <> inline const char *type_name<int64_t>() { return "long"; }
+template <> inline const char *type_name<__int128>() { return "__int128"; }
+
+// ------------------------------------------------------------- device helpers --
+
+constexpr int32_t kEmpty = -1;  // empty hash slot (labels are >= 0)
+
+// Fibonacci hashing of a label to a power-of-two table of 2^bits slots.
+__device__ __forceinline__ uint32_t hash_pow2(int32_t key, int bits) {
+    return ((uint32_t)key * 0x9E3779B1u) >> (32 - bits);
+}
+// Hash of a label into a table of any size (multiply-shift range reduction).
+__device__ __forceinline__ uint64_t hash_range(int32_t key, uint64_t size) {
+    uint32_t h = (uint32_t)key * 0x9E3779B1u;
+    h ^= h >> 16;
+    return ((uint64_t)h * size) >> 32;
+}
+
+// 128-bit value split in two 64-bit words for shuffles and stores.
+__host__ __device__ __forceinline__ i128 make_i128(uint64_t lo, int64_t hi) {
+    return (i128)(((u128)(uint64_t)hi << 64) | (u128)lo);
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl_xor_any(T v, int mask);
+template <>
+__device__ __forceinline__ int64_t shfl_xor_any<int64_t>(int64_t v, int mask) {
+    return __shfl_xor(v, mask);
+}
+template <>
+__device__ __forceinline__ i128 shfl_xor_any<i128>(i128 v, int mask) {
+    uint64_t lo = (uint64_t)v;
+    int64_t hi = (int64_t)(v >> 64);
+    lo = (uint64_t)__shfl_xor((long long)lo, mask);
+    hi = __shfl_xor((long long)hi, mask);
+    return make_i128(lo, hi);
+}
+
+// Scores: exact integer s(C) = TW*e - delta*deg.  With TW <= floor(sqrt(2^63-1))
+// every product and difference fits in int64 (all of e, delta, deg lie in
+// [0, TW]); otherwise 128-bit arithmetic is used.
+constexpr int64_t kTwFastMax = 3037000499LL;
+
+__device__ __forceinline__ i128 mul_wide(int64_t a, int64_t b) {
+    // a, b >= 0: one 64x64 -> 128 unsigned product
+    uint64_t ua = (uint64_t)a, ub = (uint64_t)b;
+    return make_i128(ua * ub, (int64_t)__umul64hi(ua, ub));
+}
+template <typename S>
+__device__ __forceinline__ S score_mul(int64_t a, int64_t b);
+template <>
+__device__ __forceinline__ int64_t score_mul<int64_t>(int64_t a, int64_t b) { return a * b; }
+template <>
+__device__ __forceinline__ i128 score_mul<i128>(int64_t a, int64_t b) { return mul_wide(a, b); }
+
+// Candidate order: larger score first, then smaller label; label < 0 = none.
+template <typename S>
+__device__ __forceinline__ bool better(S s, int32_t l, S bs, int32_t bl) {
+    return l >= 0 && (bl < 0 || s > bs || (s == bs && l < bl));
+}
+
+inline unsigned grid_for(int64_t items, int per_block) {
+    int64_t g = (items + per_block - 1) / per_block;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+}  // namespace lv

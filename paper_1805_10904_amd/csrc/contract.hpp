@@ -1,0 +1,40 @@
+// Renumbering, graph contraction and modularity on the device.
+#pragma once
+
+#include "common.hpp"
+#include "sweep.hpp"
+
+namespace lv {
+
+class Contractor {
+  public:
+    Contractor(hipStream_t s, Timer *t) : s_(s), t_(t) {}
+    // Allocate for graphs of at most n vertices and nnz entries.
+    void reserve(int64_t n, int64_t nnz);
+    // New consecutive IDs of the labels present, in ascending label order:
+    // newlab[i] = rank of labels[i] among the distinct labels.  Returns the
+    // number of communities (synchronises the stream).
+    int64_t renumber(const int32_t *labels, int64_t n, int32_t *newlab);
+    // final[v] = newlab[final[v]] for v in [0, n0).
+    void compose(int32_t *final_labels, int64_t n0, const int32_t *newlab);
+    // Contract g so that vertex a of the result is {i : newlab[i] == a};
+    // writes row_ptr (n_new + 1), col and int64 weights (capacity g.nnz) and
+    // returns the number of entries (synchronises the stream).
+    int64_t contract(const GraphView &g, const int32_t *newlab, int64_t n_new, int64_t *rp_out,
+                     int32_t *col_out, int64_t *w_out);
+
+  private:
+    hipStream_t s_;
+    Timer *t_;
+    int64_t cap_n_ = -1, cap_nnz_ = -1;
+    DevBuf<int32_t> flags_;     // n: label present / renumber map
+    DevBuf<uint64_t> key_[2];   // nnz: (row', col') sort keys
+    DevBuf<int64_t> val_[2];    // nnz: weights
+    DevBuf<int32_t> head_;      // nnz: segment heads
+    DevBuf<int64_t> uid_;       // nnz: unique index of each sorted entry
+};
+
+// Q_int = TW*I - sum_C deg_C^2 of labels (device int32[n] in [0, n)).
+i128 modularity_int(const GraphView &g, const int32_t *labels, hipStream_t s, Timer *t);
+
+}  // namespace lv

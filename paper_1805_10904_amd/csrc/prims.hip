@@ -1,0 +1,364 @@
+// Device-wide primitives: scans, fills, CSR ingest (validation, delta, TW)
+// and row sums.
+#include "prims.hpp"
+
+namespace lv {
+
+// ------------------------------------------------------------------ fills --
+
+template <typename T>
+__global__ void k_fill(T *p, T v, int64_t m) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <typename T>
+void fill(T *p, T v, int64_t m, hipStream_t s) {
+    if (m <= 0) return;
+    unsigned g = grid_for(m, 256);
+    if (g > 65536) g = 65536;
+    k_fill<T><<<g, 256, 0, s>>>(p, v, m);
+    LV_LAUNCHED("k_fill");
+}
+template void fill<int32_t>(int32_t *, int32_t, int64_t, hipStream_t);
+template void fill<int64_t>(int64_t *, int64_t, int64_t, hipStream_t);
+template void fill<uint64_t>(uint64_t *, uint64_t, int64_t, hipStream_t);
+
+__global__ void k_iota(int32_t *p, int64_t m) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (int32_t)i;
+}
+
+void iota_i32(int32_t *p, int64_t m, hipStream_t s) {
+    if (m <= 0) return;
+    unsigned g = grid_for(m, 256);
+    if (g > 65536) g = 65536;
+    k_iota<<<g, 256, 0, s>>>(p, m);
+    LV_LAUNCHED("k_iota");
+}
+
+// ------------------------------------------------------------ block scans --
+
+// Exclusive scan across a 256-thread block; `total` gets the block sum.
+template <typename T>
+__device__ __forceinline__ T block_excl_scan_256(T v, T &total) {
+    __shared__ T wsum[4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    T x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        T y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    T woff = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        T sw = wsum[w];
+        if (w < wid) woff += sw;
+        tot += sw;
+    }
+    __syncthreads();
+    total = tot;
+    return woff + x - v;
+}
+
+template <typename T>
+__device__ __forceinline__ T block_sum_256(T v) {
+    T tot;
+    (void)block_excl_scan_256<T>(v, tot);
+    return tot;
+}
+
+constexpr int kScanItems = 8;
+constexpr int kScanTile = 256 * kScanItems;
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_scan_reduce(const TI *__restrict__ in, int64_t m,
+                                                     TO *__restrict__ block_sums) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    TO s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k * 256 + threadIdx.x;
+        if (i < m) s += (TO)in[i];
+    }
+    s = block_sum_256<TO>(s);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = s;
+}
+
+// Down-sweep of one tile: out = exclusive prefix + the tile's offset.  The
+// last block writes the grand total to *total (if non-null).
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_scan_down(const TI *in, TO *out, int64_t m,
+                                                   const TO *__restrict__ block_off, TO *total) {
+    __shared__ TO tile[kScanTile];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k * 256 + t;
+        tile[k * 256 + t] = i < m ? (TO)in[i] : (TO)0;
+    }
+    __syncthreads();
+    TO loc[kScanItems];
+    TO sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        loc[k] = tile[t * kScanItems + k];
+        sum += loc[k];
+    }
+    TO tot;
+    TO run = block_excl_scan_256<TO>(sum, tot);
+    const TO off = block_off ? block_off[blockIdx.x] : (TO)0;
+    run += off;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        tile[t * kScanItems + k] = run;
+        run += loc[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k * 256 + t;
+        if (i < m) out[i] = tile[k * 256 + t];
+    }
+    if (total && t == 0 && blockIdx.x == gridDim.x - 1) *total = off + tot;
+}
+
+template <typename TI, typename TO>
+void scan_exclusive(const TI *in, TO *out, int64_t m, TO *total_dev, hipStream_t s, Timer *t) {
+    if (m <= 0) {
+        if (total_dev) fill<TO>(total_dev, (TO)0, 1, s);
+        return;
+    }
+    const int64_t nb = (m + kScanTile - 1) / kScanTile;
+    if (nb == 1) {
+        TimedLaunch tl(t, TG_OTHER, "k_scan_down", (double)m * (sizeof(TI) + sizeof(TO)));
+        k_scan_down<TI, TO><<<1, 256, 0, s>>>(in, out, m, nullptr, total_dev);
+        LV_LAUNCHED("k_scan_down");
+        return;
+    }
+    TempBuf bs((size_t)nb * sizeof(TO), s);
+    {
+        TimedLaunch tl(t, TG_OTHER, "k_scan_reduce", (double)m * sizeof(TI));
+        k_scan_reduce<TI, TO><<<(unsigned)nb, 256, 0, s>>>(in, m, bs.as<TO>());
+        LV_LAUNCHED("k_scan_reduce");
+    }
+    scan_exclusive<TO, TO>(bs.as<TO>(), bs.as<TO>(), nb, (TO *)nullptr, s, t);
+    {
+        TimedLaunch tl(t, TG_OTHER, "k_scan_down", (double)m * (sizeof(TI) + sizeof(TO)));
+        k_scan_down<TI, TO><<<(unsigned)nb, 256, 0, s>>>(in, out, m, bs.as<TO>(), total_dev);
+        LV_LAUNCHED("k_scan_down");
+    }
+}
+template void scan_exclusive<int32_t, int32_t>(const int32_t *, int32_t *, int64_t, int32_t *, hipStream_t, Timer *);
+template void scan_exclusive<int32_t, int64_t>(const int32_t *, int64_t *, int64_t, int64_t *, hipStream_t, Timer *);
+template void scan_exclusive<int64_t, int64_t>(const int64_t *, int64_t *, int64_t, int64_t *, hipStream_t, Timer *);
+
+// ------------------------------------------------------------ 128-bit sums --
+
+__global__ __launch_bounds__(256) void k_sum_i128(const uint64_t *__restrict__ partials, int64_t count,
+                                                  uint64_t *out) {
+    __shared__ uint64_t slo[256];
+    __shared__ int64_t shi[256];
+    i128 s = 0;
+    for (int64_t i = threadIdx.x; i < count; i += 256)
+        s += make_i128(partials[2 * i], (int64_t)partials[2 * i + 1]);
+    slo[threadIdx.x] = (uint64_t)s;
+    shi[threadIdx.x] = (int64_t)(s >> 64);
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            i128 a = make_i128(slo[threadIdx.x], shi[threadIdx.x]);
+            i128 b = make_i128(slo[threadIdx.x + w], shi[threadIdx.x + w]);
+            a += b;
+            slo[threadIdx.x] = (uint64_t)a;
+            shi[threadIdx.x] = (int64_t)(a >> 64);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = slo[0];
+        out[1] = (uint64_t)shi[0];
+    }
+}
+
+void sum_i128_partials(const uint64_t *partials, int64_t count, uint64_t *out, hipStream_t s) {
+    k_sum_i128<<<1, 256, 0, s>>>(partials, count, out);
+    LV_LAUNCHED("k_sum_i128");
+}
+
+// Block-wide 128-bit sum of one value per thread, written as a (lo, hi) pair.
+__device__ __forceinline__ void block_store_i128_sum(i128 v, uint64_t *dst) {
+    __shared__ uint64_t slo[4];
+    __shared__ int64_t shi[4];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += shfl_xor_any<i128>(v, off);
+    if (lane == 0) {
+        slo[wid] = (uint64_t)v;
+        shi[wid] = (int64_t)(v >> 64);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        i128 s = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += make_i128(slo[w], shi[w]);
+        dst[0] = (uint64_t)s;
+        dst[1] = (uint64_t)(int64_t)(s >> 64);
+    }
+}
+
+// ------------------------------------------------------------------ ingest --
+
+enum { BAD_ROWPTR = 1, BAD_COL = 2, BAD_WEIGHT = 4, BAD_ORDER = 8, BAD_SYMMETRY = 16 };
+
+__global__ void k_check_rowptr(const int64_t *__restrict__ rp, int64_t n, int64_t nnz, int *bad) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    int64_t v = rp[i];
+    bool ok = v >= 0 && v <= nnz;
+    if (i == 0) ok = ok && v == 0;
+    if (i == n) ok = ok && v == nnz;
+    if (i < n) ok = ok && rp[i + 1] >= v;
+    if (!ok) atomicOr(bad, BAD_ROWPTR);
+}
+
+template <typename W>
+__global__ __launch_bounds__(256) void k_ingest_entries(const int64_t *__restrict__ rp, int64_t n,
+                                                        int64_t nnz, const int32_t *__restrict__ col,
+                                                        const W *__restrict__ w, int64_t *delta,
+                                                        uint64_t *tw_partials, int *bad, int check_sym) {
+    __shared__ int64_t srange[2];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kEntriesPerBlock;
+    if (t == 0) {
+        int64_t last = base + kEntriesPerBlock - 1;
+        if (last > nnz - 1) last = nnz - 1;
+        srange[0] = row_of_entry(rp, 0, n - 1, base);
+        srange[1] = row_of_entry(rp, 0, n - 1, last);
+    }
+    __syncthreads();
+    const int64_t rlo = srange[0], rhi = srange[1];
+    int errs = 0;
+    i128 tw = 0;
+#pragma unroll 1
+    for (int k = 0; k < kEntryItems; ++k) {
+        const int64_t e = base + k * 256 + t;
+        const bool valid = e < nnz;
+        int64_t r = 0, wv = 0;
+        if (valid) {
+            r = row_of_entry(rp, rlo, rhi, e);
+            const int32_t j = col[e];
+            const int64_t x = (int64_t)w[e];
+            if (j < 0 || (int64_t)j >= n) errs |= BAD_COL;
+            if (x < 1) errs |= BAD_WEIGHT;
+            if (e + 1 < rp[r + 1] && col[e + 1] <= j) errs |= BAD_ORDER;
+            wv = x;
+            tw += (i128)x;
+            if (check_sym && j >= 0 && (int64_t)j < n) {
+                int64_t lo = rp[j], hi = rp[j + 1] - 1;
+                bool found = false;
+                while (lo <= hi) {
+                    int64_t mid = (lo + hi) >> 1;
+                    int32_t cm = col[mid];
+                    if (cm == (int32_t)r) { found = (int64_t)w[mid] == x; break; }
+                    if (cm < (int32_t)r) lo = mid + 1; else hi = mid - 1;
+                }
+                if (!found) errs |= BAD_SYMMETRY;
+            }
+        }
+        seg_add_wave(delta, r, wv, valid && !(errs & BAD_COL));
+    }
+    if (errs) atomicOr(bad, errs);
+    block_store_i128_sum(tw, tw_partials + 2 * blockIdx.x);
+}
+
+template <typename W>
+void ingest_csr(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col, const W *w,
+                int64_t *delta, int64_t *tw_host, bool check_symmetry, hipStream_t s, Timer *t) {
+    TempBuf badb(sizeof(int) + 2 * sizeof(uint64_t), s);
+    int *bad = badb.as<int>();
+    uint64_t *tw2 = (uint64_t *)((char *)badb.p + 8);
+    LV_HIP(hipMemsetAsync(badb.p, 0, sizeof(int) + 2 * sizeof(uint64_t), s));
+    fill<int64_t>(delta, 0, n, s);
+    {
+        TimedLaunch tl(t, TG_INGEST, "k_check_rowptr", (double)(n + 1) * 8);
+        k_check_rowptr<<<grid_for(n + 1, 256), 256, 0, s>>>(row_ptr, n, nnz, bad);
+        LV_LAUNCHED("k_check_rowptr");
+    }
+    int hbad = 0;
+    LV_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    LV_HIP(hipStreamSynchronize(s));
+    require(hbad == 0, LOUVAIN_EINVAL, "row_ptr is malformed (must start at 0, be nondecreasing and end at nnz)");
+    uint64_t hw[2] = {0, 0};
+    if (nnz > 0) {
+        const int64_t nb = (nnz + kEntriesPerBlock - 1) / kEntriesPerBlock;
+        TempBuf parts((size_t)nb * 2 * sizeof(uint64_t), s);
+        {
+            TimedLaunch tl(t, TG_INGEST, "k_ingest_entries", (double)nnz * (4 + sizeof(W)) + (double)n * 16, type_name<W>());
+            k_ingest_entries<W><<<(unsigned)nb, 256, 0, s>>>(row_ptr, n, nnz, col, w, delta,
+                                                             parts.as<uint64_t>(), bad,
+                                                             check_symmetry ? 1 : 0);
+            LV_LAUNCHED("k_ingest_entries");
+        }
+        sum_i128_partials(parts.as<uint64_t>(), nb, tw2, s);
+        LV_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+        LV_HIP(hipMemcpyAsync(hw, tw2, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+        LV_HIP(hipStreamSynchronize(s));
+    }
+    require(!(hbad & BAD_COL), LOUVAIN_EINVAL, "column index out of range [0, n)");
+    require(!(hbad & BAD_WEIGHT), LOUVAIN_EINVAL, "edge weight < 1 (weights must be positive integers)");
+    require(!(hbad & BAD_ORDER), LOUVAIN_EINVAL, "columns must be strictly ascending inside each row (no multi-edges)");
+    require(!(hbad & BAD_SYMMETRY), LOUVAIN_EINVAL, "graph is not symmetric (A_ij != A_ji)");
+    i128 tw = make_i128(hw[0], (int64_t)hw[1]);
+    require(tw < ((i128)1 << 62), LOUVAIN_EOVERFLOW, "total weight 2W must be below 2^62");
+    *tw_host = (int64_t)tw;
+}
+template void ingest_csr<int32_t>(int64_t, int64_t, const int64_t *, const int32_t *, const int32_t *,
+                                  int64_t *, int64_t *, bool, hipStream_t, Timer *);
+template void ingest_csr<int64_t>(int64_t, int64_t, const int64_t *, const int32_t *, const int64_t *,
+                                  int64_t *, int64_t *, bool, hipStream_t, Timer *);
+
+// ---------------------------------------------------------------- row sums --
+
+__global__ __launch_bounds__(256) void k_row_sums(const int64_t *__restrict__ rp, int64_t n, int64_t nnz,
+                                                  const int64_t *__restrict__ w, int64_t *delta) {
+    __shared__ int64_t srange[2];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)blockIdx.x * kEntriesPerBlock;
+    if (t == 0) {
+        int64_t last = base + kEntriesPerBlock - 1;
+        if (last > nnz - 1) last = nnz - 1;
+        srange[0] = row_of_entry(rp, 0, n - 1, base);
+        srange[1] = row_of_entry(rp, 0, n - 1, last);
+    }
+    __syncthreads();
+    const int64_t rlo = srange[0], rhi = srange[1];
+#pragma unroll 1
+    for (int k = 0; k < kEntryItems; ++k) {
+        const int64_t e = base + k * 256 + t;
+        const bool valid = e < nnz;
+        int64_t r = 0, wv = 0;
+        if (valid) {
+            r = row_of_entry(rp, rlo, rhi, e);
+            wv = w[e];
+        }
+        seg_add_wave(delta, r, wv, valid);
+    }
+}
+
+void row_sums_i64(int64_t n, int64_t nnz, const int64_t *row_ptr, const int64_t *w, int64_t *delta,
+                  hipStream_t s, Timer *t) {
+    fill<int64_t>(delta, 0, n, s);
+    if (nnz <= 0) return;
+    const int64_t nb = (nnz + kEntriesPerBlock - 1) / kEntriesPerBlock;
+    TimedLaunch tl(t, TG_CONTRACT, "k_row_sums", (double)nnz * 8 + (double)n * 16);
+    k_row_sums<<<(unsigned)nb, 256, 0, s>>>(row_ptr, n, nnz, w, delta);
+    LV_LAUNCHED("k_row_sums");
+}
+
+}  // namespace lv

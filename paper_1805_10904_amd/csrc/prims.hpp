@@ -1,0 +1,86 @@
+// Device-wide primitives: scans, fills, CSR ingest and row sums.
+#pragma once
+
+#include "common.hpp"
+
+namespace lv {
+
+// Stream-ordered temporary device allocation (hipMallocAsync / hipFreeAsync).
+struct TempBuf {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    TempBuf(size_t bytes, hipStream_t stream) : s(stream) {
+        hipError_t e = hipMallocAsync(&p, bytes ? bytes : 16, stream);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            throw Error(LOUVAIN_ENOMEM, "temporary device allocation of " + std::to_string(bytes) + " bytes failed");
+        }
+    }
+    TempBuf(const TempBuf &) = delete;
+    TempBuf &operator=(const TempBuf &) = delete;
+    ~TempBuf() {
+        if (p) (void)hipFreeAsync(p, s);
+    }
+    template <typename T> T *as() const { return (T *)p; }
+};
+
+// out[i] = sum_{k<i} in[k] for i in [0, m); *total_dev (optional, device)
+// receives the sum of all m values.  in and out may alias.  TI, TO are
+// int32_t or int64_t; sums are formed in TO.
+template <typename TI, typename TO>
+void scan_exclusive(const TI *in, TO *out, int64_t m, TO *total_dev, hipStream_t s, Timer *t);
+
+template <typename T>
+void fill(T *p, T v, int64_t m, hipStream_t s);
+
+void iota_i32(int32_t *p, int64_t m, hipStream_t s);
+
+// Reduction of per-block 128-bit partials (lo, hi word pairs) into one value at out[0..1].
+void sum_i128_partials(const uint64_t *partials, int64_t count, uint64_t *out, hipStream_t s);
+
+// CSR ingest (a1).  Validates row_ptr, columns (in range, strictly
+// ascending per row) and weights (>= 1); computes delta (int64[n]) and
+// TW.  Optionally checks symmetry.  Throws Error(EINVAL / EOVERFLOW).
+template <typename W>
+void ingest_csr(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col, const W *w,
+                int64_t *delta, int64_t *tw_host, bool check_symmetry, hipStream_t s, Timer *t);
+
+// delta[i] = sum of row i's weights (int64 weights), for trusted CSR.
+void row_sums_i64(int64_t n, int64_t nnz, const int64_t *row_ptr, const int64_t *w, int64_t *delta,
+                  hipStream_t s, Timer *t);
+
+// Device helper: largest r in [lo, hi] with row_ptr[r] <= e (the row holding entry e).
+__device__ __forceinline__ int64_t row_of_entry(const int64_t *__restrict__ row_ptr, int64_t lo,
+                                                int64_t hi, int64_t e) {
+    while (lo < hi) {
+        int64_t mid = (lo + hi + 1) >> 1;
+        if (row_ptr[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Adds v to out[r] for lanes holding consecutive entries of nondecreasing
+// rows r (segmented inclusive scan over the wavefront, one atomic per
+// row segment).  Lanes with valid == false must form the wave's tail.
+__device__ __forceinline__ void seg_add_wave(int64_t *out, int64_t r, int64_t v, bool valid) {
+    const int lane = threadIdx.x & 63;
+    int64_t x = valid ? v : 0;
+    int64_t rr = valid ? r : -1;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int64_t xo = __shfl_up(x, off);
+        int64_t ro = __shfl_up(rr, off);
+        if (lane >= off && ro == rr) x += xo;
+    }
+    int64_t rn = __shfl_down(rr, 1);
+    bool last = lane == 63 || rn != rr;
+    if (valid && last && x != 0) atomicAdd((unsigned long long *)&out[rr], (unsigned long long)x);
+}
+
+// Entry-parallel tiling: a 256-thread block covers kEntriesPerBlock consecutive
+// CSR entries, item k of thread t is entry base + k*256 + t.
+constexpr int kEntryItems = 8;
+constexpr int kEntriesPerBlock = 256 * kEntryItems;
+
+}  // namespace lv

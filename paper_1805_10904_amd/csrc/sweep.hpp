@@ -1,0 +1,93 @@
+// Local-moving phase on the device: degree bucketing, synchronous sweeps,
+// commit of community degrees and sizes, exact modularity and the sweep
+// acceptance test.
+#pragma once
+
+#include "common.hpp"
+
+namespace lv {
+
+// A graph as the kernels see it (device pointers).
+struct GraphView {
+    int64_t n = 0, nnz = 0;
+    const int64_t *row_ptr = nullptr;
+    const int32_t *col = nullptr;
+    const void *w = nullptr;   // int32 (wbytes 4) or int64 (wbytes 8)
+    int wbytes = 4;
+    const int64_t *delta = nullptr;
+    int64_t tw = 0;
+};
+
+// Device-resident control block of one phase.
+struct PhaseState {
+    unsigned long long acc_I;   // sum of e_{i->c_i} (loops included) of the labelling read by the pass
+    unsigned long long moved;   // vertices whose label changed in the pass
+    int32_t pass;               // passes finalized in the phase
+    int32_t accepted;           // sweeps kept
+    int32_t done;               // phase finished
+    int32_t limit;              // max_sweeps reached
+    int32_t final_slot;         // label ring slot holding the phase result
+    int32_t pad;
+    uint64_t q_ref[2];          // Q_int of the last kept labelling (lo, hi)
+    uint64_t q_last[2];         // Q_int computed by the last finalize
+};
+
+// Degree buckets: row length d (entries incl. a loop) -> sweep kernel.
+enum { B_G4 = 0, B_G16, B_G64, B_BLOCK, B_HUB, NBUCKET };
+constexpr int64_t kBucketMax[NBUCKET - 1] = {8, 32, 128, 1024};
+constexpr int kHubChunk = 1024;      // row entries per hub accumulation workgroup
+constexpr int kHubScan = 1024;       // table slots per hub scan workgroup
+
+struct SweepParams {
+    int64_t theta_num = 1, theta_den = 1000000;
+    int32_t max_sweeps = 1000;
+    int singlet = 1;
+};
+
+class Sweeper {
+  public:
+    explicit Sweeper(hipStream_t s, Timer *t) : s_(s), t_(t) {}
+    // Allocate for levels of at most n vertices and nnz entries.
+    void reserve(int64_t n, int64_t nnz);
+    // Degree bucketing of the level's vertices (a3) and hub table set-up.
+    void plan(const GraphView &g);
+    // Singleton communities (a2): every ring slot = identity, deg = delta, size = 1.
+    void init_singletons(const GraphView &g);
+    // Communities from labels (device int32[n]): ring slots = labels, deg/size recomputed.
+    void init_from_labels(const GraphView &g, const int32_t *labels);
+    // Enqueue sweep pass p >= 1: reads ring slot (p-1)%3, writes slot p%3,
+    // computes Q_int of the labelling it reads and runs the acceptance test.
+    void pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e_self_out);
+    // Copy the control block to the host (synchronises the stream).
+    PhaseState read_state();
+    int32_t *slot(int k) { return c_[k % 3].p; }
+    int64_t *deg() { return deg_.p; }
+    int32_t *size() { return size_.p; }
+    int64_t bucket_count(int b) const { return bstart_[b + 1] - bstart_[b]; }
+
+  private:
+    hipStream_t s_;
+    Timer *t_;
+    int64_t cap_n_ = -1, cap_nnz_ = -1;
+    DevBuf<int32_t> c_[3];
+    DevBuf<int64_t> deg_;
+    DevBuf<int32_t> size_;
+    DevBuf<int32_t> list_;          // vertices grouped by bucket, ascending inside a bucket
+    DevBuf<int32_t> bcount_;        // bucketing scratch (per-block counts / offsets)
+    DevBuf<PhaseState> st_;
+    DevBuf<uint64_t> qpart_;        // per-block partial sums of deg^2 (lo, hi)
+    // hubs
+    DevBuf<int64_t> hub_meta_;      // 4 arrays of (hubs+1): table offset, chunk offset, scan offset, table size
+    DevBuf<int32_t> hub_key_;
+    DevBuf<unsigned long long> hub_val_;
+    DevBuf<unsigned long long> hub_loop_;
+    DevBuf<uint64_t> hub_part_;     // per scan block: score lo, score hi, label, e_own
+    int64_t bstart_[NBUCKET + 1] = {0};
+    int64_t bucket_nnz_[NBUCKET] = {0};
+    int64_t hubs_ = 0, hub_chunks_ = 0, hub_scans_ = 0, hub_slots_ = 0;
+    int64_t hub_slot_cap_ = 0;
+    int64_t qblocks_ = 0;
+    int64_t n_ = 0;
+};
+
+}  // namespace lv

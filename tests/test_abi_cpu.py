@@ -1,0 +1,55 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads and
+exports every function include/louvain.h declares, and the Python binding
+covers exactly those."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "louvain.h")
+PKG = os.path.join(ROOT, "paper_1805_10904_amd")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(louvain_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for f in ("louvain_graph_create", "louvain_local_move", "louvain_aggregate", "louvain_run",
+              "louvain_modularity"):
+        assert f in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1805_10904_amd import _native
+    if not os.path.exists(_native.LIB_PATH):
+        from paper_1805_10904_amd import build
+        build.build()
+    out = subprocess.run(["nm", "-D", "--defined-only", _native.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (louvain_[a-z0-9_]+)\b", out))
+    missing = [f for f in declared_functions() if f not in exported]
+    assert not missing, f"declared but not exported: {missing}"
+    # the binding's list matches the header
+    assert sorted(_native.ABI_SYMBOLS) == declared_functions()
+    # and ctypes resolves them
+    assert sorted(_native.exported_symbols()) == declared_functions()
+
+
+def test_product_path_never_touches_the_oracle():
+    for dirpath, _, files in os.walk(PKG):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"\boracle\b", text), f"{f} mentions the oracle"
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    from paper_1805_10904_amd import _native
+    with pytest.raises(RuntimeError, match="not built"):
+        _native.load_library(str(tmp_path / "missing.so"))
