@@ -69,6 +69,12 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library not built: {path} is missing "
                            "(run paper_1805_10904_amd/build.py or __graft_entry__.build())")
+    # torch ships its own HIP runtime under the same soname; load it first so
+    # that the library and torch share one runtime (device memory, streams).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     p, i64, u32, i32 = C.c_void_p, C.c_int64, C.c_uint32, C.c_int
     lib.louvain_ctx_create.argtypes = [i32, p, C.POINTER(p)]

@@ -199,9 +199,12 @@ __global__ __launch_bounds__(256) void k_reduce_by_key(const uint64_t *__restric
         const bool valid = e < m;
         int64_t u = 0, v = 0;
         if (valid) {
-            u = uid[e];
+            // uid is the exclusive count of heads: a head's own segment index,
+            // one past it for the entries that follow the head
+            const int32_t h = head[e];
+            u = uid[e] + h - 1;
             v = vals[e];
-            if (head[e]) {
+            if (h) {
                 const uint64_t key = keys[e];
                 col_out[u] = (int32_t)(key & mask);
                 ukey[u] = key;

@@ -280,10 +280,11 @@ __global__ __launch_bounds__(256) void k_ingest_entries(const int64_t *__restric
 template <typename W>
 void ingest_csr(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col, const W *w,
                 int64_t *delta, int64_t *tw_host, bool check_symmetry, hipStream_t s, Timer *t) {
-    TempBuf badb(sizeof(int) + 2 * sizeof(uint64_t), s);
+    // scratch: [0, 4) error bits, [16, 32) the 128-bit total weight
+    TempBuf badb(32, s);
     int *bad = badb.as<int>();
-    uint64_t *tw2 = (uint64_t *)((char *)badb.p + 8);
-    LV_HIP(hipMemsetAsync(badb.p, 0, sizeof(int) + 2 * sizeof(uint64_t), s));
+    uint64_t *tw2 = (uint64_t *)((char *)badb.p + 16);
+    LV_HIP(hipMemsetAsync(badb.p, 0, 32, s));
     fill<int64_t>(delta, 0, n, s);
     {
         TimedLaunch tl(t, TG_INGEST, "k_check_rowptr", (double)(n + 1) * 8);

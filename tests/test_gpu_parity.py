@@ -246,7 +246,7 @@ def test_degenerate_graphs(ctx, L):
 def test_errors_leave_outputs_untouched(ctx, L):
     g = gg.from_edge_list(4, [(0, 1), (1, 2), (2, 3)])
     bad = [
-        (g.row_ptr, np.array([1, 0, 2, 1, 3, 2], np.int32), g.w),             # unsorted row
+        (g.row_ptr, np.array([1, 2, 0, 1, 3, 2], np.int32), g.w),             # unsorted row
         (g.row_ptr, np.array([1, 0, 2, 1, 9, 2], np.int32), g.w),             # column out of range
         (g.row_ptr, g.col, np.array([1, 1, 0, 1, 1, 1], np.int32)),           # weight 0
         (np.array([0, 1, 3, 2, 6], np.int64), g.col, g.w),                     # row_ptr not monotone
