@@ -86,7 +86,7 @@ typedef struct {
     double ms_contract;           /* device time of renumber + contraction (stats mode)    */
 } louvain_level_stats;
 
-#define LOUVAIN_MAX_KERNEL_STATS 24
+#define LOUVAIN_MAX_KERNEL_STATS 64
 
 /* Per-kernel device-time record (stats mode): one per kernel family. */
 typedef struct {

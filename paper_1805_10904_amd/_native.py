@@ -55,7 +55,7 @@ class louvain_kernel_stats(C.Structure):
 class louvain_run_stats(C.Structure):
     _fields_ = [("timing", C.c_int32), ("levels", C.c_int32), ("status", C.c_int32),
                 ("n_kernels", C.c_int32), ("total_edges_swept", C.c_int64), ("ms_total", C.c_double),
-                ("level", louvain_level_stats * 64), ("kernels", louvain_kernel_stats * 24)]
+                ("level", louvain_level_stats * 64), ("kernels", louvain_kernel_stats * 64)]
 
 
 _lib = None

@@ -9,6 +9,7 @@
 #include "sweep.hpp"
 
 struct louvain_ctx_s {
+    std::shared_ptr<lv::Pool> pool = std::make_shared<lv::Pool>();   // destroyed last
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
@@ -16,6 +17,7 @@ struct louvain_ctx_s {
 };
 
 struct louvain_graph_s {
+    std::shared_ptr<lv::Pool> pool;   // keeps the blocks' pool alive; destroyed last
     louvain_ctx ctx = nullptr;
     int device = 0;
     int64_t n = 0, nnz = 0, tw = 0;
@@ -46,9 +48,17 @@ using lv::DevBuf;
 using lv::Error;
 using lv::require;
 
+// Installs a context's pool as the thread's current pool for one call.
+struct PoolScope {
+    lv::Pool *saved;
+    explicit PoolScope(lv::Pool *p) : saved(lv::current_pool()) { lv::current_pool() = p; }
+    ~PoolScope() { lv::current_pool() = saved; }
+};
+
 template <typename F>
 int guarded(louvain_ctx ctx, F &&f) {
     if (!ctx) return LOUVAIN_EINVAL;
+    PoolScope scope(ctx->pool.get());
     try {
         LV_HIP(hipSetDevice(ctx->device));
         f();
@@ -195,6 +205,7 @@ int louvain_graph_create(louvain_ctx ctx, int64_t n, int64_t nnz, const int64_t 
         const bool dev = device_ptrs(flags);
         std::unique_ptr<louvain_graph_s> g(new louvain_graph_s());
         g->ctx = ctx;
+        g->pool = ctx->pool;
         g->device = ctx->device;
         g->n = n;
         g->nnz = nnz;
@@ -311,6 +322,7 @@ int louvain_aggregate(louvain_ctx ctx, louvain_graph g, const int32_t *labels, i
         const int64_t k = ct.renumber(lab.p, g->n, newlab.p);
         std::unique_ptr<louvain_graph_s> g2(new louvain_graph_s());
         g2->ctx = ctx;
+        g2->pool = ctx->pool;
         g2->device = ctx->device;
         g2->n = k;
         g2->wbytes = 8;

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <cstdio>
+#include <map>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -37,40 +38,124 @@ inline void require(bool ok, int code, const std::string &msg) {
     if (!ok) throw Error(code, msg);
 }
 
-// ---------------------------------------------------------- device buffers --
+// ---------------------------------------------------------- device memory --
 
-// Owning device allocation (hipMalloc / hipFree).
+// Caching device allocator of one context.  Blocks are rounded to size
+// classes (powers of two up to 1 MiB, multiples of 2 MiB above) and kept
+// for reuse until the pool dies.  All users enqueue on the context's single
+// stream, so a block handed back while kernels still use it is only reused
+// by work ordered after them.
+struct Pool {
+    std::multimap<size_t, void *> free_;
+    std::map<void *, size_t> live_;
+    size_t cached = 0, in_use = 0;
+
+    static size_t round(size_t b) {
+        if (b <= 512) return 512;
+        if (b <= (1u << 20)) {
+            size_t r = 512;
+            while (r < b) r <<= 1;
+            return r;
+        }
+        const size_t g = (size_t)2 << 20;
+        return (b + g - 1) / g * g;
+    }
+    void *get(size_t bytes) {
+        const size_t r = round(bytes);
+        auto it = free_.find(r);
+        void *p = nullptr;
+        if (it != free_.end()) {
+            p = it->second;
+            free_.erase(it);
+            cached -= r;
+        } else {
+            hipError_t e = hipMalloc(&p, r);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                trim();
+                e = hipMalloc(&p, r);
+            }
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                throw Error(LOUVAIN_ENOMEM, "device allocation of " + std::to_string(r) + " bytes failed");
+            }
+        }
+        live_[p] = r;
+        in_use += r;
+        return p;
+    }
+    void put(void *p) {
+        auto it = live_.find(p);
+        if (it == live_.end()) return;
+        free_.emplace(it->second, p);
+        cached += it->second;
+        in_use -= it->second;
+        live_.erase(it);
+    }
+    // Release every cached block (waits for the device first).
+    void trim() {
+        if (free_.empty()) return;
+        (void)hipDeviceSynchronize();
+        for (auto &kv : free_) (void)hipFree(kv.second);
+        free_.clear();
+        cached = 0;
+    }
+    ~Pool() {
+        (void)hipDeviceSynchronize();
+        for (auto &kv : free_) (void)hipFree(kv.second);
+        for (auto &kv : live_) (void)hipFree(kv.first);
+    }
+};
+
+// The pool of the context whose call is running on this thread (set at the
+// C ABI boundary); nullptr means plain hipMalloc / hipFree.
+Pool *&current_pool();
+
+// Owning device allocation from the current pool (or hipMalloc).
 template <typename T>
 struct DevBuf {
     T *p = nullptr;
     size_t n = 0;
+    Pool *pool = nullptr;
     DevBuf() = default;
     explicit DevBuf(size_t count) { alloc(count); }
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+    DevBuf(DevBuf &&o) noexcept : p(o.p), n(o.n), pool(o.pool) { o.p = nullptr; o.n = 0; o.pool = nullptr; }
     DevBuf &operator=(DevBuf &&o) noexcept {
-        if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+        if (this != &o) {
+            release();
+            p = o.p; n = o.n; pool = o.pool;
+            o.p = nullptr; o.n = 0; o.pool = nullptr;
+        }
         return *this;
     }
     ~DevBuf() { release(); }
     void alloc(size_t count) {
         release();
-        size_t bytes = (count ? count : 1) * sizeof(T);
-        hipError_t e = hipMalloc((void **)&p, bytes);
-        if (e != hipSuccess) {
-            p = nullptr;
-            (void)hipGetLastError();
-            throw Error(LOUVAIN_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+        const size_t bytes = (count ? count : 1) * sizeof(T);
+        pool = current_pool();
+        if (pool) {
+            p = (T *)pool->get(bytes);
+        } else {
+            hipError_t e = hipMalloc((void **)&p, bytes);
+            if (e != hipSuccess) {
+                p = nullptr;
+                (void)hipGetLastError();
+                throw Error(LOUVAIN_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
+            }
         }
         n = count;
     }
     // grow-only reallocation (contents are not preserved)
     void reserve(size_t count) { if (count > n || !p) alloc(count); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (pool) pool->put(p); else (void)hipFree(p);
+        }
         p = nullptr;
         n = 0;
+        pool = nullptr;
     }
     T *get() const { return p; }
 };

@@ -4,6 +4,11 @@
 
 namespace lv {
 
+Pool *&current_pool() {
+    static thread_local Pool *p = nullptr;
+    return p;
+}
+
 // ------------------------------------------------------------------ fills --
 
 template <typename T>

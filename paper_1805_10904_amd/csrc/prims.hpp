@@ -5,11 +5,17 @@
 
 namespace lv {
 
-// Stream-ordered temporary device allocation (hipMallocAsync / hipFreeAsync).
+// Temporary device allocation for the duration of a host scope: from the
+// current context's pool (stream-ordered reuse), else hipMallocAsync.
 struct TempBuf {
     void *p = nullptr;
     hipStream_t s = nullptr;
-    TempBuf(size_t bytes, hipStream_t stream) : s(stream) {
+    Pool *pool = nullptr;
+    TempBuf(size_t bytes, hipStream_t stream) : s(stream), pool(current_pool()) {
+        if (pool) {
+            p = pool->get(bytes ? bytes : 16);
+            return;
+        }
         hipError_t e = hipMallocAsync(&p, bytes ? bytes : 16, stream);
         if (e != hipSuccess) {
             p = nullptr;
@@ -20,7 +26,8 @@ struct TempBuf {
     TempBuf(const TempBuf &) = delete;
     TempBuf &operator=(const TempBuf &) = delete;
     ~TempBuf() {
-        if (p) (void)hipFreeAsync(p, s);
+        if (!p) return;
+        if (pool) pool->put(p); else (void)hipFreeAsync(p, s);
     }
     template <typename T> T *as() const { return (T *)p; }
 };
