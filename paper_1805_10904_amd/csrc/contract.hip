@@ -82,13 +82,7 @@ __global__ __launch_bounds__(256) void k_contract_keys(const int64_t *__restrict
     __shared__ int64_t srange[2];
     const int t = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * kEntriesPerBlock;
-    if (t == 0) {
-        int64_t last = base + kEntriesPerBlock - 1;
-        if (last > nnz - 1) last = nnz - 1;
-        srange[0] = row_of_entry(rp, 0, n - 1, base);
-        srange[1] = row_of_entry(rp, 0, n - 1, last);
-    }
-    __syncthreads();
+    block_row_range(rp, n, nnz, base, kEntriesPerBlock, srange);
     const int64_t rlo = srange[0], rhi = srange[1];
 #pragma unroll 1
     for (int k = 0; k < kEntryItems; ++k) {
@@ -311,13 +305,9 @@ __global__ __launch_bounds__(256) void k_inner_weight(const int64_t *__restrict_
     const int t = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * kEntriesPerBlock;
     if (t == 0) {
-        int64_t last = base + kEntriesPerBlock - 1;
-        if (last > nnz - 1) last = nnz - 1;
-        srange[0] = row_of_entry(rp, 0, n - 1, base);
-        srange[1] = row_of_entry(rp, 0, n - 1, last);
         s_acc = 0;
     }
-    __syncthreads();
+    block_row_range(rp, n, nnz, base, kEntriesPerBlock, srange);
     const int64_t rlo = srange[0], rhi = srange[1];
     unsigned long long s = 0;
 #pragma unroll 1

@@ -67,6 +67,42 @@ __device__ __forceinline__ int64_t row_of_entry(const int64_t *__restrict__ row_
     return lo;
 }
 
+// Largest r in [0, n) with a[r] <= x, for a nondecreasing with a[0] <= x,
+// searched by all 64 lanes of a converged wavefront (each round probes 64
+// positions at once, so about log64(n) dependent loads); every lane gets r.
+__device__ __forceinline__ int64_t wave_find_le(const int64_t *__restrict__ a, int64_t n, int64_t x) {
+    const int lane = threadIdx.x & 63;
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int64_t step = (hi - lo + 64) / 64;
+        const int64_t p = lo + (int64_t)lane * step;
+        const bool ok = p <= hi && a[p] <= x;
+        const unsigned long long m = __ballot(ok);
+        const int last = 63 - __clzll(m);
+        lo = lo + (int64_t)last * step;
+        const int64_t top = lo + step - 1;
+        hi = top < hi ? top : hi;
+    }
+    return lo;
+}
+
+// The rows holding the first and last entry of an entry-parallel block,
+// found by the block's first wavefront and shared through LDS.
+__device__ __forceinline__ void block_row_range(const int64_t *__restrict__ row_ptr, int64_t n, int64_t nnz,
+                                                int64_t base, int64_t per_block, int64_t *srange) {
+    if (threadIdx.x < 64) {
+        int64_t last = base + per_block - 1;
+        if (last > nnz - 1) last = nnz - 1;
+        const int64_t r0 = wave_find_le(row_ptr, n, base);
+        const int64_t r1 = wave_find_le(row_ptr, n, last);
+        if (threadIdx.x == 0) {
+            srange[0] = r0;
+            srange[1] = r1;
+        }
+    }
+    __syncthreads();
+}
+
 // Adds v to out[r] for lanes holding consecutive entries of nondecreasing
 // rows r (segmented inclusive scan over the wavefront, one atomic per
 // row segment).  Lanes with valid == false must form the wave's tail.

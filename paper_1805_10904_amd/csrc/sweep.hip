@@ -1,18 +1,22 @@
 // Local-moving phase on the device (paper: Alg. 1 with eqs. 1-5 and the
 // minimum-label heuristics of Section 3.1).
 //
-// One sweep pass over ring slot cur -> nxt:
+// One sweep pass over label ring slot cur -> nxt and degree state p-1 -> p:
 //   k_qsum      sum_C deg_C^2 of the labelling read by the pass
 //   k_sweep_*   per vertex: e_{i->C} for every neighbouring community C,
-//               accumulated in an LDS hash table keyed by community label
-//               (HBM tables for hubs), integer scores, argmax with the
-//               minimum-label tie-break, the singlet rule, the new label,
-//               and e_{i->c_i} (+ loop) summed into I for Q_int
+//               integer scores, argmax with the minimum-label tie-break, the
+//               singlet rule, the new label, and e_{i->c_i} (+ loop) summed
+//               into I for Q_int.  Rows of <= 8 entries: one thread per
+//               vertex in registers; <= 512: packed workgroups with LDS hash
+//               tables; <= 1024: one workgroup per vertex; longer rows: LDS
+//               pre-aggregation into HBM hash tables.
 //   k_commit    deg_C / size updates of the movers with integer atomics
 //   k_finalize  Q_int = TW*I - sum deg_C^2 of the labelling read, and the
 //               exact acceptance test of the previous sweep
 // Every decision is integer arithmetic, so results do not depend on the
 // order in which threads run.
+#include <type_traits>
+
 #include "prims.hpp"
 #include "sweep.hpp"
 
@@ -25,7 +29,7 @@ struct SweepArgs {
     const int32_t *c_cur;
     int32_t *c_nxt;
     const int64_t *delta;
-    const int64_t *deg;
+    const int64_t *deg;        // deg_C of the labelling read (read-only in the pass)
     const int32_t *size;
     int64_t tw;
     int singlet;
@@ -219,6 +223,351 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a, const int32_t 
     if (tid == 0 && s_I) atomicAdd(&a.st->acc_I, s_I);
 }
 
+// ---------------------------------------------------- thread-per-vertex kernel --
+
+// One thread per vertex of row length <= MAXD: the row is held in registers,
+// equal neighbour labels are merged by pairwise compares (fully unrolled),
+// and every load of a vertex (entries, neighbour labels, candidate degrees)
+// is independent of the others, so a wavefront keeps many in flight.  No
+// LDS and no barriers.  64-bit scores.
+template <int MAXD, typename W>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_sweep_thread(SweepArgs a, const int32_t *__restrict__ list,
+                                                      int64_t count) {
+    if (a.st->done) return;
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool active = k < count;
+    int64_t self = 0;
+    if (active) {
+        const int32_t v = list[k];
+        const int64_t rs = a.row_ptr[v];
+        const int d = (int)(a.row_ptr[v + 1] - rs);
+        const int32_t ci = a.c_cur[v];
+        const int64_t di = a.delta[v];
+        const int64_t deg_ci = a.deg[ci];
+        const int32_t size_ci = a.size[ci];
+        int32_t lab[MAXD];
+        int64_t w[MAXD];
+#pragma unroll
+        for (int p = 0; p < MAXD; ++p) {
+            lab[p] = -1;
+            w[p] = 0;
+            if (p < d) {
+                lab[p] = a.col[rs + p];
+                w[p] = wload<W>(a.w, rs + p);
+            }
+        }
+        int64_t loop = 0;
+#pragma unroll
+        for (int p = 0; p < MAXD; ++p) {
+            if (p < d) {
+                if (lab[p] == v) {
+                    loop += w[p];
+                    lab[p] = -1;
+                } else {
+                    lab[p] = a.c_cur[lab[p]];
+                }
+            }
+        }
+        // merge equal labels into their first occurrence
+        int64_t e_own = 0;
+#pragma unroll
+        for (int p = 0; p < MAXD; ++p) {
+            if (lab[p] == ci && lab[p] >= 0) {
+                e_own += w[p];
+                lab[p] = -1;
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < MAXD; ++p) {
+#pragma unroll
+            for (int q = p + 1; q < MAXD; ++q) {
+                if (lab[p] >= 0 && lab[q] == lab[p]) {
+                    w[p] += w[q];
+                    lab[q] = -1;
+                }
+            }
+        }
+        int64_t dg[MAXD];
+#pragma unroll
+        for (int p = 0; p < MAXD; ++p) dg[p] = lab[p] >= 0 ? a.deg[lab[p]] : 0;
+        int64_t bs = 0;
+        int32_t bl = -1;
+#pragma unroll
+        for (int p = 0; p < MAXD; ++p) {
+            if (lab[p] < 0) continue;
+            const int64_t sc = a.tw * w[p] - di * dg[p];
+            if (better<int64_t>(sc, lab[p], bs, bl)) {
+                bs = sc;
+                bl = lab[p];
+            }
+        }
+        int32_t nxt = ci;
+        if (bl >= 0 && bs > a.tw * e_own - di * (deg_ci - di)) {
+            nxt = bl;
+            if (a.singlet && size_ci == 1 && bl > ci && a.size[bl] == 1) nxt = ci;
+        }
+        a.c_nxt[v] = nxt;
+        self = e_own + loop;
+        if (a.e_self) a.e_self[v] = self;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) self += __shfl_xor(self, off);
+    if ((threadIdx.x & 63) == 0 && self) atomicAdd(&a.st->acc_I, (unsigned long long)self);
+}
+
+// ------------------------------------------------------- packed sweep kernel --
+
+// log2 of the LDS table size of a row of d >= 1 entries: smallest b >= 1
+// with 2^b >= 2d.
+__device__ __forceinline__ int pack_bits(int64_t d) {
+    return 64 - __clzll((unsigned long long)(2 * d - 1));
+}
+
+// Largest k in [0, n) with a[k] <= x (a strictly increasing, a[0] <= x).
+__device__ __forceinline__ int lds_find(const int32_t *a, int n, int32_t x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Add w under label k in the table of 2^bits slots at key/val (runtime
+// size); the thread that claims a slot records the table's owner vertex.
+__device__ __forceinline__ void lds_insert_rt(int32_t *key, unsigned long long *val, uint8_t *owner, int bits,
+                                             int32_t k, int64_t w, int own) {
+    const uint32_t mask = (1u << bits) - 1;
+    uint32_t h = ((uint32_t)k * 0x9E3779B1u) >> (32 - bits);
+    while (true) {
+        const int32_t cur = ((volatile int32_t *)key)[h];
+        if (cur == k) {
+            atomicAdd(&val[h], (unsigned long long)w);
+            return;
+        }
+        if (cur == kEmpty) {
+            const int32_t prev = atomicCAS(&key[h], kEmpty, k);
+            if (prev == kEmpty) owner[h] = (uint8_t)own;
+            if (prev == kEmpty || prev == k) {
+                atomicAdd(&val[h], (unsigned long long)w);
+                return;
+            }
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+// Line position cost of a packed vertex.
+__global__ void k_pack_cost(const int64_t *__restrict__ rp, const int32_t *__restrict__ list, int64_t m,
+                            int32_t *cost) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= m) return;
+    const int32_t v = list[k];
+    const int c = 1 << pack_bits(rp[v + 1] - rp[v]);
+    cost[k] = c > kPackMinCost ? c : kPackMinCost;
+}
+
+// first[b] = first packed vertex whose line position is >= b * kPackW
+// (b in [0, nblocks]; first[nblocks] = m).
+__global__ void k_pack_first(const int64_t *__restrict__ pos, int64_t m, int64_t nblocks, int64_t *first) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > nblocks) return;
+    const int64_t target = b * kPackW;
+    int64_t lo = 0, hi = m;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (pos[mid] < target) lo = mid + 1; else hi = mid;
+    }
+    first[b] = b == nblocks ? m : lo;
+}
+
+constexpr int kPackUnroll = 4;
+
+// Many vertices per workgroup, edges spread over all threads (independent
+// loads of kPackUnroll entries per thread in flight), per-vertex LDS tables,
+// scores stored back into the table and reduced with LDS atomics on an
+// order-preserving key (score with the sign bit flipped), ties broken by a
+// second pass of atomicMin on the label.  64-bit scores only.
+template <typename W>
+__global__ __launch_bounds__(256) void k_sweep_pack(SweepArgs a, const int32_t *__restrict__ list,
+                                                    const int64_t *__restrict__ pos,
+                                                    const int64_t *__restrict__ first) {
+    __shared__ int32_t s_key[kPackSlots];
+    __shared__ unsigned long long s_val[kPackSlots];
+    __shared__ uint8_t s_own[kPackSlots];
+    __shared__ int32_t s_v[256], s_ci[256], s_toff[256], s_eoff[257];
+    __shared__ int64_t s_rs[256], s_delta[256];
+    __shared__ int32_t s_bits[256];
+    __shared__ unsigned long long s_best[256], s_eown[256], s_loop[256];
+    __shared__ int32_t s_bestl[256];
+    __shared__ unsigned long long s_I;
+    if (a.st->done) return;
+    const int t = threadIdx.x;
+    const int64_t lo_pos = (int64_t)blockIdx.x * kPackW;
+    if (t == 0) s_I = 0;
+    for (int x = t; x < kPackSlots; x += 256) {
+        s_key[x] = kEmpty;
+        s_val[x] = 0;
+    }
+    const int64_t k0 = first[blockIdx.x];
+    const int nv = (int)(first[blockIdx.x + 1] - k0);
+    // vertex descriptors (thread t owns vertex t)
+    int32_t v = 0, ci = 0;
+    int64_t d = 0, di = 0, deg_ci = 0;
+    int32_t size_ci = 0;
+    if (t < nv) {
+        v = list[k0 + t];
+        const int64_t rs = a.row_ptr[v];
+        d = a.row_ptr[v + 1] - rs;
+        ci = a.c_cur[v];
+        di = a.delta[v];
+        s_v[t] = v;
+        s_ci[t] = ci;
+        s_rs[t] = rs;
+        s_delta[t] = di;
+        s_toff[t] = (int32_t)(pos[k0 + t] - lo_pos);
+        s_bits[t] = pack_bits(d);
+        s_best[t] = 0;
+        s_bestl[t] = 0x7fffffff;
+        s_eown[t] = 0;
+        s_loop[t] = 0;
+    }
+    {   // exclusive scan of row lengths -> edge offsets
+        __shared__ int32_t wsum[4];
+        const int lane = t & 63, wid = t >> 6;
+        int32_t x = (int32_t)d;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[wid] = x;
+        __syncthreads();
+        int32_t before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            if (w < wid) before += wsum[w];
+            total += wsum[w];
+        }
+        s_eoff[t] = before + x - (int32_t)d;
+        if (t == 0) s_eoff[256] = total;
+    }
+    if (t < nv) {   // loads for the decision, issued early
+        deg_ci = a.deg[ci];
+        size_ci = a.size[ci];
+    }
+    __syncthreads();
+    const int32_t E = s_eoff[256];
+    // entries: kPackUnroll independent loads per thread in flight
+    for (int32_t base = 0; base < E; base += 256 * kPackUnroll) {
+        int kk[kPackUnroll];
+        int64_t e[kPackUnroll];
+        int32_t j[kPackUnroll], lab[kPackUnroll];
+        int64_t w[kPackUnroll];
+#pragma unroll
+        for (int u = 0; u < kPackUnroll; ++u) {
+            const int32_t x = base + u * 256 + t;
+            kk[u] = -1;
+            if (x < E) {
+                kk[u] = lds_find(s_eoff, nv, x);
+                e[u] = s_rs[kk[u]] + (x - s_eoff[kk[u]]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kPackUnroll; ++u) {
+            if (kk[u] >= 0) {
+                j[u] = a.col[e[u]];
+                w[u] = wload<W>(a.w, e[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kPackUnroll; ++u) {
+            lab[u] = -1;
+            if (kk[u] >= 0 && j[u] != s_v[kk[u]]) lab[u] = a.c_cur[j[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kPackUnroll; ++u) {
+            if (kk[u] < 0) continue;
+            if (lab[u] < 0)
+                atomicAdd(&s_loop[kk[u]], (unsigned long long)w[u]);
+            else
+                lds_insert_rt(s_key + s_toff[kk[u]], s_val + s_toff[kk[u]], s_own + s_toff[kk[u]], s_bits[kk[u]],
+                              lab[u], w[u], kk[u]);
+        }
+    }
+    __syncthreads();
+    // scores: the own community is recorded and removed; every other
+    // candidate's score key is stored in place of its weight.  Each thread
+    // takes kPackSlots / 256 slots with all their deg_C gathers in flight.
+    constexpr int SPT = kPackSlots / 256;
+    const int32_t used = nv > 0 ? s_toff[nv - 1] + (1 << s_bits[nv - 1]) : 0;
+    {
+        int32_t key[SPT];
+        int kv[SPT];
+        int64_t ev[SPT], dg[SPT];
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+            const int32_t x = q * 256 + t;
+            key[q] = x < used ? s_key[x] : kEmpty;
+            kv[q] = 0;
+            ev[q] = 0;
+            if (key[q] != kEmpty) {
+                kv[q] = s_own[x];
+                ev[q] = (int64_t)s_val[x];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+            dg[q] = 0;
+            if (key[q] != kEmpty && key[q] != s_ci[kv[q]]) dg[q] = a.deg[key[q]];
+        }
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) {
+            if (key[q] == kEmpty) continue;
+            const int32_t x = q * 256 + t;
+            if (key[q] == s_ci[kv[q]]) {
+                s_eown[kv[q]] = (unsigned long long)ev[q];
+                s_key[x] = kEmpty;
+                continue;
+            }
+            const int64_t sc = a.tw * ev[q] - s_delta[kv[q]] * dg[q];
+            const unsigned long long ok = (unsigned long long)sc ^ 0x8000000000000000ull;
+            s_val[x] = ok;
+            atomicMax(&s_best[kv[q]], ok);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+        const int32_t x = q * 256 + t;
+        if (x >= used) continue;
+        const int32_t key = s_key[x];
+        if (key == kEmpty) continue;
+        const int kv = s_own[x];
+        if (s_val[x] == s_best[kv]) atomicMin(&s_bestl[kv], key);
+    }
+    __syncthreads();
+    if (t < nv) {
+        const int64_t e_own = (int64_t)s_eown[t];
+        const int64_t s_own = a.tw * e_own - di * (deg_ci - di);
+        int32_t nxt = ci;
+        if (s_best[t] != 0) {
+            const int64_t bs = (int64_t)(s_best[t] ^ 0x8000000000000000ull);
+            const int32_t bl = s_bestl[t];
+            if (bs > s_own) {
+                nxt = bl;
+                if (a.singlet && size_ci == 1 && bl > ci && a.size[bl] == 1) nxt = ci;
+            }
+        }
+        a.c_nxt[v] = nxt;
+        const int64_t self = e_own + (int64_t)s_loop[t];
+        if (a.e_self) a.e_self[v] = self;
+        if (self) atomicAdd(&s_I, (unsigned long long)self);
+    }
+    __syncthreads();
+    if (t == 0 && s_I) atomicAdd(&a.st->acc_I, s_I);
+}
+
 // ------------------------------------------------------------- hub kernels --
 
 // Hub metadata: 4 arrays of (hubs + 1) int64 laid out back to back.
@@ -228,18 +577,10 @@ struct HubMeta {
     const int64_t *chunk_off;// first accumulation block of each hub
     const int64_t *scan_off; // first scan block of each hub
     const int64_t *tab_size; // table slots of each hub (multiple of kHubScan, >= 2 * row length)
+    const int32_t *chunk_hub;// hub of each accumulation workgroup
+    const int32_t *scan_hub; // hub of each scan workgroup
     int64_t hubs;
 };
-
-// Largest h in [0, hubs) with off[h] <= b.
-__device__ __forceinline__ int64_t find_segment(const int64_t *off, int64_t hubs, int64_t b) {
-    int64_t lo = 0, hi = hubs - 1;
-    while (lo < hi) {
-        int64_t mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= b) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
 
 constexpr int kHubLdsBits = 11;  // 2048 slots for a chunk of kHubChunk = 1024 entries
 
@@ -254,7 +595,7 @@ __global__ __launch_bounds__(256) void k_hub_accum(SweepArgs a, HubMeta hm, int3
     __shared__ int64_t s_h;
     if (a.st->done) return;
     const int t = threadIdx.x;
-    if (t == 0) s_h = find_segment(hm.chunk_off, hm.hubs, blockIdx.x);
+    if (t == 0) s_h = hm.chunk_hub[blockIdx.x];
     for (int x = t; x < T; x += 256) {
         s_key[x] = kEmpty;
         s_val[x] = 0;
@@ -291,7 +632,7 @@ __global__ __launch_bounds__(256) void k_hub_scan(SweepArgs a, HubMeta hm, int32
     __shared__ int64_t s_h;
     if (a.st->done) return;
     const int t = threadIdx.x;
-    if (t == 0) s_h = find_segment(hm.scan_off, hm.hubs, blockIdx.x);
+    if (t == 0) s_h = hm.scan_hub[blockIdx.x];
     __syncthreads();
     const int64_t h = s_h;
     const int32_t v = hm.v[h];
@@ -365,6 +706,8 @@ __global__ __launch_bounds__(256) void k_hub_decide(SweepArgs a, HubMeta hm, con
 
 // --------------------------------------------------- commit, Q, acceptance --
 
+constexpr int kQsumTile = 2048;
+
 // Community degrees and sizes follow the movers (integer atomics, so the
 // result does not depend on their order).
 __global__ __launch_bounds__(256) void k_commit(const int32_t *__restrict__ c_cur, const int32_t *__restrict__ c_nxt,
@@ -390,9 +733,7 @@ __global__ __launch_bounds__(256) void k_commit(const int32_t *__restrict__ c_cu
     if (threadIdx.x == 0 && s_m) atomicAdd(&st->moved, s_m);
 }
 
-constexpr int kQsumTile = 2048;
-
-// Per-block partial sums of deg_C^2 (128-bit).
+// Per-block partial sums of deg_C^2 (128-bit) of the labelling a pass reads.
 __global__ __launch_bounds__(256) void k_qsum(const int64_t *__restrict__ deg, int64_t n, uint64_t *part,
                                               const PhaseState *st) {
     __shared__ uint64_t slo[4];
@@ -596,6 +937,13 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(const int64_t *__restric
     }
 }
 
+// hub_of[b] = h for every workgroup b in [off[h], off[h + 1]).
+__global__ void k_hub_map(const int64_t *__restrict__ off, int64_t hubs, int32_t *hub_of) {
+    const int64_t h = blockIdx.x;
+    if (h >= hubs) return;
+    for (int64_t b = off[h] + threadIdx.x; b < off[h + 1]; b += blockDim.x) hub_of[b] = (int32_t)h;
+}
+
 __global__ void k_hub_sizes(const int64_t *__restrict__ rp, const int32_t *__restrict__ hubv, int64_t hubs,
                             int64_t *tab_off, int64_t *chunk_off, int64_t *scan_off, int64_t *tab_size) {
     const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -623,6 +971,7 @@ void Sweeper::reserve(int64_t n, int64_t nnz) {
     qpart_.alloc((size_t)(2 * ((n + kQsumTile - 1) / kQsumTile) + 2));
     const int64_t max_hubs = nnz / (kBucketMax[NBUCKET - 2] + 1) + 1;
     hub_meta_.alloc((size_t)(4 * (max_hubs + 1)));
+    pack_pos_.alloc((size_t)n + 1);
     hub_loop_.alloc((size_t)max_hubs);
     cap_n_ = n;
     cap_nnz_ = nnz;
@@ -633,6 +982,7 @@ void Sweeper::plan(const GraphView &g) {
     const int64_t nblk = (g.n + kBucketTile - 1) / kBucketTile;
     for (int b = 0; b <= NBUCKET; ++b) bstart_[b] = 0;
     hubs_ = hub_chunks_ = hub_scans_ = hub_slots_ = 0;
+    pack_count_ = pack_blocks_ = 0;
     qblocks_ = (g.n + kQsumTile - 1) / kQsumTile;
     if (g.n == 0) return;
     TempBuf bnnz(NBUCKET * sizeof(unsigned long long), s_);
@@ -659,6 +1009,24 @@ void Sweeper::plan(const GraphView &g) {
     LV_HIP(hipStreamSynchronize(s_));
     for (int b = 0; b <= NBUCKET; ++b) bstart_[b] = hs[b];
     for (int b = 0; b < NBUCKET; ++b) bucket_nnz_[b] = (int64_t)hn[b];
+    // line positions of the packed vertices (buckets B_T16 to B_MID, contiguous in the list)
+    pack_count_ = bstart_[B_BLOCK] - bstart_[B_T16];
+    if (pack_count_ > 0 && g.tw <= kTwFastMax) {
+        TempBuf cost((size_t)pack_count_ * sizeof(int32_t), s_);
+        k_pack_cost<<<grid_for(pack_count_, 256), 256, 0, s_>>>(g.row_ptr, list_.p + bstart_[B_T16], pack_count_,
+                                                               cost.as<int32_t>());
+        LV_LAUNCHED("k_pack_cost");
+        scan_exclusive<int32_t, int64_t>(cost.as<int32_t>(), pack_pos_.p, pack_count_, pack_pos_.p + pack_count_,
+                                         s_, t_);
+        int64_t line = 0;
+        LV_HIP(hipMemcpyAsync(&line, pack_pos_.p + pack_count_, sizeof line, hipMemcpyDeviceToHost, s_));
+        LV_HIP(hipStreamSynchronize(s_));
+        pack_blocks_ = (line + kPackW - 1) / kPackW;
+        pack_first_.reserve((size_t)pack_blocks_ + 1);
+        k_pack_first<<<grid_for(pack_blocks_ + 1, 256), 256, 0, s_>>>(pack_pos_.p, pack_count_, pack_blocks_,
+                                                                      pack_first_.p);
+        LV_LAUNCHED("k_pack_first");
+    }
     hubs_ = bucket_count(B_HUB);
     if (hubs_ == 0) return;
     int64_t *tab_off = hub_meta_.p, *chunk_off = tab_off + (hubs_ + 1), *scan_off = chunk_off + (hubs_ + 1),
@@ -683,6 +1051,12 @@ void Sweeper::plan(const GraphView &g) {
         hub_slot_cap_ = hub_slots_;
     }
     hub_part_.reserve((size_t)(4 * hub_scans_));
+    hub_of_chunk_.reserve((size_t)hub_chunks_);
+    hub_of_scan_.reserve((size_t)hub_scans_);
+    k_hub_map<<<(unsigned)hubs_, 256, 0, s_>>>(chunk_off, hubs_, hub_of_chunk_.p);
+    LV_LAUNCHED("k_hub_map");
+    k_hub_map<<<(unsigned)hubs_, 256, 0, s_>>>(scan_off, hubs_, hub_of_scan_.p);
+    LV_LAUNCHED("k_hub_map");
     fill<int32_t>(hub_key_.p, kEmpty, hub_slots_, s_);
     fill<uint64_t>((uint64_t *)hub_val_.p, 0, hub_slots_, s_);
     fill<uint64_t>((uint64_t *)hub_loop_.p, 0, hubs_, s_);
@@ -691,7 +1065,8 @@ void Sweeper::plan(const GraphView &g) {
 void Sweeper::init_singletons(const GraphView &g) {
     if (g.n > 0) {
         TimedLaunch tl(t_, TG_LEVEL, "k_init_singletons", (double)g.n * 28);
-        k_init_singletons<<<grid_for(g.n, 256), 256, 0, s_>>>(c_[0].p, c_[1].p, c_[2].p, g.delta, deg_.p, size_.p, g.n);
+        k_init_singletons<<<grid_for(g.n, 256), 256, 0, s_>>>(c_[0].p, c_[1].p, c_[2].p, g.delta, deg_.p,
+                                                             size_.p, g.n);
         LV_LAUNCHED("k_init_singletons");
     }
     LV_HIP(hipMemsetAsync(st_.p, 0, sizeof(PhaseState), s_));
@@ -702,7 +1077,8 @@ void Sweeper::init_from_labels(const GraphView &g, const int32_t *labels) {
     fill<int32_t>(size_.p, 0, g.n, s_);
     if (g.n > 0) {
         TimedLaunch tl(t_, TG_LEVEL, "k_init_labels", (double)g.n * 28);
-        k_init_labels<<<grid_for(g.n, 256), 256, 0, s_>>>(c_[0].p, c_[1].p, c_[2].p, labels, g.delta, deg_.p, size_.p, g.n);
+        k_init_labels<<<grid_for(g.n, 256), 256, 0, s_>>>(c_[0].p, c_[1].p, c_[2].p, labels, g.delta, deg_.p,
+                                                         size_.p, g.n);
         LV_LAUNCHED("k_init_labels");
     }
     LV_HIP(hipMemsetAsync(st_.p, 0, sizeof(PhaseState), s_));
@@ -710,9 +1086,10 @@ void Sweeper::init_from_labels(const GraphView &g, const int32_t *labels) {
 
 template <typename W, typename S>
 static void launch_pass(const SweepArgs &a, const int32_t *list, const int64_t *bstart,
-                        const int64_t *bnnz, HubMeta hm, int64_t hub_chunks, int64_t hub_scans, int32_t *hkey,
-                        unsigned long long *hval, unsigned long long *hloop, uint64_t *hpart, hipStream_t s,
-                        Timer *t) {
+                        const int64_t *bnnz, const int64_t *pack_pos, const int64_t *pack_first,
+                        int64_t pack_blocks, HubMeta hm,
+                        int64_t hub_chunks, int64_t hub_scans, int32_t *hkey, unsigned long long *hval,
+                        unsigned long long *hloop, uint64_t *hpart, hipStream_t s, Timer *t) {
     const std::string sfx = t ? std::string(type_name<W>()) + "," + type_name<S>() + ">" : std::string();
     const std::string wsfx = t ? std::string(type_name<W>()) + ">" : std::string();
     const std::string ssfx = t ? std::string(type_name<S>()) + ">" : std::string();
@@ -720,25 +1097,46 @@ static void launch_pass(const SweepArgs &a, const int32_t *list, const int64_t *
     const double vb = 40.0;              // per evaluated vertex
     auto cnt = [&](int b) { return bstart[b + 1] - bstart[b]; };
     auto bytes = [&](int b) { return (double)cnt(b) * vb + (double)bnnz[b] * eb; };
-    if (cnt(B_G4) > 0) {
-        TimedLaunch tl(t, TG_SWEEP, "k_sweep_group<4,4,", bytes(B_G4), sfx.c_str());
-        k_sweep_group<4, 4, W, S><<<grid_for(cnt(B_G4), 64), 256, 0, s>>>(a, list + bstart[B_G4], cnt(B_G4));
-        LV_LAUNCHED("k_sweep_group<4>");
-    }
-    if (cnt(B_G16) > 0) {
-        TimedLaunch tl(t, TG_SWEEP, "k_sweep_group<16,6,", bytes(B_G16), sfx.c_str());
-        k_sweep_group<16, 6, W, S><<<grid_for(cnt(B_G16), 16), 256, 0, s>>>(a, list + bstart[B_G16], cnt(B_G16));
-        LV_LAUNCHED("k_sweep_group<16>");
-    }
-    if (cnt(B_G64) > 0) {
-        TimedLaunch tl(t, TG_SWEEP, "k_sweep_group<64,8,", bytes(B_G64), sfx.c_str());
-        k_sweep_group<64, 8, W, S><<<grid_for(cnt(B_G64), 4), 256, 0, s>>>(a, list + bstart[B_G64], cnt(B_G64));
-        LV_LAUNCHED("k_sweep_group<64>");
-    }
-    if (cnt(B_BLOCK) > 0) {
-        TimedLaunch tl(t, TG_SWEEP, "k_sweep_group<256,11,", bytes(B_BLOCK), sfx.c_str());
-        k_sweep_group<256, 11, W, S><<<(unsigned)cnt(B_BLOCK), 256, 0, s>>>(a, list + bstart[B_BLOCK], cnt(B_BLOCK));
-        LV_LAUNCHED("k_sweep_group<256>");
+    if constexpr (std::is_same<S, int64_t>::value) {
+        if (cnt(B_T8) > 0) {
+            TimedLaunch tl(t, TG_SWEEP, "k_sweep_thread<8,", bytes(B_T8), wsfx.c_str());
+            k_sweep_thread<8, W><<<grid_for(cnt(B_T8), 256), 256, 0, s>>>(a, list + bstart[B_T8], cnt(B_T8));
+            LV_LAUNCHED("k_sweep_thread<8>");
+        }
+        const int64_t np = bstart[B_BLOCK] - bstart[B_T16];
+        if (np > 0) {
+            TimedLaunch tl(t, TG_SWEEP, "k_sweep_pack<", bytes(B_T16) + bytes(B_G64) + bytes(B_MID), wsfx.c_str());
+            k_sweep_pack<W><<<(unsigned)pack_blocks, 256, 0, s>>>(a, list + bstart[B_T16], pack_pos, pack_first);
+            LV_LAUNCHED("k_sweep_pack");
+        }
+        if (cnt(B_BLOCK) > 0) {
+            TimedLaunch tl(t, TG_SWEEP, "k_sweep_group<256,11,", bytes(B_BLOCK), sfx.c_str());
+            k_sweep_group<256, 11, W, S><<<(unsigned)cnt(B_BLOCK), 256, 0, s>>>(a, list + bstart[B_BLOCK],
+                                                                                cnt(B_BLOCK));
+            LV_LAUNCHED("k_sweep_group<256>");
+        }
+    } else {
+        if (cnt(B_T8) > 0) {
+            TimedLaunch tl(t, TG_SWEEP, "k_sweep_group<4,4,", bytes(B_T8), sfx.c_str());
+            k_sweep_group<4, 4, W, S><<<grid_for(cnt(B_T8), 64), 256, 0, s>>>(a, list + bstart[B_T8], cnt(B_T8));
+            LV_LAUNCHED("k_sweep_group<4>");
+        }
+        if (cnt(B_T16) > 0) {
+            TimedLaunch tl(t, TG_SWEEP, "k_sweep_group<16,6,", bytes(B_T16), sfx.c_str());
+            k_sweep_group<16, 6, W, S><<<grid_for(cnt(B_T16), 16), 256, 0, s>>>(a, list + bstart[B_T16], cnt(B_T16));
+            LV_LAUNCHED("k_sweep_group<16>");
+        }
+        if (cnt(B_G64) > 0) {
+            TimedLaunch tl(t, TG_SWEEP, "k_sweep_group<64,8,", bytes(B_G64), sfx.c_str());
+            k_sweep_group<64, 8, W, S><<<grid_for(cnt(B_G64), 4), 256, 0, s>>>(a, list + bstart[B_G64], cnt(B_G64));
+            LV_LAUNCHED("k_sweep_group<64>");
+        }
+        const int64_t nb = bstart[B_HUB] - bstart[B_MID];
+        if (nb > 0) {
+            TimedLaunch tl(t, TG_SWEEP, "k_sweep_group<256,11,", bytes(B_MID) + bytes(B_BLOCK), sfx.c_str());
+            k_sweep_group<256, 11, W, S><<<(unsigned)nb, 256, 0, s>>>(a, list + bstart[B_MID], nb);
+            LV_LAUNCHED("k_sweep_group<256>");
+        }
     }
     if (hm.hubs > 0) {
         {
@@ -770,21 +1168,21 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
                 g.tw, prm.singlet, st_.p, e_self_out};
     int64_t *tab_off = hub_meta_.p;
     HubMeta hm{list_.p + bstart_[B_HUB], tab_off, tab_off + (hubs_ + 1), tab_off + 2 * (hubs_ + 1),
-               tab_off + 3 * (hubs_ + 1), hubs_};
+               tab_off + 3 * (hubs_ + 1), hub_of_chunk_.p, hub_of_scan_.p, hubs_};
     const bool fast = g.tw <= kTwFastMax;
     if (g.wbytes == 4) {
         if (fast)
-            launch_pass<int32_t, int64_t>(a, list_.p, bstart_, bucket_nnz_, hm, hub_chunks_, hub_scans_,
+            launch_pass<int32_t, int64_t>(a, list_.p, bstart_, bucket_nnz_, pack_pos_.p, pack_first_.p, pack_blocks_, hm, hub_chunks_, hub_scans_,
                                           hub_key_.p, hub_val_.p, hub_loop_.p, hub_part_.p, s_, t_);
         else
-            launch_pass<int32_t, i128>(a, list_.p, bstart_, bucket_nnz_, hm, hub_chunks_, hub_scans_,
+            launch_pass<int32_t, i128>(a, list_.p, bstart_, bucket_nnz_, pack_pos_.p, pack_first_.p, pack_blocks_, hm, hub_chunks_, hub_scans_,
                                        hub_key_.p, hub_val_.p, hub_loop_.p, hub_part_.p, s_, t_);
     } else {
         if (fast)
-            launch_pass<int64_t, int64_t>(a, list_.p, bstart_, bucket_nnz_, hm, hub_chunks_, hub_scans_,
+            launch_pass<int64_t, int64_t>(a, list_.p, bstart_, bucket_nnz_, pack_pos_.p, pack_first_.p, pack_blocks_, hm, hub_chunks_, hub_scans_,
                                           hub_key_.p, hub_val_.p, hub_loop_.p, hub_part_.p, s_, t_);
         else
-            launch_pass<int64_t, i128>(a, list_.p, bstart_, bucket_nnz_, hm, hub_chunks_, hub_scans_,
+            launch_pass<int64_t, i128>(a, list_.p, bstart_, bucket_nnz_, pack_pos_.p, pack_first_.p, pack_blocks_, hm, hub_chunks_, hub_scans_,
                                        hub_key_.p, hub_val_.p, hub_loop_.p, hub_part_.p, s_, t_);
     }
     if (g.n > 0) {

@@ -33,8 +33,21 @@ struct PhaseState {
 };
 
 // Degree buckets: row length d (entries incl. a loop) -> sweep kernel.
-enum { B_G4 = 0, B_G16, B_G64, B_BLOCK, B_HUB, NBUCKET };
-constexpr int64_t kBucketMax[NBUCKET - 1] = {8, 32, 128, 1024};
+// Row-length buckets.  64-bit scores: <= 8 and <= 16 one thread per vertex,
+// <= 512 packed workgroups, <= 1024 one workgroup per vertex, larger rows the
+// HBM hub path.  128-bit scores: lane groups of 4, 16, 64 and a workgroup.
+enum { B_T8 = 0, B_T16, B_G64, B_MID, B_BLOCK, B_HUB, NBUCKET };
+constexpr int64_t kBucketMax[NBUCKET - 1] = {8, 16, 128, 512, 1024};
+
+// Packed sweep: one workgroup evaluates up to 256 vertices of row length
+// <= kPackMaxDeg whose LDS tables (2^ceil(log2(2d)) slots each) fit
+// kPackSlots slots.  Vertices are laid out on a line by their cost
+// max(table size, kPackMinCost); workgroup b takes the vertices whose line
+// position falls in [b * kPackW, (b + 1) * kPackW).
+constexpr int kPackSlots = 2048;
+constexpr int kPackW = kPackSlots / 2;
+constexpr int kPackMinCost = kPackW / 256;
+constexpr int64_t kPackMaxDeg = kPackW / 2;
 constexpr int kHubChunk = 1024;      // row entries per hub accumulation workgroup
 constexpr int kHubScan = 1024;       // table slots per hub scan workgroup
 
@@ -56,7 +69,8 @@ class Sweeper {
     // Communities from labels (device int32[n]): ring slots = labels, deg/size recomputed.
     void init_from_labels(const GraphView &g, const int32_t *labels);
     // Enqueue sweep pass p >= 1: reads ring slot (p-1)%3, writes slot p%3,
-    // computes Q_int of the labelling it reads and runs the acceptance test.
+    // commits the movers to deg_C and sizes, computes Q_int of the labelling
+    // it reads and runs the acceptance test.
     void pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e_self_out);
     // Copy the control block to the host (synchronises the stream).
     PhaseState read_state();
@@ -70,7 +84,7 @@ class Sweeper {
     Timer *t_;
     int64_t cap_n_ = -1, cap_nnz_ = -1;
     DevBuf<int32_t> c_[3];
-    DevBuf<int64_t> deg_;
+    DevBuf<int64_t> deg_;           // deg_C by label (updated in place by the commit)
     DevBuf<int32_t> size_;
     DevBuf<int32_t> list_;          // vertices grouped by bucket, ascending inside a bucket
     DevBuf<int32_t> bcount_;        // bucketing scratch (per-block counts / offsets)
@@ -82,6 +96,11 @@ class Sweeper {
     DevBuf<unsigned long long> hub_val_;
     DevBuf<unsigned long long> hub_loop_;
     DevBuf<uint64_t> hub_part_;     // per scan block: score lo, score hi, label, e_own
+    DevBuf<int64_t> pack_pos_;      // line position of every packed vertex (+ total)
+    DevBuf<int64_t> pack_first_;    // first packed vertex of every packed workgroup (+ end)
+    DevBuf<int32_t> hub_of_chunk_;  // hub of every accumulation workgroup
+    DevBuf<int32_t> hub_of_scan_;   // hub of every scan workgroup
+    int64_t pack_count_ = 0, pack_blocks_ = 0;
     int64_t bstart_[NBUCKET + 1] = {0};
     int64_t bucket_nnz_[NBUCKET] = {0};
     int64_t hubs_ = 0, hub_chunks_ = 0, hub_scans_ = 0, hub_slots_ = 0;
