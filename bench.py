@@ -35,6 +35,140 @@ def log(msg):
     sys.stderr.flush()
 
 
+def _gen_chunk(args):
+    import graphgen as gg
+    kind, first, count, kw = args
+    fn = gg.batch_sbm if kind == "batch" else gg.served_chunglu
+    return fn(count, first=first, **kw)
+
+
+def generate(kind: str, count: int, workers: int, **kw) -> list:
+    """Seeded graphs generated in worker processes (forked before any GPU use)."""
+    import multiprocessing as mp
+    chunk = max(1, min(64, (count + 4 * workers - 1) // (4 * workers)))
+    jobs = [(kind, f, min(chunk, count - f), kw) for f in range(0, count, chunk)]
+    if workers <= 1:
+        parts = [_gen_chunk(j) for j in jobs]
+    else:
+        with mp.get_context("fork").Pool(workers) as pool:
+            parts = pool.map(_gen_chunk, jobs, chunksize=1)
+    return [g for part in parts for g in part]
+
+
+def percentile(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
+
+
+def bench_batched(L, torch, graphs, warmup: int):
+    """One louvain_run_batch call against the plain louvain_run loop on the
+    same device-resident graphs; outputs must be identical."""
+    ctx = L.Context(0)
+    dev = torch.device("cuda", 0)
+    Gs = [ctx.graph_create(g.row_ptr, g.col, g.w) for g in graphs]
+    out_p = [torch.empty(g.n, dtype=torch.int32, device=dev) for g in graphs]
+    out_b = [torch.empty(g.n, dtype=torch.int32, device=dev) for g in graphs]
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        ctx.run_batch(Gs, labels_out=out_b, stats=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain = [ctx.run(G, labels_out=o) for G, o in zip(Gs, out_p)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    res = ctx.run_batch(Gs, labels_out=out_b, stats=True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    same = all(torch.equal(a, b) for a, b in zip(out_p, out_b)) and \
+        all(p.q_int == r.q_int for p, r in zip(plain, res))
+    edges = sum(lv["sweeps_executed"] * lv["nnz"] for r in res for lv in r.stats["levels"])
+    for G in Gs:
+        G.destroy()
+    ctx.close()
+    tp, tb = t1 - t0, t2 - t1
+    return {"graphs": len(graphs), "n_total": int(sum(g.n for g in graphs)),
+            "nnz_total": int(sum(g.nnz for g in graphs)), "edges_swept": int(edges),
+            "plain_s": round(tp, 4), "batched_s": round(tb, 4), "speedup": round(tp / tb, 3),
+            "batched_gteps": round(edges / tb / 1e9, 4), "plain_gteps": round(edges / tp / 1e9, 4),
+            "identical_outputs": bool(same)}
+
+
+def bench_served(L, torch, pool, requests: int, load: float, seed: int = 1005):
+    """Request loop on a Poisson trace against the plain path on the same trace.
+
+    The plain path's per-graph times are measured alone; its latencies on the
+    trace follow from a first-come-first-served queue over those times."""
+    import numpy as np
+    ctx = L.Context(0)
+    dev = torch.device("cuda", 0)
+    res_in = [(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev), torch.from_numpy(g.w).to(dev))
+              for g in pool]
+    Gs = [ctx.graph_create(*t) for t in res_in]
+    outs = [torch.empty(g.n, dtype=torch.int32, device=dev) for g in pool]
+    torch.cuda.synchronize()
+    for G, o in zip(Gs, outs):           # warm-up
+        ctx.run(G, labels_out=o)
+    svc = []
+    ref_q = []
+    for G, o in zip(Gs, outs):
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        r = ctx.run(G, labels_out=o)
+        torch.cuda.synchronize()
+        svc.append(time.perf_counter() - a)
+        ref_q.append(r.q_int)
+    trace = [k % len(pool) for k in range(requests)]
+    mean_svc = float(np.mean([svc[k] for k in trace]))
+    capacity = 1.0 / mean_svc
+    rng = np.random.default_rng([seed, 7])
+
+    def run_trace(qps):
+        arrivals = np.zeros(len(trace)) if qps is None else np.cumsum(rng.exponential(1.0 / qps, len(trace)))
+        labels = [torch.empty(pool[k].n, dtype=torch.int32, device=dev) for k in trace]
+        tickets = []
+        t0 = time.perf_counter()
+        for i, k in enumerate(trace):
+            wait = t0 + arrivals[i] - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            rp, cl, w = res_in[k]
+            tickets.append(ctx.submit(rp, cl, w, labels_out=labels[i]))
+        done = {}
+        while len(done) < len(tickets):
+            for t in tickets:
+                if t not in done:
+                    r = ctx.poll(t, wait_us=1000)
+                    if r is not None:
+                        done[t] = r
+        lat = [(done[t].t_done_us - done[t].t_submit_us) / 1e6 for t in tickets]
+        span = (max(done[t].t_done_us for t in tickets) - min(done[t].t_submit_us for t in tickets)) / 1e6
+        ok = all(done[t].status in (0, -6) and done[t].q_int == ref_q[k] for t, k in zip(tickets, trace))
+        ok = ok and all(torch.equal(labels[i], outs[k]) for i, k in enumerate(trace))
+        return lat, span, ok, arrivals
+
+    lat_sat, span_sat, ok_sat, _ = run_trace(None)
+    qps = load * capacity
+    lat, span, ok, arrivals = run_trace(qps)
+    # the plain path on the same trace: one graph at a time, first come first served
+    fin = 0.0
+    plain_lat = []
+    for i, k in enumerate(trace):
+        fin = max(fin, arrivals[i]) + svc[k]
+        plain_lat.append(fin - arrivals[i])
+    for G in Gs:
+        G.destroy()
+    ctx.close()
+    return {"distinct_graphs": len(pool), "requests": requests,
+            "mean_nnz": int(np.mean([pool[k].nnz for k in trace])),
+            "plain_capacity_gps": round(capacity, 3),
+            "saturated_gps": round(len(trace) / span_sat, 3),
+            "saturated_speedup": round(len(trace) / span_sat / capacity, 3),
+            "trace_qps": round(qps, 3), "load": load,
+            "p50_s": round(percentile(lat, 50), 5), "p99_s": round(percentile(lat, 99), 5),
+            "plain_p50_s": round(percentile(plain_lat, 50), 5), "plain_p99_s": round(percentile(plain_lat, 99), 5),
+            "identical_outputs": bool(ok and ok_sat)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -44,6 +178,19 @@ def main():
     ap.add_argument("--pass-batch", type=int, default=0)
     ap.add_argument("--no-timing", action="store_true", help="time steps without per-kernel events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched", type=int, default=0,
+                    help="also compare one batched call on this many graphs of the batched SBM workload "
+                         "against the plain loop (4096 = the full workload)")
+    ap.add_argument("--batched-nmax", type=int, default=100_000)
+    ap.add_argument("--served", type=int, default=0,
+                    help="also run the request loop on a Poisson trace over this many distinct Chung-Lu "
+                         "request graphs")
+    ap.add_argument("--served-requests", type=int, default=0, help="trace length (default 4x the graphs)")
+    ap.add_argument("--served-load", type=float, default=0.7, help="trace QPS as a fraction of plain capacity")
+    ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1))
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB (for scaling the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -52,7 +199,31 @@ def main():
         sys.exit(2)
 
     import numpy as np
+
+    # graphs of the batched and served workloads, generated before any GPU use
+    batch_graphs = served_pool = None
+    if args.batched > 0:
+        t = time.time()
+        batch_graphs = generate("batch", args.batched, args.gen_workers, n_hi=args.batched_nmax)
+        log(f"generated {len(batch_graphs)} batched graphs, {sum(g.nnz for g in batch_graphs)} entries, "
+            f"in {time.time() - t:.1f}s")
+    if args.served > 0:
+        t = time.time()
+        served_pool = generate("served", args.served, args.gen_workers)
+        log(f"generated {len(served_pool)} request graphs, {sum(g.nnz for g in served_pool)} entries, "
+            f"in {time.time() - t:.1f}s")
+
     import torch
+
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {args.copy_calibration_mib} MiB three times")
+        return
 
     import graphgen as gg
     import paper_1805_10904_amd as L
@@ -95,6 +266,7 @@ def main():
 
     roofline = None
     sweep_gteps = None
+    kernel_ms = None
     if timing:
         agg = {}
         for res in results:
@@ -112,6 +284,9 @@ def main():
                     "launches_per_step": dom["launches"] / len(results)}
         top = sorted(agg.items(), key=lambda kv: -kv[1]["ms"])[:8]
         log("kernel time per step: " + ", ".join(f"{n} {a['ms'] / len(results):.3f} ms" for n, a in top))
+        kernel_ms = sum(a["ms"] for a in agg.values()) / len(results)
+        log(f"all kernels {kernel_ms:.3f} ms per step ({sum(a['launches'] for a in agg.values()) / len(results):.0f} "
+            f"launches); step {ms_per_step:.3f} ms")
 
     cpu = None
     parity = None
@@ -134,6 +309,18 @@ def main():
         parity = bool(np.array_equal(labels, ref.labels) and r.q_int == ref.q_int)
         log(f"oracle {spent / runs:.2f} s per run, parity {parity}")
 
+    batched = served = None
+    if batch_graphs is not None:
+        log("batched vs plain")
+        batched = bench_batched(L, torch, batch_graphs, warmup=1)
+        log(f"batched: {batched}")
+        del batch_graphs
+    if served_pool is not None:
+        log("served vs plain")
+        served = bench_served(L, torch, served_pool, args.served_requests or 4 * len(served_pool),
+                              args.served_load)
+        log(f"served: {served}")
+
     line = {
         "metric": METRIC, "value": round(value, 4), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
@@ -142,11 +329,16 @@ def main():
                    "edges_swept": edges, "parallelism": "single GPU"},
         "full_louvain_s": round(ms_per_step / 1000.0, 6),
         "sweep_gteps": None if sweep_gteps is None else round(sweep_gteps, 3),
+        "kernel_ms_per_step": None if kernel_ms is None else round(kernel_ms, 4),
         "q": r.q,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity,
     }
+    if batched is not None:
+        line["batched"] = batched
+    if served is not None:
+        line["served"] = served
     print(json.dumps(line))
 
 

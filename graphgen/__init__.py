@@ -29,7 +29,7 @@ import numpy as np
 __all__ = [
     "Graph", "splitmix64", "csr_from_canonical_keys", "canonical_keys",
     "weights_uniform", "weights_geometric", "sbm_dense", "sbm_sparse",
-    "chung_lu", "rmat", "random_small", "random_labels", "config",
+    "chung_lu", "rmat", "random_small", "random_labels", "config", "batch_sbm", "served_chunglu",
     "CONFIG_NAMES",
 ]
 
@@ -326,6 +326,46 @@ def random_labels(n: int, k: int, seed: int) -> np.ndarray:
 # --- the benchmark workloads -------------------------------------------------
 
 CONFIG_NAMES = ("sbm1k", "chunglu1m", "rmat24")
+
+
+def _log_uniform(rng: np.random.Generator, lo: float, hi: float) -> float:
+    return float(math.exp(rng.uniform(math.log(lo), math.log(hi))))
+
+
+def batch_sbm(count: int = 4096, seed: int = 1004, n_lo: int = 100, n_hi: int = 100_000, first: int = 0) -> list:
+    """Many independent SBM graphs of uneven sizes (the batched workload).
+
+    Graph g draws from its own stream (seed, g): n log-uniform in
+    [n_lo, n_hi], block count log-uniform in [2, 200] (at most n / 2), mean
+    degree log-uniform in [4, 64], mixing 0.3, weights uniform 1..10.
+    ``first`` skips the first graphs (graph g is the same in every call)."""
+    out = []
+    for g in range(first, first + count):
+        rng = np.random.default_rng([seed, g])
+        n = int(round(_log_uniform(rng, n_lo, n_hi)))
+        k = int(round(_log_uniform(rng, 2, 200)))
+        k = max(1, min(k, n // 2))
+        d = _log_uniform(rng, 4, 64)
+        out.append(sbm_sparse(n, k, d, 0.3, 10, rng, (seed << 32) ^ g, f"batch_sbm_{g}"))
+    return out
+
+
+def served_chunglu(count: int, seed: int = 1005, first: int = 0, n_lo: int = 1000,
+                   n_hi: int = 2_000_000) -> list:
+    """Requests of the served workload: Chung-Lu graphs with exponent uniform
+    in [2.1, 2.5], n log-uniform in [n_lo, n_hi], mean degree uniform in
+    [8, 32], planted blocks of about 4,096 vertices with mixing 0.3 and
+    weights uniform 1..50.  Request g draws its parameters from stream
+    (seed, g) and its structure from seed (seed << 32) | g."""
+    out = []
+    for g in range(first, first + count):
+        rng = np.random.default_rng([seed, g])
+        gamma = float(rng.uniform(2.1, 2.5))
+        n = int(round(_log_uniform(rng, n_lo, n_hi)))
+        d = float(rng.uniform(8.0, 32.0))
+        out.append(chung_lu(n, gamma, d, max(1, n // 4096), 0.3, (seed << 32) | g,
+                            lambda h: weights_uniform(h, 50), f"served_{g}"))
+    return out
 
 
 def config(name: str) -> Graph:

@@ -42,6 +42,7 @@ extern "C" {
 #define LOUVAIN_EINVAL    (-1)  /* invalid argument or malformed graph          */
 #define LOUVAIN_ENOMEM    (-2)  /* device or host allocation failed             */
 #define LOUVAIN_EDEVICE   (-3)  /* HIP runtime error                            */
+#define LOUVAIN_EAGAIN    (-4)  /* poll: the request is still pending            */
 #define LOUVAIN_ELIMIT    (-6)  /* max_sweeps / max_levels reached; result valid */
 #define LOUVAIN_EOVERFLOW (-7)  /* n >= 2^31 or TW >= 2^62                      */
 
@@ -210,6 +211,99 @@ int louvain_aggregate(louvain_ctx ctx, louvain_graph g, const int32_t *labels,
 int louvain_run(louvain_ctx ctx, louvain_graph g, const louvain_params *params,
                 int32_t *labels_out, louvain_i128 *q_int, double *q,
                 louvain_run_stats *stats, uint32_t flags);
+
+/*
+ * Batched form of louvain_run: the method on ngraphs independent graphs in
+ * one call.  The graphs' current level graphs are swept, renumbered and
+ * contracted together as one block-diagonal union (one set of launches per
+ * sweep pass and per level for all of them), while every graph keeps its own
+ * 2W, modularity, acceptance test, phase end, level count and community
+ * numbering, so each graph's outputs are the ones louvain_run gives for it
+ * alone.  The paper treats one graph; batching is this library's extension
+ * of Alg. 2 to many graphs.
+ *   graphs:     ngraphs handles created on ctx (not modified).
+ *   params:     as for louvain_run, shared by all graphs.
+ *   labels_out: ngraphs pointers; labels_out[i] is int32[n_i], host or
+ *               device per flags (LOUVAIN_DEVICE_PTRS).
+ *   q_int, q, status:
+ *               optional arrays of ngraphs: per-graph Q_int, Q and status
+ *               (LOUVAIN_OK or LOUVAIN_ELIMIT).
+ *   stats:      optional array of ngraphs records (per-level fields as for
+ *               louvain_run; the ms fields stay 0).  If stats[0].timing is 1
+ *               on entry, stats[0] also receives the kernel table and
+ *               ms_total of the whole call.
+ * Graphs with 2W >= 2^31 are run one at a time through the plain path
+ * before the batch.  Returns LOUVAIN_OK, LOUVAIN_ELIMIT (some graph hit a
+ * cap; see status), or an error; after an error, outputs of graphs that
+ * were run alone before the batch may already be written, the others are
+ * untouched.
+ */
+int louvain_run_batch(louvain_ctx ctx, int64_t ngraphs, const louvain_graph *graphs,
+                      const louvain_params *params, int32_t *const *labels_out,
+                      louvain_i128 *q_int, double *q, int32_t *status,
+                      louvain_run_stats *stats, uint32_t flags);
+
+/* ---- served form --------------------------------------------------------- */
+
+/* Result of one served request (louvain_poll). */
+typedef struct {
+    int32_t status;               /* LOUVAIN_OK, LOUVAIN_ELIMIT or the request's error     */
+    int32_t levels;               /* phases executed                                       */
+    int64_t n, nnz;               /* the submitted graph                                   */
+    int64_t total_edges_swept;    /* sum over device passes of the level's nnz             */
+    louvain_i128 q_int;           /* Q_int of the final labels                             */
+    double q;                     /* Q = Q_int / (2W)^2                                    */
+    double t_submit_us;           /* submit, admission and completion times (steady clock, */
+    double t_admit_us;            /*   microseconds; differences are latencies)            */
+    double t_done_us;
+    louvain_level_stats level[64];/* per-level records as for louvain_run (ms fields 0)    */
+    char error[128];              /* message of a failed request                           */
+} louvain_request_result;
+
+/* Estimated peak device bytes one graph of n vertices and nnz entries holds
+ * while it is served (its resident CSR and its share of the batch's level
+ * buffers); the request loop admits graphs while the sum fits its budget.
+ * Contraction never grows a graph (every level has at most the previous
+ * level's vertices and entries), so the level-0 estimate bounds the run. */
+size_t louvain_workspace_bytes(int64_t n, int64_t nnz);
+
+/* Device-memory budget of ctx's request loop (0 = 80% of the free device
+ * memory when the loop starts). */
+int louvain_serve_budget(louvain_ctx ctx, size_t hbm_bytes);
+
+/*
+ * Queue the method on one graph for the context's request loop, which a
+ * worker thread runs on its own stream.  Requests are admitted in arrival
+ * order while their louvain_workspace_bytes fit the budget; an admitted
+ * graph joins the running batch at the next level boundary, beside graphs
+ * already at deeper levels (continuous batching), and its result equals
+ * louvain_run on that graph alone.  Requests with different params are
+ * batched separately.
+ *   n, nnz, row_ptr, col_idx, weight, flags: as for louvain_graph_create;
+ *               the arrays are read when the request is admitted and must
+ *               stay valid (and, for device pointers, complete on their
+ *               streams) until louvain_poll has delivered the result.
+ *   params:     as for louvain_run (NULL = defaults).
+ *   labels_out: int32[n], host or device per flags; written before the
+ *               result is delivered.
+ *   ticket:     receives the request's id for louvain_poll.
+ * Thread-safe; does not set louvain_last_error.  Returns LOUVAIN_OK,
+ * LOUVAIN_EINVAL / LOUVAIN_EOVERFLOW for bad arguments (nothing queued),
+ * LOUVAIN_ENOMEM or LOUVAIN_EDEVICE.  Malformed graphs fail at admission
+ * (their result carries the error); a failing request does not disturb the
+ * others.
+ */
+int louvain_submit(louvain_ctx ctx, int64_t n, int64_t nnz, const int64_t *row_ptr,
+                   const int32_t *col_idx, const void *weight, const louvain_params *params,
+                   int32_t *labels_out, uint32_t flags, uint64_t *ticket);
+
+/*
+ * Wait up to wait_us microseconds (0 = do not wait, < 0 = without limit)
+ * for a request.  Returns LOUVAIN_EAGAIN while it is pending; otherwise
+ * fills *result (optional), retires the ticket and returns the request's
+ * status.  Unknown or retired tickets: LOUVAIN_EINVAL.  Thread-safe.
+ */
+int louvain_poll(louvain_ctx ctx, uint64_t ticket, int32_t wait_us, louvain_request_result *result);
 
 #ifdef __cplusplus
 }

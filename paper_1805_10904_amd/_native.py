@@ -13,6 +13,7 @@ LOUVAIN_OK = 0
 LOUVAIN_EINVAL = -1
 LOUVAIN_ENOMEM = -2
 LOUVAIN_EDEVICE = -3
+LOUVAIN_EAGAIN = -4
 LOUVAIN_ELIMIT = -6
 LOUVAIN_EOVERFLOW = -7
 
@@ -25,7 +26,8 @@ LOUVAIN_WEIGHTS_I64 = 0x8
 ABI_SYMBOLS = (
     "louvain_ctx_create", "louvain_ctx_destroy", "louvain_last_error",
     "louvain_graph_create", "louvain_graph_destroy", "louvain_graph_info", "louvain_graph_export",
-    "louvain_local_move", "louvain_modularity", "louvain_aggregate", "louvain_run",
+    "louvain_local_move", "louvain_modularity", "louvain_aggregate", "louvain_run", "louvain_run_batch",
+    "louvain_workspace_bytes", "louvain_serve_budget", "louvain_submit", "louvain_poll",
 )
 
 
@@ -50,6 +52,13 @@ class louvain_level_stats(C.Structure):
 class louvain_kernel_stats(C.Structure):
     _fields_ = [("name", C.c_char * 40), ("launches", C.c_int64), ("ms", C.c_double),
                 ("alg_bytes", C.c_double)]
+
+
+class louvain_request_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("levels", C.c_int32), ("n", C.c_int64), ("nnz", C.c_int64),
+                ("total_edges_swept", C.c_int64), ("q_int", louvain_i128), ("q", C.c_double),
+                ("t_submit_us", C.c_double), ("t_admit_us", C.c_double), ("t_done_us", C.c_double),
+                ("level", louvain_level_stats * 64), ("error", C.c_char * 128)]
 
 
 class louvain_run_stats(C.Structure):
@@ -90,8 +99,14 @@ def load_library(path: str = LIB_PATH):
     lib.louvain_aggregate.argtypes = [p, p, p, p, C.POINTER(p), u32]
     lib.louvain_run.argtypes = [p, p, C.POINTER(louvain_params), p, C.POINTER(louvain_i128), p,
                                 C.POINTER(louvain_run_stats), u32]
+    lib.louvain_run_batch.argtypes = [p, i64, p, C.POINTER(louvain_params), p, p, p, p, p, u32]
+    lib.louvain_workspace_bytes.argtypes = [i64, i64]
+    lib.louvain_workspace_bytes.restype = C.c_size_t
+    lib.louvain_serve_budget.argtypes = [p, C.c_size_t]
+    lib.louvain_submit.argtypes = [p, i64, i64, p, p, p, C.POINTER(louvain_params), p, u32, C.POINTER(C.c_uint64)]
+    lib.louvain_poll.argtypes = [p, C.c_uint64, C.c_int32, C.POINTER(louvain_request_result)]
     for f in ABI_SYMBOLS:
-        if f != "louvain_last_error":
+        if f not in ("louvain_last_error", "louvain_workspace_bytes"):
             getattr(lib, f).restype = C.c_int
     if path == LIB_PATH:
         _lib = lib
@@ -142,6 +157,24 @@ class RunResult(NamedTuple):
     q: float
     status: int          # LOUVAIN_OK or LOUVAIN_ELIMIT
     stats: dict
+
+
+class ServeResult(NamedTuple):
+    labels: object       # int32[n] final dense community IDs (numpy or torch)
+    q_int: int
+    q: float
+    status: int          # LOUVAIN_OK, LOUVAIN_ELIMIT or the request's error
+    levels: list         # per-level records
+    total_edges_swept: int
+    t_submit_us: float   # library steady clock
+    t_admit_us: float
+    t_done_us: float
+    error: str
+
+
+def workspace_bytes(n: int, nnz: int) -> int:
+    """Device bytes the request loop budgets for a graph of n vertices and nnz entries."""
+    return int(load_library().louvain_workspace_bytes(n, nnz))
 
 
 class Graph:
@@ -199,6 +232,7 @@ class Context:
         if rc != LOUVAIN_OK:
             raise LouvainError(rc, "louvain_ctx_create failed")
         self.h = h
+        self._inflight = {}
 
     def _check(self, rc: int, ok=(LOUVAIN_OK,)):
         if rc not in ok:
@@ -240,6 +274,56 @@ class Context:
         self._check(self.lib.louvain_graph_create(self.h, n, nnz, _ptr(keep[0]), _ptr(keep[1]),
                                                   _ptr(keep[2]), flags, C.byref(h)))
         return Graph(self, h, dev)
+
+    def serve_budget(self, nbytes: int):
+        """Device-memory budget of the request loop (0: 80% of free memory at start)."""
+        self._check(self.lib.louvain_serve_budget(self.h, int(nbytes)))
+
+    def submit(self, row_ptr, col, w, theta_num: int = 1, theta_den: int = 1_000_000, max_sweeps: int = 1000,
+               max_levels: int = 64, singlet_rule: bool = True, pass_batch: int = 0, labels_out=None,
+               check_symmetry: bool = False) -> int:
+        """Queue one graph for the request loop; returns a ticket for poll().
+
+        The arrays are kept referenced until the result is polled.  Device
+        (torch) inputs must be complete on their streams before the call."""
+        dev = _is_torch(row_ptr) and row_ptr.is_cuda
+        if dev:
+            n = row_ptr.shape[0] - 1
+            nnz = col.shape[0]
+            wide = str(w.dtype) == "torch.int64"
+        else:
+            row_ptr = _host(row_ptr, np.int64)
+            col = _host(col, np.int32)
+            wide = np.asarray(w).dtype == np.int64
+            w = _host(w, np.int64 if wide else np.int32)
+            n = row_ptr.shape[0] - 1
+            nnz = col.shape[0]
+        out = labels_out if labels_out is not None else _empty_like_kind(dev, n, np.int32, self.torch_device)
+        flags = (LOUVAIN_DEVICE_PTRS if dev else 0) | (LOUVAIN_CHECK_SYMMETRY if check_symmetry else 0) \
+            | (LOUVAIN_WEIGHTS_I64 if wide else 0)
+        prm = louvain_params(theta_num, theta_den, max_sweeps, max_levels, 1 if singlet_rule else 0, pass_batch)
+        t = C.c_uint64()
+        rc = self.lib.louvain_submit(self.h, n, nnz, _ptr(row_ptr), _ptr(col), _ptr(w), C.byref(prm), _ptr(out),
+                                     flags, C.byref(t))
+        if rc != LOUVAIN_OK:
+            raise LouvainError(rc, "submit rejected the request")
+        self._inflight[t.value] = (row_ptr, col, w, out)
+        return t.value
+
+    def poll(self, ticket: int, wait_us: int = 0) -> Optional["ServeResult"]:
+        """None while pending; the ServeResult once done (the ticket is then retired).
+        A failed request is returned with its status and error text."""
+        res = louvain_request_result()
+        rc = self.lib.louvain_poll(self.h, ticket, int(wait_us), C.byref(res))
+        if rc == LOUVAIN_EAGAIN:
+            return None
+        if rc == LOUVAIN_EINVAL and ticket not in self._inflight:
+            raise LouvainError(rc, f"unknown ticket {ticket}")
+        keep = self._inflight.pop(ticket)
+        levels = [dict(n=lv.n, nnz=lv.nnz, sweeps_executed=lv.sweeps_executed, sweeps_accepted=lv.sweeps_accepted,
+                       gpu_passes=lv.gpu_passes, q_int=lv.q_int.value()) for lv in res.level[:res.levels]]
+        return ServeResult(keep[3], res.q_int.value(), res.q, rc, levels, res.total_edges_swept,
+                           res.t_submit_us, res.t_admit_us, res.t_done_us, res.error.decode(errors="replace"))
 
     def _labels(self, labels, dev):
         if labels is None:
@@ -295,6 +379,42 @@ class Context:
                                               C.byref(st), LOUVAIN_DEVICE_PTRS if dev else 0),
                          ok=(LOUVAIN_OK, LOUVAIN_ELIMIT))
         return RunResult(out, qi.value(), q.value, rc, stats_dict(st))
+
+
+    def run_batch(self, graphs, theta_num: int = 1, theta_den: int = 1_000_000, max_sweeps: int = 1000,
+                  max_levels: int = 64, singlet_rule: bool = True, pass_batch: int = 0, timing: bool = False,
+                  stats: bool = True, device: Optional[bool] = None, labels_out=None):
+        """The whole method on many graphs in one call (one RunResult per graph).
+
+        stats=False skips the per-graph statistics records (about 9 KB each).
+        With timing=True the first result's stats hold the call's kernel table.
+        """
+        k = len(graphs)
+        if k == 0:
+            return []
+        dev = graphs[0].dev if device is None else device
+        outs = []
+        for i, g in enumerate(graphs):
+            if labels_out is not None:
+                outs.append(labels_out[i])
+            else:
+                n, _, _ = g.info()
+                outs.append(_empty_like_kind(dev, n, np.int32, self.torch_device))
+        prm = louvain_params(theta_num, theta_den, max_sweeps, max_levels, 1 if singlet_rule else 0, pass_batch)
+        handles = (C.c_void_p * k)(*[g.h for g in graphs])
+        ptrs = (C.c_void_p * k)(*[_ptr(o) for o in outs])
+        qi = (louvain_i128 * k)()
+        q = (C.c_double * k)()
+        status = (C.c_int32 * k)()
+        st = None
+        if stats or timing:
+            st = (louvain_run_stats * k)()
+            st[0].timing = 1 if timing else 0
+        self._check(self.lib.louvain_run_batch(self.h, k, handles, C.byref(prm), ptrs, qi, q, status,
+                                               st, LOUVAIN_DEVICE_PTRS if dev else 0),
+                    ok=(LOUVAIN_OK, LOUVAIN_ELIMIT))
+        return [RunResult(outs[i], qi[i].value(), q[i], status[i], stats_dict(st[i]) if st is not None else None)
+                for i in range(k)]
 
 
 def stats_dict(st: louvain_run_stats) -> dict:

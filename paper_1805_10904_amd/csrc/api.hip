@@ -2,10 +2,14 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 
+#include "batch.hpp"
 #include "contract.hpp"
+#include "driver.hpp"
 #include "prims.hpp"
+#include "serve.hpp"
 #include "sweep.hpp"
 
 struct louvain_ctx_s {
@@ -14,6 +18,9 @@ struct louvain_ctx_s {
     hipStream_t stream = nullptr;
     std::string err;
     lv::Timer timer;
+    std::mutex serve_mu;                  // guards server creation and serve_budget
+    size_t serve_budget = 0;              // 0: a share of the device's free memory
+    std::unique_ptr<lv::Server> server;   // request loop, started by the first submit
 };
 
 struct louvain_graph_s {
@@ -135,6 +142,43 @@ double q_of(lv::i128 q_int, int64_t tw) {
     return tw ? (double)q_int / ((double)tw * (double)tw) : 0.0;
 }
 
+louvain_params checked_params(const louvain_params *params) {
+    louvain_params prm{1, 1000000, 1000, 64, 1, 0};
+    if (params) prm = *params;
+    require(prm.theta_num >= 0 && prm.theta_den > 0, LOUVAIN_EINVAL, "theta must be num >= 0, den > 0");
+    require(prm.max_sweeps >= 0 && prm.max_levels >= 1 && prm.max_levels <= 64, LOUVAIN_EINVAL,
+            "max_sweeps must be >= 0 and max_levels in [1, 64]");
+    return prm;
+}
+
+lv::SweepParams sweep_params(const louvain_params &prm) {
+    lv::SweepParams sp;
+    sp.theta_num = prm.theta_num;
+    sp.theta_den = prm.theta_den;
+    sp.max_sweeps = prm.max_sweeps;
+    sp.singlet = prm.singlet_rule ? 1 : 0;
+    return sp;
+}
+
+// A finished batch member's record in the ABI's form.
+void member_stats(const lv::BatchMember &m, int32_t timing, louvain_run_stats *st) {
+    memset(st, 0, sizeof *st);
+    st->timing = timing;
+    st->levels = (int32_t)m.levels.size();
+    st->status = m.status;
+    st->total_edges_swept = m.edges_swept;
+    for (size_t l = 0; l < m.levels.size() && l < 64; ++l) {
+        const lv::LevelRec &r = m.levels[l];
+        louvain_level_stats &ls = st->level[l];
+        ls.n = r.n;
+        ls.nnz = r.nnz;
+        ls.sweeps_executed = r.executed;
+        ls.sweeps_accepted = r.accepted;
+        ls.gpu_passes = r.passes;
+        ls.q_int = to_abi(r.q);
+    }
+}
+
 // Aggregate the timer's records into per-family statistics.
 void collect_kernel_stats(lv::Timer &t, louvain_run_stats *st, size_t first, size_t last, double *ms_sweep,
                           double *ms_contract) {
@@ -164,6 +208,134 @@ void collect_kernel_stats(lv::Timer &t, louvain_run_stats *st, size_t first, siz
 
 }  // namespace
 
+namespace lv {
+
+// Alg. 2 on one graph: phases of sweeps, renumbering and contraction until a
+// phase keeps no sweep.  fin_p (device int32[n]) receives the final labels.
+int run_plain(const GraphView &g0, const louvain_params &prm, hipStream_t s, Timer &timer, bool timing, int32_t *fin_p,
+              i128 *q_out, louvain_run_stats *stats_out) {
+    int status = LOUVAIN_OK;
+    const int batch = prm.pass_batch > 0 ? prm.pass_batch : 1;
+    timer.on = timing;
+    timer.reset();
+    lv::Timer *t = timing ? &timer : nullptr;
+    louvain_run_stats local;
+    memset(&local, 0, sizeof local);
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (timing) {
+        LV_HIP(hipEventCreate(&ev0));
+        LV_HIP(hipEventCreate(&ev1));
+        LV_HIP(hipEventRecord(ev0, s));
+    }
+    struct EvGuard {
+        hipEvent_t a, b;
+        ~EvGuard() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } evg{ev0, ev1};
+
+    const int64_t n0 = g0.n, nnz0 = g0.nnz;
+    lv::iota_i32(fin_p, n0, s);
+    lv::i128 q_final = 0;
+    lv::GraphView v = g0;
+    if (g0.tw > 0) {
+        lv::Sweeper sw(s, t);
+        lv::Contractor ct(s, t);
+        sw.reserve(n0, nnz0);
+        ct.reserve(n0, nnz0);
+        DevBuf<int32_t> newlab((size_t)n0);
+        struct LevelGraph {
+            DevBuf<int64_t> rp, delta, w;
+            DevBuf<int32_t> col;
+        } lg[2];
+        int which = 0;
+        const lv::SweepParams sp = sweep_params(prm);
+        for (int level = 0; level < prm.max_levels; ++level) {
+            const size_t rec0 = timer.recs.size();
+            sw.plan(v);
+            sw.init_singletons(v);
+            lv::PhaseState st;
+            int p = 0;
+            for (;;) {
+                for (int b = 0; b < batch; ++b) sw.pass(v, ++p, sp, nullptr);
+                st = sw.read_state();
+                if (st.done) break;
+                require(p <= prm.max_sweeps + 4 + batch, LOUVAIN_EDEVICE, "sweep loop did not converge");
+            }
+            auto &ls = local.level[level];
+            ls.n = v.n;
+            ls.nnz = v.nnz;
+            ls.sweeps_accepted = st.accepted;
+            ls.sweeps_executed = st.accepted + (st.limit ? 0 : 1);
+            ls.gpu_passes = st.pass;
+            ls.q_int.lo = st.q_ref[0];
+            ls.q_int.hi = (int64_t)st.q_ref[1];
+            local.total_edges_swept += (int64_t)st.pass * v.nnz;
+            local.levels = level + 1;
+            q_final = lv::make_i128(st.q_ref[0], (int64_t)st.q_ref[1]);
+            if (st.limit) status = LOUVAIN_ELIMIT;
+            if (st.accepted == 0) {
+                if (timing) {
+                    LV_HIP(hipStreamSynchronize(s));
+                    collect_kernel_stats(timer, nullptr, rec0, timer.recs.size(), &ls.ms_sweep, &ls.ms_contract);
+                }
+                break;
+            }
+            const int32_t *cfin = sw.slot(st.final_slot);
+            const int64_t k = ct.renumber(cfin, v.n, newlab.p);
+            ct.compose(fin_p, n0, newlab.p);
+            if (level + 1 >= prm.max_levels) {
+                status = LOUVAIN_ELIMIT;
+                if (timing) {
+                    LV_HIP(hipStreamSynchronize(s));
+                    collect_kernel_stats(timer, nullptr, rec0, timer.recs.size(), &ls.ms_sweep, &ls.ms_contract);
+                }
+                break;
+            }
+            LevelGraph &nb = lg[which];
+            if (!nb.rp.p) {
+                nb.rp.alloc((size_t)n0 + 1);
+                nb.delta.alloc((size_t)n0);
+                nb.w.alloc((size_t)nnz0);
+                nb.col.alloc((size_t)nnz0);
+            }
+            const int64_t m2 = ct.contract(v, newlab.p, k, nb.rp.p, nb.col.p, nb.w.p);
+            lv::row_sums_i64(k, m2, nb.rp.p, nb.w.p, nb.delta.p, s, t);
+            lv::GraphView v2;
+            v2.n = k;
+            v2.nnz = m2;
+            v2.row_ptr = nb.rp.p;
+            v2.col = nb.col.p;
+            v2.w = nb.w.p;
+            v2.wbytes = 8;
+            v2.delta = nb.delta.p;
+            v2.tw = g0.tw;
+            v = v2;
+            which = 1 - which;
+            if (timing) {
+                LV_HIP(hipStreamSynchronize(s));
+                collect_kernel_stats(timer, nullptr, rec0, timer.recs.size(), &ls.ms_sweep, &ls.ms_contract);
+            }
+        }
+    }
+    local.status = status;
+    if (timing) {
+        LV_HIP(hipEventRecord(ev1, s));
+        LV_HIP(hipStreamSynchronize(s));
+        float ms = 0;
+        LV_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+        local.ms_total = ms;
+        collect_kernel_stats(timer, &local, 0, timer.recs.size(), nullptr, nullptr);
+    }
+    timer.on = false;
+    *q_out = q_final;
+    *stats_out = local;
+    return status;
+}
+
+}  // namespace lv
+
 extern "C" {
 
 int louvain_ctx_create(int device, void *hip_stream, louvain_ctx *out) {
@@ -186,6 +358,7 @@ int louvain_ctx_create(int device, void *hip_stream, louvain_ctx *out) {
 int louvain_ctx_destroy(louvain_ctx ctx) {
     if (!ctx) return LOUVAIN_EINVAL;
     (void)hipSetDevice(ctx->device);
+    ctx->server.reset();   // stops the request loop first
     delete ctx;
     return LOUVAIN_OK;
 }
@@ -286,6 +459,7 @@ int louvain_local_move(louvain_ctx ctx, louvain_graph g, const int32_t *labels, 
         lv::SweepParams prm;
         prm.singlet = (flags & LOUVAIN_NO_SINGLET) ? 0 : 1;
         sw.pass(v, 1, prm, eself.p);
+        if (sw.compact()) sw.e_self_out(eself.p);
         LV_HIP(hipStreamSynchronize(s));
         const bool dev = device_ptrs(flags);
         copy_out(labels_out, sw.slot(1), g->n, dev, s);
@@ -345,134 +519,14 @@ int louvain_run(louvain_ctx ctx, louvain_graph g, const louvain_params *params, 
     const int rc = guarded(ctx, [&] {
         require(g != nullptr && g->ctx == ctx, LOUVAIN_EINVAL, "graph missing or from another context");
         require(labels_out != nullptr || g->n == 0, LOUVAIN_EINVAL, "labels_out must not be NULL");
-        louvain_params prm{1, 1000000, 1000, 64, 1, 0};
-        if (params) prm = *params;
-        require(prm.theta_num >= 0 && prm.theta_den > 0, LOUVAIN_EINVAL, "theta must be num >= 0, den > 0");
-        require(prm.max_sweeps >= 0 && prm.max_levels >= 1 && prm.max_levels <= 64, LOUVAIN_EINVAL,
-                "max_sweeps must be >= 0 and max_levels in [1, 64]");
-        const int batch = prm.pass_batch > 0 ? prm.pass_batch : 1;
+        const louvain_params prm = checked_params(params);
         hipStream_t s = ctx->stream;
-        lv::Timer &timer = ctx->timer;
         const bool timing = stats && stats->timing;
-        timer.on = timing;
-        timer.reset();
-        lv::Timer *t = timing ? &timer : nullptr;
         louvain_run_stats local;
-        memset(&local, 0, sizeof local);
-        hipEvent_t ev0 = nullptr, ev1 = nullptr;
-        if (timing) {
-            LV_HIP(hipEventCreate(&ev0));
-            LV_HIP(hipEventCreate(&ev1));
-            LV_HIP(hipEventRecord(ev0, s));
-        }
-        struct EvGuard {
-            hipEvent_t a, b;
-            ~EvGuard() {
-                if (a) (void)hipEventDestroy(a);
-                if (b) (void)hipEventDestroy(b);
-            }
-        } evg{ev0, ev1};
-
-        const int64_t n0 = g->n, nnz0 = g->nnz;
-        DevBuf<int32_t> fin((size_t)n0);
-        lv::iota_i32(fin.p, n0, s);
+        DevBuf<int32_t> fin((size_t)g->n);
         lv::i128 q_final = 0;
-        lv::GraphView v = g->view();
-        if (g->tw > 0) {
-            lv::Sweeper sw(s, t);
-            lv::Contractor ct(s, t);
-            sw.reserve(n0, nnz0);
-            ct.reserve(n0, nnz0);
-            DevBuf<int32_t> newlab((size_t)n0);
-            struct LevelGraph {
-                DevBuf<int64_t> rp, delta, w;
-                DevBuf<int32_t> col;
-            } lg[2];
-            int which = 0;
-            lv::SweepParams sp;
-            sp.theta_num = prm.theta_num;
-            sp.theta_den = prm.theta_den;
-            sp.max_sweeps = prm.max_sweeps;
-            sp.singlet = prm.singlet_rule ? 1 : 0;
-            for (int level = 0; level < prm.max_levels; ++level) {
-                const size_t rec0 = timer.recs.size();
-                sw.plan(v);
-                sw.init_singletons(v);
-                lv::PhaseState st;
-                int p = 0;
-                for (;;) {
-                    for (int b = 0; b < batch; ++b) sw.pass(v, ++p, sp, nullptr);
-                    st = sw.read_state();
-                    if (st.done) break;
-                    require(p <= prm.max_sweeps + 4 + batch, LOUVAIN_EDEVICE, "sweep loop did not converge");
-                }
-                auto &ls = local.level[level];
-                ls.n = v.n;
-                ls.nnz = v.nnz;
-                ls.sweeps_accepted = st.accepted;
-                ls.sweeps_executed = st.accepted + (st.limit ? 0 : 1);
-                ls.gpu_passes = st.pass;
-                ls.q_int.lo = st.q_ref[0];
-                ls.q_int.hi = (int64_t)st.q_ref[1];
-                local.total_edges_swept += (int64_t)st.pass * v.nnz;
-                local.levels = level + 1;
-                q_final = lv::make_i128(st.q_ref[0], (int64_t)st.q_ref[1]);
-                if (st.limit) status = LOUVAIN_ELIMIT;
-                if (st.accepted == 0) {
-                    if (timing) {
-                        LV_HIP(hipStreamSynchronize(s));
-                        collect_kernel_stats(timer, nullptr, rec0, timer.recs.size(), &ls.ms_sweep, &ls.ms_contract);
-                    }
-                    break;
-                }
-                const int32_t *cfin = sw.slot(st.final_slot);
-                const int64_t k = ct.renumber(cfin, v.n, newlab.p);
-                ct.compose(fin.p, n0, newlab.p);
-                if (level + 1 >= prm.max_levels) {
-                    status = LOUVAIN_ELIMIT;
-                    if (timing) {
-                        LV_HIP(hipStreamSynchronize(s));
-                        collect_kernel_stats(timer, nullptr, rec0, timer.recs.size(), &ls.ms_sweep, &ls.ms_contract);
-                    }
-                    break;
-                }
-                LevelGraph &nb = lg[which];
-                if (!nb.rp.p) {
-                    nb.rp.alloc((size_t)n0 + 1);
-                    nb.delta.alloc((size_t)n0);
-                    nb.w.alloc((size_t)nnz0);
-                    nb.col.alloc((size_t)nnz0);
-                }
-                const int64_t m2 = ct.contract(v, newlab.p, k, nb.rp.p, nb.col.p, nb.w.p);
-                lv::row_sums_i64(k, m2, nb.rp.p, nb.w.p, nb.delta.p, s, t);
-                lv::GraphView v2;
-                v2.n = k;
-                v2.nnz = m2;
-                v2.row_ptr = nb.rp.p;
-                v2.col = nb.col.p;
-                v2.w = nb.w.p;
-                v2.wbytes = 8;
-                v2.delta = nb.delta.p;
-                v2.tw = g->tw;
-                v = v2;
-                which = 1 - which;
-                if (timing) {
-                    LV_HIP(hipStreamSynchronize(s));
-                    collect_kernel_stats(timer, nullptr, rec0, timer.recs.size(), &ls.ms_sweep, &ls.ms_contract);
-                }
-            }
-        }
-        local.status = status;
-        if (timing) {
-            LV_HIP(hipEventRecord(ev1, s));
-            LV_HIP(hipStreamSynchronize(s));
-            float ms = 0;
-            LV_HIP(hipEventElapsedTime(&ms, ev0, ev1));
-            local.ms_total = ms;
-            collect_kernel_stats(timer, &local, 0, timer.recs.size(), nullptr, nullptr);
-        }
-        timer.on = false;
-        copy_out(labels_out, fin.p, n0, device_ptrs(flags), s);
+        status = lv::run_plain(g->view(), prm, s, ctx->timer, timing, fin.p, &q_final, &local);
+        copy_out(labels_out, fin.p, g->n, device_ptrs(flags), s);
         LV_HIP(hipStreamSynchronize(s));
         if (q_int) *q_int = to_abi(q_final);
         if (q) *q = q_of(q_final, g->tw);
@@ -480,6 +534,224 @@ int louvain_run(louvain_ctx ctx, louvain_graph g, const louvain_params *params, 
             local.timing = stats->timing;
             *stats = local;
         }
+    });
+    if (ctx) ctx->timer.on = false;
+    return rc != LOUVAIN_OK ? rc : status;
+}
+
+size_t louvain_workspace_bytes(int64_t n, int64_t nnz) {
+    if (n < 0 || nnz < 0) return 0;
+    return lv::Server::workspace_bytes(n, nnz);
+}
+
+int louvain_serve_budget(louvain_ctx ctx, size_t hbm_bytes) {
+    if (!ctx) return LOUVAIN_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->serve_mu);
+    ctx->serve_budget = hbm_bytes;
+    if (ctx->server && hbm_bytes > 0) ctx->server->set_budget(hbm_bytes);
+    return LOUVAIN_OK;
+}
+
+int louvain_submit(louvain_ctx ctx, int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col_idx,
+                   const void *weight, const louvain_params *params, int32_t *labels_out, uint32_t flags,
+                   uint64_t *ticket) {
+    if (!ctx || !ticket) return LOUVAIN_EINVAL;
+    if (n < 0 || nnz < 0 || !row_ptr || (nnz > 0 && (!col_idx || !weight)) || (n > 0 && !labels_out) ||
+        (n == 0 && nnz > 0))
+        return LOUVAIN_EINVAL;
+    if (n >= ((int64_t)1 << 31) || nnz >= ((int64_t)1 << 40)) return LOUVAIN_EOVERFLOW;
+    louvain_params prm{1, 1000000, 1000, 64, 1, 0};
+    if (params) prm = *params;
+    if (prm.theta_num < 0 || prm.theta_den <= 0 || prm.max_sweeps < 0 || prm.max_levels < 1 || prm.max_levels > 64)
+        return LOUVAIN_EINVAL;
+    try {
+        std::unique_ptr<lv::ServeRequest> r(new lv::ServeRequest());
+        r->n = n;
+        r->nnz = nnz;
+        r->rp = row_ptr;
+        r->col = col_idx;
+        r->w = weight;
+        r->wbytes = (flags & LOUVAIN_WEIGHTS_I64) ? 8 : 4;
+        r->dev = device_ptrs(flags);
+        r->check_symmetry = (flags & LOUVAIN_CHECK_SYMMETRY) != 0;
+        r->prm = prm;
+        r->labels_out = labels_out;
+        lv::Server *srv;
+        {
+            std::lock_guard<std::mutex> lk(ctx->serve_mu);
+            if (!ctx->server) {
+                size_t budget = ctx->serve_budget;
+                if (budget == 0) {
+                    size_t free_b = 0, total_b = 0;
+                    if (hipSetDevice(ctx->device) != hipSuccess || hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+                        (void)hipGetLastError();
+                        return LOUVAIN_EDEVICE;
+                    }
+                    budget = free_b / 10 * 8;
+                }
+                ctx->server.reset(new lv::Server(ctx->device, budget));
+            }
+            srv = ctx->server.get();
+        }
+        *ticket = srv->submit(std::move(r));
+        return LOUVAIN_OK;
+    } catch (const std::bad_alloc &) {
+        return LOUVAIN_ENOMEM;
+    } catch (...) {
+        return LOUVAIN_EDEVICE;
+    }
+}
+
+int louvain_poll(louvain_ctx ctx, uint64_t ticket, int32_t wait_us, louvain_request_result *result) {
+    if (!ctx) return LOUVAIN_EINVAL;
+    lv::Server *srv;
+    {
+        std::lock_guard<std::mutex> lk(ctx->serve_mu);
+        srv = ctx->server.get();
+    }
+    if (!srv) return LOUVAIN_EINVAL;
+    std::unique_ptr<lv::ServeRequest> r;
+    const int st = srv->poll(ticket, wait_us, &r);
+    if (st == LOUVAIN_EAGAIN || !r) return st;
+    if (result) {
+        memset(result, 0, sizeof *result);
+        result->status = r->status;
+        result->levels = (int32_t)r->levels.size();
+        result->n = r->n;
+        result->nnz = r->nnz;
+        result->total_edges_swept = r->edges_swept;
+        result->q_int = to_abi(r->q);
+        result->q = q_of(r->q, r->tw);
+        result->t_submit_us = r->t_submit;
+        result->t_admit_us = r->t_admit;
+        result->t_done_us = r->t_done;
+        for (size_t l = 0; l < r->levels.size() && l < 64; ++l) {
+            const lv::LevelRec &x = r->levels[l];
+            louvain_level_stats &ls = result->level[l];
+            ls.n = x.n;
+            ls.nnz = x.nnz;
+            ls.sweeps_executed = x.executed;
+            ls.sweeps_accepted = x.accepted;
+            ls.gpu_passes = x.passes;
+            ls.q_int = to_abi(x.q);
+        }
+        strncpy(result->error, r->err.c_str(), sizeof result->error - 1);
+    }
+    return st;
+}
+
+int louvain_run_batch(louvain_ctx ctx, int64_t ngraphs, const louvain_graph *graphs, const louvain_params *params,
+                      int32_t *const *labels_out, louvain_i128 *q_int, double *q, int32_t *status_out,
+                      louvain_run_stats *stats, uint32_t flags) {
+    int status = LOUVAIN_OK;
+    const int rc = guarded(ctx, [&] {
+        require(ngraphs >= 0, LOUVAIN_EINVAL, "ngraphs must be >= 0");
+        if (ngraphs == 0) return;
+        require(graphs != nullptr && labels_out != nullptr, LOUVAIN_EINVAL, "graphs and labels_out must not be NULL");
+        for (int64_t i = 0; i < ngraphs; ++i) {
+            require(graphs[i] != nullptr && graphs[i]->ctx == ctx, LOUVAIN_EINVAL,
+                    "graph " + std::to_string(i) + " missing or from another context");
+            require(labels_out[i] != nullptr || graphs[i]->n == 0, LOUVAIN_EINVAL,
+                    "labels_out[" + std::to_string(i) + "] must not be NULL");
+        }
+        const louvain_params prm = checked_params(params);
+        hipStream_t s = ctx->stream;
+        const bool dev = device_ptrs(flags);
+        const int32_t timing = stats ? stats[0].timing : 0;
+        std::vector<louvain_run_stats> st_local;
+        if (stats) st_local.resize((size_t)ngraphs);
+
+        // graphs too heavy for compact words run alone, first
+        std::vector<int64_t> eligible;
+        std::vector<lv::i128> qv((size_t)ngraphs, 0);
+        std::vector<int32_t> sv((size_t)ngraphs, LOUVAIN_OK);
+        for (int64_t i = 0; i < ngraphs; ++i) {
+            if (graphs[i]->tw < lv::kCompactTwMax) {
+                eligible.push_back(i);
+                continue;
+            }
+            louvain_i128 qi;
+            louvain_run_stats *si = stats ? &st_local[(size_t)i] : nullptr;
+            if (si) si->timing = 0;
+            const int r = louvain_run(ctx, graphs[i], &prm, labels_out[i], &qi, nullptr, si, flags);
+            if (r != LOUVAIN_OK && r != LOUVAIN_ELIMIT) throw Error(r, ctx->err);
+            qv[(size_t)i] = lv::make_i128(qi.lo, qi.hi);
+            sv[(size_t)i] = r;
+        }
+
+        lv::Timer &timer = ctx->timer;
+        timer.on = timing != 0;
+        timer.reset();
+        lv::Timer *t = timing ? &timer : nullptr;
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        struct EvGuard {
+            hipEvent_t *a, *b;
+            ~EvGuard() {
+                if (*a) (void)hipEventDestroy(*a);
+                if (*b) (void)hipEventDestroy(*b);
+            }
+        } evg{&ev0, &ev1};
+        if (timing) {
+            LV_HIP(hipEventCreate(&ev0));
+            LV_HIP(hipEventCreate(&ev1));
+            LV_HIP(hipEventRecord(ev0, s));
+        }
+        const int64_t ne = (int64_t)eligible.size();
+        std::vector<int64_t> off((size_t)ne + 1, 0);
+        for (int64_t k = 0; k < ne; ++k) off[(size_t)k + 1] = off[(size_t)k] + graphs[eligible[(size_t)k]]->n;
+        DevBuf<int32_t> fin((size_t)off[(size_t)ne]);
+        std::vector<lv::BatchMember> mem((size_t)ne);
+        lv::BatchEngine eng(s, t, sweep_params(prm), prm.max_levels, prm.pass_batch);
+        for (int64_t k = 0; k < ne; ++k) {
+            lv::BatchMember &m = mem[(size_t)k];
+            m.g0 = graphs[eligible[(size_t)k]]->view();
+            m.fin = fin.p + off[(size_t)k];
+            eng.admit(&m);
+        }
+        while (!eng.idle()) eng.step();
+
+        // outputs
+        if (dev) {
+            std::vector<int32_t *> dst((size_t)ne);
+            std::vector<int64_t> cnt((size_t)ne);
+            for (int64_t k = 0; k < ne; ++k) {
+                dst[(size_t)k] = labels_out[eligible[(size_t)k]];
+                cnt[(size_t)k] = mem[(size_t)k].g0.n;
+            }
+            lv::copy_segments(dst.data(), cnt.data(), off.data(), ne, fin.p, s);
+        } else if (off[(size_t)ne] > 0) {
+            std::vector<int32_t> host((size_t)off[(size_t)ne]);
+            LV_HIP(hipMemcpyAsync(host.data(), fin.p, host.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            LV_HIP(hipStreamSynchronize(s));
+            for (int64_t k = 0; k < ne; ++k)
+                if (mem[(size_t)k].g0.n > 0)
+                    memcpy(labels_out[eligible[(size_t)k]], host.data() + off[(size_t)k],
+                           (size_t)mem[(size_t)k].g0.n * sizeof(int32_t));
+        }
+        for (int64_t k = 0; k < ne; ++k) {
+            const int64_t i = eligible[(size_t)k];
+            qv[(size_t)i] = mem[(size_t)k].q;
+            sv[(size_t)i] = mem[(size_t)k].status;
+            if (stats) member_stats(mem[(size_t)k], timing, &st_local[(size_t)i]);
+        }
+        if (timing) {
+            LV_HIP(hipEventRecord(ev1, s));
+            LV_HIP(hipStreamSynchronize(s));
+            float ms = 0;
+            LV_HIP(hipEventElapsedTime(&ms, ev0, ev1));
+            st_local[0].ms_total = ms;
+            st_local[0].n_kernels = 0;
+            collect_kernel_stats(timer, &st_local[0], 0, timer.recs.size(), nullptr, nullptr);
+        }
+        timer.on = false;
+        LV_HIP(hipStreamSynchronize(s));
+        for (int64_t i = 0; i < ngraphs; ++i) {
+            if (q_int) q_int[i] = to_abi(qv[(size_t)i]);
+            if (q) q[i] = q_of(qv[(size_t)i], graphs[i]->tw);
+            if (status_out) status_out[i] = sv[(size_t)i];
+            if (sv[(size_t)i] == LOUVAIN_ELIMIT) status = LOUVAIN_ELIMIT;
+        }
+        if (stats) memcpy(stats, st_local.data(), sizeof(louvain_run_stats) * (size_t)ngraphs);
     });
     if (ctx) ctx->timer.on = false;
     return rc != LOUVAIN_OK ? rc : status;

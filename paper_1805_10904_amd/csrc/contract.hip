@@ -25,6 +25,25 @@ __global__ void k_relabel(const int32_t *__restrict__ labels, const int32_t *__r
     if (i < n) newlab[i] = map[labels[i]];
 }
 
+__global__ void k_mark_kept(const int32_t *__restrict__ labels, const int32_t *__restrict__ gid,
+                            const int32_t *__restrict__ keep, int64_t n, int32_t *flags) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && keep[gid[i]]) flags[labels[i]] = 1;
+}
+
+__global__ void k_gather_offsets(const int32_t *__restrict__ map, const int64_t *__restrict__ loff, int64_t nslots,
+                                 int64_t *newoff) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s <= nslots) newoff[s] = map[loff[s]];
+}
+
+__global__ void k_relabel_kept(const int32_t *__restrict__ labels, const int32_t *__restrict__ map,
+                               const int32_t *__restrict__ gid, const int32_t *__restrict__ keep, int64_t n,
+                               int32_t *newlab) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) newlab[i] = keep[gid[i]] ? map[labels[i]] : -1;
+}
+
 __global__ void k_compose(int32_t *fin, int64_t n0, const int32_t *__restrict__ newlab) {
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v < n0) fin[v] = newlab[fin[v]];
@@ -65,6 +84,32 @@ int64_t Contractor::renumber(const int32_t *labels, int64_t n, int32_t *newlab) 
     return k;
 }
 
+int64_t Contractor::renumber_kept(const int32_t *labels, int64_t n, const int32_t *gid, const int32_t *keep,
+                                  const int64_t *loff, int64_t nslots, int32_t *newlab, int64_t *newoff) {
+    if (n == 0) return 0;
+    int32_t *flags = flags_.p;
+    fill<int32_t>(flags, 0, n, s_);
+    {
+        TimedLaunch tl(t_, TG_CONTRACT, "k_mark_kept", (double)n * 12);
+        k_mark_kept<<<grid_for(n, 256), 256, 0, s_>>>(labels, gid, keep, n, flags);
+        LV_LAUNCHED("k_mark_kept");
+    }
+    scan_exclusive<int32_t, int32_t>(flags, flags, n, flags + n, s_, t_);
+    {
+        TimedLaunch tl(t_, TG_CONTRACT, "k_relabel_kept", (double)n * 16);
+        k_relabel_kept<<<grid_for(n, 256), 256, 0, s_>>>(labels, flags, gid, keep, n, newlab);
+        LV_LAUNCHED("k_relabel_kept");
+    }
+    // a kept graph's labels lie in its own vertex range, so the count of
+    // present labels below loff[s] is the first new ID of graph s
+    k_gather_offsets<<<grid_for(nslots + 1, 256), 256, 0, s_>>>(flags, loff, nslots, newoff);
+    LV_LAUNCHED("k_gather_offsets");
+    int32_t k = 0;
+    LV_HIP(hipMemcpyAsync(&k, flags + n, sizeof k, hipMemcpyDeviceToHost, s_));
+    LV_HIP(hipStreamSynchronize(s_));
+    return k;
+}
+
 void Contractor::compose(int32_t *final_labels, int64_t n0, const int32_t *newlab) {
     if (n0 == 0) return;
     TimedLaunch tl(t_, TG_CONTRACT, "k_compose", (double)n0 * 12);
@@ -89,7 +134,13 @@ __global__ __launch_bounds__(256) void k_contract_keys(const int64_t *__restrict
         const int64_t e = base + k * 256 + t;
         if (e >= nnz) break;
         const int64_t r = row_of_entry(rp, rlo, rhi, e);
-        const uint64_t a = (uint32_t)newlab[r], b = (uint32_t)newlab[col[e]];
+        const int32_t na = newlab[r];
+        if (na < 0) {
+            keys[e] = (bits >= 32) ? ~0ull : ((1ull << (2 * bits)) - 1);   // dropped: sorts last
+            vals[e] = 0;
+            continue;
+        }
+        const uint64_t a = (uint32_t)na, b = (uint32_t)newlab[col[e]];
         keys[e] = (a << bits) | b;
         vals[e] = (int64_t)w[e];
     }
@@ -234,7 +285,7 @@ int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t 
         fill<int64_t>(rp_out, 0, n_new + 1, s_);
         return 0;
     }
-    const int bits = bits_for(n_new);
+    const int bits = bits_for(n_new + 1);   // leaves the all-ones key free for dropped entries
     const int64_t eb = (m + kEntriesPerBlock - 1) / kEntriesPerBlock;
     {
         TimedLaunch tl(t_, TG_CONTRACT, "k_contract_keys", (double)m * (4 + g.wbytes + 4 + 16) + (double)g.n * 12, g.wbytes == 4 ? "<int>" : "<long>");
@@ -278,9 +329,13 @@ int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t 
     }
     scan_exclusive<int32_t, int64_t>(head_.p, uid_.p, m, uid_.p + m, s_, t_);
     int64_t m_new = 0;
+    uint64_t last_key = 0;
     LV_HIP(hipMemcpyAsync(&m_new, uid_.p + m, sizeof m_new, hipMemcpyDeviceToHost, s_));
+    LV_HIP(hipMemcpyAsync(&last_key, keys + (m - 1), sizeof last_key, hipMemcpyDeviceToHost, s_));
     LV_HIP(hipStreamSynchronize(s_));
-    fill<int64_t>(w_out, 0, m_new, s_);
+    const uint64_t dropped_key = (bits >= 32) ? ~0ull : ((1ull << (2 * bits)) - 1);
+    const int64_t m_keep = last_key == dropped_key ? m_new - 1 : m_new;
+    fill<int64_t>(w_out, 0, m_new, s_);   // the dropped segment (if any) is the last one
     {
         TimedLaunch tl(t_, TG_CONTRACT, "k_reduce_by_key", (double)m * 28 + (double)m_new * 20);
         k_reduce_by_key<<<(unsigned)eb, 256, 0, s_>>>(keys, vals, head_.p, uid_.p, m, bits, col_out, w_out, ukey);
@@ -288,10 +343,10 @@ int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t 
     }
     {
         TimedLaunch tl(t_, TG_CONTRACT, "k_rowptr", (double)(n_new + 1) * 8);
-        k_rowptr<<<grid_for(n_new + 1, 256), 256, 0, s_>>>(ukey, m_new, bits, n_new, rp_out);
+        k_rowptr<<<grid_for(n_new + 1, 256), 256, 0, s_>>>(ukey, m_keep, bits, n_new, rp_out);
         LV_LAUNCHED("k_rowptr");
     }
-    return m_new;
+    return m_keep;
 }
 
 // ----------------------------------------------------------- modularity --

@@ -15,11 +15,20 @@ class Contractor {
     // newlab[i] = rank of labels[i] among the distinct labels.  Returns the
     // number of communities (synchronises the stream).
     int64_t renumber(const int32_t *labels, int64_t n, int32_t *newlab);
+    // Batched form over a block-diagonal union whose graph s owns vertices
+    // [loff[s], loff[s+1]) (device, nslots + 1 entries): only vertices whose
+    // graph is kept (keep[gid[i]] != 0) take part, the others get
+    // newlab = -1.  Kept graphs' communities get consecutive IDs in ascending
+    // label order, so graph s's new IDs are [newoff[s], newoff[s+1])
+    // (device, nslots + 1 entries; empty for graphs not kept).
+    int64_t renumber_kept(const int32_t *labels, int64_t n, const int32_t *gid, const int32_t *keep,
+                          const int64_t *loff, int64_t nslots, int32_t *newlab, int64_t *newoff);
     // final[v] = newlab[final[v]] for v in [0, n0).
     void compose(int32_t *final_labels, int64_t n0, const int32_t *newlab);
     // Contract g so that vertex a of the result is {i : newlab[i] == a};
     // writes row_ptr (n_new + 1), col and int64 weights (capacity g.nnz) and
     // returns the number of entries (synchronises the stream).
+    // Entries of rows with newlab == -1 are dropped.
     int64_t contract(const GraphView &g, const int32_t *newlab, int64_t n_new, int64_t *rp_out,
                      int32_t *col_out, int64_t *w_out);
 

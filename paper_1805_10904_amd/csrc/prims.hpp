@@ -23,11 +23,25 @@ struct TempBuf {
             throw Error(LOUVAIN_ENOMEM, "temporary device allocation of " + std::to_string(bytes) + " bytes failed");
         }
     }
+    TempBuf() = default;
     TempBuf(const TempBuf &) = delete;
     TempBuf &operator=(const TempBuf &) = delete;
-    ~TempBuf() {
+    TempBuf(TempBuf &&o) noexcept : p(o.p), s(o.s), pool(o.pool) { o.p = nullptr; }
+    TempBuf &operator=(TempBuf &&o) noexcept {
+        if (this != &o) {
+            release();
+            p = o.p;
+            s = o.s;
+            pool = o.pool;
+            o.p = nullptr;
+        }
+        return *this;
+    }
+    ~TempBuf() { release(); }
+    void release() {
         if (!p) return;
         if (pool) pool->put(p); else (void)hipFreeAsync(p, s);
+        p = nullptr;
     }
     template <typename T> T *as() const { return (T *)p; }
 };

@@ -1,0 +1,82 @@
+// Request loop of the served form: graphs are submitted from any thread, a
+// worker thread admits them in arrival order while their estimated device
+// footprint fits the memory budget, and every admitted graph joins the
+// running batch at the next level boundary (continuous batching: newcomers
+// at level 0 are swept in the same launches as members at deeper levels).
+// Results are identical to louvain_run on each graph alone.
+#pragma once
+
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+
+#include "batch.hpp"
+
+namespace lv {
+
+struct ServeRequest {
+    uint64_t ticket = 0;
+    // input: caller memory, read when the request is admitted
+    int64_t n = 0, nnz = 0;
+    const int64_t *rp = nullptr;
+    const int32_t *col = nullptr;
+    const void *w = nullptr;
+    int wbytes = 4;
+    bool dev = false;            // input and output pointers are device pointers
+    bool check_symmetry = false;
+    louvain_params prm{};
+    int32_t *labels_out = nullptr;
+    // result
+    size_t bytes = 0;            // admitted footprint estimate
+    bool done = false;
+    int status = LOUVAIN_OK;
+    std::string err;
+    int64_t tw = 0;
+    i128 q = 0;
+    std::vector<LevelRec> levels;
+    int64_t edges_swept = 0;
+    double t_submit = 0, t_admit = 0, t_done = 0;   // microseconds, steady clock
+    // device state while resident
+    DevBuf<int64_t> d_rp, d_delta, d_w64;
+    DevBuf<int32_t> d_col, d_w32, d_fin;
+    BatchMember member;
+};
+
+class Server {
+  public:
+    Server(int device, size_t budget);
+    ~Server();
+    // Queue a request (thread-safe); returns its ticket.
+    uint64_t submit(std::unique_ptr<ServeRequest> r);
+    // LOUVAIN_EAGAIN while the request is pending after waiting up to wait_us
+    // microseconds (< 0: without limit); otherwise hands the finished request
+    // over (*out) and returns its status.  Unknown tickets: LOUVAIN_EINVAL.
+    int poll(uint64_t ticket, int32_t wait_us, std::unique_ptr<ServeRequest> *out);
+    void set_budget(size_t bytes);
+    size_t budget();
+    // Estimated peak device bytes of one graph of n vertices and nnz entries
+    // in the batch (its resident CSR plus its share of every level buffer).
+    static size_t workspace_bytes(int64_t n, int64_t nnz);
+    static double now_us();
+
+  private:
+    void loop();
+    void finish(ServeRequest *r);
+
+    int device_;
+    std::mutex mu_;
+    std::condition_variable cv_work_, cv_done_;
+    std::deque<ServeRequest *> incoming_;
+    std::unordered_map<uint64_t, std::unique_ptr<ServeRequest>> all_;
+    uint64_t next_ = 1;
+    bool stop_ = false;
+    size_t budget_;
+    size_t in_use_ = 0;   // worker thread only
+    std::thread th_;
+};
+
+}  // namespace lv

@@ -964,6 +964,11 @@ void Sweeper::reserve(int64_t n, int64_t nnz) {
     for (auto &c : c_) c.alloc((size_t)n);
     deg_.alloc((size_t)n);
     size_.alloc((size_t)n);
+    ds_.alloc((size_t)n);
+    vw_.alloc((size_t)n);
+    es_.alloc((size_t)n);
+    active_.alloc(2);
+    tw_one_.alloc(1);
     list_.alloc((size_t)n);
     const int64_t nblk = (n + kBucketTile - 1) / kBucketTile;
     bcount_.alloc((size_t)(NBUCKET * nblk + 1));
@@ -977,8 +982,25 @@ void Sweeper::reserve(int64_t n, int64_t nnz) {
     cap_nnz_ = nnz;
 }
 
+void Sweeper::set_batch(int64_t ngraphs, const int32_t *gid, const int64_t *tw) {
+    batch_ = true;
+    ngraphs_ = ngraphs;
+    gid_ = gid;
+    tw_ = tw;
+}
+
 void Sweeper::plan(const GraphView &g) {
     n_ = g.n;
+    compact_ = batch_ || g.tw < kCompactTwMax;
+    if (!batch_) {
+        ngraphs_ = 1;
+        gid_ = nullptr;
+        if (compact_) {
+            LV_HIP(hipMemcpyAsync(tw_one_.p, &g.tw, sizeof(int64_t), hipMemcpyHostToDevice, s_));
+            tw_ = tw_one_.p;
+        }
+    }
+    if ((int64_t)st_.n < ngraphs_) st_.alloc((size_t)ngraphs_);
     const int64_t nblk = (g.n + kBucketTile - 1) / kBucketTile;
     for (int b = 0; b <= NBUCKET; ++b) bstart_[b] = 0;
     hubs_ = hub_chunks_ = hub_scans_ = hub_slots_ = 0;
@@ -1063,7 +1085,11 @@ void Sweeper::plan(const GraphView &g) {
 }
 
 void Sweeper::init_singletons(const GraphView &g) {
-    if (g.n > 0) {
+    if (compact_) {
+        compact_init_singletons(c_[0].p, c_[1].p, c_[2].p, g.delta, ds_.p, es_.p, g.n, s_);
+        LV_HIP(hipMemsetAsync(st_.p, 0, sizeof(PhaseState) * (size_t)ngraphs_, s_));
+        return;
+    } else if (g.n > 0) {
         TimedLaunch tl(t_, TG_LEVEL, "k_init_singletons", (double)g.n * 28);
         k_init_singletons<<<grid_for(g.n, 256), 256, 0, s_>>>(c_[0].p, c_[1].p, c_[2].p, g.delta, deg_.p,
                                                              size_.p, g.n);
@@ -1073,6 +1099,12 @@ void Sweeper::init_singletons(const GraphView &g) {
 }
 
 void Sweeper::init_from_labels(const GraphView &g, const int32_t *labels) {
+    if (compact_) {
+        fill<uint64_t>(ds_.p, 0, g.n, s_);
+        compact_init_labels(c_[0].p, c_[1].p, c_[2].p, labels, g.delta, ds_.p, es_.p, g.n, s_);
+        LV_HIP(hipMemsetAsync(st_.p, 0, sizeof(PhaseState) * (size_t)ngraphs_, s_));
+        return;
+    }
     fill<int64_t>(deg_.p, 0, g.n, s_);
     fill<int32_t>(size_.p, 0, g.n, s_);
     if (g.n > 0) {
@@ -1157,8 +1189,60 @@ static void launch_pass(const SweepArgs &a, const int32_t *list, const int64_t *
     }
 }
 
+int64_t *Sweeper::deg() {
+    if (compact_) compact_expand(ds_.p, es_.p, n_, deg_.p, size_.p, nullptr, s_);
+    return deg_.p;
+}
+
+void Sweeper::e_self_out(int64_t *dst) {
+    if (compact_) compact_expand(ds_.p, es_.p, n_, deg_.p, size_.p, dst, s_);
+}
+
+unsigned int Sweeper::active_after(int p) {
+    unsigned int h = 0;
+    LV_HIP(hipMemcpyAsync(&h, active_.p + (p & 1), sizeof h, hipMemcpyDeviceToHost, s_));
+    LV_HIP(hipStreamSynchronize(s_));
+    return h;
+}
+
 void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e_self_out) {
     const int cur = (p - 1) % 3, nxt = p % 3;
+    if (compact_) {
+        CompactPass cp;
+        cp.n = g.n;
+        cp.list = list_.p;
+        for (int b = 0; b <= NBUCKET; ++b) cp.bstart[b] = bstart_[b];
+        for (int b = 0; b < NBUCKET; ++b) cp.bnnz[b] = bucket_nnz_[b];
+        cp.pack_pos = pack_pos_.p;
+        cp.pack_first = pack_first_.p;
+        cp.pack_blocks = pack_blocks_;
+        cp.hubs = hubs_;
+        cp.hub_chunks = hub_chunks_;
+        cp.hub_scans = hub_scans_;
+        cp.tab_off = hub_meta_.p;
+        cp.chunk_off = hub_meta_.p + (hubs_ + 1);
+        cp.scan_off = hub_meta_.p + 2 * (hubs_ + 1);
+        cp.tab_size = hub_meta_.p + 3 * (hubs_ + 1);
+        cp.chunk_hub = hub_of_chunk_.p;
+        cp.scan_hub = hub_of_scan_.p;
+        cp.hkey = hub_key_.p;
+        cp.hval = hub_val_.p;
+        cp.hloop = hub_loop_.p;
+        cp.hpart = hub_part_.p;
+        CompactState cs;
+        cs.c_cur = c_[cur].p;
+        cs.c_nxt = c_[nxt].p;
+        cs.ds = ds_.p;
+        cs.vw = vw_.p;
+        cs.es = es_.p;
+        cs.gid = gid_;
+        cs.tw = tw_;
+        cs.st = st_.p;
+        cs.active = active_.p;
+        cs.ngraphs = ngraphs_;
+        compact_pass(g, cp, cs, p, prm, s_, t_);
+        return;
+    }
     if (g.n > 0) {
         TimedLaunch tl(t_, TG_SWEEP, "k_qsum", (double)g.n * 8);
         k_qsum<<<(unsigned)qblocks_, 256, 0, s_>>>(deg_.p, g.n, qpart_.p, st_.p);

@@ -19,9 +19,11 @@ struct GraphView {
 };
 
 // Device-resident control block of one phase.
+// Device-resident control block of one phase of one graph.
 struct PhaseState {
     unsigned long long acc_I;   // sum of e_{i->c_i} (loops included) of the labelling read by the pass
     unsigned long long moved;   // vertices whose label changed in the pass
+    unsigned long long s_acc;   // sum of deg_C^2 of the labelling read (compact levels)
     int32_t pass;               // passes finalized in the phase
     int32_t accepted;           // sweeps kept
     int32_t done;               // phase finished
@@ -51,17 +53,66 @@ constexpr int64_t kPackMaxDeg = kPackW / 2;
 constexpr int kHubChunk = 1024;      // row entries per hub accumulation workgroup
 constexpr int kHubScan = 1024;       // table slots per hub scan workgroup
 
+// Everything a compact pass needs from the level plan (device pointers).
+struct CompactPass {
+    int64_t n = 0;
+    const int32_t *list = nullptr;
+    int64_t bstart[NBUCKET + 1] = {0};
+    int64_t bnnz[NBUCKET] = {0};
+    const int64_t *pack_pos = nullptr, *pack_first = nullptr;
+    int64_t pack_blocks = 0;
+    int64_t hubs = 0, hub_chunks = 0, hub_scans = 0;
+    const int64_t *tab_off = nullptr, *chunk_off = nullptr, *scan_off = nullptr, *tab_size = nullptr;
+    const int32_t *chunk_hub = nullptr, *scan_hub = nullptr;
+    int32_t *hkey = nullptr;
+    unsigned long long *hval = nullptr, *hloop = nullptr;
+    uint64_t *hpart = nullptr;
+};
+
 struct SweepParams {
     int64_t theta_num = 1, theta_den = 1000000;
     int32_t max_sweeps = 1000;
     int singlet = 1;
 };
 
+// Device state of a compact pass (one graph or a block-diagonal batch).
+struct CompactState {
+    int32_t *c_cur = nullptr, *c_nxt = nullptr;
+    uint64_t *ds = nullptr;        // size_C << 32 | deg_C by label
+    uint64_t *vw = nullptr;        // published words by vertex
+    uint32_t *es = nullptr;        // e_{i->c_i} incl. loop by vertex
+    const int32_t *gid = nullptr;  // graph of every vertex (nullptr: one graph)
+    const int64_t *tw = nullptr;   // TW of every graph
+    PhaseState *st = nullptr;      // phase state of every graph
+    unsigned int *active = nullptr;// two counters of graphs still in their phase (pass parity)
+    int64_t ngraphs = 1;
+};
+
+// Levels whose graphs all have TW < 2^31 run on packed community words
+// (sweep_compact.hip).
+constexpr int64_t kCompactTwMax = (int64_t)1 << 31;
+void compact_init_singletons(int32_t *c0, int32_t *c1, int32_t *c2, const int64_t *delta, uint64_t *ds, uint32_t *es,
+                             int64_t n, hipStream_t s);
+void compact_init_labels(int32_t *c0, int32_t *c1, int32_t *c2, const int32_t *labels, const int64_t *delta,
+                         uint64_t *ds, uint32_t *es, int64_t n, hipStream_t s);
+void compact_final_labels(const int32_t *c0, const int32_t *c1, const int32_t *c2, const int32_t *gid,
+                          const PhaseState *st, int64_t n, int32_t *out, hipStream_t s, Timer *t);
+void compact_expand(const uint64_t *ds, const uint32_t *es, int64_t n, int64_t *deg, int32_t *size, int64_t *e_self,
+                    hipStream_t s);
+void compact_pass(const GraphView &g, const CompactPass &cp, const CompactState &cs, int p, const SweepParams &prm,
+                  hipStream_t s, Timer *t);
+
+
 class Sweeper {
   public:
     explicit Sweeper(hipStream_t s, Timer *t) : s_(s), t_(t) {}
     // Allocate for levels of at most n vertices and nnz entries.
     void reserve(int64_t n, int64_t nnz);
+    // Graphs of the next level: ngraphs graphs laid out as a block-diagonal
+    // union, gid (device, per vertex) their ids and tw (device, per graph)
+    // their total weights; all TW < 2^31.  Without a call a level is one
+    // graph.
+    void set_batch(int64_t ngraphs, const int32_t *gid, const int64_t *tw);
     // Degree bucketing of the level's vertices (a3) and hub table set-up.
     void plan(const GraphView &g);
     // Singleton communities (a2): every ring slot = identity, deg = delta, size = 1.
@@ -72,11 +123,23 @@ class Sweeper {
     // commits the movers to deg_C and sizes, computes Q_int of the labelling
     // it reads and runs the acceptance test.
     void pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e_self_out);
-    // Copy the control block to the host (synchronises the stream).
+    // Copy the control block of graph 0 to the host (synchronises the stream).
     PhaseState read_state();
+    // Number of graphs still in their phase after pass p (synchronises).
+    unsigned int active_after(int p);
+    // Control blocks of every graph (device; compact levels).
+    PhaseState *states() { return st_.p; }
+    bool compact() const { return compact_; }
+    int64_t ngraphs() const { return ngraphs_; }
+    // e_{i->labels_in[i]} incl. loop of the last pass (compact levels, int64 copy)
+    void e_self_out(int64_t *dst);
     int32_t *slot(int k) { return c_[k % 3].p; }
-    int64_t *deg() { return deg_.p; }
-    int32_t *size() { return size_.p; }
+    // Batch: every vertex's label from its graph's final ring slot.
+    void final_labels(int32_t *out) {
+        compact_final_labels(c_[0].p, c_[1].p, c_[2].p, gid_, st_.p, n_, out, s_, t_);
+    }
+    // deg_C by label of the current labelling (after a pass: of its result)
+    int64_t *deg();
     int64_t bucket_count(int b) const { return bstart_[b + 1] - bstart_[b]; }
 
   private:
@@ -86,6 +149,16 @@ class Sweeper {
     DevBuf<int32_t> c_[3];
     DevBuf<int64_t> deg_;           // deg_C by label (updated in place by the commit)
     DevBuf<int32_t> size_;
+    bool compact_ = false;          // this level runs on compact words
+    DevBuf<uint64_t> ds_;           // compact: size_C << 32 | deg_C by label
+    DevBuf<uint64_t> vw_;           // compact: published words by vertex
+    DevBuf<uint32_t> es_;           // compact: e_{i->c_i} incl. loop by vertex
+    DevBuf<unsigned int> active_;   // compact: graphs still in their phase (two counters)
+    DevBuf<int64_t> tw_one_;        // compact single graph: its TW
+    int64_t ngraphs_ = 1;
+    const int32_t *gid_ = nullptr;
+    const int64_t *tw_ = nullptr;
+    bool batch_ = false;
     DevBuf<int32_t> list_;          // vertices grouped by bucket, ascending inside a bucket
     DevBuf<int32_t> bcount_;        // bucketing scratch (per-block counts / offsets)
     DevBuf<PhaseState> st_;

@@ -1,0 +1,881 @@
+// Local-moving sweeps for levels whose total weight TW = 2W is below 2^31
+// (paper: Alg. 1, eqs. 1-5, minimum-label heuristics of Section 3.1), for
+// one graph or for a batch of graphs laid out as one block-diagonal union
+// (graph g owns a contiguous vertex range; every graph keeps its own TW,
+// modularity, acceptance test and phase state, so each result equals a run
+// on that graph alone).
+//
+// Below 2^31 every degree, community degree and e_{i->C} fits in 31 bits,
+// which allows two compact words:
+//   community word DS[C]   low 32 bits deg_C, high 32 bits size_C; a mover
+//                          updates both halves with one 64-bit atomic;
+//   published word VW[j]   low 32 bits the label c_j, bits 32..62 deg of
+//                          community c_j, bit 63 set iff c_j is a singleton.
+// Each pass first publishes VW from the labelling it reads, so a vertex
+// gets a neighbour's community, that community's degree and its singleton
+// flag with one 8-byte gather; scores need no further global loads.
+// Scores TW*e - delta*deg stay below 2^62 (int64); sum_C deg_C^2 <= TW^2
+// fits 64 bits.
+//
+// Pass kernels: k_cpt_publish (VW, sum deg^2 per graph) -> k_cpt_small /
+// k_cpt_pack / hub kernels (new labels, e_{i->c_i} incl. loop per vertex)
+// -> k_cpt_commit (movers' atomics, per-graph I and mover counts) ->
+// k_cpt_finalize (per graph: Q_int and the acceptance test).
+#include "prims.hpp"
+#include "sweep.hpp"
+
+namespace lv {
+namespace {
+
+constexpr uint64_t kSizeOne = 1ull << 32;
+
+__device__ __forceinline__ uint64_t vw_make(int32_t c, uint64_t ds) {
+    const uint32_t deg = (uint32_t)ds, sz = (uint32_t)(ds >> 32);
+    return ((uint64_t)(deg | (sz == 1 ? 0x80000000u : 0u)) << 32) | (uint32_t)c;
+}
+__device__ __forceinline__ int32_t vw_label(uint64_t w) { return (int32_t)(uint32_t)w; }
+__device__ __forceinline__ uint32_t hi_deg(uint32_t hi) { return hi & 0x7fffffffu; }
+__device__ __forceinline__ bool hi_single(uint32_t hi) { return (hi >> 31) != 0; }
+
+struct CArgs {
+    const int64_t *row_ptr;
+    const int32_t *col;
+    const void *w;
+    const int32_t *c_cur;
+    int32_t *c_nxt;
+    const int64_t *delta;
+    const uint64_t *vw;      // published words of the labelling read
+    const int32_t *gid;      // graph of every vertex (nullptr: a single graph)
+    const int64_t *tw;       // TW of every graph
+    const PhaseState *st;    // phase state of every graph
+    uint32_t *e_self;        // e_{i->c_i} incl. loop, written for every evaluated vertex
+    int singlet;
+};
+
+__device__ __forceinline__ int graph_of(const int32_t *gid, int64_t v) { return gid ? gid[v] : 0; }
+
+template <typename W>
+__device__ __forceinline__ uint32_t cw(const void *w, int64_t e) {
+    return (uint32_t)((const W *)w)[e];   // weights are below TW < 2^31 here
+}
+
+// New label of a vertex: own word (ci, own_hi), best candidate (score bs,
+// label bl, singleton flag bsingle), e_own = e_{i->C(i)\{i}}.
+__device__ __forceinline__ int32_t cpt_decide(int singlet, int64_t tw, int32_t ci, uint32_t own_hi, int64_t di,
+                                              int64_t e_own, bool has, int64_t bs, int32_t bl, bool bsingle) {
+    if (!has) return ci;
+    const int64_t s_own = tw * e_own - di * ((int64_t)hi_deg(own_hi) - di);
+    if (bs <= s_own) return ci;
+    if (singlet && hi_single(own_hi) && bsingle && bl > ci) return ci;
+    return bl;
+}
+
+// Per-graph sums over a workgroup that covers the contiguous vertex range
+// [lo, hi]: graphs are contiguous vertex ranges, so the range touches the
+// graphs gid[lo] .. gid[hi]; up to kSpan of them are summed in LDS and
+// flushed with one atomic each, wider spans fall back to per-lane atomics.
+constexpr int kSpan = 64;
+
+struct SpanSums {
+    int g_lo, span;
+};
+
+__device__ __forceinline__ SpanSums span_begin(const int32_t *gid, int64_t lo, int64_t hi, int *s_glo, int *s_span,
+                                               unsigned long long (*acc)[2]) {
+    if (threadIdx.x == 0) {
+        const int a = graph_of(gid, lo), b = graph_of(gid, hi);
+        *s_glo = a;
+        *s_span = b - a + 1;
+    }
+    if (threadIdx.x < kSpan) {
+        acc[threadIdx.x][0] = 0;
+        acc[threadIdx.x][1] = 0;
+    }
+    __syncthreads();
+    return SpanSums{*s_glo, *s_span};
+}
+
+__device__ __forceinline__ void span_add(const SpanSums &sp, unsigned long long (*acc)[2], int k, int g,
+                                         unsigned long long x, PhaseState *st, int field) {
+    if (x == 0) return;
+    if (sp.span <= kSpan) {
+        atomicAdd(&acc[g - sp.g_lo][k], x);
+    } else {
+        unsigned long long *f = field == 0 ? &st[g].acc_I : field == 1 ? &st[g].moved : &st[g].s_acc;
+        atomicAdd(f, x);
+    }
+}
+
+__device__ __forceinline__ void span_flush(const SpanSums &sp, unsigned long long (*acc)[2], PhaseState *st,
+                                           int field0, int field1) {
+    __syncthreads();
+    if (sp.span <= kSpan && (int)threadIdx.x < sp.span) {
+        const int g = sp.g_lo + threadIdx.x;
+        const int fs[2] = {field0, field1};
+        for (int k = 0; k < 2; ++k) {
+            if (fs[k] < 0 || acc[threadIdx.x][k] == 0) continue;
+            unsigned long long *f = fs[k] == 0 ? &st[g].acc_I : fs[k] == 1 ? &st[g].moved : &st[g].s_acc;
+            atomicAdd(f, acc[threadIdx.x][k]);
+        }
+    }
+}
+
+// ----------------------------------------------------------------- set-up --
+
+__global__ void k_cpt_init_singletons(int32_t *c0, int32_t *c1, int32_t *c2, const int64_t *__restrict__ delta,
+                                      uint64_t *ds, uint32_t *es, int64_t n) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    c0[v] = c1[v] = c2[v] = (int32_t)v;
+    ds[v] = kSizeOne | (uint64_t)delta[v];
+    es[v] = 0;
+}
+
+__global__ void k_cpt_init_labels(int32_t *c0, int32_t *c1, int32_t *c2, const int32_t *__restrict__ labels,
+                                  const int64_t *__restrict__ delta, uint64_t *ds, uint32_t *es, int64_t n) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int32_t l = labels[v];
+    c0[v] = c1[v] = c2[v] = l;
+    es[v] = 0;
+    atomicAdd((unsigned long long *)&ds[l], (unsigned long long)(kSizeOne + (uint64_t)delta[v]));
+}
+
+// Each vertex's label in its own graph's result slot (graphs of a batch end
+// their phases at different passes).
+__global__ void k_cpt_final_labels(const int32_t *__restrict__ c0, const int32_t *__restrict__ c1,
+                                   const int32_t *__restrict__ c2, const int32_t *__restrict__ gid,
+                                   const PhaseState *__restrict__ st, int64_t n, int32_t *out) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int k = st[graph_of(gid, v)].final_slot;
+    out[v] = k == 0 ? c0[v] : k == 1 ? c1[v] : c2[v];
+}
+
+__global__ void k_cpt_expand(const uint64_t *__restrict__ ds, const uint32_t *__restrict__ es, int64_t n,
+                             int64_t *deg, int32_t *size, int64_t *e_self) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    deg[v] = (int64_t)(uint32_t)ds[v];
+    size[v] = (int32_t)(ds[v] >> 32);
+    if (e_self) e_self[v] = (int64_t)es[v];
+}
+
+// ---------------------------------------------------- publish + sum deg^2 --
+
+constexpr int kPubTile = 2048;
+
+__global__ __launch_bounds__(256) void k_cpt_publish(const uint64_t *__restrict__ ds, const int32_t *__restrict__ c,
+                                                     uint64_t *vw, const int32_t *__restrict__ gid, PhaseState *st,
+                                                     int64_t n, unsigned int *active_zero) {
+    __shared__ unsigned long long acc[kSpan][2];
+    __shared__ int s_glo, s_span;
+    if (active_zero && blockIdx.x == 0 && threadIdx.x == 0) *active_zero = 0;
+    const int64_t base = (int64_t)blockIdx.x * kPubTile;
+    const int64_t last = base + kPubTile - 1 < n - 1 ? base + kPubTile - 1 : n - 1;
+    const SpanSums sp = span_begin(gid, base, last, &s_glo, &s_span, acc);
+#pragma unroll
+    for (int k = 0; k < kPubTile / 256; ++k) {
+        const int64_t v = base + k * 256 + threadIdx.x;
+        if (v > last) continue;
+        const int g = graph_of(gid, v);
+        if (st[g].done) continue;
+        const uint64_t d = (uint32_t)ds[v];
+        span_add(sp, acc, 1, g, d * d, st, 2);
+        const int32_t cv = c[v];
+        vw[v] = vw_make(cv, ds[cv]);
+    }
+    span_flush(sp, acc, st, -1, 2);
+}
+
+// ------------------------------------------------------------------ commit --
+
+constexpr int kCommitTile = 256;
+
+__global__ __launch_bounds__(256) void k_cpt_commit(const int32_t *__restrict__ c_cur, const int32_t *__restrict__ c_nxt,
+                                                    const int64_t *__restrict__ delta, const uint32_t *__restrict__ es,
+                                                    uint64_t *ds, const int32_t *__restrict__ gid, PhaseState *st,
+                                                    int64_t n) {
+    __shared__ unsigned long long acc[kSpan][2];
+    __shared__ int s_glo, s_span;
+    const int64_t base = (int64_t)blockIdx.x * kCommitTile;
+    const int64_t last = base + kCommitTile - 1 < n - 1 ? base + kCommitTile - 1 : n - 1;
+    const SpanSums sp = span_begin(gid, base, last, &s_glo, &s_span, acc);
+    const int64_t v = base + threadIdx.x;
+    if (v <= last) {
+        const int g = graph_of(gid, v);
+        if (!st[g].done) {
+            const int32_t from = c_cur[v], to = c_nxt[v];
+            if (from != to) {
+                const uint64_t inc = kSizeOne + (uint64_t)delta[v];
+                atomicAdd((unsigned long long *)&ds[to], (unsigned long long)inc);
+                atomicAdd((unsigned long long *)&ds[from], (unsigned long long)(0 - inc));
+                span_add(sp, acc, 1, g, 1, st, 1);
+            }
+            span_add(sp, acc, 0, g, es[v], st, 0);
+        }
+    }
+    span_flush(sp, acc, st, 0, 1);
+}
+
+// ------------------------------------------------------------- acceptance --
+
+__device__ __forceinline__ void cpt_mul_u128_u64(u128 a, uint64_t b, uint64_t &hi, u128 &lo) {
+    const u128 p0 = (u128)(uint64_t)a * b;
+    const u128 p1 = (u128)(uint64_t)(a >> 64) * b;
+    const u128 l = p0 + (p1 << 64);
+    hi = (uint64_t)(p1 >> 64) + (l < p0 ? 1 : 0);
+    lo = l;
+}
+
+// theta_den * (qn - qp) > theta_num * |qp|, exactly.
+__device__ __forceinline__ bool cpt_gain_passes(i128 qn, i128 qp, int64_t num, int64_t den) {
+    if (qn <= qp) return false;
+    const u128 gain = (u128)(qn - qp);
+    const u128 mag = (u128)(qp < 0 ? -qp : qp);
+    uint64_t lh, rh;
+    u128 ll, rl;
+    cpt_mul_u128_u64(gain, (uint64_t)den, lh, ll);
+    cpt_mul_u128_u64(mag, (uint64_t)num, rh, rl);
+    return lh > rh || (lh == rh && ll > rl);
+}
+
+// One thread per graph: Q_int of the labelling the pass read (slot p-1) and
+// the acceptance test of sweep p-1 against the last kept labelling.
+__global__ void k_cpt_finalize(PhaseState *st, const int64_t *__restrict__ tw, int64_t ngraphs, int64_t theta_num,
+                               int64_t theta_den, int32_t max_sweeps, int32_t p, unsigned int *active) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ngraphs) return;
+    PhaseState &s = st[g];
+    if (s.done) return;
+    const i128 q = (i128)tw[g] * (i128)s.acc_I - (i128)s.s_acc;
+    s.pass = p;
+    s.q_last[0] = (uint64_t)q;
+    s.q_last[1] = (uint64_t)(int64_t)(q >> 64);
+    const i128 qref = make_i128(s.q_ref[0], (int64_t)s.q_ref[1]);
+    bool keep = true;
+    if (p == 1) {
+        s.q_ref[0] = (uint64_t)q;
+        s.q_ref[1] = (uint64_t)(int64_t)(q >> 64);
+    } else if (cpt_gain_passes(q, qref, theta_num, theta_den)) {
+        s.q_ref[0] = (uint64_t)q;
+        s.q_ref[1] = (uint64_t)(int64_t)(q >> 64);
+        s.accepted += 1;
+    } else {
+        keep = false;
+        s.done = 1;
+        s.final_slot = (p - 2) % 3;
+    }
+    if (keep) {
+        if (s.accepted >= max_sweeps) {
+            s.done = 1;
+            s.limit = 1;
+            s.final_slot = (p - 1) % 3;
+        } else if (s.moved == 0) {
+            s.done = 1;   // the next sweep cannot change Q, so it would be discarded
+            s.final_slot = (p - 1) % 3;
+        }
+    }
+    s.acc_I = 0;
+    s.moved = 0;
+    s.s_acc = 0;
+    if (!s.done) atomicAdd(active, 1u);
+}
+
+// ------------------------------------------------------ rows of <= 8 entries --
+
+// One thread per vertex in vertex-ID order (coalesced per-vertex accesses);
+// threads whose row is empty or longer than 8 entries do nothing.  The row
+// is held in registers and equal labels are merged by pairwise compares.
+template <typename W>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_cpt_small(CArgs a, int64_t n) {
+    constexpr int MAXD = 8;
+    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (v >= n) return;
+    const int64_t rs = a.row_ptr[v];
+    const int d = (int)(a.row_ptr[v + 1] - rs);
+    if (d < 1 || d > MAXD) return;
+    const int g = graph_of(a.gid, v);
+    if (a.st[g].done) return;
+    const int64_t tw = a.tw[g];
+    const uint64_t own = a.vw[v];
+    const int32_t ci = vw_label(own);
+    const uint32_t own_hi = (uint32_t)(own >> 32);
+    const int64_t di = a.delta[v];
+    int32_t lab[MAXD];
+    uint32_t hi[MAXD], wt[MAXD];
+#pragma unroll
+    for (int p = 0; p < MAXD; ++p) {
+        lab[p] = -1;
+        wt[p] = 0;
+        hi[p] = 0;
+        if (p < d) {
+            lab[p] = a.col[rs + p];
+            wt[p] = cw<W>(a.w, rs + p);
+        }
+    }
+    uint32_t loop = 0;
+#pragma unroll
+    for (int p = 0; p < MAXD; ++p) {
+        if (p < d) {
+            if (lab[p] == (int32_t)v) {
+                loop += wt[p];
+                lab[p] = -1;
+            } else {
+                const uint64_t nw = a.vw[lab[p]];
+                lab[p] = vw_label(nw);
+                hi[p] = (uint32_t)(nw >> 32);
+            }
+        }
+    }
+    uint32_t e_own = 0;
+#pragma unroll
+    for (int p = 0; p < MAXD; ++p) {
+        if (lab[p] == ci) {
+            e_own += wt[p];
+            lab[p] = -1;
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < MAXD; ++p) {
+#pragma unroll
+        for (int q = p + 1; q < MAXD; ++q) {
+            if (lab[p] >= 0 && lab[q] == lab[p]) {
+                wt[p] += wt[q];
+                lab[q] = -1;
+            }
+        }
+    }
+    bool has = false;
+    int64_t bs = 0;
+    int32_t bl = 0;
+    bool bsingle = false;
+#pragma unroll
+    for (int p = 0; p < MAXD; ++p) {
+        if (lab[p] < 0) continue;
+        const int64_t sc = tw * (int64_t)wt[p] - di * (int64_t)hi_deg(hi[p]);
+        if (!has || sc > bs || (sc == bs && lab[p] < bl)) {
+            has = true;
+            bs = sc;
+            bl = lab[p];
+            bsingle = hi_single(hi[p]);
+        }
+    }
+    a.c_nxt[v] = cpt_decide(a.singlet, tw, ci, own_hi, di, e_own, has, bs, bl, bsingle);
+    a.e_self[v] = e_own + loop;
+}
+
+// ----------------------------------------------------------- packed groups --
+
+// LDS table slot: key = label; ed = e_{i->C} in the low 32 bits, the
+// community's published high word (degree | singleton flag) in the high 32
+// bits, added once by the thread that claims the slot.
+__device__ __forceinline__ void cpt_insert(int32_t *key, unsigned long long *ed, uint8_t *own, int bits, int32_t k,
+                                           uint32_t w, uint32_t hi, int owner) {
+    const uint32_t mask = (1u << bits) - 1;
+    uint32_t h = ((uint32_t)k * 0x9E3779B1u) >> (32 - bits);
+    while (true) {
+        const int32_t cur = ((volatile int32_t *)key)[h];
+        if (cur == k) {
+            atomicAdd(&ed[h], (unsigned long long)w);
+            return;
+        }
+        if (cur == kEmpty) {
+            const int32_t prev = atomicCAS(&key[h], kEmpty, k);
+            if (prev == kEmpty) {
+                own[h] = (uint8_t)owner;
+                atomicAdd(&ed[h], ((unsigned long long)hi << 32) + w);
+                return;
+            }
+            if (prev == k) {
+                atomicAdd(&ed[h], (unsigned long long)w);
+                return;
+            }
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+__device__ __forceinline__ int cpt_bits(int64_t d) { return d > 0 ? 64 - __clzll((unsigned long long)(2 * d - 1)) : 0; }
+
+__device__ __forceinline__ int cpt_find(const int32_t *a, int n, int32_t x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+constexpr int kCptUnroll = 4;
+
+// Packed workgroups (WIN < SLOTS): the vertices whose line position lies in
+// [b*WIN, (b+1)*WIN), at most MAXV of them, tables of 2^ceil(log2(2d)) <= WIN
+// slots.  Wide mode (WIN == SLOTS, MAXV == 1): one vertex per workgroup.
+// Vertices of graphs whose phase is over take part with no entries and
+// write nothing.
+template <int SLOTS, int WIN, int MAXV, typename W>
+__global__ __launch_bounds__(256) void k_cpt_pack(CArgs a, const int32_t *__restrict__ list,
+                                                  const int64_t *__restrict__ pos, const int64_t *__restrict__ first,
+                                                  int64_t count) {
+    constexpr bool kWide = WIN == SLOTS;
+    __shared__ int32_t s_key[SLOTS];
+    __shared__ unsigned long long s_ed[SLOTS];
+    __shared__ uint8_t s_own[SLOTS];
+    __shared__ int32_t s_v[MAXV], s_ci[MAXV], s_toff[MAXV], s_eoff[MAXV], s_bits[MAXV], s_bestl[MAXV];
+    __shared__ int32_t s_bestf[MAXV];
+    __shared__ int64_t s_rs[MAXV], s_delta[MAXV], s_tw[MAXV];
+    __shared__ unsigned long long s_best[MAXV];
+    __shared__ uint32_t s_eown[MAXV], s_loop[MAXV];
+    __shared__ int32_t s_E;
+    const int t = threadIdx.x;
+    int64_t k0;
+    int nv;
+    if constexpr (kWide) {
+        k0 = blockIdx.x;
+        nv = k0 < count ? 1 : 0;
+    } else {
+        k0 = first[blockIdx.x];
+        nv = (int)(first[blockIdx.x + 1] - k0);
+    }
+    const int64_t lo_pos = (int64_t)blockIdx.x * WIN;
+    for (int x = t; x < SLOTS; x += 256) {
+        s_key[x] = kEmpty;
+        s_ed[x] = 0;
+    }
+    // descriptors: thread t owns vertex t
+    int32_t v = 0, ci = 0;
+    uint32_t own_hi = 0;
+    int64_t d = 0, di = 0, tw = 0;
+    bool live = false;
+    if (t < nv) {
+        v = list[k0 + t];
+        const int g = graph_of(a.gid, v);
+        live = !a.st[g].done;
+        const int64_t rs = a.row_ptr[v];
+        d = live ? a.row_ptr[v + 1] - rs : 0;
+        const uint64_t own = a.vw[v];
+        ci = vw_label(own);
+        own_hi = (uint32_t)(own >> 32);
+        di = a.delta[v];
+        tw = a.tw[g];
+        s_v[t] = v;
+        s_ci[t] = ci;
+        s_rs[t] = rs;
+        s_delta[t] = di;
+        s_tw[t] = tw;
+        s_toff[t] = kWide ? 0 : (int32_t)(pos[k0 + t] - lo_pos);
+        s_bits[t] = cpt_bits(d);
+        s_best[t] = 0;
+        s_bestl[t] = 0x7fffffff;
+        s_bestf[t] = 0;
+        s_eown[t] = 0;
+        s_loop[t] = 0;
+    }
+    if (t < 64) {   // edge offsets: exclusive scan of the row lengths (MAXV <= 64)
+        int32_t x = t < nv ? (int32_t)d : 0;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int32_t y = __shfl_up(x, off);
+            if (t >= off) x += y;
+        }
+        if (t < MAXV) s_eoff[t] = x - (t < nv ? (int32_t)d : 0);
+        if (t == 63) s_E = x;
+    }
+    __syncthreads();
+    const int32_t E = s_E;
+    for (int32_t base = 0; base < E; base += 256 * kCptUnroll) {
+        int kk[kCptUnroll];
+        int64_t e[kCptUnroll];
+        int32_t j[kCptUnroll];
+        uint32_t w[kCptUnroll];
+        uint64_t nw[kCptUnroll];
+#pragma unroll
+        for (int u = 0; u < kCptUnroll; ++u) {
+            const int32_t x = base + u * 256 + t;
+            kk[u] = -1;
+            if (x < E) {
+                kk[u] = kWide ? 0 : cpt_find(s_eoff, nv, x);
+                e[u] = s_rs[kk[u]] + (x - s_eoff[kk[u]]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kCptUnroll; ++u) {
+            if (kk[u] >= 0) {
+                j[u] = a.col[e[u]];
+                w[u] = cw<W>(a.w, e[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kCptUnroll; ++u)
+            if (kk[u] >= 0 && j[u] != s_v[kk[u]]) nw[u] = a.vw[j[u]];
+#pragma unroll
+        for (int u = 0; u < kCptUnroll; ++u) {
+            if (kk[u] < 0) continue;
+            if (j[u] == s_v[kk[u]])
+                atomicAdd(&s_loop[kk[u]], w[u]);
+            else
+                cpt_insert(s_key + s_toff[kk[u]], s_ed + s_toff[kk[u]], s_own + s_toff[kk[u]], s_bits[kk[u]],
+                           vw_label(nw[u]), w[u], (uint32_t)(nw[u] >> 32), kk[u]);
+        }
+    }
+    __syncthreads();
+    // scores (order key = score with the sign bit flipped) replace the slot's
+    // weight word; the own community is recorded and removed; the winner's
+    // singleton flag moves to bit 7 of the owner byte
+    constexpr int SPT = SLOTS / 256;
+    const int32_t used = nv > 0 ? s_toff[nv - 1] + (1 << s_bits[nv - 1]) : 0;
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+        const int32_t x = q * 256 + t;
+        if (x >= used) continue;
+        const int32_t key = s_key[x];
+        if (key == kEmpty) continue;
+        const int kv = s_own[x];
+        const unsigned long long ed = s_ed[x];
+        if (key == s_ci[kv]) {
+            s_eown[kv] = (uint32_t)ed;
+            s_key[x] = kEmpty;
+            continue;
+        }
+        const uint32_t hi = (uint32_t)(ed >> 32);
+        const int64_t sc = s_tw[kv] * (int64_t)(uint32_t)ed - s_delta[kv] * (int64_t)hi_deg(hi);
+        const unsigned long long ok = (unsigned long long)sc ^ 0x8000000000000000ull;
+        s_ed[x] = ok;
+        s_own[x] = (uint8_t)(kv | (hi_single(hi) ? 0x80 : 0));
+        atomicMax(&s_best[kv], ok);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+        const int32_t x = q * 256 + t;
+        if (x >= used) continue;
+        const int32_t key = s_key[x];
+        if (key == kEmpty) continue;
+        const int kv = s_own[x] & 0x7f;
+        if (s_ed[x] == s_best[kv]) atomicMin(&s_bestl[kv], key);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+        const int32_t x = q * 256 + t;
+        if (x >= used) continue;
+        const int32_t key = s_key[x];
+        if (key == kEmpty) continue;
+        const int kv = s_own[x] & 0x7f;
+        if (key == s_bestl[kv] && s_ed[x] == s_best[kv]) s_bestf[kv] = (s_own[x] >> 7) & 1;
+    }
+    __syncthreads();
+    if (t < nv && live) {
+        const bool has = s_best[t] != 0;
+        const int64_t bs = (int64_t)(s_best[t] ^ 0x8000000000000000ull);
+        const int64_t e_own = (int64_t)s_eown[t];
+        a.c_nxt[v] = cpt_decide(a.singlet, tw, ci, own_hi, di, e_own, has, bs, s_bestl[t], s_bestf[t] != 0);
+        a.e_self[v] = s_eown[t] + s_loop[t];
+    }
+}
+
+// ------------------------------------------------------------------ hubs --
+
+struct CHub {
+    const int32_t *v;
+    const int64_t *tab_off, *chunk_off, *scan_off, *tab_size;
+    const int32_t *chunk_hub, *scan_hub;
+    int64_t hubs;
+};
+
+constexpr int kCHubLdsBits = 11;
+
+// Workgroup per kHubChunk entries of a hub row: LDS pre-aggregation of
+// (label -> e, published high word), then one HBM insert per distinct label.
+template <typename W>
+__global__ __launch_bounds__(256) void k_cpt_hub_accum(CArgs a, CHub hm, int32_t *gkey, unsigned long long *ged,
+                                                       unsigned long long *hub_loop) {
+    constexpr int T = 1 << kCHubLdsBits;
+    __shared__ int32_t s_key[T];
+    __shared__ unsigned long long s_ed[T];
+    __shared__ uint8_t s_own[T];
+    __shared__ int64_t s_h;
+    const int t = threadIdx.x;
+    if (t == 0) s_h = hm.chunk_hub[blockIdx.x];
+    for (int x = t; x < T; x += 256) {
+        s_key[x] = kEmpty;
+        s_ed[x] = 0;
+    }
+    __syncthreads();
+    const int64_t h = s_h;
+    const int32_t v = hm.v[h];
+    if (a.st[graph_of(a.gid, v)].done) return;   // uniform over the workgroup
+    const int64_t k = (int64_t)blockIdx.x - hm.chunk_off[h];
+    const int64_t row_end = a.row_ptr[v + 1];
+    const int64_t rs = a.row_ptr[v] + k * kHubChunk;
+    const int64_t re = rs + kHubChunk < row_end ? rs + kHubChunk : row_end;
+    for (int64_t e = rs + t; e < re; e += 256) {
+        const int32_t j = a.col[e];
+        const uint32_t w = cw<W>(a.w, e);
+        if (j == v) {
+            atomicAdd(&hub_loop[h], (unsigned long long)w);
+            continue;
+        }
+        const uint64_t nw = a.vw[j];
+        cpt_insert(s_key, s_ed, s_own, kCHubLdsBits, vw_label(nw), w, (uint32_t)(nw >> 32), 0);
+    }
+    __syncthreads();
+    const int64_t base = hm.tab_off[h], size = hm.tab_size[h];
+    for (int x = t; x < T; x += 256) {
+        const int32_t key = s_key[x];
+        if (key == kEmpty) continue;
+        const unsigned long long ed = s_ed[x];
+        uint64_t p = hash_range(key, (uint64_t)size);
+        while (true) {
+            const int32_t prev = atomicCAS(&gkey[base + p], kEmpty, key);
+            if (prev == kEmpty) {
+                atomicAdd(&ged[base + p], ed);                       // claimer brings the high word
+                break;
+            }
+            if (prev == key) {
+                atomicAdd(&ged[base + p], (unsigned long long)(uint32_t)ed);
+                break;
+            }
+            p = (p + 1 == (uint64_t)size) ? 0 : p + 1;
+        }
+    }
+}
+
+// Workgroup per kHubScan table slots: partial best (order key, label,
+// singleton flag) and own e; clears the slots for the next pass.
+__global__ __launch_bounds__(256) void k_cpt_hub_scan(CArgs a, CHub hm, int32_t *gkey, unsigned long long *ged,
+                                                      uint64_t *part) {
+    __shared__ int64_t s_h;
+    __shared__ unsigned long long r_ok[4];
+    __shared__ int32_t r_l[4], r_f[4];
+    __shared__ uint32_t r_e[4];
+    const int t = threadIdx.x;
+    if (t == 0) s_h = hm.scan_hub[blockIdx.x];
+    __syncthreads();
+    const int64_t h = s_h;
+    const int32_t v = hm.v[h];
+    const int g = graph_of(a.gid, v);
+    const int32_t ci = vw_label(a.vw[v]);
+    const int64_t di = a.delta[v];
+    const int64_t tw = a.tw[g];
+    const int64_t base = hm.tab_off[h] + ((int64_t)blockIdx.x - hm.scan_off[h]) * kHubScan;
+    unsigned long long bok = 0;
+    int32_t bl = 0x7fffffff, bf = 0;
+    uint32_t e_own = 0;
+#pragma unroll
+    for (int q = 0; q < kHubScan / 256; ++q) {
+        const int64_t x = base + q * 256 + t;
+        const int32_t k = gkey[x];
+        if (k == kEmpty) continue;
+        const unsigned long long ed = ged[x];
+        gkey[x] = kEmpty;
+        ged[x] = 0;
+        if (k == ci) {
+            e_own += (uint32_t)ed;
+            continue;
+        }
+        const uint32_t hi = (uint32_t)(ed >> 32);
+        const int64_t sc = tw * (int64_t)(uint32_t)ed - di * (int64_t)hi_deg(hi);
+        const unsigned long long ok = (unsigned long long)sc ^ 0x8000000000000000ull;
+        if (ok > bok || (ok == bok && k < bl)) {
+            bok = ok;
+            bl = k;
+            bf = hi_single(hi) ? 1 : 0;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long ook = __shfl_xor(bok, off);
+        const int32_t ol = __shfl_xor(bl, off);
+        const int32_t of = __shfl_xor(bf, off);
+        if (ook > bok || (ook == bok && ol < bl)) {
+            bok = ook;
+            bl = ol;
+            bf = of;
+        }
+        e_own += __shfl_xor(e_own, off);
+    }
+    const int lane = t & 63, wid = t >> 6;
+    if (lane == 0) {
+        r_ok[wid] = bok;
+        r_l[wid] = bl;
+        r_f[wid] = bf;
+        r_e[wid] = e_own;
+    }
+    __syncthreads();
+    if (t == 0) {
+        for (int w = 1; w < 4; ++w) {
+            if (r_ok[w] > bok || (r_ok[w] == bok && r_l[w] < bl)) {
+                bok = r_ok[w];
+                bl = r_l[w];
+                bf = r_f[w];
+            }
+            e_own += r_e[w];
+        }
+        uint64_t *p = part + 4 * (int64_t)blockIdx.x;
+        p[0] = bok;
+        p[1] = (uint64_t)(uint32_t)bl | ((uint64_t)bf << 32);
+        p[2] = e_own;
+        p[3] = 0;
+    }
+}
+
+// Wavefront per hub: combine the scan partials and decide.
+__global__ __launch_bounds__(256) void k_cpt_hub_decide(CArgs a, CHub hm, const uint64_t *part,
+                                                        unsigned long long *hub_loop) {
+    const int lane = threadIdx.x & 63;
+    const int64_t h = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (h >= hm.hubs) return;
+    const int32_t v = hm.v[h];
+    const int g = graph_of(a.gid, v);
+    if (a.st[g].done) return;
+    unsigned long long bok = 0;
+    int32_t bl = 0x7fffffff, bf = 0;
+    uint64_t e_own = 0;
+    for (int64_t b = hm.scan_off[h] + lane; b < hm.scan_off[h + 1]; b += 64) {
+        const uint64_t *p = part + 4 * b;
+        const unsigned long long ok = p[0];
+        const int32_t l = (int32_t)(uint32_t)p[1];
+        if (ok > bok || (ok == bok && l < bl)) {
+            bok = ok;
+            bl = l;
+            bf = (int32_t)(p[1] >> 32);
+        }
+        e_own += p[2];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long ook = __shfl_xor(bok, off);
+        const int32_t ol = __shfl_xor(bl, off);
+        const int32_t of = __shfl_xor(bf, off);
+        if (ook > bok || (ook == bok && ol < bl)) {
+            bok = ook;
+            bl = ol;
+            bf = of;
+        }
+        e_own += __shfl_xor(e_own, off);
+    }
+    if (lane == 0) {
+        const uint64_t own = a.vw[v];
+        const int32_t ci = vw_label(own);
+        const int64_t di = a.delta[v];
+        a.c_nxt[v] = cpt_decide(a.singlet, a.tw[g], ci, (uint32_t)(own >> 32), di, (int64_t)e_own, bok != 0,
+                                (int64_t)(bok ^ 0x8000000000000000ull), bl, bf != 0);
+        a.e_self[v] = (uint32_t)(e_own + hub_loop[h]);
+        hub_loop[h] = 0;
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- host --
+
+void compact_init_singletons(int32_t *c0, int32_t *c1, int32_t *c2, const int64_t *delta, uint64_t *ds, uint32_t *es,
+                             int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_cpt_init_singletons<<<grid_for(n, 256), 256, 0, s>>>(c0, c1, c2, delta, ds, es, n);
+    LV_LAUNCHED("k_cpt_init_singletons");
+}
+
+void compact_init_labels(int32_t *c0, int32_t *c1, int32_t *c2, const int32_t *labels, const int64_t *delta,
+                         uint64_t *ds, uint32_t *es, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    k_cpt_init_labels<<<grid_for(n, 256), 256, 0, s>>>(c0, c1, c2, labels, delta, ds, es, n);
+    LV_LAUNCHED("k_cpt_init_labels");
+}
+
+void compact_final_labels(const int32_t *c0, const int32_t *c1, const int32_t *c2, const int32_t *gid,
+                          const PhaseState *st, int64_t n, int32_t *out, hipStream_t s, Timer *t) {
+    if (n <= 0) return;
+    TimedLaunch tl(t, TG_CONTRACT, "k_cpt_final_labels", (double)n * 12);
+    k_cpt_final_labels<<<grid_for(n, 256), 256, 0, s>>>(c0, c1, c2, gid, st, n, out);
+    LV_LAUNCHED("k_cpt_final_labels");
+}
+
+void compact_expand(const uint64_t *ds, const uint32_t *es, int64_t n, int64_t *deg, int32_t *size, int64_t *e_self,
+                    hipStream_t s) {
+    if (n <= 0) return;
+    k_cpt_expand<<<grid_for(n, 256), 256, 0, s>>>(ds, es, n, deg, size, e_self);
+    LV_LAUNCHED("k_cpt_expand");
+}
+
+template <typename W>
+static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s, Timer *t) {
+    const char *wn = type_name<W>();
+    const std::string sfx = t ? std::string(wn) + ">" : std::string();
+    const double eb = 8.0 + sizeof(W);   // column, weight, neighbour word
+    const double vb = 40.0;
+    auto bytes = [&](int b0, int b1) {
+        double x = 0;
+        for (int b = b0; b < b1; ++b) x += (double)(cp.bstart[b + 1] - cp.bstart[b]) * vb + (double)cp.bnnz[b] * eb;
+        return x;
+    };
+    if (cp.bstart[B_T16] - cp.bstart[B_T8] > 0) {
+        TimedLaunch tl(t, TG_SWEEP, "k_cpt_small<", bytes(B_T8, B_T16), sfx.c_str());
+        k_cpt_small<W><<<grid_for(cp.n, 256), 256, 0, s>>>(a, cp.n);
+        LV_LAUNCHED("k_cpt_small");
+    }
+    if (cp.pack_blocks > 0) {
+        TimedLaunch tl(t, TG_SWEEP, "k_cpt_pack<2048,1024,64,", bytes(B_T16, B_BLOCK), sfx.c_str());
+        k_cpt_pack<2048, 1024, 64, W><<<(unsigned)cp.pack_blocks, 256, 0, s>>>(
+            a, cp.list + cp.bstart[B_T16], cp.pack_pos, cp.pack_first, cp.bstart[B_BLOCK] - cp.bstart[B_T16]);
+        LV_LAUNCHED("k_cpt_pack");
+    }
+    const int64_t nw = cp.bstart[B_HUB] - cp.bstart[B_BLOCK];
+    if (nw > 0) {
+        TimedLaunch tl(t, TG_SWEEP, "k_cpt_pack<2048,2048,1,", bytes(B_BLOCK, B_HUB), sfx.c_str());
+        k_cpt_pack<2048, 2048, 1, W><<<(unsigned)nw, 256, 0, s>>>(a, cp.list + cp.bstart[B_BLOCK], nullptr, nullptr,
+                                                                   nw);
+        LV_LAUNCHED("k_cpt_pack<wide>");
+    }
+    if (cp.hubs > 0) {
+        CHub hm{cp.list + cp.bstart[B_HUB], cp.tab_off, cp.chunk_off, cp.scan_off, cp.tab_size,
+                cp.chunk_hub, cp.scan_hub, cp.hubs};
+        {
+            TimedLaunch tl(t, TG_SWEEP, "k_cpt_hub_accum<", (double)cp.bnnz[B_HUB] * eb, sfx.c_str());
+            k_cpt_hub_accum<W><<<(unsigned)cp.hub_chunks, 256, 0, s>>>(a, hm, cp.hkey, cp.hval, cp.hloop);
+            LV_LAUNCHED("k_cpt_hub_accum");
+        }
+        {
+            TimedLaunch tl(t, TG_SWEEP, "k_cpt_hub_scan", (double)cp.hub_scans * kHubScan * 24.0);
+            k_cpt_hub_scan<<<(unsigned)cp.hub_scans, 256, 0, s>>>(a, hm, cp.hkey, cp.hval, cp.hpart);
+            LV_LAUNCHED("k_cpt_hub_scan");
+        }
+        {
+            TimedLaunch tl(t, TG_SWEEP, "k_cpt_hub_decide", (double)cp.hubs * vb + (double)cp.hub_scans * 32.0);
+            k_cpt_hub_decide<<<grid_for(cp.hubs, 4), 256, 0, s>>>(a, hm, cp.hpart, cp.hloop);
+            LV_LAUNCHED("k_cpt_hub_decide");
+        }
+    }
+}
+
+void compact_pass(const GraphView &g, const CompactPass &cp, const CompactState &cs, int p,
+                  const SweepParams &prm, hipStream_t s, Timer *t) {
+    if (g.n > 0) {
+        TimedLaunch tl(t, TG_SWEEP, "k_cpt_publish", (double)g.n * 28);
+        k_cpt_publish<<<grid_for(g.n, kPubTile), 256, 0, s>>>(cs.ds, cs.c_cur, cs.vw, cs.gid, cs.st, g.n,
+                                                              cs.active + (p & 1));
+        LV_LAUNCHED("k_cpt_publish");
+    }
+    CArgs a{g.row_ptr, g.col, g.w, cs.c_cur, cs.c_nxt, g.delta, cs.vw, cs.gid, cs.tw, cs.st, cs.es, prm.singlet};
+    if (g.wbytes == 4)
+        compact_sweeps<int32_t>(a, cp, s, t);
+    else
+        compact_sweeps<int64_t>(a, cp, s, t);
+    if (g.n > 0) {
+        TimedLaunch tl(t, TG_SWEEP, "k_cpt_commit", (double)g.n * 12);
+        k_cpt_commit<<<grid_for(g.n, kCommitTile), 256, 0, s>>>(cs.c_cur, cs.c_nxt, g.delta, cs.es, cs.ds, cs.gid,
+                                                                cs.st, g.n);
+        LV_LAUNCHED("k_cpt_commit");
+    }
+    {
+        TimedLaunch tl(t, TG_SWEEP, "k_cpt_finalize", 0.0);
+        k_cpt_finalize<<<grid_for(cs.ngraphs, 256), 256, 0, s>>>(cs.st, cs.tw, cs.ngraphs, prm.theta_num,
+                                                                 prm.theta_den, prm.max_sweeps, p,
+                                                                 cs.active + (p & 1));
+        LV_LAUNCHED("k_cpt_finalize");
+    }
+}
+
+}  // namespace lv

@@ -53,3 +53,26 @@ def test_binding_fails_loudly_without_library(tmp_path):
     from paper_1805_10904_amd import _native
     with pytest.raises(RuntimeError, match="not built"):
         _native.load_library(str(tmp_path / "missing.so"))
+
+
+def test_workspace_bytes_bounds_the_served_footprint():
+    """The admission estimate grows with the graph and covers at least the
+    bytes a level-0 graph occupies in the batch (resident CSR, two union
+    copies, sort keys and values of the contraction)."""
+    from paper_1805_10904_amd import workspace_bytes
+    assert workspace_bytes(0, 0) > 0
+    prev = 0
+    for n, nnz in [(10, 20), (1000, 20000), (10**5, 2 * 10**6), (2 * 10**6, 6 * 10**7)]:
+        b = workspace_bytes(n, nnz)
+        assert b > prev
+        prev = b
+        floor = (8 * (n + 1) + 4 * nnz + 4 * nnz + 8 * n + 4 * n) + 2 * (16 * n + 12 * nnz) + 32 * nnz
+        assert b >= floor
+    assert workspace_bytes(-1, 5) == 0
+
+
+def test_served_and_batched_calls_are_declared():
+    names = declared_functions()
+    for f in ("louvain_run_batch", "louvain_submit", "louvain_poll", "louvain_workspace_bytes",
+              "louvain_serve_budget"):
+        assert f in names
