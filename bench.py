@@ -60,7 +60,7 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
 
 
-def bench_batched(L, torch, graphs, warmup: int):
+def bench_batched(L, torch, graphs, warmup: int, profile: bool = False):
     """One louvain_run_batch call against the plain louvain_run loop on the
     same device-resident graphs; outputs must be identical."""
     ctx = L.Context(0)
@@ -82,6 +82,16 @@ def bench_batched(L, torch, graphs, warmup: int):
     same = all(torch.equal(a, b) for a, b in zip(out_p, out_b)) and \
         all(p.q_int == r.q_int for p, r in zip(plain, res))
     edges = sum(lv["sweeps_executed"] * lv["nnz"] for r in res for lv in r.stats["levels"])
+    if profile:
+        pr = ctx.run_batch(Gs, labels_out=out_b, stats=True, timing=True)
+        ks = sorted(pr[0].stats["kernels"].items(), key=lambda kv: -kv[1]["ms"])
+        log(f"batched call with kernel timing: {pr[0].stats['ms_total']:.1f} ms device, kernels " +
+            ", ".join(f"{n} {k['ms']:.1f} ms/{k['launches']}" for n, k in ks[:14]))
+        passes = {}
+        for r in res:
+            for lvl, lv in enumerate(r.stats["levels"]):
+                passes[lvl] = max(passes.get(lvl, 0), lv["gpu_passes"])
+        log(f"max device passes per level: {passes}")
     for G in Gs:
         G.destroy()
     ctx.close()
@@ -182,6 +192,7 @@ def main():
                     help="also compare one batched call on this many graphs of the batched SBM workload "
                          "against the plain loop (4096 = the full workload)")
     ap.add_argument("--batched-nmax", type=int, default=100_000)
+    ap.add_argument("--batched-profile", action="store_true", help="log the batched call's kernel table")
     ap.add_argument("--served", type=int, default=0,
                     help="also run the request loop on a Poisson trace over this many distinct Chung-Lu "
                          "request graphs")
@@ -312,7 +323,7 @@ def main():
     batched = served = None
     if batch_graphs is not None:
         log("batched vs plain")
-        batched = bench_batched(L, torch, batch_graphs, warmup=1)
+        batched = bench_batched(L, torch, batch_graphs, warmup=1, profile=args.batched_profile)
         log(f"batched: {batched}")
         del batch_graphs
     if served_pool is not None:

@@ -314,10 +314,17 @@ std::vector<BatchMember *> BatchEngine::step() {
     sw_.plan(v);
     sw_.init_singletons(v);
     int p = 0;
+    unsigned int planned = (unsigned int)ns;   // graphs the current bucket lists cover
     for (;;) {
         for (int b = 0; b < pass_batch_; ++b) sw_.pass(v, ++p, sp_, nullptr);
-        if (sw_.active_after(p) == 0) break;
+        const unsigned int act = sw_.active_after(p);
+        if (act == 0) break;
         require(p <= sp_.max_sweeps + 4 + pass_batch_, LOUVAIN_EDEVICE, "batched sweep loop did not converge");
+        if (2 * act <= planned) {
+            // most graphs have ended their phase: sweep only the others
+            sw_.replan_active(v);
+            planned = act;
+        }
     }
     std::vector<PhaseState> st((size_t)ns);
     LV_HIP(hipMemcpyAsync(st.data(), sw_.states(), sizeof(PhaseState) * (size_t)ns, hipMemcpyDeviceToHost, s_));

@@ -874,8 +874,20 @@ __device__ __forceinline__ int bucket_of(int64_t d) {
     return B_HUB;
 }
 
+// Bucket of vertex v, or -1 if it is not evaluated (empty row, or its graph's
+// phase is over when gid and st are given).
+__device__ __forceinline__ int bucket_of_vertex(const int64_t *__restrict__ rp, const int32_t *__restrict__ gid,
+                                                const PhaseState *__restrict__ st, int64_t v, int64_t *deg) {
+    const int64_t d = rp[v + 1] - rp[v];
+    *deg = d;
+    if (gid && st[gid[v]].done) return -1;
+    return bucket_of(d);
+}
+
 __global__ __launch_bounds__(256) void k_bucket_count(const int64_t *__restrict__ rp, int64_t n, int32_t *counts,
-                                                      int64_t nblocks, unsigned long long *bucket_nnz) {
+                                                      int64_t nblocks, unsigned long long *bucket_nnz,
+                                                      const int32_t *__restrict__ gid,
+                                                      const PhaseState *__restrict__ st) {
     __shared__ int cnt[NBUCKET];
     __shared__ unsigned long long ecnt[NBUCKET];
     if (threadIdx.x < NBUCKET) {
@@ -888,8 +900,8 @@ __global__ __launch_bounds__(256) void k_bucket_count(const int64_t *__restrict_
     for (int k = 0; k < kBucketTile / 256; ++k) {
         const int64_t v = base + k * 256 + threadIdx.x;
         if (v < n) {
-            const int64_t d = rp[v + 1] - rp[v];
-            const int b = bucket_of(d);
+            int64_t d;
+            const int b = bucket_of_vertex(rp, gid, st, v, &d);
             if (b >= 0) {
                 atomicAdd(&cnt[b], 1);
                 atomicAdd(&ecnt[b], (unsigned long long)d);
@@ -907,7 +919,8 @@ __global__ __launch_bounds__(256) void k_bucket_count(const int64_t *__restrict_
 // inside each bucket).
 __global__ __launch_bounds__(256) void k_bucket_scatter(const int64_t *__restrict__ rp, int64_t n,
                                                         const int32_t *__restrict__ offs, int64_t nblocks,
-                                                        int32_t *list) {
+                                                        int32_t *list, const int32_t *__restrict__ gid,
+                                                        const PhaseState *__restrict__ st) {
     __shared__ int run[NBUCKET];
     __shared__ int wc[4][NBUCKET];
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
@@ -917,7 +930,8 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(const int64_t *__restric
     const int64_t base = (int64_t)blockIdx.x * kBucketTile;
     for (int k = 0; k < kBucketTile / 256; ++k) {
         const int64_t v = base + k * 256 + t;
-        const int b = v < n ? bucket_of(rp[v + 1] - rp[v]) : -1;
+        int64_t d;
+        const int b = v < n ? bucket_of_vertex(rp, gid, st, v, &d) : -1;
         int rank = 0;
 #pragma unroll
         for (int bb = 0; bb < NBUCKET; ++bb) {
@@ -989,8 +1003,14 @@ void Sweeper::set_batch(int64_t ngraphs, const int32_t *gid, const int64_t *tw) 
     tw_ = tw;
 }
 
-void Sweeper::plan(const GraphView &g) {
+void Sweeper::plan(const GraphView &g) { plan_impl(g, false); }
+
+void Sweeper::replan_active(const GraphView &g) { plan_impl(g, true); }
+
+void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     n_ = g.n;
+    const int32_t *skip_gid = active_only && batch_ ? gid_ : nullptr;
+    const PhaseState *skip_st = active_only && batch_ ? st_.p : nullptr;
     compact_ = batch_ || g.tw < kCompactTwMax;
     if (!batch_) {
         ngraphs_ = 1;
@@ -1012,14 +1032,15 @@ void Sweeper::plan(const GraphView &g) {
     int32_t *counts = bcount_.p;
     {
         TimedLaunch tl(t_, TG_LEVEL, "k_bucket_count", (double)g.n * 16);
-        k_bucket_count<<<(unsigned)nblk, 256, 0, s_>>>(g.row_ptr, g.n, counts, nblk, bnnz.as<unsigned long long>());
+        k_bucket_count<<<(unsigned)nblk, 256, 0, s_>>>(g.row_ptr, g.n, counts, nblk, bnnz.as<unsigned long long>(),
+                                                       skip_gid, skip_st);
         LV_LAUNCHED("k_bucket_count");
     }
     const int64_t m = NBUCKET * nblk;
     scan_exclusive<int32_t, int32_t>(counts, counts, m, counts + m, s_, t_);
     {
         TimedLaunch tl(t_, TG_LEVEL, "k_bucket_scatter", (double)g.n * 20);
-        k_bucket_scatter<<<(unsigned)nblk, 256, 0, s_>>>(g.row_ptr, g.n, counts, nblk, list_.p);
+        k_bucket_scatter<<<(unsigned)nblk, 256, 0, s_>>>(g.row_ptr, g.n, counts, nblk, list_.p, skip_gid, skip_st);
         LV_LAUNCHED("k_bucket_scatter");
     }
     int32_t hs[NBUCKET + 1];

@@ -115,6 +115,9 @@ class Sweeper {
     void set_batch(int64_t ngraphs, const int32_t *gid, const int64_t *tw);
     // Degree bucketing of the level's vertices (a3) and hub table set-up.
     void plan(const GraphView &g);
+    // Batch, inside a phase: the same plan restricted to graphs whose phase
+    // is still running (labels and phase state are kept).
+    void replan_active(const GraphView &g);
     // Singleton communities (a2): every ring slot = identity, deg = delta, size = 1.
     void init_singletons(const GraphView &g);
     // Communities from labels (device int32[n]): ring slots = labels, deg/size recomputed.
@@ -143,6 +146,7 @@ class Sweeper {
     int64_t bucket_count(int b) const { return bstart_[b + 1] - bstart_[b]; }
 
   private:
+    void plan_impl(const GraphView &g, bool active_only);
     hipStream_t s_;
     Timer *t_;
     int64_t cap_n_ = -1, cap_nnz_ = -1;
