@@ -98,9 +98,11 @@ typedef struct {
 } louvain_kernel_stats;
 
 /* Statistics of a run.  Set `timing` to 1 before the call to record
- * per-kernel device times with HIP events (adds a little overhead). */
+ * per-kernel device times with HIP events around every launch (adds host
+ * overhead per launch), or to 2 to record only the launches whose kernel
+ * name equals `timing_only` (the per-level ms fields then cover only them). */
 typedef struct {
-    int32_t timing;               /* in: 1 = record kernel times                          */
+    int32_t timing;               /* in: 0 off, 1 every kernel, 2 only `timing_only`     */
     int32_t levels;               /* out: phases executed                                  */
     int32_t status;               /* out: LOUVAIN_OK or LOUVAIN_ELIMIT                     */
     int32_t n_kernels;            /* out: entries used in kernels[]                        */
@@ -108,6 +110,7 @@ typedef struct {
     double ms_total;              /* out: device time of the whole run (stats mode)        */
     louvain_level_stats level[64];
     louvain_kernel_stats kernels[LOUVAIN_MAX_KERNEL_STATS];
+    char timing_only[40];         /* in: kernel name for timing == 2 (as in kernels[])     */
 } louvain_run_stats;
 
 /* ---- context ------------------------------------------------------------ */

@@ -64,7 +64,8 @@ class louvain_request_result(C.Structure):
 class louvain_run_stats(C.Structure):
     _fields_ = [("timing", C.c_int32), ("levels", C.c_int32), ("status", C.c_int32),
                 ("n_kernels", C.c_int32), ("total_edges_swept", C.c_int64), ("ms_total", C.c_double),
-                ("level", louvain_level_stats * 64), ("kernels", louvain_kernel_stats * 64)]
+                ("level", louvain_level_stats * 64), ("kernels", louvain_kernel_stats * 64),
+                ("timing_only", C.c_char * 40)]
 
 
 _lib = None
@@ -364,9 +365,12 @@ class Context:
         return Graph(self, h, dev), ren
 
     def run(self, g: Graph, theta_num: int = 1, theta_den: int = 1_000_000, max_sweeps: int = 1000,
-            max_levels: int = 64, singlet_rule: bool = True, pass_batch: int = 0, timing: bool = False,
+            max_levels: int = 64, singlet_rule: bool = True, pass_batch: int = 0, timing=False,
             device: Optional[bool] = None, labels_out=None) -> RunResult:
-        """The whole method (Alg. 2 over Alg. 1 phases)."""
+        """The whole method (Alg. 2 over Alg. 1 phases).
+
+        timing: False, True (HIP events around every launch) or a kernel
+        name as it appears in stats["kernels"] (events around its launches only)."""
         dev = g.dev if device is None else device
         n, _, _ = g.info()
         out = labels_out if labels_out is not None else _empty_like_kind(dev, n, np.int32, self.torch_device)
@@ -374,7 +378,11 @@ class Context:
         qi = louvain_i128()
         q = C.c_double()
         st = louvain_run_stats()
-        st.timing = 1 if timing else 0
+        if isinstance(timing, str):
+            st.timing = 2
+            st.timing_only = timing.encode()[:39]
+        else:
+            st.timing = 1 if timing else 0
         rc = self._check(self.lib.louvain_run(self.h, g.h, C.byref(prm), _ptr(out), C.byref(qi), C.byref(q),
                                               C.byref(st), LOUVAIN_DEVICE_PTRS if dev else 0),
                          ok=(LOUVAIN_OK, LOUVAIN_ELIMIT))

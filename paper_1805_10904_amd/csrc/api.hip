@@ -212,11 +212,12 @@ namespace lv {
 
 // Alg. 2 on one graph: phases of sweeps, renumbering and contraction until a
 // phase keeps no sweep.  fin_p (device int32[n]) receives the final labels.
-int run_plain(const GraphView &g0, const louvain_params &prm, hipStream_t s, Timer &timer, bool timing, int32_t *fin_p,
+int run_plain(const GraphView &g0, const louvain_params &prm, hipStream_t s, Timer &timer, int timing, int32_t *fin_p,
               i128 *q_out, louvain_run_stats *stats_out) {
     int status = LOUVAIN_OK;
     const int batch = prm.pass_batch > 0 ? prm.pass_batch : 1;
-    timer.on = timing;
+    timer.on = timing != 0;
+    if (timing != 2) timer.only.clear();
     timer.reset();
     lv::Timer *t = timing ? &timer : nullptr;
     louvain_run_stats local;
@@ -521,7 +522,14 @@ int louvain_run(louvain_ctx ctx, louvain_graph g, const louvain_params *params, 
         require(labels_out != nullptr || g->n == 0, LOUVAIN_EINVAL, "labels_out must not be NULL");
         const louvain_params prm = checked_params(params);
         hipStream_t s = ctx->stream;
-        const bool timing = stats && stats->timing;
+        const int timing = stats ? stats->timing : 0;
+        require(timing >= 0 && timing <= 2, LOUVAIN_EINVAL, "stats->timing must be 0, 1 or 2");
+        if (timing == 2) {
+            char only[sizeof stats->timing_only + 1];
+            memcpy(only, stats->timing_only, sizeof stats->timing_only);
+            only[sizeof stats->timing_only] = 0;
+            ctx->timer.only = only;
+        }
         louvain_run_stats local;
         DevBuf<int32_t> fin((size_t)g->n);
         lv::i128 q_final = 0;
@@ -532,10 +540,14 @@ int louvain_run(louvain_ctx ctx, louvain_graph g, const louvain_params *params, 
         if (q) *q = q_of(q_final, g->tw);
         if (stats) {
             local.timing = stats->timing;
+            memcpy(local.timing_only, stats->timing_only, sizeof local.timing_only);
             *stats = local;
         }
     });
-    if (ctx) ctx->timer.on = false;
+    if (ctx) {
+        ctx->timer.on = false;
+        ctx->timer.only.clear();
+    }
     return rc != LOUVAIN_OK ? rc : status;
 }
 
@@ -680,7 +692,15 @@ int louvain_run_batch(louvain_ctx ctx, int64_t ngraphs, const louvain_graph *gra
         }
 
         lv::Timer &timer = ctx->timer;
+        require(timing >= 0 && timing <= 2, LOUVAIN_EINVAL, "stats[0].timing must be 0, 1 or 2");
         timer.on = timing != 0;
+        timer.only.clear();
+        if (timing == 2) {
+            char only[sizeof stats[0].timing_only + 1];
+            memcpy(only, stats[0].timing_only, sizeof stats[0].timing_only);
+            only[sizeof stats[0].timing_only] = 0;
+            timer.only = only;
+        }
         timer.reset();
         lv::Timer *t = timing ? &timer : nullptr;
         hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -744,6 +764,7 @@ int louvain_run_batch(louvain_ctx ctx, int64_t ngraphs, const louvain_graph *gra
             collect_kernel_stats(timer, &st_local[0], 0, timer.recs.size(), nullptr, nullptr);
         }
         timer.on = false;
+        timer.only.clear();
         LV_HIP(hipStreamSynchronize(s));
         for (int64_t i = 0; i < ngraphs; ++i) {
             if (q_int) q_int[i] = to_abi(qv[(size_t)i]);
@@ -753,7 +774,10 @@ int louvain_run_batch(louvain_ctx ctx, int64_t ngraphs, const louvain_graph *gra
         }
         if (stats) memcpy(stats, st_local.data(), sizeof(louvain_run_stats) * (size_t)ngraphs);
     });
-    if (ctx) ctx->timer.on = false;
+    if (ctx) {
+        ctx->timer.on = false;
+        ctx->timer.only.clear();
+    }
     return rc != LOUVAIN_OK ? rc : status;
 }
 

@@ -168,6 +168,7 @@ enum TimerGroup { TG_INGEST = 0, TG_LEVEL, TG_SWEEP, TG_CONTRACT, TG_OTHER };
 // Optional per-launch device timing with HIP events (run statistics).
 struct Timer {
     bool on = false;
+    std::string only;   // non-empty: record only launches of this name
     hipStream_t stream = nullptr;
     struct Rec {
         std::string name;
@@ -188,7 +189,9 @@ struct Timer {
     }
     int begin(int group, const char *name, const char *suffix, double bytes) {
         if (!on) return -1;
-        Rec r{std::string(name) + (suffix ? suffix : ""), group, next_event(), next_event(), bytes};
+        std::string full = std::string(name) + (suffix ? suffix : "");
+        if (!only.empty() && full != only) return -1;
+        Rec r{std::move(full), group, next_event(), next_event(), bytes};
         LV_HIP(hipEventRecord(r.a, stream));
         recs.push_back(std::move(r));
         return (int)recs.size() - 1;

@@ -11,7 +11,8 @@ namespace lv {
 // sweep or a cap is reached.  fin_p (device int32[g0.n]) receives the final
 // labels, *q_out Q_int of them, *stats_out the run record (kernel times when
 // timing).  Returns LOUVAIN_OK or LOUVAIN_ELIMIT; throws Error.
-int run_plain(const GraphView &g0, const louvain_params &prm, hipStream_t s, Timer &timer, bool timing, int32_t *fin_p,
+// timing: 0 off, 1 every launch, 2 only launches named timer.only.
+int run_plain(const GraphView &g0, const louvain_params &prm, hipStream_t s, Timer &timer, int timing, int32_t *fin_p,
               i128 *q_out, louvain_run_stats *stats_out);
 
 }  // namespace lv

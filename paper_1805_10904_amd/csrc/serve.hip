@@ -223,7 +223,7 @@ void Server::loop() {
                 if (r->tw >= kCompactTwMax) {
                     // too heavy for the batch's compact words: the plain path, alone
                     louvain_run_stats st;
-                    r->status = run_plain(r->member.g0, r->prm, s, timer, false, r->d_fin.p, &r->q, &st);
+                    r->status = run_plain(r->member.g0, r->prm, s, timer, 0, r->d_fin.p, &r->q, &st);
                     for (int l = 0; l < st.levels; ++l) {
                         LevelRec rec;
                         rec.n = st.level[l].n;

@@ -1100,7 +1100,7 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     LV_LAUNCHED("k_hub_map");
     k_hub_map<<<(unsigned)hubs_, 256, 0, s_>>>(scan_off, hubs_, hub_of_scan_.p);
     LV_LAUNCHED("k_hub_map");
-    fill<int32_t>(hub_key_.p, kEmpty, hub_slots_, s_);
+    if (!compact_) fill<int32_t>(hub_key_.p, kEmpty, hub_slots_, s_);   // compact tables are one word per slot
     fill<uint64_t>((uint64_t *)hub_val_.p, 0, hub_slots_, s_);
     fill<uint64_t>((uint64_t *)hub_loop_.p, 0, hubs_, s_);
 }

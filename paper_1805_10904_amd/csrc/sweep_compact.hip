@@ -45,6 +45,7 @@ struct CArgs {
     int32_t *c_nxt;
     const int64_t *delta;
     const uint64_t *vw;      // published words of the labelling read
+    const uint64_t *ds;      // community words of the labelling read (not written during the sweep)
     const int32_t *gid;      // graph of every vertex (nullptr: a single graph)
     const int64_t *tw;       // TW of every graph
     const PhaseState *st;    // phase state of every graph
@@ -190,30 +191,71 @@ __global__ __launch_bounds__(256) void k_cpt_publish(const uint64_t *__restrict_
 
 // ------------------------------------------------------------------ commit --
 
-constexpr int kCommitTile = 256;
+constexpr int kCommitTile = 512;
+constexpr int kCommitBits = 11;   // LDS table of 2^11 slots: at most two updates per vertex of the tile
 
+// Add x to community k's pending update in the workgroup's LDS table.
+__device__ __forceinline__ void commit_insert(int32_t *key, unsigned long long *val, int32_t k,
+                                              unsigned long long x) {
+    constexpr uint32_t mask = (1u << kCommitBits) - 1;
+    uint32_t h = ((uint32_t)k * 0x9E3779B1u) >> (32 - kCommitBits);
+    while (true) {
+        const int32_t cur = ((volatile int32_t *)key)[h];
+        if (cur == k) {
+            atomicAdd(&val[h], x);
+            return;
+        }
+        if (cur == kEmpty) {
+            const int32_t prev = atomicCAS(&key[h], kEmpty, k);
+            if (prev == kEmpty || prev == k) {
+                atomicAdd(&val[h], x);
+                return;
+            }
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+// Movers' community updates (size +-1, degree +-delta in one word) are
+// summed per community in LDS first, so a community that many vertices of
+// the tile join or leave takes one global atomic instead of one per mover
+// (the sums are integers modulo 2^64, so the result does not depend on the
+// order).
 __global__ __launch_bounds__(256) void k_cpt_commit(const int32_t *__restrict__ c_cur, const int32_t *__restrict__ c_nxt,
                                                     const int64_t *__restrict__ delta, const uint32_t *__restrict__ es,
                                                     uint64_t *ds, const int32_t *__restrict__ gid, PhaseState *st,
                                                     int64_t n) {
+    constexpr int T = 1 << kCommitBits;
     __shared__ unsigned long long acc[kSpan][2];
     __shared__ int s_glo, s_span;
+    __shared__ int32_t s_key[T];
+    __shared__ unsigned long long s_val[T];
+    for (int x = threadIdx.x; x < T; x += 256) {
+        s_key[x] = kEmpty;
+        s_val[x] = 0;
+    }
     const int64_t base = (int64_t)blockIdx.x * kCommitTile;
     const int64_t last = base + kCommitTile - 1 < n - 1 ? base + kCommitTile - 1 : n - 1;
     const SpanSums sp = span_begin(gid, base, last, &s_glo, &s_span, acc);
-    const int64_t v = base + threadIdx.x;
-    if (v <= last) {
+#pragma unroll
+    for (int k = 0; k < kCommitTile / 256; ++k) {
+        const int64_t v = base + k * 256 + threadIdx.x;
+        if (v > last) continue;
         const int g = graph_of(gid, v);
-        if (!st[g].done) {
-            const int32_t from = c_cur[v], to = c_nxt[v];
-            if (from != to) {
-                const uint64_t inc = kSizeOne + (uint64_t)delta[v];
-                atomicAdd((unsigned long long *)&ds[to], (unsigned long long)inc);
-                atomicAdd((unsigned long long *)&ds[from], (unsigned long long)(0 - inc));
-                span_add(sp, acc, 1, g, 1, st, 1);
-            }
-            span_add(sp, acc, 0, g, es[v], st, 0);
+        if (st[g].done) continue;
+        const int32_t from = c_cur[v], to = c_nxt[v];
+        if (from != to) {
+            const uint64_t inc = kSizeOne + (uint64_t)delta[v];
+            commit_insert(s_key, s_val, to, (unsigned long long)inc);
+            commit_insert(s_key, s_val, from, (unsigned long long)(0 - inc));
+            span_add(sp, acc, 1, g, 1, st, 1);
         }
+        span_add(sp, acc, 0, g, es[v], st, 0);
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < T; x += 256) {
+        const int32_t key = s_key[x];
+        if (key != kEmpty && s_val[x] != 0) atomicAdd((unsigned long long *)&ds[key], s_val[x]);
     }
     span_flush(sp, acc, st, 0, 1);
 }
@@ -585,23 +627,44 @@ struct CHub {
 };
 
 constexpr int kCHubLdsBits = 11;
+constexpr unsigned long long kTagMask = 0xffffffff00000000ull;
+
+// Hub tables hold one word per slot: (label + 1) << 32 | e, 0 = empty
+// (labels are below 2^31 and e below TW < 2^31, so the add never carries
+// into the tag).  Insert or add e for a label into a table of `size` slots
+// starting at h0's probe sequence.
+__device__ __forceinline__ void word_insert(unsigned long long *tab, uint64_t size, uint64_t h, int32_t label,
+                                            uint32_t x) {
+    const unsigned long long tag = (unsigned long long)(uint32_t)(label + 1) << 32;
+    while (true) {
+        const unsigned long long cur = ((volatile unsigned long long *)tab)[h];
+        if ((cur & kTagMask) == tag) {
+            atomicAdd(&tab[h], (unsigned long long)x);
+            return;
+        }
+        if (cur == 0) {
+            const unsigned long long prev = atomicCAS(&tab[h], 0ull, tag | x);
+            if (prev == 0) return;
+            if ((prev & kTagMask) == tag) {
+                atomicAdd(&tab[h], (unsigned long long)x);
+                return;
+            }
+        }
+        h = (h + 1 == size) ? 0 : h + 1;
+    }
+}
 
 // Workgroup per kHubChunk entries of a hub row: LDS pre-aggregation of
-// (label -> e, published high word), then one HBM insert per distinct label.
+// label -> e, then one HBM table insert per distinct label.
 template <typename W>
-__global__ __launch_bounds__(256) void k_cpt_hub_accum(CArgs a, CHub hm, int32_t *gkey, unsigned long long *ged,
+__global__ __launch_bounds__(256) void k_cpt_hub_accum(CArgs a, CHub hm, unsigned long long *gtab,
                                                        unsigned long long *hub_loop) {
     constexpr int T = 1 << kCHubLdsBits;
-    __shared__ int32_t s_key[T];
-    __shared__ unsigned long long s_ed[T];
-    __shared__ uint8_t s_own[T];
+    __shared__ unsigned long long s_tab[T];
     __shared__ int64_t s_h;
     const int t = threadIdx.x;
     if (t == 0) s_h = hm.chunk_hub[blockIdx.x];
-    for (int x = t; x < T; x += 256) {
-        s_key[x] = kEmpty;
-        s_ed[x] = 0;
-    }
+    for (int x = t; x < T; x += 256) s_tab[x] = 0;
     __syncthreads();
     const int64_t h = s_h;
     const int32_t v = hm.v[h];
@@ -617,35 +680,23 @@ __global__ __launch_bounds__(256) void k_cpt_hub_accum(CArgs a, CHub hm, int32_t
             atomicAdd(&hub_loop[h], (unsigned long long)w);
             continue;
         }
-        const uint64_t nw = a.vw[j];
-        cpt_insert(s_key, s_ed, s_own, kCHubLdsBits, vw_label(nw), w, (uint32_t)(nw >> 32), 0);
+        const int32_t l = vw_label(a.vw[j]);
+        word_insert(s_tab, T, ((uint32_t)l * 0x9E3779B1u) >> (32 - kCHubLdsBits), l, w);
     }
     __syncthreads();
     const int64_t base = hm.tab_off[h], size = hm.tab_size[h];
     for (int x = t; x < T; x += 256) {
-        const int32_t key = s_key[x];
-        if (key == kEmpty) continue;
-        const unsigned long long ed = s_ed[x];
-        uint64_t p = hash_range(key, (uint64_t)size);
-        while (true) {
-            const int32_t prev = atomicCAS(&gkey[base + p], kEmpty, key);
-            if (prev == kEmpty) {
-                atomicAdd(&ged[base + p], ed);                       // claimer brings the high word
-                break;
-            }
-            if (prev == key) {
-                atomicAdd(&ged[base + p], (unsigned long long)(uint32_t)ed);
-                break;
-            }
-            p = (p + 1 == (uint64_t)size) ? 0 : p + 1;
-        }
+        const unsigned long long wd = s_tab[x];
+        if (wd == 0) continue;
+        const int32_t l = (int32_t)(wd >> 32) - 1;
+        word_insert(gtab + base, (uint64_t)size, hash_range(l, (uint64_t)size), l, (uint32_t)wd);
     }
 }
 
 // Workgroup per kHubScan table slots: partial best (order key, label,
-// singleton flag) and own e; clears the slots for the next pass.
-__global__ __launch_bounds__(256) void k_cpt_hub_scan(CArgs a, CHub hm, int32_t *gkey, unsigned long long *ged,
-                                                      uint64_t *part) {
+// singleton flag) and own e; clears the slots for the next pass.  The
+// community's degree and size come from its community word.
+__global__ __launch_bounds__(256) void k_cpt_hub_scan(CArgs a, CHub hm, unsigned long long *gtab, uint64_t *part) {
     __shared__ int64_t s_h;
     __shared__ unsigned long long r_ok[4];
     __shared__ int32_t r_l[4], r_f[4];
@@ -666,22 +717,22 @@ __global__ __launch_bounds__(256) void k_cpt_hub_scan(CArgs a, CHub hm, int32_t 
 #pragma unroll
     for (int q = 0; q < kHubScan / 256; ++q) {
         const int64_t x = base + q * 256 + t;
-        const int32_t k = gkey[x];
-        if (k == kEmpty) continue;
-        const unsigned long long ed = ged[x];
-        gkey[x] = kEmpty;
-        ged[x] = 0;
+        const unsigned long long wd = gtab[x];
+        if (wd == 0) continue;
+        gtab[x] = 0;
+        const int32_t k = (int32_t)(wd >> 32) - 1;
+        const uint32_t e = (uint32_t)wd;
         if (k == ci) {
-            e_own += (uint32_t)ed;
+            e_own += e;
             continue;
         }
-        const uint32_t hi = (uint32_t)(ed >> 32);
-        const int64_t sc = tw * (int64_t)(uint32_t)ed - di * (int64_t)hi_deg(hi);
+        const uint64_t dsk = a.ds[k];
+        const int64_t sc = tw * (int64_t)e - di * (int64_t)(uint32_t)dsk;
         const unsigned long long ok = (unsigned long long)sc ^ 0x8000000000000000ull;
         if (ok > bok || (ok == bok && k < bl)) {
             bok = ok;
             bl = k;
-            bf = hi_single(hi) ? 1 : 0;
+            bf = (dsk >> 32) == 1 ? 1 : 0;
         }
     }
 #pragma unroll
@@ -834,12 +885,12 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
                 cp.chunk_hub, cp.scan_hub, cp.hubs};
         {
             TimedLaunch tl(t, TG_SWEEP, "k_cpt_hub_accum<", (double)cp.bnnz[B_HUB] * eb, sfx.c_str());
-            k_cpt_hub_accum<W><<<(unsigned)cp.hub_chunks, 256, 0, s>>>(a, hm, cp.hkey, cp.hval, cp.hloop);
+            k_cpt_hub_accum<W><<<(unsigned)cp.hub_chunks, 256, 0, s>>>(a, hm, cp.hval, cp.hloop);
             LV_LAUNCHED("k_cpt_hub_accum");
         }
         {
-            TimedLaunch tl(t, TG_SWEEP, "k_cpt_hub_scan", (double)cp.hub_scans * kHubScan * 24.0);
-            k_cpt_hub_scan<<<(unsigned)cp.hub_scans, 256, 0, s>>>(a, hm, cp.hkey, cp.hval, cp.hpart);
+            TimedLaunch tl(t, TG_SWEEP, "k_cpt_hub_scan", (double)cp.hub_scans * kHubScan * 16.0);
+            k_cpt_hub_scan<<<(unsigned)cp.hub_scans, 256, 0, s>>>(a, hm, cp.hval, cp.hpart);
             LV_LAUNCHED("k_cpt_hub_scan");
         }
         {
@@ -858,7 +909,7 @@ void compact_pass(const GraphView &g, const CompactPass &cp, const CompactState 
                                                               cs.active + (p & 1));
         LV_LAUNCHED("k_cpt_publish");
     }
-    CArgs a{g.row_ptr, g.col, g.w, cs.c_cur, cs.c_nxt, g.delta, cs.vw, cs.gid, cs.tw, cs.st, cs.es, prm.singlet};
+    CArgs a{g.row_ptr, g.col, g.w, cs.c_cur, cs.c_nxt, g.delta, cs.vw, cs.ds, cs.gid, cs.tw, cs.st, cs.es, prm.singlet};
     if (g.wbytes == 4)
         compact_sweeps<int32_t>(a, cp, s, t);
     else
