@@ -307,7 +307,7 @@ def main():
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom_name,
                     "avg_launch_us": round(dom["ms"] * 1000.0 / dom["launches"], 2),
                     "launches_per_step": dom["launches"] / len(results)}
-        top = sorted(agg.items(), key=lambda kv: -kv[1]["ms"])[:8]
+        top = sorted(agg.items(), key=lambda kv: -kv[1]["ms"])[:20]
         log("kernel time of one step (all launches timed): " + ", ".join(f"{n} {a['ms']:.3f} ms" for n, a in top))
         kernel_ms = sum(a["ms"] for a in agg.values())
         log(f"all kernels {kernel_ms:.3f} ms per step ({sum(a['launches'] for a in agg.values()):.0f} "

@@ -317,11 +317,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
 
 // ------------------------------------------------------- packed sweep kernel --
 
-// log2 of the LDS table size of a row of d >= 1 entries: smallest b >= 1
-// with 2^b >= 2d.
-__device__ __forceinline__ int pack_bits(int64_t d) {
-    return 64 - __clzll((unsigned long long)(2 * d - 1));
-}
+__device__ __forceinline__ int pack_bits(int64_t d) { return pack_table_bits(d); }
 
 // Largest k in [0, n) with a[k] <= x (a strictly increasing, a[0] <= x).
 __device__ __forceinline__ int lds_find(const int32_t *a, int n, int32_t x) {

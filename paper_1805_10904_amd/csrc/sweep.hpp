@@ -35,21 +35,28 @@ struct PhaseState {
 };
 
 // Degree buckets: row length d (entries incl. a loop) -> sweep kernel.
-// Row-length buckets.  64-bit scores: <= 8 and <= 16 one thread per vertex,
-// <= 512 packed workgroups, <= 1024 one workgroup per vertex, larger rows the
-// HBM hub path.  128-bit scores: lane groups of 4, 16, 64 and a workgroup.
+// Row-length buckets.  64-bit scores: <= 8 one thread per vertex, <= 341
+// packed workgroups, <= 1024 one workgroup per vertex, larger rows the HBM
+// hub path.  128-bit scores: lane groups of 4, 16, 64 and a workgroup.
 enum { B_T8 = 0, B_T16, B_G64, B_MID, B_BLOCK, B_HUB, NBUCKET };
-constexpr int64_t kBucketMax[NBUCKET - 1] = {8, 16, 128, 512, 1024};
+constexpr int64_t kBucketMax[NBUCKET - 1] = {8, 16, 128, 341, 1024};
 
-// Packed sweep: one workgroup evaluates up to 256 vertices of row length
-// <= kPackMaxDeg whose LDS tables (2^ceil(log2(2d)) slots each) fit
-// kPackSlots slots.  Vertices are laid out on a line by their cost
-// max(table size, kPackMinCost); workgroup b takes the vertices whose line
-// position falls in [b * kPackW, (b + 1) * kPackW).
+// Packed sweep: one workgroup evaluates up to 64 vertices of row length
+// <= kPackMaxDeg (tables of at most 512 slots, see pack_table_bits).
+// Vertices are laid out on a line by their cost max(table size,
+// kPackMinCost); workgroup b takes the vertices whose line position falls in
+// [b * kPackW, (b + 1) * kPackW), so its tables fit kPackW + 512 slots.
 constexpr int kPackSlots = 2048;
-constexpr int kPackW = kPackSlots / 2;
+constexpr int kPackW = 1024;
 constexpr int kPackMinCost = kPackW / 256;
-constexpr int64_t kPackMaxDeg = kPackW / 2;
+constexpr int64_t kPackMaxDeg = 341;
+constexpr int kPackSlotsCompact = kPackW + 512;
+// log2 of the LDS hash table size of a packed row of d >= 1 entries: the
+// smallest b >= 1 with 2^b >= ceil(3d/2) (load at most 2/3).
+__device__ __forceinline__ int pack_table_bits(int64_t d) {
+    const int64_t need = d + (d + 1) / 2;
+    return need <= 2 ? 1 : 64 - __clzll((unsigned long long)(need - 1));
+}
 constexpr int kHubChunk = 1024;      // row entries per hub accumulation workgroup
 constexpr int kHubScan = 1024;       // table slots per hub scan workgroup
 

@@ -438,7 +438,7 @@ __device__ __forceinline__ void cpt_insert(int32_t *key, unsigned long long *ed,
     }
 }
 
-__device__ __forceinline__ int cpt_bits(int64_t d) { return d > 0 ? 64 - __clzll((unsigned long long)(2 * d - 1)) : 0; }
+__device__ __forceinline__ int cpt_bits(int64_t d) { return d > 0 ? pack_table_bits(d) : 0; }
 
 __device__ __forceinline__ int cpt_find(const int32_t *a, int n, int32_t x) {
     int lo = 0, hi = n - 1;
@@ -464,8 +464,8 @@ __global__ __launch_bounds__(256) void k_cpt_pack(CArgs a, const int32_t *__rest
     __shared__ int32_t s_key[SLOTS];
     __shared__ unsigned long long s_ed[SLOTS];
     __shared__ uint8_t s_own[SLOTS];
-    __shared__ int32_t s_v[MAXV], s_ci[MAXV], s_toff[MAXV], s_eoff[MAXV], s_bits[MAXV], s_bestl[MAXV];
-    __shared__ int32_t s_bestf[MAXV];
+    __shared__ int32_t s_v[MAXV], s_ci[MAXV], s_toff[MAXV], s_eoff[MAXV], s_bits[MAXV];
+    __shared__ uint32_t s_bestl[MAXV];
     __shared__ int64_t s_rs[MAXV], s_delta[MAXV], s_tw[MAXV];
     __shared__ unsigned long long s_best[MAXV];
     __shared__ uint32_t s_eown[MAXV], s_loop[MAXV];
@@ -481,10 +481,6 @@ __global__ __launch_bounds__(256) void k_cpt_pack(CArgs a, const int32_t *__rest
         nv = (int)(first[blockIdx.x + 1] - k0);
     }
     const int64_t lo_pos = (int64_t)blockIdx.x * WIN;
-    for (int x = t; x < SLOTS; x += 256) {
-        s_key[x] = kEmpty;
-        s_ed[x] = 0;
-    }
     // descriptors: thread t owns vertex t
     int32_t v = 0, ci = 0;
     uint32_t own_hi = 0;
@@ -509,8 +505,7 @@ __global__ __launch_bounds__(256) void k_cpt_pack(CArgs a, const int32_t *__rest
         s_toff[t] = kWide ? 0 : (int32_t)(pos[k0 + t] - lo_pos);
         s_bits[t] = cpt_bits(d);
         s_best[t] = 0;
-        s_bestl[t] = 0x7fffffff;
-        s_bestf[t] = 0;
+        s_bestl[t] = 0xffffffffu;
         s_eown[t] = 0;
         s_loop[t] = 0;
     }
@@ -526,6 +521,13 @@ __global__ __launch_bounds__(256) void k_cpt_pack(CArgs a, const int32_t *__rest
     }
     __syncthreads();
     const int32_t E = s_E;
+    // clear only the slots the workgroup's tables use
+    const int32_t used = nv > 0 ? s_toff[nv - 1] + (1 << s_bits[nv - 1]) : 0;
+    for (int x = t; x < used; x += 256) {
+        s_key[x] = kEmpty;
+        s_ed[x] = 0;
+    }
+    __syncthreads();
     for (int32_t base = 0; base < E; base += 256 * kCptUnroll) {
         int kk[kCptUnroll];
         int64_t e[kCptUnroll];
@@ -566,7 +568,6 @@ __global__ __launch_bounds__(256) void k_cpt_pack(CArgs a, const int32_t *__rest
     // weight word; the own community is recorded and removed; the winner's
     // singleton flag moves to bit 7 of the owner byte
     constexpr int SPT = SLOTS / 256;
-    const int32_t used = nv > 0 ? s_toff[nv - 1] + (1 << s_bits[nv - 1]) : 0;
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
         const int32_t x = q * 256 + t;
@@ -588,6 +589,7 @@ __global__ __launch_bounds__(256) void k_cpt_pack(CArgs a, const int32_t *__rest
         atomicMax(&s_best[kv], ok);
     }
     __syncthreads();
+    // the minimum label among the best scores, with its singleton flag in bit 0
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
         const int32_t x = q * 256 + t;
@@ -595,24 +597,15 @@ __global__ __launch_bounds__(256) void k_cpt_pack(CArgs a, const int32_t *__rest
         const int32_t key = s_key[x];
         if (key == kEmpty) continue;
         const int kv = s_own[x] & 0x7f;
-        if (s_ed[x] == s_best[kv]) atomicMin(&s_bestl[kv], key);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < SPT; ++q) {
-        const int32_t x = q * 256 + t;
-        if (x >= used) continue;
-        const int32_t key = s_key[x];
-        if (key == kEmpty) continue;
-        const int kv = s_own[x] & 0x7f;
-        if (key == s_bestl[kv] && s_ed[x] == s_best[kv]) s_bestf[kv] = (s_own[x] >> 7) & 1;
+        if (s_ed[x] == s_best[kv]) atomicMin(&s_bestl[kv], ((uint32_t)key << 1) | ((s_own[x] >> 7) & 1u));
     }
     __syncthreads();
     if (t < nv && live) {
         const bool has = s_best[t] != 0;
         const int64_t bs = (int64_t)(s_best[t] ^ 0x8000000000000000ull);
         const int64_t e_own = (int64_t)s_eown[t];
-        a.c_nxt[v] = cpt_decide(a.singlet, tw, ci, own_hi, di, e_own, has, bs, s_bestl[t], s_bestf[t] != 0);
+        const uint32_t blf = s_bestl[t];
+        a.c_nxt[v] = cpt_decide(a.singlet, tw, ci, own_hi, di, e_own, has, bs, (int32_t)(blf >> 1), (blf & 1u) != 0);
         a.e_self[v] = s_eown[t] + s_loop[t];
     }
 }
@@ -868,8 +861,8 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
         LV_LAUNCHED("k_cpt_small");
     }
     if (cp.pack_blocks > 0) {
-        TimedLaunch tl(t, TG_SWEEP, "k_cpt_pack<2048,1024,64,", bytes(B_T16, B_BLOCK), sfx.c_str());
-        k_cpt_pack<2048, 1024, 64, W><<<(unsigned)cp.pack_blocks, 256, 0, s>>>(
+        TimedLaunch tl(t, TG_SWEEP, "k_cpt_pack<1536,1024,64,", bytes(B_T16, B_BLOCK), sfx.c_str());
+        k_cpt_pack<kPackSlotsCompact, kPackW, 64, W><<<(unsigned)cp.pack_blocks, 256, 0, s>>>(
             a, cp.list + cp.bstart[B_T16], cp.pack_pos, cp.pack_first, cp.bstart[B_BLOCK] - cp.bstart[B_T16]);
         LV_LAUNCHED("k_cpt_pack");
     }
