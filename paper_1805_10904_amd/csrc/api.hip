@@ -505,7 +505,7 @@ int louvain_aggregate(louvain_ctx ctx, louvain_graph g, const int32_t *labels, i
         g2->col.alloc((size_t)g->nnz);
         g2->w64.alloc((size_t)g->nnz);
         g2->delta.alloc((size_t)k);
-        g2->nnz = ct.contract(g->view(), newlab.p, k, g2->row_ptr.p, g2->col.p, g2->w64.p);
+        g2->nnz = ct.contract(g->view(), newlab.p, k, g2->row_ptr.p, g2->col.p, g2->w64.p, true);
         lv::row_sums_i64(k, g2->nnz, g2->row_ptr.p, g2->w64.p, g2->delta.p, s, t);
         g2->tw = g->tw;
         copy_out(renumber_out, newlab.p, g->n, device_ptrs(flags), s);

@@ -2,11 +2,10 @@
 // and "Inducing new graph"), and modularity (eq. 3) of a labelling.
 //
 // Renumbering: presence flags per label -> exclusive scan -> rank.
-// Contraction: every CSR entry (i, j, w) becomes the key (a, b) =
-// (new(i), new(j)) with weight w; an LSD radix sort on the packed key
-// brings equal pairs together in (a, b) order, a segmented reduction sums
-// their weights, and the row pointers come from a binary search per row
-// over the sorted unique keys.
+// Contraction: every CSR entry (i, j, w) becomes (new(i), new(j), w); the
+// entries are grouped by new(i), equal new(j) within a group are summed and
+// the groups sorted by new(j) (segmented contraction below), which gives the
+// contracted CSR with ascending columns.
 #include "contract.hpp"
 #include "prims.hpp"
 
@@ -52,6 +51,10 @@ __global__ void k_compose(int32_t *fin, int64_t n0, const int32_t *__restrict__ 
 void Contractor::reserve(int64_t n, int64_t nnz) {
     if (n > cap_n_) {
         flags_.alloc((size_t)n + 1);
+        seg_off_.alloc((size_t)n + 1);
+        seg_cur_.alloc((size_t)n + 1);
+        seg_start_.alloc((size_t)n + 1);
+        seg_m_.alloc((size_t)n + 1);
         cap_n_ = n;
     }
     if (nnz > cap_nnz_) {
@@ -59,6 +62,8 @@ void Contractor::reserve(int64_t n, int64_t nnz) {
         for (auto &v : val_) v.alloc((size_t)nnz);
         head_.alloc((size_t)nnz);
         uid_.alloc((size_t)nnz + 1);
+        tcol_.alloc((size_t)nnz);
+        tw_.alloc((size_t)nnz);
         cap_nnz_ = nnz;
     }
 }
@@ -118,33 +123,6 @@ void Contractor::compose(int32_t *final_labels, int64_t n0, const int32_t *newla
 }
 
 // ----------------------------------------------------------- contraction --
-
-template <typename W>
-__global__ __launch_bounds__(256) void k_contract_keys(const int64_t *__restrict__ rp, int64_t n, int64_t nnz,
-                                                       const int32_t *__restrict__ col, const W *__restrict__ w,
-                                                       const int32_t *__restrict__ newlab, int bits,
-                                                       uint64_t *keys, int64_t *vals) {
-    __shared__ int64_t srange[2];
-    const int t = threadIdx.x;
-    const int64_t base = (int64_t)blockIdx.x * kEntriesPerBlock;
-    block_row_range(rp, n, nnz, base, kEntriesPerBlock, srange);
-    const int64_t rlo = srange[0], rhi = srange[1];
-#pragma unroll 1
-    for (int k = 0; k < kEntryItems; ++k) {
-        const int64_t e = base + k * 256 + t;
-        if (e >= nnz) break;
-        const int64_t r = row_of_entry(rp, rlo, rhi, e);
-        const int32_t na = newlab[r];
-        if (na < 0) {
-            keys[e] = (bits >= 32) ? ~0ull : ((1ull << (2 * bits)) - 1);   // dropped: sorts last
-            vals[e] = 0;
-            continue;
-        }
-        const uint64_t a = (uint32_t)na, b = (uint32_t)newlab[col[e]];
-        keys[e] = (a << bits) | b;
-        vals[e] = (int64_t)w[e];
-    }
-}
 
 constexpr int kRadixItems = 16;
 constexpr int kRadixTile = 256 * kRadixItems;
@@ -251,25 +229,12 @@ __global__ __launch_bounds__(256) void k_reduce_by_key(const uint64_t *__restric
             v = vals[e];
             if (h) {
                 const uint64_t key = keys[e];
-                col_out[u] = (int32_t)(key & mask);
+                if (col_out) col_out[u] = (int32_t)(key & mask);
                 ukey[u] = key;
             }
         }
         seg_add_wave(w_out, u, v, valid);
     }
-}
-
-// row_ptr[a] = first unique entry whose row is >= a.
-__global__ void k_rowptr(const uint64_t *__restrict__ ukey, int64_t m, int bits, int64_t n_new, int64_t *rp) {
-    const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (a > n_new) return;
-    const uint64_t target = (uint64_t)a << bits;
-    int64_t lo = 0, hi = m;
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (ukey[mid] < target) lo = mid + 1; else hi = mid;
-    }
-    rp[a] = lo;
 }
 
 static int bits_for(int64_t k) {
@@ -278,27 +243,446 @@ static int bits_for(int64_t k) {
     return b;
 }
 
-int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t n_new, int64_t *rp_out,
-                             int32_t *col_out, int64_t *w_out) {
-    const int64_t m = g.nnz;
-    if (m == 0) {
-        fill<int64_t>(rp_out, 0, n_new + 1, s_);
-        return 0;
+// ------------------------------------------------- segmented contraction --
+//
+// 1. every kept vertex's row gets a place in its community's segment of a
+//    grouped entry array (segment sizes: per-community sums of row lengths;
+//    places: one LDS-aggregated cursor add per workgroup and community);
+// 2. entries are copied there with their new column (community of the
+//    neighbour) and weight;
+// 3. workgroups take 1,024 grouped entries each, sum equal (segment, column)
+//    pairs in an LDS hash table and sort the distinct pairs (bitonic, in
+//    LDS): a segment that lies inside one chunk is final and written back in
+//    place; the pairs of segments spread over several chunks are merged by a
+//    radix sort and a segmented sum;
+// 4. row pointers are the scan of the distinct counts, and a last pass packs
+//    the segments into the output CSR.
+
+constexpr int kSegTile = 512;     // vertices per workgroup in the grouping kernels
+constexpr int kSegBits = 11;      // their LDS tables: 2^11 slots for at most 512 keys
+constexpr int kChunk = 1024;      // grouped entries per aggregation workgroup
+constexpr int kChunkBits = 11;    // its LDS hash table: 2^11 slots
+constexpr unsigned long long kNoKey = ~0ull;
+
+__device__ __forceinline__ int lds_slot(int32_t *key, int32_t k) {
+    constexpr uint32_t mask = (1u << kSegBits) - 1;
+    uint32_t h = ((uint32_t)k * 0x9E3779B1u) >> (32 - kSegBits);
+    while (true) {
+        const int32_t cur = ((volatile int32_t *)key)[h];
+        if (cur == k) return (int)h;
+        if (cur == kEmpty) {
+            const int32_t prev = atomicCAS(&key[h], kEmpty, k);
+            if (prev == kEmpty || prev == k) return (int)h;
+        }
+        h = (h + 1) & mask;
     }
-    const int bits = bits_for(n_new + 1);   // leaves the all-ones key free for dropped entries
-    const int64_t eb = (m + kEntriesPerBlock - 1) / kEntriesPerBlock;
-    {
-        TimedLaunch tl(t_, TG_CONTRACT, "k_contract_keys", (double)m * (4 + g.wbytes + 4 + 16) + (double)g.n * 12, g.wbytes == 4 ? "<int>" : "<long>");
-        if (g.wbytes == 4)
-            k_contract_keys<int32_t><<<(unsigned)eb, 256, 0, s_>>>(g.row_ptr, g.n, m, g.col, (const int32_t *)g.w,
-                                                                   newlab, bits, key_[0].p, val_[0].p);
-        else
-            k_contract_keys<int64_t><<<(unsigned)eb, 256, 0, s_>>>(g.row_ptr, g.n, m, g.col, (const int64_t *)g.w,
-                                                                   newlab, bits, key_[0].p, val_[0].p);
-        LV_LAUNCHED("k_contract_keys");
+}
+
+// cnt[a] += row length of every kept vertex of community a.
+__global__ __launch_bounds__(256) void k_seg_count(const int64_t *__restrict__ rp, const int32_t *__restrict__ newlab,
+                                                   int64_t n, unsigned long long *cnt) {
+    constexpr int T = 1 << kSegBits;
+    __shared__ int32_t s_key[T];
+    __shared__ unsigned long long s_sum[T];
+    for (int x = threadIdx.x; x < T; x += 256) {
+        s_key[x] = kEmpty;
+        s_sum[x] = 0;
     }
-    // LSD radix sort of (key, weight) on the 2*bits key bits
-    const int key_bits = 2 * bits;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSegTile;
+#pragma unroll
+    for (int k = 0; k < kSegTile / 256; ++k) {
+        const int64_t v = base + k * 256 + threadIdx.x;
+        if (v >= n) continue;
+        const int32_t a = newlab[v];
+        const int64_t d = rp[v + 1] - rp[v];
+        if (a < 0 || d == 0) continue;
+        atomicAdd(&s_sum[lds_slot(s_key, a)], (unsigned long long)d);
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < T; x += 256)
+        if (s_key[x] != kEmpty) atomicAdd(&cnt[s_key[x]], s_sum[x]);
+}
+
+// start[v] = place of vertex v's row in its community's segment.
+__global__ __launch_bounds__(256) void k_seg_start(const int64_t *__restrict__ rp, const int32_t *__restrict__ newlab,
+                                                   int64_t n, const int64_t *__restrict__ off,
+                                                   unsigned long long *cursor, int64_t *start) {
+    constexpr int T = 1 << kSegBits;
+    constexpr int K = kSegTile / 256;
+    __shared__ int32_t s_key[T];
+    __shared__ unsigned long long s_sum[T];
+    for (int x = threadIdx.x; x < T; x += 256) {
+        s_key[x] = kEmpty;
+        s_sum[x] = 0;
+    }
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kSegTile;
+    int slot[K];
+    unsigned long long local[K];
+    int32_t lab[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        slot[k] = -1;
+        const int64_t v = base + k * 256 + threadIdx.x;
+        if (v >= n) continue;
+        lab[k] = newlab[v];
+        const int64_t d = rp[v + 1] - rp[v];
+        if (lab[k] < 0 || d == 0) continue;
+        slot[k] = lds_slot(s_key, lab[k]);
+        local[k] = atomicAdd(&s_sum[slot[k]], (unsigned long long)d);
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < T; x += 256)   // the workgroup's share of each community's segment
+        if (s_key[x] != kEmpty) s_sum[x] = atomicAdd(&cursor[s_key[x]], s_sum[x]);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        if (slot[k] < 0) continue;
+        const int64_t v = base + k * 256 + threadIdx.x;
+        start[v] = off[lab[k]] + (int64_t)(s_sum[slot[k]] + local[k]);
+    }
+}
+
+template <typename W>
+__global__ __launch_bounds__(256) void k_seg_scatter(const int64_t *__restrict__ rp, int64_t n, int64_t nnz,
+                                                     const int32_t *__restrict__ col, const W *__restrict__ w,
+                                                     const int32_t *__restrict__ newlab,
+                                                     const int64_t *__restrict__ start, int32_t *tcol, int64_t *tw) {
+    __shared__ int64_t srange[2];
+    const int64_t base = (int64_t)blockIdx.x * kEntriesPerBlock;
+    block_row_range(rp, n, nnz, base, kEntriesPerBlock, srange);
+    const int64_t rlo = srange[0], rhi = srange[1];
+#pragma unroll 1
+    for (int k = 0; k < kEntryItems; ++k) {
+        const int64_t e = base + k * 256 + threadIdx.x;
+        if (e >= nnz) break;
+        const int64_t r = row_of_entry(rp, rlo, rhi, e);
+        const int32_t a = newlab[r];
+        if (a < 0) continue;
+        const int64_t dst = start[r] + (e - rp[r]);
+        tcol[dst] = newlab[col[e]];
+        tw[dst] = (int64_t)w[e];
+    }
+}
+
+// Inclusive max-scan of s[0, kChunk) in place (256 threads, 4 items each).
+__device__ __forceinline__ void block_max_scan_chunk(int32_t *s, int32_t *s_wave) {
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    int32_t v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[i] = s[4 * t + i];
+#pragma unroll
+    for (int i = 1; i < 4; ++i) v[i] = v[i] > v[i - 1] ? v[i] : v[i - 1];
+    int32_t x = v[3];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int32_t y = __shfl_up(x, off);
+        if (lane >= off && y > x) x = y;
+    }
+    if (lane == 63) s_wave[wid] = x;
+    __syncthreads();
+    int32_t before = __shfl_up(x, 1);
+    if (lane == 0) before = INT32_MIN;
+    for (int w2 = 0; w2 < wid; ++w2) before = s_wave[w2] > before ? s_wave[w2] : before;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) s[4 * t + i] = v[i] > before ? v[i] : before;
+    __syncthreads();
+}
+
+// Shared first half of the chunk kernels: the chunk's first and last
+// segment (slo, shi), the local segment of every entry (s_mark) and the sum
+// of every (local segment, column) pair in the LDS hash table s_hk / s_hv.
+__device__ __forceinline__ void chunk_aggregate(const int64_t *__restrict__ off, int64_t k, int64_t cb, int len,
+                                                const int32_t *__restrict__ tcol, const int64_t *__restrict__ tw,
+                                                unsigned long long *s_hk, long long *s_hv, int32_t *s_mark,
+                                                int32_t *s_wave, int64_t *s_range) {
+    constexpr int T = 1 << kChunkBits;
+    constexpr uint32_t mask = T - 1;
+    const int t = threadIdx.x;
+    for (int x = t; x < T; x += 256) {
+        s_hk[x] = kNoKey;
+        s_hv[x] = 0;
+    }
+    for (int x = t; x < kChunk; x += 256) s_mark[x] = -1;
+    if (t < 64) {   // segments of the chunk's first and last entry (64-way search)
+        const int64_t a0 = wave_find_le(off, k, cb);
+        const int64_t a1 = wave_find_le(off, k, cb + len - 1);
+        if (t == 0) {
+            s_range[0] = a0;
+            s_range[1] = a1;
+        }
+    }
+    __syncthreads();
+    const int64_t slo = s_range[0], shi = s_range[1];
+    // segment of every entry: markers at segment starts, then a max-scan
+    for (int64_t sg = slo + 1 + t; sg <= shi; sg += 256) atomicMax(&s_mark[off[sg] - cb], (int32_t)(sg - slo));
+    if (t == 0) s_mark[0] = 0;   // markers never land on position 0
+    __syncthreads();
+    block_max_scan_chunk(s_mark, s_wave);
+    for (int x = t; x < len; x += 256) {
+        const unsigned long long key = ((unsigned long long)(uint32_t)s_mark[x] << 32) | (uint32_t)tcol[cb + x];
+        const long long val = (long long)tw[cb + x];
+        uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - kChunkBits));
+        while (true) {
+            const unsigned long long cur = ((volatile unsigned long long *)s_hk)[h];
+            if (cur == key) break;
+            if (cur == kNoKey) {
+                const unsigned long long prev = atomicCAS(&s_hk[h], kNoKey, key);
+                if (prev == kNoKey || prev == key) break;
+            }
+            h = (h + 1) & mask;
+        }
+        atomicAdd((unsigned long long *)&s_hv[h], (unsigned long long)val);
+    }
+    __syncthreads();
+}
+
+// Levels inside a run: the order of a row's columns does not matter to the
+// method (sweeps and contraction depend on each row's multiset of columns
+// and weights only), so distinct pairs are placed in table order, each
+// segment's through its own LDS counter, without sorting.
+__global__ __launch_bounds__(256) void k_seg_chunk_any(const int64_t *__restrict__ off, int64_t k, int64_t m_raw,
+                                                       int32_t *tcol, int64_t *tw, int64_t *mcount, uint64_t *pkey,
+                                                       int64_t *pval, unsigned long long *pcount, int bits) {
+    constexpr int T = 1 << kChunkBits;
+    __shared__ unsigned long long s_hk[T];
+    __shared__ long long s_hv[T];
+    __shared__ int32_t s_mark[kChunk];
+    __shared__ int32_t s_cnt[kChunk];   // pairs per segment, at the segment's first position
+    __shared__ int32_t s_cur[kChunk];
+    __shared__ int32_t s_wave[4];
+    __shared__ int64_t s_range[2];
+    __shared__ unsigned long long s_pbase;
+    const int t = threadIdx.x;
+    const int64_t cb = (int64_t)blockIdx.x * kChunk;
+    const int64_t ce = cb + kChunk < m_raw ? cb + kChunk : m_raw;
+    const int len = (int)(ce - cb);
+    for (int x = t; x < kChunk; x += 256) {
+        s_cnt[x] = 0;
+        s_cur[x] = 0;
+    }
+    chunk_aggregate(off, k, cb, len, tcol, tw, s_hk, s_hv, s_mark, s_wave, s_range);
+    const int64_t slo = s_range[0], shi = s_range[1];
+    const bool first_spans = off[slo] < cb;
+    const bool last_spans = off[shi + 1] > ce;
+    const uint32_t last_local = (uint32_t)(shi - slo);
+    for (int x = t; x < T; x += 256) {
+        const unsigned long long key = s_hk[x];
+        if (key == kNoKey) continue;
+        const uint32_t ls = (uint32_t)(key >> 32);
+        const int p = ls == 0 ? 0 : (int)(off[slo + ls] - cb);
+        atomicAdd(&s_cnt[p], 1);
+    }
+    __syncthreads();
+    const int p_last = last_local == 0 ? 0 : (int)(off[shi] - cb);
+    if (t == 0) {
+        int np = 0;
+        if (last_local == 0) {
+            if (first_spans || last_spans) np = s_cnt[0];
+        } else {
+            if (first_spans) np += s_cnt[0];
+            if (last_spans) np += s_cnt[p_last];
+        }
+        s_pbase = np ? atomicAdd(pcount, (unsigned long long)np) : 0;
+    }
+    __syncthreads();
+    const unsigned long long pbase = s_pbase;
+    const int first_n = (first_spans && last_local != 0) ? s_cnt[0] : 0;
+    for (int x = t; x < T; x += 256) {
+        const unsigned long long key = s_hk[x];
+        if (key == kNoKey) continue;
+        const uint32_t ls = (uint32_t)(key >> 32);
+        const int64_t sg = slo + ls;
+        const int p = ls == 0 ? 0 : (int)(off[sg] - cb);
+        const int pos = atomicAdd(&s_cur[p], 1);
+        const int32_t c = (int32_t)(uint32_t)key;
+        const long long val = s_hv[x];
+        if (ls == 0 && first_spans) {
+            pkey[pbase + pos] = ((uint64_t)sg << bits) | (uint32_t)c;
+            pval[pbase + pos] = val;
+        } else if (ls == last_local && last_spans) {
+            pkey[pbase + first_n + pos] = ((uint64_t)sg << bits) | (uint32_t)c;
+            pval[pbase + first_n + pos] = val;
+        } else {
+            tcol[off[sg] + pos] = c;
+            tw[off[sg] + pos] = val;
+        }
+    }
+    // counts of the segments that end here
+    for (int p = t; p < len; p += 256) {
+        const int32_t n_p = s_cnt[p];
+        if (n_p == 0) continue;
+        const uint32_t ls = (uint32_t)s_mark[p];
+        if ((ls == 0 && first_spans) || (ls == last_local && last_spans)) continue;
+        mcount[slo + ls] = n_p;
+    }
+}
+
+// The exported contraction: as k_seg_chunk_any, but the distinct pairs of
+// a chunk are sorted (bitonic, in LDS) so that every row's columns ascend.
+__global__ __launch_bounds__(256) void k_seg_chunk(const int64_t *__restrict__ off, int64_t k, int64_t m_raw,
+                                                   int32_t *tcol, int64_t *tw, int64_t *mcount, uint64_t *pkey,
+                                                   int64_t *pval, unsigned long long *pcount, int bits) {
+    constexpr int T = 1 << kChunkBits;
+    __shared__ unsigned long long s_hk[T];
+    __shared__ long long s_hv[T];
+    __shared__ unsigned long long s_sk[kChunk];
+    __shared__ long long s_sv[kChunk];
+    __shared__ int32_t s_mark[kChunk];
+    __shared__ int32_t s_wave[4];
+    __shared__ int s_nd;
+    __shared__ int64_t s_range[2];
+    __shared__ unsigned long long s_pbase;
+    const int t = threadIdx.x;
+    const int64_t cb = (int64_t)blockIdx.x * kChunk;
+    const int64_t ce = cb + kChunk < m_raw ? cb + kChunk : m_raw;
+    const int len = (int)(ce - cb);
+    if (t == 0) {
+        s_nd = 0;
+        s_pbase = 0;
+    }
+    chunk_aggregate(off, k, cb, len, tcol, tw, s_hk, s_hv, s_mark, s_wave, s_range);
+    const int64_t slo = s_range[0], shi = s_range[1];
+    {   // compaction of the occupied slots: one LDS atomic per wavefront and round
+        const int lane = t & 63;
+        const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+        for (int x0 = 0; x0 < T; x0 += 256) {
+            const int x = x0 + t;
+            const bool occ = s_hk[x] != kNoKey;
+            const unsigned long long msk = __ballot(occ);
+            int base = 0;
+            if (lane == 0 && msk) base = atomicAdd(&s_nd, (int)__popcll(msk));
+            base = __shfl(base, 0);
+            if (occ) {
+                const int i = base + (int)__popcll(msk & lt);
+                s_sk[i] = s_hk[x];
+                s_sv[i] = s_hv[x];
+            }
+        }
+    }
+    __syncthreads();
+    const int nd = s_nd;
+    int P = 1;
+    while (P < nd) P <<= 1;
+    for (int x = nd + t; x < P; x += 256) s_sk[x] = kNoKey;
+    __syncthreads();
+    // bitonic sort of (key, value) pairs, keys ascending
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int q = t; q < P / 2; q += 256) {
+                const int i = 2 * q - (q & (stride - 1));
+                const int j = i + stride;
+                const bool up = (i & size) == 0;
+                const unsigned long long a = s_sk[i], b = s_sk[j];
+                if ((a > b) == up) {
+                    s_sk[i] = b;
+                    s_sk[j] = a;
+                    const long long va = s_sv[i];
+                    s_sv[i] = s_sv[j];
+                    s_sv[j] = va;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // the first and the last segment may continue in other chunks
+    const bool first_spans = off[slo] < cb;
+    const bool last_spans = off[shi + 1] > ce;
+    const uint32_t last_local = (uint32_t)(shi - slo);
+    int n_first = 0, n_last = 0;
+    if (first_spans || last_spans) {
+        // entries of the first segment form a prefix, those of the last a suffix
+        int lo = 0, hi = nd;   // first index with local segment > 0
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if ((s_sk[mid] >> 32) > 0) hi = mid; else lo = mid + 1;
+        }
+        n_first = lo;
+        lo = 0;
+        hi = nd;                // first index of the last segment
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if ((uint32_t)(s_sk[mid] >> 32) >= last_local) hi = mid; else lo = mid + 1;
+        }
+        n_last = nd - lo;
+        if (t == 0) {
+            int np = 0;
+            if (first_spans) np += n_first;
+            if (last_spans && !(first_spans && last_local == 0)) np += n_last;
+            s_pbase = np ? atomicAdd(pcount, (unsigned long long)np) : 0;
+        }
+    }
+    __syncthreads();
+    const unsigned long long pbase = s_pbase;
+    for (int i = t; i < nd; i += 256) {
+        const unsigned long long key = s_sk[i];
+        const uint32_t sl = (uint32_t)(key >> 32);
+        const int64_t sg = slo + sl;
+        const int32_t c = (int32_t)(uint32_t)key;
+        const long long val = s_sv[i];
+        const bool spans = (sl == 0 && first_spans) || (sl == last_local && last_spans);
+        if (spans) {
+            const int64_t r = (sl == 0 && first_spans) ? i : (first_spans ? n_first : 0) + (i - (nd - n_last));
+            pkey[pbase + r] = ((uint64_t)sg << bits) | (uint32_t)c;
+            pval[pbase + r] = val;
+            continue;
+        }
+        // first index of this segment in the sorted pairs
+        int lo = 0, hi = i;
+        const unsigned long long lb = (unsigned long long)sl << 32;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (s_sk[mid] < lb) lo = mid + 1; else hi = mid;
+        }
+        const int64_t pos = i - lo;
+        tcol[off[sg] + pos] = c;
+        tw[off[sg] + pos] = val;
+        if (i + 1 == nd || (uint32_t)(s_sk[i + 1] >> 32) != sl) mcount[sg] = pos + 1;
+    }
+}
+
+// Merged pairs of segments spread over several chunks: write them to their
+// segments in key order and record the counts.
+__global__ void k_seg_merge_write(const uint64_t *__restrict__ ukey, const int64_t *__restrict__ usum, int64_t u_n,
+                                  int bits, const int64_t *__restrict__ off, int32_t *tcol, int64_t *tw,
+                                  int64_t *mcount) {
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u >= u_n) return;
+    const uint64_t key = ukey[u];
+    const int64_t sg = (int64_t)(key >> bits);
+    const uint64_t lb = (uint64_t)sg << bits;
+    int64_t lo = 0, hi = u;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (ukey[mid] < lb) lo = mid + 1; else hi = mid;
+    }
+    const int64_t pos = u - lo;
+    tcol[off[sg] + pos] = (int32_t)(key & ((1ull << bits) - 1));
+    tw[off[sg] + pos] = usum[u];
+    if (u + 1 == u_n || (int64_t)(ukey[u + 1] >> bits) != sg) mcount[sg] = pos + 1;
+}
+
+// Output CSR: entry u of row a comes from its segment's u - rp[a]-th pair.
+__global__ __launch_bounds__(256) void k_seg_pack(const int64_t *__restrict__ rp, int64_t n_new, int64_t m_new,
+                                                  const int64_t *__restrict__ off, const int32_t *__restrict__ tcol,
+                                                  const int64_t *__restrict__ tw, int32_t *col_out, int64_t *w_out) {
+    __shared__ int64_t srange[2];
+    const int64_t base = (int64_t)blockIdx.x * kEntriesPerBlock;
+    block_row_range(rp, n_new, m_new, base, kEntriesPerBlock, srange);
+    const int64_t rlo = srange[0], rhi = srange[1];
+#pragma unroll 1
+    for (int k = 0; k < kEntryItems; ++k) {
+        const int64_t u = base + k * 256 + threadIdx.x;
+        if (u >= m_new) break;
+        const int64_t a = row_of_entry(rp, rlo, rhi, u);
+        const int64_t src = off[a] + (u - rp[a]);
+        col_out[u] = tcol[src];
+        w_out[u] = tw[src];
+    }
+}
+
+int64_t Contractor::sort_sum(int64_t m, int key_bits, const uint64_t **ukeys, const int64_t **usums) {
     const int64_t rb = (m + kRadixTile - 1) / kRadixTile;
     TempBuf hist((size_t)256 * rb * sizeof(int32_t), s_);
     TempBuf offs((size_t)256 * rb * sizeof(int64_t), s_);
@@ -322,31 +706,113 @@ int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t 
     const uint64_t *keys = key_[src].p;
     const int64_t *vals = val_[src].p;
     uint64_t *ukey = key_[1 - src].p;
+    int64_t *usum = val_[1 - src].p;
     {
         TimedLaunch tl(t_, TG_CONTRACT, "k_heads", (double)m * 12);
         k_heads<<<grid_for(m, 256), 256, 0, s_>>>(keys, m, head_.p);
         LV_LAUNCHED("k_heads");
     }
     scan_exclusive<int32_t, int64_t>(head_.p, uid_.p, m, uid_.p + m, s_, t_);
-    int64_t m_new = 0;
-    uint64_t last_key = 0;
-    LV_HIP(hipMemcpyAsync(&m_new, uid_.p + m, sizeof m_new, hipMemcpyDeviceToHost, s_));
-    LV_HIP(hipMemcpyAsync(&last_key, keys + (m - 1), sizeof last_key, hipMemcpyDeviceToHost, s_));
+    int64_t u_n = 0;
+    LV_HIP(hipMemcpyAsync(&u_n, uid_.p + m, sizeof u_n, hipMemcpyDeviceToHost, s_));
     LV_HIP(hipStreamSynchronize(s_));
-    const uint64_t dropped_key = (bits >= 32) ? ~0ull : ((1ull << (2 * bits)) - 1);
-    const int64_t m_keep = last_key == dropped_key ? m_new - 1 : m_new;
-    fill<int64_t>(w_out, 0, m_new, s_);   // the dropped segment (if any) is the last one
+    fill<int64_t>(usum, 0, u_n, s_);
     {
-        TimedLaunch tl(t_, TG_CONTRACT, "k_reduce_by_key", (double)m * 28 + (double)m_new * 20);
-        k_reduce_by_key<<<(unsigned)eb, 256, 0, s_>>>(keys, vals, head_.p, uid_.p, m, bits, col_out, w_out, ukey);
+        const int64_t eb = (m + kEntriesPerBlock - 1) / kEntriesPerBlock;
+        TimedLaunch tl(t_, TG_CONTRACT, "k_reduce_by_key", (double)m * 28 + (double)u_n * 16);
+        k_reduce_by_key<<<(unsigned)eb, 256, 0, s_>>>(keys, vals, head_.p, uid_.p, m, 64, nullptr, usum, ukey);
         LV_LAUNCHED("k_reduce_by_key");
     }
-    {
-        TimedLaunch tl(t_, TG_CONTRACT, "k_rowptr", (double)(n_new + 1) * 8);
-        k_rowptr<<<grid_for(n_new + 1, 256), 256, 0, s_>>>(ukey, m_keep, bits, n_new, rp_out);
-        LV_LAUNCHED("k_rowptr");
+    *ukeys = ukey;
+    *usums = usum;
+    return u_n;
+}
+
+int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t n_new, int64_t *rp_out,
+                             int32_t *col_out, int64_t *w_out, bool sorted) {
+    if (n_new == 0) {
+        fill<int64_t>(rp_out, 0, 1, s_);
+        return 0;
     }
-    return m_keep;
+    if (g.nnz == 0) {
+        fill<int64_t>(rp_out, 0, n_new + 1, s_);
+        return 0;
+    }
+    const int64_t n = g.n, k = n_new;
+    int64_t *cnt = seg_off_.p;            // k + 1: raw counts, then (scanned) segment offsets
+    int64_t *off = seg_off_.p;
+    unsigned long long *cursor = (unsigned long long *)seg_cur_.p;
+    fill<int64_t>(cnt, 0, k + 1, s_);
+    fill<int64_t>(seg_cur_.p, 0, k, s_);
+    const unsigned vb = (unsigned)((n + kSegTile - 1) / kSegTile);
+    {
+        TimedLaunch tl(t_, TG_CONTRACT, "k_seg_count", (double)n * 20);
+        k_seg_count<<<vb, 256, 0, s_>>>(g.row_ptr, newlab, n, (unsigned long long *)cnt);
+        LV_LAUNCHED("k_seg_count");
+    }
+    scan_exclusive<int64_t, int64_t>(cnt, off, k, off + k, s_, t_);
+    {
+        TimedLaunch tl(t_, TG_CONTRACT, "k_seg_start", (double)n * 28);
+        k_seg_start<<<vb, 256, 0, s_>>>(g.row_ptr, newlab, n, off, cursor, seg_start_.p);
+        LV_LAUNCHED("k_seg_start");
+    }
+    int64_t m_raw = 0;
+    LV_HIP(hipMemcpyAsync(&m_raw, off + k, sizeof m_raw, hipMemcpyDeviceToHost, s_));
+    {
+        const int64_t eb = (g.nnz + kEntriesPerBlock - 1) / kEntriesPerBlock;
+        TimedLaunch tl(t_, TG_CONTRACT, "k_seg_scatter", (double)g.nnz * (4 + g.wbytes + 4 + 12) + (double)n * 12,
+                       g.wbytes == 4 ? "<int>" : "<long>");
+        if (g.wbytes == 4)
+            k_seg_scatter<int32_t><<<(unsigned)eb, 256, 0, s_>>>(g.row_ptr, n, g.nnz, g.col, (const int32_t *)g.w,
+                                                                 newlab, seg_start_.p, tcol_.p, tw_.p);
+        else
+            k_seg_scatter<int64_t><<<(unsigned)eb, 256, 0, s_>>>(g.row_ptr, n, g.nnz, g.col, (const int64_t *)g.w,
+                                                                 newlab, seg_start_.p, tcol_.p, tw_.p);
+        LV_LAUNCHED("k_seg_scatter");
+    }
+    LV_HIP(hipStreamSynchronize(s_));
+    int64_t *mcount = seg_m_.p;           // k + 1
+    fill<int64_t>(mcount, 0, k + 1, s_);
+    if (m_raw == 0) {
+        fill<int64_t>(rp_out, 0, k + 1, s_);
+        return 0;
+    }
+    const int bits = bits_for(k + 1);
+    TempBuf pc(sizeof(unsigned long long), s_);
+    fill<uint64_t>(pc.as<uint64_t>(), 0, 1, s_);
+    {
+        const int64_t cb = (m_raw + kChunk - 1) / kChunk;
+        TimedLaunch tl(t_, TG_CONTRACT, sorted ? "k_seg_chunk" : "k_seg_chunk_any", (double)m_raw * 24);
+        if (sorted)
+            k_seg_chunk<<<(unsigned)cb, 256, 0, s_>>>(off, k, m_raw, tcol_.p, tw_.p, mcount, key_[0].p, val_[0].p,
+                                                      pc.as<unsigned long long>(), bits);
+        else
+            k_seg_chunk_any<<<(unsigned)cb, 256, 0, s_>>>(off, k, m_raw, tcol_.p, tw_.p, mcount, key_[0].p,
+                                                          val_[0].p, pc.as<unsigned long long>(), bits);
+        LV_LAUNCHED("k_seg_chunk");
+    }
+    uint64_t np = 0;
+    LV_HIP(hipMemcpyAsync(&np, pc.p, sizeof np, hipMemcpyDeviceToHost, s_));
+    LV_HIP(hipStreamSynchronize(s_));
+    if (np > 0) {
+        const uint64_t *ukey;
+        const int64_t *usum;
+        const int64_t u_n = sort_sum((int64_t)np, 2 * bits, &ukey, &usum);
+        TimedLaunch tl(t_, TG_CONTRACT, "k_seg_merge_write", (double)u_n * 28);
+        k_seg_merge_write<<<grid_for(u_n, 256), 256, 0, s_>>>(ukey, usum, u_n, bits, off, tcol_.p, tw_.p, mcount);
+        LV_LAUNCHED("k_seg_merge_write");
+    }
+    scan_exclusive<int64_t, int64_t>(mcount, rp_out, k, rp_out + k, s_, t_);
+    int64_t m_new = 0;
+    LV_HIP(hipMemcpyAsync(&m_new, rp_out + k, sizeof m_new, hipMemcpyDeviceToHost, s_));
+    LV_HIP(hipStreamSynchronize(s_));
+    if (m_new > 0) {
+        const int64_t eb = (m_new + kEntriesPerBlock - 1) / kEntriesPerBlock;
+        TimedLaunch tl(t_, TG_CONTRACT, "k_seg_pack", (double)m_new * 32);
+        k_seg_pack<<<(unsigned)eb, 256, 0, s_>>>(rp_out, k, m_new, off, tcol_.p, tw_.p, col_out, w_out);
+        LV_LAUNCHED("k_seg_pack");
+    }
+    return m_new;
 }
 
 // ----------------------------------------------------------- modularity --

@@ -27,20 +27,34 @@ class Contractor {
     void compose(int32_t *final_labels, int64_t n0, const int32_t *newlab);
     // Contract g so that vertex a of the result is {i : newlab[i] == a};
     // writes row_ptr (n_new + 1), col and int64 weights (capacity g.nnz) and
-    // returns the number of entries (synchronises the stream).
-    // Entries of rows with newlab == -1 are dropped.
+    // returns the number of entries (synchronises the stream).  Entries of
+    // rows with newlab == -1 are dropped.  sorted: columns ascend in every
+    // row (the canonical form); otherwise their order within a row is
+    // unspecified, which the method does not depend on.
     int64_t contract(const GraphView &g, const int32_t *newlab, int64_t n_new, int64_t *rp_out,
-                     int32_t *col_out, int64_t *w_out);
+                     int32_t *col_out, int64_t *w_out, bool sorted = false);
 
   private:
+    // Sort (key_[0], val_[0])[0, m) by the low key_bits of the keys and sum
+    // the values of equal keys; *ukeys / *usums receive the unique keys in
+    // ascending order and their sums (contractor buffers).  Returns their
+    // number (synchronises the stream).
+    int64_t sort_sum(int64_t m, int key_bits, const uint64_t **ukeys, const int64_t **usums);
+
     hipStream_t s_;
     Timer *t_;
     int64_t cap_n_ = -1, cap_nnz_ = -1;
     DevBuf<int32_t> flags_;     // n: label present / renumber map
-    DevBuf<uint64_t> key_[2];   // nnz: (row', col') sort keys
-    DevBuf<int64_t> val_[2];    // nnz: weights
+    DevBuf<uint64_t> key_[2];   // nnz: sort keys of merged pairs
+    DevBuf<int64_t> val_[2];    // nnz: their weights
     DevBuf<int32_t> head_;      // nnz: segment heads
     DevBuf<int64_t> uid_;       // nnz: unique index of each sorted entry
+    DevBuf<int64_t> seg_off_;   // n + 1: entries per community, then segment offsets
+    DevBuf<int64_t> seg_cur_;   // n: per-community placement cursors
+    DevBuf<int64_t> seg_start_; // n: place of every vertex's row in its segment
+    DevBuf<int64_t> seg_m_;     // n + 1: distinct columns per community
+    DevBuf<int32_t> tcol_;      // nnz: grouped entries: new column
+    DevBuf<int64_t> tw_;        // nnz: grouped entries: weight
 };
 
 // Q_int = TW*I - sum_C deg_C^2 of labels (device int32[n] in [0, n)).

@@ -96,7 +96,11 @@ size_t Server::workspace_bytes(int64_t n, int64_t nnz) {
 }
 
 Server::Server(int device, size_t budget) : device_(device), budget_(budget) {
-    th_ = std::thread([this] { loop(); });
+    for (int k = 0; k < 2; ++k) workers_.emplace_back(new Worker());
+    for (auto &w : workers_) {
+        Worker *wp = w.get();
+        w->th = std::thread([this, wp] { loop(wp); });
+    }
 }
 
 Server::~Server() {
@@ -105,7 +109,8 @@ Server::~Server() {
         stop_ = true;
     }
     cv_work_.notify_all();
-    if (th_.joinable()) th_.join();
+    for (auto &w : workers_)
+        if (w->th.joinable()) w->th.join();
 }
 
 uint64_t Server::submit(std::unique_ptr<ServeRequest> r) {
@@ -116,7 +121,7 @@ uint64_t Server::submit(std::unique_ptr<ServeRequest> r) {
         std::lock_guard<std::mutex> lk(mu_);
         t = next_++;
         r->ticket = t;
-        incoming_.push_back(r.get());
+        workers_[r->nnz <= kSmallEntries ? 0 : 1]->incoming.push_back(r.get());
         all_[t] = std::move(r);
     }
     cv_work_.notify_all();
@@ -157,16 +162,18 @@ size_t Server::budget() {
 
 void Server::finish(ServeRequest *r) {
     release_device(r);
-    in_use_ -= std::min(in_use_, r->bytes);
     r->t_done = now_us();
     {
         std::lock_guard<std::mutex> lk(mu_);
+        if (r->admitted) in_use_ -= std::min(in_use_, r->bytes);
+        r->admitted = false;
         r->done = true;
     }
     cv_done_.notify_all();
+    cv_work_.notify_all();   // memory freed: the other worker may admit
 }
 
-void Server::loop() {
+void Server::loop(Worker *w) {
     Pool pool;
     current_pool() = &pool;
     hipStream_t s = nullptr;
@@ -190,33 +197,46 @@ void Server::loop() {
         return false;
     };
     for (;;) {
-        size_t budget;
         {
             std::unique_lock<std::mutex> lk(mu_);
-            cv_work_.wait(lk, [&] { return stop_ || !incoming_.empty() || (!queue.empty() && !busy()) || busy(); });
+            // the head of the queue can be admitted (or rejected) now
+            auto ready = [&] {
+                if (queue.empty()) return false;
+                const ServeRequest *r = queue.front();
+                return r->bytes > budget_ || in_use_ + r->bytes <= budget_;
+            };
+            cv_work_.wait(lk, [&] { return stop_ || !w->incoming.empty() || busy() || ready(); });
             if (stop_) break;
-            while (!incoming_.empty()) {
-                queue.push_back(incoming_.front());
-                incoming_.pop_front();
+            while (!w->incoming.empty()) {
+                queue.push_back(w->incoming.front());
+                w->incoming.pop_front();
             }
-            budget = budget_;
         }
         // admission in arrival order while the footprint fits the budget
         while (!queue.empty()) {
             ServeRequest *r = queue.front();
+            bool too_big = false, fits = false;
+            {
+                std::lock_guard<std::mutex> lk(mu_);
+                too_big = r->bytes > budget_;
+                fits = !too_big && in_use_ + r->bytes <= budget_;
+                if (fits && ok) {
+                    in_use_ += r->bytes;
+                    r->admitted = true;
+                }
+            }
             if (!ok) {
                 queue.pop_front();
                 fail(r, LOUVAIN_EDEVICE, "the request loop could not set up its device stream");
                 continue;
             }
-            if (r->bytes > budget) {
+            if (too_big) {
                 queue.pop_front();
                 fail(r, LOUVAIN_ENOMEM, "the graph needs more device memory than the serving budget");
                 continue;
             }
-            if (in_use_ + r->bytes > budget) break;
+            if (!fits) break;
             queue.pop_front();
-            in_use_ += r->bytes;
             r->t_admit = now_us();
             try {
                 ingest(r, s);

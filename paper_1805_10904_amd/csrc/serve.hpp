@@ -1,9 +1,13 @@
-// Request loop of the served form: graphs are submitted from any thread, a
-// worker thread admits them in arrival order while their estimated device
-// footprint fits the memory budget, and every admitted graph joins the
-// running batch at the next level boundary (continuous batching: newcomers
-// at level 0 are swept in the same launches as members at deeper levels).
-// Results are identical to louvain_run on each graph alone.
+// Request loop of the served form: graphs are submitted from any thread and
+// routed by size to one of two workers (each a thread with its own stream,
+// device pool and batch engines, so small graphs are not held back by the
+// level steps of large ones and the two streams overlap on the device).  A
+// worker admits its requests in arrival order while their estimated device
+// footprints fit the shared memory budget, and every admitted graph joins
+// the worker's running batch at the next level boundary (continuous
+// batching: newcomers at level 0 are swept in the same launches as members
+// at deeper levels).  Results are identical to louvain_run on each graph
+// alone.
 #pragma once
 
 #include <condition_variable>
@@ -31,7 +35,8 @@ struct ServeRequest {
     louvain_params prm{};
     int32_t *labels_out = nullptr;
     // result
-    size_t bytes = 0;            // admitted footprint estimate
+    size_t bytes = 0;            // footprint estimate
+    bool admitted = false;       // bytes are counted against the budget
     bool done = false;
     int status = LOUVAIN_OK;
     std::string err;
@@ -63,20 +68,26 @@ class Server {
     static size_t workspace_bytes(int64_t n, int64_t nnz);
     static double now_us();
 
+    // Requests with at most this many entries go to the small-graph worker.
+    static constexpr int64_t kSmallEntries = (int64_t)1 << 20;
+
   private:
-    void loop();
+    struct Worker {
+        std::thread th;
+        std::deque<ServeRequest *> incoming;
+    };
+    void loop(Worker *w);
     void finish(ServeRequest *r);
 
     int device_;
     std::mutex mu_;
     std::condition_variable cv_work_, cv_done_;
-    std::deque<ServeRequest *> incoming_;
     std::unordered_map<uint64_t, std::unique_ptr<ServeRequest>> all_;
     uint64_t next_ = 1;
     bool stop_ = false;
     size_t budget_;
-    size_t in_use_ = 0;   // worker thread only
-    std::thread th_;
+    size_t in_use_ = 0;   // footprints of admitted, unfinished requests
+    std::vector<std::unique_ptr<Worker>> workers_;
 };
 
 }  // namespace lv

@@ -1050,7 +1050,10 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     for (int b = 0; b < NBUCKET; ++b) bucket_nnz_[b] = (int64_t)hn[b];
     // line positions of the packed vertices (buckets B_T16 to B_MID, contiguous in the list)
     pack_count_ = bstart_[B_BLOCK] - bstart_[B_T16];
-    if (pack_count_ > 0 && g.tw <= kTwFastMax) {
+    if (compact_) {
+        glist_.reserve((size_t)(pack_count_ > 0 ? pack_count_ : 1));
+        compact_classes(g.row_ptr, list_.p + bstart_[B_T16], pack_count_, glist_.p, cstart_, cnnz_, s_, t_);
+    } else if (pack_count_ > 0 && g.tw <= kTwFastMax) {
         TempBuf cost((size_t)pack_count_ * sizeof(int32_t), s_);
         k_pack_cost<<<grid_for(pack_count_, 256), 256, 0, s_>>>(g.row_ptr, list_.p + bstart_[B_T16], pack_count_,
                                                                cost.as<int32_t>());
@@ -1233,6 +1236,9 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
         cp.pack_pos = pack_pos_.p;
         cp.pack_first = pack_first_.p;
         cp.pack_blocks = pack_blocks_;
+        cp.glist = glist_.p;
+        for (int c = 0; c <= kGroupClasses; ++c) cp.cstart[c] = cstart_[c];
+        for (int c = 0; c < kGroupClasses; ++c) cp.cnnz[c] = cnnz_[c];
         cp.hubs = hubs_;
         cp.hub_chunks = hub_chunks_;
         cp.hub_scans = hub_scans_;

@@ -610,6 +610,363 @@ __global__ __launch_bounds__(256) void k_cpt_pack(CArgs a, const int32_t *__rest
     }
 }
 
+// ------------------------------------------------------ lane groups by size --
+
+// Insert or add for a table of 2^bits slots with keys and e | high words.
+__device__ __forceinline__ void grp_insert(int32_t *key, unsigned long long *ed, int bits, int32_t k, uint32_t w,
+                                           uint32_t hi) {
+    const uint32_t mask = (1u << bits) - 1;
+    uint32_t h = ((uint32_t)k * 0x9E3779B1u) >> (32 - bits);
+    while (true) {
+        const int32_t cur = ((volatile int32_t *)key)[h];
+        if (cur == k) {
+            atomicAdd(&ed[h], (unsigned long long)w);
+            return;
+        }
+        if (cur == kEmpty) {
+            const int32_t prev = atomicCAS(&key[h], kEmpty, k);
+            if (prev == kEmpty) {
+                atomicAdd(&ed[h], ((unsigned long long)hi << 32) + w);
+                return;
+            }
+            if (prev == k) {
+                atomicAdd(&ed[h], (unsigned long long)w);
+                return;
+            }
+        }
+        h = (h + 1) & mask;
+    }
+}
+
+template <int X> struct Log2 { static constexpr int value = 1 + Log2<X / 2>::value; };
+template <> struct Log2<1> { static constexpr int value = 0; };
+
+// Rows sorted into table-size classes: a workgroup holds 256/G vertices of
+// one class, each with an LDS table of S slots (S >= 1.5 d) and a group of G
+// lanes (packed classes G = S/4; rows of up to 1,024 entries S = 2048,
+// G = 256).  Lane i of a group takes entries i, i + G, ... of its vertex's
+// row, then scores slots [i*S/G, (i+1)*S/G); the argmax (largest score,
+// then smallest label) is a shuffle reduction inside the group, with an LDS
+// step across waves when the group spans several.
+template <int S, int G, typename W>
+__global__ __launch_bounds__(256) void k_cpt_group(CArgs a, const int32_t *__restrict__ list, int64_t count) {
+    constexpr int NV = 256 / G;
+    constexpr int SPL = S / G;
+    constexpr int BITS = Log2<S>::value;
+    constexpr int GW = G < 64 ? G : 64;   // lanes of a group inside one wave
+    constexpr int WPG = G / GW;           // waves per group
+    __shared__ int32_t s_key[NV * S];
+    __shared__ unsigned long long s_ed[NV * S];
+    __shared__ unsigned long long r_ok[4];
+    __shared__ uint32_t r_lf[4], r_eo[4], r_lp[4];
+    const int t = threadIdx.x;
+    const int kv = t / G, li = t % G;
+    int32_t *key = s_key + kv * S;
+    unsigned long long *ed = s_ed + kv * S;
+#pragma unroll
+    for (int q = 0; q < SPL; ++q) {
+        key[li * SPL + q] = kEmpty;
+        ed[li * SPL + q] = 0;
+    }
+    const int64_t k = (int64_t)blockIdx.x * NV + kv;
+    bool live = false;
+    int32_t v = 0;
+    int g = 0;
+    int64_t rs = 0, d = 0;
+    if (k < count) {
+        v = list[k];
+        g = graph_of(a.gid, v);
+        live = !a.st[g].done;
+        if (live) {
+            rs = a.row_ptr[v];
+            d = a.row_ptr[v + 1] - rs;
+        }
+    }
+    __syncthreads();
+    uint32_t loop = 0;
+    for (int64_t x = li; x < d; x += G) {
+        const int32_t j = a.col[rs + x];
+        const uint32_t w = cw<W>(a.w, rs + x);
+        if (j == v) {
+            loop += w;
+            continue;
+        }
+        const uint64_t nw = a.vw[j];
+        grp_insert(key, ed, BITS, vw_label(nw), w, (uint32_t)(nw >> 32));
+    }
+    __syncthreads();
+    int32_t ci = -1;
+    uint32_t own_hi = 0;
+    int64_t di = 0, tw = 0;
+    if (live) {
+        const uint64_t own = a.vw[v];
+        ci = vw_label(own);
+        own_hi = (uint32_t)(own >> 32);
+        di = a.delta[v];
+        tw = a.tw[g];
+    }
+    unsigned long long bok = 0;
+    uint32_t blf = 0xffffffffu, e_own = 0;
+#pragma unroll
+    for (int q = 0; q < SPL; ++q) {
+        const int x = li * SPL + q;
+        const int32_t kk = key[x];
+        if (kk == kEmpty) continue;
+        const unsigned long long edx = ed[x];
+        const uint32_t e = (uint32_t)edx;
+        if (kk == ci) {
+            e_own += e;
+            continue;
+        }
+        const uint32_t hi = (uint32_t)(edx >> 32);
+        const int64_t sc = tw * (int64_t)e - di * (int64_t)hi_deg(hi);
+        const unsigned long long ok = (unsigned long long)sc ^ 0x8000000000000000ull;
+        const uint32_t lf = ((uint32_t)kk << 1) | (hi_single(hi) ? 1u : 0u);
+        if (ok > bok || (ok == bok && lf < blf)) {
+            bok = ok;
+            blf = lf;
+        }
+    }
+#pragma unroll
+    for (int off = GW / 2; off > 0; off >>= 1) {
+        const unsigned long long ook = __shfl_xor(bok, off);
+        const uint32_t olf = __shfl_xor(blf, off);
+        if (ook > bok || (ook == bok && olf < blf)) {
+            bok = ook;
+            blf = olf;
+        }
+        e_own += __shfl_xor(e_own, off);
+        loop += __shfl_xor(loop, off);
+    }
+    if constexpr (WPG > 1) {
+        const int wid = t >> 6;
+        if ((t & 63) == 0) {
+            r_ok[wid] = bok;
+            r_lf[wid] = blf;
+            r_eo[wid] = e_own;
+            r_lp[wid] = loop;
+        }
+        __syncthreads();
+        if (li == 0) {
+            for (int w2 = wid + 1; w2 < wid + WPG; ++w2) {
+                if (r_ok[w2] > bok || (r_ok[w2] == bok && r_lf[w2] < blf)) {
+                    bok = r_ok[w2];
+                    blf = r_lf[w2];
+                }
+                e_own += r_eo[w2];
+                loop += r_lp[w2];
+            }
+        }
+    }
+    if (li == 0 && live) {
+        a.c_nxt[v] = cpt_decide(a.singlet, tw, ci, own_hi, di, (int64_t)e_own, bok != 0,
+                                (int64_t)(bok ^ 0x8000000000000000ull), (int32_t)(blf >> 1), (blf & 1u) != 0);
+        a.e_self[v] = e_own + loop;
+    }
+}
+
+// All packed classes in one launch: workgroups [bo[c], bo[c+1]) take class
+// c (S = 16 << c slots per table, G = S/4 lanes per vertex, 64 >> c
+// vertices per workgroup, 1,024 table slots in all), otherwise as
+// k_cpt_group.
+struct GroupBlocks {
+    int64_t bo[kGroupClasses + 1];     // first workgroup of every class
+    int64_t cstart[kGroupClasses + 1]; // first row of every class in the class list
+};
+
+template <typename W>
+__global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__restrict__ list, GroupBlocks gb) {
+    constexpr int SPL = 4;
+    __shared__ int32_t s_key[1024];
+    __shared__ unsigned long long s_ed[1024];
+    __shared__ unsigned long long r_ok[4];
+    __shared__ uint32_t r_lf[4], r_eo[4], r_lp[4];
+    const int t = threadIdx.x;
+    int c = 0;
+    while (c < kGroupClasses - 1 && (int64_t)blockIdx.x >= gb.bo[c + 1]) ++c;
+    const int bits = 4 + c;                  // log2 S
+    const int G = 4 << c;
+    const int NV = 64 >> c;
+    const int kv = t >> (2 + c), li = t & (G - 1);
+    const int S = 16 << c;
+    int32_t *key = s_key + kv * S;
+    unsigned long long *ed = s_ed + kv * S;
+#pragma unroll
+    for (int q = 0; q < SPL; ++q) {
+        key[li * SPL + q] = kEmpty;
+        ed[li * SPL + q] = 0;
+    }
+    const int64_t k = gb.cstart[c] + ((int64_t)blockIdx.x - gb.bo[c]) * NV + kv;
+    bool live = false;
+    int32_t v = 0;
+    int g = 0;
+    int64_t rs = 0, d = 0;
+    if (k < gb.cstart[c + 1]) {
+        v = list[k];
+        g = graph_of(a.gid, v);
+        live = !a.st[g].done;
+        if (live) {
+            rs = a.row_ptr[v];
+            d = a.row_ptr[v + 1] - rs;
+        }
+    }
+    __syncthreads();
+    uint32_t loop = 0;
+    for (int64_t x = li; x < d; x += G) {
+        const int32_t j = a.col[rs + x];
+        const uint32_t w = cw<W>(a.w, rs + x);
+        if (j == v) {
+            loop += w;
+            continue;
+        }
+        const uint64_t nw = a.vw[j];
+        grp_insert(key, ed, bits, vw_label(nw), w, (uint32_t)(nw >> 32));
+    }
+    __syncthreads();
+    int32_t ci = -1;
+    uint32_t own_hi = 0;
+    int64_t di = 0, tw = 0;
+    if (live) {
+        const uint64_t own = a.vw[v];
+        ci = vw_label(own);
+        own_hi = (uint32_t)(own >> 32);
+        di = a.delta[v];
+        tw = a.tw[g];
+    }
+    unsigned long long bok = 0;
+    uint32_t blf = 0xffffffffu, e_own = 0;
+#pragma unroll
+    for (int q = 0; q < SPL; ++q) {
+        const int x = li * SPL + q;
+        const int32_t kk = key[x];
+        if (kk == kEmpty) continue;
+        const unsigned long long edx = ed[x];
+        const uint32_t e = (uint32_t)edx;
+        if (kk == ci) {
+            e_own += e;
+            continue;
+        }
+        const uint32_t hi = (uint32_t)(edx >> 32);
+        const int64_t sc = tw * (int64_t)e - di * (int64_t)hi_deg(hi);
+        const unsigned long long ok = (unsigned long long)sc ^ 0x8000000000000000ull;
+        const uint32_t lf = ((uint32_t)kk << 1) | (hi_single(hi) ? 1u : 0u);
+        if (ok > bok || (ok == bok && lf < blf)) {
+            bok = ok;
+            blf = lf;
+        }
+    }
+    const int GW = G < 64 ? G : 64;
+    for (int off = GW >> 1; off > 0; off >>= 1) {
+        const unsigned long long ook = __shfl_xor(bok, off);
+        const uint32_t olf = __shfl_xor(blf, off);
+        if (ook > bok || (ook == bok && olf < blf)) {
+            bok = ook;
+            blf = olf;
+        }
+        e_own += __shfl_xor(e_own, off);
+        loop += __shfl_xor(loop, off);
+    }
+    if (G > 64) {   // uniform over the workgroup: the class is
+        const int wid = t >> 6;
+        if ((t & 63) == 0) {
+            r_ok[wid] = bok;
+            r_lf[wid] = blf;
+            r_eo[wid] = e_own;
+            r_lp[wid] = loop;
+        }
+        __syncthreads();
+        if (li == 0) {
+            for (int w2 = wid + 1; w2 < wid + G / 64; ++w2) {
+                if (r_ok[w2] > bok || (r_ok[w2] == bok && r_lf[w2] < blf)) {
+                    bok = r_ok[w2];
+                    blf = r_lf[w2];
+                }
+                e_own += r_eo[w2];
+                loop += r_lp[w2];
+            }
+        }
+    }
+    if (li == 0 && live) {
+        a.c_nxt[v] = cpt_decide(a.singlet, tw, ci, own_hi, di, (int64_t)e_own, bok != 0,
+                                (int64_t)(bok ^ 0x8000000000000000ull), (int32_t)(blf >> 1), (blf & 1u) != 0);
+        a.e_self[v] = e_own + loop;
+    }
+}
+
+// Table-size class of a packed row: smallest c with 3d <= 2 * (16 << c).
+__device__ __forceinline__ int size_class(int64_t d) {
+    int c = 0;
+    while (c < kGroupClasses - 1 && 3 * d > 2 * ((int64_t)16 << c)) ++c;
+    return c;
+}
+
+constexpr int kClassTile = 2048;
+
+__global__ __launch_bounds__(256) void k_class_count(const int64_t *__restrict__ rp, const int32_t *__restrict__ list,
+                                                     int64_t m, int32_t *counts, int64_t nblocks,
+                                                     unsigned long long *cls_nnz) {
+    __shared__ int cnt[kGroupClasses];
+    __shared__ unsigned long long ecnt[kGroupClasses];
+    if (threadIdx.x < kGroupClasses) {
+        cnt[threadIdx.x] = 0;
+        ecnt[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kClassTile;
+    for (int k = 0; k < kClassTile / 256; ++k) {
+        const int64_t i = base + k * 256 + threadIdx.x;
+        if (i >= m) break;
+        const int32_t v = list[i];
+        const int64_t d = rp[v + 1] - rp[v];
+        const int c = size_class(d);
+        atomicAdd(&cnt[c], 1);
+        atomicAdd(&ecnt[c], (unsigned long long)d);
+    }
+    __syncthreads();
+    if (threadIdx.x < kGroupClasses) {
+        counts[threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
+        if (ecnt[threadIdx.x]) atomicAdd(&cls_nnz[threadIdx.x], ecnt[threadIdx.x]);
+    }
+}
+
+// Stable scatter of the packed rows into their classes.
+__global__ __launch_bounds__(256) void k_class_scatter(const int64_t *__restrict__ rp, const int32_t *__restrict__ list,
+                                                       int64_t m, const int32_t *__restrict__ offs, int64_t nblocks,
+                                                       int32_t *out) {
+    __shared__ int run[kGroupClasses];
+    __shared__ int wc[4][kGroupClasses];
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    if (t < kGroupClasses) run[t] = offs[t * nblocks + blockIdx.x];
+    __syncthreads();
+    const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int64_t base = (int64_t)blockIdx.x * kClassTile;
+    for (int k = 0; k < kClassTile / 256; ++k) {
+        const int64_t i = base + k * 256 + t;
+        int32_t v = 0;
+        int c = -1;
+        if (i < m) {
+            v = list[i];
+            c = size_class(rp[v + 1] - rp[v]);
+        }
+        int rank = 0;
+#pragma unroll
+        for (int cc = 0; cc < kGroupClasses; ++cc) {
+            const unsigned long long msk = __ballot(c == cc);
+            if (c == cc) rank = __popcll(msk & lt);
+            if (lane == 0) wc[wid][cc] = __popcll(msk);
+        }
+        __syncthreads();
+        if (c >= 0) {
+            int pos = run[c] + rank;
+            for (int w2 = 0; w2 < wid; ++w2) pos += wc[w2][c];
+            out[pos] = v;
+        }
+        __syncthreads();
+        if (t < kGroupClasses) run[t] += wc[0][t] + wc[1][t] + wc[2][t] + wc[3][t];
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------------ hubs --
 
 struct CHub {
@@ -815,6 +1172,42 @@ __global__ __launch_bounds__(256) void k_cpt_hub_decide(CArgs a, CHub hm, const 
 
 // ------------------------------------------------------------------- host --
 
+void compact_classes(const int64_t *rp, const int32_t *list, int64_t m, int32_t *out, int64_t *cstart,
+                     int64_t *cnnz, hipStream_t s, Timer *t) {
+    for (int c = 0; c <= kGroupClasses; ++c) cstart[c] = 0;
+    for (int c = 0; c < kGroupClasses; ++c) cnnz[c] = 0;
+    if (m <= 0) return;
+    const int64_t nblk = (m + kClassTile - 1) / kClassTile;
+    const int64_t cm = kGroupClasses * nblk;
+    TempBuf counts((size_t)(cm + 1) * sizeof(int32_t), s);
+    TempBuf enz(kGroupClasses * sizeof(unsigned long long), s);
+    fill<uint64_t>(enz.as<uint64_t>(), 0, kGroupClasses, s);
+    {
+        TimedLaunch tl(t, TG_LEVEL, "k_class_count", (double)m * 20);
+        k_class_count<<<(unsigned)nblk, 256, 0, s>>>(rp, list, m, counts.as<int32_t>(), nblk,
+                                                    enz.as<unsigned long long>());
+        LV_LAUNCHED("k_class_count");
+    }
+    scan_exclusive<int32_t, int32_t>(counts.as<int32_t>(), counts.as<int32_t>(), cm, counts.as<int32_t>() + cm, s, t);
+    {
+        TimedLaunch tl(t, TG_LEVEL, "k_class_scatter", (double)m * 24);
+        k_class_scatter<<<(unsigned)nblk, 256, 0, s>>>(rp, list, m, counts.as<int32_t>(), nblk, out);
+        LV_LAUNCHED("k_class_scatter");
+    }
+    int32_t hs[kGroupClasses];
+    for (int c = 0; c < kGroupClasses; ++c)
+        LV_HIP(hipMemcpyAsync(&hs[c], counts.as<int32_t>() + (int64_t)c * nblk, sizeof(int32_t), hipMemcpyDeviceToHost,
+                              s));
+    unsigned long long hn[kGroupClasses];
+    LV_HIP(hipMemcpyAsync(hn, enz.p, sizeof hn, hipMemcpyDeviceToHost, s));
+    LV_HIP(hipStreamSynchronize(s));
+    for (int c = 0; c < kGroupClasses; ++c) {
+        cstart[c] = hs[c];
+        cnnz[c] = (int64_t)hn[c];
+    }
+    cstart[kGroupClasses] = m;
+}
+
 void compact_init_singletons(int32_t *c0, int32_t *c1, int32_t *c2, const int64_t *delta, uint64_t *ds, uint32_t *es,
                              int64_t n, hipStream_t s) {
     if (n <= 0) return;
@@ -860,18 +1253,28 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
         k_cpt_small<W><<<grid_for(cp.n, 256), 256, 0, s>>>(a, cp.n);
         LV_LAUNCHED("k_cpt_small");
     }
-    if (cp.pack_blocks > 0) {
-        TimedLaunch tl(t, TG_SWEEP, "k_cpt_pack<1536,1024,64,", bytes(B_T16, B_BLOCK), sfx.c_str());
-        k_cpt_pack<kPackSlotsCompact, kPackW, 64, W><<<(unsigned)cp.pack_blocks, 256, 0, s>>>(
-            a, cp.list + cp.bstart[B_T16], cp.pack_pos, cp.pack_first, cp.bstart[B_BLOCK] - cp.bstart[B_T16]);
-        LV_LAUNCHED("k_cpt_pack");
+    {
+        GroupBlocks gb;
+        gb.bo[0] = 0;
+        double gbytes = 0;
+        for (int c = 0; c < kGroupClasses; ++c) {
+            const int64_t cnt = cp.cstart[c + 1] - cp.cstart[c];
+            const int nv = 64 >> c;
+            gb.bo[c + 1] = gb.bo[c] + (cnt + nv - 1) / nv;
+            gbytes += (double)cnt * vb + (double)cp.cnnz[c] * eb;
+        }
+        for (int c = 0; c <= kGroupClasses; ++c) gb.cstart[c] = cp.cstart[c];
+        if (gb.bo[kGroupClasses] > 0) {
+            TimedLaunch tl(t, TG_SWEEP, "k_cpt_groups<", gbytes, sfx.c_str());
+            k_cpt_groups<W><<<(unsigned)gb.bo[kGroupClasses], 256, 0, s>>>(a, cp.glist, gb);
+            LV_LAUNCHED("k_cpt_groups");
+        }
     }
     const int64_t nw = cp.bstart[B_HUB] - cp.bstart[B_BLOCK];
     if (nw > 0) {
-        TimedLaunch tl(t, TG_SWEEP, "k_cpt_pack<2048,2048,1,", bytes(B_BLOCK, B_HUB), sfx.c_str());
-        k_cpt_pack<2048, 2048, 1, W><<<(unsigned)nw, 256, 0, s>>>(a, cp.list + cp.bstart[B_BLOCK], nullptr, nullptr,
-                                                                   nw);
-        LV_LAUNCHED("k_cpt_pack<wide>");
+        TimedLaunch tl(t, TG_SWEEP, "k_cpt_group<2048,256,", bytes(B_BLOCK, B_HUB), sfx.c_str());
+        k_cpt_group<2048, 256, W><<<(unsigned)nw, 256, 0, s>>>(a, cp.list + cp.bstart[B_BLOCK], nw);
+        LV_LAUNCHED("k_cpt_group<wide>");
     }
     if (cp.hubs > 0) {
         CHub hm{cp.list + cp.bstart[B_HUB], cp.tab_off, cp.chunk_off, cp.scan_off, cp.tab_size,
