@@ -862,28 +862,31 @@ __global__ void k_init_labels(int32_t *c0, int32_t *c1, int32_t *c2, const int32
 
 constexpr int kBucketTile = 2048;  // vertices per bucketing block (256 x 8)
 
-__device__ __forceinline__ int bucket_of(int64_t d) {
+// block_max: the longest row of the workgroup-per-vertex bucket (the hub
+// path takes longer ones).
+__device__ __forceinline__ int bucket_of(int64_t d, int64_t block_max) {
     if (d <= 0) return -1;
 #pragma unroll
-    for (int b = 0; b < NBUCKET - 1; ++b)
+    for (int b = 0; b < B_BLOCK; ++b)
         if (d <= kBucketMax[b]) return b;
-    return B_HUB;
+    return d <= block_max ? B_BLOCK : B_HUB;
 }
 
 // Bucket of vertex v, or -1 if it is not evaluated (empty row, or its graph's
 // phase is over when gid and st are given).
 __device__ __forceinline__ int bucket_of_vertex(const int64_t *__restrict__ rp, const int32_t *__restrict__ gid,
-                                                const PhaseState *__restrict__ st, int64_t v, int64_t *deg) {
+                                                const PhaseState *__restrict__ st, int64_t v, int64_t *deg,
+                                                int64_t block_max) {
     const int64_t d = rp[v + 1] - rp[v];
     *deg = d;
     if (gid && st[gid[v]].done) return -1;
-    return bucket_of(d);
+    return bucket_of(d, block_max);
 }
 
 __global__ __launch_bounds__(256) void k_bucket_count(const int64_t *__restrict__ rp, int64_t n, int32_t *counts,
                                                       int64_t nblocks, unsigned long long *bucket_nnz,
                                                       const int32_t *__restrict__ gid,
-                                                      const PhaseState *__restrict__ st) {
+                                                      const PhaseState *__restrict__ st, int64_t block_max) {
     __shared__ int cnt[NBUCKET];
     __shared__ unsigned long long ecnt[NBUCKET];
     if (threadIdx.x < NBUCKET) {
@@ -897,7 +900,7 @@ __global__ __launch_bounds__(256) void k_bucket_count(const int64_t *__restrict_
         const int64_t v = base + k * 256 + threadIdx.x;
         if (v < n) {
             int64_t d;
-            const int b = bucket_of_vertex(rp, gid, st, v, &d);
+            const int b = bucket_of_vertex(rp, gid, st, v, &d, block_max);
             if (b >= 0) {
                 atomicAdd(&cnt[b], 1);
                 atomicAdd(&ecnt[b], (unsigned long long)d);
@@ -916,7 +919,7 @@ __global__ __launch_bounds__(256) void k_bucket_count(const int64_t *__restrict_
 __global__ __launch_bounds__(256) void k_bucket_scatter(const int64_t *__restrict__ rp, int64_t n,
                                                         const int32_t *__restrict__ offs, int64_t nblocks,
                                                         int32_t *list, const int32_t *__restrict__ gid,
-                                                        const PhaseState *__restrict__ st) {
+                                                        const PhaseState *__restrict__ st, int64_t block_max) {
     __shared__ int run[NBUCKET];
     __shared__ int wc[4][NBUCKET];
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
@@ -927,7 +930,7 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(const int64_t *__restric
     for (int k = 0; k < kBucketTile / 256; ++k) {
         const int64_t v = base + k * 256 + t;
         int64_t d;
-        const int b = v < n ? bucket_of_vertex(rp, gid, st, v, &d) : -1;
+        const int b = v < n ? bucket_of_vertex(rp, gid, st, v, &d, block_max) : -1;
         int rank = 0;
 #pragma unroll
         for (int bb = 0; bb < NBUCKET; ++bb) {
@@ -1005,6 +1008,7 @@ void Sweeper::replan_active(const GraphView &g) { plan_impl(g, true); }
 
 void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     n_ = g.n;
+    const int64_t block_max = compact_ ? kCompactBlockMax : kBucketMax[B_BLOCK];
     const int32_t *skip_gid = active_only && batch_ ? gid_ : nullptr;
     const PhaseState *skip_st = active_only && batch_ ? st_.p : nullptr;
     compact_ = batch_ || g.tw < kCompactTwMax;
@@ -1029,14 +1033,15 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     {
         TimedLaunch tl(t_, TG_LEVEL, "k_bucket_count", (double)g.n * 16);
         k_bucket_count<<<(unsigned)nblk, 256, 0, s_>>>(g.row_ptr, g.n, counts, nblk, bnnz.as<unsigned long long>(),
-                                                       skip_gid, skip_st);
+                                                       skip_gid, skip_st, block_max);
         LV_LAUNCHED("k_bucket_count");
     }
     const int64_t m = NBUCKET * nblk;
     scan_exclusive<int32_t, int32_t>(counts, counts, m, counts + m, s_, t_);
     {
         TimedLaunch tl(t_, TG_LEVEL, "k_bucket_scatter", (double)g.n * 20);
-        k_bucket_scatter<<<(unsigned)nblk, 256, 0, s_>>>(g.row_ptr, g.n, counts, nblk, list_.p, skip_gid, skip_st);
+        k_bucket_scatter<<<(unsigned)nblk, 256, 0, s_>>>(g.row_ptr, g.n, counts, nblk, list_.p, skip_gid, skip_st,
+                                                         block_max);
         LV_LAUNCHED("k_bucket_scatter");
     }
     int32_t hs[NBUCKET + 1];
@@ -1051,8 +1056,10 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     // line positions of the packed vertices (buckets B_T16 to B_MID, contiguous in the list)
     pack_count_ = bstart_[B_BLOCK] - bstart_[B_T16];
     if (compact_) {
-        glist_.reserve((size_t)(pack_count_ > 0 ? pack_count_ : 1));
-        compact_classes(g.row_ptr, list_.p + bstart_[B_T16], pack_count_, glist_.p, cstart_, cnnz_, s_, t_);
+        // every row swept from LDS (9 .. kCompactBlockMax entries), by table size
+        const int64_t nl = bstart_[B_HUB] - bstart_[B_T16];
+        glist_.reserve((size_t)(nl > 0 ? nl : 1));
+        compact_classes(g.row_ptr, list_.p + bstart_[B_T16], nl, glist_.p, cstart_, cnnz_, s_, t_);
     } else if (pack_count_ > 0 && g.tw <= kTwFastMax) {
         TempBuf cost((size_t)pack_count_ * sizeof(int32_t), s_);
         k_pack_cost<<<grid_for(pack_count_, 256), 256, 0, s_>>>(g.row_ptr, list_.p + bstart_[B_T16], pack_count_,
@@ -1237,8 +1244,8 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
         cp.pack_first = pack_first_.p;
         cp.pack_blocks = pack_blocks_;
         cp.glist = glist_.p;
-        for (int c = 0; c <= kGroupClasses; ++c) cp.cstart[c] = cstart_[c];
-        for (int c = 0; c < kGroupClasses; ++c) cp.cnnz[c] = cnnz_[c];
+        for (int c = 0; c <= kLdsClasses; ++c) cp.cstart[c] = cstart_[c];
+        for (int c = 0; c < kLdsClasses; ++c) cp.cnnz[c] = cnnz_[c];
         cp.hubs = hubs_;
         cp.hub_chunks = hub_chunks_;
         cp.hub_scans = hub_scans_;

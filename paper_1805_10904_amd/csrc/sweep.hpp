@@ -50,10 +50,13 @@ constexpr int kPackSlots = 2048;
 constexpr int kPackW = 1024;
 constexpr int kPackMinCost = kPackW / 256;
 constexpr int64_t kPackMaxDeg = 341;
-constexpr int kPackSlotsCompact = kPackW + 512;
-// Compact levels sort the packed rows (9..341 entries) into table-size
-// classes S = 16 << c, c < kGroupClasses, rows with 3d <= 2S.
+// Compact levels sort the rows they sweep from LDS into table-size classes:
+// packed classes c < kGroupClasses with S = 16 << c slots (rows with
+// 3d <= 2S, up to 341 entries), then S = 2048 (up to 1,365 entries) and
+// S = 4096 (up to kCompactBlockMax entries), one vertex per workgroup.
 constexpr int kGroupClasses = 6;
+constexpr int kLdsClasses = kGroupClasses + 2;
+constexpr int64_t kCompactBlockMax = 2730;
 // log2 of the LDS hash table size of a packed row of d >= 1 entries: the
 // smallest b >= 1 with 2^b >= ceil(3d/2) (load at most 2/3).
 __device__ __forceinline__ int pack_table_bits(int64_t d) {
@@ -71,9 +74,9 @@ struct CompactPass {
     int64_t bnnz[NBUCKET] = {0};
     const int64_t *pack_pos = nullptr, *pack_first = nullptr;
     int64_t pack_blocks = 0;
-    const int32_t *glist = nullptr;            // packed rows by class
-    int64_t cstart[kGroupClasses + 1] = {0};   // class c: glist[cstart[c], cstart[c+1])
-    int64_t cnnz[kGroupClasses] = {0};
+    const int32_t *glist = nullptr;            // rows swept from LDS, by class
+    int64_t cstart[kLdsClasses + 1] = {0};     // class c: glist[cstart[c], cstart[c+1])
+    int64_t cnnz[kLdsClasses] = {0};
     int64_t hubs = 0, hub_chunks = 0, hub_scans = 0;
     const int64_t *tab_off = nullptr, *chunk_off = nullptr, *scan_off = nullptr, *tab_size = nullptr;
     const int32_t *chunk_hub = nullptr, *scan_hub = nullptr;
@@ -108,9 +111,9 @@ void compact_init_singletons(int32_t *c0, int32_t *c1, int32_t *c2, const int64_
                              int64_t n, hipStream_t s);
 void compact_init_labels(int32_t *c0, int32_t *c1, int32_t *c2, const int32_t *labels, const int64_t *delta,
                          uint64_t *ds, uint32_t *es, int64_t n, hipStream_t s);
-// Stable partition of the m packed rows in list by table-size class into
-// out; cstart (kGroupClasses + 1) and cnnz (kGroupClasses) receive the class
-// offsets and entry counts (synchronises the stream).
+// Stable partition of the m rows in list by table-size class into out;
+// cstart (kLdsClasses + 1) and cnnz (kLdsClasses) receive the class offsets
+// and entry counts (synchronises the stream).
 void compact_classes(const int64_t *rp, const int32_t *list, int64_t m, int32_t *out, int64_t *cstart,
                      int64_t *cnnz, hipStream_t s, Timer *t);
 void compact_final_labels(const int32_t *c0, const int32_t *c1, const int32_t *c2, const int32_t *gid,
@@ -182,9 +185,9 @@ class Sweeper {
     const int64_t *tw_ = nullptr;
     bool batch_ = false;
     DevBuf<int32_t> list_;          // vertices grouped by bucket, ascending inside a bucket
-    DevBuf<int32_t> glist_;         // compact: packed rows grouped by table-size class
-    int64_t cstart_[kGroupClasses + 1] = {0};
-    int64_t cnnz_[kGroupClasses] = {0};
+    DevBuf<int32_t> glist_;         // compact: rows swept from LDS, grouped by table-size class
+    int64_t cstart_[kLdsClasses + 1] = {0};
+    int64_t cnnz_[kLdsClasses] = {0};
     DevBuf<int32_t> bcount_;        // bucketing scratch (per-block counts / offsets)
     DevBuf<PhaseState> st_;
     DevBuf<uint64_t> qpart_;        // per-block partial sums of deg^2 (lo, hi)

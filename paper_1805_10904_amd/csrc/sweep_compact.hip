@@ -18,7 +18,8 @@
 // fits 64 bits.
 //
 // Pass kernels: k_cpt_publish (VW, sum deg^2 per graph) -> k_cpt_small /
-// k_cpt_pack / hub kernels (new labels, e_{i->c_i} incl. loop per vertex)
+// k_cpt_groups / k_cpt_group / hub kernels (new labels, e_{i->c_i} incl.
+// loop per vertex)
 // -> k_cpt_commit (movers' atomics, per-graph I and mover counts) ->
 // k_cpt_finalize (per graph: Q_int and the acceptance test).
 #include "prims.hpp"
@@ -407,235 +408,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     a.e_self[v] = e_own + loop;
 }
 
-// ----------------------------------------------------------- packed groups --
-
-// LDS table slot: key = label; ed = e_{i->C} in the low 32 bits, the
-// community's published high word (degree | singleton flag) in the high 32
-// bits, added once by the thread that claims the slot.
-__device__ __forceinline__ void cpt_insert(int32_t *key, unsigned long long *ed, uint8_t *own, int bits, int32_t k,
-                                           uint32_t w, uint32_t hi, int owner) {
-    const uint32_t mask = (1u << bits) - 1;
-    uint32_t h = ((uint32_t)k * 0x9E3779B1u) >> (32 - bits);
-    while (true) {
-        const int32_t cur = ((volatile int32_t *)key)[h];
-        if (cur == k) {
-            atomicAdd(&ed[h], (unsigned long long)w);
-            return;
-        }
-        if (cur == kEmpty) {
-            const int32_t prev = atomicCAS(&key[h], kEmpty, k);
-            if (prev == kEmpty) {
-                own[h] = (uint8_t)owner;
-                atomicAdd(&ed[h], ((unsigned long long)hi << 32) + w);
-                return;
-            }
-            if (prev == k) {
-                atomicAdd(&ed[h], (unsigned long long)w);
-                return;
-            }
-        }
-        h = (h + 1) & mask;
-    }
-}
-
-__device__ __forceinline__ int cpt_bits(int64_t d) { return d > 0 ? pack_table_bits(d) : 0; }
-
-__device__ __forceinline__ int cpt_find(const int32_t *a, int n, int32_t x) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (a[mid] <= x) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-constexpr int kCptUnroll = 4;
-
-// Packed workgroups (WIN < SLOTS): the vertices whose line position lies in
-// [b*WIN, (b+1)*WIN), at most MAXV of them, tables of 2^ceil(log2(2d)) <= WIN
-// slots.  Wide mode (WIN == SLOTS, MAXV == 1): one vertex per workgroup.
-// Vertices of graphs whose phase is over take part with no entries and
-// write nothing.
-template <int SLOTS, int WIN, int MAXV, typename W>
-__global__ __launch_bounds__(256) void k_cpt_pack(CArgs a, const int32_t *__restrict__ list,
-                                                  const int64_t *__restrict__ pos, const int64_t *__restrict__ first,
-                                                  int64_t count) {
-    constexpr bool kWide = WIN == SLOTS;
-    __shared__ int32_t s_key[SLOTS];
-    __shared__ unsigned long long s_ed[SLOTS];
-    __shared__ uint8_t s_own[SLOTS];
-    __shared__ int32_t s_v[MAXV], s_ci[MAXV], s_toff[MAXV], s_eoff[MAXV], s_bits[MAXV];
-    __shared__ uint32_t s_bestl[MAXV];
-    __shared__ int64_t s_rs[MAXV], s_delta[MAXV], s_tw[MAXV];
-    __shared__ unsigned long long s_best[MAXV];
-    __shared__ uint32_t s_eown[MAXV], s_loop[MAXV];
-    __shared__ int32_t s_E;
-    const int t = threadIdx.x;
-    int64_t k0;
-    int nv;
-    if constexpr (kWide) {
-        k0 = blockIdx.x;
-        nv = k0 < count ? 1 : 0;
-    } else {
-        k0 = first[blockIdx.x];
-        nv = (int)(first[blockIdx.x + 1] - k0);
-    }
-    const int64_t lo_pos = (int64_t)blockIdx.x * WIN;
-    // descriptors: thread t owns vertex t
-    int32_t v = 0, ci = 0;
-    uint32_t own_hi = 0;
-    int64_t d = 0, di = 0, tw = 0;
-    bool live = false;
-    if (t < nv) {
-        v = list[k0 + t];
-        const int g = graph_of(a.gid, v);
-        live = !a.st[g].done;
-        const int64_t rs = a.row_ptr[v];
-        d = live ? a.row_ptr[v + 1] - rs : 0;
-        const uint64_t own = a.vw[v];
-        ci = vw_label(own);
-        own_hi = (uint32_t)(own >> 32);
-        di = a.delta[v];
-        tw = a.tw[g];
-        s_v[t] = v;
-        s_ci[t] = ci;
-        s_rs[t] = rs;
-        s_delta[t] = di;
-        s_tw[t] = tw;
-        s_toff[t] = kWide ? 0 : (int32_t)(pos[k0 + t] - lo_pos);
-        s_bits[t] = cpt_bits(d);
-        s_best[t] = 0;
-        s_bestl[t] = 0xffffffffu;
-        s_eown[t] = 0;
-        s_loop[t] = 0;
-    }
-    if (t < 64) {   // edge offsets: exclusive scan of the row lengths (MAXV <= 64)
-        int32_t x = t < nv ? (int32_t)d : 0;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int32_t y = __shfl_up(x, off);
-            if (t >= off) x += y;
-        }
-        if (t < MAXV) s_eoff[t] = x - (t < nv ? (int32_t)d : 0);
-        if (t == 63) s_E = x;
-    }
-    __syncthreads();
-    const int32_t E = s_E;
-    // clear only the slots the workgroup's tables use
-    const int32_t used = nv > 0 ? s_toff[nv - 1] + (1 << s_bits[nv - 1]) : 0;
-    for (int x = t; x < used; x += 256) {
-        s_key[x] = kEmpty;
-        s_ed[x] = 0;
-    }
-    __syncthreads();
-    for (int32_t base = 0; base < E; base += 256 * kCptUnroll) {
-        int kk[kCptUnroll];
-        int64_t e[kCptUnroll];
-        int32_t j[kCptUnroll];
-        uint32_t w[kCptUnroll];
-        uint64_t nw[kCptUnroll];
-#pragma unroll
-        for (int u = 0; u < kCptUnroll; ++u) {
-            const int32_t x = base + u * 256 + t;
-            kk[u] = -1;
-            if (x < E) {
-                kk[u] = kWide ? 0 : cpt_find(s_eoff, nv, x);
-                e[u] = s_rs[kk[u]] + (x - s_eoff[kk[u]]);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kCptUnroll; ++u) {
-            if (kk[u] >= 0) {
-                j[u] = a.col[e[u]];
-                w[u] = cw<W>(a.w, e[u]);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kCptUnroll; ++u)
-            if (kk[u] >= 0 && j[u] != s_v[kk[u]]) nw[u] = a.vw[j[u]];
-#pragma unroll
-        for (int u = 0; u < kCptUnroll; ++u) {
-            if (kk[u] < 0) continue;
-            if (j[u] == s_v[kk[u]])
-                atomicAdd(&s_loop[kk[u]], w[u]);
-            else
-                cpt_insert(s_key + s_toff[kk[u]], s_ed + s_toff[kk[u]], s_own + s_toff[kk[u]], s_bits[kk[u]],
-                           vw_label(nw[u]), w[u], (uint32_t)(nw[u] >> 32), kk[u]);
-        }
-    }
-    __syncthreads();
-    // scores (order key = score with the sign bit flipped) replace the slot's
-    // weight word; the own community is recorded and removed; the winner's
-    // singleton flag moves to bit 7 of the owner byte
-    constexpr int SPT = SLOTS / 256;
-#pragma unroll
-    for (int q = 0; q < SPT; ++q) {
-        const int32_t x = q * 256 + t;
-        if (x >= used) continue;
-        const int32_t key = s_key[x];
-        if (key == kEmpty) continue;
-        const int kv = s_own[x];
-        const unsigned long long ed = s_ed[x];
-        if (key == s_ci[kv]) {
-            s_eown[kv] = (uint32_t)ed;
-            s_key[x] = kEmpty;
-            continue;
-        }
-        const uint32_t hi = (uint32_t)(ed >> 32);
-        const int64_t sc = s_tw[kv] * (int64_t)(uint32_t)ed - s_delta[kv] * (int64_t)hi_deg(hi);
-        const unsigned long long ok = (unsigned long long)sc ^ 0x8000000000000000ull;
-        s_ed[x] = ok;
-        s_own[x] = (uint8_t)(kv | (hi_single(hi) ? 0x80 : 0));
-        atomicMax(&s_best[kv], ok);
-    }
-    __syncthreads();
-    // the minimum label among the best scores, with its singleton flag in bit 0
-#pragma unroll
-    for (int q = 0; q < SPT; ++q) {
-        const int32_t x = q * 256 + t;
-        if (x >= used) continue;
-        const int32_t key = s_key[x];
-        if (key == kEmpty) continue;
-        const int kv = s_own[x] & 0x7f;
-        if (s_ed[x] == s_best[kv]) atomicMin(&s_bestl[kv], ((uint32_t)key << 1) | ((s_own[x] >> 7) & 1u));
-    }
-    __syncthreads();
-    if (t < nv && live) {
-        const bool has = s_best[t] != 0;
-        const int64_t bs = (int64_t)(s_best[t] ^ 0x8000000000000000ull);
-        const int64_t e_own = (int64_t)s_eown[t];
-        const uint32_t blf = s_bestl[t];
-        a.c_nxt[v] = cpt_decide(a.singlet, tw, ci, own_hi, di, e_own, has, bs, (int32_t)(blf >> 1), (blf & 1u) != 0);
-        a.e_self[v] = s_eown[t] + s_loop[t];
-    }
-}
-
 // ------------------------------------------------------ lane groups by size --
 
-// Insert or add for a table of 2^bits slots with keys and e | high words.
-__device__ __forceinline__ void grp_insert(int32_t *key, unsigned long long *ed, int bits, int32_t k, uint32_t w,
+// Insert or add for a table of 2^bits slots: key, e_{i->C} (32-bit adds)
+// and the community's published high word, stored once by the claimer.
+__device__ __forceinline__ void grp_insert(int32_t *key, uint32_t *es, uint32_t *hs, int bits, int32_t k, uint32_t w,
                                            uint32_t hi) {
     const uint32_t mask = (1u << bits) - 1;
     uint32_t h = ((uint32_t)k * 0x9E3779B1u) >> (32 - bits);
     while (true) {
         const int32_t cur = ((volatile int32_t *)key)[h];
-        if (cur == k) {
-            atomicAdd(&ed[h], (unsigned long long)w);
-            return;
-        }
+        if (cur == k) break;
         if (cur == kEmpty) {
             const int32_t prev = atomicCAS(&key[h], kEmpty, k);
             if (prev == kEmpty) {
-                atomicAdd(&ed[h], ((unsigned long long)hi << 32) + w);
-                return;
+                hs[h] = hi;
+                break;
             }
-            if (prev == k) {
-                atomicAdd(&ed[h], (unsigned long long)w);
-                return;
-            }
+            if (prev == k) break;
         }
         h = (h + 1) & mask;
     }
+    atomicAdd(&es[h], w);
 }
 
 template <int X> struct Log2 { static constexpr int value = 1 + Log2<X / 2>::value; };
@@ -656,17 +450,17 @@ __global__ __launch_bounds__(256) void k_cpt_group(CArgs a, const int32_t *__res
     constexpr int GW = G < 64 ? G : 64;   // lanes of a group inside one wave
     constexpr int WPG = G / GW;           // waves per group
     __shared__ int32_t s_key[NV * S];
-    __shared__ unsigned long long s_ed[NV * S];
+    __shared__ uint32_t s_e[NV * S], s_hi[NV * S];
     __shared__ unsigned long long r_ok[4];
     __shared__ uint32_t r_lf[4], r_eo[4], r_lp[4];
     const int t = threadIdx.x;
     const int kv = t / G, li = t % G;
     int32_t *key = s_key + kv * S;
-    unsigned long long *ed = s_ed + kv * S;
+    uint32_t *es = s_e + kv * S, *hs = s_hi + kv * S;
 #pragma unroll
     for (int q = 0; q < SPL; ++q) {
         key[li * SPL + q] = kEmpty;
-        ed[li * SPL + q] = 0;
+        es[li * SPL + q] = 0;
     }
     const int64_t k = (int64_t)blockIdx.x * NV + kv;
     bool live = false;
@@ -692,7 +486,7 @@ __global__ __launch_bounds__(256) void k_cpt_group(CArgs a, const int32_t *__res
             continue;
         }
         const uint64_t nw = a.vw[j];
-        grp_insert(key, ed, BITS, vw_label(nw), w, (uint32_t)(nw >> 32));
+        grp_insert(key, es, hs, BITS, vw_label(nw), w, (uint32_t)(nw >> 32));
     }
     __syncthreads();
     int32_t ci = -1;
@@ -712,13 +506,12 @@ __global__ __launch_bounds__(256) void k_cpt_group(CArgs a, const int32_t *__res
         const int x = li * SPL + q;
         const int32_t kk = key[x];
         if (kk == kEmpty) continue;
-        const unsigned long long edx = ed[x];
-        const uint32_t e = (uint32_t)edx;
+        const uint32_t e = es[x];
         if (kk == ci) {
             e_own += e;
             continue;
         }
-        const uint32_t hi = (uint32_t)(edx >> 32);
+        const uint32_t hi = hs[x];
         const int64_t sc = tw * (int64_t)e - di * (int64_t)hi_deg(hi);
         const unsigned long long ok = (unsigned long long)sc ^ 0x8000000000000000ull;
         const uint32_t lf = ((uint32_t)kk << 1) | (hi_single(hi) ? 1u : 0u);
@@ -778,7 +571,7 @@ template <typename W>
 __global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__restrict__ list, GroupBlocks gb) {
     constexpr int SPL = 4;
     __shared__ int32_t s_key[1024];
-    __shared__ unsigned long long s_ed[1024];
+    __shared__ uint32_t s_e[1024], s_hi[1024];
     __shared__ unsigned long long r_ok[4];
     __shared__ uint32_t r_lf[4], r_eo[4], r_lp[4];
     const int t = threadIdx.x;
@@ -790,11 +583,11 @@ __global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__re
     const int kv = t >> (2 + c), li = t & (G - 1);
     const int S = 16 << c;
     int32_t *key = s_key + kv * S;
-    unsigned long long *ed = s_ed + kv * S;
+    uint32_t *es = s_e + kv * S, *hs = s_hi + kv * S;
 #pragma unroll
     for (int q = 0; q < SPL; ++q) {
         key[li * SPL + q] = kEmpty;
-        ed[li * SPL + q] = 0;
+        es[li * SPL + q] = 0;
     }
     const int64_t k = gb.cstart[c] + ((int64_t)blockIdx.x - gb.bo[c]) * NV + kv;
     bool live = false;
@@ -820,7 +613,7 @@ __global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__re
             continue;
         }
         const uint64_t nw = a.vw[j];
-        grp_insert(key, ed, bits, vw_label(nw), w, (uint32_t)(nw >> 32));
+        grp_insert(key, es, hs, bits, vw_label(nw), w, (uint32_t)(nw >> 32));
     }
     __syncthreads();
     int32_t ci = -1;
@@ -840,13 +633,12 @@ __global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__re
         const int x = li * SPL + q;
         const int32_t kk = key[x];
         if (kk == kEmpty) continue;
-        const unsigned long long edx = ed[x];
-        const uint32_t e = (uint32_t)edx;
+        const uint32_t e = es[x];
         if (kk == ci) {
             e_own += e;
             continue;
         }
-        const uint32_t hi = (uint32_t)(edx >> 32);
+        const uint32_t hi = hs[x];
         const int64_t sc = tw * (int64_t)e - di * (int64_t)hi_deg(hi);
         const unsigned long long ok = (unsigned long long)sc ^ 0x8000000000000000ull;
         const uint32_t lf = ((uint32_t)kk << 1) | (hi_single(hi) ? 1u : 0u);
@@ -893,11 +685,13 @@ __global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__re
     }
 }
 
-// Table-size class of a packed row: smallest c with 3d <= 2 * (16 << c).
+// Table-size class of a row swept from LDS: the smallest packed class c
+// with 3d <= 2 * (16 << c), else 2048 slots, else 4096 slots.
 __device__ __forceinline__ int size_class(int64_t d) {
     int c = 0;
-    while (c < kGroupClasses - 1 && 3 * d > 2 * ((int64_t)16 << c)) ++c;
-    return c;
+    while (c < kGroupClasses && 3 * d > 2 * ((int64_t)16 << c)) ++c;
+    if (c < kGroupClasses) return c;
+    return 3 * d <= 2 * 2048 ? kGroupClasses : kGroupClasses + 1;
 }
 
 constexpr int kClassTile = 2048;
@@ -905,9 +699,9 @@ constexpr int kClassTile = 2048;
 __global__ __launch_bounds__(256) void k_class_count(const int64_t *__restrict__ rp, const int32_t *__restrict__ list,
                                                      int64_t m, int32_t *counts, int64_t nblocks,
                                                      unsigned long long *cls_nnz) {
-    __shared__ int cnt[kGroupClasses];
-    __shared__ unsigned long long ecnt[kGroupClasses];
-    if (threadIdx.x < kGroupClasses) {
+    __shared__ int cnt[kLdsClasses];
+    __shared__ unsigned long long ecnt[kLdsClasses];
+    if (threadIdx.x < kLdsClasses) {
         cnt[threadIdx.x] = 0;
         ecnt[threadIdx.x] = 0;
     }
@@ -923,7 +717,7 @@ __global__ __launch_bounds__(256) void k_class_count(const int64_t *__restrict__
         atomicAdd(&ecnt[c], (unsigned long long)d);
     }
     __syncthreads();
-    if (threadIdx.x < kGroupClasses) {
+    if (threadIdx.x < kLdsClasses) {
         counts[threadIdx.x * nblocks + blockIdx.x] = cnt[threadIdx.x];
         if (ecnt[threadIdx.x]) atomicAdd(&cls_nnz[threadIdx.x], ecnt[threadIdx.x]);
     }
@@ -933,10 +727,10 @@ __global__ __launch_bounds__(256) void k_class_count(const int64_t *__restrict__
 __global__ __launch_bounds__(256) void k_class_scatter(const int64_t *__restrict__ rp, const int32_t *__restrict__ list,
                                                        int64_t m, const int32_t *__restrict__ offs, int64_t nblocks,
                                                        int32_t *out) {
-    __shared__ int run[kGroupClasses];
-    __shared__ int wc[4][kGroupClasses];
+    __shared__ int run[kLdsClasses];
+    __shared__ int wc[4][kLdsClasses];
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-    if (t < kGroupClasses) run[t] = offs[t * nblocks + blockIdx.x];
+    if (t < kLdsClasses) run[t] = offs[t * nblocks + blockIdx.x];
     __syncthreads();
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t base = (int64_t)blockIdx.x * kClassTile;
@@ -950,7 +744,7 @@ __global__ __launch_bounds__(256) void k_class_scatter(const int64_t *__restrict
         }
         int rank = 0;
 #pragma unroll
-        for (int cc = 0; cc < kGroupClasses; ++cc) {
+        for (int cc = 0; cc < kLdsClasses; ++cc) {
             const unsigned long long msk = __ballot(c == cc);
             if (c == cc) rank = __popcll(msk & lt);
             if (lane == 0) wc[wid][cc] = __popcll(msk);
@@ -962,7 +756,7 @@ __global__ __launch_bounds__(256) void k_class_scatter(const int64_t *__restrict
             out[pos] = v;
         }
         __syncthreads();
-        if (t < kGroupClasses) run[t] += wc[0][t] + wc[1][t] + wc[2][t] + wc[3][t];
+        if (t < kLdsClasses) run[t] += wc[0][t] + wc[1][t] + wc[2][t] + wc[3][t];
         __syncthreads();
     }
 }
@@ -1174,14 +968,14 @@ __global__ __launch_bounds__(256) void k_cpt_hub_decide(CArgs a, CHub hm, const 
 
 void compact_classes(const int64_t *rp, const int32_t *list, int64_t m, int32_t *out, int64_t *cstart,
                      int64_t *cnnz, hipStream_t s, Timer *t) {
-    for (int c = 0; c <= kGroupClasses; ++c) cstart[c] = 0;
-    for (int c = 0; c < kGroupClasses; ++c) cnnz[c] = 0;
+    for (int c = 0; c <= kLdsClasses; ++c) cstart[c] = 0;
+    for (int c = 0; c < kLdsClasses; ++c) cnnz[c] = 0;
     if (m <= 0) return;
     const int64_t nblk = (m + kClassTile - 1) / kClassTile;
-    const int64_t cm = kGroupClasses * nblk;
+    const int64_t cm = kLdsClasses * nblk;
     TempBuf counts((size_t)(cm + 1) * sizeof(int32_t), s);
-    TempBuf enz(kGroupClasses * sizeof(unsigned long long), s);
-    fill<uint64_t>(enz.as<uint64_t>(), 0, kGroupClasses, s);
+    TempBuf enz(kLdsClasses * sizeof(unsigned long long), s);
+    fill<uint64_t>(enz.as<uint64_t>(), 0, kLdsClasses, s);
     {
         TimedLaunch tl(t, TG_LEVEL, "k_class_count", (double)m * 20);
         k_class_count<<<(unsigned)nblk, 256, 0, s>>>(rp, list, m, counts.as<int32_t>(), nblk,
@@ -1194,18 +988,18 @@ void compact_classes(const int64_t *rp, const int32_t *list, int64_t m, int32_t 
         k_class_scatter<<<(unsigned)nblk, 256, 0, s>>>(rp, list, m, counts.as<int32_t>(), nblk, out);
         LV_LAUNCHED("k_class_scatter");
     }
-    int32_t hs[kGroupClasses];
-    for (int c = 0; c < kGroupClasses; ++c)
+    int32_t hs[kLdsClasses];
+    for (int c = 0; c < kLdsClasses; ++c)
         LV_HIP(hipMemcpyAsync(&hs[c], counts.as<int32_t>() + (int64_t)c * nblk, sizeof(int32_t), hipMemcpyDeviceToHost,
                               s));
-    unsigned long long hn[kGroupClasses];
+    unsigned long long hn[kLdsClasses];
     LV_HIP(hipMemcpyAsync(hn, enz.p, sizeof hn, hipMemcpyDeviceToHost, s));
     LV_HIP(hipStreamSynchronize(s));
-    for (int c = 0; c < kGroupClasses; ++c) {
+    for (int c = 0; c < kLdsClasses; ++c) {
         cstart[c] = hs[c];
         cnnz[c] = (int64_t)hn[c];
     }
-    cstart[kGroupClasses] = m;
+    cstart[kLdsClasses] = m;
 }
 
 void compact_init_singletons(int32_t *c0, int32_t *c1, int32_t *c2, const int64_t *delta, uint64_t *ds, uint32_t *es,
@@ -1270,11 +1064,22 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
             LV_LAUNCHED("k_cpt_groups");
         }
     }
-    const int64_t nw = cp.bstart[B_HUB] - cp.bstart[B_BLOCK];
-    if (nw > 0) {
-        TimedLaunch tl(t, TG_SWEEP, "k_cpt_group<2048,256,", bytes(B_BLOCK, B_HUB), sfx.c_str());
-        k_cpt_group<2048, 256, W><<<(unsigned)nw, 256, 0, s>>>(a, cp.list + cp.bstart[B_BLOCK], nw);
-        LV_LAUNCHED("k_cpt_group<wide>");
+    {
+        const int c = kGroupClasses;
+        const int64_t nw = cp.cstart[c + 1] - cp.cstart[c];
+        if (nw > 0) {
+            TimedLaunch tl(t, TG_SWEEP, "k_cpt_group<2048,256,", (double)nw * vb + (double)cp.cnnz[c] * eb,
+                           sfx.c_str());
+            k_cpt_group<2048, 256, W><<<(unsigned)nw, 256, 0, s>>>(a, cp.glist + cp.cstart[c], nw);
+            LV_LAUNCHED("k_cpt_group<2048>");
+        }
+        const int64_t nx = cp.cstart[c + 2] - cp.cstart[c + 1];
+        if (nx > 0) {
+            TimedLaunch tl(t, TG_SWEEP, "k_cpt_group<4096,256,", (double)nx * vb + (double)cp.cnnz[c + 1] * eb,
+                           sfx.c_str());
+            k_cpt_group<4096, 256, W><<<(unsigned)nx, 256, 0, s>>>(a, cp.glist + cp.cstart[c + 1], nx);
+            LV_LAUNCHED("k_cpt_group<4096>");
+        }
     }
     if (cp.hubs > 0) {
         CHub hm{cp.list + cp.bstart[B_HUB], cp.tab_off, cp.chunk_off, cp.scan_off, cp.tab_size,
