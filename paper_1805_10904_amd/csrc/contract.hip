@@ -260,8 +260,10 @@ static int bits_for(int64_t k) {
 
 constexpr int kSegTile = 512;     // vertices per workgroup in the grouping kernels
 constexpr int kSegBits = 11;      // their LDS tables: 2^11 slots for at most 512 keys
-constexpr int kChunk = 1024;      // grouped entries per aggregation workgroup
-constexpr int kChunkBits = 11;    // its LDS hash table: 2^11 slots
+constexpr int kChunk = 1024;      // grouped entries per aggregation workgroup (nominal)
+constexpr int kChunkSnap = 256;   // a chunk starts at the first segment start within this many entries
+constexpr int kChunkMax = kChunk + kChunkSnap;
+constexpr int kChunkBits = 11;    // its LDS hash table: 2^11 slots (load <= 0.625)
 constexpr unsigned long long kNoKey = ~0ull;
 
 __device__ __forceinline__ int lds_slot(int32_t *key, int32_t k) {
@@ -366,15 +368,17 @@ __global__ __launch_bounds__(256) void k_seg_scatter(const int64_t *__restrict__
     }
 }
 
-// Inclusive max-scan of s[0, kChunk) in place (256 threads, 4 items each).
+// Inclusive max-scan of s[0, kChunkMax) in place (256 threads, R items each).
 __device__ __forceinline__ void block_max_scan_chunk(int32_t *s, int32_t *s_wave) {
+    constexpr int R = kChunkMax / 256;
+    static_assert(kChunkMax % 256 == 0, "scan tiling");
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-    int32_t v[4];
+    int32_t v[R];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = s[4 * t + i];
+    for (int i = 0; i < R; ++i) v[i] = s[R * t + i];
 #pragma unroll
-    for (int i = 1; i < 4; ++i) v[i] = v[i] > v[i - 1] ? v[i] : v[i - 1];
-    int32_t x = v[3];
+    for (int i = 1; i < R; ++i) v[i] = v[i] > v[i - 1] ? v[i] : v[i - 1];
+    int32_t x = v[R - 1];
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
         const int32_t y = __shfl_up(x, off);
@@ -386,8 +390,21 @@ __device__ __forceinline__ void block_max_scan_chunk(int32_t *s, int32_t *s_wave
     if (lane == 0) before = INT32_MIN;
     for (int w2 = 0; w2 < wid; ++w2) before = s_wave[w2] > before ? s_wave[w2] : before;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) s[4 * t + i] = v[i] > before ? v[i] : before;
+    for (int i = 0; i < R; ++i) s[R * t + i] = v[i] > before ? v[i] : before;
     __syncthreads();
+}
+
+// Start of chunk b: b * kChunk moved forward to the first segment start
+// within kChunkSnap entries, if there is one, so that segments shorter than
+// kChunkSnap rarely cross a chunk boundary.  Called by one full wavefront.
+__device__ __forceinline__ int64_t chunk_start(const int64_t *__restrict__ off, int64_t k, int64_t m_raw, int64_t b) {
+    const int64_t x = b * kChunk;
+    if (x <= 0) return 0;
+    if (x >= m_raw) return m_raw;
+    const int64_t s = wave_find_le(off, k, x);   // segment holding entry x
+    if (off[s] == x) return x;
+    const int64_t nxt = off[s + 1];              // the next segment start (off[k] = m_raw)
+    return nxt - x <= kChunkSnap ? nxt : x;
 }
 
 // Shared first half of the chunk kernels: the chunk's first and last
@@ -404,7 +421,7 @@ __device__ __forceinline__ void chunk_aggregate(const int64_t *__restrict__ off,
         s_hk[x] = kNoKey;
         s_hv[x] = 0;
     }
-    for (int x = t; x < kChunk; x += 256) s_mark[x] = -1;
+    for (int x = t; x < kChunkMax; x += 256) s_mark[x] = -1;
     if (t < 64) {   // segments of the chunk's first and last entry (64-way search)
         const int64_t a0 = wave_find_le(off, k, cb);
         const int64_t a1 = wave_find_le(off, k, cb + len - 1);
@@ -448,20 +465,30 @@ __global__ __launch_bounds__(256) void k_seg_chunk_any(const int64_t *__restrict
     constexpr int T = 1 << kChunkBits;
     __shared__ unsigned long long s_hk[T];
     __shared__ long long s_hv[T];
-    __shared__ int32_t s_mark[kChunk];
-    __shared__ int32_t s_cnt[kChunk];   // pairs per segment, at the segment's first position
-    __shared__ int32_t s_cur[kChunk];
+    __shared__ int32_t s_mark[kChunkMax];
+    __shared__ int32_t s_cnt[kChunkMax];   // pairs per segment, at the segment's first position
+    __shared__ int32_t s_cur[kChunkMax];
     __shared__ int32_t s_wave[4];
     __shared__ int64_t s_range[2];
+    __shared__ int64_t s_bounds[2];
     __shared__ unsigned long long s_pbase;
     const int t = threadIdx.x;
-    const int64_t cb = (int64_t)blockIdx.x * kChunk;
-    const int64_t ce = cb + kChunk < m_raw ? cb + kChunk : m_raw;
-    const int len = (int)(ce - cb);
-    for (int x = t; x < kChunk; x += 256) {
+    if (t < 64) {
+        const int64_t b0 = chunk_start(off, k, m_raw, blockIdx.x);
+        const int64_t b1 = chunk_start(off, k, m_raw, (int64_t)blockIdx.x + 1);
+        if (t == 0) {
+            s_bounds[0] = b0;
+            s_bounds[1] = b1;
+        }
+    }
+    for (int x = t; x < kChunkMax; x += 256) {
         s_cnt[x] = 0;
         s_cur[x] = 0;
     }
+    __syncthreads();
+    const int64_t cb = s_bounds[0], ce = s_bounds[1];
+    const int len = (int)(ce - cb);
+    if (len <= 0) return;   // uniform: every segment around here was taken by a neighbour
     chunk_aggregate(off, k, cb, len, tcol, tw, s_hk, s_hv, s_mark, s_wave, s_range);
     const int64_t slo = s_range[0], shi = s_range[1];
     const bool first_spans = off[slo] < cb;
@@ -527,21 +554,29 @@ __global__ __launch_bounds__(256) void k_seg_chunk(const int64_t *__restrict__ o
     constexpr int T = 1 << kChunkBits;
     __shared__ unsigned long long s_hk[T];
     __shared__ long long s_hv[T];
-    __shared__ unsigned long long s_sk[kChunk];
-    __shared__ long long s_sv[kChunk];
-    __shared__ int32_t s_mark[kChunk];
+    __shared__ unsigned long long s_sk[2 * kChunk];   // sorted pairs (padded to a power of two)
+    __shared__ long long s_sv[2 * kChunk];
+    __shared__ int32_t s_mark[kChunkMax];
     __shared__ int32_t s_wave[4];
     __shared__ int s_nd;
     __shared__ int64_t s_range[2];
+    __shared__ int64_t s_bounds[2];
     __shared__ unsigned long long s_pbase;
     const int t = threadIdx.x;
-    const int64_t cb = (int64_t)blockIdx.x * kChunk;
-    const int64_t ce = cb + kChunk < m_raw ? cb + kChunk : m_raw;
-    const int len = (int)(ce - cb);
-    if (t == 0) {
-        s_nd = 0;
-        s_pbase = 0;
+    if (t < 64) {
+        const int64_t b0 = chunk_start(off, k, m_raw, blockIdx.x);
+        const int64_t b1 = chunk_start(off, k, m_raw, (int64_t)blockIdx.x + 1);
+        if (t == 0) {
+            s_bounds[0] = b0;
+            s_bounds[1] = b1;
+            s_nd = 0;
+            s_pbase = 0;
+        }
     }
+    __syncthreads();
+    const int64_t cb = s_bounds[0], ce = s_bounds[1];
+    const int len = (int)(ce - cb);
+    if (len <= 0) return;
     chunk_aggregate(off, k, cb, len, tcol, tw, s_hk, s_hv, s_mark, s_wave, s_range);
     const int64_t slo = s_range[0], shi = s_range[1];
     {   // compaction of the occupied slots: one LDS atomic per wavefront and round
