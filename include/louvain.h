@@ -246,6 +246,38 @@ int louvain_run_batch(louvain_ctx ctx, int64_t ngraphs, const louvain_graph *gra
                       louvain_i128 *q_int, double *q, int32_t *status,
                       louvain_run_stats *stats, uint32_t flags);
 
+/* ---- launch shapes -------------------------------------------------------- */
+
+/* Launch-shape settings of levels whose 2W is below 2^31.  They change which
+ * kernel sweeps which rows, never the results (every setting gives the same
+ * labels, Q and level records). */
+typedef struct {
+    int32_t small_max;   /* rows of at most this many entries are swept one thread per
+                            vertex (1..8; default 8)                                     */
+    int32_t block_max;   /* longest row swept from an LDS table; longer rows use HBM hub
+                            tables (341..2730; default 2730)                             */
+    int32_t pass_batch;  /* sweep passes between host checks when the run's params say 0
+                            (1..64; default 1)                                           */
+    int32_t reserved;
+    double ms;           /* louvain_autotune: device time of one run with this setting */
+} louvain_tuning;
+
+/* Set (NULL = defaults) or read the context's launch shapes; they apply to
+ * later louvain_run / louvain_run_batch calls and to a request loop started
+ * afterwards.  Returns LOUVAIN_EINVAL for values out of range. */
+int louvain_set_tuning(louvain_ctx ctx, const louvain_tuning *tuning);
+int louvain_get_tuning(louvain_ctx ctx, louvain_tuning *tuning);
+
+/*
+ * Autotuner: times one whole run of the method on g (params as for
+ * louvain_run) under each candidate setting (small_max in {4, 8},
+ * block_max in {1024, 1365, 2730}, pass_batch in {1, 2}), best of two runs
+ * each, and makes the fastest the context's setting.  *best (optional)
+ * receives it with its time.  Graphs with 2W >= 2^31 do not use these
+ * shapes; the setting is left as it is and best->ms is -1.
+ */
+int louvain_autotune(louvain_ctx ctx, louvain_graph g, const louvain_params *params, louvain_tuning *best);
+
 /* ---- served form --------------------------------------------------------- */
 
 /* Result of one served request (louvain_poll). */

@@ -28,6 +28,7 @@ ABI_SYMBOLS = (
     "louvain_graph_create", "louvain_graph_destroy", "louvain_graph_info", "louvain_graph_export",
     "louvain_local_move", "louvain_modularity", "louvain_aggregate", "louvain_run", "louvain_run_batch",
     "louvain_workspace_bytes", "louvain_serve_budget", "louvain_submit", "louvain_poll",
+    "louvain_set_tuning", "louvain_get_tuning", "louvain_autotune",
 )
 
 
@@ -59,6 +60,11 @@ class louvain_request_result(C.Structure):
                 ("total_edges_swept", C.c_int64), ("q_int", louvain_i128), ("q", C.c_double),
                 ("t_submit_us", C.c_double), ("t_admit_us", C.c_double), ("t_done_us", C.c_double),
                 ("level", louvain_level_stats * 64), ("error", C.c_char * 128)]
+
+
+class louvain_tuning(C.Structure):
+    _fields_ = [("small_max", C.c_int32), ("block_max", C.c_int32), ("pass_batch", C.c_int32),
+                ("reserved", C.c_int32), ("ms", C.c_double)]
 
 
 class louvain_run_stats(C.Structure):
@@ -101,6 +107,9 @@ def load_library(path: str = LIB_PATH):
     lib.louvain_run.argtypes = [p, p, C.POINTER(louvain_params), p, C.POINTER(louvain_i128), p,
                                 C.POINTER(louvain_run_stats), u32]
     lib.louvain_run_batch.argtypes = [p, i64, p, C.POINTER(louvain_params), p, p, p, p, p, u32]
+    lib.louvain_set_tuning.argtypes = [p, C.POINTER(louvain_tuning)]
+    lib.louvain_get_tuning.argtypes = [p, C.POINTER(louvain_tuning)]
+    lib.louvain_autotune.argtypes = [p, p, C.POINTER(louvain_params), C.POINTER(louvain_tuning)]
     lib.louvain_workspace_bytes.argtypes = [i64, i64]
     lib.louvain_workspace_bytes.restype = C.c_size_t
     lib.louvain_serve_budget.argtypes = [p, C.c_size_t]
@@ -275,6 +284,24 @@ class Context:
         self._check(self.lib.louvain_graph_create(self.h, n, nnz, _ptr(keep[0]), _ptr(keep[1]),
                                                   _ptr(keep[2]), flags, C.byref(h)))
         return Graph(self, h, dev)
+
+    def set_tuning(self, small_max: int = 8, block_max: int = 2730, pass_batch: int = 1):
+        """Launch shapes of compact levels (results do not depend on them)."""
+        t = louvain_tuning(small_max, block_max, pass_batch, 0, 0.0)
+        self._check(self.lib.louvain_set_tuning(self.h, C.byref(t)))
+
+    def get_tuning(self) -> dict:
+        t = louvain_tuning()
+        self._check(self.lib.louvain_get_tuning(self.h, C.byref(t)))
+        return dict(small_max=t.small_max, block_max=t.block_max, pass_batch=t.pass_batch)
+
+    def autotune(self, g: "Graph", theta_num: int = 1, theta_den: int = 1_000_000, max_sweeps: int = 1000,
+                 max_levels: int = 64, singlet_rule: bool = True) -> dict:
+        """Time whole runs of g under the candidate launch shapes; the fastest becomes the context's."""
+        prm = louvain_params(theta_num, theta_den, max_sweeps, max_levels, 1 if singlet_rule else 0, 0)
+        t = louvain_tuning()
+        self._check(self.lib.louvain_autotune(self.h, g.h, C.byref(prm), C.byref(t)))
+        return dict(small_max=t.small_max, block_max=t.block_max, pass_batch=t.pass_batch, ms=t.ms)
 
     def serve_budget(self, nbytes: int):
         """Device-memory budget of the request loop (0: 80% of free memory at start)."""

@@ -1,4 +1,5 @@
 // The C ABI (include/louvain.h): contexts, graphs, and the method's calls.
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 #include <memory>
@@ -18,6 +19,7 @@ struct louvain_ctx_s {
     hipStream_t stream = nullptr;
     std::string err;
     lv::Timer timer;
+    lv::Tuning tuning;                    // launch shapes of compact levels
     std::mutex serve_mu;                  // guards server creation and serve_budget
     size_t serve_budget = 0;              // 0: a share of the device's free memory
     std::unique_ptr<lv::Server> server;   // request loop, started by the first submit
@@ -212,10 +214,10 @@ namespace lv {
 
 // Alg. 2 on one graph: phases of sweeps, renumbering and contraction until a
 // phase keeps no sweep.  fin_p (device int32[n]) receives the final labels.
-int run_plain(const GraphView &g0, const louvain_params &prm, hipStream_t s, Timer &timer, int timing, int32_t *fin_p,
-              i128 *q_out, louvain_run_stats *stats_out) {
+int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, hipStream_t s, Timer &timer,
+              int timing, int32_t *fin_p, i128 *q_out, louvain_run_stats *stats_out) {
     int status = LOUVAIN_OK;
-    const int batch = prm.pass_batch > 0 ? prm.pass_batch : 1;
+    const int batch = prm.pass_batch > 0 ? prm.pass_batch : tn.pass_batch;
     timer.on = timing != 0;
     if (timing != 2) timer.only.clear();
     timer.reset();
@@ -243,6 +245,7 @@ int run_plain(const GraphView &g0, const louvain_params &prm, hipStream_t s, Tim
     if (g0.tw > 0) {
         lv::Sweeper sw(s, t);
         lv::Contractor ct(s, t);
+        sw.set_tuning(tn);
         sw.reserve(n0, nnz0);
         ct.reserve(n0, nnz0);
         DevBuf<int32_t> newlab((size_t)n0);
@@ -452,6 +455,7 @@ int louvain_local_move(louvain_ctx ctx, louvain_graph g, const int32_t *labels, 
         DevBuf<int32_t> lin;
         if (labels) lin = labels_in(ctx, labels, g->n, flags);
         lv::Sweeper sw(s, t);
+        sw.set_tuning(ctx->tuning);
         sw.reserve(v.n, v.nnz);
         sw.plan(v);
         if (labels) sw.init_from_labels(v, lin.p); else sw.init_singletons(v);
@@ -533,7 +537,7 @@ int louvain_run(louvain_ctx ctx, louvain_graph g, const louvain_params *params, 
         louvain_run_stats local;
         DevBuf<int32_t> fin((size_t)g->n);
         lv::i128 q_final = 0;
-        status = lv::run_plain(g->view(), prm, s, ctx->timer, timing, fin.p, &q_final, &local);
+        status = lv::run_plain(g->view(), prm, ctx->tuning, s, ctx->timer, timing, fin.p, &q_final, &local);
         copy_out(labels_out, fin.p, g->n, device_ptrs(flags), s);
         LV_HIP(hipStreamSynchronize(s));
         if (q_int) *q_int = to_abi(q_final);
@@ -549,6 +553,91 @@ int louvain_run(louvain_ctx ctx, louvain_graph g, const louvain_params *params, 
         ctx->timer.only.clear();
     }
     return rc != LOUVAIN_OK ? rc : status;
+}
+
+int louvain_set_tuning(louvain_ctx ctx, const louvain_tuning *tuning) {
+    return guarded(ctx, [&] {
+        lv::Tuning tn;
+        if (tuning) {
+            require(tuning->small_max >= 1 && tuning->small_max <= 8, LOUVAIN_EINVAL, "small_max must be in [1, 8]");
+            require(tuning->block_max >= lv::kPackMaxDeg && tuning->block_max <= lv::kCompactBlockMax, LOUVAIN_EINVAL,
+                    "block_max must be in [341, 2730]");
+            require(tuning->pass_batch >= 1 && tuning->pass_batch <= 64, LOUVAIN_EINVAL,
+                    "pass_batch must be in [1, 64]");
+            tn.small_max = tuning->small_max;
+            tn.block_max = tuning->block_max;
+            tn.pass_batch = tuning->pass_batch;
+        }
+        ctx->tuning = tn;
+    });
+}
+
+int louvain_get_tuning(louvain_ctx ctx, louvain_tuning *tuning) {
+    if (!ctx || !tuning) return LOUVAIN_EINVAL;
+    memset(tuning, 0, sizeof *tuning);
+    tuning->small_max = ctx->tuning.small_max;
+    tuning->block_max = (int32_t)ctx->tuning.block_max;
+    tuning->pass_batch = ctx->tuning.pass_batch;
+    return LOUVAIN_OK;
+}
+
+int louvain_autotune(louvain_ctx ctx, louvain_graph g, const louvain_params *params, louvain_tuning *best) {
+    return guarded(ctx, [&] {
+        require(g != nullptr && g->ctx == ctx, LOUVAIN_EINVAL, "graph missing or from another context");
+        louvain_params prm = checked_params(params);
+        prm.pass_batch = 0;   // the candidates' pass batching applies
+        if (g->tw >= lv::kCompactTwMax || g->n == 0) {
+            if (best) {
+                louvain_get_tuning(ctx, best);
+                best->ms = -1.0;
+            }
+            return;
+        }
+        hipStream_t s = ctx->stream;
+        DevBuf<int32_t> fin((size_t)g->n);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        struct EvGuard {
+            hipEvent_t *a, *b;
+            ~EvGuard() {
+                if (*a) (void)hipEventDestroy(*a);
+                if (*b) (void)hipEventDestroy(*b);
+            }
+        } evg{&e0, &e1};
+        LV_HIP(hipEventCreate(&e0));
+        LV_HIP(hipEventCreate(&e1));
+        auto time_run = [&](const lv::Tuning &tn) {
+            lv::i128 q;
+            louvain_run_stats st;
+            LV_HIP(hipEventRecord(e0, s));
+            (void)lv::run_plain(g->view(), prm, tn, s, ctx->timer, 0, fin.p, &q, &st);
+            LV_HIP(hipEventRecord(e1, s));
+            LV_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            LV_HIP(hipEventElapsedTime(&ms, e0, e1));
+            return (double)ms;
+        };
+        (void)time_run(ctx->tuning);   // warm-up (allocations, code loading)
+        lv::Tuning pick = ctx->tuning;
+        double pick_ms = 1e30;
+        for (int sm : {4, 8})
+            for (int64_t bm : {(int64_t)1024, (int64_t)1365, lv::kCompactBlockMax})
+                for (int pb : {1, 2}) {
+                    lv::Tuning tn;
+                    tn.small_max = sm;
+                    tn.block_max = bm;
+                    tn.pass_batch = pb;
+                    const double ms = std::min(time_run(tn), time_run(tn));
+                    if (ms < pick_ms) {
+                        pick_ms = ms;
+                        pick = tn;
+                    }
+                }
+        ctx->tuning = pick;
+        if (best) {
+            louvain_get_tuning(ctx, best);
+            best->ms = pick_ms;
+        }
+    });
 }
 
 size_t louvain_workspace_bytes(int64_t n, int64_t nnz) {
@@ -601,7 +690,7 @@ int louvain_submit(louvain_ctx ctx, int64_t n, int64_t nnz, const int64_t *row_p
                     }
                     budget = free_b / 10 * 8;
                 }
-                ctx->server.reset(new lv::Server(ctx->device, budget));
+                ctx->server.reset(new lv::Server(ctx->device, budget, ctx->tuning));
             }
             srv = ctx->server.get();
         }
@@ -721,7 +810,9 @@ int louvain_run_batch(louvain_ctx ctx, int64_t ngraphs, const louvain_graph *gra
         for (int64_t k = 0; k < ne; ++k) off[(size_t)k + 1] = off[(size_t)k] + graphs[eligible[(size_t)k]]->n;
         DevBuf<int32_t> fin((size_t)off[(size_t)ne]);
         std::vector<lv::BatchMember> mem((size_t)ne);
-        lv::BatchEngine eng(s, t, sweep_params(prm), prm.max_levels, prm.pass_batch);
+        lv::BatchEngine eng(s, t, sweep_params(prm), prm.max_levels,
+                            prm.pass_batch > 0 ? prm.pass_batch : ctx->tuning.pass_batch);
+        eng.set_tuning(ctx->tuning);
         for (int64_t k = 0; k < ne; ++k) {
             lv::BatchMember &m = mem[(size_t)k];
             m.g0 = graphs[eligible[(size_t)k]]->view();

@@ -50,6 +50,7 @@ class BatchEngine {
     // has drained; step() synchronises it before returning).
     std::vector<BatchMember *> step();
     bool idle() const { return slots_.empty() && pending_.empty() && finished_.empty(); }
+    void set_tuning(const Tuning &tn) { sw_.set_tuning(tn); }
     size_t resident() const { return slots_.size(); }
     size_t pending() const { return pending_.size(); }
     // Vertices and entries of the union the next step sweeps.

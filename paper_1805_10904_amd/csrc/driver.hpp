@@ -12,7 +12,8 @@ namespace lv {
 // labels, *q_out Q_int of them, *stats_out the run record (kernel times when
 // timing).  Returns LOUVAIN_OK or LOUVAIN_ELIMIT; throws Error.
 // timing: 0 off, 1 every launch, 2 only launches named timer.only.
-int run_plain(const GraphView &g0, const louvain_params &prm, hipStream_t s, Timer &timer, int timing, int32_t *fin_p,
-              i128 *q_out, louvain_run_stats *stats_out);
+// tn: launch shapes of compact levels (prm.pass_batch 0 takes tn.pass_batch).
+int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, hipStream_t s, Timer &timer,
+              int timing, int32_t *fin_p, i128 *q_out, louvain_run_stats *stats_out);
 
 }  // namespace lv

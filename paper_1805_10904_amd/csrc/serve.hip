@@ -95,7 +95,7 @@ size_t Server::workspace_bytes(int64_t n, int64_t nnz) {
     return (size_t)b;
 }
 
-Server::Server(int device, size_t budget) : device_(device), budget_(budget) {
+Server::Server(int device, size_t budget, const Tuning &tn) : device_(device), tuning_(tn), budget_(budget) {
     for (int k = 0; k < 2; ++k) workers_.emplace_back(new Worker());
     for (auto &w : workers_) {
         Worker *wp = w.get();
@@ -243,7 +243,7 @@ void Server::loop(Worker *w) {
                 if (r->tw >= kCompactTwMax) {
                     // too heavy for the batch's compact words: the plain path, alone
                     louvain_run_stats st;
-                    r->status = run_plain(r->member.g0, r->prm, s, timer, 0, r->d_fin.p, &r->q, &st);
+                    r->status = run_plain(r->member.g0, r->prm, tuning_, s, timer, 0, r->d_fin.p, &r->q, &st);
                     for (int l = 0; l < st.levels; ++l) {
                         LevelRec rec;
                         rec.n = st.level[l].n;
@@ -265,8 +265,10 @@ void Server::loop(Worker *w) {
                 if (!lane) {
                     lanes.emplace_back(new Lane{r->prm, std::unique_ptr<BatchEngine>(new BatchEngine(
                                                     s, nullptr, to_sweep(r->prm), r->prm.max_levels,
-                                                    r->prm.pass_batch)), {}});
+                                                    r->prm.pass_batch > 0 ? r->prm.pass_batch : tuning_.pass_batch)),
+                                                {}});
                     lane = lanes.back().get();
+                    lane->eng->set_tuning(tuning_);
                 }
                 lane->eng->admit(&r->member);
                 lane->members.push_back(r);
@@ -299,7 +301,8 @@ void Server::loop(Worker *w) {
                 for (ServeRequest *r : lane.members) fail(r, e.code, e.what());
                 lane.members.clear();
                 lane.eng.reset(new BatchEngine(s, nullptr, to_sweep(lane.prm), lane.prm.max_levels,
-                                               lane.prm.pass_batch));
+                                               lane.prm.pass_batch > 0 ? lane.prm.pass_batch : tuning_.pass_batch));
+                lane.eng->set_tuning(tuning_);
                 continue;
             }
             for (BatchMember *m : fin) {

@@ -53,7 +53,7 @@ struct ServeRequest {
 
 class Server {
   public:
-    Server(int device, size_t budget);
+    Server(int device, size_t budget, const Tuning &tn);
     ~Server();
     // Queue a request (thread-safe); returns its ticket.
     uint64_t submit(std::unique_ptr<ServeRequest> r);
@@ -80,6 +80,7 @@ class Server {
     void finish(ServeRequest *r);
 
     int device_;
+    Tuning tuning_;
     std::mutex mu_;
     std::condition_variable cv_work_, cv_done_;
     std::unordered_map<uint64_t, std::unique_ptr<ServeRequest>> all_;

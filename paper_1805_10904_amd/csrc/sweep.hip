@@ -862,12 +862,14 @@ __global__ void k_init_labels(int32_t *c0, int32_t *c1, int32_t *c2, const int32
 
 constexpr int kBucketTile = 2048;  // vertices per bucketing block (256 x 8)
 
-// block_max: the longest row of the workgroup-per-vertex bucket (the hub
-// path takes longer ones).
-__device__ __forceinline__ int bucket_of(int64_t d, int64_t block_max) {
+// small_max: the longest row of the thread-per-vertex bucket; block_max: the
+// longest row of the workgroup-per-vertex bucket (the hub path takes longer
+// ones).
+__device__ __forceinline__ int bucket_of(int64_t d, int small_max, int64_t block_max) {
     if (d <= 0) return -1;
+    if (d <= small_max) return B_T8;
 #pragma unroll
-    for (int b = 0; b < B_BLOCK; ++b)
+    for (int b = B_T16; b < B_BLOCK; ++b)
         if (d <= kBucketMax[b]) return b;
     return d <= block_max ? B_BLOCK : B_HUB;
 }
@@ -876,17 +878,18 @@ __device__ __forceinline__ int bucket_of(int64_t d, int64_t block_max) {
 // phase is over when gid and st are given).
 __device__ __forceinline__ int bucket_of_vertex(const int64_t *__restrict__ rp, const int32_t *__restrict__ gid,
                                                 const PhaseState *__restrict__ st, int64_t v, int64_t *deg,
-                                                int64_t block_max) {
+                                                int small_max, int64_t block_max) {
     const int64_t d = rp[v + 1] - rp[v];
     *deg = d;
     if (gid && st[gid[v]].done) return -1;
-    return bucket_of(d, block_max);
+    return bucket_of(d, small_max, block_max);
 }
 
 __global__ __launch_bounds__(256) void k_bucket_count(const int64_t *__restrict__ rp, int64_t n, int32_t *counts,
                                                       int64_t nblocks, unsigned long long *bucket_nnz,
                                                       const int32_t *__restrict__ gid,
-                                                      const PhaseState *__restrict__ st, int64_t block_max) {
+                                                      const PhaseState *__restrict__ st, int small_max,
+                                                      int64_t block_max) {
     __shared__ int cnt[NBUCKET];
     __shared__ unsigned long long ecnt[NBUCKET];
     if (threadIdx.x < NBUCKET) {
@@ -900,7 +903,7 @@ __global__ __launch_bounds__(256) void k_bucket_count(const int64_t *__restrict_
         const int64_t v = base + k * 256 + threadIdx.x;
         if (v < n) {
             int64_t d;
-            const int b = bucket_of_vertex(rp, gid, st, v, &d, block_max);
+            const int b = bucket_of_vertex(rp, gid, st, v, &d, small_max, block_max);
             if (b >= 0) {
                 atomicAdd(&cnt[b], 1);
                 atomicAdd(&ecnt[b], (unsigned long long)d);
@@ -919,7 +922,8 @@ __global__ __launch_bounds__(256) void k_bucket_count(const int64_t *__restrict_
 __global__ __launch_bounds__(256) void k_bucket_scatter(const int64_t *__restrict__ rp, int64_t n,
                                                         const int32_t *__restrict__ offs, int64_t nblocks,
                                                         int32_t *list, const int32_t *__restrict__ gid,
-                                                        const PhaseState *__restrict__ st, int64_t block_max) {
+                                                        const PhaseState *__restrict__ st, int small_max,
+                                                        int64_t block_max) {
     __shared__ int run[NBUCKET];
     __shared__ int wc[4][NBUCKET];
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
@@ -930,7 +934,7 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(const int64_t *__restric
     for (int k = 0; k < kBucketTile / 256; ++k) {
         const int64_t v = base + k * 256 + t;
         int64_t d;
-        const int b = v < n ? bucket_of_vertex(rp, gid, st, v, &d, block_max) : -1;
+        const int b = v < n ? bucket_of_vertex(rp, gid, st, v, &d, small_max, block_max) : -1;
         int rank = 0;
 #pragma unroll
         for (int bb = 0; bb < NBUCKET; ++bb) {
@@ -987,7 +991,10 @@ void Sweeper::reserve(int64_t n, int64_t nnz) {
     bcount_.alloc((size_t)(NBUCKET * nblk + 1));
     st_.alloc(1);
     qpart_.alloc((size_t)(2 * ((n + kQsumTile - 1) / kQsumTile) + 2));
-    const int64_t max_hubs = nnz / (kBucketMax[NBUCKET - 2] + 1) + 1;
+    // hubs are rows longer than the workgroup bucket's limit, at least
+    // kPackMaxDeg + 1 entries whatever the tuning
+    const int64_t max_hubs = nnz / (kPackMaxDeg + 1) + 1;
+    hub_cap_ = max_hubs;
     hub_meta_.alloc((size_t)(4 * (max_hubs + 1)));
     pack_pos_.alloc((size_t)n + 1);
     hub_loop_.alloc((size_t)max_hubs);
@@ -1008,10 +1015,11 @@ void Sweeper::replan_active(const GraphView &g) { plan_impl(g, true); }
 
 void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     n_ = g.n;
-    const int64_t block_max = compact_ ? kCompactBlockMax : kBucketMax[B_BLOCK];
+    compact_ = batch_ || g.tw < kCompactTwMax;   // before anything that depends on the level's kind
+    const int small_max = compact_ ? tuning_.small_max : (int)kBucketMax[B_T8];
+    const int64_t block_max = compact_ ? tuning_.block_max : kBucketMax[B_BLOCK];
     const int32_t *skip_gid = active_only && batch_ ? gid_ : nullptr;
     const PhaseState *skip_st = active_only && batch_ ? st_.p : nullptr;
-    compact_ = batch_ || g.tw < kCompactTwMax;
     if (!batch_) {
         ngraphs_ = 1;
         gid_ = nullptr;
@@ -1033,7 +1041,7 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     {
         TimedLaunch tl(t_, TG_LEVEL, "k_bucket_count", (double)g.n * 16);
         k_bucket_count<<<(unsigned)nblk, 256, 0, s_>>>(g.row_ptr, g.n, counts, nblk, bnnz.as<unsigned long long>(),
-                                                       skip_gid, skip_st, block_max);
+                                                       skip_gid, skip_st, small_max, block_max);
         LV_LAUNCHED("k_bucket_count");
     }
     const int64_t m = NBUCKET * nblk;
@@ -1041,7 +1049,7 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     {
         TimedLaunch tl(t_, TG_LEVEL, "k_bucket_scatter", (double)g.n * 20);
         k_bucket_scatter<<<(unsigned)nblk, 256, 0, s_>>>(g.row_ptr, g.n, counts, nblk, list_.p, skip_gid, skip_st,
-                                                         block_max);
+                                                         small_max, block_max);
         LV_LAUNCHED("k_bucket_scatter");
     }
     int32_t hs[NBUCKET + 1];
@@ -1056,7 +1064,7 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     // line positions of the packed vertices (buckets B_T16 to B_MID, contiguous in the list)
     pack_count_ = bstart_[B_BLOCK] - bstart_[B_T16];
     if (compact_) {
-        // every row swept from LDS (9 .. kCompactBlockMax entries), by table size
+        // every row swept from LDS (small_max + 1 .. block_max entries), by table size
         const int64_t nl = bstart_[B_HUB] - bstart_[B_T16];
         glist_.reserve((size_t)(nl > 0 ? nl : 1));
         compact_classes(g.row_ptr, list_.p + bstart_[B_T16], nl, glist_.p, cstart_, cnnz_, s_, t_);
@@ -1078,6 +1086,7 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     }
     hubs_ = bucket_count(B_HUB);
     if (hubs_ == 0) return;
+    require(hubs_ <= hub_cap_, LOUVAIN_EDEVICE, "hub count exceeds the reserved hub tables");
     int64_t *tab_off = hub_meta_.p, *chunk_off = tab_off + (hubs_ + 1), *scan_off = chunk_off + (hubs_ + 1),
             *tab_size = scan_off + (hubs_ + 1);
     const int32_t *hubv = list_.p + bstart_[B_HUB];
@@ -1244,6 +1253,7 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
         cp.pack_first = pack_first_.p;
         cp.pack_blocks = pack_blocks_;
         cp.glist = glist_.p;
+        cp.small_max = tuning_.small_max;
         for (int c = 0; c <= kLdsClasses; ++c) cp.cstart[c] = cstart_[c];
         for (int c = 0; c < kLdsClasses; ++c) cp.cnnz[c] = cnnz_[c];
         cp.hubs = hubs_;

@@ -57,6 +57,14 @@ constexpr int64_t kPackMaxDeg = 341;
 constexpr int kGroupClasses = 6;
 constexpr int kLdsClasses = kGroupClasses + 2;
 constexpr int64_t kCompactBlockMax = 2730;
+
+// Launch-shape settings of compact levels (chosen by the autotuner or the
+// caller; every setting gives the same results).
+struct Tuning {
+    int small_max = 8;                  // rows of at most this many entries: one thread per vertex (1..8)
+    int64_t block_max = kCompactBlockMax;   // longest row swept from LDS; longer rows: HBM hub tables
+    int pass_batch = 1;                 // sweep passes between host checks
+};
 // log2 of the LDS hash table size of a packed row of d >= 1 entries: the
 // smallest b >= 1 with 2^b >= ceil(3d/2) (load at most 2/3).
 __device__ __forceinline__ int pack_table_bits(int64_t d) {
@@ -77,6 +85,7 @@ struct CompactPass {
     const int32_t *glist = nullptr;            // rows swept from LDS, by class
     int64_t cstart[kLdsClasses + 1] = {0};     // class c: glist[cstart[c], cstart[c+1])
     int64_t cnnz[kLdsClasses] = {0};
+    int small_max = 8;                         // rows swept one thread per vertex
     int64_t hubs = 0, hub_chunks = 0, hub_scans = 0;
     const int64_t *tab_off = nullptr, *chunk_off = nullptr, *scan_off = nullptr, *tab_size = nullptr;
     const int32_t *chunk_hub = nullptr, *scan_hub = nullptr;
@@ -139,6 +148,8 @@ class Sweeper {
     // Batch, inside a phase: the same plan restricted to graphs whose phase
     // is still running (labels and phase state are kept).
     void replan_active(const GraphView &g);
+    // Row-length thresholds of compact levels (before plan).
+    void set_tuning(const Tuning &tn) { tuning_ = tn; }
     // Singleton communities (a2): every ring slot = identity, deg = delta, size = 1.
     void init_singletons(const GraphView &g);
     // Communities from labels (device int32[n]): ring slots = labels, deg/size recomputed.
@@ -168,6 +179,7 @@ class Sweeper {
 
   private:
     void plan_impl(const GraphView &g, bool active_only);
+    Tuning tuning_;
     hipStream_t s_;
     Timer *t_;
     int64_t cap_n_ = -1, cap_nnz_ = -1;
@@ -206,6 +218,7 @@ class Sweeper {
     int64_t bucket_nnz_[NBUCKET] = {0};
     int64_t hubs_ = 0, hub_chunks_ = 0, hub_scans_ = 0, hub_slots_ = 0;
     int64_t hub_slot_cap_ = 0;
+    int64_t hub_cap_ = 0;           // hubs the hub metadata arrays hold
     int64_t qblocks_ = 0;
     int64_t n_ = 0;
 };

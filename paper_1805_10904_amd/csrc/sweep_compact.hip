@@ -325,19 +325,20 @@ __global__ void k_cpt_finalize(PhaseState *st, const int64_t *__restrict__ tw, i
     if (!s.done) atomicAdd(active, 1u);
 }
 
-// ------------------------------------------------------ rows of <= 8 entries --
+// ---------------------------------------------- rows of <= small_max entries --
 
 // One thread per vertex in vertex-ID order (coalesced per-vertex accesses);
-// threads whose row is empty or longer than 8 entries do nothing.  The row
+// threads whose row is empty or longer than small_max (<= 8) entries do nothing.  The row
 // is held in registers and equal labels are merged by pairwise compares.
 template <typename W>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_cpt_small(CArgs a, int64_t n) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_cpt_small(CArgs a, int64_t n,
+                                                                                          int small_max) {
     constexpr int MAXD = 8;
     const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (v >= n) return;
     const int64_t rs = a.row_ptr[v];
     const int d = (int)(a.row_ptr[v + 1] - rs);
-    if (d < 1 || d > MAXD) return;
+    if (d < 1 || d > small_max) return;   // small_max <= MAXD
     const int g = graph_of(a.gid, v);
     if (a.st[g].done) return;
     const int64_t tw = a.tw[g];
@@ -1044,7 +1045,7 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
     };
     if (cp.bstart[B_T16] - cp.bstart[B_T8] > 0) {
         TimedLaunch tl(t, TG_SWEEP, "k_cpt_small<", bytes(B_T8, B_T16), sfx.c_str());
-        k_cpt_small<W><<<grid_for(cp.n, 256), 256, 0, s>>>(a, cp.n);
+        k_cpt_small<W><<<grid_for(cp.n, 256), 256, 0, s>>>(a, cp.n, cp.small_max);
         LV_LAUNCHED("k_cpt_small");
     }
     {

@@ -274,3 +274,48 @@ def test_errors_leave_outputs_untouched(ctx, L):
     with pytest.raises(L.LouvainError):
         ctx.modularity(G, np.array([0, -1, 2, 3], np.int32))
     G.destroy()
+
+
+# --------------------------------------------------------- launch shapes --
+
+def test_launch_shapes_do_not_change_results(ctx):
+    """Every row-length threshold and pass batching gives the oracle's result
+    (rows move between the thread, LDS and HBM hub kernels)."""
+    graphs = [gg.config("chunglu_n20000"), hub_graph(), gg.config("rmat_s14")]
+    refs = [oracle.louvain(g.row_ptr, g.col, g.w) for g in graphs]
+    Gs = [ctx.graph_create(g.row_ptr, g.col, g.w) for g in graphs]
+    try:
+        for sm, bm, pb in [(1, 341, 1), (4, 1024, 2), (8, 1365, 1), (2, 2730, 3)]:
+            ctx.set_tuning(sm, bm, pb)
+            assert ctx.get_tuning() == dict(small_max=sm, block_max=bm, pass_batch=pb)
+            for k, (G, ref) in enumerate(zip(Gs, refs)):
+                r = ctx.run(G)
+                assert np.array_equal(r.labels, ref.labels), f"labels differ, graph {k}, shapes {(sm, bm, pb)}"
+                assert r.q_int == ref.q_int
+            res = ctx.run_batch(Gs)
+            for k, (r, ref) in enumerate(zip(res, refs)):
+                assert np.array_equal(r.labels, ref.labels), f"batched labels differ, graph {k}, {(sm, bm, pb)}"
+    finally:
+        ctx.set_tuning()
+        for G in Gs:
+            G.destroy()
+
+
+def test_autotune(ctx, L):
+    g = gg.config("chunglu_n20000")
+    G = ctx.graph_create(g.row_ptr, g.col, g.w)
+    try:
+        best = ctx.autotune(G)
+        assert best["small_max"] in (4, 8) and best["block_max"] in (1024, 1365, 2730)
+        assert best["pass_batch"] in (1, 2) and best["ms"] > 0
+        assert ctx.get_tuning() == {k: best[k] for k in ("small_max", "block_max", "pass_batch")}
+        r = ctx.run(G)
+        ref = oracle.louvain(g.row_ptr, g.col, g.w)
+        assert np.array_equal(r.labels, ref.labels) and r.q_int == ref.q_int
+        with pytest.raises(L.LouvainError):
+            ctx.set_tuning(small_max=9)
+        with pytest.raises(L.LouvainError):
+            ctx.set_tuning(block_max=100)
+    finally:
+        ctx.set_tuning()
+        G.destroy()
