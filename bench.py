@@ -60,10 +60,12 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
 
 
-def bench_batched(L, torch, graphs, warmup: int, profile: bool = False):
+def bench_batched(L, torch, graphs, warmup: int, profile: bool = False, tuning=None):
     """One louvain_run_batch call against the plain louvain_run loop on the
     same device-resident graphs; outputs must be identical."""
     ctx = L.Context(0)
+    if tuning:
+        ctx.set_tuning(**tuning)
     dev = torch.device("cuda", 0)
     Gs = [ctx.graph_create(g.row_ptr, g.col, g.w) for g in graphs]
     out_p = [torch.empty(g.n, dtype=torch.int32, device=dev) for g in graphs]
@@ -103,13 +105,15 @@ def bench_batched(L, torch, graphs, warmup: int, profile: bool = False):
             "identical_outputs": bool(same)}
 
 
-def bench_served(L, torch, pool, requests: int, load: float, seed: int = 1005):
+def bench_served(L, torch, pool, requests: int, load: float, seed: int = 1005, tuning=None):
     """Request loop on a Poisson trace against the plain path on the same trace.
 
     The plain path's per-graph times are measured alone; its latencies on the
     trace follow from a first-come-first-served queue over those times."""
     import numpy as np
     ctx = L.Context(0)
+    if tuning:
+        ctx.set_tuning(**tuning)
     dev = torch.device("cuda", 0)
     res_in = [(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev), torch.from_numpy(g.w).to(dev))
               for g in pool]
@@ -187,6 +191,8 @@ def main():
     ap.add_argument("--workload", default="chunglu1m")
     ap.add_argument("--pass-batch", type=int, default=0)
     ap.add_argument("--no-timing", action="store_true", help="time steps without per-kernel events")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch shapes instead of autotuning them on the workload first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched", type=int, default=4096,
                     help="also compare one batched call on this many graphs of the batched SBM workload "
@@ -256,6 +262,15 @@ def main():
         r = ctx.run(G, timing=tm, pass_batch=args.pass_batch, labels_out=out)
         G.destroy()
         return r
+
+    tuning = ctx.get_tuning()
+    if not args.no_autotune:
+        G = ctx.graph_create(rp, col, w)
+        t = time.time()
+        best = ctx.autotune(G)
+        G.destroy()
+        tuning = ctx.get_tuning()
+        log(f"autotuned launch shapes in {time.time() - t:.2f}s: {tuning} ({best['ms']:.3f} ms per run)")
 
     # warm-up steps; the first one records every kernel to find the dominant one,
     # whose launches alone carry HIP events in the timed steps
@@ -339,7 +354,7 @@ def main():
     if batch_graphs is not None:
         log("batched vs plain")
         try:
-            batched = bench_batched(L, torch, batch_graphs, warmup=1, profile=args.batched_profile)
+            batched = bench_batched(L, torch, batch_graphs, warmup=1, profile=args.batched_profile, tuning=tuning)
         except Exception as e:  # the main measurement stands on its own
             batched = {"error": f"{type(e).__name__}: {e}"}
         log(f"batched: {batched}")
@@ -348,7 +363,7 @@ def main():
         log("served vs plain")
         try:
             served = bench_served(L, torch, served_pool, args.served_requests or 4 * len(served_pool),
-                                  args.served_load)
+                                  args.served_load, tuning=tuning)
         except Exception as e:
             served = {"error": f"{type(e).__name__}: {e}"}
         log(f"served: {served}")
@@ -358,7 +373,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
         "config": {"workload": args.workload, "n": g.n, "nnz": g.nnz, "levels": len(levels), "sweeps": sweeps,
-                   "edges_swept": edges, "parallelism": "single GPU"},
+                   "edges_swept": edges, "parallelism": "single GPU", "launch_shapes": tuning},
         "full_louvain_s": round(ms_per_step / 1000.0, 6),
         "sweep_gteps": None if sweep_gteps is None else round(sweep_gteps, 3),
         "kernel_ms_per_step": None if kernel_ms is None else round(kernel_ms, 4),
