@@ -98,9 +98,11 @@ typedef struct {
 } louvain_kernel_stats;
 
 /* Statistics of a run.  Set `timing` to 1 before the call to record
- * per-kernel device times with HIP events around every launch (adds host
- * overhead per launch), or to 2 to record only the launches whose kernel
- * name equals `timing_only` (the per-level ms fields then cover only them). */
+ * per-kernel device times (HIP events filled by each kernel dispatch; the
+ * run also waits for the device at the end of every level to attribute
+ * them), or to 2 to record only the launches whose kernel name equals
+ * `timing_only` (kernels[] then holds only them; the per-level ms fields
+ * stay 0 and no per-level wait is added). */
 typedef struct {
     int32_t timing;               /* in: 0 off, 1 every kernel, 2 only `timing_only`     */
     int32_t levels;               /* out: phases executed                                  */

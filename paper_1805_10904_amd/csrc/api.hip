@@ -125,10 +125,10 @@ DevBuf<int32_t> labels_in(louvain_ctx ctx, const int32_t *labels, int64_t n, uin
         LV_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), ctx->stream));
         k_label_range<<<lv::grid_for(n, 256), 256, 0, ctx->stream>>>(d.p, n, bad.as<int>());
         LV_LAUNCHED("k_label_range");
-        int h = 0;
-        LV_HIP(hipMemcpyAsync(&h, bad.p, sizeof h, hipMemcpyDeviceToHost, ctx->stream));
-        LV_HIP(hipStreamSynchronize(ctx->stream));
-        require(h == 0, LOUVAIN_EINVAL, "label out of range [0, n)");
+        lv::Readback rb(ctx->stream);
+        const int *h = rb.add(bad.as<int>());
+        rb.fetch();
+        require(*h == 0, LOUVAIN_EINVAL, "label out of range [0, n)");
     }
     return d;
 }
@@ -186,6 +186,7 @@ void collect_kernel_stats(lv::Timer &t, louvain_run_stats *st, size_t first, siz
                           double *ms_contract) {
     for (size_t r = first; r < last; ++r) {
         auto &rec = t.recs[r];
+        if (!rec.launched) continue;
         float ms = 0;
         LV_HIP(hipEventElapsedTime(&ms, rec.a, rec.b));
         const bool sweep_fam = rec.group == lv::TG_SWEEP;
@@ -280,7 +281,7 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
             q_final = lv::make_i128(st.q_ref[0], (int64_t)st.q_ref[1]);
             if (st.limit) status = LOUVAIN_ELIMIT;
             if (st.accepted == 0) {
-                if (timing) {
+                if (timing == 1) {
                     LV_HIP(hipStreamSynchronize(s));
                     collect_kernel_stats(timer, nullptr, rec0, timer.recs.size(), &ls.ms_sweep, &ls.ms_contract);
                 }
@@ -291,7 +292,7 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
             ct.compose(fin_p, n0, newlab.p);
             if (level + 1 >= prm.max_levels) {
                 status = LOUVAIN_ELIMIT;
-                if (timing) {
+                if (timing == 1) {
                     LV_HIP(hipStreamSynchronize(s));
                     collect_kernel_stats(timer, nullptr, rec0, timer.recs.size(), &ls.ms_sweep, &ls.ms_contract);
                 }
@@ -317,7 +318,7 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
             v2.tw = g0.tw;
             v = v2;
             which = 1 - which;
-            if (timing) {
+            if (timing == 1) {
                 LV_HIP(hipStreamSynchronize(s));
                 collect_kernel_stats(timer, nullptr, rec0, timer.recs.size(), &ls.ms_sweep, &ls.ms_contract);
             }

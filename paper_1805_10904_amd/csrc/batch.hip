@@ -267,11 +267,11 @@ std::vector<BatchMember *> BatchEngine::step() {
         {
             TimedLaunch tl(t_, TG_LEVEL, "k_union_copy", (double)m_arr * (wide ? 16 : 12) + (double)n_arr * 32);
             if (wide)
-                k_union_copy<int64_t><<<(unsigned)b, 256, 0, s_>>>(jb.as<UnionSeg>(), ubk, (int)us.size(), U.rp.p,
-                                                                    U.col.p, U.w64.p, U.delta.p);
+                tl.launch(k_union_copy<int64_t>, (unsigned)b, 256, 0, s_, jb.as<UnionSeg>(), ubk, (int)us.size(),
+                          U.rp.p, U.col.p, U.w64.p, U.delta.p);
             else
-                k_union_copy<int32_t><<<(unsigned)b, 256, 0, s_>>>(jb.as<UnionSeg>(), ubk, (int)us.size(), U.rp.p,
-                                                                    U.col.p, U.w32.p, U.delta.p);
+                tl.launch(k_union_copy<int32_t>, (unsigned)b, 256, 0, s_, jb.as<UnionSeg>(), ubk, (int)us.size(),
+                          U.rp.p, U.col.p, U.w32.p, U.delta.p);
             LV_LAUNCHED("k_union_copy");
         }
         const int64_t *fbk = upload(vb, fs, fb0, s_);
@@ -292,8 +292,8 @@ std::vector<BatchMember *> BatchEngine::step() {
         TempBuf gbuf;
         const int64_t *gbk = upload(gbuf, gs, gb0, s_);
         TimedLaunch tl(t_, TG_LEVEL, "k_vert_segments", (double)N * 4);
-        k_vert_segments<<<(unsigned)b, 256, 0, s_>>>(gbuf.as<VertSeg>(), gbk, (int)gs.size(), SEG_SLOT, nullptr,
-                                                     nullptr, nullptr);
+        tl.launch(k_vert_segments, (unsigned)b, 256, 0, s_, gbuf.as<VertSeg>(), gbk, (int)gs.size(), SEG_SLOT, nullptr,
+                  nullptr, nullptr);
         LV_LAUNCHED("k_vert_segments");
         LV_HIP(hipStreamSynchronize(s_));
     }
@@ -378,8 +378,8 @@ std::vector<BatchMember *> BatchEngine::step() {
         const int64_t *cbk = upload(cb, cs, cb0, s_);
         {
             TimedLaunch tl(t_, TG_CONTRACT, "k_compose_batch", (double)nv * 12);
-            k_vert_segments<<<(unsigned)b, 256, 0, s_>>>(cb.as<VertSeg>(), cbk, (int)cs.size(), SEG_COMPOSE,
-                                                         loff_.p, newoff_.p, newlab_.p);
+            tl.launch(k_vert_segments, (unsigned)b, 256, 0, s_, cb.as<VertSeg>(), cbk, (int)cs.size(), SEG_COMPOSE,
+                      loff_.p, newoff_.p, newlab_.p);
             LV_LAUNCHED("k_compose_batch");
         }
         if (any_k && !same) {

@@ -2,12 +2,15 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include <cstdio>
 #include <map>
 #include <stdexcept>
 #include <string>
+#include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "louvain.h"
@@ -175,6 +178,7 @@ struct Timer {
         int group;
         hipEvent_t a, b;
         double bytes;   // algorithmic HBM bytes of the launch
+        bool launched = false;
     };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> pool;
@@ -187,18 +191,16 @@ struct Timer {
         }
         return pool[used++];
     }
+    // Opens the record of one launch when timing is on (with a filter, only
+    // for the filtered name); returns its index, or -1.  The launch fills
+    // the record's events.
     int begin(int group, const char *name, const char *suffix, double bytes) {
         if (!on) return -1;
         std::string full = std::string(name) + (suffix ? suffix : "");
         if (!only.empty() && full != only) return -1;
-        Rec r{std::move(full), group, next_event(), next_event(), bytes};
-        LV_HIP(hipEventRecord(r.a, stream));
+        Rec r{std::move(full), group, next_event(), next_event(), bytes, false};
         recs.push_back(std::move(r));
         return (int)recs.size() - 1;
-    }
-    void end(int id) {
-        if (id < 0) return;
-        LV_HIP(hipEventRecord(recs[id].b, stream));
     }
     void reset() { recs.clear(); used = 0; }
     ~Timer() {
@@ -206,14 +208,34 @@ struct Timer {
     }
 };
 
-// RAII scope around one launch.
+// Scope of one timed launch.  When the launch is recorded, its two events
+// are filled by the kernel dispatch itself (hipExtLaunchKernel), so they
+// bracket the kernel's execution and add no packets to the stream; a scope
+// with several launches spans from the first kernel's start to the last
+// one's end.
 struct TimedLaunch {
     Timer *t;
     int id;
+    bool started = false;
     TimedLaunch(Timer *t_, int group, const char *name, double bytes, const char *suffix = nullptr)
         : t(t_), id(t_ ? t_->begin(group, name, suffix, bytes) : -1) {}
-    ~TimedLaunch() {
-        if (t && id >= 0) t->end(id);
+    template <typename... KArgs, typename... Args>
+    void launch(void (*k)(KArgs...), dim3 grid, dim3 block, uint32_t shm, hipStream_t s, Args... args) {
+        hipEvent_t a = nullptr, b = nullptr;
+        if (id >= 0) {
+            b = t->recs[id].b;
+            if (!started) a = t->recs[id].a;
+            started = true;
+            t->recs[id].launched = true;
+        }
+        static_assert(sizeof...(KArgs) == sizeof...(Args), "kernel argument count");
+        std::tuple<std::decay_t<KArgs>...> tup{static_cast<std::decay_t<KArgs>>(args)...};
+        void *argv[sizeof...(KArgs) + 1];
+        std::apply([&argv](auto &...x) {
+            int i = 0;
+            ((argv[i++] = (void *)&x), ...);
+        }, tup);
+        LV_HIP(hipExtLaunchKernel((const void *)k, grid, block, argv, shm, s, a, b, 0));
     }
 };
 

@@ -74,19 +74,19 @@ int64_t Contractor::renumber(const int32_t *labels, int64_t n, int32_t *newlab) 
     fill<int32_t>(flags, 0, n, s_);
     {
         TimedLaunch tl(t_, TG_CONTRACT, "k_mark", (double)n * 8);
-        k_mark<<<grid_for(n, 256), 256, 0, s_>>>(labels, n, flags);
+        tl.launch(k_mark, grid_for(n, 256), 256, 0, s_, labels, n, flags);
         LV_LAUNCHED("k_mark");
     }
     scan_exclusive<int32_t, int32_t>(flags, flags, n, flags + n, s_, t_);
     {
         TimedLaunch tl(t_, TG_CONTRACT, "k_relabel", (double)n * 12);
-        k_relabel<<<grid_for(n, 256), 256, 0, s_>>>(labels, flags, n, newlab);
+        tl.launch(k_relabel, grid_for(n, 256), 256, 0, s_, labels, flags, n, newlab);
         LV_LAUNCHED("k_relabel");
     }
-    int32_t k = 0;
-    LV_HIP(hipMemcpyAsync(&k, flags + n, sizeof k, hipMemcpyDeviceToHost, s_));
-    LV_HIP(hipStreamSynchronize(s_));
-    return k;
+    Readback rb(s_);
+    const int32_t *k = rb.add(flags + n);
+    rb.fetch();
+    return *k;
 }
 
 int64_t Contractor::renumber_kept(const int32_t *labels, int64_t n, const int32_t *gid, const int32_t *keep,
@@ -96,29 +96,29 @@ int64_t Contractor::renumber_kept(const int32_t *labels, int64_t n, const int32_
     fill<int32_t>(flags, 0, n, s_);
     {
         TimedLaunch tl(t_, TG_CONTRACT, "k_mark_kept", (double)n * 12);
-        k_mark_kept<<<grid_for(n, 256), 256, 0, s_>>>(labels, gid, keep, n, flags);
+        tl.launch(k_mark_kept, grid_for(n, 256), 256, 0, s_, labels, gid, keep, n, flags);
         LV_LAUNCHED("k_mark_kept");
     }
     scan_exclusive<int32_t, int32_t>(flags, flags, n, flags + n, s_, t_);
     {
         TimedLaunch tl(t_, TG_CONTRACT, "k_relabel_kept", (double)n * 16);
-        k_relabel_kept<<<grid_for(n, 256), 256, 0, s_>>>(labels, flags, gid, keep, n, newlab);
+        tl.launch(k_relabel_kept, grid_for(n, 256), 256, 0, s_, labels, flags, gid, keep, n, newlab);
         LV_LAUNCHED("k_relabel_kept");
     }
     // a kept graph's labels lie in its own vertex range, so the count of
     // present labels below loff[s] is the first new ID of graph s
     k_gather_offsets<<<grid_for(nslots + 1, 256), 256, 0, s_>>>(flags, loff, nslots, newoff);
     LV_LAUNCHED("k_gather_offsets");
-    int32_t k = 0;
-    LV_HIP(hipMemcpyAsync(&k, flags + n, sizeof k, hipMemcpyDeviceToHost, s_));
-    LV_HIP(hipStreamSynchronize(s_));
-    return k;
+    Readback rb(s_);
+    const int32_t *k = rb.add(flags + n);
+    rb.fetch();
+    return *k;
 }
 
 void Contractor::compose(int32_t *final_labels, int64_t n0, const int32_t *newlab) {
     if (n0 == 0) return;
     TimedLaunch tl(t_, TG_CONTRACT, "k_compose", (double)n0 * 12);
-    k_compose<<<grid_for(n0, 256), 256, 0, s_>>>(final_labels, n0, newlab);
+    tl.launch(k_compose, grid_for(n0, 256), 256, 0, s_, final_labels, n0, newlab);
     LV_LAUNCHED("k_compose");
 }
 
@@ -679,10 +679,11 @@ __global__ __launch_bounds__(256) void k_seg_chunk(const int64_t *__restrict__ o
 
 // Merged pairs of segments spread over several chunks: write them to their
 // segments in key order and record the counts.
-__global__ void k_seg_merge_write(const uint64_t *__restrict__ ukey, const int64_t *__restrict__ usum, int64_t u_n,
-                                  int bits, const int64_t *__restrict__ off, int32_t *tcol, int64_t *tw,
-                                  int64_t *mcount) {
+__global__ void k_seg_merge_write(const uint64_t *__restrict__ ukey, const int64_t *__restrict__ usum,
+                                  const int64_t *__restrict__ u_n_dev, int bits, const int64_t *__restrict__ off,
+                                  int32_t *tcol, int64_t *tw, int64_t *mcount) {
     const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t u_n = *u_n_dev;
     if (u >= u_n) return;
     const uint64_t key = ukey[u];
     const int64_t sg = (int64_t)(key >> bits);
@@ -699,11 +700,15 @@ __global__ void k_seg_merge_write(const uint64_t *__restrict__ ukey, const int64
 }
 
 // Output CSR: entry u of row a comes from its segment's u - rp[a]-th pair.
-__global__ __launch_bounds__(256) void k_seg_pack(const int64_t *__restrict__ rp, int64_t n_new, int64_t m_new,
+// The entry count m_new = rp[n_new] is read on the device; the grid covers
+// an upper bound of it.
+__global__ __launch_bounds__(256) void k_seg_pack(const int64_t *__restrict__ rp, int64_t n_new,
                                                   const int64_t *__restrict__ off, const int32_t *__restrict__ tcol,
                                                   const int64_t *__restrict__ tw, int32_t *col_out, int64_t *w_out) {
     __shared__ int64_t srange[2];
     const int64_t base = (int64_t)blockIdx.x * kEntriesPerBlock;
+    const int64_t m_new = rp[n_new];
+    if (base >= m_new) return;   // uniform over the workgroup
     block_row_range(rp, n_new, m_new, base, kEntriesPerBlock, srange);
     const int64_t rlo = srange[0], rhi = srange[1];
 #pragma unroll 1
@@ -717,7 +722,7 @@ __global__ __launch_bounds__(256) void k_seg_pack(const int64_t *__restrict__ rp
     }
 }
 
-int64_t Contractor::sort_sum(int64_t m, int key_bits, const uint64_t **ukeys, const int64_t **usums) {
+const int64_t *Contractor::sort_sum(int64_t m, int key_bits, const uint64_t **ukeys, const int64_t **usums) {
     const int64_t rb = (m + kRadixTile - 1) / kRadixTile;
     TempBuf hist((size_t)256 * rb * sizeof(int32_t), s_);
     TempBuf offs((size_t)256 * rb * sizeof(int64_t), s_);
@@ -725,15 +730,15 @@ int64_t Contractor::sort_sum(int64_t m, int key_bits, const uint64_t **ukeys, co
     for (int shift = 0; shift < key_bits; shift += 8) {
         {
             TimedLaunch tl(t_, TG_CONTRACT, "k_radix_hist", (double)m * 8);
-            k_radix_hist<<<(unsigned)rb, 256, 0, s_>>>(key_[src].p, m, shift, hist.as<int32_t>(), rb);
+            tl.launch(k_radix_hist, (unsigned)rb, 256, 0, s_, key_[src].p, m, shift, hist.as<int32_t>(), rb);
             LV_LAUNCHED("k_radix_hist");
         }
         scan_exclusive<int32_t, int64_t>(hist.as<int32_t>(), offs.as<int64_t>(), 256 * rb, (int64_t *)nullptr,
                                          s_, t_);
         {
             TimedLaunch tl(t_, TG_CONTRACT, "k_radix_scatter", (double)m * 32);
-            k_radix_scatter<<<(unsigned)rb, 256, 0, s_>>>(key_[src].p, val_[src].p, key_[1 - src].p,
-                                                          val_[1 - src].p, m, shift, offs.as<int64_t>(), rb);
+            tl.launch(k_radix_scatter, (unsigned)rb, 256, 0, s_, key_[src].p, val_[src].p, key_[1 - src].p,
+                      val_[1 - src].p, m, shift, offs.as<int64_t>(), rb);
             LV_LAUNCHED("k_radix_scatter");
         }
         src = 1 - src;
@@ -744,23 +749,20 @@ int64_t Contractor::sort_sum(int64_t m, int key_bits, const uint64_t **ukeys, co
     int64_t *usum = val_[1 - src].p;
     {
         TimedLaunch tl(t_, TG_CONTRACT, "k_heads", (double)m * 12);
-        k_heads<<<grid_for(m, 256), 256, 0, s_>>>(keys, m, head_.p);
+        tl.launch(k_heads, grid_for(m, 256), 256, 0, s_, keys, m, head_.p);
         LV_LAUNCHED("k_heads");
     }
     scan_exclusive<int32_t, int64_t>(head_.p, uid_.p, m, uid_.p + m, s_, t_);
-    int64_t u_n = 0;
-    LV_HIP(hipMemcpyAsync(&u_n, uid_.p + m, sizeof u_n, hipMemcpyDeviceToHost, s_));
-    LV_HIP(hipStreamSynchronize(s_));
-    fill<int64_t>(usum, 0, u_n, s_);
+    fill<int64_t>(usum, 0, m, s_);   // the distinct-key count (uid_[m]) is at most m
     {
         const int64_t eb = (m + kEntriesPerBlock - 1) / kEntriesPerBlock;
-        TimedLaunch tl(t_, TG_CONTRACT, "k_reduce_by_key", (double)m * 28 + (double)u_n * 16);
-        k_reduce_by_key<<<(unsigned)eb, 256, 0, s_>>>(keys, vals, head_.p, uid_.p, m, 64, nullptr, usum, ukey);
+        TimedLaunch tl(t_, TG_CONTRACT, "k_reduce_by_key", (double)m * 44);
+        tl.launch(k_reduce_by_key, (unsigned)eb, 256, 0, s_, keys, vals, head_.p, uid_.p, m, 64, nullptr, usum, ukey);
         LV_LAUNCHED("k_reduce_by_key");
     }
     *ukeys = ukey;
     *usums = usum;
-    return u_n;
+    return uid_.p + m;
 }
 
 int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t n_new, int64_t *rp_out,
@@ -782,30 +784,32 @@ int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t 
     const unsigned vb = (unsigned)((n + kSegTile - 1) / kSegTile);
     {
         TimedLaunch tl(t_, TG_CONTRACT, "k_seg_count", (double)n * 20);
-        k_seg_count<<<vb, 256, 0, s_>>>(g.row_ptr, newlab, n, (unsigned long long *)cnt);
+        tl.launch(k_seg_count, vb, 256, 0, s_, g.row_ptr, newlab, n, (unsigned long long *)cnt);
         LV_LAUNCHED("k_seg_count");
     }
     scan_exclusive<int64_t, int64_t>(cnt, off, k, off + k, s_, t_);
     {
         TimedLaunch tl(t_, TG_CONTRACT, "k_seg_start", (double)n * 28);
-        k_seg_start<<<vb, 256, 0, s_>>>(g.row_ptr, newlab, n, off, cursor, seg_start_.p);
+        tl.launch(k_seg_start, vb, 256, 0, s_, g.row_ptr, newlab, n, off, cursor, seg_start_.p);
         LV_LAUNCHED("k_seg_start");
     }
-    int64_t m_raw = 0;
-    LV_HIP(hipMemcpyAsync(&m_raw, off + k, sizeof m_raw, hipMemcpyDeviceToHost, s_));
+    Readback rb(s_);
+    const int64_t *mr = rb.add(off + k);
+    rb.issue();   // read while the scatter runs
     {
         const int64_t eb = (g.nnz + kEntriesPerBlock - 1) / kEntriesPerBlock;
         TimedLaunch tl(t_, TG_CONTRACT, "k_seg_scatter", (double)g.nnz * (4 + g.wbytes + 4 + 12) + (double)n * 12,
                        g.wbytes == 4 ? "<int>" : "<long>");
         if (g.wbytes == 4)
-            k_seg_scatter<int32_t><<<(unsigned)eb, 256, 0, s_>>>(g.row_ptr, n, g.nnz, g.col, (const int32_t *)g.w,
-                                                                 newlab, seg_start_.p, tcol_.p, tw_.p);
+            tl.launch(k_seg_scatter<int32_t>, (unsigned)eb, 256, 0, s_, g.row_ptr, n, g.nnz, g.col,
+                      (const int32_t *)g.w, newlab, seg_start_.p, tcol_.p, tw_.p);
         else
-            k_seg_scatter<int64_t><<<(unsigned)eb, 256, 0, s_>>>(g.row_ptr, n, g.nnz, g.col, (const int64_t *)g.w,
-                                                                 newlab, seg_start_.p, tcol_.p, tw_.p);
+            tl.launch(k_seg_scatter<int64_t>, (unsigned)eb, 256, 0, s_, g.row_ptr, n, g.nnz, g.col,
+                      (const int64_t *)g.w, newlab, seg_start_.p, tcol_.p, tw_.p);
         LV_LAUNCHED("k_seg_scatter");
     }
-    LV_HIP(hipStreamSynchronize(s_));
+    rb.wait();
+    const int64_t m_raw = *mr;
     int64_t *mcount = seg_m_.p;           // k + 1
     fill<int64_t>(mcount, 0, k + 1, s_);
     if (m_raw == 0) {
@@ -819,34 +823,37 @@ int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t 
         const int64_t cb = (m_raw + kChunk - 1) / kChunk;
         TimedLaunch tl(t_, TG_CONTRACT, sorted ? "k_seg_chunk" : "k_seg_chunk_any", (double)m_raw * 24);
         if (sorted)
-            k_seg_chunk<<<(unsigned)cb, 256, 0, s_>>>(off, k, m_raw, tcol_.p, tw_.p, mcount, key_[0].p, val_[0].p,
-                                                      pc.as<unsigned long long>(), bits);
+            tl.launch(k_seg_chunk, (unsigned)cb, 256, 0, s_, off, k, m_raw, tcol_.p, tw_.p, mcount, key_[0].p,
+                      val_[0].p, pc.as<unsigned long long>(), bits);
         else
-            k_seg_chunk_any<<<(unsigned)cb, 256, 0, s_>>>(off, k, m_raw, tcol_.p, tw_.p, mcount, key_[0].p,
-                                                          val_[0].p, pc.as<unsigned long long>(), bits);
+            tl.launch(k_seg_chunk_any, (unsigned)cb, 256, 0, s_, off, k, m_raw, tcol_.p, tw_.p, mcount, key_[0].p,
+                      val_[0].p, pc.as<unsigned long long>(), bits);
         LV_LAUNCHED("k_seg_chunk");
     }
-    uint64_t np = 0;
-    LV_HIP(hipMemcpyAsync(&np, pc.p, sizeof np, hipMemcpyDeviceToHost, s_));
-    LV_HIP(hipStreamSynchronize(s_));
+    const uint64_t *npp = rb.add(pc.as<uint64_t>());
+    rb.fetch();
+    const uint64_t np = *npp;
     if (np > 0) {
         const uint64_t *ukey;
         const int64_t *usum;
-        const int64_t u_n = sort_sum((int64_t)np, 2 * bits, &ukey, &usum);
-        TimedLaunch tl(t_, TG_CONTRACT, "k_seg_merge_write", (double)u_n * 28);
-        k_seg_merge_write<<<grid_for(u_n, 256), 256, 0, s_>>>(ukey, usum, u_n, bits, off, tcol_.p, tw_.p, mcount);
+        // the merged pair count stays on the device; np bounds the grid
+        const int64_t *u_n = sort_sum((int64_t)np, 2 * bits, &ukey, &usum);
+        TimedLaunch tl(t_, TG_CONTRACT, "k_seg_merge_write", (double)np * 28);
+        tl.launch(k_seg_merge_write, grid_for((int64_t)np, 256), 256, 0, s_, ukey, usum, u_n, bits, off, tcol_.p,
+                  tw_.p, mcount);
         LV_LAUNCHED("k_seg_merge_write");
     }
     scan_exclusive<int64_t, int64_t>(mcount, rp_out, k, rp_out + k, s_, t_);
-    int64_t m_new = 0;
-    LV_HIP(hipMemcpyAsync(&m_new, rp_out + k, sizeof m_new, hipMemcpyDeviceToHost, s_));
-    LV_HIP(hipStreamSynchronize(s_));
-    if (m_new > 0) {
-        const int64_t eb = (m_new + kEntriesPerBlock - 1) / kEntriesPerBlock;
-        TimedLaunch tl(t_, TG_CONTRACT, "k_seg_pack", (double)m_new * 32);
-        k_seg_pack<<<(unsigned)eb, 256, 0, s_>>>(rp_out, k, m_new, off, tcol_.p, tw_.p, col_out, w_out);
+    {
+        // m_new <= m_raw: merging pairs only removes entries
+        const int64_t eb = (m_raw + kEntriesPerBlock - 1) / kEntriesPerBlock;
+        TimedLaunch tl(t_, TG_CONTRACT, "k_seg_pack", (double)m_raw * 32);
+        tl.launch(k_seg_pack, (unsigned)eb, 256, 0, s_, rp_out, k, off, tcol_.p, tw_.p, col_out, w_out);
         LV_LAUNCHED("k_seg_pack");
     }
+    const int64_t *mn = rb.add(rp_out + k);
+    rb.fetch();
+    const int64_t m_new = *mn;
     return m_new;
 }
 
@@ -920,19 +927,19 @@ i128 modularity_int(const GraphView &g, const int32_t *labels, hipStream_t s, Ti
     fill<int64_t>(deg.as<int64_t>(), 0, g.n, s);
     fill<uint64_t>(acc, 0, 1, s);
     TimedLaunch tl(t, TG_OTHER, "modularity", (double)g.nnz * 16 + (double)g.n * 24);
-    k_label_degrees<<<grid_for(g.n, 256), 256, 0, s>>>(labels, g.delta, g.n, deg.as<int64_t>());
+    tl.launch(k_label_degrees, grid_for(g.n, 256), 256, 0, s, labels, g.delta, g.n, deg.as<int64_t>());
     LV_LAUNCHED("k_label_degrees");
     if (g.nnz > 0) {
         const int64_t eb = (g.nnz + kEntriesPerBlock - 1) / kEntriesPerBlock;
         if (g.wbytes == 4)
-            k_inner_weight<int32_t><<<(unsigned)eb, 256, 0, s>>>(g.row_ptr, g.n, g.nnz, g.col, (const int32_t *)g.w,
-                                                                 labels, (unsigned long long *)acc);
+            tl.launch(k_inner_weight<int32_t>, (unsigned)eb, 256, 0, s, g.row_ptr, g.n, g.nnz, g.col,
+                      (const int32_t *)g.w, labels, (unsigned long long *)acc);
         else
-            k_inner_weight<int64_t><<<(unsigned)eb, 256, 0, s>>>(g.row_ptr, g.n, g.nnz, g.col, (const int64_t *)g.w,
-                                                                 labels, (unsigned long long *)acc);
+            tl.launch(k_inner_weight<int64_t>, (unsigned)eb, 256, 0, s, g.row_ptr, g.n, g.nnz, g.col,
+                      (const int64_t *)g.w, labels, (unsigned long long *)acc);
         LV_LAUNCHED("k_inner_weight");
     }
-    k_sq_partials<<<(unsigned)nb, 256, 0, s>>>(deg.as<int64_t>(), g.n, part.as<uint64_t>());
+    tl.launch(k_sq_partials, (unsigned)nb, 256, 0, s, deg.as<int64_t>(), g.n, part.as<uint64_t>());
     LV_LAUNCHED("k_sq_partials");
     sum_i128_partials(part.as<uint64_t>(), nb, tot, s);
     uint64_t h[4];

@@ -37,9 +37,9 @@ class Contractor {
   private:
     // Sort (key_[0], val_[0])[0, m) by the low key_bits of the keys and sum
     // the values of equal keys; *ukeys / *usums receive the unique keys in
-    // ascending order and their sums (contractor buffers).  Returns their
-    // number (synchronises the stream).
-    int64_t sort_sum(int64_t m, int key_bits, const uint64_t **ukeys, const int64_t **usums);
+    // ascending order and their sums (contractor buffers).  Returns the
+    // device address of their number (at most m); does not synchronise.
+    const int64_t *sort_sum(int64_t m, int key_bits, const uint64_t **ukeys, const int64_t **usums);
 
     hipStream_t s_;
     Timer *t_;

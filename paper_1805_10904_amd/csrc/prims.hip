@@ -2,6 +2,9 @@
 // and row sums.
 #include "prims.hpp"
 
+#include <mutex>
+#include <vector>
+
 namespace lv {
 
 Pool *&current_pool() {
@@ -143,20 +146,20 @@ void scan_exclusive(const TI *in, TO *out, int64_t m, TO *total_dev, hipStream_t
     const int64_t nb = (m + kScanTile - 1) / kScanTile;
     if (nb == 1) {
         TimedLaunch tl(t, TG_OTHER, "k_scan_down", (double)m * (sizeof(TI) + sizeof(TO)));
-        k_scan_down<TI, TO><<<1, 256, 0, s>>>(in, out, m, nullptr, total_dev);
+        tl.launch(k_scan_down<TI, TO>, 1, 256, 0, s, in, out, m, nullptr, total_dev);
         LV_LAUNCHED("k_scan_down");
         return;
     }
     TempBuf bs((size_t)nb * sizeof(TO), s);
     {
         TimedLaunch tl(t, TG_OTHER, "k_scan_reduce", (double)m * sizeof(TI));
-        k_scan_reduce<TI, TO><<<(unsigned)nb, 256, 0, s>>>(in, m, bs.as<TO>());
+        tl.launch(k_scan_reduce<TI, TO>, (unsigned)nb, 256, 0, s, in, m, bs.as<TO>());
         LV_LAUNCHED("k_scan_reduce");
     }
     scan_exclusive<TO, TO>(bs.as<TO>(), bs.as<TO>(), nb, (TO *)nullptr, s, t);
     {
         TimedLaunch tl(t, TG_OTHER, "k_scan_down", (double)m * (sizeof(TI) + sizeof(TO)));
-        k_scan_down<TI, TO><<<(unsigned)nb, 256, 0, s>>>(in, out, m, bs.as<TO>(), total_dev);
+        tl.launch(k_scan_down<TI, TO>, (unsigned)nb, 256, 0, s, in, out, m, bs.as<TO>(), total_dev);
         LV_LAUNCHED("k_scan_down");
     }
 }
@@ -287,12 +290,13 @@ void ingest_csr(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *c
     fill<int64_t>(delta, 0, n, s);
     {
         TimedLaunch tl(t, TG_INGEST, "k_check_rowptr", (double)(n + 1) * 8);
-        k_check_rowptr<<<grid_for(n + 1, 256), 256, 0, s>>>(row_ptr, n, nnz, bad);
+        tl.launch(k_check_rowptr, grid_for(n + 1, 256), 256, 0, s, row_ptr, n, nnz, bad);
         LV_LAUNCHED("k_check_rowptr");
     }
-    int hbad = 0;
-    LV_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
-    LV_HIP(hipStreamSynchronize(s));
+    Readback rb(s);
+    const int *hb0 = rb.add(bad);
+    rb.fetch();
+    int hbad = *hb0;
     require(hbad == 0, LOUVAIN_EINVAL, "row_ptr is malformed (must start at 0, be nondecreasing and end at nnz)");
     uint64_t hw[2] = {0, 0};
     if (nnz > 0) {
@@ -300,15 +304,17 @@ void ingest_csr(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *c
         TempBuf parts((size_t)nb * 2 * sizeof(uint64_t), s);
         {
             TimedLaunch tl(t, TG_INGEST, "k_ingest_entries", (double)nnz * (4 + sizeof(W)) + (double)n * 16, type_name<W>());
-            k_ingest_entries<W><<<(unsigned)nb, 256, 0, s>>>(row_ptr, n, nnz, col, w, delta,
-                                                             parts.as<uint64_t>(), bad,
-                                                             check_symmetry ? 1 : 0);
+            tl.launch(k_ingest_entries<W>, (unsigned)nb, 256, 0, s, row_ptr, n, nnz, col, w, delta,
+                      parts.as<uint64_t>(), bad, check_symmetry ? 1 : 0);
             LV_LAUNCHED("k_ingest_entries");
         }
         sum_i128_partials(parts.as<uint64_t>(), nb, tw2, s);
-        LV_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
-        LV_HIP(hipMemcpyAsync(hw, tw2, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
-        LV_HIP(hipStreamSynchronize(s));
+        const int *hb1 = rb.add(bad);
+        const uint64_t *hw1 = rb.add(tw2, 2);
+        rb.fetch();
+        hbad = *hb1;
+        hw[0] = hw1[0];
+        hw[1] = hw1[1];
     }
     require(!(hbad & BAD_COL), LOUVAIN_EINVAL, "column index out of range [0, n)");
     require(!(hbad & BAD_WEIGHT), LOUVAIN_EINVAL, "edge weight < 1 (weights must be positive integers)");
@@ -351,8 +357,74 @@ void row_sums_i64(int64_t n, int64_t nnz, const int64_t *row_ptr, const int64_t 
     if (nnz <= 0) return;
     const int64_t nb = (nnz + kEntriesPerBlock - 1) / kEntriesPerBlock;
     TimedLaunch tl(t, TG_CONTRACT, "k_row_sums", (double)nnz * 8 + (double)n * 16);
-    k_row_sums<<<(unsigned)nb, 256, 0, s>>>(row_ptr, n, nnz, w, delta);
+    tl.launch(k_row_sums, (unsigned)nb, 256, 0, s, row_ptr, n, nnz, w, delta);
     LV_LAUNCHED("k_row_sums");
 }
+
+// ------------------------------------------------------------- read-back --
+
+namespace {
+
+struct GatherRanges {
+    const uint32_t *src[Readback::kMaxRanges];
+    int off[Readback::kMaxRanges], len[Readback::kMaxRanges];
+    int n;
+};
+
+__global__ __launch_bounds__(256) void k_readback(GatherRanges r, uint32_t *dst) {
+    for (int k = 0; k < r.n; ++k)
+        for (int i = threadIdx.x; i < r.len[k]; i += 256) dst[r.off[k] + i] = r.src[k][i];
+    __threadfence_system();
+}
+
+std::mutex g_rb_mu;
+std::vector<uint32_t *> g_rb_free;
+
+}  // namespace
+
+Readback::Readback(hipStream_t s) : s_(s) {
+    {
+        std::lock_guard<std::mutex> lk(g_rb_mu);
+        if (!g_rb_free.empty()) {
+            host_ = g_rb_free.back();
+            g_rb_free.pop_back();
+        }
+    }
+    if (!host_) LV_HIP(hipHostMalloc((void **)&host_, kReadbackWords * sizeof(uint32_t), hipHostMallocCoherent));
+    LV_HIP(hipHostGetDevicePointer((void **)&dev_, host_, 0));
+}
+
+Readback::~Readback() {
+    std::lock_guard<std::mutex> lk(g_rb_mu);
+    g_rb_free.push_back(host_);
+}
+
+void *Readback::add_words(const void *src, int64_t words) {
+    require(n_ < kMaxRanges && used_ + words <= kReadbackWords, LOUVAIN_EDEVICE, "read-back block is full");
+    src_[n_] = (const uint32_t *)src;
+    off_[n_] = used_;
+    len_[n_] = (int)words;
+    ++n_;
+    void *at = host_ + used_;
+    used_ += (int)((words + 1) & ~(int64_t)1);   // keep 8-byte alignment
+    return at;
+}
+
+void Readback::issue() {
+    if (n_ > 0) {
+        GatherRanges r;
+        for (int k = 0; k < n_; ++k) {
+            r.src[k] = src_[k];
+            r.off[k] = off_[k];
+            r.len[k] = len_[k];
+        }
+        r.n = n_;
+        k_readback<<<1, 256, 0, s_>>>(r, dev_);
+        LV_LAUNCHED("k_readback");
+    }
+    n_ = 0;
+}
+
+void Readback::wait() { LV_HIP(hipStreamSynchronize(s_)); }
 
 }  // namespace lv

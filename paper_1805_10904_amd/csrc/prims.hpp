@@ -46,6 +46,41 @@ struct TempBuf {
     template <typename T> T *as() const { return (T *)p; }
 };
 
+// Device values the host needs, read in one round trip: each add() queues
+// a device range (4-byte words) and returns where it will land in pinned
+// host memory; fetch() (issue() then wait()) gathers every queued range with
+// one small kernel that writes straight into that memory, then waits for the
+// stream once.  The
+// pinned block (kReadbackWords words) comes from a process-wide free list.
+class Readback {
+  public:
+    static constexpr int kMaxRanges = 24;
+    static constexpr int kReadbackWords = 1024;
+    explicit Readback(hipStream_t s);
+    ~Readback();
+    Readback(const Readback &) = delete;
+    Readback &operator=(const Readback &) = delete;
+    template <typename T> T *add(const T *src, int64_t count = 1) {
+        static_assert(sizeof(T) % 4 == 0, "whole 4-byte words");
+        return (T *)add_words(src, count * (int64_t)(sizeof(T) / 4));
+    }
+    void issue();   // launch the gather of the queued ranges
+    void wait();    // wait for the stream (after issue, the values are in place)
+    void fetch() {
+        issue();
+        wait();
+    }
+
+  private:
+    void *add_words(const void *src, int64_t words);
+    hipStream_t s_;
+    uint32_t *host_ = nullptr, *dev_ = nullptr;
+    int n_ = 0;
+    int used_ = 0;
+    const uint32_t *src_[kMaxRanges];
+    int off_[kMaxRanges], len_[kMaxRanges];
+};
+
 // out[i] = sum_{k<i} in[k] for i in [0, m); *total_dev (optional, device)
 // receives the sum of all m values.  in and out may alias.  TI, TO are
 // int32_t or int64_t; sums are formed in TO.

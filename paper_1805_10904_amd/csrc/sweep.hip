@@ -1040,26 +1040,25 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     int32_t *counts = bcount_.p;
     {
         TimedLaunch tl(t_, TG_LEVEL, "k_bucket_count", (double)g.n * 16);
-        k_bucket_count<<<(unsigned)nblk, 256, 0, s_>>>(g.row_ptr, g.n, counts, nblk, bnnz.as<unsigned long long>(),
-                                                       skip_gid, skip_st, small_max, block_max);
+        tl.launch(k_bucket_count, (unsigned)nblk, 256, 0, s_, g.row_ptr, g.n, counts, nblk,
+                  bnnz.as<unsigned long long>(), skip_gid, skip_st, small_max, block_max);
         LV_LAUNCHED("k_bucket_count");
     }
     const int64_t m = NBUCKET * nblk;
     scan_exclusive<int32_t, int32_t>(counts, counts, m, counts + m, s_, t_);
     {
         TimedLaunch tl(t_, TG_LEVEL, "k_bucket_scatter", (double)g.n * 20);
-        k_bucket_scatter<<<(unsigned)nblk, 256, 0, s_>>>(g.row_ptr, g.n, counts, nblk, list_.p, skip_gid, skip_st,
-                                                         small_max, block_max);
+        tl.launch(k_bucket_scatter, (unsigned)nblk, 256, 0, s_, g.row_ptr, g.n, counts, nblk, list_.p, skip_gid,
+                  skip_st, small_max, block_max);
         LV_LAUNCHED("k_bucket_scatter");
     }
-    int32_t hs[NBUCKET + 1];
-    for (int b = 0; b < NBUCKET; ++b)
-        LV_HIP(hipMemcpyAsync(&hs[b], counts + (int64_t)b * nblk, sizeof(int32_t), hipMemcpyDeviceToHost, s_));
-    LV_HIP(hipMemcpyAsync(&hs[NBUCKET], counts + m, sizeof(int32_t), hipMemcpyDeviceToHost, s_));
-    unsigned long long hn[NBUCKET];
-    LV_HIP(hipMemcpyAsync(hn, bnnz.p, sizeof hn, hipMemcpyDeviceToHost, s_));
-    LV_HIP(hipStreamSynchronize(s_));
-    for (int b = 0; b <= NBUCKET; ++b) bstart_[b] = hs[b];
+    Readback rb(s_);
+    const int32_t *hs[NBUCKET + 1];
+    for (int b = 0; b < NBUCKET; ++b) hs[b] = rb.add(counts + (int64_t)b * nblk);
+    hs[NBUCKET] = rb.add(counts + m);
+    const unsigned long long *hn = rb.add(bnnz.as<unsigned long long>(), NBUCKET);
+    rb.fetch();
+    for (int b = 0; b <= NBUCKET; ++b) bstart_[b] = *hs[b];
     for (int b = 0; b < NBUCKET; ++b) bucket_nnz_[b] = (int64_t)hn[b];
     // line positions of the packed vertices (buckets B_T16 to B_MID, contiguous in the list)
     pack_count_ = bstart_[B_BLOCK] - bstart_[B_T16];
@@ -1075,9 +1074,9 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
         LV_LAUNCHED("k_pack_cost");
         scan_exclusive<int32_t, int64_t>(cost.as<int32_t>(), pack_pos_.p, pack_count_, pack_pos_.p + pack_count_,
                                          s_, t_);
-        int64_t line = 0;
-        LV_HIP(hipMemcpyAsync(&line, pack_pos_.p + pack_count_, sizeof line, hipMemcpyDeviceToHost, s_));
-        LV_HIP(hipStreamSynchronize(s_));
+        const int64_t *lp = rb.add(pack_pos_.p + pack_count_);
+        rb.fetch();
+        const int64_t line = *lp;
         pack_blocks_ = (line + kPackW - 1) / kPackW;
         pack_first_.reserve((size_t)pack_blocks_ + 1);
         k_pack_first<<<grid_for(pack_blocks_ + 1, 256), 256, 0, s_>>>(pack_pos_.p, pack_count_, pack_blocks_,
@@ -1095,14 +1094,11 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     scan_exclusive<int64_t, int64_t>(tab_off, tab_off, hubs_, tab_off + hubs_, s_, t_);
     scan_exclusive<int64_t, int64_t>(chunk_off, chunk_off, hubs_, chunk_off + hubs_, s_, t_);
     scan_exclusive<int64_t, int64_t>(scan_off, scan_off, hubs_, scan_off + hubs_, s_, t_);
-    int64_t tot[3];
-    LV_HIP(hipMemcpyAsync(&tot[0], tab_off + hubs_, 8, hipMemcpyDeviceToHost, s_));
-    LV_HIP(hipMemcpyAsync(&tot[1], chunk_off + hubs_, 8, hipMemcpyDeviceToHost, s_));
-    LV_HIP(hipMemcpyAsync(&tot[2], scan_off + hubs_, 8, hipMemcpyDeviceToHost, s_));
-    LV_HIP(hipStreamSynchronize(s_));
-    hub_slots_ = tot[0];
-    hub_chunks_ = tot[1];
-    hub_scans_ = tot[2];
+    const int64_t *tot[3] = {rb.add(tab_off + hubs_), rb.add(chunk_off + hubs_), rb.add(scan_off + hubs_)};
+    rb.fetch();
+    hub_slots_ = *tot[0];
+    hub_chunks_ = *tot[1];
+    hub_scans_ = *tot[2];
     if (hub_slots_ > hub_slot_cap_) {
         hub_key_.alloc((size_t)hub_slots_);
         hub_val_.alloc((size_t)hub_slots_);
@@ -1127,8 +1123,8 @@ void Sweeper::init_singletons(const GraphView &g) {
         return;
     } else if (g.n > 0) {
         TimedLaunch tl(t_, TG_LEVEL, "k_init_singletons", (double)g.n * 28);
-        k_init_singletons<<<grid_for(g.n, 256), 256, 0, s_>>>(c_[0].p, c_[1].p, c_[2].p, g.delta, deg_.p,
-                                                             size_.p, g.n);
+        tl.launch(k_init_singletons, grid_for(g.n, 256), 256, 0, s_, c_[0].p, c_[1].p, c_[2].p, g.delta, deg_.p,
+                  size_.p, g.n);
         LV_LAUNCHED("k_init_singletons");
     }
     LV_HIP(hipMemsetAsync(st_.p, 0, sizeof(PhaseState), s_));
@@ -1145,8 +1141,8 @@ void Sweeper::init_from_labels(const GraphView &g, const int32_t *labels) {
     fill<int32_t>(size_.p, 0, g.n, s_);
     if (g.n > 0) {
         TimedLaunch tl(t_, TG_LEVEL, "k_init_labels", (double)g.n * 28);
-        k_init_labels<<<grid_for(g.n, 256), 256, 0, s_>>>(c_[0].p, c_[1].p, c_[2].p, labels, g.delta, deg_.p,
-                                                         size_.p, g.n);
+        tl.launch(k_init_labels, grid_for(g.n, 256), 256, 0, s_, c_[0].p, c_[1].p, c_[2].p, labels, g.delta, deg_.p,
+                  size_.p, g.n);
         LV_LAUNCHED("k_init_labels");
     }
     LV_HIP(hipMemsetAsync(st_.p, 0, sizeof(PhaseState), s_));
@@ -1168,58 +1164,60 @@ static void launch_pass(const SweepArgs &a, const int32_t *list, const int64_t *
     if constexpr (std::is_same<S, int64_t>::value) {
         if (cnt(B_T8) > 0) {
             TimedLaunch tl(t, TG_SWEEP, "k_sweep_thread<8,", bytes(B_T8), wsfx.c_str());
-            k_sweep_thread<8, W><<<grid_for(cnt(B_T8), 256), 256, 0, s>>>(a, list + bstart[B_T8], cnt(B_T8));
+            tl.launch(k_sweep_thread<8, W>, grid_for(cnt(B_T8), 256), 256, 0, s, a, list + bstart[B_T8], cnt(B_T8));
             LV_LAUNCHED("k_sweep_thread<8>");
         }
         const int64_t np = bstart[B_BLOCK] - bstart[B_T16];
         if (np > 0) {
             TimedLaunch tl(t, TG_SWEEP, "k_sweep_pack<", bytes(B_T16) + bytes(B_G64) + bytes(B_MID), wsfx.c_str());
-            k_sweep_pack<W><<<(unsigned)pack_blocks, 256, 0, s>>>(a, list + bstart[B_T16], pack_pos, pack_first);
+            tl.launch(k_sweep_pack<W>, (unsigned)pack_blocks, 256, 0, s, a, list + bstart[B_T16], pack_pos, pack_first);
             LV_LAUNCHED("k_sweep_pack");
         }
         if (cnt(B_BLOCK) > 0) {
             TimedLaunch tl(t, TG_SWEEP, "k_sweep_group<256,11,", bytes(B_BLOCK), sfx.c_str());
-            k_sweep_group<256, 11, W, S><<<(unsigned)cnt(B_BLOCK), 256, 0, s>>>(a, list + bstart[B_BLOCK],
-                                                                                cnt(B_BLOCK));
+            tl.launch(k_sweep_group<256, 11, W, S>, (unsigned)cnt(B_BLOCK), 256, 0, s, a, list + bstart[B_BLOCK],
+                      cnt(B_BLOCK));
             LV_LAUNCHED("k_sweep_group<256>");
         }
     } else {
         if (cnt(B_T8) > 0) {
             TimedLaunch tl(t, TG_SWEEP, "k_sweep_group<4,4,", bytes(B_T8), sfx.c_str());
-            k_sweep_group<4, 4, W, S><<<grid_for(cnt(B_T8), 64), 256, 0, s>>>(a, list + bstart[B_T8], cnt(B_T8));
+            tl.launch(k_sweep_group<4, 4, W, S>, grid_for(cnt(B_T8), 64), 256, 0, s, a, list + bstart[B_T8], cnt(B_T8));
             LV_LAUNCHED("k_sweep_group<4>");
         }
         if (cnt(B_T16) > 0) {
             TimedLaunch tl(t, TG_SWEEP, "k_sweep_group<16,6,", bytes(B_T16), sfx.c_str());
-            k_sweep_group<16, 6, W, S><<<grid_for(cnt(B_T16), 16), 256, 0, s>>>(a, list + bstart[B_T16], cnt(B_T16));
+            tl.launch(k_sweep_group<16, 6, W, S>, grid_for(cnt(B_T16), 16), 256, 0, s, a, list + bstart[B_T16],
+                      cnt(B_T16));
             LV_LAUNCHED("k_sweep_group<16>");
         }
         if (cnt(B_G64) > 0) {
             TimedLaunch tl(t, TG_SWEEP, "k_sweep_group<64,8,", bytes(B_G64), sfx.c_str());
-            k_sweep_group<64, 8, W, S><<<grid_for(cnt(B_G64), 4), 256, 0, s>>>(a, list + bstart[B_G64], cnt(B_G64));
+            tl.launch(k_sweep_group<64, 8, W, S>, grid_for(cnt(B_G64), 4), 256, 0, s, a, list + bstart[B_G64],
+                      cnt(B_G64));
             LV_LAUNCHED("k_sweep_group<64>");
         }
         const int64_t nb = bstart[B_HUB] - bstart[B_MID];
         if (nb > 0) {
             TimedLaunch tl(t, TG_SWEEP, "k_sweep_group<256,11,", bytes(B_MID) + bytes(B_BLOCK), sfx.c_str());
-            k_sweep_group<256, 11, W, S><<<(unsigned)nb, 256, 0, s>>>(a, list + bstart[B_MID], nb);
+            tl.launch(k_sweep_group<256, 11, W, S>, (unsigned)nb, 256, 0, s, a, list + bstart[B_MID], nb);
             LV_LAUNCHED("k_sweep_group<256>");
         }
     }
     if (hm.hubs > 0) {
         {
             TimedLaunch tl(t, TG_SWEEP, "k_hub_accum<", (double)bnnz[B_HUB] * eb, wsfx.c_str());
-            k_hub_accum<W><<<(unsigned)hub_chunks, 256, 0, s>>>(a, hm, hkey, hval, hloop);
+            tl.launch(k_hub_accum<W>, (unsigned)hub_chunks, 256, 0, s, a, hm, hkey, hval, hloop);
             LV_LAUNCHED("k_hub_accum");
         }
         {
             TimedLaunch tl(t, TG_SWEEP, "k_hub_scan<", (double)hub_scans * kHubScan * 24.0, ssfx.c_str());
-            k_hub_scan<S><<<(unsigned)hub_scans, 256, 0, s>>>(a, hm, hkey, hval, hpart);
+            tl.launch(k_hub_scan<S>, (unsigned)hub_scans, 256, 0, s, a, hm, hkey, hval, hpart);
             LV_LAUNCHED("k_hub_scan");
         }
         {
             TimedLaunch tl(t, TG_SWEEP, "k_hub_decide<", (double)hm.hubs * vb + (double)hub_scans * 32.0, ssfx.c_str());
-            k_hub_decide<S><<<grid_for(hm.hubs, 4), 256, 0, s>>>(a, hm, hpart, hloop);
+            tl.launch(k_hub_decide<S>, grid_for(hm.hubs, 4), 256, 0, s, a, hm, hpart, hloop);
             LV_LAUNCHED("k_hub_decide");
         }
     }
@@ -1235,10 +1233,10 @@ void Sweeper::e_self_out(int64_t *dst) {
 }
 
 unsigned int Sweeper::active_after(int p) {
-    unsigned int h = 0;
-    LV_HIP(hipMemcpyAsync(&h, active_.p + (p & 1), sizeof h, hipMemcpyDeviceToHost, s_));
-    LV_HIP(hipStreamSynchronize(s_));
-    return h;
+    Readback rb(s_);
+    const unsigned int *h = rb.add(active_.p + (p & 1));
+    rb.fetch();
+    return *h;
 }
 
 void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e_self_out) {
@@ -1285,7 +1283,7 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
     }
     if (g.n > 0) {
         TimedLaunch tl(t_, TG_SWEEP, "k_qsum", (double)g.n * 8);
-        k_qsum<<<(unsigned)qblocks_, 256, 0, s_>>>(deg_.p, g.n, qpart_.p, st_.p);
+        tl.launch(k_qsum, (unsigned)qblocks_, 256, 0, s_, deg_.p, g.n, qpart_.p, st_.p);
         LV_LAUNCHED("k_qsum");
     }
     SweepArgs a{g.row_ptr, g.col, g.w, c_[cur].p, c_[nxt].p, g.delta, deg_.p, size_.p,
@@ -1311,22 +1309,22 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
     }
     if (g.n > 0) {
         TimedLaunch tl(t_, TG_SWEEP, "k_commit", (double)g.n * 8);
-        k_commit<<<grid_for(g.n, 256), 256, 0, s_>>>(c_[cur].p, c_[nxt].p, g.delta, deg_.p, size_.p, g.n, st_.p);
+        tl.launch(k_commit, grid_for(g.n, 256), 256, 0, s_, c_[cur].p, c_[nxt].p, g.delta, deg_.p, size_.p, g.n, st_.p);
         LV_LAUNCHED("k_commit");
     }
     {
         TimedLaunch tl(t_, TG_SWEEP, "k_finalize", 0.0);
-        k_finalize<<<1, 256, 0, s_>>>(st_.p, qpart_.p, qblocks_, g.tw, prm.theta_num, prm.theta_den,
-                                      prm.max_sweeps, p);
+        tl.launch(k_finalize, 1, 256, 0, s_, st_.p, qpart_.p, qblocks_, g.tw, prm.theta_num, prm.theta_den,
+                  prm.max_sweeps, p);
         LV_LAUNCHED("k_finalize");
     }
 }
 
 PhaseState Sweeper::read_state() {
-    PhaseState h;
-    LV_HIP(hipMemcpyAsync(&h, st_.p, sizeof h, hipMemcpyDeviceToHost, s_));
-    LV_HIP(hipStreamSynchronize(s_));
-    return h;
+    Readback rb(s_);
+    const PhaseState *h = rb.add(st_.p);
+    rb.fetch();
+    return *h;
 }
 
 }  // namespace lv

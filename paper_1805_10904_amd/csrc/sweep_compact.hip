@@ -477,19 +477,6 @@ __global__ __launch_bounds__(256) void k_cpt_group(CArgs a, const int32_t *__res
             d = a.row_ptr[v + 1] - rs;
         }
     }
-    __syncthreads();
-    uint32_t loop = 0;
-    for (int64_t x = li; x < d; x += G) {
-        const int32_t j = a.col[rs + x];
-        const uint32_t w = cw<W>(a.w, rs + x);
-        if (j == v) {
-            loop += w;
-            continue;
-        }
-        const uint64_t nw = a.vw[j];
-        grp_insert(key, es, hs, BITS, vw_label(nw), w, (uint32_t)(nw >> 32));
-    }
-    __syncthreads();
     int32_t ci = -1;
     uint32_t own_hi = 0;
     int64_t di = 0, tw = 0;
@@ -500,6 +487,39 @@ __global__ __launch_bounds__(256) void k_cpt_group(CArgs a, const int32_t *__res
         di = a.delta[v];
         tw = a.tw[g];
     }
+    __syncthreads();
+    // Entries in rounds of U per lane: a round's loads and gathers are all
+    // issued before its inserts.
+    constexpr int U = 4;
+    uint32_t loop = 0;
+    for (int64_t x0 = li; x0 < d; x0 += (int64_t)U * G) {
+        int32_t jq[U];
+        uint32_t wq[U];
+        uint64_t nq[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int64_t x = x0 + (int64_t)q * G;
+            jq[q] = v;
+            wq[q] = 0;
+            if (x < d) {
+                jq[q] = a.col[rs + x];
+                wq[q] = cw<W>(a.w, rs + x);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            nq[q] = 0;
+            if (jq[q] != v) nq[q] = a.vw[jq[q]];
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            if (jq[q] == v)
+                loop += wq[q];
+            else
+                grp_insert(key, es, hs, BITS, vw_label(nq[q]), wq[q], (uint32_t)(nq[q] >> 32));
+        }
+    }
+    __syncthreads();
     unsigned long long bok = 0;
     uint32_t blf = 0xffffffffu, e_own = 0;
 #pragma unroll
@@ -604,19 +624,27 @@ __global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__re
             d = a.row_ptr[v + 1] - rs;
         }
     }
-    __syncthreads();
+    // A class-c row has d <= 2S/3 < 3G entries, so every lane holds at most
+    // three: their loads and gathers are all issued before the first insert.
+    int32_t jq[3];
+    uint32_t wq[3];
+    uint64_t nq[3];
     uint32_t loop = 0;
-    for (int64_t x = li; x < d; x += G) {
-        const int32_t j = a.col[rs + x];
-        const uint32_t w = cw<W>(a.w, rs + x);
-        if (j == v) {
-            loop += w;
-            continue;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int64_t x = li + (int64_t)q * G;
+        jq[q] = v;
+        wq[q] = 0;
+        if (x < d) {
+            jq[q] = a.col[rs + x];
+            wq[q] = cw<W>(a.w, rs + x);
         }
-        const uint64_t nw = a.vw[j];
-        grp_insert(key, es, hs, bits, vw_label(nw), w, (uint32_t)(nw >> 32));
     }
-    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        nq[q] = 0;
+        if (jq[q] != v) nq[q] = a.vw[jq[q]];
+    }
     int32_t ci = -1;
     uint32_t own_hi = 0;
     int64_t di = 0, tw = 0;
@@ -627,6 +655,25 @@ __global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__re
         di = a.delta[v];
         tw = a.tw[g];
     }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        if (jq[q] == v)
+            loop += wq[q];
+        else
+            grp_insert(key, es, hs, bits, vw_label(nq[q]), wq[q], (uint32_t)(nq[q] >> 32));
+    }
+    for (int64_t x = li + 3 * (int64_t)G; x < d; x += G) {   // not reached for class rows
+        const int32_t j = a.col[rs + x];
+        const uint32_t w = cw<W>(a.w, rs + x);
+        if (j == v) {
+            loop += w;
+            continue;
+        }
+        const uint64_t nw = a.vw[j];
+        grp_insert(key, es, hs, bits, vw_label(nw), w, (uint32_t)(nw >> 32));
+    }
+    __syncthreads();
     unsigned long long bok = 0;
     uint32_t blf = 0xffffffffu, e_own = 0;
 #pragma unroll
@@ -818,16 +865,34 @@ __global__ __launch_bounds__(256) void k_cpt_hub_accum(CArgs a, CHub hm, unsigne
     const int64_t row_end = a.row_ptr[v + 1];
     const int64_t rs = a.row_ptr[v] + k * kHubChunk;
     const int64_t re = rs + kHubChunk < row_end ? rs + kHubChunk : row_end;
-    for (int64_t e = rs + t; e < re; e += 256) {
-        const int32_t j = a.col[e];
-        const uint32_t w = cw<W>(a.w, e);
-        if (j == v) {
-            atomicAdd(&hub_loop[h], (unsigned long long)w);
-            continue;
+    // kHubChunk / 256 entries per lane: loads and gathers first, then inserts.
+    constexpr int U = kHubChunk / 256;
+    static_assert(kHubChunk % 256 == 0, "a chunk is whole rounds of the workgroup");
+    int32_t jq[U];
+    uint32_t wq[U];
+    int32_t lq[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+        const int64_t e = rs + t + q * 256;
+        jq[q] = -1;
+        wq[q] = 0;
+        if (e < re) {
+            jq[q] = a.col[e];
+            wq[q] = cw<W>(a.w, e);
         }
-        const int32_t l = vw_label(a.vw[j]);
-        word_insert(s_tab, T, ((uint32_t)l * 0x9E3779B1u) >> (32 - kCHubLdsBits), l, w);
     }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+        lq[q] = -1;
+        if (jq[q] >= 0 && jq[q] != v) lq[q] = vw_label(a.vw[jq[q]]);
+    }
+    uint32_t loop = 0;
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+        if (jq[q] == v) loop += wq[q];
+        if (lq[q] >= 0) word_insert(s_tab, T, ((uint32_t)lq[q] * 0x9E3779B1u) >> (32 - kCHubLdsBits), lq[q], wq[q]);
+    }
+    if (loop) atomicAdd(&hub_loop[h], (unsigned long long)loop);
     __syncthreads();
     const int64_t base = hm.tab_off[h], size = hm.tab_size[h];
     for (int x = t; x < T; x += 256) {
@@ -979,25 +1044,23 @@ void compact_classes(const int64_t *rp, const int32_t *list, int64_t m, int32_t 
     fill<uint64_t>(enz.as<uint64_t>(), 0, kLdsClasses, s);
     {
         TimedLaunch tl(t, TG_LEVEL, "k_class_count", (double)m * 20);
-        k_class_count<<<(unsigned)nblk, 256, 0, s>>>(rp, list, m, counts.as<int32_t>(), nblk,
-                                                    enz.as<unsigned long long>());
+        tl.launch(k_class_count, (unsigned)nblk, 256, 0, s, rp, list, m, counts.as<int32_t>(), nblk,
+                  enz.as<unsigned long long>());
         LV_LAUNCHED("k_class_count");
     }
     scan_exclusive<int32_t, int32_t>(counts.as<int32_t>(), counts.as<int32_t>(), cm, counts.as<int32_t>() + cm, s, t);
     {
         TimedLaunch tl(t, TG_LEVEL, "k_class_scatter", (double)m * 24);
-        k_class_scatter<<<(unsigned)nblk, 256, 0, s>>>(rp, list, m, counts.as<int32_t>(), nblk, out);
+        tl.launch(k_class_scatter, (unsigned)nblk, 256, 0, s, rp, list, m, counts.as<int32_t>(), nblk, out);
         LV_LAUNCHED("k_class_scatter");
     }
-    int32_t hs[kLdsClasses];
-    for (int c = 0; c < kLdsClasses; ++c)
-        LV_HIP(hipMemcpyAsync(&hs[c], counts.as<int32_t>() + (int64_t)c * nblk, sizeof(int32_t), hipMemcpyDeviceToHost,
-                              s));
-    unsigned long long hn[kLdsClasses];
-    LV_HIP(hipMemcpyAsync(hn, enz.p, sizeof hn, hipMemcpyDeviceToHost, s));
-    LV_HIP(hipStreamSynchronize(s));
+    Readback rb(s);
+    const int32_t *hs[kLdsClasses];
+    for (int c = 0; c < kLdsClasses; ++c) hs[c] = rb.add(counts.as<int32_t>() + (int64_t)c * nblk);
+    const unsigned long long *hn = rb.add(enz.as<unsigned long long>(), kLdsClasses);
+    rb.fetch();
     for (int c = 0; c < kLdsClasses; ++c) {
-        cstart[c] = hs[c];
+        cstart[c] = *hs[c];
         cnnz[c] = (int64_t)hn[c];
     }
     cstart[kLdsClasses] = m;
@@ -1021,7 +1084,7 @@ void compact_final_labels(const int32_t *c0, const int32_t *c1, const int32_t *c
                           const PhaseState *st, int64_t n, int32_t *out, hipStream_t s, Timer *t) {
     if (n <= 0) return;
     TimedLaunch tl(t, TG_CONTRACT, "k_cpt_final_labels", (double)n * 12);
-    k_cpt_final_labels<<<grid_for(n, 256), 256, 0, s>>>(c0, c1, c2, gid, st, n, out);
+    tl.launch(k_cpt_final_labels, grid_for(n, 256), 256, 0, s, c0, c1, c2, gid, st, n, out);
     LV_LAUNCHED("k_cpt_final_labels");
 }
 
@@ -1045,7 +1108,7 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
     };
     if (cp.bstart[B_T16] - cp.bstart[B_T8] > 0) {
         TimedLaunch tl(t, TG_SWEEP, "k_cpt_small<", bytes(B_T8, B_T16), sfx.c_str());
-        k_cpt_small<W><<<grid_for(cp.n, 256), 256, 0, s>>>(a, cp.n, cp.small_max);
+        tl.launch(k_cpt_small<W>, grid_for(cp.n, 256), 256, 0, s, a, cp.n, cp.small_max);
         LV_LAUNCHED("k_cpt_small");
     }
     {
@@ -1061,7 +1124,7 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
         for (int c = 0; c <= kGroupClasses; ++c) gb.cstart[c] = cp.cstart[c];
         if (gb.bo[kGroupClasses] > 0) {
             TimedLaunch tl(t, TG_SWEEP, "k_cpt_groups<", gbytes, sfx.c_str());
-            k_cpt_groups<W><<<(unsigned)gb.bo[kGroupClasses], 256, 0, s>>>(a, cp.glist, gb);
+            tl.launch(k_cpt_groups<W>, (unsigned)gb.bo[kGroupClasses], 256, 0, s, a, cp.glist, gb);
             LV_LAUNCHED("k_cpt_groups");
         }
     }
@@ -1071,14 +1134,14 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
         if (nw > 0) {
             TimedLaunch tl(t, TG_SWEEP, "k_cpt_group<2048,256,", (double)nw * vb + (double)cp.cnnz[c] * eb,
                            sfx.c_str());
-            k_cpt_group<2048, 256, W><<<(unsigned)nw, 256, 0, s>>>(a, cp.glist + cp.cstart[c], nw);
+            tl.launch(k_cpt_group<2048, 256, W>, (unsigned)nw, 256, 0, s, a, cp.glist + cp.cstart[c], nw);
             LV_LAUNCHED("k_cpt_group<2048>");
         }
         const int64_t nx = cp.cstart[c + 2] - cp.cstart[c + 1];
         if (nx > 0) {
             TimedLaunch tl(t, TG_SWEEP, "k_cpt_group<4096,256,", (double)nx * vb + (double)cp.cnnz[c + 1] * eb,
                            sfx.c_str());
-            k_cpt_group<4096, 256, W><<<(unsigned)nx, 256, 0, s>>>(a, cp.glist + cp.cstart[c + 1], nx);
+            tl.launch(k_cpt_group<4096, 256, W>, (unsigned)nx, 256, 0, s, a, cp.glist + cp.cstart[c + 1], nx);
             LV_LAUNCHED("k_cpt_group<4096>");
         }
     }
@@ -1087,17 +1150,17 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
                 cp.chunk_hub, cp.scan_hub, cp.hubs};
         {
             TimedLaunch tl(t, TG_SWEEP, "k_cpt_hub_accum<", (double)cp.bnnz[B_HUB] * eb, sfx.c_str());
-            k_cpt_hub_accum<W><<<(unsigned)cp.hub_chunks, 256, 0, s>>>(a, hm, cp.hval, cp.hloop);
+            tl.launch(k_cpt_hub_accum<W>, (unsigned)cp.hub_chunks, 256, 0, s, a, hm, cp.hval, cp.hloop);
             LV_LAUNCHED("k_cpt_hub_accum");
         }
         {
             TimedLaunch tl(t, TG_SWEEP, "k_cpt_hub_scan", (double)cp.hub_scans * kHubScan * 16.0);
-            k_cpt_hub_scan<<<(unsigned)cp.hub_scans, 256, 0, s>>>(a, hm, cp.hval, cp.hpart);
+            tl.launch(k_cpt_hub_scan, (unsigned)cp.hub_scans, 256, 0, s, a, hm, cp.hval, cp.hpart);
             LV_LAUNCHED("k_cpt_hub_scan");
         }
         {
             TimedLaunch tl(t, TG_SWEEP, "k_cpt_hub_decide", (double)cp.hubs * vb + (double)cp.hub_scans * 32.0);
-            k_cpt_hub_decide<<<grid_for(cp.hubs, 4), 256, 0, s>>>(a, hm, cp.hpart, cp.hloop);
+            tl.launch(k_cpt_hub_decide, grid_for(cp.hubs, 4), 256, 0, s, a, hm, cp.hpart, cp.hloop);
             LV_LAUNCHED("k_cpt_hub_decide");
         }
     }
@@ -1107,8 +1170,8 @@ void compact_pass(const GraphView &g, const CompactPass &cp, const CompactState 
                   const SweepParams &prm, hipStream_t s, Timer *t) {
     if (g.n > 0) {
         TimedLaunch tl(t, TG_SWEEP, "k_cpt_publish", (double)g.n * 28);
-        k_cpt_publish<<<grid_for(g.n, kPubTile), 256, 0, s>>>(cs.ds, cs.c_cur, cs.vw, cs.gid, cs.st, g.n,
-                                                              cs.active + (p & 1));
+        tl.launch(k_cpt_publish, grid_for(g.n, kPubTile), 256, 0, s, cs.ds, cs.c_cur, cs.vw, cs.gid, cs.st, g.n,
+                  cs.active + (p & 1));
         LV_LAUNCHED("k_cpt_publish");
     }
     CArgs a{g.row_ptr, g.col, g.w, cs.c_cur, cs.c_nxt, g.delta, cs.vw, cs.ds, cs.gid, cs.tw, cs.st, cs.es, prm.singlet};
@@ -1118,15 +1181,14 @@ void compact_pass(const GraphView &g, const CompactPass &cp, const CompactState 
         compact_sweeps<int64_t>(a, cp, s, t);
     if (g.n > 0) {
         TimedLaunch tl(t, TG_SWEEP, "k_cpt_commit", (double)g.n * 12);
-        k_cpt_commit<<<grid_for(g.n, kCommitTile), 256, 0, s>>>(cs.c_cur, cs.c_nxt, g.delta, cs.es, cs.ds, cs.gid,
-                                                                cs.st, g.n);
+        tl.launch(k_cpt_commit, grid_for(g.n, kCommitTile), 256, 0, s, cs.c_cur, cs.c_nxt, g.delta, cs.es, cs.ds,
+                  cs.gid, cs.st, g.n);
         LV_LAUNCHED("k_cpt_commit");
     }
     {
         TimedLaunch tl(t, TG_SWEEP, "k_cpt_finalize", 0.0);
-        k_cpt_finalize<<<grid_for(cs.ngraphs, 256), 256, 0, s>>>(cs.st, cs.tw, cs.ngraphs, prm.theta_num,
-                                                                 prm.theta_den, prm.max_sweeps, p,
-                                                                 cs.active + (p & 1));
+        tl.launch(k_cpt_finalize, grid_for(cs.ngraphs, 256), 256, 0, s, cs.st, cs.tw, cs.ngraphs, prm.theta_num,
+                  prm.theta_den, prm.max_sweeps, p, cs.active + (p & 1));
         LV_LAUNCHED("k_cpt_finalize");
     }
 }
