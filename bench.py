@@ -10,8 +10,9 @@ with the final labels written to device memory.
 value = local-move GTEPS of the whole job: the method's executed sweeps
 (including each phase's final discarded one) times the edge entries of
 their level's graph, divided by the wall time of the step.  Per-kernel
-device times come from HIP events recorded around every launch on the
-library's stream during the timed steps.
+device times come from HIP events that the kernel dispatches themselves
+fill (hipExtLaunchKernel) on the library's stream: every launch in the last
+warm-up step, the dominant kernel's launches in the timed steps.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -273,7 +274,7 @@ def main():
         log(f"autotuned launch shapes in {time.time() - t:.2f}s: {tuning} ({best['ms']:.3f} ms per run)")
 
     # warm-up steps; the first one records every kernel to find the dominant one,
-    # whose launches alone carry HIP events in the timed steps
+    # whose launches alone are timed in the timed steps
     # (the last warm-up step, at least the second, is the one timed in full)
     dominant = None
     table = None

@@ -103,19 +103,38 @@ def csr_from_canonical_keys(n: int, keys: np.ndarray, salt: int, weight_fn) -> t
     allk = np.concatenate([keys, rev])
     del rev
     allk.sort()
-    rows = (allk >> np.uint64(32)).astype(np.int64)
-    cols = (allk & _M32).astype(np.int64)
-    del allk
-    counts = np.bincount(rows, minlength=n) if rows.size else np.zeros(n, np.int64)
+    return _csr_from_entry_keys(n, allk, salt, weight_fn)
+
+
+def _csr_from_entry_keys(n: int, allk: np.ndarray, salt: int, weight_fn, pool=None) -> tuple:
+    """CSR from the sorted unique entry keys row << 32 | col of a symmetric
+    graph; the weight of an entry comes from its canonical pair key.  With a
+    thread pool, the per-entry work is split into slices."""
+    m = allk.size
     row_ptr = np.zeros(n + 1, dtype=np.int64)
-    np.cumsum(counts, out=row_ptr[1:])
-    lo = np.minimum(rows, cols).astype(np.uint64)
-    hi = np.maximum(rows, cols).astype(np.uint64)
-    del rows
-    ck = (lo << np.uint64(32)) | hi
-    del lo, hi
-    w = weight_fn(splitmix64(ck ^ np.uint64(salt)))
-    return row_ptr, cols.astype(np.int32), w
+    col = np.empty(m, np.int32)
+    w = np.empty(m, np.int32)
+
+    def part(lo_hi):
+        a, b = lo_hi
+        k = allk[a:b]
+        r = k >> np.uint64(32)
+        c = k & _M32
+        col[a:b] = c.astype(np.int32)
+        ck = (np.minimum(r, c) << np.uint64(32)) | np.maximum(r, c)
+        w[a:b] = weight_fn(splitmix64(ck ^ np.uint64(salt)))
+
+    step = max(1, 1 << 22)
+    slices = [(a, min(m, a + step)) for a in range(0, m, step)]
+    if pool is not None and len(slices) > 1:
+        list(pool.map(part, slices))
+    else:
+        for sl in slices:
+            part(sl)
+    if m:
+        # first entry of every row: rows are the high words of the sorted keys
+        row_ptr[:] = np.searchsorted(allk, np.arange(n + 1, dtype=np.uint64) << np.uint64(32))
+    return row_ptr, col, w
 
 
 def sbm_dense(n: int, nblocks: int, p_in: float, p_out: float, wmax: int, seed: int,
@@ -232,21 +251,30 @@ def chung_lu(n: int, gamma: float, mean_deg: float, nblocks: int, mixing: float,
 
 
 def rmat(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int,
-         weight_fn, name: str = "rmat", chunk: int = 1 << 23) -> Graph:
+         weight_fn, name: str = "rmat", chunk: int = 1 << 22, threads: Optional[int] = None) -> Graph:
     """R-MAT graph (Chakrabarti, Zhan and Faloutsos, SDM 2004): each edge picks
     one adjacency-matrix quadrant per bit with probabilities (a, b, c, d), no
-    noise.  Vertex IDs go through a seeded permutation; the result is
-    symmetrised, deduplicated and loop-free."""
+    noise.  Edges are drawn in chunks of ``chunk``, chunk i from its own
+    PCG64 stream seeded (seed, i); vertex IDs go through a permutation seeded
+    by ``seed``; the result is symmetrised, deduplicated and loop-free.  The
+    chunks, the sort and the weights run on a thread pool (numpy releases
+    the interpreter lock in them); the graph does not depend on ``threads``."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+
     n = 1 << scale
     m = edge_factor * n
-    rng = np.random.default_rng(seed)
-    perm = rng.permutation(n).astype(np.uint64)
+    perm = np.random.default_rng(seed).permutation(n).astype(np.uint64)
     ab = a + b
     abc = a + b + c
-    parts = []
-    done = 0
-    while done < m:
-        k = min(chunk, m - done)
+    nchunks = (m + chunk - 1) // chunk
+    nb = min(64, n)                                   # row ranges of the merge
+    bounds = (np.arange(nb + 1, dtype=np.uint64) * np.uint64(n // nb)) << np.uint64(32)
+    bounds[-1] = np.uint64(n) << np.uint64(32)
+
+    def draw(i):
+        k = min(chunk, m - i * chunk)
+        rng = np.random.default_rng([seed, i])
         u = np.zeros(k, dtype=np.uint64)
         v = np.zeros(k, dtype=np.uint64)
         for bit in range(scale):
@@ -255,11 +283,31 @@ def rmat(scale: int, edge_factor: int, a: float, b: float, c: float, seed: int,
             vbit = ((r >= a) & (r < ab)) | (r >= abc)
             u |= ubit.astype(np.uint64) << np.uint64(bit)
             v |= vbit.astype(np.uint64) << np.uint64(bit)
-        parts.append(canonical_keys(perm[u], perm[v]))
-        done += k
-    keys = np.unique(np.concatenate(parts)) if len(parts) > 1 else parts[0]
-    del parts
-    rp, col, w = csr_from_canonical_keys(n, keys, seed, weight_fn)
+        u = perm[u]
+        v = perm[v]
+        keep = u != v
+        u = u[keep]
+        v = v[keep]
+        ent = np.concatenate([(u << np.uint64(32)) | v, (v << np.uint64(32)) | u])
+        ent.sort()
+        cut = np.searchsorted(ent, bounds)
+        return [ent[cut[j]:cut[j + 1]] for j in range(nb)]
+
+    def merge(j):
+        x = np.concatenate([p[j] for p in parts])
+        x.sort()
+        if x.size:
+            x = x[np.concatenate(([True], x[1:] != x[:-1]))]
+        return x
+
+    workers = threads or min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(workers) as pool:
+        parts = list(pool.map(draw, range(nchunks)))
+        merged = list(pool.map(merge, range(nb)))
+        del parts
+        allk = np.concatenate(merged)
+        del merged
+        rp, col, w = _csr_from_entry_keys(n, allk, seed, weight_fn, pool)
     return Graph(n, rp, col, w, None, name)
 
 

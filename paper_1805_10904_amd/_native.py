@@ -396,8 +396,9 @@ class Context:
             device: Optional[bool] = None, labels_out=None) -> RunResult:
         """The whole method (Alg. 2 over Alg. 1 phases).
 
-        timing: False, True (HIP events around every launch) or a kernel
-        name as it appears in stats["kernels"] (events around its launches only)."""
+        timing: False, True (device time of every launch, from HIP events
+        filled by the dispatches) or a kernel name as it appears in
+        stats["kernels"] (only its launches are timed)."""
         dev = g.dev if device is None else device
         n, _, _ = g.info()
         out = labels_out if labels_out is not None else _empty_like_kind(dev, n, np.int32, self.torch_device)

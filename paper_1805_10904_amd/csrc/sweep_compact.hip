@@ -176,52 +176,66 @@ __global__ __launch_bounds__(256) void k_cpt_publish(const uint64_t *__restrict_
     const int64_t base = (int64_t)blockIdx.x * kPubTile;
     const int64_t last = base + kPubTile - 1 < n - 1 ? base + kPubTile - 1 : n - 1;
     const SpanSums sp = span_begin(gid, base, last, &s_glo, &s_span, acc);
+    // per-thread sums while consecutive vertices share a graph
+    int gcur = -1;
+    unsigned long long sum = 0;
 #pragma unroll
     for (int k = 0; k < kPubTile / 256; ++k) {
         const int64_t v = base + k * 256 + threadIdx.x;
         if (v > last) continue;
         const int g = graph_of(gid, v);
         if (st[g].done) continue;
+        if (g != gcur) {
+            if (gcur >= 0) span_add(sp, acc, 1, gcur, sum, st, 2);
+            gcur = g;
+            sum = 0;
+        }
         const uint64_t d = (uint32_t)ds[v];
-        span_add(sp, acc, 1, g, d * d, st, 2);
+        sum += d * d;
         const int32_t cv = c[v];
         vw[v] = vw_make(cv, ds[cv]);
     }
+    if (gcur >= 0) span_add(sp, acc, 1, gcur, sum, st, 2);
     span_flush(sp, acc, st, -1, 2);
 }
 
 // ------------------------------------------------------------------ commit --
 
-constexpr int kCommitTile = 512;
-constexpr int kCommitBits = 11;   // LDS table of 2^11 slots: at most two updates per vertex of the tile
+constexpr int kCommitTile = 2048;
+constexpr int kCommitBits = 12;    // LDS table of 2^12 slots
+constexpr int kCommitProbe = 32;   // probes before an update goes straight to HBM
 
-// Add x to community k's pending update in the workgroup's LDS table.
-__device__ __forceinline__ void commit_insert(int32_t *key, unsigned long long *val, int32_t k,
+// Add x to community k's pending update in the workgroup's LDS table;
+// false if no slot was found within kCommitProbe probes.
+__device__ __forceinline__ bool commit_insert(int32_t *key, unsigned long long *val, int32_t k,
                                               unsigned long long x) {
     constexpr uint32_t mask = (1u << kCommitBits) - 1;
     uint32_t h = ((uint32_t)k * 0x9E3779B1u) >> (32 - kCommitBits);
-    while (true) {
+    for (int probe = 0; probe < kCommitProbe; ++probe) {
         const int32_t cur = ((volatile int32_t *)key)[h];
         if (cur == k) {
             atomicAdd(&val[h], x);
-            return;
+            return true;
         }
         if (cur == kEmpty) {
             const int32_t prev = atomicCAS(&key[h], kEmpty, k);
             if (prev == kEmpty || prev == k) {
                 atomicAdd(&val[h], x);
-                return;
+                return true;
             }
         }
         h = (h + 1) & mask;
     }
+    return false;
 }
 
 // Movers' community updates (size +-1, degree +-delta in one word) are
 // summed per community in LDS first, so a community that many vertices of
-// the tile join or leave takes one global atomic instead of one per mover
-// (the sums are integers modulo 2^64, so the result does not depend on the
-// order).
+// the tile join or leave takes one global atomic instead of one per mover;
+// a tile of 2,048 vertices keeps the atomics on a large community's word to
+// one per tile.  Updates that find no LDS slot (tiles where most vertices
+// move between distinct communities) go to HBM directly.  The sums are
+// integers modulo 2^64, so the result does not depend on the order.
 __global__ __launch_bounds__(256) void k_cpt_commit(const int32_t *__restrict__ c_cur, const int32_t *__restrict__ c_nxt,
                                                     const int64_t *__restrict__ delta, const uint32_t *__restrict__ es,
                                                     uint64_t *ds, const int32_t *__restrict__ gid, PhaseState *st,
@@ -238,20 +252,38 @@ __global__ __launch_bounds__(256) void k_cpt_commit(const int32_t *__restrict__ 
     const int64_t base = (int64_t)blockIdx.x * kCommitTile;
     const int64_t last = base + kCommitTile - 1 < n - 1 ? base + kCommitTile - 1 : n - 1;
     const SpanSums sp = span_begin(gid, base, last, &s_glo, &s_span, acc);
-#pragma unroll
+    // per-thread sums while consecutive vertices share a graph
+    int gcur = -1;
+    unsigned long long sum_e = 0, sum_m = 0;
+#pragma unroll 2
     for (int k = 0; k < kCommitTile / 256; ++k) {
         const int64_t v = base + k * 256 + threadIdx.x;
         if (v > last) continue;
         const int g = graph_of(gid, v);
         if (st[g].done) continue;
+        if (g != gcur) {
+            if (gcur >= 0) {
+                span_add(sp, acc, 0, gcur, sum_e, st, 0);
+                span_add(sp, acc, 1, gcur, sum_m, st, 1);
+            }
+            gcur = g;
+            sum_e = 0;
+            sum_m = 0;
+        }
         const int32_t from = c_cur[v], to = c_nxt[v];
         if (from != to) {
             const uint64_t inc = kSizeOne + (uint64_t)delta[v];
-            commit_insert(s_key, s_val, to, (unsigned long long)inc);
-            commit_insert(s_key, s_val, from, (unsigned long long)(0 - inc));
-            span_add(sp, acc, 1, g, 1, st, 1);
+            if (!commit_insert(s_key, s_val, to, (unsigned long long)inc))
+                atomicAdd((unsigned long long *)&ds[to], (unsigned long long)inc);
+            if (!commit_insert(s_key, s_val, from, (unsigned long long)(0 - inc)))
+                atomicAdd((unsigned long long *)&ds[from], (unsigned long long)(0 - inc));
+            sum_m += 1;
         }
-        span_add(sp, acc, 0, g, es[v], st, 0);
+        sum_e += es[v];
+    }
+    if (gcur >= 0) {
+        span_add(sp, acc, 0, gcur, sum_e, st, 0);
+        span_add(sp, acc, 1, gcur, sum_m, st, 1);
     }
     __syncthreads();
     for (int x = threadIdx.x; x < T; x += 256) {
