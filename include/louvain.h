@@ -260,7 +260,8 @@ typedef struct {
                             tables (341..2730; default 2730)                             */
     int32_t pass_batch;  /* sweep passes between host checks when the run's params say 0
                             (1..64; default 1)                                           */
-    int32_t reserved;
+    int32_t group_slots; /* LDS table slots scored per lane for rows of up to 341 entries
+                            (2, 4 or 8; 0 = 4): fewer lanes per row, more work per lane */
     double ms;           /* louvain_autotune: device time of one run with this setting */
 } louvain_tuning;
 
@@ -273,7 +274,8 @@ int louvain_get_tuning(louvain_ctx ctx, louvain_tuning *tuning);
 /*
  * Autotuner: times one whole run of the method on g (params as for
  * louvain_run) under each candidate setting (small_max in {4, 8},
- * block_max in {1024, 1365, 2730}, pass_batch in {1, 2}), best of two runs
+ * block_max in {1024, 1365, 2730}, pass_batch in {1, 2}, group_slots in
+ * {2, 4, 8}), best of two runs
  * each, and makes the fastest the context's setting.  *best (optional)
  * receives it with its time.  Graphs with 2W >= 2^31 do not use these
  * shapes; the setting is left as it is and best->ms is -1.

@@ -250,9 +250,12 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
         sw.reserve(n0, nnz0);
         ct.reserve(n0, nnz0);
         DevBuf<int32_t> newlab((size_t)n0);
+        // levels below 2^31 total weight keep int32 weights (every weight
+        // of a contracted graph is at most 2W)
+        const bool narrow = g0.tw < lv::kCompactTwMax;
         struct LevelGraph {
-            DevBuf<int64_t> rp, delta, w;
-            DevBuf<int32_t> col;
+            DevBuf<int64_t> rp, delta, w64;
+            DevBuf<int32_t> col, w32;
         } lg[2];
         int which = 0;
         const lv::SweepParams sp = sweep_params(prm);
@@ -302,18 +305,21 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
             if (!nb.rp.p) {
                 nb.rp.alloc((size_t)n0 + 1);
                 nb.delta.alloc((size_t)n0);
-                nb.w.alloc((size_t)nnz0);
+                if (narrow)
+                    nb.w32.alloc((size_t)nnz0);
+                else
+                    nb.w64.alloc((size_t)nnz0);
                 nb.col.alloc((size_t)nnz0);
             }
-            const int64_t m2 = ct.contract(v, newlab.p, k, nb.rp.p, nb.col.p, nb.w.p);
-            lv::row_sums_i64(k, m2, nb.rp.p, nb.w.p, nb.delta.p, s, t);
+            void *wout = narrow ? (void *)nb.w32.p : (void *)nb.w64.p;
+            const int64_t m2 = ct.contract(v, newlab.p, k, nb.rp.p, nb.col.p, wout, narrow ? 4 : 8, nb.delta.p);
             lv::GraphView v2;
             v2.n = k;
             v2.nnz = m2;
             v2.row_ptr = nb.rp.p;
             v2.col = nb.col.p;
-            v2.w = nb.w.p;
-            v2.wbytes = 8;
+            v2.w = wout;
+            v2.wbytes = narrow ? 4 : 8;
             v2.delta = nb.delta.p;
             v2.tw = g0.tw;
             v = v2;
@@ -510,8 +516,7 @@ int louvain_aggregate(louvain_ctx ctx, louvain_graph g, const int32_t *labels, i
         g2->col.alloc((size_t)g->nnz);
         g2->w64.alloc((size_t)g->nnz);
         g2->delta.alloc((size_t)k);
-        g2->nnz = ct.contract(g->view(), newlab.p, k, g2->row_ptr.p, g2->col.p, g2->w64.p, true);
-        lv::row_sums_i64(k, g2->nnz, g2->row_ptr.p, g2->w64.p, g2->delta.p, s, t);
+        g2->nnz = ct.contract(g->view(), newlab.p, k, g2->row_ptr.p, g2->col.p, g2->w64.p, 8, g2->delta.p, true);
         g2->tw = g->tw;
         copy_out(renumber_out, newlab.p, g->n, device_ptrs(flags), s);
         LV_HIP(hipStreamSynchronize(s));
@@ -565,9 +570,13 @@ int louvain_set_tuning(louvain_ctx ctx, const louvain_tuning *tuning) {
                     "block_max must be in [341, 2730]");
             require(tuning->pass_batch >= 1 && tuning->pass_batch <= 64, LOUVAIN_EINVAL,
                     "pass_batch must be in [1, 64]");
+            require(tuning->group_slots == 0 || tuning->group_slots == 2 || tuning->group_slots == 4 ||
+                        tuning->group_slots == 8,
+                    LOUVAIN_EINVAL, "group_slots must be 0, 2, 4 or 8");
             tn.small_max = tuning->small_max;
             tn.block_max = tuning->block_max;
             tn.pass_batch = tuning->pass_batch;
+            tn.group_slots = tuning->group_slots == 0 ? 4 : tuning->group_slots;
         }
         ctx->tuning = tn;
     });
@@ -579,6 +588,7 @@ int louvain_get_tuning(louvain_ctx ctx, louvain_tuning *tuning) {
     tuning->small_max = ctx->tuning.small_max;
     tuning->block_max = (int32_t)ctx->tuning.block_max;
     tuning->pass_batch = ctx->tuning.pass_batch;
+    tuning->group_slots = ctx->tuning.group_slots;
     return LOUVAIN_OK;
 }
 
@@ -622,17 +632,19 @@ int louvain_autotune(louvain_ctx ctx, louvain_graph g, const louvain_params *par
         double pick_ms = 1e30;
         for (int sm : {4, 8})
             for (int64_t bm : {(int64_t)1024, (int64_t)1365, lv::kCompactBlockMax})
-                for (int pb : {1, 2}) {
-                    lv::Tuning tn;
-                    tn.small_max = sm;
-                    tn.block_max = bm;
-                    tn.pass_batch = pb;
-                    const double ms = std::min(time_run(tn), time_run(tn));
-                    if (ms < pick_ms) {
-                        pick_ms = ms;
-                        pick = tn;
+                for (int pb : {1, 2})
+                    for (int gs : {2, 4, 8}) {
+                        lv::Tuning tn;
+                        tn.small_max = sm;
+                        tn.block_max = bm;
+                        tn.pass_batch = pb;
+                        tn.group_slots = gs;
+                        const double ms = std::min(time_run(tn), time_run(tn));
+                        if (ms < pick_ms) {
+                            pick_ms = ms;
+                            pick = tn;
+                        }
                     }
-                }
         ctx->tuning = pick;
         if (best) {
             louvain_get_tuning(ctx, best);

@@ -192,14 +192,11 @@ void BatchEngine::admit(BatchMember *m) {
     pending_.push_back(m);
 }
 
-void BatchEngine::ensure(UBuf &u, int64_t n, int64_t m, bool wide, int64_t keep_n, int64_t keep_m) {
+void BatchEngine::ensure(UBuf &u, int64_t n, int64_t m, int64_t keep_n, int64_t keep_m) {
     grow(u.rp, (size_t)n + 1, keep_n > 0 ? (size_t)keep_n + 1 : 0, s_);
     grow(u.delta, (size_t)(n > 0 ? n : 1), (size_t)keep_n, s_);
     grow(u.col, (size_t)(m > 0 ? m : 1), (size_t)keep_m, s_);
-    if (wide)
-        grow(u.w64, (size_t)(m > 0 ? m : 1), (size_t)keep_m, s_);
-    else
-        grow(u.w32, (size_t)(m > 0 ? m : 1), 0, s_);
+    grow(u.w32, (size_t)(m > 0 ? m : 1), (size_t)keep_m, s_);
 }
 
 std::vector<BatchMember *> BatchEngine::step() {
@@ -223,11 +220,10 @@ std::vector<BatchMember *> BatchEngine::step() {
         LV_HIP(hipStreamSynchronize(s_));
         return out;
     }
-    bool wide = !slots_.empty();
-    for (auto *m : join) wide = wide || m->g0.wbytes == 8;
+    // the union keeps int32 weights: every member has 2W < 2^31
     const int64_t N = un_ + n_arr, M = um_ + m_arr;
     UBuf &U = ub_[cur_];
-    ensure(U, N, M, wide, slots_.empty() ? 0 : un_, slots_.empty() ? 0 : um_);
+    ensure(U, N, M, slots_.empty() ? 0 : un_, slots_.empty() ? 0 : um_);
 
     std::vector<BatchMember *> sl = slots_;
     sl.insert(sl.end(), join.begin(), join.end());
@@ -265,13 +261,9 @@ std::vector<BatchMember *> BatchEngine::step() {
         }
         const int64_t *ubk = upload(jb, us, ub0, s_);
         {
-            TimedLaunch tl(t_, TG_LEVEL, "k_union_copy", (double)m_arr * (wide ? 16 : 12) + (double)n_arr * 32);
-            if (wide)
-                tl.launch(k_union_copy<int64_t>, (unsigned)b, 256, 0, s_, jb.as<UnionSeg>(), ubk, (int)us.size(),
-                          U.rp.p, U.col.p, U.w64.p, U.delta.p);
-            else
-                tl.launch(k_union_copy<int32_t>, (unsigned)b, 256, 0, s_, jb.as<UnionSeg>(), ubk, (int)us.size(),
-                          U.rp.p, U.col.p, U.w32.p, U.delta.p);
+            TimedLaunch tl(t_, TG_LEVEL, "k_union_copy", (double)m_arr * 16 + (double)n_arr * 32);
+            tl.launch(k_union_copy<int32_t>, (unsigned)b, 256, 0, s_, jb.as<UnionSeg>(), ubk, (int)us.size(),
+                      U.rp.p, U.col.p, U.w32.p, U.delta.p);
             LV_LAUNCHED("k_union_copy");
         }
         const int64_t *fbk = upload(vb, fs, fb0, s_);
@@ -303,8 +295,8 @@ std::vector<BatchMember *> BatchEngine::step() {
     v.nnz = M;
     v.row_ptr = U.rp.p;
     v.col = U.col.p;
-    v.w = wide ? (const void *)U.w64.p : (const void *)U.w32.p;
-    v.wbytes = wide ? 8 : 4;
+    v.w = U.w32.p;
+    v.wbytes = 4;
     v.delta = U.delta.p;
     v.tw = twmax;
 
@@ -390,9 +382,9 @@ std::vector<BatchMember *> BatchEngine::step() {
     std::vector<BatchMember *> next;
     if (any_k) {
         UBuf &D = ub_[1 - cur_];
-        ensure(D, k, M, true, 0, 0);
-        const int64_t m2 = ct_.contract(v, newlab_.p, k, D.rp.p, D.col.p, D.w64.p);
-        row_sums_i64(k, m2, D.rp.p, D.w64.p, D.delta.p, s_, t_);
+        ensure(D, k, M, 0, 0);
+        // every member has 2W < 2^31, so every contracted weight fits int32
+        const int64_t m2 = ct_.contract(v, newlab_.p, k, D.rp.p, D.col.p, D.w32.p, 4, D.delta.p);
         std::vector<int64_t> hno((size_t)ns + 1), hrp((size_t)ns + 1);
         TempBuf rpb((size_t)(ns + 1) * sizeof(int64_t), s_);
         k_rp_at<<<grid_for(ns + 1, 256), 256, 0, s_>>>(D.rp.p, newoff_.p, ns, rpb.as<int64_t>());

@@ -59,10 +59,10 @@ class BatchEngine {
 
   private:
     struct UBuf {
-        DevBuf<int64_t> rp, delta, w64;
+        DevBuf<int64_t> rp, delta;
         DevBuf<int32_t> col, w32;
     };
-    void ensure(UBuf &u, int64_t n, int64_t m, bool wide, int64_t keep_n, int64_t keep_m);
+    void ensure(UBuf &u, int64_t n, int64_t m, int64_t keep_n, int64_t keep_m);
 
     hipStream_t s_;
     Timer *t_;

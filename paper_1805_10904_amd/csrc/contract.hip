@@ -281,14 +281,20 @@ __device__ __forceinline__ int lds_slot(int32_t *key, int32_t k) {
 }
 
 // cnt[a] += row length of every kept vertex of community a.
+// Entries per community segment; with dsum, also the weighted degree of
+// every super-vertex (delta'_a = sum of delta_i over its members: the row
+// sums of the contracted graph, whose entry (a, b) sums A_ij over i in a,
+// j in b).
 __global__ __launch_bounds__(256) void k_seg_count(const int64_t *__restrict__ rp, const int32_t *__restrict__ newlab,
-                                                   int64_t n, unsigned long long *cnt) {
+                                                   int64_t n, unsigned long long *cnt,
+                                                   const int64_t *__restrict__ delta, unsigned long long *dsum) {
     constexpr int T = 1 << kSegBits;
     __shared__ int32_t s_key[T];
-    __shared__ unsigned long long s_sum[T];
+    __shared__ unsigned long long s_sum[T], s_del[T];
     for (int x = threadIdx.x; x < T; x += 256) {
         s_key[x] = kEmpty;
         s_sum[x] = 0;
+        s_del[x] = 0;
     }
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kSegTile;
@@ -299,11 +305,16 @@ __global__ __launch_bounds__(256) void k_seg_count(const int64_t *__restrict__ r
         const int32_t a = newlab[v];
         const int64_t d = rp[v + 1] - rp[v];
         if (a < 0 || d == 0) continue;
-        atomicAdd(&s_sum[lds_slot(s_key, a)], (unsigned long long)d);
+        const int slot = lds_slot(s_key, a);
+        atomicAdd(&s_sum[slot], (unsigned long long)d);
+        if (dsum) atomicAdd(&s_del[slot], (unsigned long long)delta[v]);
     }
     __syncthreads();
     for (int x = threadIdx.x; x < T; x += 256)
-        if (s_key[x] != kEmpty) atomicAdd(&cnt[s_key[x]], s_sum[x]);
+        if (s_key[x] != kEmpty) {
+            atomicAdd(&cnt[s_key[x]], s_sum[x]);
+            if (dsum) atomicAdd(&dsum[s_key[x]], s_del[x]);
+        }
 }
 
 // start[v] = place of vertex v's row in its community's segment.
@@ -701,10 +712,12 @@ __global__ void k_seg_merge_write(const uint64_t *__restrict__ ukey, const int64
 
 // Output CSR: entry u of row a comes from its segment's u - rp[a]-th pair.
 // The entry count m_new = rp[n_new] is read on the device; the grid covers
-// an upper bound of it.
+// an upper bound of it.  WO: output weight type (int32 only where every
+// weight is known to be below 2^31).
+template <typename WO>
 __global__ __launch_bounds__(256) void k_seg_pack(const int64_t *__restrict__ rp, int64_t n_new,
                                                   const int64_t *__restrict__ off, const int32_t *__restrict__ tcol,
-                                                  const int64_t *__restrict__ tw, int32_t *col_out, int64_t *w_out) {
+                                                  const int64_t *__restrict__ tw, int32_t *col_out, WO *w_out) {
     __shared__ int64_t srange[2];
     const int64_t base = (int64_t)blockIdx.x * kEntriesPerBlock;
     const int64_t m_new = rp[n_new];
@@ -718,7 +731,7 @@ __global__ __launch_bounds__(256) void k_seg_pack(const int64_t *__restrict__ rp
         const int64_t a = row_of_entry(rp, rlo, rhi, u);
         const int64_t src = off[a] + (u - rp[a]);
         col_out[u] = tcol[src];
-        w_out[u] = tw[src];
+        w_out[u] = (WO)tw[src];
     }
 }
 
@@ -766,7 +779,9 @@ const int64_t *Contractor::sort_sum(int64_t m, int key_bits, const uint64_t **uk
 }
 
 int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t n_new, int64_t *rp_out,
-                             int32_t *col_out, int64_t *w_out, bool sorted) {
+                             int32_t *col_out, void *w_out, int wout_bytes, int64_t *delta_out, bool sorted) {
+    require(wout_bytes == 4 || wout_bytes == 8, LOUVAIN_EDEVICE, "contracted weights are 4 or 8 bytes");
+    if (delta_out) fill<int64_t>(delta_out, 0, n_new, s_);
     if (n_new == 0) {
         fill<int64_t>(rp_out, 0, 1, s_);
         return 0;
@@ -783,8 +798,9 @@ int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t 
     fill<int64_t>(seg_cur_.p, 0, k, s_);
     const unsigned vb = (unsigned)((n + kSegTile - 1) / kSegTile);
     {
-        TimedLaunch tl(t_, TG_CONTRACT, "k_seg_count", (double)n * 20);
-        tl.launch(k_seg_count, vb, 256, 0, s_, g.row_ptr, newlab, n, (unsigned long long *)cnt);
+        TimedLaunch tl(t_, TG_CONTRACT, "k_seg_count", (double)n * (delta_out ? 28 : 20));
+        tl.launch(k_seg_count, vb, 256, 0, s_, g.row_ptr, newlab, n, (unsigned long long *)cnt, g.delta,
+                  (unsigned long long *)delta_out);
         LV_LAUNCHED("k_seg_count");
     }
     scan_exclusive<int64_t, int64_t>(cnt, off, k, off + k, s_, t_);
@@ -847,8 +863,14 @@ int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t 
     {
         // m_new <= m_raw: merging pairs only removes entries
         const int64_t eb = (m_raw + kEntriesPerBlock - 1) / kEntriesPerBlock;
-        TimedLaunch tl(t_, TG_CONTRACT, "k_seg_pack", (double)m_raw * 32);
-        tl.launch(k_seg_pack, (unsigned)eb, 256, 0, s_, rp_out, k, off, tcol_.p, tw_.p, col_out, w_out);
+        TimedLaunch tl(t_, TG_CONTRACT, "k_seg_pack", (double)m_raw * (24 + wout_bytes),
+                       wout_bytes == 4 ? "<int>" : "<long>");
+        if (wout_bytes == 4)
+            tl.launch(k_seg_pack<int32_t>, (unsigned)eb, 256, 0, s_, rp_out, k, off, tcol_.p, tw_.p, col_out,
+                      (int32_t *)w_out);
+        else
+            tl.launch(k_seg_pack<int64_t>, (unsigned)eb, 256, 0, s_, rp_out, k, off, tcol_.p, tw_.p, col_out,
+                      (int64_t *)w_out);
         LV_LAUNCHED("k_seg_pack");
     }
     const int64_t *mn = rb.add(rp_out + k);

@@ -26,13 +26,16 @@ class Contractor {
     // final[v] = newlab[final[v]] for v in [0, n0).
     void compose(int32_t *final_labels, int64_t n0, const int32_t *newlab);
     // Contract g so that vertex a of the result is {i : newlab[i] == a};
-    // writes row_ptr (n_new + 1), col and int64 weights (capacity g.nnz) and
-    // returns the number of entries (synchronises the stream).  Entries of
-    // rows with newlab == -1 are dropped.  sorted: columns ascend in every
-    // row (the canonical form); otherwise their order within a row is
-    // unspecified, which the method does not depend on.
+    // writes row_ptr (n_new + 1), col and weights of wout_bytes = 8 (int64)
+    // or 4 (int32: only where every weight of the result is below 2^31, as
+    // when 2W < 2^31), capacity g.nnz, and returns the number of entries
+    // (synchronises the stream).  delta_out (optional, n_new): the weighted
+    // degree of every super-vertex.  Entries of rows with newlab == -1 are
+    // dropped.  sorted: columns ascend in every row (the canonical form);
+    // otherwise their order within a row is unspecified, which the method
+    // does not depend on.
     int64_t contract(const GraphView &g, const int32_t *newlab, int64_t n_new, int64_t *rp_out,
-                     int32_t *col_out, int64_t *w_out, bool sorted = false);
+                     int32_t *col_out, void *w_out, int wout_bytes, int64_t *delta_out, bool sorted = false);
 
   private:
     // Sort (key_[0], val_[0])[0, m) by the low key_bits of the keys and sum

@@ -329,38 +329,6 @@ template void ingest_csr<int32_t>(int64_t, int64_t, const int64_t *, const int32
 template void ingest_csr<int64_t>(int64_t, int64_t, const int64_t *, const int32_t *, const int64_t *,
                                   int64_t *, int64_t *, bool, hipStream_t, Timer *);
 
-// ---------------------------------------------------------------- row sums --
-
-__global__ __launch_bounds__(256) void k_row_sums(const int64_t *__restrict__ rp, int64_t n, int64_t nnz,
-                                                  const int64_t *__restrict__ w, int64_t *delta) {
-    __shared__ int64_t srange[2];
-    const int t = threadIdx.x;
-    const int64_t base = (int64_t)blockIdx.x * kEntriesPerBlock;
-    block_row_range(rp, n, nnz, base, kEntriesPerBlock, srange);
-    const int64_t rlo = srange[0], rhi = srange[1];
-#pragma unroll 1
-    for (int k = 0; k < kEntryItems; ++k) {
-        const int64_t e = base + k * 256 + t;
-        const bool valid = e < nnz;
-        int64_t r = 0, wv = 0;
-        if (valid) {
-            r = row_of_entry(rp, rlo, rhi, e);
-            wv = w[e];
-        }
-        seg_add_wave(delta, r, wv, valid);
-    }
-}
-
-void row_sums_i64(int64_t n, int64_t nnz, const int64_t *row_ptr, const int64_t *w, int64_t *delta,
-                  hipStream_t s, Timer *t) {
-    fill<int64_t>(delta, 0, n, s);
-    if (nnz <= 0) return;
-    const int64_t nb = (nnz + kEntriesPerBlock - 1) / kEntriesPerBlock;
-    TimedLaunch tl(t, TG_CONTRACT, "k_row_sums", (double)nnz * 8 + (double)n * 16);
-    tl.launch(k_row_sums, (unsigned)nb, 256, 0, s, row_ptr, n, nnz, w, delta);
-    LV_LAUNCHED("k_row_sums");
-}
-
 // ------------------------------------------------------------- read-back --
 
 namespace {

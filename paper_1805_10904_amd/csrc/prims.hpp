@@ -102,10 +102,6 @@ template <typename W>
 void ingest_csr(int64_t n, int64_t nnz, const int64_t *row_ptr, const int32_t *col, const W *w,
                 int64_t *delta, int64_t *tw_host, bool check_symmetry, hipStream_t s, Timer *t);
 
-// delta[i] = sum of row i's weights (int64 weights), for trusted CSR.
-void row_sums_i64(int64_t n, int64_t nnz, const int64_t *row_ptr, const int64_t *w, int64_t *delta,
-                  hipStream_t s, Timer *t);
-
 // Device helper: largest r in [lo, hi] with row_ptr[r] <= e (the row holding entry e).
 __device__ __forceinline__ int64_t row_of_entry(const int64_t *__restrict__ row_ptr, int64_t lo,
                                                 int64_t hi, int64_t e) {

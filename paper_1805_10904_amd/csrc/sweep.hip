@@ -1066,7 +1066,8 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
         // every row swept from LDS (small_max + 1 .. block_max entries), by table size
         const int64_t nl = bstart_[B_HUB] - bstart_[B_T16];
         glist_.reserve((size_t)(nl > 0 ? nl : 1));
-        compact_classes(g.row_ptr, list_.p + bstart_[B_T16], nl, glist_.p, cstart_, cnnz_, s_, t_);
+        ginfo_.reserve((size_t)(nl > 0 ? nl : 1));
+        compact_classes(g.row_ptr, list_.p + bstart_[B_T16], nl, glist_.p, ginfo_.p, cstart_, cnnz_, s_, t_);
     } else if (pack_count_ > 0 && g.tw <= kTwFastMax) {
         TempBuf cost((size_t)pack_count_ * sizeof(int32_t), s_);
         k_pack_cost<<<grid_for(pack_count_, 256), 256, 0, s_>>>(g.row_ptr, list_.p + bstart_[B_T16], pack_count_,
@@ -1251,7 +1252,9 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
         cp.pack_first = pack_first_.p;
         cp.pack_blocks = pack_blocks_;
         cp.glist = glist_.p;
+        cp.ginfo = ginfo_.p;
         cp.small_max = tuning_.small_max;
+        cp.group_slots = tuning_.group_slots;
         for (int c = 0; c <= kLdsClasses; ++c) cp.cstart[c] = cstart_[c];
         for (int c = 0; c < kLdsClasses; ++c) cp.cnnz[c] = cnnz_[c];
         cp.hubs = hubs_;

@@ -64,6 +64,7 @@ struct Tuning {
     int small_max = 8;                  // rows of at most this many entries: one thread per vertex (1..8)
     int64_t block_max = kCompactBlockMax;   // longest row swept from LDS; longer rows: HBM hub tables
     int pass_batch = 1;                 // sweep passes between host checks
+    int group_slots = 4;                // LDS slots per lane of the packed-class sweep (2, 4 or 8)
 };
 // log2 of the LDS hash table size of a packed row of d >= 1 entries: the
 // smallest b >= 1 with 2^b >= ceil(3d/2) (load at most 2/3).
@@ -83,9 +84,11 @@ struct CompactPass {
     const int64_t *pack_pos = nullptr, *pack_first = nullptr;
     int64_t pack_blocks = 0;
     const int32_t *glist = nullptr;            // rows swept from LDS, by class
+    const uint64_t *ginfo = nullptr;           // their row start << 12 | length
     int64_t cstart[kLdsClasses + 1] = {0};     // class c: glist[cstart[c], cstart[c+1])
     int64_t cnnz[kLdsClasses] = {0};
     int small_max = 8;                         // rows swept one thread per vertex
+    int group_slots = 4;                       // slots per lane of the packed classes
     int64_t hubs = 0, hub_chunks = 0, hub_scans = 0;
     const int64_t *tab_off = nullptr, *chunk_off = nullptr, *scan_off = nullptr, *tab_size = nullptr;
     const int32_t *chunk_hub = nullptr, *scan_hub = nullptr;
@@ -120,11 +123,12 @@ void compact_init_singletons(int32_t *c0, int32_t *c1, int32_t *c2, const int64_
                              int64_t n, hipStream_t s);
 void compact_init_labels(int32_t *c0, int32_t *c1, int32_t *c2, const int32_t *labels, const int64_t *delta,
                          uint64_t *ds, uint32_t *es, int64_t n, hipStream_t s);
-// Stable partition of the m rows in list by table-size class into out;
+// Stable partition of the m rows in list by table-size class into out,
+// with every row's start and length packed in info (start << 12 | length);
 // cstart (kLdsClasses + 1) and cnnz (kLdsClasses) receive the class offsets
 // and entry counts (synchronises the stream).
-void compact_classes(const int64_t *rp, const int32_t *list, int64_t m, int32_t *out, int64_t *cstart,
-                     int64_t *cnnz, hipStream_t s, Timer *t);
+void compact_classes(const int64_t *rp, const int32_t *list, int64_t m, int32_t *out, uint64_t *info,
+                     int64_t *cstart, int64_t *cnnz, hipStream_t s, Timer *t);
 void compact_final_labels(const int32_t *c0, const int32_t *c1, const int32_t *c2, const int32_t *gid,
                           const PhaseState *st, int64_t n, int32_t *out, hipStream_t s, Timer *t);
 void compact_expand(const uint64_t *ds, const uint32_t *es, int64_t n, int64_t *deg, int32_t *size, int64_t *e_self,
@@ -198,6 +202,7 @@ class Sweeper {
     bool batch_ = false;
     DevBuf<int32_t> list_;          // vertices grouped by bucket, ascending inside a bucket
     DevBuf<int32_t> glist_;         // compact: rows swept from LDS, grouped by table-size class
+    DevBuf<uint64_t> ginfo_;        // compact: their row start << 12 | length
     int64_t cstart_[kLdsClasses + 1] = {0};
     int64_t cnnz_[kLdsClasses] = {0};
     DevBuf<int32_t> bcount_;        // bucketing scratch (per-block counts / offsets)

@@ -38,6 +38,13 @@ __device__ __forceinline__ int32_t vw_label(uint64_t w) { return (int32_t)(uint3
 __device__ __forceinline__ uint32_t hi_deg(uint32_t hi) { return hi & 0x7fffffffu; }
 __device__ __forceinline__ bool hi_single(uint32_t hi) { return (hi >> 31) != 0; }
 
+// Row start and length of a class-list entry in one word: start << 12 |
+// length (rows swept from LDS have at most kCompactBlockMax < 4096 entries).
+__device__ __forceinline__ uint64_t row_info(int64_t rs, int64_t d) { return ((uint64_t)rs << 12) | (uint64_t)d; }
+__device__ __forceinline__ int64_t info_start(uint64_t x) { return (int64_t)(x >> 12); }
+__device__ __forceinline__ int64_t info_len(uint64_t x) { return (int64_t)(x & 4095u); }
+static_assert(kCompactBlockMax < 4096, "row lengths swept from LDS fit 12 bits");
+
 struct CArgs {
     const int64_t *row_ptr;
     const int32_t *col;
@@ -476,7 +483,8 @@ template <> struct Log2<1> { static constexpr int value = 0; };
 // then smallest label) is a shuffle reduction inside the group, with an LDS
 // step across waves when the group spans several.
 template <int S, int G, typename W>
-__global__ __launch_bounds__(256) void k_cpt_group(CArgs a, const int32_t *__restrict__ list, int64_t count) {
+__global__ __launch_bounds__(256) void k_cpt_group(CArgs a, const int32_t *__restrict__ list,
+                                                   const uint64_t *__restrict__ info, int64_t count) {
     constexpr int NV = 256 / G;
     constexpr int SPL = S / G;
     constexpr int BITS = Log2<S>::value;
@@ -502,11 +510,12 @@ __global__ __launch_bounds__(256) void k_cpt_group(CArgs a, const int32_t *__res
     int64_t rs = 0, d = 0;
     if (k < count) {
         v = list[k];
+        const uint64_t ri = info[k];
         g = graph_of(a.gid, v);
         live = !a.st[g].done;
         if (live) {
-            rs = a.row_ptr[v];
-            d = a.row_ptr[v + 1] - rs;
+            rs = info_start(ri);
+            d = info_len(ri);
         }
     }
     int32_t ci = -1;
@@ -612,28 +621,33 @@ __global__ __launch_bounds__(256) void k_cpt_group(CArgs a, const int32_t *__res
 }
 
 // All packed classes in one launch: workgroups [bo[c], bo[c+1]) take class
-// c (S = 16 << c slots per table, G = S/4 lanes per vertex, 64 >> c
-// vertices per workgroup, 1,024 table slots in all), otherwise as
-// k_cpt_group.
+// c (S = 16 << c slots per table, G = S/SPL lanes per vertex, 16 SPL >> c
+// vertices per workgroup, 256 SPL table slots in all), otherwise as
+// k_cpt_group.  SPL (slots per lane, 2, 4 or 8) trades lanes per vertex for
+// work per lane: each lane scores SPL slots and takes at most
+// ceil(2 SPL / 3) entries of its row.
 struct GroupBlocks {
     int64_t bo[kGroupClasses + 1];     // first workgroup of every class
     int64_t cstart[kGroupClasses + 1]; // first row of every class in the class list
 };
 
-template <typename W>
-__global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__restrict__ list, GroupBlocks gb) {
-    constexpr int SPL = 4;
-    __shared__ int32_t s_key[1024];
-    __shared__ uint32_t s_e[1024], s_hi[1024];
+template <int SPL, typename W>
+__global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__restrict__ list,
+                                                    const uint64_t *__restrict__ info, GroupBlocks gb) {
+    static_assert(SPL == 2 || SPL == 4 || SPL == 8, "2, 4 or 8 slots per lane");
+    constexpr int LB = SPL == 2 ? 1 : SPL == 4 ? 2 : 3;   // log2 SPL
+    constexpr int U = (2 * SPL + 2) / 3;     // entries per lane at most
+    __shared__ int32_t s_key[256 * SPL];
+    __shared__ uint32_t s_e[256 * SPL], s_hi[256 * SPL];
     __shared__ unsigned long long r_ok[4];
     __shared__ uint32_t r_lf[4], r_eo[4], r_lp[4];
     const int t = threadIdx.x;
     int c = 0;
     while (c < kGroupClasses - 1 && (int64_t)blockIdx.x >= gb.bo[c + 1]) ++c;
     const int bits = 4 + c;                  // log2 S
-    const int G = 4 << c;
-    const int NV = 64 >> c;
-    const int kv = t >> (2 + c), li = t & (G - 1);
+    const int G = (16 >> LB) << c;
+    const int NV = (16 * SPL) >> c;
+    const int kv = t >> (4 - LB + c), li = t & (G - 1);
     const int S = 16 << c;
     int32_t *key = s_key + kv * S;
     uint32_t *es = s_e + kv * S, *hs = s_hi + kv * S;
@@ -649,21 +663,22 @@ __global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__re
     int64_t rs = 0, d = 0;
     if (k < gb.cstart[c + 1]) {
         v = list[k];
+        const uint64_t ri = info[k];
         g = graph_of(a.gid, v);
         live = !a.st[g].done;
         if (live) {
-            rs = a.row_ptr[v];
-            d = a.row_ptr[v + 1] - rs;
+            rs = info_start(ri);
+            d = info_len(ri);
         }
     }
-    // A class-c row has d <= 2S/3 < 3G entries, so every lane holds at most
-    // three: their loads and gathers are all issued before the first insert.
-    int32_t jq[3];
-    uint32_t wq[3];
-    uint64_t nq[3];
+    // A class-c row has d <= 2S/3 entries, at most U per lane: their loads
+    // and gathers are all issued before the first insert.
+    int32_t jq[U];
+    uint32_t wq[U];
+    uint64_t nq[U];
     uint32_t loop = 0;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < U; ++q) {
         const int64_t x = li + (int64_t)q * G;
         jq[q] = v;
         wq[q] = 0;
@@ -673,7 +688,7 @@ __global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__re
         }
     }
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < U; ++q) {
         nq[q] = 0;
         if (jq[q] != v) nq[q] = a.vw[jq[q]];
     }
@@ -689,13 +704,13 @@ __global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__re
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < U; ++q) {
         if (jq[q] == v)
             loop += wq[q];
         else
             grp_insert(key, es, hs, bits, vw_label(nq[q]), wq[q], (uint32_t)(nq[q] >> 32));
     }
-    for (int64_t x = li + 3 * (int64_t)G; x < d; x += G) {   // not reached for class rows
+    for (int64_t x = li + (int64_t)U * G; x < d; x += G) {   // not reached for class rows
         const int32_t j = a.col[rs + x];
         const uint32_t w = cw<W>(a.w, rs + x);
         if (j == v) {
@@ -806,7 +821,7 @@ __global__ __launch_bounds__(256) void k_class_count(const int64_t *__restrict__
 // Stable scatter of the packed rows into their classes.
 __global__ __launch_bounds__(256) void k_class_scatter(const int64_t *__restrict__ rp, const int32_t *__restrict__ list,
                                                        int64_t m, const int32_t *__restrict__ offs, int64_t nblocks,
-                                                       int32_t *out) {
+                                                       int32_t *out, uint64_t *info) {
     __shared__ int run[kLdsClasses];
     __shared__ int wc[4][kLdsClasses];
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
@@ -818,9 +833,12 @@ __global__ __launch_bounds__(256) void k_class_scatter(const int64_t *__restrict
         const int64_t i = base + k * 256 + t;
         int32_t v = 0;
         int c = -1;
+        int64_t rs = 0, d = 0;
         if (i < m) {
             v = list[i];
-            c = size_class(rp[v + 1] - rp[v]);
+            rs = rp[v];
+            d = rp[v + 1] - rs;
+            c = size_class(d);
         }
         int rank = 0;
 #pragma unroll
@@ -834,6 +852,7 @@ __global__ __launch_bounds__(256) void k_class_scatter(const int64_t *__restrict
             int pos = run[c] + rank;
             for (int w2 = 0; w2 < wid; ++w2) pos += wc[w2][c];
             out[pos] = v;
+            info[pos] = row_info(rs, d);
         }
         __syncthreads();
         if (t < kLdsClasses) run[t] += wc[0][t] + wc[1][t] + wc[2][t] + wc[3][t];
@@ -1064,8 +1083,8 @@ __global__ __launch_bounds__(256) void k_cpt_hub_decide(CArgs a, CHub hm, const 
 
 // ------------------------------------------------------------------- host --
 
-void compact_classes(const int64_t *rp, const int32_t *list, int64_t m, int32_t *out, int64_t *cstart,
-                     int64_t *cnnz, hipStream_t s, Timer *t) {
+void compact_classes(const int64_t *rp, const int32_t *list, int64_t m, int32_t *out, uint64_t *info,
+                     int64_t *cstart, int64_t *cnnz, hipStream_t s, Timer *t) {
     for (int c = 0; c <= kLdsClasses; ++c) cstart[c] = 0;
     for (int c = 0; c < kLdsClasses; ++c) cnnz[c] = 0;
     if (m <= 0) return;
@@ -1082,8 +1101,8 @@ void compact_classes(const int64_t *rp, const int32_t *list, int64_t m, int32_t 
     }
     scan_exclusive<int32_t, int32_t>(counts.as<int32_t>(), counts.as<int32_t>(), cm, counts.as<int32_t>() + cm, s, t);
     {
-        TimedLaunch tl(t, TG_LEVEL, "k_class_scatter", (double)m * 24);
-        tl.launch(k_class_scatter, (unsigned)nblk, 256, 0, s, rp, list, m, counts.as<int32_t>(), nblk, out);
+        TimedLaunch tl(t, TG_LEVEL, "k_class_scatter", (double)m * 32);
+        tl.launch(k_class_scatter, (unsigned)nblk, 256, 0, s, rp, list, m, counts.as<int32_t>(), nblk, out, info);
         LV_LAUNCHED("k_class_scatter");
     }
     Readback rb(s);
@@ -1147,16 +1166,24 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
         GroupBlocks gb;
         gb.bo[0] = 0;
         double gbytes = 0;
+        const int spl = cp.group_slots == 8 ? 8 : cp.group_slots == 2 ? 2 : 4;
         for (int c = 0; c < kGroupClasses; ++c) {
             const int64_t cnt = cp.cstart[c + 1] - cp.cstart[c];
-            const int nv = 64 >> c;
+            const int nv = (16 * spl) >> c;
             gb.bo[c + 1] = gb.bo[c] + (cnt + nv - 1) / nv;
             gbytes += (double)cnt * vb + (double)cp.cnnz[c] * eb;
         }
         for (int c = 0; c <= kGroupClasses; ++c) gb.cstart[c] = cp.cstart[c];
         if (gb.bo[kGroupClasses] > 0) {
-            TimedLaunch tl(t, TG_SWEEP, "k_cpt_groups<", gbytes, sfx.c_str());
-            tl.launch(k_cpt_groups<W>, (unsigned)gb.bo[kGroupClasses], 256, 0, s, a, cp.glist, gb);
+            TimedLaunch tl(t, TG_SWEEP, spl == 8 ? "k_cpt_groups<8," : spl == 2 ? "k_cpt_groups<2," : "k_cpt_groups<4,",
+                           gbytes, sfx.c_str());
+            const unsigned nb = (unsigned)gb.bo[kGroupClasses];
+            if (spl == 8)
+                tl.launch(k_cpt_groups<8, W>, nb, 256, 0, s, a, cp.glist, cp.ginfo, gb);
+            else if (spl == 2)
+                tl.launch(k_cpt_groups<2, W>, nb, 256, 0, s, a, cp.glist, cp.ginfo, gb);
+            else
+                tl.launch(k_cpt_groups<4, W>, nb, 256, 0, s, a, cp.glist, cp.ginfo, gb);
             LV_LAUNCHED("k_cpt_groups");
         }
     }
@@ -1166,14 +1193,16 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
         if (nw > 0) {
             TimedLaunch tl(t, TG_SWEEP, "k_cpt_group<2048,256,", (double)nw * vb + (double)cp.cnnz[c] * eb,
                            sfx.c_str());
-            tl.launch(k_cpt_group<2048, 256, W>, (unsigned)nw, 256, 0, s, a, cp.glist + cp.cstart[c], nw);
+            tl.launch(k_cpt_group<2048, 256, W>, (unsigned)nw, 256, 0, s, a, cp.glist + cp.cstart[c],
+                      cp.ginfo + cp.cstart[c], nw);
             LV_LAUNCHED("k_cpt_group<2048>");
         }
         const int64_t nx = cp.cstart[c + 2] - cp.cstart[c + 1];
         if (nx > 0) {
             TimedLaunch tl(t, TG_SWEEP, "k_cpt_group<4096,256,", (double)nx * vb + (double)cp.cnnz[c + 1] * eb,
                            sfx.c_str());
-            tl.launch(k_cpt_group<4096, 256, W>, (unsigned)nx, 256, 0, s, a, cp.glist + cp.cstart[c + 1], nx);
+            tl.launch(k_cpt_group<4096, 256, W>, (unsigned)nx, 256, 0, s, a, cp.glist + cp.cstart[c + 1],
+                      cp.ginfo + cp.cstart[c + 1], nx);
             LV_LAUNCHED("k_cpt_group<4096>");
         }
     }
