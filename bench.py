@@ -194,6 +194,9 @@ def main():
     ap.add_argument("--no-timing", action="store_true", help="time steps without per-kernel events")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default launch shapes instead of autotuning them on the workload first")
+    ap.add_argument("--shapes", default=None,
+                    help="explicit launch shapes small_max,block_max,pass_batch,group_slots,group_vertices,overlap "
+                         "(no autotuning)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batched", type=int, default=4096,
                     help="also compare one batched call on this many graphs of the batched SBM workload "
@@ -264,8 +267,10 @@ def main():
         G.destroy()
         return r
 
+    if args.shapes:
+        ctx.set_tuning(*[int(x) for x in args.shapes.split(",")])
     tuning = ctx.get_tuning()
-    if not args.no_autotune:
+    if not args.no_autotune and not args.shapes:
         G = ctx.graph_create(rp, col, w)
         t = time.time()
         best = ctx.autotune(G)

@@ -255,13 +255,17 @@ int louvain_run_batch(louvain_ctx ctx, int64_t ngraphs, const louvain_graph *gra
  * labels, Q and level records). */
 typedef struct {
     int32_t small_max;   /* rows of at most this many entries are swept one thread per
-                            vertex (1..8; default 8)                                     */
+                            vertex (1..8; default 4)                                     */
     int32_t block_max;   /* longest row swept from an LDS table; longer rows use HBM hub
                             tables (341..2730; default 2730)                             */
     int32_t pass_batch;  /* sweep passes between host checks when the run's params say 0
-                            (1..64; default 1)                                           */
+                            (1..64; default 2)                                           */
     int32_t group_slots; /* LDS table slots scored per lane for rows of up to 341 entries
                             (2, 4 or 8; 0 = 4): fewer lanes per row, more work per lane */
+    int32_t group_vertices; /* rows of up to 341 entries each lane group sweeps side by
+                            side (1 or 2; 0 = 1): more independent work per lane      */
+    int32_t overlap;     /* 1: the rows of 342..block_max entries and the hub rows are swept
+                            on two extra streams beside the shorter rows (0 or 1)      */
     double ms;           /* louvain_autotune: device time of one run with this setting */
 } louvain_tuning;
 
@@ -273,9 +277,11 @@ int louvain_get_tuning(louvain_ctx ctx, louvain_tuning *tuning);
 
 /*
  * Autotuner: times one whole run of the method on g (params as for
- * louvain_run) under each candidate setting (small_max in {4, 8},
- * block_max in {1024, 1365, 2730}, pass_batch in {1, 2}, group_slots in
- * {2, 4, 8}), best of two runs
+ * louvain_run) under the context's current setting and each candidate
+ * (small_max in {4, 8}, block_max in {1024, 1365, 2730}, pass_batch in
+ * {1, 2}, group_vertices in {1, 2}; group_slots 4, overlap as set), best
+ * of two runs each; a candidate replaces the current setting only when it
+ * is more than 2% faster, so that timing noise does not flip the setting
  * each, and makes the fastest the context's setting.  *best (optional)
  * receives it with its time.  Graphs with 2W >= 2^31 do not use these
  * shapes; the setting is left as it is and best->ms is -1.

@@ -64,7 +64,8 @@ class louvain_request_result(C.Structure):
 
 class louvain_tuning(C.Structure):
     _fields_ = [("small_max", C.c_int32), ("block_max", C.c_int32), ("pass_batch", C.c_int32),
-                ("group_slots", C.c_int32), ("ms", C.c_double)]
+                ("group_slots", C.c_int32), ("group_vertices", C.c_int32), ("overlap", C.c_int32),
+                ("ms", C.c_double)]
 
 
 class louvain_run_stats(C.Structure):
@@ -285,16 +286,17 @@ class Context:
                                                   _ptr(keep[2]), flags, C.byref(h)))
         return Graph(self, h, dev)
 
-    def set_tuning(self, small_max: int = 8, block_max: int = 2730, pass_batch: int = 1, group_slots: int = 4):
+    def set_tuning(self, small_max: int = 4, block_max: int = 2730, pass_batch: int = 2, group_slots: int = 4,
+                   group_vertices: int = 1, overlap: int = 0):
         """Launch shapes of compact levels (results do not depend on them)."""
-        t = louvain_tuning(small_max, block_max, pass_batch, group_slots, 0.0)
+        t = louvain_tuning(small_max, block_max, pass_batch, group_slots, group_vertices, overlap, 0.0)
         self._check(self.lib.louvain_set_tuning(self.h, C.byref(t)))
 
     def get_tuning(self) -> dict:
         t = louvain_tuning()
         self._check(self.lib.louvain_get_tuning(self.h, C.byref(t)))
         return dict(small_max=t.small_max, block_max=t.block_max, pass_batch=t.pass_batch,
-                    group_slots=t.group_slots)
+                    group_slots=t.group_slots, group_vertices=t.group_vertices, overlap=t.overlap)
 
     def autotune(self, g: "Graph", theta_num: int = 1, theta_den: int = 1_000_000, max_sweeps: int = 1000,
                  max_levels: int = 64, singlet_rule: bool = True) -> dict:
@@ -303,7 +305,7 @@ class Context:
         t = louvain_tuning()
         self._check(self.lib.louvain_autotune(self.h, g.h, C.byref(prm), C.byref(t)))
         return dict(small_max=t.small_max, block_max=t.block_max, pass_batch=t.pass_batch,
-                    group_slots=t.group_slots, ms=t.ms)
+                    group_slots=t.group_slots, group_vertices=t.group_vertices, overlap=t.overlap, ms=t.ms)
 
     def serve_budget(self, nbytes: int):
         """Device-memory budget of the request loop (0: 80% of free memory at start)."""

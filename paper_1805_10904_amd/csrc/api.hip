@@ -576,7 +576,12 @@ int louvain_set_tuning(louvain_ctx ctx, const louvain_tuning *tuning) {
             tn.small_max = tuning->small_max;
             tn.block_max = tuning->block_max;
             tn.pass_batch = tuning->pass_batch;
+            require(tuning->group_vertices >= 0 && tuning->group_vertices <= 2, LOUVAIN_EINVAL,
+                    "group_vertices must be 0, 1 or 2");
+            require(tuning->overlap == 0 || tuning->overlap == 1, LOUVAIN_EINVAL, "overlap must be 0 or 1");
             tn.group_slots = tuning->group_slots == 0 ? 4 : tuning->group_slots;
+            tn.group_vertices = tuning->group_vertices == 0 ? 1 : tuning->group_vertices;
+            tn.overlap = tuning->overlap;
         }
         ctx->tuning = tn;
     });
@@ -589,6 +594,8 @@ int louvain_get_tuning(louvain_ctx ctx, louvain_tuning *tuning) {
     tuning->block_max = (int32_t)ctx->tuning.block_max;
     tuning->pass_batch = ctx->tuning.pass_batch;
     tuning->group_slots = ctx->tuning.group_slots;
+    tuning->group_vertices = ctx->tuning.group_vertices;
+    tuning->overlap = ctx->tuning.overlap;
     return LOUVAIN_OK;
 }
 
@@ -628,19 +635,22 @@ int louvain_autotune(louvain_ctx ctx, louvain_graph g, const louvain_params *par
             return (double)ms;
         };
         (void)time_run(ctx->tuning);   // warm-up (allocations, code loading)
-        lv::Tuning pick = ctx->tuning;
-        double pick_ms = 1e30;
+        const lv::Tuning cur = ctx->tuning;
+        const double cur_ms = std::min(time_run(cur), time_run(cur));
+        lv::Tuning pick = cur;
+        double pick_ms = cur_ms;
         for (int sm : {4, 8})
             for (int64_t bm : {(int64_t)1024, (int64_t)1365, lv::kCompactBlockMax})
                 for (int pb : {1, 2})
-                    for (int gs : {2, 4, 8}) {
+                    for (int gv : {1, 2}) {
                         lv::Tuning tn;
                         tn.small_max = sm;
                         tn.block_max = bm;
                         tn.pass_batch = pb;
-                        tn.group_slots = gs;
+                        tn.group_vertices = gv;
+                        tn.overlap = cur.overlap;
                         const double ms = std::min(time_run(tn), time_run(tn));
-                        if (ms < pick_ms) {
+                        if (ms < pick_ms && ms < 0.98 * cur_ms) {
                             pick_ms = ms;
                             pick = tn;
                         }

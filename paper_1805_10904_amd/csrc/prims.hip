@@ -395,4 +395,52 @@ void Readback::issue() {
 
 void Readback::wait() { LV_HIP(hipStreamSynchronize(s_)); }
 
+// ---------------------------------------------------------- side streams --
+
+namespace {
+std::mutex g_side_mu;
+std::vector<void *> g_side_free;
+}  // namespace
+
+SideStreams::SideStreams() {
+    int dev = 0;
+    LV_HIP(hipGetDevice(&dev));
+    {
+        std::lock_guard<std::mutex> lk(g_side_mu);
+        for (size_t k = 0; k < g_side_free.size(); ++k) {
+            Set *x = (Set *)g_side_free[k];
+            if (x->device == dev) {
+                set_ = x;
+                g_side_free.erase(g_side_free.begin() + (std::ptrdiff_t)k);
+                break;
+            }
+        }
+    }
+    if (set_) return;
+    Set *x = new Set();
+    x->device = dev;
+    for (int k = 0; k < 2; ++k) LV_HIP(hipStreamCreateWithFlags(&x->s[k], hipStreamNonBlocking));
+    LV_HIP(hipEventCreateWithFlags(&x->fork, hipEventDisableTiming));
+    for (int k = 0; k < 2; ++k) LV_HIP(hipEventCreateWithFlags(&x->join[k], hipEventDisableTiming));
+    set_ = x;
+}
+
+SideStreams::~SideStreams() {
+    if (!set_) return;
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    g_side_free.push_back(set_);
+}
+
+void SideStreams::fork(hipStream_t main) {
+    LV_HIP(hipEventRecord(set_->fork, main));
+    for (int k = 0; k < 2; ++k) LV_HIP(hipStreamWaitEvent(set_->s[k], set_->fork, 0));
+}
+
+void SideStreams::join(hipStream_t main) {
+    for (int k = 0; k < 2; ++k) {
+        LV_HIP(hipEventRecord(set_->join[k], set_->s[k]));
+        LV_HIP(hipStreamWaitEvent(main, set_->join[k], 0));
+    }
+}
+
 }  // namespace lv

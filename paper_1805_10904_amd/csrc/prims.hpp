@@ -81,6 +81,29 @@ class Readback {
     int off_[kMaxRanges], len_[kMaxRanges];
 };
 
+// Two extra streams of the current device, and the events that fork work
+// from a main stream onto them and join it back, leased from a per-device
+// free list so that repeated runs reuse them (default priority, like every
+// stream here).
+class SideStreams {
+  public:
+    SideStreams();
+    ~SideStreams();
+    SideStreams(const SideStreams &) = delete;
+    SideStreams &operator=(const SideStreams &) = delete;
+    hipStream_t operator[](int k) const { return set_->s[k]; }
+    void fork(hipStream_t main);   // the side streams wait for the work enqueued on main so far
+    void join(hipStream_t main);   // main waits for the work enqueued on the side streams so far
+
+  private:
+    struct Set {
+        int device;
+        hipStream_t s[2];
+        hipEvent_t fork, join[2];
+    };
+    Set *set_ = nullptr;
+};
+
 // out[i] = sum_{k<i} in[k] for i in [0, m); *total_dev (optional, device)
 // receives the sum of all m values.  in and out may alias.  TI, TO are
 // int32_t or int64_t; sums are formed in TO.

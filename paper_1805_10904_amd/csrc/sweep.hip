@@ -1255,6 +1255,8 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
         cp.ginfo = ginfo_.p;
         cp.small_max = tuning_.small_max;
         cp.group_slots = tuning_.group_slots;
+        cp.group_vertices = tuning_.group_vertices;
+        cp.overlap = tuning_.overlap;
         for (int c = 0; c <= kLdsClasses; ++c) cp.cstart[c] = cstart_[c];
         for (int c = 0; c < kLdsClasses; ++c) cp.cnnz[c] = cnnz_[c];
         cp.hubs = hubs_;
@@ -1281,6 +1283,8 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
         cs.st = st_.p;
         cs.active = active_.p;
         cs.ngraphs = ngraphs_;
+        if (tuning_.overlap && !side_) side_.reset(new SideStreams());
+        cs.side = side_.get();
         compact_pass(g, cp, cs, p, prm, s_, t_);
         return;
     }

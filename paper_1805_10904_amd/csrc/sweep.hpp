@@ -3,7 +3,9 @@
 // acceptance test.
 #pragma once
 
-#include "common.hpp"
+#include <memory>
+
+#include "prims.hpp"
 
 namespace lv {
 
@@ -61,10 +63,12 @@ constexpr int64_t kCompactBlockMax = 2730;
 // Launch-shape settings of compact levels (chosen by the autotuner or the
 // caller; every setting gives the same results).
 struct Tuning {
-    int small_max = 8;                  // rows of at most this many entries: one thread per vertex (1..8)
+    int small_max = 4;                  // rows of at most this many entries: one thread per vertex (1..8)
     int64_t block_max = kCompactBlockMax;   // longest row swept from LDS; longer rows: HBM hub tables
-    int pass_batch = 1;                 // sweep passes between host checks
+    int pass_batch = 2;                 // sweep passes between host checks
     int group_slots = 4;                // LDS slots per lane of the packed-class sweep (2, 4 or 8)
+    int group_vertices = 1;             // vertices per lane group of the packed-class sweep (1 or 2)
+    int overlap = 0;                    // 1: row families on side streams, side by side
 };
 // log2 of the LDS hash table size of a packed row of d >= 1 entries: the
 // smallest b >= 1 with 2^b >= ceil(3d/2) (load at most 2/3).
@@ -89,6 +93,8 @@ struct CompactPass {
     int64_t cnnz[kLdsClasses] = {0};
     int small_max = 8;                         // rows swept one thread per vertex
     int group_slots = 4;                       // slots per lane of the packed classes
+    int group_vertices = 1;                    // vertices per lane group of the packed classes
+    int overlap = 0;                           // row families side by side on side streams
     int64_t hubs = 0, hub_chunks = 0, hub_scans = 0;
     const int64_t *tab_off = nullptr, *chunk_off = nullptr, *scan_off = nullptr, *tab_size = nullptr;
     const int32_t *chunk_hub = nullptr, *scan_hub = nullptr;
@@ -114,6 +120,7 @@ struct CompactState {
     PhaseState *st = nullptr;      // phase state of every graph
     unsigned int *active = nullptr;// two counters of graphs still in their phase (pass parity)
     int64_t ngraphs = 1;
+    SideStreams *side = nullptr;   // optional: streams for the one-workgroup rows and the hubs
 };
 
 // Levels whose graphs all have TW < 2^31 run on packed community words
@@ -186,6 +193,7 @@ class Sweeper {
     Tuning tuning_;
     hipStream_t s_;
     Timer *t_;
+    std::unique_ptr<SideStreams> side_;   // leased on the first compact pass
     int64_t cap_n_ = -1, cap_nnz_ = -1;
     DevBuf<int32_t> c_[3];
     DevBuf<int64_t> deg_;           // deg_C by label (updated in place by the commit)

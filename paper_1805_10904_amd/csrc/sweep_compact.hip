@@ -457,16 +457,13 @@ __device__ __forceinline__ void grp_insert(int32_t *key, uint32_t *es, uint32_t 
     const uint32_t mask = (1u << bits) - 1;
     uint32_t h = ((uint32_t)k * 0x9E3779B1u) >> (32 - bits);
     while (true) {
-        const int32_t cur = ((volatile int32_t *)key)[h];
-        if (cur == k) break;
-        if (cur == kEmpty) {
-            const int32_t prev = atomicCAS(&key[h], kEmpty, k);
-            if (prev == kEmpty) {
-                hs[h] = hi;
-                break;
-            }
-            if (prev == k) break;
+        // the compare-and-swap returns the slot's key whether or not it claims it
+        const int32_t prev = atomicCAS(&key[h], kEmpty, k);
+        if (prev == kEmpty) {
+            hs[h] = hi;
+            break;
         }
+        if (prev == k) break;
         h = (h + 1) & mask;
     }
     atomicAdd(&es[h], w);
@@ -474,6 +471,49 @@ __device__ __forceinline__ void grp_insert(int32_t *key, uint32_t *es, uint32_t 
 
 template <int X> struct Log2 { static constexpr int value = 1 + Log2<X / 2>::value; };
 template <> struct Log2<1> { static constexpr int value = 0; };
+
+// One step of the arg-max over a lane group: take the partner's candidate
+// if its key is larger, or equal with a smaller label word (branch-free).
+__device__ __forceinline__ void best_take(unsigned long long &bok, uint32_t &blf, uint32_t olo, uint32_t ohi,
+                                          uint32_t olf) {
+    const unsigned long long ook = ((unsigned long long)ohi << 32) | olo;
+    const bool take = (ook > bok) | ((ook == bok) & (olf < blf));
+    bok = take ? ook : bok;
+    blf = take ? olf : blf;
+}
+
+template <int CTRL>
+__device__ __forceinline__ void best_dpp(unsigned long long &bok, uint32_t &blf) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)bok, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(bok >> 32), CTRL, 0xF, 0xF, false);
+    const uint32_t lf = (uint32_t)__builtin_amdgcn_mov_dpp((int)blf, CTRL, 0xF, 0xF, false);
+    best_take(bok, blf, lo, hi, lf);
+}
+
+// Arg-max (largest key, then smallest label word) over every aligned group
+// of G lanes of the wavefront (G a power of two, 2..64; uniform): after the
+// quad steps every lane holds its quad's best, so the half-row and row
+// mirrors pair whole quads and half-rows; a swizzle and a permute cover 16
+// and 32.  Every lane ends with its group's best.
+__device__ __forceinline__ void group_best(unsigned long long &bok, uint32_t &blf, int G) {
+    if (G >= 2) best_dpp<0xB1>(bok, blf);    // quad_perm [1,0,3,2]
+    if (G >= 4) best_dpp<0x4E>(bok, blf);    // quad_perm [2,3,0,1]
+    if (G >= 8) best_dpp<0x141>(bok, blf);   // row_half_mirror
+    if (G >= 16) best_dpp<0x140>(bok, blf);  // row_mirror
+    if (G >= 32) {                           // lanes xor 16 inside each half-wavefront
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_swizzle((int)(uint32_t)bok, 0x401F);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_swizzle((int)(uint32_t)(bok >> 32), 0x401F);
+        const uint32_t lf = (uint32_t)__builtin_amdgcn_ds_swizzle((int)blf, 0x401F);
+        best_take(bok, blf, lo, hi, lf);
+    }
+    if (G >= 64) {                           // lanes xor 32
+        const int addr = (int)((__lane_id() ^ 32u) << 2);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)bok);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)(uint32_t)(bok >> 32));
+        const uint32_t lf = (uint32_t)__builtin_amdgcn_ds_bpermute(addr, (int)blf);
+        best_take(bok, blf, lo, hi, lf);
+    }
+}
 
 // Rows sorted into table-size classes: a workgroup holds 256/G vertices of
 // one class, each with an LDS table of S slots (S >= 1.5 d) and a group of G
@@ -574,22 +614,15 @@ __global__ __launch_bounds__(256) void k_cpt_group(CArgs a, const int32_t *__res
             continue;
         }
         const uint32_t hi = hs[x];
-        const int64_t sc = tw * (int64_t)e - di * (int64_t)hi_deg(hi);
-        const unsigned long long ok = (unsigned long long)sc ^ 0x8000000000000000ull;
+        // TW, delta_i, deg_C, e_{i->C} < 2^31: products of 32-bit operands
+        const unsigned long long ok =
+            ((uint64_t)(uint32_t)tw * e - (uint64_t)(uint32_t)di * hi_deg(hi)) ^ 0x8000000000000000ull;
         const uint32_t lf = ((uint32_t)kk << 1) | (hi_single(hi) ? 1u : 0u);
-        if (ok > bok || (ok == bok && lf < blf)) {
-            bok = ok;
-            blf = lf;
-        }
+        best_take(bok, blf, (uint32_t)ok, (uint32_t)(ok >> 32), lf);
     }
+    group_best(bok, blf, GW);
 #pragma unroll
     for (int off = GW / 2; off > 0; off >>= 1) {
-        const unsigned long long ook = __shfl_xor(bok, off);
-        const uint32_t olf = __shfl_xor(blf, off);
-        if (ook > bok || (ook == bok && olf < blf)) {
-            bok = ook;
-            blf = olf;
-        }
         e_own += __shfl_xor(e_own, off);
         loop += __shfl_xor(loop, off);
     }
@@ -631,152 +664,201 @@ struct GroupBlocks {
     int64_t cstart[kGroupClasses + 1]; // first row of every class in the class list
 };
 
-template <int SPL, typename W>
+template <int SPL, int VPG, typename W>
 __global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__restrict__ list,
                                                     const uint64_t *__restrict__ info, GroupBlocks gb) {
     static_assert(SPL == 2 || SPL == 4 || SPL == 8, "2, 4 or 8 slots per lane");
+    static_assert(VPG == 1 || VPG == 2, "one or two vertices per lane group");
     constexpr int LB = SPL == 2 ? 1 : SPL == 4 ? 2 : 3;   // log2 SPL
     constexpr int U = (2 * SPL + 2) / 3;     // entries per lane at most
-    __shared__ int32_t s_key[256 * SPL];
-    __shared__ uint32_t s_e[256 * SPL], s_hi[256 * SPL];
-    __shared__ unsigned long long r_ok[4];
-    __shared__ uint32_t r_lf[4], r_eo[4], r_lp[4];
+    __shared__ int32_t s_key[VPG * 256 * SPL];
+    __shared__ uint32_t s_e[VPG * 256 * SPL], s_hi[VPG * 256 * SPL];
+    __shared__ unsigned long long r_ok[VPG][4];
+    __shared__ uint32_t r_lf[VPG][4];
+    // e_{i->c_i} and the loop weight of every vertex of the workgroup: each
+    // has one writer (one table slot holds c_i, a row has at most one loop)
+    __shared__ uint32_t s_eown[VPG * 128], s_loop[VPG * 128];
     const int t = threadIdx.x;
     int c = 0;
     while (c < kGroupClasses - 1 && (int64_t)blockIdx.x >= gb.bo[c + 1]) ++c;
     const int bits = 4 + c;                  // log2 S
     const int G = (16 >> LB) << c;
-    const int NV = (16 * SPL) >> c;
+    const int NV = (16 * SPL) >> c;          // lane groups per workgroup
     const int kv = t >> (4 - LB + c), li = t & (G - 1);
     const int S = 16 << c;
-    int32_t *key = s_key + kv * S;
-    uint32_t *es = s_e + kv * S, *hs = s_hi + kv * S;
+    // lane group kv sweeps vertices k0 + kv + j * NV, j < VPG, interleaved
+    int32_t *key[VPG];
+    uint32_t *es[VPG], *hs[VPG];
 #pragma unroll
-    for (int q = 0; q < SPL; ++q) {
-        key[li * SPL + q] = kEmpty;
-        es[li * SPL + q] = 0;
-    }
-    const int64_t k = gb.cstart[c] + ((int64_t)blockIdx.x - gb.bo[c]) * NV + kv;
-    bool live = false;
-    int32_t v = 0;
-    int g = 0;
-    int64_t rs = 0, d = 0;
-    if (k < gb.cstart[c + 1]) {
-        v = list[k];
-        const uint64_t ri = info[k];
-        g = graph_of(a.gid, v);
-        live = !a.st[g].done;
-        if (live) {
-            rs = info_start(ri);
-            d = info_len(ri);
-        }
-    }
-    // A class-c row has d <= 2S/3 entries, at most U per lane: their loads
-    // and gathers are all issued before the first insert.
-    int32_t jq[U];
-    uint32_t wq[U];
-    uint64_t nq[U];
-    uint32_t loop = 0;
+    for (int j = 0; j < VPG; ++j) {
+        key[j] = s_key + (j * NV + kv) * S;
+        es[j] = s_e + (j * NV + kv) * S;
+        hs[j] = s_hi + (j * NV + kv) * S;
 #pragma unroll
-    for (int q = 0; q < U; ++q) {
-        const int64_t x = li + (int64_t)q * G;
-        jq[q] = v;
-        wq[q] = 0;
-        if (x < d) {
-            jq[q] = a.col[rs + x];
-            wq[q] = cw<W>(a.w, rs + x);
+        for (int q = 0; q < SPL; ++q) {
+            key[j][li * SPL + q] = kEmpty;
+            es[j][li * SPL + q] = 0;
         }
-    }
-#pragma unroll
-    for (int q = 0; q < U; ++q) {
-        nq[q] = 0;
-        if (jq[q] != v) nq[q] = a.vw[jq[q]];
-    }
-    int32_t ci = -1;
-    uint32_t own_hi = 0;
-    int64_t di = 0, tw = 0;
-    if (live) {
-        const uint64_t own = a.vw[v];
-        ci = vw_label(own);
-        own_hi = (uint32_t)(own >> 32);
-        di = a.delta[v];
-        tw = a.tw[g];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < U; ++q) {
-        if (jq[q] == v)
-            loop += wq[q];
-        else
-            grp_insert(key, es, hs, bits, vw_label(nq[q]), wq[q], (uint32_t)(nq[q] >> 32));
-    }
-    for (int64_t x = li + (int64_t)U * G; x < d; x += G) {   // not reached for class rows
-        const int32_t j = a.col[rs + x];
-        const uint32_t w = cw<W>(a.w, rs + x);
-        if (j == v) {
-            loop += w;
-            continue;
-        }
-        const uint64_t nw = a.vw[j];
-        grp_insert(key, es, hs, bits, vw_label(nw), w, (uint32_t)(nw >> 32));
-    }
-    __syncthreads();
-    unsigned long long bok = 0;
-    uint32_t blf = 0xffffffffu, e_own = 0;
-#pragma unroll
-    for (int q = 0; q < SPL; ++q) {
-        const int x = li * SPL + q;
-        const int32_t kk = key[x];
-        if (kk == kEmpty) continue;
-        const uint32_t e = es[x];
-        if (kk == ci) {
-            e_own += e;
-            continue;
-        }
-        const uint32_t hi = hs[x];
-        const int64_t sc = tw * (int64_t)e - di * (int64_t)hi_deg(hi);
-        const unsigned long long ok = (unsigned long long)sc ^ 0x8000000000000000ull;
-        const uint32_t lf = ((uint32_t)kk << 1) | (hi_single(hi) ? 1u : 0u);
-        if (ok > bok || (ok == bok && lf < blf)) {
-            bok = ok;
-            blf = lf;
-        }
-    }
-    const int GW = G < 64 ? G : 64;
-    for (int off = GW >> 1; off > 0; off >>= 1) {
-        const unsigned long long ook = __shfl_xor(bok, off);
-        const uint32_t olf = __shfl_xor(blf, off);
-        if (ook > bok || (ook == bok && olf < blf)) {
-            bok = ook;
-            blf = olf;
-        }
-        e_own += __shfl_xor(e_own, off);
-        loop += __shfl_xor(loop, off);
-    }
-    if (G > 64) {   // uniform over the workgroup: the class is
-        const int wid = t >> 6;
-        if ((t & 63) == 0) {
-            r_ok[wid] = bok;
-            r_lf[wid] = blf;
-            r_eo[wid] = e_own;
-            r_lp[wid] = loop;
-        }
-        __syncthreads();
         if (li == 0) {
-            for (int w2 = wid + 1; w2 < wid + G / 64; ++w2) {
-                if (r_ok[w2] > bok || (r_ok[w2] == bok && r_lf[w2] < blf)) {
-                    bok = r_ok[w2];
-                    blf = r_lf[w2];
-                }
-                e_own += r_eo[w2];
-                loop += r_lp[w2];
+            s_eown[j * NV + kv] = 0;
+            s_loop[j * NV + kv] = 0;
+        }
+    }
+    const int64_t k0 = gb.cstart[c] + ((int64_t)blockIdx.x - gb.bo[c]) * NV * VPG;
+    bool live[VPG];
+    int32_t v[VPG];
+    int g[VPG];
+    int64_t rs[VPG], d[VPG];
+#pragma unroll
+    for (int j = 0; j < VPG; ++j) {
+        const int64_t k = k0 + kv + (int64_t)j * NV;
+        live[j] = false;
+        v[j] = 0;
+        g[j] = 0;
+        rs[j] = 0;
+        d[j] = 0;
+        if (k < gb.cstart[c + 1]) {
+            v[j] = list[k];
+            const uint64_t ri = info[k];
+            g[j] = graph_of(a.gid, v[j]);
+            live[j] = !a.st[g[j]].done;
+            if (live[j]) {
+                rs[j] = info_start(ri);
+                d[j] = info_len(ri);
             }
         }
     }
-    if (li == 0 && live) {
-        a.c_nxt[v] = cpt_decide(a.singlet, tw, ci, own_hi, di, (int64_t)e_own, bok != 0,
-                                (int64_t)(bok ^ 0x8000000000000000ull), (int32_t)(blf >> 1), (blf & 1u) != 0);
-        a.e_self[v] = e_own + loop;
+    // A class-c row has d <= 2S/3 entries, at most U per lane: the loads and
+    // gathers of all of a lane's entries are issued before the first insert.
+    int32_t jq[VPG][U];
+    uint32_t wq[VPG][U];
+    uint64_t nq[VPG][U];
+#pragma unroll
+    for (int j = 0; j < VPG; ++j) {
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int64_t x = li + (int64_t)q * G;
+            jq[j][q] = v[j];
+            wq[j][q] = 0;
+            if (x < d[j]) {
+                jq[j][q] = a.col[rs[j] + x];
+                wq[j][q] = cw<W>(a.w, rs[j] + x);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < VPG; ++j)
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            nq[j][q] = 0;
+            if (jq[j][q] != v[j]) nq[j][q] = a.vw[jq[j][q]];
+        }
+    // TW, delta_i, deg_C and e_{i->C} are below 2^31 here: scores are
+    // products of 32-bit operands
+    int32_t ci[VPG];
+    uint32_t own_hi[VPG], di[VPG], tw[VPG];
+#pragma unroll
+    for (int j = 0; j < VPG; ++j) {
+        ci[j] = -1;
+        own_hi[j] = 0;
+        di[j] = 0;
+        tw[j] = 0;
+        if (live[j]) {
+            const uint64_t own = a.vw[v[j]];
+            ci[j] = vw_label(own);
+            own_hi[j] = (uint32_t)(own >> 32);
+            di[j] = (uint32_t)a.delta[v[j]];
+            tw[j] = (uint32_t)a.tw[g[j]];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+#pragma unroll
+        for (int j = 0; j < VPG; ++j) {
+            if (jq[j][q] == v[j]) {
+                if (wq[j][q]) s_loop[j * NV + kv] = wq[j][q];
+            } else
+                grp_insert(key[j], es[j], hs[j], bits, vw_label(nq[j][q]), wq[j][q], (uint32_t)(nq[j][q] >> 32));
+        }
+#pragma unroll
+    for (int j = 0; j < VPG; ++j)
+        for (int64_t x = li + (int64_t)U * G; x < d[j]; x += G) {   // not reached for class rows
+            const int32_t nb = a.col[rs[j] + x];
+            const uint32_t w = cw<W>(a.w, rs[j] + x);
+            if (nb == v[j]) {
+                s_loop[j * NV + kv] = w;
+                continue;
+            }
+            const uint64_t nw = a.vw[nb];
+            grp_insert(key[j], es[j], hs[j], bits, vw_label(nw), w, (uint32_t)(nw >> 32));
+        }
+    __syncthreads();
+    unsigned long long bok[VPG];
+    uint32_t blf[VPG];
+#pragma unroll
+    for (int j = 0; j < VPG; ++j) {
+        bok[j] = 0;
+        blf[j] = 0xffffffffu;
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) {
+            const int x = li * SPL + q;
+            const int32_t kk = key[j][x];
+            if (kk == kEmpty) continue;
+            const uint32_t e = es[j][x];
+            if (kk == ci[j]) {
+                s_eown[j * NV + kv] = e;
+                continue;
+            }
+            const uint32_t hi = hs[j][x];
+            // TW e - delta_i deg_C as a two's complement word, its sign bit
+            // flipped so that unsigned order is signed order
+            const unsigned long long ok =
+                ((uint64_t)tw[j] * e - (uint64_t)di[j] * hi_deg(hi)) ^ 0x8000000000000000ull;
+            const uint32_t lf = ((uint32_t)kk << 1) | (hi_single(hi) ? 1u : 0u);
+            best_take(bok[j], blf[j], (uint32_t)ok, (uint32_t)(ok >> 32), lf);
+        }
+    }
+    const int GW = G < 64 ? G : 64;
+#pragma unroll
+    for (int j = 0; j < VPG; ++j) group_best(bok[j], blf[j], GW);
+    if (G > 64) {   // uniform over the workgroup: the class is
+        const int wid = t >> 6;
+        if ((t & 63) == 0) {
+#pragma unroll
+            for (int j = 0; j < VPG; ++j) {
+                r_ok[j][wid] = bok[j];
+                r_lf[j][wid] = blf[j];
+            }
+        }
+        __syncthreads();
+        if (li == 0) {
+#pragma unroll
+            for (int j = 0; j < VPG; ++j)
+                for (int w2 = wid + 1; w2 < wid + G / 64; ++w2) {
+                    if (r_ok[j][w2] > bok[j] || (r_ok[j][w2] == bok[j] && r_lf[j][w2] < blf[j])) {
+                        bok[j] = r_ok[j][w2];
+                        blf[j] = r_lf[j][w2];
+                    }
+                }
+        }
+    } else {
+        // the group's lanes are in one wavefront: its LDS accesses complete
+        // in order, so the cells written above are visible to lane 0
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    if (li == 0) {
+#pragma unroll
+        for (int j = 0; j < VPG; ++j) {
+            if (!live[j]) continue;
+            const uint32_t e_own = s_eown[j * NV + kv];
+            a.c_nxt[v[j]] = cpt_decide(a.singlet, (int64_t)tw[j], ci[j], own_hi[j], (int64_t)di[j], (int64_t)e_own,
+                                       bok[j] != 0, (int64_t)(bok[j] ^ 0x8000000000000000ull),
+                                       (int32_t)(blf[j] >> 1), (blf[j] & 1u) != 0);
+            a.e_self[v[j]] = e_own + s_loop[j * NV + kv];
+        }
     }
 }
 
@@ -960,8 +1042,7 @@ __global__ __launch_bounds__(256) void k_cpt_hub_accum(CArgs a, CHub hm, unsigne
 __global__ __launch_bounds__(256) void k_cpt_hub_scan(CArgs a, CHub hm, unsigned long long *gtab, uint64_t *part) {
     __shared__ int64_t s_h;
     __shared__ unsigned long long r_ok[4];
-    __shared__ int32_t r_l[4], r_f[4];
-    __shared__ uint32_t r_e[4];
+    __shared__ uint32_t r_lf[4], r_e[4];
     const int t = threadIdx.x;
     if (t == 0) s_h = hm.scan_hub[blockIdx.x];
     __syncthreads();
@@ -969,11 +1050,12 @@ __global__ __launch_bounds__(256) void k_cpt_hub_scan(CArgs a, CHub hm, unsigned
     const int32_t v = hm.v[h];
     const int g = graph_of(a.gid, v);
     const int32_t ci = vw_label(a.vw[v]);
-    const int64_t di = a.delta[v];
-    const int64_t tw = a.tw[g];
+    // TW, delta_i, deg_C and e_{i->C} are below 2^31: 32-bit operands
+    const uint32_t di = (uint32_t)a.delta[v];
+    const uint32_t tw = (uint32_t)a.tw[g];
     const int64_t base = hm.tab_off[h] + ((int64_t)blockIdx.x - hm.scan_off[h]) * kHubScan;
     unsigned long long bok = 0;
-    int32_t bl = 0x7fffffff, bf = 0;
+    uint32_t blf = 0xffffffffu;
     uint32_t e_own = 0;
 #pragma unroll
     for (int q = 0; q < kHubScan / 256; ++q) {
@@ -988,46 +1070,28 @@ __global__ __launch_bounds__(256) void k_cpt_hub_scan(CArgs a, CHub hm, unsigned
             continue;
         }
         const uint64_t dsk = a.ds[k];
-        const int64_t sc = tw * (int64_t)e - di * (int64_t)(uint32_t)dsk;
-        const unsigned long long ok = (unsigned long long)sc ^ 0x8000000000000000ull;
-        if (ok > bok || (ok == bok && k < bl)) {
-            bok = ok;
-            bl = k;
-            bf = (dsk >> 32) == 1 ? 1 : 0;
-        }
+        const unsigned long long ok = ((uint64_t)tw * e - (uint64_t)di * (uint32_t)dsk) ^ 0x8000000000000000ull;
+        const uint32_t lf = ((uint32_t)k << 1) | ((dsk >> 32) == 1 ? 1u : 0u);
+        best_take(bok, blf, (uint32_t)ok, (uint32_t)(ok >> 32), lf);
     }
+    group_best(bok, blf, 64);
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long ook = __shfl_xor(bok, off);
-        const int32_t ol = __shfl_xor(bl, off);
-        const int32_t of = __shfl_xor(bf, off);
-        if (ook > bok || (ook == bok && ol < bl)) {
-            bok = ook;
-            bl = ol;
-            bf = of;
-        }
-        e_own += __shfl_xor(e_own, off);
-    }
+    for (int off = 32; off > 0; off >>= 1) e_own += __shfl_xor(e_own, off);
     const int lane = t & 63, wid = t >> 6;
     if (lane == 0) {
         r_ok[wid] = bok;
-        r_l[wid] = bl;
-        r_f[wid] = bf;
+        r_lf[wid] = blf;
         r_e[wid] = e_own;
     }
     __syncthreads();
     if (t == 0) {
         for (int w = 1; w < 4; ++w) {
-            if (r_ok[w] > bok || (r_ok[w] == bok && r_l[w] < bl)) {
-                bok = r_ok[w];
-                bl = r_l[w];
-                bf = r_f[w];
-            }
+            best_take(bok, blf, (uint32_t)r_ok[w], (uint32_t)(r_ok[w] >> 32), r_lf[w]);
             e_own += r_e[w];
         }
         uint64_t *p = part + 4 * (int64_t)blockIdx.x;
         p[0] = bok;
-        p[1] = (uint64_t)(uint32_t)bl | ((uint64_t)bf << 32);
+        p[1] = (uint64_t)(blf >> 1) | ((uint64_t)(blf & 1u) << 32);
         p[2] = e_own;
         p[3] = 0;
     }
@@ -1146,8 +1210,13 @@ void compact_expand(const uint64_t *ds, const uint32_t *es, int64_t n, int64_t *
     LV_LAUNCHED("k_cpt_expand");
 }
 
+// The row families are independent within a pass (each reads the
+// published words and writes its own rows' labels).  With side streams,
+// the one-workgroup rows and the hub kernels run on them beside the rows of
+// up to 341 entries on s (each family fills the others' tails; they share
+// the device, so each one's own duration grows), and s waits for both.
 template <typename W>
-static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s, Timer *t) {
+static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s, SideStreams *side, Timer *t) {
     const char *wn = type_name<W>();
     const std::string sfx = t ? std::string(wn) + ">" : std::string();
     const double eb = 8.0 + sizeof(W);   // column, weight, neighbour word
@@ -1157,6 +1226,13 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
         for (int b = b0; b < b1; ++b) x += (double)(cp.bstart[b + 1] - cp.bstart[b]) * vb + (double)cp.bnnz[b] * eb;
         return x;
     };
+    const bool fork = side && (cp.hubs > 0 || cp.cstart[kGroupClasses + 2] > cp.cstart[kGroupClasses]);
+    hipStream_t s1 = s, s2 = s;
+    if (fork) {
+        side->fork(s);
+        s1 = (*side)[0];
+        s2 = (*side)[1];
+    }
     if (cp.bstart[B_T16] - cp.bstart[B_T8] > 0) {
         TimedLaunch tl(t, TG_SWEEP, "k_cpt_small<", bytes(B_T8, B_T16), sfx.c_str());
         tl.launch(k_cpt_small<W>, grid_for(cp.n, 256), 256, 0, s, a, cp.n, cp.small_max);
@@ -1167,23 +1243,30 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
         gb.bo[0] = 0;
         double gbytes = 0;
         const int spl = cp.group_slots == 8 ? 8 : cp.group_slots == 2 ? 2 : 4;
+        const int vpg = cp.group_vertices == 2 ? 2 : 1;
         for (int c = 0; c < kGroupClasses; ++c) {
             const int64_t cnt = cp.cstart[c + 1] - cp.cstart[c];
-            const int nv = (16 * spl) >> c;
+            const int nv = ((16 * spl) >> c) * vpg;
             gb.bo[c + 1] = gb.bo[c] + (cnt + nv - 1) / nv;
             gbytes += (double)cnt * vb + (double)cp.cnnz[c] * eb;
         }
         for (int c = 0; c <= kGroupClasses; ++c) gb.cstart[c] = cp.cstart[c];
         if (gb.bo[kGroupClasses] > 0) {
-            TimedLaunch tl(t, TG_SWEEP, spl == 8 ? "k_cpt_groups<8," : spl == 2 ? "k_cpt_groups<2," : "k_cpt_groups<4,",
-                           gbytes, sfx.c_str());
+            const std::string name = "k_cpt_groups<" + std::to_string(spl) + "," + std::to_string(vpg) + ",";
+            TimedLaunch tl(t, TG_SWEEP, name.c_str(), gbytes, sfx.c_str());
             const unsigned nb = (unsigned)gb.bo[kGroupClasses];
-            if (spl == 8)
-                tl.launch(k_cpt_groups<8, W>, nb, 256, 0, s, a, cp.glist, cp.ginfo, gb);
+            if (spl == 8 && vpg == 1)
+                tl.launch(k_cpt_groups<8, 1, W>, nb, 256, 0, s, a, cp.glist, cp.ginfo, gb);
+            else if (spl == 8)
+                tl.launch(k_cpt_groups<8, 2, W>, nb, 256, 0, s, a, cp.glist, cp.ginfo, gb);
+            else if (spl == 2 && vpg == 1)
+                tl.launch(k_cpt_groups<2, 1, W>, nb, 256, 0, s, a, cp.glist, cp.ginfo, gb);
             else if (spl == 2)
-                tl.launch(k_cpt_groups<2, W>, nb, 256, 0, s, a, cp.glist, cp.ginfo, gb);
+                tl.launch(k_cpt_groups<2, 2, W>, nb, 256, 0, s, a, cp.glist, cp.ginfo, gb);
+            else if (vpg == 1)
+                tl.launch(k_cpt_groups<4, 1, W>, nb, 256, 0, s, a, cp.glist, cp.ginfo, gb);
             else
-                tl.launch(k_cpt_groups<4, W>, nb, 256, 0, s, a, cp.glist, cp.ginfo, gb);
+                tl.launch(k_cpt_groups<4, 2, W>, nb, 256, 0, s, a, cp.glist, cp.ginfo, gb);
             LV_LAUNCHED("k_cpt_groups");
         }
     }
@@ -1193,7 +1276,7 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
         if (nw > 0) {
             TimedLaunch tl(t, TG_SWEEP, "k_cpt_group<2048,256,", (double)nw * vb + (double)cp.cnnz[c] * eb,
                            sfx.c_str());
-            tl.launch(k_cpt_group<2048, 256, W>, (unsigned)nw, 256, 0, s, a, cp.glist + cp.cstart[c],
+            tl.launch(k_cpt_group<2048, 256, W>, (unsigned)nw, 256, 0, s1, a, cp.glist + cp.cstart[c],
                       cp.ginfo + cp.cstart[c], nw);
             LV_LAUNCHED("k_cpt_group<2048>");
         }
@@ -1201,7 +1284,7 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
         if (nx > 0) {
             TimedLaunch tl(t, TG_SWEEP, "k_cpt_group<4096,256,", (double)nx * vb + (double)cp.cnnz[c + 1] * eb,
                            sfx.c_str());
-            tl.launch(k_cpt_group<4096, 256, W>, (unsigned)nx, 256, 0, s, a, cp.glist + cp.cstart[c + 1],
+            tl.launch(k_cpt_group<4096, 256, W>, (unsigned)nx, 256, 0, s1, a, cp.glist + cp.cstart[c + 1],
                       cp.ginfo + cp.cstart[c + 1], nx);
             LV_LAUNCHED("k_cpt_group<4096>");
         }
@@ -1211,20 +1294,21 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
                 cp.chunk_hub, cp.scan_hub, cp.hubs};
         {
             TimedLaunch tl(t, TG_SWEEP, "k_cpt_hub_accum<", (double)cp.bnnz[B_HUB] * eb, sfx.c_str());
-            tl.launch(k_cpt_hub_accum<W>, (unsigned)cp.hub_chunks, 256, 0, s, a, hm, cp.hval, cp.hloop);
+            tl.launch(k_cpt_hub_accum<W>, (unsigned)cp.hub_chunks, 256, 0, s2, a, hm, cp.hval, cp.hloop);
             LV_LAUNCHED("k_cpt_hub_accum");
         }
         {
             TimedLaunch tl(t, TG_SWEEP, "k_cpt_hub_scan", (double)cp.hub_scans * kHubScan * 16.0);
-            tl.launch(k_cpt_hub_scan, (unsigned)cp.hub_scans, 256, 0, s, a, hm, cp.hval, cp.hpart);
+            tl.launch(k_cpt_hub_scan, (unsigned)cp.hub_scans, 256, 0, s2, a, hm, cp.hval, cp.hpart);
             LV_LAUNCHED("k_cpt_hub_scan");
         }
         {
             TimedLaunch tl(t, TG_SWEEP, "k_cpt_hub_decide", (double)cp.hubs * vb + (double)cp.hub_scans * 32.0);
-            tl.launch(k_cpt_hub_decide, grid_for(cp.hubs, 4), 256, 0, s, a, hm, cp.hpart, cp.hloop);
+            tl.launch(k_cpt_hub_decide, grid_for(cp.hubs, 4), 256, 0, s2, a, hm, cp.hpart, cp.hloop);
             LV_LAUNCHED("k_cpt_hub_decide");
         }
     }
+    if (fork) side->join(s);
 }
 
 void compact_pass(const GraphView &g, const CompactPass &cp, const CompactState &cs, int p,
@@ -1236,10 +1320,11 @@ void compact_pass(const GraphView &g, const CompactPass &cp, const CompactState 
         LV_LAUNCHED("k_cpt_publish");
     }
     CArgs a{g.row_ptr, g.col, g.w, cs.c_cur, cs.c_nxt, g.delta, cs.vw, cs.ds, cs.gid, cs.tw, cs.st, cs.es, prm.singlet};
+    SideStreams *side = cp.overlap ? cs.side : nullptr;
     if (g.wbytes == 4)
-        compact_sweeps<int32_t>(a, cp, s, t);
+        compact_sweeps<int32_t>(a, cp, s, side, t);
     else
-        compact_sweeps<int64_t>(a, cp, s, t);
+        compact_sweeps<int64_t>(a, cp, s, side, t);
     if (g.n > 0) {
         TimedLaunch tl(t, TG_SWEEP, "k_cpt_commit", (double)g.n * 12);
         tl.launch(k_cpt_commit, grid_for(g.n, kCommitTile), 256, 0, s, cs.c_cur, cs.c_nxt, g.delta, cs.es, cs.ds,

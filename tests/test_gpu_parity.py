@@ -285,17 +285,18 @@ def test_launch_shapes_do_not_change_results(ctx):
     refs = [oracle.louvain(g.row_ptr, g.col, g.w) for g in graphs]
     Gs = [ctx.graph_create(g.row_ptr, g.col, g.w) for g in graphs]
     try:
-        for sm, bm, pb, gs in [(1, 341, 1, 4), (4, 1024, 2, 8), (8, 1365, 1, 2), (2, 2730, 3, 4), (4, 2730, 2, 8),
-                               (3, 700, 1, 2)]:
-            ctx.set_tuning(sm, bm, pb, gs)
-            assert ctx.get_tuning() == dict(small_max=sm, block_max=bm, pass_batch=pb, group_slots=gs)
+        for shp in [(1, 341, 1, 4, 1, 0), (4, 1024, 2, 8, 2, 1), (8, 1365, 1, 2, 2, 0), (2, 2730, 3, 4, 1, 1),
+                    (4, 2730, 2, 8, 1, 0), (3, 700, 1, 2, 1, 1), (4, 2730, 2, 4, 2, 1)]:
+            ctx.set_tuning(*shp)
+            keys = ("small_max", "block_max", "pass_batch", "group_slots", "group_vertices", "overlap")
+            assert ctx.get_tuning() == dict(zip(keys, shp))
             for k, (G, ref) in enumerate(zip(Gs, refs)):
                 r = ctx.run(G)
-                assert np.array_equal(r.labels, ref.labels), f"labels differ, graph {k}, shapes {(sm, bm, pb, gs)}"
+                assert np.array_equal(r.labels, ref.labels), f"labels differ, graph {k}, shapes {shp}"
                 assert r.q_int == ref.q_int
             res = ctx.run_batch(Gs)
             for k, (r, ref) in enumerate(zip(res, refs)):
-                assert np.array_equal(r.labels, ref.labels), f"batched labels differ, graph {k}, {(sm, bm, pb, gs)}"
+                assert np.array_equal(r.labels, ref.labels), f"batched labels differ, graph {k}, {shp}"
     finally:
         ctx.set_tuning()
         for G in Gs:
@@ -308,8 +309,10 @@ def test_autotune(ctx, L):
     try:
         best = ctx.autotune(G)
         assert best["small_max"] in (4, 8) and best["block_max"] in (1024, 1365, 2730)
-        assert best["pass_batch"] in (1, 2) and best["group_slots"] in (2, 4, 8) and best["ms"] > 0
-        assert ctx.get_tuning() == {k: best[k] for k in ("small_max", "block_max", "pass_batch", "group_slots")}
+        assert best["pass_batch"] in (1, 2) and best["group_slots"] == 4 and best["ms"] > 0
+        assert best["group_vertices"] in (1, 2) and best["overlap"] == 0
+        assert ctx.get_tuning() == {k: best[k] for k in ("small_max", "block_max", "pass_batch", "group_slots",
+                                                         "group_vertices", "overlap")}
         r = ctx.run(G)
         ref = oracle.louvain(g.row_ptr, g.col, g.w)
         assert np.array_equal(r.labels, ref.labels) and r.q_int == ref.q_int
@@ -319,6 +322,10 @@ def test_autotune(ctx, L):
             ctx.set_tuning(block_max=100)
         with pytest.raises(L.LouvainError):
             ctx.set_tuning(group_slots=6)
+        with pytest.raises(L.LouvainError):
+            ctx.set_tuning(group_vertices=3)
+        with pytest.raises(L.LouvainError):
+            ctx.set_tuning(overlap=2)
     finally:
         ctx.set_tuning()
         G.destroy()
