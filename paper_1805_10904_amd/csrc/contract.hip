@@ -270,12 +270,8 @@ __device__ __forceinline__ int lds_slot(int32_t *key, int32_t k) {
     constexpr uint32_t mask = (1u << kSegBits) - 1;
     uint32_t h = ((uint32_t)k * 0x9E3779B1u) >> (32 - kSegBits);
     while (true) {
-        const int32_t cur = ((volatile int32_t *)key)[h];
-        if (cur == k) return (int)h;
-        if (cur == kEmpty) {
-            const int32_t prev = atomicCAS(&key[h], kEmpty, k);
-            if (prev == kEmpty || prev == k) return (int)h;
-        }
+        const int32_t prev = atomicCAS(&key[h], kEmpty, k);   // claims, or returns the slot's key
+        if (prev == kEmpty || prev == k) return (int)h;
         h = (h + 1) & mask;
     }
 }
@@ -453,12 +449,8 @@ __device__ __forceinline__ void chunk_aggregate(const int64_t *__restrict__ off,
         const long long val = (long long)tw[cb + x];
         uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - kChunkBits));
         while (true) {
-            const unsigned long long cur = ((volatile unsigned long long *)s_hk)[h];
-            if (cur == key) break;
-            if (cur == kNoKey) {
-                const unsigned long long prev = atomicCAS(&s_hk[h], kNoKey, key);
-                if (prev == kNoKey || prev == key) break;
-            }
+            const unsigned long long prev = atomicCAS(&s_hk[h], kNoKey, key);   // claims, or returns the key
+            if (prev == kNoKey || prev == key) break;
             h = (h + 1) & mask;
         }
         atomicAdd((unsigned long long *)&s_hv[h], (unsigned long long)val);

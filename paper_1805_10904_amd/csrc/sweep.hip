@@ -51,17 +51,10 @@ __device__ __forceinline__ void lds_insert(int32_t *key, unsigned long long *val
     constexpr uint32_t kMask = (1u << BITS) - 1;
     uint32_t h = hash_pow2(k, BITS);
     while (true) {
-        int32_t cur = ((volatile int32_t *)key)[h];
-        if (cur == k) {
+        const int32_t prev = atomicCAS(&key[h], kEmpty, k);   // claims, or returns the slot's key
+        if (prev == kEmpty || prev == k) {
             atomicAdd(&val[h], (unsigned long long)w);
             return;
-        }
-        if (cur == kEmpty) {
-            int32_t prev = atomicCAS(&key[h], kEmpty, k);
-            if (prev == kEmpty || prev == k) {
-                atomicAdd(&val[h], (unsigned long long)w);
-                return;
-            }
         }
         h = (h + 1) & kMask;
     }
@@ -336,18 +329,11 @@ __device__ __forceinline__ void lds_insert_rt(int32_t *key, unsigned long long *
     const uint32_t mask = (1u << bits) - 1;
     uint32_t h = ((uint32_t)k * 0x9E3779B1u) >> (32 - bits);
     while (true) {
-        const int32_t cur = ((volatile int32_t *)key)[h];
-        if (cur == k) {
+        const int32_t prev = atomicCAS(&key[h], kEmpty, k);   // claims, or returns the slot's key
+        if (prev == kEmpty) owner[h] = (uint8_t)own;
+        if (prev == kEmpty || prev == k) {
             atomicAdd(&val[h], (unsigned long long)w);
             return;
-        }
-        if (cur == kEmpty) {
-            const int32_t prev = atomicCAS(&key[h], kEmpty, k);
-            if (prev == kEmpty) owner[h] = (uint8_t)own;
-            if (prev == kEmpty || prev == k) {
-                atomicAdd(&val[h], (unsigned long long)w);
-                return;
-            }
         }
         h = (h + 1) & mask;
     }

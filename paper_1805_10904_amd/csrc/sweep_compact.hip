@@ -219,17 +219,10 @@ __device__ __forceinline__ bool commit_insert(int32_t *key, unsigned long long *
     constexpr uint32_t mask = (1u << kCommitBits) - 1;
     uint32_t h = ((uint32_t)k * 0x9E3779B1u) >> (32 - kCommitBits);
     for (int probe = 0; probe < kCommitProbe; ++probe) {
-        const int32_t cur = ((volatile int32_t *)key)[h];
-        if (cur == k) {
+        const int32_t prev = atomicCAS(&key[h], kEmpty, k);   // claims, or returns the slot's key
+        if (prev == kEmpty || prev == k) {
             atomicAdd(&val[h], x);
             return true;
-        }
-        if (cur == kEmpty) {
-            const int32_t prev = atomicCAS(&key[h], kEmpty, k);
-            if (prev == kEmpty || prev == k) {
-                atomicAdd(&val[h], x);
-                return true;
-            }
         }
         h = (h + 1) & mask;
     }
@@ -956,10 +949,27 @@ constexpr unsigned long long kTagMask = 0xffffffff00000000ull;
 
 // Hub tables hold one word per slot: (label + 1) << 32 | e, 0 = empty
 // (labels are below 2^31 and e below TW < 2^31, so the add never carries
-// into the tag).  Insert or add e for a label into a table of `size` slots
-// starting at h0's probe sequence.
+// into the tag).  Insert or add x for a label into an LDS table of `size`
+// slots, probing from slot h.
 __device__ __forceinline__ void word_insert(unsigned long long *tab, uint64_t size, uint64_t h, int32_t label,
                                             uint32_t x) {
+    const unsigned long long tag = (unsigned long long)(uint32_t)(label + 1) << 32;
+    while (true) {
+        // the compare-and-swap claims an empty slot, or returns its word
+        const unsigned long long prev = atomicCAS(&tab[h], 0ull, tag | x);
+        if (prev == 0) return;
+        if ((prev & kTagMask) == tag) {
+            atomicAdd(&tab[h], (unsigned long long)x);
+            return;
+        }
+        h = (h + 1 == size) ? 0 : h + 1;
+    }
+}
+
+// The same in an HBM table: a plain read first, so that a slot already
+// holding the label takes one add whose result is not waited for.
+__device__ __forceinline__ void word_insert_hbm(unsigned long long *tab, uint64_t size, uint64_t h, int32_t label,
+                                                uint32_t x) {
     const unsigned long long tag = (unsigned long long)(uint32_t)(label + 1) << 32;
     while (true) {
         const unsigned long long cur = ((volatile unsigned long long *)tab)[h];
@@ -1032,7 +1042,7 @@ __global__ __launch_bounds__(256) void k_cpt_hub_accum(CArgs a, CHub hm, unsigne
         const unsigned long long wd = s_tab[x];
         if (wd == 0) continue;
         const int32_t l = (int32_t)(wd >> 32) - 1;
-        word_insert(gtab + base, (uint64_t)size, hash_range(l, (uint64_t)size), l, (uint32_t)wd);
+        word_insert_hbm(gtab + base, (uint64_t)size, hash_range(l, (uint64_t)size), l, (uint32_t)wd);
     }
 }
 
