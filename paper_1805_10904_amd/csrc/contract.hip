@@ -420,7 +420,7 @@ __device__ __forceinline__ int64_t chunk_start(const int64_t *__restrict__ off, 
 __device__ __forceinline__ void chunk_aggregate(const int64_t *__restrict__ off, int64_t k, int64_t cb, int len,
                                                 const int32_t *__restrict__ tcol, const int64_t *__restrict__ tw,
                                                 unsigned long long *s_hk, long long *s_hv, int32_t *s_mark,
-                                                int32_t *s_wave, int64_t *s_range) {
+                                                int32_t *s_wave, int64_t *s_range, bool skip_big) {
     constexpr int T = 1 << kChunkBits;
     constexpr uint32_t mask = T - 1;
     const int t = threadIdx.x;
@@ -444,8 +444,15 @@ __device__ __forceinline__ void chunk_aggregate(const int64_t *__restrict__ off,
     if (t == 0) s_mark[0] = 0;   // markers never land on position 0
     __syncthreads();
     block_max_scan_chunk(s_mark, s_wave);
+    // with skip_big, entries of segments longer than kChunkMax (only the
+    // chunk's first and last segment can be) are left to k_big_piece
+    const int32_t last_local = (int32_t)(shi - slo);
+    const bool first_big = skip_big && off[slo + 1] - off[slo] > kChunkMax;
+    const bool last_big = skip_big && off[shi + 1] - off[shi] > kChunkMax;
     for (int x = t; x < len; x += 256) {
-        const unsigned long long key = ((unsigned long long)(uint32_t)s_mark[x] << 32) | (uint32_t)tcol[cb + x];
+        const int32_t ls = s_mark[x];
+        if ((ls == 0 && first_big) || (ls == last_local && last_big)) continue;
+        const unsigned long long key = ((unsigned long long)(uint32_t)ls << 32) | (uint32_t)tcol[cb + x];
         const long long val = (long long)tw[cb + x];
         uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - kChunkBits));
         while (true) {
@@ -492,7 +499,7 @@ __global__ __launch_bounds__(256) void k_seg_chunk_any(const int64_t *__restrict
     const int64_t cb = s_bounds[0], ce = s_bounds[1];
     const int len = (int)(ce - cb);
     if (len <= 0) return;   // uniform: every segment around here was taken by a neighbour
-    chunk_aggregate(off, k, cb, len, tcol, tw, s_hk, s_hv, s_mark, s_wave, s_range);
+    chunk_aggregate(off, k, cb, len, tcol, tw, s_hk, s_hv, s_mark, s_wave, s_range, true);
     const int64_t slo = s_range[0], shi = s_range[1];
     const bool first_spans = off[slo] < cb;
     const bool last_spans = off[shi + 1] > ce;
@@ -549,6 +556,114 @@ __global__ __launch_bounds__(256) void k_seg_chunk_any(const int64_t *__restrict
     }
 }
 
+// Segments longer than kChunkMax entries (the communities with the most
+// member entries) are cut into pieces of kPiece entries, one 1,024-thread
+// workgroup each with a 2^13-slot LDS table keyed by column.  A segment of
+// one piece whose columns all found a slot and that has at most
+// kPieceDirectMax distinct columns writes its pairs in place (table order)
+// and its count.  Otherwise the piece's pairs (and any pair that found no
+// slot within kPieceProbe probes) join the partial pairs that are sorted and
+// merged, like those of segments crossing a chunk boundary: the longer rows
+// are swept through HBM hub tables at the next level, whose LDS
+// pre-aggregation gains from ascending columns.
+constexpr int kPiece = 16384;
+constexpr int kPieceBits = 13;
+constexpr int kPieceProbe = 32;
+constexpr int kPieceThreads = 1024;
+constexpr int kPieceDirectMax = 2730;
+
+// Pieces of every segment (0 for segments of at most kChunkMax entries).
+__global__ __launch_bounds__(256) void k_big_pieces(const int64_t *__restrict__ off, int64_t k, int64_t *pieces) {
+    const int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (a >= k) return;
+    const int64_t sz = off[a + 1] - off[a];
+    pieces[a] = sz > kChunkMax ? (sz + kPiece - 1) / kPiece : 0;
+}
+
+// One workgroup per piece; poff: exclusive scan of the pieces (k + 1).
+__global__ __launch_bounds__(kPieceThreads) void k_big_piece(const int64_t *__restrict__ off, int64_t k,
+                                                             const int64_t *__restrict__ poff, int32_t *tcol,
+                                                             int64_t *tw, int64_t *mcount, uint64_t *pkey,
+                                                             int64_t *pval, unsigned long long *pcount, int bits) {
+    constexpr int T = 1 << kPieceBits;
+    constexpr int Q = T / kPieceThreads;
+    __shared__ int32_t s_k[T];
+    __shared__ long long s_v[T];
+    __shared__ int64_t s_seg, s_idx;
+    __shared__ int s_n, s_over;
+    __shared__ unsigned long long s_base;
+    const int t = threadIdx.x;
+    for (int x = t; x < T; x += kPieceThreads) {
+        s_k[x] = kEmpty;
+        s_v[x] = 0;
+    }
+    if (t < 64) {
+        const int64_t a = wave_find_le(poff, k, (int64_t)blockIdx.x);   // the segment holding this piece
+        if (t == 0) {
+            s_seg = a;
+            s_idx = (int64_t)blockIdx.x - poff[a];
+            s_n = 0;
+            s_over = 0;
+        }
+    }
+    __syncthreads();
+    const int64_t a = s_seg;
+    const int64_t lo = off[a] + s_idx * kPiece;
+    const int64_t end = off[a + 1] < lo + kPiece ? off[a + 1] : lo + kPiece;
+    for (int64_t e = lo + t; e < end; e += kPieceThreads) {
+        const int32_t c = tcol[e];
+        const int64_t w = tw[e];
+        uint32_t h = ((uint32_t)c * 0x9E3779B1u) >> (32 - kPieceBits);
+        bool placed = false;
+        for (int p = 0; p < kPieceProbe; ++p) {
+            const int32_t prev = atomicCAS(&s_k[h], kEmpty, c);   // claims, or returns the slot's column
+            if (prev == kEmpty || prev == c) {
+                atomicAdd((unsigned long long *)&s_v[h], (unsigned long long)w);
+                placed = true;
+                break;
+            }
+            h = (h + 1) & (T - 1);
+        }
+        if (!placed) {
+            s_over = 1;
+            const unsigned long long q = atomicAdd(pcount, 1ull);
+            pkey[q] = ((uint64_t)a << bits) | (uint32_t)c;
+            pval[q] = w;
+        }
+    }
+    __syncthreads();
+    int pos[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int x = t + q * kPieceThreads;
+        pos[q] = s_k[x] != kEmpty ? atomicAdd(&s_n, 1) : -1;
+    }
+    __syncthreads();
+    const bool direct = poff[a + 1] - poff[a] == 1 && s_over == 0 && s_n <= kPieceDirectMax;
+    if (direct) {
+        // the whole segment was read above; its pairs go in place
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (pos[q] < 0) continue;
+            const int x = t + q * kPieceThreads;
+            tcol[off[a] + pos[q]] = s_k[x];
+            tw[off[a] + pos[q]] = s_v[x];
+        }
+        if (t == 0) mcount[a] = s_n;
+        return;
+    }
+    if (t == 0) s_base = atomicAdd(pcount, (unsigned long long)s_n);
+    __syncthreads();
+    const unsigned long long base = s_base;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        if (pos[q] < 0) continue;
+        const int x = t + q * kPieceThreads;
+        pkey[base + pos[q]] = ((uint64_t)a << bits) | (uint32_t)s_k[x];
+        pval[base + pos[q]] = s_v[x];
+    }
+}
+
 // The exported contraction: as k_seg_chunk_any, but the distinct pairs of
 // a chunk are sorted (bitonic, in LDS) so that every row's columns ascend.
 __global__ __launch_bounds__(256) void k_seg_chunk(const int64_t *__restrict__ off, int64_t k, int64_t m_raw,
@@ -580,7 +695,7 @@ __global__ __launch_bounds__(256) void k_seg_chunk(const int64_t *__restrict__ o
     const int64_t cb = s_bounds[0], ce = s_bounds[1];
     const int len = (int)(ce - cb);
     if (len <= 0) return;
-    chunk_aggregate(off, k, cb, len, tcol, tw, s_hk, s_hv, s_mark, s_wave, s_range);
+    chunk_aggregate(off, k, cb, len, tcol, tw, s_hk, s_hv, s_mark, s_wave, s_range, false);
     const int64_t slo = s_range[0], shi = s_range[1];
     {   // compaction of the occupied slots: one LDS atomic per wavefront and round
         const int lane = t & 63;
@@ -801,8 +916,18 @@ int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t 
         tl.launch(k_seg_start, vb, 256, 0, s_, g.row_ptr, newlab, n, off, cursor, seg_start_.p);
         LV_LAUNCHED("k_seg_start");
     }
+    // pieces of the segments longer than kChunkMax (unsorted contraction)
+    TempBuf pieces(sorted ? 16 : (size_t)(k + 1) * sizeof(int64_t), s_);
+    int64_t *poff = pieces.as<int64_t>();
+    if (!sorted) {
+        TimedLaunch tl(t_, TG_CONTRACT, "k_big_pieces", (double)k * 24);
+        tl.launch(k_big_pieces, grid_for(k, 256), 256, 0, s_, off, k, poff);
+        LV_LAUNCHED("k_big_pieces");
+    }
+    if (!sorted) scan_exclusive<int64_t, int64_t>(poff, poff, k, poff + k, s_, t_);
     Readback rb(s_);
     const int64_t *mr = rb.add(off + k);
+    const int64_t *npc = sorted ? nullptr : rb.add(poff + k);
     rb.issue();   // read while the scatter runs
     {
         const int64_t eb = (g.nnz + kEntriesPerBlock - 1) / kEntriesPerBlock;
@@ -837,6 +962,13 @@ int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t 
             tl.launch(k_seg_chunk_any, (unsigned)cb, 256, 0, s_, off, k, m_raw, tcol_.p, tw_.p, mcount, key_[0].p,
                       val_[0].p, pc.as<unsigned long long>(), bits);
         LV_LAUNCHED("k_seg_chunk");
+    }
+    if (npc && *npc > 0) {
+        // at most kPiece entries (column, weight) read per piece
+        TimedLaunch tl(t_, TG_CONTRACT, "k_big_piece", (double)*npc * kPiece * 12);
+        tl.launch(k_big_piece, (unsigned)*npc, kPieceThreads, 0, s_, off, k, (const int64_t *)poff, tcol_.p, tw_.p,
+                  mcount, key_[0].p, val_[0].p, pc.as<unsigned long long>(), bits);
+        LV_LAUNCHED("k_big_piece");
     }
     const uint64_t *npp = rb.add(pc.as<uint64_t>());
     rb.fetch();
