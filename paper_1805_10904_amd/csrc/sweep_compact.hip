@@ -510,11 +510,12 @@ __device__ __forceinline__ void group_best(unsigned long long &bok, uint32_t &bl
 
 // Rows sorted into table-size classes: a workgroup holds 256/G vertices of
 // one class, each with an LDS table of S slots (S >= 1.5 d) and a group of G
-// lanes (packed classes G = S/4; rows of up to 1,024 entries S = 2048,
-// G = 256).  Lane i of a group takes entries i, i + G, ... of its vertex's
-// row, then scores slots [i*S/G, (i+1)*S/G); the argmax (largest score,
-// then smallest label) is a shuffle reduction inside the group, with an LDS
-// step across waves when the group spans several.
+// lanes (packed classes G = S/4; rows of up to 1,365 entries S = 2048 and of
+// up to 2,730 entries S = 4096, G = 256).  Lane i of a group takes entries
+// i, i + G, ... of its vertex's row, then scores slots i, i + G, ... (lanes
+// read consecutive words, free of bank conflicts); the argmax (largest
+// score, then smallest label) is a DPP / swizzle reduction inside each
+// wavefront, with an LDS step across waves when the group spans several.
 template <int S, int G, typename W>
 __global__ __launch_bounds__(256) void k_cpt_group(CArgs a, const int32_t *__restrict__ list,
                                                    const uint64_t *__restrict__ info, int64_t count) {
@@ -533,8 +534,8 @@ __global__ __launch_bounds__(256) void k_cpt_group(CArgs a, const int32_t *__res
     uint32_t *es = s_e + kv * S, *hs = s_hi + kv * S;
 #pragma unroll
     for (int q = 0; q < SPL; ++q) {
-        key[li * SPL + q] = kEmpty;
-        es[li * SPL + q] = 0;
+        key[li + q * G] = kEmpty;   // lane-consecutive words: no bank conflicts
+        es[li + q * G] = 0;
     }
     const int64_t k = (int64_t)blockIdx.x * NV + kv;
     bool live = false;
@@ -598,7 +599,7 @@ __global__ __launch_bounds__(256) void k_cpt_group(CArgs a, const int32_t *__res
     uint32_t blf = 0xffffffffu, e_own = 0;
 #pragma unroll
     for (int q = 0; q < SPL; ++q) {
-        const int x = li * SPL + q;
+        const int x = li + q * G;
         const int32_t kk = key[x];
         if (kk == kEmpty) continue;
         const uint32_t e = es[x];
@@ -689,8 +690,8 @@ __global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__re
         hs[j] = s_hi + (j * NV + kv) * S;
 #pragma unroll
         for (int q = 0; q < SPL; ++q) {
-            key[j][li * SPL + q] = kEmpty;
-            es[j][li * SPL + q] = 0;
+            key[j][li + q * G] = kEmpty;   // lane-consecutive words: no bank conflicts
+            es[j][li + q * G] = 0;
         }
         if (li == 0) {
             s_eown[j * NV + kv] = 0;
@@ -795,7 +796,7 @@ __global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__re
         blf[j] = 0xffffffffu;
 #pragma unroll
         for (int q = 0; q < SPL; ++q) {
-            const int x = li * SPL + q;
+            const int x = li + q * G;
             const int32_t kk = key[j][x];
             if (kk == kEmpty) continue;
             const uint32_t e = es[j][x];
@@ -1229,7 +1230,7 @@ template <typename W>
 static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s, SideStreams *side, Timer *t) {
     const char *wn = type_name<W>();
     const std::string sfx = t ? std::string(wn) + ">" : std::string();
-    const double eb = 8.0 + sizeof(W);   // column, weight, neighbour word
+    const double eb = 12.0 + sizeof(W);  // column (4), weight, neighbour word (8)
     const double vb = 40.0;
     auto bytes = [&](int b0, int b1) {
         double x = 0;
