@@ -257,7 +257,7 @@ typedef struct {
     int32_t small_max;   /* rows of at most this many entries are swept one thread per
                             vertex (1..8; default 4)                                     */
     int32_t block_max;   /* longest row swept from an LDS table; longer rows use HBM hub
-                            tables (341..2730; default 2730)                             */
+                            tables (341..10922; default 2730)                            */
     int32_t pass_batch;  /* sweep passes between host checks when the run's params say 0
                             (1..64; default 2)                                           */
     int32_t group_slots; /* LDS table slots scored per lane for rows of up to 341 entries
@@ -278,7 +278,7 @@ int louvain_get_tuning(louvain_ctx ctx, louvain_tuning *tuning);
 /*
  * Autotuner: times one whole run of the method on g (params as for
  * louvain_run) under the context's current setting and each candidate
- * (small_max in {4, 8}, block_max in {1024, 1365, 2730}, pass_batch in
+ * (small_max in {4, 8}, block_max in {1365, 2730, 10922}, pass_batch in
  * {1, 2}, group_vertices in {1, 2}; group_slots 4, overlap as set), best
  * of two runs each; a candidate replaces the current setting only when it
  * is more than 2% faster, so that timing noise does not flip the setting

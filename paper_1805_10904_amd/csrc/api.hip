@@ -567,7 +567,7 @@ int louvain_set_tuning(louvain_ctx ctx, const louvain_tuning *tuning) {
         if (tuning) {
             require(tuning->small_max >= 1 && tuning->small_max <= 8, LOUVAIN_EINVAL, "small_max must be in [1, 8]");
             require(tuning->block_max >= lv::kPackMaxDeg && tuning->block_max <= lv::kCompactBlockMax, LOUVAIN_EINVAL,
-                    "block_max must be in [341, 2730]");
+                    "block_max must be in [341, 10922]");
             require(tuning->pass_batch >= 1 && tuning->pass_batch <= 64, LOUVAIN_EINVAL,
                     "pass_batch must be in [1, 64]");
             require(tuning->group_slots == 0 || tuning->group_slots == 2 || tuning->group_slots == 4 ||
@@ -640,7 +640,7 @@ int louvain_autotune(louvain_ctx ctx, louvain_graph g, const louvain_params *par
         lv::Tuning pick = cur;
         double pick_ms = cur_ms;
         for (int sm : {4, 8})
-            for (int64_t bm : {(int64_t)1024, (int64_t)1365, lv::kCompactBlockMax})
+            for (int64_t bm : {(int64_t)1365, (int64_t)2730, lv::kCompactBlockMax})
                 for (int pb : {1, 2})
                     for (int gv : {1, 2}) {
                         lv::Tuning tn;

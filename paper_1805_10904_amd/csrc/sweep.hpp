@@ -54,17 +54,18 @@ constexpr int kPackMinCost = kPackW / 256;
 constexpr int64_t kPackMaxDeg = 341;
 // Compact levels sort the rows they sweep from LDS into table-size classes:
 // packed classes c < kGroupClasses with S = 16 << c slots (rows with
-// 3d <= 2S, up to 341 entries), then S = 2048 (up to 1,365 entries) and
-// S = 4096 (up to kCompactBlockMax entries), one vertex per workgroup.
+// 3d <= 2S, up to 341 entries), then S = 2048 (up to 1,365 entries),
+// S = 4096 (up to 2,730) and S = 16384 (up to kCompactBlockMax entries,
+// 1,024 threads), one vertex per workgroup.
 constexpr int kGroupClasses = 6;
-constexpr int kLdsClasses = kGroupClasses + 2;
-constexpr int64_t kCompactBlockMax = 2730;
+constexpr int kLdsClasses = kGroupClasses + 3;
+constexpr int64_t kCompactBlockMax = 10922;
 
 // Launch-shape settings of compact levels (chosen by the autotuner or the
 // caller; every setting gives the same results).
 struct Tuning {
     int small_max = 4;                  // rows of at most this many entries: one thread per vertex (1..8)
-    int64_t block_max = kCompactBlockMax;   // longest row swept from LDS; longer rows: HBM hub tables
+    int64_t block_max = 2730;           // longest row swept from LDS (<= kCompactBlockMax); longer: HBM hub tables
     int pass_batch = 2;                 // sweep passes between host checks
     int group_slots = 4;                // LDS slots per lane of the packed-class sweep (2, 4 or 8)
     int group_vertices = 1;             // vertices per lane group of the packed-class sweep (1 or 2)

@@ -38,12 +38,12 @@ __device__ __forceinline__ int32_t vw_label(uint64_t w) { return (int32_t)(uint3
 __device__ __forceinline__ uint32_t hi_deg(uint32_t hi) { return hi & 0x7fffffffu; }
 __device__ __forceinline__ bool hi_single(uint32_t hi) { return (hi >> 31) != 0; }
 
-// Row start and length of a class-list entry in one word: start << 12 |
-// length (rows swept from LDS have at most kCompactBlockMax < 4096 entries).
-__device__ __forceinline__ uint64_t row_info(int64_t rs, int64_t d) { return ((uint64_t)rs << 12) | (uint64_t)d; }
-__device__ __forceinline__ int64_t info_start(uint64_t x) { return (int64_t)(x >> 12); }
-__device__ __forceinline__ int64_t info_len(uint64_t x) { return (int64_t)(x & 4095u); }
-static_assert(kCompactBlockMax < 4096, "row lengths swept from LDS fit 12 bits");
+// Row start and length of a class-list entry in one word: start << 14 |
+// length (rows swept from LDS have at most kCompactBlockMax < 2^14 entries).
+__device__ __forceinline__ uint64_t row_info(int64_t rs, int64_t d) { return ((uint64_t)rs << 14) | (uint64_t)d; }
+__device__ __forceinline__ int64_t info_start(uint64_t x) { return (int64_t)(x >> 14); }
+__device__ __forceinline__ int64_t info_len(uint64_t x) { return (int64_t)(x & 16383u); }
+static_assert(kCompactBlockMax < 16384, "row lengths swept from LDS fit 14 bits");
 
 struct CArgs {
     const int64_t *row_ptr;
@@ -62,6 +62,13 @@ struct CArgs {
 };
 
 __device__ __forceinline__ int graph_of(const int32_t *gid, int64_t v) { return gid ? gid[v] : 0; }
+
+// A single graph whose phase has ended: the pass (one of a batch of passes
+// enqueued ahead of the host's check) has nothing to do.  Uniform over the
+// grid, so kernels return at once, before any barrier.
+__device__ __forceinline__ bool single_done(const int32_t *gid, const PhaseState *st) {
+    return gid == nullptr && st[0].done;
+}
 
 template <typename W>
 __device__ __forceinline__ uint32_t cw(const void *w, int64_t e) {
@@ -180,6 +187,7 @@ __global__ __launch_bounds__(256) void k_cpt_publish(const uint64_t *__restrict_
     __shared__ unsigned long long acc[kSpan][2];
     __shared__ int s_glo, s_span;
     if (active_zero && blockIdx.x == 0 && threadIdx.x == 0) *active_zero = 0;
+    if (single_done(gid, st)) return;
     const int64_t base = (int64_t)blockIdx.x * kPubTile;
     const int64_t last = base + kPubTile - 1 < n - 1 ? base + kPubTile - 1 : n - 1;
     const SpanSums sp = span_begin(gid, base, last, &s_glo, &s_span, acc);
@@ -240,6 +248,7 @@ __global__ __launch_bounds__(256) void k_cpt_commit(const int32_t *__restrict__ 
                                                     const int64_t *__restrict__ delta, const uint32_t *__restrict__ es,
                                                     uint64_t *ds, const int32_t *__restrict__ gid, PhaseState *st,
                                                     int64_t n) {
+    if (single_done(gid, st)) return;
     constexpr int T = 1 << kCommitBits;
     __shared__ unsigned long long acc[kSpan][2];
     __shared__ int s_glo, s_span;
@@ -365,6 +374,7 @@ __global__ void k_cpt_finalize(PhaseState *st, const int64_t *__restrict__ tw, i
 template <typename W>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_cpt_small(CArgs a, int64_t n,
                                                                                           int small_max) {
+    if (single_done(a.gid, a.st)) return;
     constexpr int MAXD = 8;
     const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (v >= n) return;
@@ -519,6 +529,7 @@ __device__ __forceinline__ void group_best(unsigned long long &bok, uint32_t &bl
 template <int S, int G, typename W>
 __global__ __launch_bounds__(256) void k_cpt_group(CArgs a, const int32_t *__restrict__ list,
                                                    const uint64_t *__restrict__ info, int64_t count) {
+    if (single_done(a.gid, a.st)) return;
     constexpr int NV = 256 / G;
     constexpr int SPL = S / G;
     constexpr int BITS = Log2<S>::value;
@@ -661,6 +672,7 @@ struct GroupBlocks {
 template <int SPL, int VPG, typename W>
 __global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__restrict__ list,
                                                     const uint64_t *__restrict__ info, GroupBlocks gb) {
+    if (single_done(a.gid, a.st)) return;
     static_assert(SPL == 2 || SPL == 4 || SPL == 8, "2, 4 or 8 slots per lane");
     static_assert(VPG == 1 || VPG == 2, "one or two vertices per lane group");
     constexpr int LB = SPL == 2 ? 1 : SPL == 4 ? 2 : 3;   // log2 SPL
@@ -857,12 +869,117 @@ __global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__re
 }
 
 // Table-size class of a row swept from LDS: the smallest packed class c
-// with 3d <= 2 * (16 << c), else 2048 slots, else 4096 slots.
+// with 3d <= 2 * (16 << c), else 2048, 4096 or 16384 slots.
 __device__ __forceinline__ int size_class(int64_t d) {
     int c = 0;
     while (c < kGroupClasses && 3 * d > 2 * ((int64_t)16 << c)) ++c;
     if (c < kGroupClasses) return c;
-    return 3 * d <= 2 * 2048 ? kGroupClasses : kGroupClasses + 1;
+    if (3 * d <= 2 * 2048) return kGroupClasses;
+    return 3 * d <= 2 * 4096 ? kGroupClasses + 1 : kGroupClasses + 2;
+}
+
+// Rows of up to kCompactBlockMax entries, one 1,024-thread workgroup each
+// with a table of S = 16384 slots (key and e_{i->C} only: 128 KB of LDS);
+// the degree and size of each candidate community come from its community
+// word at scoring time.  Otherwise as k_cpt_group.
+constexpr int kBigRowSlots = 16384;
+constexpr int kBigRowThreads = 1024;
+
+template <typename W>
+__global__ __launch_bounds__(kBigRowThreads) void k_cpt_bigrow(CArgs a, const int32_t *__restrict__ list,
+                                                               const uint64_t *__restrict__ info, int64_t count) {
+    if (single_done(a.gid, a.st)) return;
+    constexpr int S = kBigRowSlots, T = kBigRowThreads, SPL = S / T, NW = T / 64;
+    constexpr int BITS = Log2<S>::value;
+    __shared__ int32_t key[S];
+    __shared__ uint32_t es[S];
+    __shared__ unsigned long long r_ok[NW];
+    __shared__ uint32_t r_lf[NW];
+    __shared__ uint32_t s_eown, s_loop;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < SPL; ++q) {
+        key[t + q * T] = kEmpty;
+        es[t + q * T] = 0;
+    }
+    if (t == 0) {
+        s_eown = 0;
+        s_loop = 0;
+    }
+    const int64_t k = blockIdx.x;
+    const int32_t v = list[k];
+    const uint64_t ri = info[k];
+    const int g = graph_of(a.gid, v);
+    const bool live = !a.st[g].done;
+    const int64_t rs = info_start(ri), d = live ? info_len(ri) : 0;
+    const uint64_t own = a.vw[v];
+    const int32_t ci = vw_label(own);
+    const uint32_t own_hi = (uint32_t)(own >> 32);
+    // TW, delta_i, deg_C and e_{i->C} are below 2^31: 32-bit operands
+    const uint32_t di = (uint32_t)a.delta[v];
+    const uint32_t tw = (uint32_t)a.tw[g];
+    __syncthreads();
+    constexpr int U = 4;
+    for (int64_t x0 = t; x0 < d; x0 += (int64_t)U * T) {
+        int32_t jq[U];
+        uint32_t wq[U];
+        int32_t lq[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int64_t x = x0 + (int64_t)q * T;
+            jq[q] = -1;
+            wq[q] = 0;
+            if (x < d) {
+                jq[q] = a.col[rs + x];
+                wq[q] = cw<W>(a.w, rs + x);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) lq[q] = (jq[q] >= 0 && jq[q] != v) ? vw_label(a.vw[jq[q]]) : -1;
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            if (jq[q] == v) s_loop = wq[q];   // a row has at most one loop
+            if (lq[q] < 0) continue;
+            uint32_t h = ((uint32_t)lq[q] * 0x9E3779B1u) >> (32 - BITS);
+            while (true) {
+                const int32_t prev = atomicCAS(&key[h], kEmpty, lq[q]);   // claims, or returns the slot's key
+                if (prev == kEmpty || prev == lq[q]) break;
+                h = (h + 1) & (S - 1);
+            }
+            atomicAdd(&es[h], wq[q]);
+        }
+    }
+    __syncthreads();
+    unsigned long long bok = 0;
+    uint32_t blf = 0xffffffffu;
+#pragma unroll 4
+    for (int q = 0; q < SPL; ++q) {
+        const int x = t + q * T;
+        const int32_t kk = key[x];
+        if (kk == kEmpty) continue;
+        const uint32_t e = es[x];
+        if (kk == ci) {
+            s_eown = e;
+            continue;
+        }
+        const uint64_t dsk = a.ds[kk];
+        const unsigned long long ok = ((uint64_t)tw * e - (uint64_t)di * (uint32_t)dsk) ^ 0x8000000000000000ull;
+        const uint32_t lf = ((uint32_t)kk << 1) | ((dsk >> 32) == 1 ? 1u : 0u);
+        best_take(bok, blf, (uint32_t)ok, (uint32_t)(ok >> 32), lf);
+    }
+    group_best(bok, blf, 64);
+    const int wid = t >> 6;
+    if ((t & 63) == 0) {
+        r_ok[wid] = bok;
+        r_lf[wid] = blf;
+    }
+    __syncthreads();
+    if (t == 0 && live) {
+        for (int w2 = 1; w2 < NW; ++w2) best_take(bok, blf, (uint32_t)r_ok[w2], (uint32_t)(r_ok[w2] >> 32), r_lf[w2]);
+        a.c_nxt[v] = cpt_decide(a.singlet, (int64_t)tw, ci, own_hi, (int64_t)di, (int64_t)s_eown, bok != 0,
+                                (int64_t)(bok ^ 0x8000000000000000ull), (int32_t)(blf >> 1), (blf & 1u) != 0);
+        a.e_self[v] = s_eown + s_loop;
+    }
 }
 
 constexpr int kClassTile = 2048;
@@ -995,6 +1112,7 @@ __device__ __forceinline__ void word_insert_hbm(unsigned long long *tab, uint64_
 template <typename W>
 __global__ __launch_bounds__(256) void k_cpt_hub_accum(CArgs a, CHub hm, unsigned long long *gtab,
                                                        unsigned long long *hub_loop) {
+    if (single_done(a.gid, a.st)) return;
     constexpr int T = 1 << kCHubLdsBits;
     __shared__ unsigned long long s_tab[T];
     __shared__ int64_t s_h;
@@ -1051,6 +1169,7 @@ __global__ __launch_bounds__(256) void k_cpt_hub_accum(CArgs a, CHub hm, unsigne
 // singleton flag) and own e; clears the slots for the next pass.  The
 // community's degree and size come from its community word.
 __global__ __launch_bounds__(256) void k_cpt_hub_scan(CArgs a, CHub hm, unsigned long long *gtab, uint64_t *part) {
+    if (single_done(a.gid, a.st)) return;
     __shared__ int64_t s_h;
     __shared__ unsigned long long r_ok[4];
     __shared__ uint32_t r_lf[4], r_e[4];
@@ -1111,6 +1230,7 @@ __global__ __launch_bounds__(256) void k_cpt_hub_scan(CArgs a, CHub hm, unsigned
 // Wavefront per hub: combine the scan partials and decide.
 __global__ __launch_bounds__(256) void k_cpt_hub_decide(CArgs a, CHub hm, const uint64_t *part,
                                                         unsigned long long *hub_loop) {
+    if (single_done(a.gid, a.st)) return;
     const int lane = threadIdx.x & 63;
     const int64_t h = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (h >= hm.hubs) return;
@@ -1237,7 +1357,7 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
         for (int b = b0; b < b1; ++b) x += (double)(cp.bstart[b + 1] - cp.bstart[b]) * vb + (double)cp.bnnz[b] * eb;
         return x;
     };
-    const bool fork = side && (cp.hubs > 0 || cp.cstart[kGroupClasses + 2] > cp.cstart[kGroupClasses]);
+    const bool fork = side && (cp.hubs > 0 || cp.cstart[kLdsClasses] > cp.cstart[kGroupClasses]);
     hipStream_t s1 = s, s2 = s;
     if (fork) {
         side->fork(s);
@@ -1298,6 +1418,13 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
             tl.launch(k_cpt_group<4096, 256, W>, (unsigned)nx, 256, 0, s1, a, cp.glist + cp.cstart[c + 1],
                       cp.ginfo + cp.cstart[c + 1], nx);
             LV_LAUNCHED("k_cpt_group<4096>");
+        }
+        const int64_t ny = cp.cstart[c + 3] - cp.cstart[c + 2];
+        if (ny > 0) {
+            TimedLaunch tl(t, TG_SWEEP, "k_cpt_bigrow<", (double)ny * vb + (double)cp.cnnz[c + 2] * eb, sfx.c_str());
+            tl.launch(k_cpt_bigrow<W>, (unsigned)ny, kBigRowThreads, 0, s1, a, cp.glist + cp.cstart[c + 2],
+                      cp.ginfo + cp.cstart[c + 2], ny);
+            LV_LAUNCHED("k_cpt_bigrow");
         }
     }
     if (cp.hubs > 0) {

@@ -46,12 +46,14 @@ def small_graphs():
     return gs
 
 
-def hub_graph(seed=7, leaves=5000, extra=20000, n=8000):
-    """A star with thousands of leaves (row beyond the workgroup bucket) plus
-    random edges, so every bucket including the HBM hub path is used."""
+def hub_graph(seed=7, leaves=15000, mid=5000, extra=20000, n=20000):
+    """Two stars plus random edges: vertex 0 with 15,000 leaves (a row past
+    every LDS kernel: the HBM hub path) and vertex 1 with 5,000 (the
+    1,024-thread LDS kernel), so that every row kernel is used."""
     rng = np.random.default_rng(seed)
-    u = np.concatenate([np.zeros(leaves, np.int64), rng.integers(0, n, extra)])
-    v = np.concatenate([np.arange(1, leaves + 1), rng.integers(0, n, extra)])
+    u = np.concatenate([np.zeros(leaves, np.int64), np.ones(mid, np.int64), rng.integers(0, n, extra)])
+    v = np.concatenate([np.arange(2, leaves + 2), rng.choice(np.arange(2, n), mid, replace=False),
+                        rng.integers(0, n, extra)])
     keys = gg.canonical_keys(u, v)
     rp, col, w = gg.csr_from_canonical_keys(n, keys, seed, lambda h: gg.weights_uniform(h, 20))
     return gg.Graph(n, rp, col, w, None, "hub")
@@ -286,7 +288,7 @@ def test_launch_shapes_do_not_change_results(ctx):
     Gs = [ctx.graph_create(g.row_ptr, g.col, g.w) for g in graphs]
     try:
         for shp in [(1, 341, 1, 4, 1, 0), (4, 1024, 2, 8, 2, 1), (8, 1365, 1, 2, 2, 0), (2, 2730, 3, 4, 1, 1),
-                    (4, 2730, 2, 8, 1, 0), (3, 700, 1, 2, 1, 1), (4, 2730, 2, 4, 2, 1)]:
+                    (4, 10922, 2, 8, 1, 0), (3, 700, 1, 2, 1, 1), (4, 5000, 2, 4, 2, 1), (4, 10922, 2, 4, 1, 1)]:
             ctx.set_tuning(*shp)
             keys = ("small_max", "block_max", "pass_batch", "group_slots", "group_vertices", "overlap")
             assert ctx.get_tuning() == dict(zip(keys, shp))
@@ -308,7 +310,7 @@ def test_autotune(ctx, L):
     G = ctx.graph_create(g.row_ptr, g.col, g.w)
     try:
         best = ctx.autotune(G)
-        assert best["small_max"] in (4, 8) and best["block_max"] in (1024, 1365, 2730)
+        assert best["small_max"] in (4, 8) and best["block_max"] in (1365, 2730, 10922)
         assert best["pass_batch"] in (1, 2) and best["group_slots"] == 4 and best["ms"] > 0
         assert best["group_vertices"] in (1, 2) and best["overlap"] == 0
         assert ctx.get_tuning() == {k: best[k] for k in ("small_max", "block_max", "pass_batch", "group_slots",
