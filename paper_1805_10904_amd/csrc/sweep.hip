@@ -35,6 +35,7 @@ struct SweepArgs {
     int singlet;
     PhaseState *st;
     int64_t *e_self;   // optional per-vertex e_{i->c_i} incl. loop
+    int hub_shift;     // > 0: hub tables hold one word (label + 1) << hub_shift | e per slot
 };
 
 template <typename W>
@@ -71,6 +72,34 @@ __device__ __forceinline__ void hbm_insert(int32_t *key, unsigned long long *val
             return;
         }
         h = (h + 1 == (uint64_t)size) ? 0 : h + 1;
+    }
+}
+
+// Insert or add x for a label into an HBM hub table of one word per slot,
+// (label + 1) << shift | e, 0 = empty: used when every label + 1 fits the
+// 64 - shift high bits and every e (at most 2W) the low shift bits, so the
+// add never carries into the label.  One atomic per insert instead of a key
+// compare-and-swap plus a value add.
+__device__ __forceinline__ void packed_insert(unsigned long long *tab, uint64_t size, int32_t label,
+                                              unsigned long long x, int shift) {
+    const unsigned long long tag = (unsigned long long)(uint32_t)(label + 1) << shift;
+    const unsigned long long tmask = ~0ull << shift;
+    uint64_t h = hash_range(label, size);
+    while (true) {
+        const unsigned long long cur = ((volatile unsigned long long *)tab)[h];
+        if ((cur & tmask) == tag) {
+            atomicAdd(&tab[h], x);
+            return;
+        }
+        if (cur == 0) {
+            const unsigned long long prev = atomicCAS(&tab[h], 0ull, tag | x);
+            if (prev == 0) return;
+            if ((prev & tmask) == tag) {
+                atomicAdd(&tab[h], x);
+                return;
+            }
+        }
+        h = (h + 1 == size) ? 0 : h + 1;
     }
 }
 
@@ -602,7 +631,11 @@ __global__ __launch_bounds__(256) void k_hub_accum(SweepArgs a, HubMeta hm, int3
     const int64_t base = hm.tab_off[h], size = hm.tab_size[h];
     for (int x = t; x < T; x += 256) {
         const int32_t key = s_key[x];
-        if (key != kEmpty) hbm_insert(gkey + base, gval + base, size, key, s_val[x]);
+        if (key == kEmpty) continue;
+        if (a.hub_shift)
+            packed_insert(gval + base, (uint64_t)size, key, s_val[x], a.hub_shift);
+        else
+            hbm_insert(gkey + base, gval + base, size, key, s_val[x]);
     }
 }
 
@@ -624,14 +657,25 @@ __global__ __launch_bounds__(256) void k_hub_scan(SweepArgs a, HubMeta hm, int32
     S bs = 0;
     int32_t bl = -1;
     int64_t e_own = 0, unused = 0;
+    const int shift = a.hub_shift;
 #pragma unroll
     for (int q = 0; q < kHubScan / 256; ++q) {
         const int64_t x = base + q * 256 + t;
-        const int32_t k = gkey[x];
-        if (k == kEmpty) continue;
-        const int64_t ev = (int64_t)gval[x];
-        gkey[x] = kEmpty;
-        gval[x] = 0;
+        int32_t k;
+        int64_t ev;
+        if (shift) {
+            const unsigned long long wd = gval[x];
+            if (wd == 0) continue;
+            gval[x] = 0;
+            k = (int32_t)(wd >> shift) - 1;
+            ev = (int64_t)(wd & ~(~0ull << shift));
+        } else {
+            k = gkey[x];
+            if (k == kEmpty) continue;
+            ev = (int64_t)gval[x];
+            gkey[x] = kEmpty;
+            gval[x] = 0;
+        }
         if (k == ci) {
             e_own += ev;
             continue;
@@ -1279,8 +1323,13 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
         tl.launch(k_qsum, (unsigned)qblocks_, 256, 0, s_, deg_.p, g.n, qpart_.p, st_.p);
         LV_LAUNCHED("k_qsum");
     }
+    // hub tables as single words when label + 1 (< 2^tag_bits) and e (<= 2W)
+    // fit 64 bits together
+    int tag_bits = 1;
+    while (tag_bits < 32 && ((int64_t)1 << tag_bits) <= g.n) ++tag_bits;
+    const int hub_shift = (64 - tag_bits < 63 && (uint64_t)g.tw < (1ull << (64 - tag_bits))) ? 64 - tag_bits : 0;
     SweepArgs a{g.row_ptr, g.col, g.w, c_[cur].p, c_[nxt].p, g.delta, deg_.p, size_.p,
-                g.tw, prm.singlet, st_.p, e_self_out};
+                g.tw, prm.singlet, st_.p, e_self_out, hub_shift};
     int64_t *tab_off = hub_meta_.p;
     HubMeta hm{list_.p + bstart_[B_HUB], tab_off, tab_off + (hubs_ + 1), tab_off + 2 * (hubs_ + 1),
                tab_off + 3 * (hubs_ + 1), hub_of_chunk_.p, hub_of_scan_.p, hubs_};

@@ -224,6 +224,25 @@ def test_int64_weights(ctx):
     G.destroy()
 
 
+@pytest.mark.parametrize("scale", [1 << 26, 1 << 36])
+def test_heavy_hubs(ctx, scale):
+    """Hubs on the kernels for 2W >= 2^31: with weights near 2^30 the hub
+    tables hold one word per slot (label and e fit 64 bits together); with
+    weights near 2^40 (int64) they fall back to separate key and value
+    arrays."""
+    g = hub_graph(seed=11)
+    w = g.w.astype(np.int64) * scale
+    _say(f"hub graph with weights x {scale}")
+    G = ctx.graph_create(g.row_ptr, g.col, w)
+    r = ctx.run(G)
+    ref = oracle.louvain(g.row_ptr, g.col, w)
+    assert np.array_equal(r.labels, ref.labels) and r.q_int == ref.q_int
+    lm = ctx.local_move(G, None)
+    ref_lm = oracle.local_move(g.row_ptr, g.col, w, None)
+    assert np.array_equal(lm[0], ref_lm.labels) and np.array_equal(lm[2], ref_lm.e_own)
+    G.destroy()
+
+
 # -------------------------------------------------------------- edge cases --
 
 def test_degenerate_graphs(ctx, L):
