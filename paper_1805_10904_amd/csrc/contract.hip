@@ -439,11 +439,25 @@ __device__ __forceinline__ void chunk_aggregate(const int64_t *__restrict__ off,
     }
     __syncthreads();
     const int64_t slo = s_range[0], shi = s_range[1];
-    // segment of every entry: markers at segment starts, then a max-scan
-    for (int64_t sg = slo + 1 + t; sg <= shi; sg += 256) atomicMax(&s_mark[off[sg] - cb], (int32_t)(sg - slo));
-    if (t == 0) s_mark[0] = 0;   // markers never land on position 0
-    __syncthreads();
-    block_max_scan_chunk(s_mark, s_wave);
+    if (shi - slo <= kChunkMax) {
+        // segment of every entry: markers at segment starts, then a max-scan
+        for (int64_t sg = slo + 1 + t; sg <= shi; sg += 256) atomicMax(&s_mark[off[sg] - cb], (int32_t)(sg - slo));
+        if (t == 0) s_mark[0] = 0;   // markers never land on position 0
+        __syncthreads();
+        block_max_scan_chunk(s_mark, s_wave);
+    } else {
+        // the chunk spans many empty segments (communities without entries):
+        // the last segment starting at or before each entry, by binary search
+        for (int x = t; x < len; x += 256) {
+            int64_t lo = slo, hi = shi;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if (off[mid] <= cb + x) lo = mid; else hi = mid - 1;
+            }
+            s_mark[x] = (int32_t)(lo - slo);
+        }
+        __syncthreads();
+    }
     // with skip_big, entries of segments longer than kChunkMax (only the
     // chunk's first and last segment can be) are left to k_big_piece
     const int32_t last_local = (int32_t)(shi - slo);
@@ -590,8 +604,8 @@ __global__ __launch_bounds__(kPieceThreads) void k_big_piece(const int64_t *__re
     __shared__ int32_t s_k[T];
     __shared__ long long s_v[T];
     __shared__ int64_t s_seg, s_idx;
-    __shared__ int s_n, s_over;
-    __shared__ unsigned long long s_base;
+    __shared__ int s_n, s_over, s_used;
+    __shared__ unsigned long long s_base, s_obase;
     const int t = threadIdx.x;
     for (int x = t; x < T; x += kPieceThreads) {
         s_k[x] = kEmpty;
@@ -604,34 +618,64 @@ __global__ __launch_bounds__(kPieceThreads) void k_big_piece(const int64_t *__re
             s_idx = (int64_t)blockIdx.x - poff[a];
             s_n = 0;
             s_over = 0;
+            s_used = 0;
         }
     }
     __syncthreads();
     const int64_t a = s_seg;
     const int64_t lo = off[a] + s_idx * kPiece;
     const int64_t end = off[a + 1] < lo + kPiece ? off[a + 1] : lo + kPiece;
-    for (int64_t e = lo + t; e < end; e += kPieceThreads) {
+    // New columns claim slots only while the table is at most 3/4 full, so
+    // probes stay short; a column that finds neither its slot nor room is
+    // an overflow pair (marked here, written after one reservation).
+    constexpr int kClaimMax = 3 * T / 4;
+    uint32_t over = 0;   // entry q of this thread overflowed
+    int n_over = 0;
+    static_assert(kPiece / kPieceThreads <= 32, "one mask bit per entry of a thread");
+    for (int q = 0; lo + t + (int64_t)q * kPieceThreads < end; ++q) {
+        const int64_t e = lo + t + (int64_t)q * kPieceThreads;
         const int32_t c = tcol[e];
         const int64_t w = tw[e];
         uint32_t h = ((uint32_t)c * 0x9E3779B1u) >> (32 - kPieceBits);
         bool placed = false;
         for (int p = 0; p < kPieceProbe; ++p) {
-            const int32_t prev = atomicCAS(&s_k[h], kEmpty, c);   // claims, or returns the slot's column
-            if (prev == kEmpty || prev == c) {
-                atomicAdd((unsigned long long *)&s_v[h], (unsigned long long)w);
+            const int32_t cur = s_k[h];
+            if (cur == c) {
                 placed = true;
                 break;
             }
+            if (cur == kEmpty) {
+                if (s_used >= kClaimMax) break;
+                const int32_t prev = atomicCAS(&s_k[h], kEmpty, c);
+                if (prev == kEmpty) atomicAdd(&s_used, 1);
+                if (prev == kEmpty || prev == c) {
+                    placed = true;
+                    break;
+                }
+            }
             h = (h + 1) & (T - 1);
         }
-        if (!placed) {
-            s_over = 1;
-            const unsigned long long q = atomicAdd(pcount, 1ull);
-            pkey[q] = ((uint64_t)a << bits) | (uint32_t)c;
-            pval[q] = w;
+        if (placed) {
+            atomicAdd((unsigned long long *)&s_v[h], (unsigned long long)w);
+        } else {
+            over |= 1u << q;
+            ++n_over;
         }
     }
+    const int my_over = n_over ? atomicAdd(&s_over, n_over) : 0;
     __syncthreads();
+    if (t == 0 && s_over) s_obase = atomicAdd(pcount, (unsigned long long)s_over);
+    __syncthreads();
+    if (n_over) {
+        unsigned long long qpos = s_obase + (unsigned long long)my_over;
+        for (int q = 0; over; ++q, over >>= 1) {
+            if (!(over & 1u)) continue;
+            const int64_t e = lo + t + (int64_t)q * kPieceThreads;
+            pkey[qpos] = ((uint64_t)a << bits) | (uint32_t)tcol[e];
+            pval[qpos] = tw[e];
+            ++qpos;
+        }
+    }
     int pos[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {

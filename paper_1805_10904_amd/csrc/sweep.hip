@@ -200,14 +200,29 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a, const int32_t 
         ci = a.c_cur[i];
     }
     int64_t loop = 0;
-    for (int64_t e = rs + lane; e < re; e += G) {
-        const int32_t j = a.col[e];
-        const int64_t w = wload<W>(a.w, e);
-        if (j == i) {
-            loop += w;
-            continue;
+    // entries in rounds of U per lane: a round's loads and label gathers are
+    // all issued before its inserts
+    constexpr int U = 4;
+    for (int64_t e0 = rs + lane; e0 < re; e0 += (int64_t)U * G) {
+        int32_t jq[U], lq[U];
+        int64_t wq[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int64_t e = e0 + (int64_t)q * G;
+            jq[q] = -1;
+            wq[q] = 0;
+            if (e < re) {
+                jq[q] = a.col[e];
+                wq[q] = wload<W>(a.w, e);
+            }
         }
-        lds_insert<BITS>(key, val, a.c_cur[j], w);
+#pragma unroll
+        for (int q = 0; q < U; ++q) lq[q] = (jq[q] >= 0 && jq[q] != i) ? a.c_cur[jq[q]] : -1;
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            if (jq[q] == i) loop += wq[q];
+            if (lq[q] >= 0) lds_insert<BITS>(key, val, lq[q], wq[q]);
+        }
     }
     __syncthreads();
     S bs = 0;
@@ -618,15 +633,30 @@ __global__ __launch_bounds__(256) void k_hub_accum(SweepArgs a, HubMeta hm, int3
     const int64_t row_end = a.row_ptr[v + 1];
     const int64_t rs = a.row_ptr[v] + k * kHubChunk;
     const int64_t re = rs + kHubChunk < row_end ? rs + kHubChunk : row_end;
-    for (int64_t e = rs + t; e < re; e += 256) {
-        const int32_t j = a.col[e];
-        const int64_t w = wload<W>(a.w, e);
-        if (j == v) {
-            atomicAdd(&hub_loop[h], (unsigned long long)w);
-            continue;
+    // kHubChunk / 256 entries per lane: loads and label gathers first, then inserts
+    constexpr int U = kHubChunk / 256;
+    static_assert(kHubChunk % 256 == 0, "a chunk is whole rounds of the workgroup");
+    int32_t jq[U], lq[U];
+    int64_t wq[U];
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+        const int64_t e = rs + t + q * 256;
+        jq[q] = -1;
+        wq[q] = 0;
+        if (e < re) {
+            jq[q] = a.col[e];
+            wq[q] = wload<W>(a.w, e);
         }
-        lds_insert<kHubLdsBits>(s_key, s_val, a.c_cur[j], w);
     }
+#pragma unroll
+    for (int q = 0; q < U; ++q) lq[q] = (jq[q] >= 0 && jq[q] != v) ? a.c_cur[jq[q]] : -1;
+    int64_t loop = 0;
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+        if (jq[q] == v) loop += wq[q];
+        if (lq[q] >= 0) lds_insert<kHubLdsBits>(s_key, s_val, lq[q], wq[q]);
+    }
+    if (loop) atomicAdd(&hub_loop[h], (unsigned long long)loop);
     __syncthreads();
     const int64_t base = hm.tab_off[h], size = hm.tab_size[h];
     for (int x = t; x < T; x += 256) {
