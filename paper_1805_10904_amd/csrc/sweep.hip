@@ -103,6 +103,17 @@ __device__ __forceinline__ void packed_insert(unsigned long long *tab, uint64_t 
     }
 }
 
+// Low bits of a single-word table slot, (label + 1) << shift | e, for a
+// level of n vertices and total weight tw: label + 1 <= n needs the high
+// 64 - shift bits and every e (at most tw) the low ones; 0 if they do not
+// fit together.
+static int word_shift(int64_t n, int64_t tw) {
+    int tag_bits = 1;
+    while (tag_bits < 32 && ((int64_t)1 << tag_bits) <= n) ++tag_bits;
+    const int shift = 64 - tag_bits;
+    return (shift < 63 && (uint64_t)tw < (1ull << shift)) ? shift : 0;
+}
+
 // ------------------------------------------------------------- decisions --
 
 // New community of vertex i given its best candidate (bs, bl) and
@@ -923,15 +934,15 @@ __global__ void k_init_labels(int32_t *c0, int32_t *c1, int32_t *c2, const int32
 constexpr int kBucketTile = 2048;  // vertices per bucketing block (256 x 8)
 
 // small_max: the longest row of the thread-per-vertex bucket; block_max: the
-// longest row of the workgroup-per-vertex bucket (the hub path takes longer
-// ones).
+// longest row swept from an LDS table (the hub path takes longer ones).
 __device__ __forceinline__ int bucket_of(int64_t d, int small_max, int64_t block_max) {
     if (d <= 0) return -1;
     if (d <= small_max) return B_T8;
+    if (d > block_max) return B_HUB;
 #pragma unroll
-    for (int b = B_T16; b < B_BLOCK; ++b)
+    for (int b = B_T16; b < B_WIDE; ++b)
         if (d <= kBucketMax[b]) return b;
-    return d <= block_max ? B_BLOCK : B_HUB;
+    return B_WIDE;
 }
 
 // Bucket of vertex v, or -1 if it is not evaluated (empty row, or its graph's
@@ -1077,7 +1088,10 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     n_ = g.n;
     compact_ = batch_ || g.tw < kCompactTwMax;   // before anything that depends on the level's kind
     const int small_max = compact_ ? tuning_.small_max : (int)kBucketMax[B_T8];
-    const int64_t block_max = compact_ ? tuning_.block_max : kBucketMax[B_BLOCK];
+    // general levels: rows up to kBucketMax[B_WIDE] go to LDS when the wide
+    // kernel's single-word table can hold their labels and weights
+    const int64_t block_max = compact_ ? tuning_.block_max
+                                       : (word_shift(g.n, g.tw) ? kBucketMax[B_WIDE] : kBucketMax[B_BLOCK]);
     const int32_t *skip_gid = active_only && batch_ ? gid_ : nullptr;
     const PhaseState *skip_st = active_only && batch_ ? st_.p : nullptr;
     if (!batch_) {
@@ -1209,6 +1223,108 @@ void Sweeper::init_from_labels(const GraphView &g, const int32_t *labels) {
     LV_HIP(hipMemsetAsync(st_.p, 0, sizeof(PhaseState), s_));
 }
 
+// Rows of up to kBucketMax[B_WIDE] entries on general levels: one
+// 1,024-thread workgroup per vertex with an LDS table of 16,384 single-word
+// slots, (label + 1) << shift | e (only launched when labels and weights fit
+// 64 bits together), otherwise as k_sweep_group.
+constexpr int kWideThreads = 1024;
+constexpr int kWideBits = 14;
+
+template <typename W, typename S>
+__global__ __launch_bounds__(kWideThreads) void k_sweep_wide(SweepArgs a, const int32_t *__restrict__ list) {
+    constexpr int T = kWideThreads, SL = 1 << kWideBits, SPL = SL / T, NW = T / 64;
+    __shared__ unsigned long long tab[SL];
+    __shared__ S r_s[NW];
+    __shared__ int32_t r_l[NW];
+    __shared__ int64_t s_eown, s_loop;
+    if (a.st->done) return;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < SPL; ++q) tab[t + q * T] = 0;
+    if (t == 0) {
+        s_eown = 0;
+        s_loop = 0;
+    }
+    const int32_t i = list[blockIdx.x];
+    const int64_t rs = a.row_ptr[i], re = a.row_ptr[i + 1];
+    const int32_t ci = a.c_cur[i];
+    const int shift = a.hub_shift;
+    const unsigned long long tmask = ~0ull << shift;
+    __syncthreads();
+    constexpr int U = 4;
+    for (int64_t e0 = rs + t; e0 < re; e0 += (int64_t)U * T) {
+        int32_t jq[U], lq[U];
+        int64_t wq[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int64_t e = e0 + (int64_t)q * T;
+            jq[q] = -1;
+            wq[q] = 0;
+            if (e < re) {
+                jq[q] = a.col[e];
+                wq[q] = wload<W>(a.w, e);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) lq[q] = (jq[q] >= 0 && jq[q] != i) ? a.c_cur[jq[q]] : -1;
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            if (jq[q] == i) s_loop = wq[q];   // a row has at most one loop
+            if (lq[q] < 0) continue;
+            const unsigned long long tag = (unsigned long long)(uint32_t)(lq[q] + 1) << shift;
+            uint32_t h = ((uint32_t)lq[q] * 0x9E3779B1u) >> (32 - kWideBits);
+            while (true) {
+                const unsigned long long prev = atomicCAS(&tab[h], 0ull, tag | (unsigned long long)wq[q]);
+                if (prev == 0) break;
+                if ((prev & tmask) == tag) {
+                    atomicAdd(&tab[h], (unsigned long long)wq[q]);
+                    break;
+                }
+                h = (h + 1) & (SL - 1);
+            }
+        }
+    }
+    __syncthreads();
+    const int64_t di = a.delta[i];
+    S bs = 0;
+    int32_t bl = -1;
+#pragma unroll 4
+    for (int q = 0; q < SPL; ++q) {
+        const unsigned long long wd = tab[t + q * T];
+        if (wd == 0) continue;
+        const int32_t k = (int32_t)(wd >> shift) - 1;
+        const int64_t ev = (int64_t)(wd & ~tmask);
+        if (k == ci) {
+            s_eown = ev;
+            continue;
+        }
+        const S sc = score_mul<S>(a.tw, ev) - score_mul<S>(di, a.deg[k]);
+        if (better<S>(sc, k, bs, bl)) {
+            bs = sc;
+            bl = k;
+        }
+    }
+    int64_t u0 = 0, u1 = 0;
+    group_reduce_wave<64, S>(bs, bl, u0, u1);
+    const int wid = t >> 6;
+    if ((t & 63) == 0) {
+        r_s[wid] = bs;
+        r_l[wid] = bl;
+    }
+    __syncthreads();
+    if (t == 0) {
+        for (int w2 = 1; w2 < NW; ++w2)
+            if (better<S>(r_s[w2], r_l[w2], bs, bl)) {
+                bs = r_s[w2];
+                bl = r_l[w2];
+            }
+        a.c_nxt[i] = decide<S>(a, i, ci, bs, bl, s_eown);
+        const int64_t self = s_eown + s_loop;
+        if (a.e_self) a.e_self[i] = self;
+        if (self) atomicAdd(&a.st->acc_I, (unsigned long long)self);
+    }
+}
+
 template <typename W, typename S>
 static void launch_pass(const SweepArgs &a, const int32_t *list, const int64_t *bstart,
                         const int64_t *bnnz, const int64_t *pack_pos, const int64_t *pack_first,
@@ -1258,12 +1374,17 @@ static void launch_pass(const SweepArgs &a, const int32_t *list, const int64_t *
                       cnt(B_G64));
             LV_LAUNCHED("k_sweep_group<64>");
         }
-        const int64_t nb = bstart[B_HUB] - bstart[B_MID];
+        const int64_t nb = bstart[B_WIDE] - bstart[B_MID];
         if (nb > 0) {
             TimedLaunch tl(t, TG_SWEEP, "k_sweep_group<256,11,", bytes(B_MID) + bytes(B_BLOCK), sfx.c_str());
             tl.launch(k_sweep_group<256, 11, W, S>, (unsigned)nb, 256, 0, s, a, list + bstart[B_MID], nb);
             LV_LAUNCHED("k_sweep_group<256>");
         }
+    }
+    if (cnt(B_WIDE) > 0) {   // only bucketed when a.hub_shift > 0
+        TimedLaunch tl(t, TG_SWEEP, "k_sweep_wide<", bytes(B_WIDE), sfx.c_str());
+        tl.launch(k_sweep_wide<W, S>, (unsigned)cnt(B_WIDE), kWideThreads, 0, s, a, list + bstart[B_WIDE]);
+        LV_LAUNCHED("k_sweep_wide");
     }
     if (hm.hubs > 0) {
         {
@@ -1353,11 +1474,9 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
         tl.launch(k_qsum, (unsigned)qblocks_, 256, 0, s_, deg_.p, g.n, qpart_.p, st_.p);
         LV_LAUNCHED("k_qsum");
     }
-    // hub tables as single words when label + 1 (< 2^tag_bits) and e (<= 2W)
+    // hub and wide-row tables as single words when label + 1 and e (<= 2W)
     // fit 64 bits together
-    int tag_bits = 1;
-    while (tag_bits < 32 && ((int64_t)1 << tag_bits) <= g.n) ++tag_bits;
-    const int hub_shift = (64 - tag_bits < 63 && (uint64_t)g.tw < (1ull << (64 - tag_bits))) ? 64 - tag_bits : 0;
+    const int hub_shift = word_shift(g.n, g.tw);
     SweepArgs a{g.row_ptr, g.col, g.w, c_[cur].p, c_[nxt].p, g.delta, deg_.p, size_.p,
                 g.tw, prm.singlet, st_.p, e_self_out, hub_shift};
     int64_t *tab_off = hub_meta_.p;

@@ -38,10 +38,13 @@ struct PhaseState {
 
 // Degree buckets: row length d (entries incl. a loop) -> sweep kernel.
 // Row-length buckets.  64-bit scores: <= 8 one thread per vertex, <= 341
-// packed workgroups, <= 1024 one workgroup per vertex, larger rows the HBM
-// hub path.  128-bit scores: lane groups of 4, 16, 64 and a workgroup.
-enum { B_T8 = 0, B_T16, B_G64, B_MID, B_BLOCK, B_HUB, NBUCKET };
-constexpr int64_t kBucketMax[NBUCKET - 1] = {8, 16, 128, 341, 1024};
+// packed workgroups, <= 1024 one workgroup per vertex, <= 10,922 one
+// 1,024-thread workgroup on a table of single words (when labels and e fit
+// 64 bits together), larger rows the HBM hub path.  128-bit scores: lane
+// groups of 4, 16, 64, a workgroup and the same wide kernel.  Compact levels
+// sweep every bucket from B_T16 to B_WIDE by their own table-size classes.
+enum { B_T8 = 0, B_T16, B_G64, B_MID, B_BLOCK, B_WIDE, B_HUB, NBUCKET };
+constexpr int64_t kBucketMax[NBUCKET - 1] = {8, 16, 128, 341, 1024, 10922};
 
 // Packed sweep: one workgroup evaluates up to 64 vertices of row length
 // <= kPackMaxDeg (tables of at most 512 slots, see pack_table_bits).
