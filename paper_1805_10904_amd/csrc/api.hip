@@ -312,7 +312,8 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
                 nb.col.alloc((size_t)nnz0);
             }
             void *wout = narrow ? (void *)nb.w32.p : (void *)nb.w64.p;
-            const int64_t m2 = ct.contract(v, newlab.p, k, nb.rp.p, nb.col.p, wout, narrow ? 4 : 8, nb.delta.p);
+            const int64_t m2 = ct.contract(v, newlab.p, k, nb.rp.p, nb.col.p, wout, narrow ? 4 : 8, nb.delta.p, false,
+                                           lv::lds_row_max(k, g0.tw, tn));
             lv::GraphView v2;
             v2.n = k;
             v2.nnz = m2;

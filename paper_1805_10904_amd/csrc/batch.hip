@@ -384,7 +384,7 @@ std::vector<BatchMember *> BatchEngine::step() {
         UBuf &D = ub_[1 - cur_];
         ensure(D, k, M, 0, 0);
         // every member has 2W < 2^31, so every contracted weight fits int32
-        const int64_t m2 = ct_.contract(v, newlab_.p, k, D.rp.p, D.col.p, D.w32.p, 4, D.delta.p);
+        const int64_t m2 = ct_.contract(v, newlab_.p, k, D.rp.p, D.col.p, D.w32.p, 4, D.delta.p, false, block_max_);
         std::vector<int64_t> hno((size_t)ns + 1), hrp((size_t)ns + 1);
         TempBuf rpb((size_t)(ns + 1) * sizeof(int64_t), s_);
         k_rp_at<<<grid_for(ns + 1, 256), 256, 0, s_>>>(D.rp.p, newoff_.p, ns, rpb.as<int64_t>());

@@ -50,7 +50,10 @@ class BatchEngine {
     // has drained; step() synchronises it before returning).
     std::vector<BatchMember *> step();
     bool idle() const { return slots_.empty() && pending_.empty() && finished_.empty(); }
-    void set_tuning(const Tuning &tn) { sw_.set_tuning(tn); }
+    void set_tuning(const Tuning &tn) {
+        sw_.set_tuning(tn);
+        block_max_ = tn.block_max;
+    }
     size_t resident() const { return slots_.size(); }
     size_t pending() const { return pending_.size(); }
     // Vertices and entries of the union the next step sweeps.
@@ -58,6 +61,7 @@ class BatchEngine {
     int64_t union_entries() const;
 
   private:
+    int64_t block_max_ = Tuning().block_max;   // longest row swept from LDS (members are compact)
     struct UBuf {
         DevBuf<int64_t> rp, delta;
         DevBuf<int32_t> col, w32;

@@ -573,18 +573,17 @@ __global__ __launch_bounds__(256) void k_seg_chunk_any(const int64_t *__restrict
 // Segments longer than kChunkMax entries (the communities with the most
 // member entries) are cut into pieces of kPiece entries, one 1,024-thread
 // workgroup each with a 2^13-slot LDS table keyed by column.  A segment of
-// one piece whose columns all found a slot and that has at most
-// kPieceDirectMax distinct columns writes its pairs in place (table order)
-// and its count.  Otherwise the piece's pairs (and any pair that found no
-// slot within kPieceProbe probes) join the partial pairs that are sorted and
-// merged, like those of segments crossing a chunk boundary: the longer rows
-// are swept through HBM hub tables at the next level, whose LDS
+// one piece whose columns all found a slot and that has at most direct_max
+// distinct columns (the next level's longest row swept from LDS) writes its
+// pairs in place (table order) and its count.  Otherwise the piece's pairs
+// (and any pair that found no slot) join the partial pairs that are sorted
+// and merged, like those of segments crossing a chunk boundary: the longer
+// rows are swept through HBM hub tables at the next level, whose LDS
 // pre-aggregation gains from ascending columns.
 constexpr int kPiece = 16384;
 constexpr int kPieceBits = 13;
 constexpr int kPieceProbe = 32;
 constexpr int kPieceThreads = 1024;
-constexpr int kPieceDirectMax = 2730;
 
 // Pieces of every segment (0 for segments of at most kChunkMax entries).
 __global__ __launch_bounds__(256) void k_big_pieces(const int64_t *__restrict__ off, int64_t k, int64_t *pieces) {
@@ -598,7 +597,8 @@ __global__ __launch_bounds__(256) void k_big_pieces(const int64_t *__restrict__ 
 __global__ __launch_bounds__(kPieceThreads) void k_big_piece(const int64_t *__restrict__ off, int64_t k,
                                                              const int64_t *__restrict__ poff, int32_t *tcol,
                                                              int64_t *tw, int64_t *mcount, uint64_t *pkey,
-                                                             int64_t *pval, unsigned long long *pcount, int bits) {
+                                                             int64_t *pval, unsigned long long *pcount, int bits,
+                                                             int64_t direct_max) {
     constexpr int T = 1 << kPieceBits;
     constexpr int Q = T / kPieceThreads;
     __shared__ int32_t s_k[T];
@@ -683,7 +683,7 @@ __global__ __launch_bounds__(kPieceThreads) void k_big_piece(const int64_t *__re
         pos[q] = s_k[x] != kEmpty ? atomicAdd(&s_n, 1) : -1;
     }
     __syncthreads();
-    const bool direct = poff[a + 1] - poff[a] == 1 && s_over == 0 && s_n <= kPieceDirectMax;
+    const bool direct = poff[a + 1] - poff[a] == 1 && s_over == 0 && s_n <= direct_max;
     if (direct) {
         // the whole segment was read above; its pairs go in place
 #pragma unroll
@@ -930,7 +930,8 @@ const int64_t *Contractor::sort_sum(int64_t m, int key_bits, const uint64_t **uk
 }
 
 int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t n_new, int64_t *rp_out,
-                             int32_t *col_out, void *w_out, int wout_bytes, int64_t *delta_out, bool sorted) {
+                             int32_t *col_out, void *w_out, int wout_bytes, int64_t *delta_out, bool sorted,
+                             int64_t direct_max) {
     require(wout_bytes == 4 || wout_bytes == 8, LOUVAIN_EDEVICE, "contracted weights are 4 or 8 bytes");
     if (delta_out) fill<int64_t>(delta_out, 0, n_new, s_);
     if (n_new == 0) {
@@ -1011,7 +1012,7 @@ int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t 
         // at most kPiece entries (column, weight) read per piece
         TimedLaunch tl(t_, TG_CONTRACT, "k_big_piece", (double)*npc * kPiece * 12);
         tl.launch(k_big_piece, (unsigned)*npc, kPieceThreads, 0, s_, off, k, (const int64_t *)poff, tcol_.p, tw_.p,
-                  mcount, key_[0].p, val_[0].p, pc.as<unsigned long long>(), bits);
+                  mcount, key_[0].p, val_[0].p, pc.as<unsigned long long>(), bits, direct_max);
         LV_LAUNCHED("k_big_piece");
     }
     const uint64_t *npp = rb.add(pc.as<uint64_t>());

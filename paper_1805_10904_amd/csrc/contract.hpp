@@ -33,9 +33,12 @@ class Contractor {
     // degree of every super-vertex.  Entries of rows with newlab == -1 are
     // dropped.  sorted: columns ascend in every row (the canonical form);
     // otherwise their order within a row is unspecified, which the method
-    // does not depend on.
+    // does not depend on, except that rows longer than direct_max (the next
+    // level's longest row swept from LDS) keep ascending columns, which the
+    // hub kernels' pre-aggregation benefits from.
     int64_t contract(const GraphView &g, const int32_t *newlab, int64_t n_new, int64_t *rp_out,
-                     int32_t *col_out, void *w_out, int wout_bytes, int64_t *delta_out, bool sorted = false);
+                     int32_t *col_out, void *w_out, int wout_bytes, int64_t *delta_out, bool sorted = false,
+                     int64_t direct_max = 2730);
 
   private:
     // Sort (key_[0], val_[0])[0, m) by the low key_bits of the keys and sum

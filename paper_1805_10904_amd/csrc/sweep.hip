@@ -114,6 +114,11 @@ static int word_shift(int64_t n, int64_t tw) {
     return (shift < 63 && (uint64_t)tw < (1ull << shift)) ? shift : 0;
 }
 
+int64_t lds_row_max(int64_t n, int64_t tw, const Tuning &tn) {
+    if (tw < kCompactTwMax) return tn.block_max;
+    return word_shift(n, tw) ? kBucketMax[B_WIDE] : kBucketMax[B_BLOCK];
+}
+
 // ------------------------------------------------------------- decisions --
 
 // New community of vertex i given its best candidate (bs, bl) and
@@ -1088,10 +1093,7 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     n_ = g.n;
     compact_ = batch_ || g.tw < kCompactTwMax;   // before anything that depends on the level's kind
     const int small_max = compact_ ? tuning_.small_max : (int)kBucketMax[B_T8];
-    // general levels: rows up to kBucketMax[B_WIDE] go to LDS when the wide
-    // kernel's single-word table can hold their labels and weights
-    const int64_t block_max = compact_ ? tuning_.block_max
-                                       : (word_shift(g.n, g.tw) ? kBucketMax[B_WIDE] : kBucketMax[B_BLOCK]);
+    const int64_t block_max = compact_ ? tuning_.block_max : lds_row_max(g.n, g.tw, tuning_);
     const int32_t *skip_gid = active_only && batch_ ? gid_ : nullptr;
     const PhaseState *skip_st = active_only && batch_ ? st_.p : nullptr;
     if (!batch_) {

@@ -127,6 +127,12 @@ struct CompactState {
     SideStreams *side = nullptr;   // optional: streams for the one-workgroup rows and the hubs
 };
 
+// Longest row a level of n vertices and total weight tw sweeps from LDS
+// (longer rows use the HBM hub tables): the tuned block_max on compact
+// levels; on general levels kBucketMax[B_WIDE] when labels and weights fit a
+// single 64-bit table word, else kBucketMax[B_BLOCK].
+int64_t lds_row_max(int64_t n, int64_t tw, const Tuning &tn);
+
 // Levels whose graphs all have TW < 2^31 run on packed community words
 // (sweep_compact.hip).
 constexpr int64_t kCompactTwMax = (int64_t)1 << 31;
