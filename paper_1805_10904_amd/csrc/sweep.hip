@@ -1194,6 +1194,7 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
 }
 
 void Sweeper::init_singletons(const GraphView &g) {
+    singleton_start_ = true;
     if (compact_) {
         compact_init_singletons(c_[0].p, c_[1].p, c_[2].p, g.delta, ds_.p, es_.p, g.n, s_);
         LV_HIP(hipMemsetAsync(st_.p, 0, sizeof(PhaseState) * (size_t)ngraphs_, s_));
@@ -1208,6 +1209,7 @@ void Sweeper::init_singletons(const GraphView &g) {
 }
 
 void Sweeper::init_from_labels(const GraphView &g, const int32_t *labels) {
+    singleton_start_ = false;
     if (compact_) {
         fill<uint64_t>(ds_.p, 0, g.n, s_);
         compact_init_labels(c_[0].p, c_[1].p, c_[2].p, labels, g.delta, ds_.p, es_.p, g.n, s_);
@@ -1439,6 +1441,7 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
         cp.small_max = tuning_.small_max;
         cp.group_slots = tuning_.group_slots;
         cp.group_vertices = tuning_.group_vertices;
+        cp.first = singleton_start_ && p == 1 ? 1 : 0;
         cp.overlap = tuning_.overlap;
         for (int c = 0; c <= kLdsClasses; ++c) cp.cstart[c] = cstart_[c];
         for (int c = 0; c < kLdsClasses; ++c) cp.cnnz[c] = cnnz_[c];

@@ -98,6 +98,8 @@ struct CompactPass {
     int small_max = 8;                         // rows swept one thread per vertex
     int group_slots = 4;                       // slots per lane of the packed classes
     int group_vertices = 1;                    // vertices per lane group of the packed classes
+    int first = 0;                             // the labelling read is the singletons (every
+                                               // neighbour its own community): no tables
     int overlap = 0;                           // row families side by side on side streams
     int64_t hubs = 0, hub_chunks = 0, hub_scans = 0;
     const int64_t *tab_off = nullptr, *chunk_off = nullptr, *scan_off = nullptr, *tab_size = nullptr;
@@ -204,6 +206,7 @@ class Sweeper {
     hipStream_t s_;
     Timer *t_;
     std::unique_ptr<SideStreams> side_;   // leased on the first compact pass
+    bool singleton_start_ = false;        // the phase started from singletons
     int64_t cap_n_ = -1, cap_nnz_ = -1;
     DevBuf<int32_t> c_[3];
     DevBuf<int64_t> deg_;           // deg_C by label (updated in place by the commit)

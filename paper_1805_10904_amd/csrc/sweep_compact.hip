@@ -59,6 +59,7 @@ struct CArgs {
     const PhaseState *st;    // phase state of every graph
     uint32_t *e_self;        // e_{i->c_i} incl. loop, written for every evaluated vertex
     int singlet;
+    int first;   // the labelling read is the singletons: score entries directly, no tables
 };
 
 __device__ __forceinline__ int graph_of(const int32_t *gid, int64_t v) { return gid ? gid[v] : 0; }
@@ -543,10 +544,12 @@ __global__ __launch_bounds__(256) void k_cpt_group(CArgs a, const int32_t *__res
     const int kv = t / G, li = t % G;
     int32_t *key = s_key + kv * S;
     uint32_t *es = s_e + kv * S, *hs = s_hi + kv * S;
+    if (!a.first) {   // the first pass from singletons uses no table
 #pragma unroll
-    for (int q = 0; q < SPL; ++q) {
-        key[li + q * G] = kEmpty;   // lane-consecutive words: no bank conflicts
-        es[li + q * G] = 0;
+        for (int q = 0; q < SPL; ++q) {
+            key[li + q * G] = kEmpty;   // lane-consecutive words: no bank conflicts
+            es[li + q * G] = 0;
+        }
     }
     const int64_t k = (int64_t)blockIdx.x * NV + kv;
     bool live = false;
@@ -575,9 +578,11 @@ __global__ __launch_bounds__(256) void k_cpt_group(CArgs a, const int32_t *__res
     }
     __syncthreads();
     // Entries in rounds of U per lane: a round's loads and gathers are all
-    // issued before its inserts.
+    // issued before its inserts (from singletons: scored directly, no table).
     constexpr int U = 4;
     uint32_t loop = 0;
+    unsigned long long bok = 0;
+    uint32_t blf = 0xffffffffu, e_own = 0;
     for (int64_t x0 = li; x0 < d; x0 += (int64_t)U * G) {
         int32_t jq[U];
         uint32_t wq[U];
@@ -599,17 +604,23 @@ __global__ __launch_bounds__(256) void k_cpt_group(CArgs a, const int32_t *__res
         }
 #pragma unroll
         for (int q = 0; q < U; ++q) {
-            if (jq[q] == v)
+            if (jq[q] == v) {
                 loop += wq[q];
-            else
+            } else if (a.first) {
+                const uint32_t hi = (uint32_t)(nq[q] >> 32);
+                const unsigned long long ok =
+                    ((uint64_t)(uint32_t)tw * wq[q] - (uint64_t)(uint32_t)di * hi_deg(hi)) ^ 0x8000000000000000ull;
+                best_take(bok, blf, (uint32_t)ok, (uint32_t)(ok >> 32),
+                          ((uint32_t)vw_label(nq[q]) << 1) | (hi_single(hi) ? 1u : 0u));
+            } else {
                 grp_insert(key, es, hs, BITS, vw_label(nq[q]), wq[q], (uint32_t)(nq[q] >> 32));
+            }
         }
     }
     __syncthreads();
-    unsigned long long bok = 0;
-    uint32_t blf = 0xffffffffu, e_own = 0;
 #pragma unroll
     for (int q = 0; q < SPL; ++q) {
+        if (a.first) break;
         const int x = li + q * G;
         const int32_t kk = key[x];
         if (kk == kEmpty) continue;
@@ -700,10 +711,12 @@ __global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__re
         key[j] = s_key + (j * NV + kv) * S;
         es[j] = s_e + (j * NV + kv) * S;
         hs[j] = s_hi + (j * NV + kv) * S;
+        if (!a.first) {   // the first pass from singletons uses no table
 #pragma unroll
-        for (int q = 0; q < SPL; ++q) {
-            key[j][li + q * G] = kEmpty;   // lane-consecutive words: no bank conflicts
-            es[j][li + q * G] = 0;
+            for (int q = 0; q < SPL; ++q) {
+                key[j][li + q * G] = kEmpty;   // lane-consecutive words: no bank conflicts
+                es[j][li + q * G] = 0;
+            }
         }
         if (li == 0) {
             s_eown[j * NV + kv] = 0;
@@ -778,15 +791,41 @@ __global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__re
         }
     }
     __syncthreads();
+    unsigned long long bok[VPG];
+    uint32_t blf[VPG];
 #pragma unroll
-    for (int q = 0; q < U; ++q)
+    for (int j = 0; j < VPG; ++j) {
+        bok[j] = 0;
+        blf[j] = 0xffffffffu;
+    }
+    if (a.first) {
+        // singletons: every neighbour is its own community (e = the entry's
+        // weight, columns are distinct), so entries are scored directly
 #pragma unroll
-        for (int j = 0; j < VPG; ++j) {
-            if (jq[j][q] == v[j]) {
-                if (wq[j][q]) s_loop[j * NV + kv] = wq[j][q];
-            } else
-                grp_insert(key[j], es[j], hs[j], bits, vw_label(nq[j][q]), wq[j][q], (uint32_t)(nq[j][q] >> 32));
-        }
+        for (int q = 0; q < U; ++q)
+#pragma unroll
+            for (int j = 0; j < VPG; ++j) {
+                if (jq[j][q] == v[j]) {
+                    if (wq[j][q]) s_loop[j * NV + kv] = wq[j][q];
+                    continue;
+                }
+                const uint32_t hi = (uint32_t)(nq[j][q] >> 32);
+                const unsigned long long ok =
+                    ((uint64_t)tw[j] * wq[j][q] - (uint64_t)di[j] * hi_deg(hi)) ^ 0x8000000000000000ull;
+                const uint32_t lf = ((uint32_t)vw_label(nq[j][q]) << 1) | (hi_single(hi) ? 1u : 0u);
+                best_take(bok[j], blf[j], (uint32_t)ok, (uint32_t)(ok >> 32), lf);
+            }
+    } else {
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+#pragma unroll
+            for (int j = 0; j < VPG; ++j) {
+                if (jq[j][q] == v[j]) {
+                    if (wq[j][q]) s_loop[j * NV + kv] = wq[j][q];
+                } else
+                    grp_insert(key[j], es[j], hs[j], bits, vw_label(nq[j][q]), wq[j][q], (uint32_t)(nq[j][q] >> 32));
+            }
+    }
 #pragma unroll
     for (int j = 0; j < VPG; ++j)
         for (int64_t x = li + (int64_t)U * G; x < d[j]; x += G) {   // not reached for class rows
@@ -797,15 +836,20 @@ __global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__re
                 continue;
             }
             const uint64_t nw = a.vw[nb];
-            grp_insert(key[j], es[j], hs[j], bits, vw_label(nw), w, (uint32_t)(nw >> 32));
+            if (a.first) {
+                const uint32_t hi = (uint32_t)(nw >> 32);
+                const unsigned long long ok =
+                    ((uint64_t)tw[j] * w - (uint64_t)di[j] * hi_deg(hi)) ^ 0x8000000000000000ull;
+                best_take(bok[j], blf[j], (uint32_t)ok, (uint32_t)(ok >> 32),
+                          ((uint32_t)vw_label(nw) << 1) | (hi_single(hi) ? 1u : 0u));
+            } else {
+                grp_insert(key[j], es[j], hs[j], bits, vw_label(nw), w, (uint32_t)(nw >> 32));
+            }
         }
     __syncthreads();
-    unsigned long long bok[VPG];
-    uint32_t blf[VPG];
 #pragma unroll
     for (int j = 0; j < VPG; ++j) {
-        bok[j] = 0;
-        blf[j] = 0xffffffffu;
+        if (a.first) break;
 #pragma unroll
         for (int q = 0; q < SPL; ++q) {
             const int x = li + q * G;
@@ -897,10 +941,12 @@ __global__ __launch_bounds__(kBigRowThreads) void k_cpt_bigrow(CArgs a, const in
     __shared__ uint32_t r_lf[NW];
     __shared__ uint32_t s_eown, s_loop;
     const int t = threadIdx.x;
+    if (!a.first) {   // the first pass from singletons uses no table
 #pragma unroll
-    for (int q = 0; q < SPL; ++q) {
-        key[t + q * T] = kEmpty;
-        es[t + q * T] = 0;
+        for (int q = 0; q < SPL; ++q) {
+            key[t + q * T] = kEmpty;
+            es[t + q * T] = 0;
+        }
     }
     if (t == 0) {
         s_eown = 0;
@@ -919,6 +965,8 @@ __global__ __launch_bounds__(kBigRowThreads) void k_cpt_bigrow(CArgs a, const in
     const uint32_t di = (uint32_t)a.delta[v];
     const uint32_t tw = (uint32_t)a.tw[g];
     __syncthreads();
+    unsigned long long bok = 0;
+    uint32_t blf = 0xffffffffu;
     constexpr int U = 4;
     for (int64_t x0 = t; x0 < d; x0 += (int64_t)U * T) {
         int32_t jq[U];
@@ -934,12 +982,24 @@ __global__ __launch_bounds__(kBigRowThreads) void k_cpt_bigrow(CArgs a, const in
                 wq[q] = cw<W>(a.w, rs + x);
             }
         }
+        uint64_t nq[U];
 #pragma unroll
-        for (int q = 0; q < U; ++q) lq[q] = (jq[q] >= 0 && jq[q] != v) ? vw_label(a.vw[jq[q]]) : -1;
+        for (int q = 0; q < U; ++q) {
+            nq[q] = (jq[q] >= 0 && jq[q] != v) ? a.vw[jq[q]] : 0;
+            lq[q] = (jq[q] >= 0 && jq[q] != v) ? vw_label(nq[q]) : -1;
+        }
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             if (jq[q] == v) s_loop = wq[q];   // a row has at most one loop
             if (lq[q] < 0) continue;
+            if (a.first) {   // singletons: the entry is its own candidate
+                const uint32_t hi = (uint32_t)(nq[q] >> 32);
+                const unsigned long long ok =
+                    ((uint64_t)tw * wq[q] - (uint64_t)di * hi_deg(hi)) ^ 0x8000000000000000ull;
+                best_take(bok, blf, (uint32_t)ok, (uint32_t)(ok >> 32),
+                          ((uint32_t)lq[q] << 1) | (hi_single(hi) ? 1u : 0u));
+                continue;
+            }
             uint32_t h = ((uint32_t)lq[q] * 0x9E3779B1u) >> (32 - BITS);
             while (true) {
                 const int32_t prev = atomicCAS(&key[h], kEmpty, lq[q]);   // claims, or returns the slot's key
@@ -950,10 +1010,9 @@ __global__ __launch_bounds__(kBigRowThreads) void k_cpt_bigrow(CArgs a, const in
         }
     }
     __syncthreads();
-    unsigned long long bok = 0;
-    uint32_t blf = 0xffffffffu;
 #pragma unroll 4
     for (int q = 0; q < SPL; ++q) {
+        if (a.first) break;
         const int x = t + q * T;
         const int32_t kk = key[x];
         if (kk == kEmpty) continue;
@@ -1111,18 +1170,22 @@ __device__ __forceinline__ void word_insert_hbm(unsigned long long *tab, uint64_
 // label -> e, then one HBM table insert per distinct label.
 template <typename W>
 __global__ __launch_bounds__(256) void k_cpt_hub_accum(CArgs a, CHub hm, unsigned long long *gtab,
-                                                       unsigned long long *hub_loop) {
+                                                       unsigned long long *hub_loop, uint64_t *part) {
     if (single_done(a.gid, a.st)) return;
     constexpr int T = 1 << kCHubLdsBits;
     __shared__ unsigned long long s_tab[T];
+    __shared__ unsigned long long r_ok[4];
+    __shared__ uint32_t r_lf[4];
     __shared__ int64_t s_h;
     const int t = threadIdx.x;
     if (t == 0) s_h = hm.chunk_hub[blockIdx.x];
-    for (int x = t; x < T; x += 256) s_tab[x] = 0;
+    if (!a.first)
+        for (int x = t; x < T; x += 256) s_tab[x] = 0;
     __syncthreads();
     const int64_t h = s_h;
     const int32_t v = hm.v[h];
-    if (a.st[graph_of(a.gid, v)].done) return;   // uniform over the workgroup
+    const int g = graph_of(a.gid, v);
+    if (a.st[g].done) return;   // uniform over the workgroup
     const int64_t k = (int64_t)blockIdx.x - hm.chunk_off[h];
     const int64_t row_end = a.row_ptr[v + 1];
     const int64_t rs = a.row_ptr[v] + k * kHubChunk;
@@ -1132,7 +1195,7 @@ __global__ __launch_bounds__(256) void k_cpt_hub_accum(CArgs a, CHub hm, unsigne
     static_assert(kHubChunk % 256 == 0, "a chunk is whole rounds of the workgroup");
     int32_t jq[U];
     uint32_t wq[U];
-    int32_t lq[U];
+    uint64_t nq[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
         const int64_t e = rs + t + q * 256;
@@ -1144,17 +1207,50 @@ __global__ __launch_bounds__(256) void k_cpt_hub_accum(CArgs a, CHub hm, unsigne
         }
     }
 #pragma unroll
-    for (int q = 0; q < U; ++q) {
-        lq[q] = -1;
-        if (jq[q] >= 0 && jq[q] != v) lq[q] = vw_label(a.vw[jq[q]]);
-    }
+    for (int q = 0; q < U; ++q) nq[q] = (jq[q] >= 0 && jq[q] != v) ? a.vw[jq[q]] : 0;
     uint32_t loop = 0;
 #pragma unroll
-    for (int q = 0; q < U; ++q) {
+    for (int q = 0; q < U; ++q)
         if (jq[q] == v) loop += wq[q];
-        if (lq[q] >= 0) word_insert(s_tab, T, ((uint32_t)lq[q] * 0x9E3779B1u) >> (32 - kCHubLdsBits), lq[q], wq[q]);
-    }
     if (loop) atomicAdd(&hub_loop[h], (unsigned long long)loop);
+    if (a.first) {
+        // singletons: every entry is its own candidate; the chunk's best goes
+        // to its partial (decided over the hub's chunks), no tables
+        const uint32_t di = (uint32_t)a.delta[v], tw = (uint32_t)a.tw[g];
+        unsigned long long bok = 0;
+        uint32_t blf = 0xffffffffu;
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            if (jq[q] < 0 || jq[q] == v) continue;
+            const uint32_t hi = (uint32_t)(nq[q] >> 32);
+            const unsigned long long ok = ((uint64_t)tw * wq[q] - (uint64_t)di * hi_deg(hi)) ^ 0x8000000000000000ull;
+            best_take(bok, blf, (uint32_t)ok, (uint32_t)(ok >> 32),
+                      ((uint32_t)vw_label(nq[q]) << 1) | (hi_single(hi) ? 1u : 0u));
+        }
+        group_best(bok, blf, 64);
+        const int wid = t >> 6;
+        if ((t & 63) == 0) {
+            r_ok[wid] = bok;
+            r_lf[wid] = blf;
+        }
+        __syncthreads();
+        if (t == 0) {
+            for (int w2 = 1; w2 < 4; ++w2)
+                best_take(bok, blf, (uint32_t)r_ok[w2], (uint32_t)(r_ok[w2] >> 32), r_lf[w2]);
+            uint64_t *p = part + 4 * (int64_t)blockIdx.x;
+            p[0] = bok;
+            p[1] = (uint64_t)(blf >> 1) | ((uint64_t)(blf & 1u) << 32);
+            p[2] = 0;
+            p[3] = 0;
+        }
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q) {
+        if (jq[q] < 0 || jq[q] == v) continue;
+        const int32_t l = vw_label(nq[q]);
+        word_insert(s_tab, T, ((uint32_t)l * 0x9E3779B1u) >> (32 - kCHubLdsBits), l, wq[q]);
+    }
     __syncthreads();
     const int64_t base = hm.tab_off[h], size = hm.tab_size[h];
     for (int x = t; x < T; x += 256) {
@@ -1240,7 +1336,10 @@ __global__ __launch_bounds__(256) void k_cpt_hub_decide(CArgs a, CHub hm, const 
     unsigned long long bok = 0;
     int32_t bl = 0x7fffffff, bf = 0;
     uint64_t e_own = 0;
-    for (int64_t b = hm.scan_off[h] + lane; b < hm.scan_off[h + 1]; b += 64) {
+    // partials: one per scan workgroup, or one per chunk on the first pass
+    // from singletons
+    const int64_t *range = a.first ? hm.chunk_off : hm.scan_off;
+    for (int64_t b = range[h] + lane; b < range[h + 1]; b += 64) {
         const uint64_t *p = part + 4 * b;
         const unsigned long long ok = p[0];
         const int32_t l = (int32_t)(uint32_t)p[1];
@@ -1432,10 +1531,10 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
                 cp.chunk_hub, cp.scan_hub, cp.hubs};
         {
             TimedLaunch tl(t, TG_SWEEP, "k_cpt_hub_accum<", (double)cp.bnnz[B_HUB] * eb, sfx.c_str());
-            tl.launch(k_cpt_hub_accum<W>, (unsigned)cp.hub_chunks, 256, 0, s2, a, hm, cp.hval, cp.hloop);
+            tl.launch(k_cpt_hub_accum<W>, (unsigned)cp.hub_chunks, 256, 0, s2, a, hm, cp.hval, cp.hloop, cp.hpart);
             LV_LAUNCHED("k_cpt_hub_accum");
         }
-        {
+        if (!a.first) {
             TimedLaunch tl(t, TG_SWEEP, "k_cpt_hub_scan", (double)cp.hub_scans * kHubScan * 16.0);
             tl.launch(k_cpt_hub_scan, (unsigned)cp.hub_scans, 256, 0, s2, a, hm, cp.hval, cp.hpart);
             LV_LAUNCHED("k_cpt_hub_scan");
@@ -1457,7 +1556,8 @@ void compact_pass(const GraphView &g, const CompactPass &cp, const CompactState 
                   cs.active + (p & 1));
         LV_LAUNCHED("k_cpt_publish");
     }
-    CArgs a{g.row_ptr, g.col, g.w, cs.c_cur, cs.c_nxt, g.delta, cs.vw, cs.ds, cs.gid, cs.tw, cs.st, cs.es, prm.singlet};
+    CArgs a{g.row_ptr, g.col, g.w, cs.c_cur, cs.c_nxt, g.delta, cs.vw, cs.ds, cs.gid, cs.tw, cs.st, cs.es, prm.singlet,
+            cp.first};
     SideStreams *side = cp.overlap ? cs.side : nullptr;
     if (g.wbytes == 4)
         compact_sweeps<int32_t>(a, cp, s, side, t);
