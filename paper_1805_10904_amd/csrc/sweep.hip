@@ -36,6 +36,7 @@ struct SweepArgs {
     PhaseState *st;
     int64_t *e_self;   // optional per-vertex e_{i->c_i} incl. loop
     int hub_shift;     // > 0: hub tables hold one word (label + 1) << hub_shift | e per slot
+    int first;         // the labelling read is the singletons: score entries directly, no tables
 };
 
 template <typename W>
@@ -198,10 +199,12 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a, const int32_t 
     const int g = tid / G, lane = tid % G;
     int32_t *key = s_key + g * T;
     unsigned long long *val = s_val + g * T;
+    if (!a.first) {   // the first pass from singletons uses no table
 #pragma unroll
-    for (int x = lane; x < T; x += G) {
-        key[x] = kEmpty;
-        val[x] = 0;
+        for (int x = lane; x < T; x += G) {
+            key[x] = kEmpty;
+            val[x] = 0;
+        }
     }
     if (tid == 0) s_I = 0;
     __syncthreads();
@@ -216,8 +219,11 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a, const int32_t 
         ci = a.c_cur[i];
     }
     int64_t loop = 0;
+    S bs = 0;
+    int32_t bl = -1;
+    const int64_t di = active ? a.delta[i] : 0;
     // entries in rounds of U per lane: a round's loads and label gathers are
-    // all issued before its inserts
+    // all issued before its inserts (from singletons: scored directly)
     constexpr int U = 4;
     for (int64_t e0 = rs + lane; e0 < re; e0 += (int64_t)U * G) {
         int32_t jq[U], lq[U];
@@ -237,15 +243,21 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a, const int32_t 
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             if (jq[q] == i) loop += wq[q];
-            if (lq[q] >= 0) lds_insert<BITS>(key, val, lq[q], wq[q]);
+            if (lq[q] < 0) continue;
+            if (a.first) {   // every neighbour is its own community
+                const S sc = score_mul<S>(a.tw, wq[q]) - score_mul<S>(di, a.deg[lq[q]]);
+                if (better<S>(sc, lq[q], bs, bl)) {
+                    bs = sc;
+                    bl = lq[q];
+                }
+            } else {
+                lds_insert<BITS>(key, val, lq[q], wq[q]);
+            }
         }
     }
     __syncthreads();
-    S bs = 0;
-    int32_t bl = -1;
     int64_t e_own = 0;
-    if (active) {
-        const int64_t di = a.delta[i];
+    if (active && !a.first) {
 #pragma unroll
         for (int x = lane; x < T; x += G) {
             const int32_t k = key[x];
@@ -628,9 +640,10 @@ constexpr int kHubLdsBits = 11;  // 2048 slots for a chunk of kHubChunk = 1024 e
 
 // One workgroup per kHubChunk entries of a hub row: pre-aggregate e_{i->C}
 // in LDS, then add each distinct community once into the hub's HBM table.
-template <typename W>
+template <typename W, typename S>
 __global__ __launch_bounds__(256) void k_hub_accum(SweepArgs a, HubMeta hm, int32_t *gkey,
-                                                   unsigned long long *gval, unsigned long long *hub_loop) {
+                                                   unsigned long long *gval, unsigned long long *hub_loop,
+                                                   uint64_t *part) {
     constexpr int T = 1 << kHubLdsBits;
     __shared__ int32_t s_key[T];
     __shared__ unsigned long long s_val[T];
@@ -638,10 +651,11 @@ __global__ __launch_bounds__(256) void k_hub_accum(SweepArgs a, HubMeta hm, int3
     if (a.st->done) return;
     const int t = threadIdx.x;
     if (t == 0) s_h = hm.chunk_hub[blockIdx.x];
-    for (int x = t; x < T; x += 256) {
-        s_key[x] = kEmpty;
-        s_val[x] = 0;
-    }
+    if (!a.first)
+        for (int x = t; x < T; x += 256) {
+            s_key[x] = kEmpty;
+            s_val[x] = 0;
+        }
     __syncthreads();
     const int64_t h = s_h;
     const int32_t v = hm.v[h];
@@ -668,11 +682,39 @@ __global__ __launch_bounds__(256) void k_hub_accum(SweepArgs a, HubMeta hm, int3
     for (int q = 0; q < U; ++q) lq[q] = (jq[q] >= 0 && jq[q] != v) ? a.c_cur[jq[q]] : -1;
     int64_t loop = 0;
 #pragma unroll
-    for (int q = 0; q < U; ++q) {
+    for (int q = 0; q < U; ++q)
         if (jq[q] == v) loop += wq[q];
-        if (lq[q] >= 0) lds_insert<kHubLdsBits>(s_key, s_val, lq[q], wq[q]);
-    }
     if (loop) atomicAdd(&hub_loop[h], (unsigned long long)loop);
+    if (a.first) {
+        // singletons: every entry is its own candidate; the chunk's best goes
+        // to its partial (decided over the hub's chunks), no tables
+        const int64_t di = a.delta[v];
+        S bs = 0;
+        int32_t bl = -1;
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            if (lq[q] < 0) continue;
+            const S sc = score_mul<S>(a.tw, wq[q]) - score_mul<S>(di, a.deg[lq[q]]);
+            if (better<S>(sc, lq[q], bs, bl)) {
+                bs = sc;
+                bl = lq[q];
+            }
+        }
+        int64_t u0 = 0, u1 = 0;
+        group_reduce_block<S>(bs, bl, u0, u1);
+        if (t == 0) {
+            const i128 w = (i128)bs;
+            uint64_t *p = part + 4 * (int64_t)blockIdx.x;
+            p[0] = (uint64_t)w;
+            p[1] = (uint64_t)(int64_t)(w >> 64);
+            p[2] = (uint64_t)(int64_t)bl;
+            p[3] = 0;
+        }
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < U; ++q)
+        if (lq[q] >= 0) lds_insert<kHubLdsBits>(s_key, s_val, lq[q], wq[q]);
     __syncthreads();
     const int64_t base = hm.tab_off[h], size = hm.tab_size[h];
     for (int x = t; x < T; x += 256) {
@@ -754,7 +796,10 @@ __global__ __launch_bounds__(256) void k_hub_decide(SweepArgs a, HubMeta hm, con
     S bs = 0;
     int32_t bl = -1;
     int64_t e_own = 0, unused = 0;
-    for (int64_t b = hm.scan_off[h] + lane; b < hm.scan_off[h + 1]; b += 64) {
+    // partials: one per scan workgroup, or one per chunk on the first pass
+    // from singletons
+    const int64_t *range = a.first ? hm.chunk_off : hm.scan_off;
+    for (int64_t b = range[h] + lane; b < range[h + 1]; b += 64) {
         const uint64_t *p = part + 4 * b;
         const int32_t l = (int32_t)(int64_t)p[2];
         const S sc = (S)make_i128(p[0], (int64_t)p[1]);
@@ -1243,8 +1288,9 @@ __global__ __launch_bounds__(kWideThreads) void k_sweep_wide(SweepArgs a, const 
     __shared__ int64_t s_eown, s_loop;
     if (a.st->done) return;
     const int t = threadIdx.x;
+    if (!a.first)   // the first pass from singletons uses no table
 #pragma unroll
-    for (int q = 0; q < SPL; ++q) tab[t + q * T] = 0;
+        for (int q = 0; q < SPL; ++q) tab[t + q * T] = 0;
     if (t == 0) {
         s_eown = 0;
         s_loop = 0;
@@ -1255,6 +1301,9 @@ __global__ __launch_bounds__(kWideThreads) void k_sweep_wide(SweepArgs a, const 
     const int shift = a.hub_shift;
     const unsigned long long tmask = ~0ull << shift;
     __syncthreads();
+    const int64_t di = a.delta[i];
+    S bs = 0;
+    int32_t bl = -1;
     constexpr int U = 4;
     for (int64_t e0 = rs + t; e0 < re; e0 += (int64_t)U * T) {
         int32_t jq[U], lq[U];
@@ -1275,6 +1324,14 @@ __global__ __launch_bounds__(kWideThreads) void k_sweep_wide(SweepArgs a, const 
         for (int q = 0; q < U; ++q) {
             if (jq[q] == i) s_loop = wq[q];   // a row has at most one loop
             if (lq[q] < 0) continue;
+            if (a.first) {   // every neighbour is its own community
+                const S sc = score_mul<S>(a.tw, wq[q]) - score_mul<S>(di, a.deg[lq[q]]);
+                if (better<S>(sc, lq[q], bs, bl)) {
+                    bs = sc;
+                    bl = lq[q];
+                }
+                continue;
+            }
             const unsigned long long tag = (unsigned long long)(uint32_t)(lq[q] + 1) << shift;
             uint32_t h = ((uint32_t)lq[q] * 0x9E3779B1u) >> (32 - kWideBits);
             while (true) {
@@ -1289,11 +1346,9 @@ __global__ __launch_bounds__(kWideThreads) void k_sweep_wide(SweepArgs a, const 
         }
     }
     __syncthreads();
-    const int64_t di = a.delta[i];
-    S bs = 0;
-    int32_t bl = -1;
 #pragma unroll 4
     for (int q = 0; q < SPL; ++q) {
+        if (a.first) break;
         const unsigned long long wd = tab[t + q * T];
         if (wd == 0) continue;
         const int32_t k = (int32_t)(wd >> shift) - 1;
@@ -1393,10 +1448,10 @@ static void launch_pass(const SweepArgs &a, const int32_t *list, const int64_t *
     if (hm.hubs > 0) {
         {
             TimedLaunch tl(t, TG_SWEEP, "k_hub_accum<", (double)bnnz[B_HUB] * eb, wsfx.c_str());
-            tl.launch(k_hub_accum<W>, (unsigned)hub_chunks, 256, 0, s, a, hm, hkey, hval, hloop);
+            tl.launch(k_hub_accum<W, S>, (unsigned)hub_chunks, 256, 0, s, a, hm, hkey, hval, hloop, hpart);
             LV_LAUNCHED("k_hub_accum");
         }
-        {
+        if (!a.first) {
             TimedLaunch tl(t, TG_SWEEP, "k_hub_scan<", (double)hub_scans * kHubScan * 24.0, ssfx.c_str());
             tl.launch(k_hub_scan<S>, (unsigned)hub_scans, 256, 0, s, a, hm, hkey, hval, hpart);
             LV_LAUNCHED("k_hub_scan");
@@ -1483,7 +1538,7 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
     // fit 64 bits together
     const int hub_shift = word_shift(g.n, g.tw);
     SweepArgs a{g.row_ptr, g.col, g.w, c_[cur].p, c_[nxt].p, g.delta, deg_.p, size_.p,
-                g.tw, prm.singlet, st_.p, e_self_out, hub_shift};
+                g.tw, prm.singlet, st_.p, e_self_out, hub_shift, singleton_start_ && p == 1 ? 1 : 0};
     int64_t *tab_off = hub_meta_.p;
     HubMeta hm{list_.p + bstart_[B_HUB], tab_off, tab_off + (hubs_ + 1), tab_off + 2 * (hubs_ + 1),
                tab_off + 3 * (hubs_ + 1), hub_of_chunk_.p, hub_of_scan_.p, hubs_};
