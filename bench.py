@@ -12,7 +12,9 @@ value = local-move GTEPS of the whole job: the method's executed sweeps
 their level's graph, divided by the wall time of the step.  Per-kernel
 device times come from HIP events that the kernel dispatches themselves
 fill (hipExtLaunchKernel) on the library's stream: every launch in the last
-warm-up step, the dominant kernel's launches in the timed steps.
+warm-up step, the dominant kernel's launches in the last timed step (the
+events add a few microseconds around each timed kernel, so the other timed
+steps carry none).
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -29,6 +31,33 @@ sys.path.insert(0, ROOT)
 
 METRIC = "local-move GTEPS + full-Louvain seconds; batched/served vs plain, 1 GPU"
 HBM_PEAK_GBS = 8000.0
+
+
+def recorded_traffic(workload: str, kernel: str):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    rocprofv3 counter summaries (FETCH_SIZE and WRITE_SIZE, calibrated
+    against a plain copy), or None when none covers it or the sources it was
+    measured on have changed since."""
+    import glob
+    import hashlib
+    import re
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "traffic_*_pmc.md"))):
+        with open(path) as f:
+            m = re.search(r"```traffic\n(.*?)```", f.read(), re.S)
+        if not m:
+            continue
+        rec = json.loads(m.group(1))
+        if rec["workload"] != workload or rec["kernel"].replace(" ", "") != kernel.replace(" ", ""):
+            continue
+        h = hashlib.sha256()
+        try:
+            for src in rec["sources"]:
+                with open(os.path.join(ROOT, src), "rb") as f:
+                    h.update(f.read())
+        except OSError:
+            return None
+        return int(rec["bytes_per_launch"]) if h.hexdigest() == rec["sha256"] else None
+    return None
 
 
 def log(msg):
@@ -279,7 +308,7 @@ def main():
         log(f"autotuned launch shapes in {time.time() - t:.2f}s: {tuning} ({best['ms']:.3f} ms per run)")
 
     # warm-up steps; the first one records every kernel to find the dominant one,
-    # whose launches alone are timed in the timed steps
+    # whose launches alone are timed in the last timed step
     # (the last warm-up step, at least the second, is the one timed in full)
     dominant = None
     table = None
@@ -294,8 +323,11 @@ def main():
     torch.cuda.synchronize()
     results = []
     t0 = time.perf_counter()
+    # the dominant kernel's launches carry dispatch events in the last timed
+    # step only: each event adds a few microseconds before and after its
+    # kernel, which would otherwise weigh on every step's wall time
     for k in range(args.steps):
-        results.append(step(dominant if timing else False))
+        results.append(step(dominant if timing and k == args.steps - 1 else False))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     log(f"timed {args.steps} steps")
@@ -310,9 +342,9 @@ def main():
     sweep_gteps = None
     kernel_ms = None
     if timing:
-        # the dominant kernel, timed live over the timed steps
+        # the dominant kernel, timed live in the last timed step
         dom = dict(launches=0, ms=0.0, alg_bytes=0.0)
-        for res in results:
+        for res in results[-1:]:
             k = res.stats["kernels"].get(dominant)
             if k:
                 for key in dom:
@@ -324,16 +356,21 @@ def main():
         sweep_ms = sum(v["ms"] for n, v in table.items() if n.startswith(("k_cpt_", "k_sweep", "k_hub", "k_commit",
                                                                              "k_qsum", "k_finalize")))
         sweep_gteps = edges / (sweep_ms / 1000.0) / 1e9 if sweep_ms > 0 else None
+        # measured HBM bytes per launch (counters), against the algorithmic ones
+        traffic = recorded_traffic(args.workload, dom_name)
+        alg_per_launch = dom["alg_bytes"] / max(1, dom["launches"])
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom_name,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom_name,
                     "avg_launch_us": round(dom["ms"] * 1000.0 / dom["launches"], 2),
-                    "launches_per_step": dom["launches"] / len(results)}
+                    "launches_per_step": dom["launches"], "traffic_unit": "bytes per launch",
+                    "alg_bytes_per_launch": round(alg_per_launch),
+                    "traffic_over_alg": round(traffic / alg_per_launch, 3) if traffic else None}
         top = sorted(agg.items(), key=lambda kv: -kv[1]["ms"])[:20]
         log("kernel time of one step (all launches timed): " + ", ".join(f"{n} {a['ms']:.3f} ms" for n, a in top))
         kernel_ms = sum(a["ms"] for a in agg.values())
         log(f"all kernels {kernel_ms:.3f} ms per step ({sum(a['launches'] for a in agg.values()):.0f} "
             f"launches); timed step {ms_per_step:.3f} ms; dominant {dom_name} "
-            f"{dom['ms'] * 1000.0 / max(1, dom['launches']):.2f} us per launch over the timed steps")
+            f"{dom['ms'] * 1000.0 / max(1, dom['launches']):.2f} us per launch in the last timed step")
 
     cpu = None
     parity = None

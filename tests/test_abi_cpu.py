@@ -76,3 +76,13 @@ def test_served_and_batched_calls_are_declared():
     for f in ("louvain_run_batch", "louvain_submit", "louvain_poll", "louvain_workspace_bytes",
               "louvain_serve_budget"):
         assert f in names
+
+
+def test_recorded_traffic_lookup():
+    """The bench's counter-based traffic lookup parses the committed summary
+    and reports nothing for a kernel or workload it does not cover."""
+    import bench
+    got = bench.recorded_traffic("chunglu1m", "k_cpt_groups<4,1,int>")
+    assert got is None or got > 0
+    assert bench.recorded_traffic("chunglu1m", "no_such_kernel") is None
+    assert bench.recorded_traffic("no_such_workload", "k_cpt_groups<4,1,int>") is None
