@@ -16,6 +16,11 @@ warm-up step, the dominant kernel's launches in the last timed step (the
 events add a few microseconds around each timed kernel, so the other timed
 steps carry none).
 
+Beside the plain run, the line reports the run that keeps the dendrogram
+(per-level maps and the last level's graph) and a run checkpointed after its
+first level and resumed, with their wall times and whether their labels
+equal the plain run's (skip with --no-dendro).
+
 Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
@@ -213,6 +218,50 @@ def bench_served(L, torch, pool, requests: int, load: float, seed: int = 1005, t
             "identical_outputs": bool(ok and ok_sat)}
 
 
+def bench_dendro(torch, ctx, rp, col, w, ref_labels, plain_ms: float, runs: int = 3) -> dict:
+    """The run that keeps the dendrogram (per-level maps and the last level's
+    graph), and a run resumed from the first level's state, against the
+    plain run on the same graph: wall time per run, identical outputs."""
+    def one():
+        G = ctx.graph_create(rp, col, w)
+        res, D = ctx.run(G, dendrogram=True)
+        Gl = D.graph()
+        G.destroy()
+        return res, D, Gl
+
+    for r in one()[1:]:
+        r.destroy()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(runs):
+        res, D, Gl = one()
+        levels, sizes = D.levels, D.n
+        D.destroy()
+        Gl.destroy()
+    torch.cuda.synchronize()
+    dendro_ms = (time.perf_counter() - t0) * 1000.0 / runs
+    same = bool(torch.equal(res.labels, ref_labels))
+    # checkpoint after the first level, then resume: both parts timed
+    G = ctx.graph_create(rp, col, w)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    part, D = ctx.run(G, max_levels=1, dendrogram=True)
+    Gl = D.graph()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rest = ctx.resume(Gl, 1, part.labels)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    same = same and bool(torch.equal(rest.labels, ref_labels))
+    D.destroy()
+    Gl.destroy()
+    G.destroy()
+    return {"ms_per_run": round(dendro_ms, 3), "plain_ms_per_run": round(plain_ms, 3),
+            "overhead": round(dendro_ms / plain_ms, 3), "levels": levels, "map_entries": int(sum(sizes[:-1])),
+            "checkpoint_level1_ms": round((t1 - t0) * 1000.0, 3), "resume_ms": round((t2 - t1) * 1000.0, 3),
+            "identical_outputs": same}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,6 +286,8 @@ def main():
                          "request graphs (0 = skip)")
     ap.add_argument("--served-requests", type=int, default=0, help="trace length (default 4x the graphs)")
     ap.add_argument("--served-load", type=float, default=0.7, help="trace QPS as a fraction of plain capacity")
+    ap.add_argument("--no-dendro", action="store_true",
+                    help="skip the dendrogram-keeping and resumed runs beside the plain one")
     ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (for scaling the "
@@ -393,6 +444,15 @@ def main():
         parity = bool(np.array_equal(labels, ref.labels) and r.q_int == ref.q_int)
         log(f"oracle {spent / runs:.2f} s per run, parity {parity}")
 
+    dendro = None
+    if not args.no_dendro:
+        log("dendrogram and resume vs plain")
+        try:
+            dendro = bench_dendro(torch, ctx, rp, col, w, out.clone(), ms_per_step)
+        except Exception as e:  # the main measurement stands on its own
+            dendro = {"error": f"{type(e).__name__}: {e}"}
+        log(f"dendrogram: {dendro}")
+
     batched = served = None
     if batch_graphs is not None:
         log("batched vs plain")
@@ -425,6 +485,8 @@ def main():
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity,
     }
+    if dendro is not None:
+        line["dendrogram"] = dendro
     if batched is not None:
         line["batched"] = batched
     if served is not None:

@@ -248,6 +248,70 @@ int louvain_run_batch(louvain_ctx ctx, int64_t ngraphs, const louvain_graph *gra
                       louvain_i128 *q_int, double *q, int32_t *status,
                       louvain_run_stats *stats, uint32_t flags);
 
+/* ---- dendrogram export and resume ------------------------------------------ */
+
+typedef struct louvain_dendro_s *louvain_dendro;
+
+/*
+ * louvain_run that also keeps the dendrogram the renumbering step builds
+ * level by level (Section 3, renumbering: each level of the dendrogram is
+ * a map from the level's vertices to consecutive community IDs), plus the
+ * graph a further phase would run on, so that a run can be checkpointed
+ * and resumed (louvain_resume).  *dendro_out receives a handle owned by
+ * the caller (louvain_dendro_destroy) that holds, in device memory:
+ *   - map l for every phase l that kept a sweep: n[l] entries; map l sends
+ *     vertex i of level l's graph to its vertex in level l+1's graph (the
+ *     rank of its community's label among the labels present, ascending).
+ *     Level 0's graph is g; level l+1's graph is level l's contracted by
+ *     map l.  labels_out is the composition of the maps.
+ *   - the graph of the last level, n[levels] vertices, with ascending
+ *     columns: the graph of the phase that kept no sweep when the run ended
+ *     that way, or the contraction by the last map when max_levels cut the
+ *     run short (for a graph with TW = 0: a copy of g).
+ * The contractions of such a run sort every row, which costs some time
+ * over louvain_run; every other output equals louvain_run's.  Arguments
+ * and the return value are as for louvain_run; on error *dendro_out is
+ * untouched.
+ */
+int louvain_run_dendro(louvain_ctx ctx, louvain_graph g, const louvain_params *params,
+                       int32_t *labels_out, louvain_i128 *q_int, double *q,
+                       louvain_run_stats *stats, louvain_dendro *dendro_out, uint32_t flags);
+
+/* Number of maps (*levels) and the vertex count of every level's graph
+ * (n[0..levels], levels + 1 entries, at most 65).  Either may be NULL. */
+int louvain_dendro_info(louvain_dendro d, int32_t *levels, int64_t *n);
+
+/* Copy map `level` (n[level] entries) to map_out, host or device per flags
+ * (LOUVAIN_DEVICE_PTRS).  EINVAL for a level outside [0, levels). */
+int louvain_dendro_map(louvain_dendro d, int32_t level, int32_t *map_out, uint32_t flags);
+
+/* Hand the last level's graph to the caller: *out receives a graph handle
+ * of the dendrogram's context, owned by the caller.  A second call returns
+ * EINVAL. */
+int louvain_dendro_graph(louvain_dendro d, louvain_graph *out);
+
+int louvain_dendro_destroy(louvain_dendro d);
+
+/*
+ * Resume a run from a level state (Alg. 2 continued): g_level is the graph
+ * of level levels_done (as from louvain_dendro_graph), labels_so_far the
+ * composition of the first levels_done maps (n0 entries in [0, n of
+ * g_level), host or device per flags; louvain_run_dendro's labels_out).
+ * Runs the remaining params->max_levels - levels_done phases on g_level
+ * and writes labels_out[v] = the final community of vertex labels_so_far[v]
+ * of g_level (n0 entries).  The results equal those of one louvain_run with
+ * the same params on the original graph: each phase starts from singletons
+ * on its level's graph, and contraction keeps TW and Q_int, so q_int / q
+ * (of the partition on g_level) are also the original graph's.  stats
+ * describe the resumed phases only.  With levels_done >= max_levels no
+ * phase runs: labels_out = labels_so_far, and LOUVAIN_ELIMIT is returned.
+ * Errors: EINVAL (labels out of range, bad arguments), ENOMEM, EDEVICE.
+ */
+int louvain_resume(louvain_ctx ctx, louvain_graph g_level, const louvain_params *params,
+                   int32_t levels_done, int64_t n0, const int32_t *labels_so_far,
+                   int32_t *labels_out, louvain_i128 *q_int, double *q,
+                   louvain_run_stats *stats, uint32_t flags);
+
 /* ---- launch shapes -------------------------------------------------------- */
 
 /* Launch-shape settings of levels whose 2W is below 2^31.  They change which

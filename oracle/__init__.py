@@ -200,3 +200,49 @@ def louvain(row_ptr, col, w, theta_num: int = 1, theta_den: int = 1_000_000,
                sweeps_accepted=s.sweeps_accepted, q_int=i128_from_pair(np.array(s.q_int[:])))
           for s in stats[:levels.value]]
     return RunResult(lab[:n], i128_from_pair(q2), q.value, lv, rc)
+
+
+class Dendro(NamedTuple):
+    maps: list         # map l (int32[n_l]): vertex of level l's graph -> vertex of level l+1's
+    graphs: list       # (row_ptr, col, w int64) of levels 0 .. len(maps)
+    labels: np.ndarray # int32[n] composition of the maps
+    q_int: int         # Q_int of labels on the input graph
+    levels: list       # per-phase records, as louvain()'s
+    status: int        # ORC_OK or ORC_ELIMIT
+
+
+def dendrogram(row_ptr, col, w, theta_num: int = 1, theta_den: int = 1_000_000,
+               max_sweeps: int = 1000, max_levels: int = 64, singlet_rule: bool = True) -> Dendro:
+    """Alg. 2 taken level by level, keeping every level of the dendrogram:
+    a phase (Alg. 1 from singletons on the level's graph) and its
+    renumbering give the level's map; the graph rebuilt from that map is the
+    next level's graph.  The last graph is the one a further phase would run
+    on: the graph of the phase that kept no sweep, or the contraction by the
+    last map when max_levels cuts the run short."""
+    n, rp, cl, wt = _csr(row_ptr, col, w)
+    graphs = [(rp, cl, wt)]
+    maps, levels = [], []
+    lab = np.arange(n, dtype=np.int32)
+    status = ORC_OK
+    _, tw = degrees(rp, cl, wt)
+    q_int = modularity(rp, cl, wt, lab)[0] if tw > 0 else 0
+    while tw > 0 and len(levels) < max_levels:
+        g = graphs[-1]
+        # one phase and its renumbering: louvain() cut after one level
+        r = louvain(*g, theta_num=theta_num, theta_den=theta_den, max_sweeps=max_sweeps, max_levels=1,
+                    singlet_rule=singlet_rule)
+        rec = r.levels[0]
+        levels.append(rec)
+        if rec["sweeps_accepted"] >= max_sweeps:
+            status = ORC_ELIMIT
+        q_int = rec["q_int"]
+        if rec["sweeps_accepted"] == 0:
+            break
+        m = r.labels
+        k = int(m.max()) + 1 if m.shape[0] else 0
+        maps.append(m)
+        lab = m[lab]
+        graphs.append(contract(*g, m, k))
+        if len(levels) >= max_levels:
+            status = ORC_ELIMIT
+    return Dendro(maps, graphs, lab, q_int, levels, status)

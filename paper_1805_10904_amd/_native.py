@@ -29,6 +29,8 @@ ABI_SYMBOLS = (
     "louvain_local_move", "louvain_modularity", "louvain_aggregate", "louvain_run", "louvain_run_batch",
     "louvain_workspace_bytes", "louvain_serve_budget", "louvain_submit", "louvain_poll",
     "louvain_set_tuning", "louvain_get_tuning", "louvain_autotune",
+    "louvain_run_dendro", "louvain_dendro_info", "louvain_dendro_map", "louvain_dendro_graph",
+    "louvain_dendro_destroy", "louvain_resume",
 )
 
 
@@ -116,6 +118,14 @@ def load_library(path: str = LIB_PATH):
     lib.louvain_serve_budget.argtypes = [p, C.c_size_t]
     lib.louvain_submit.argtypes = [p, i64, i64, p, p, p, C.POINTER(louvain_params), p, u32, C.POINTER(C.c_uint64)]
     lib.louvain_poll.argtypes = [p, C.c_uint64, C.c_int32, C.POINTER(louvain_request_result)]
+    lib.louvain_run_dendro.argtypes = [p, p, C.POINTER(louvain_params), p, C.POINTER(louvain_i128), p,
+                                       C.POINTER(louvain_run_stats), C.POINTER(p), u32]
+    lib.louvain_dendro_info.argtypes = [p, p, p]
+    lib.louvain_dendro_map.argtypes = [p, i32, p, u32]
+    lib.louvain_dendro_graph.argtypes = [p, C.POINTER(p)]
+    lib.louvain_dendro_destroy.argtypes = [p]
+    lib.louvain_resume.argtypes = [p, p, C.POINTER(louvain_params), i32, i64, p, p, C.POINTER(louvain_i128), p,
+                                   C.POINTER(louvain_run_stats), u32]
     for f in ABI_SYMBOLS:
         if f not in ("louvain_last_error", "louvain_workspace_bytes"):
             getattr(lib, f).restype = C.c_int
@@ -213,6 +223,46 @@ class Graph:
     def destroy(self):
         if self.h:
             self.ctx.lib.louvain_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+class Dendrogram:
+    """A run's dendrogram (louvain_dendro): the map of every level and the
+    graph a further phase would run on."""
+
+    def __init__(self, ctx: "Context", handle: C.c_void_p, device_kind: bool):
+        self.ctx = ctx
+        self.h = handle
+        self.dev = device_kind
+        levels = C.c_int32()
+        sizes = (C.c_int64 * 65)()
+        ctx._check(ctx.lib.louvain_dendro_info(self.h, C.byref(levels), sizes))
+        self.levels = levels.value
+        self.n = [sizes[i] for i in range(self.levels + 1)]
+
+    def map(self, level: int, device: Optional[bool] = None):
+        """Map `level`: int32[n[level]], vertex -> vertex of the next level's graph."""
+        dev = self.dev if device is None else device
+        out = _empty_like_kind(dev, self.n[level] if 0 <= level < self.levels else 0, np.int32,
+                               self.ctx.torch_device)
+        self.ctx._check(self.ctx.lib.louvain_dendro_map(self.h, level, _ptr(out), LOUVAIN_DEVICE_PTRS if dev else 0))
+        return out
+
+    def graph(self) -> "Graph":
+        """The last level's graph (once; the caller owns it)."""
+        h = C.c_void_p()
+        self.ctx._check(self.ctx.lib.louvain_dendro_graph(self.h, C.byref(h)))
+        return Graph(self.ctx, h, self.dev)
+
+    def destroy(self):
+        if self.h:
+            self.ctx.lib.louvain_dendro_destroy(self.h)
             self.h = None
 
     def __del__(self):
@@ -395,28 +445,61 @@ class Context:
                                                LOUVAIN_DEVICE_PTRS if dev else 0))
         return Graph(self, h, dev), ren
 
-    def run(self, g: Graph, theta_num: int = 1, theta_den: int = 1_000_000, max_sweeps: int = 1000,
-            max_levels: int = 64, singlet_rule: bool = True, pass_batch: int = 0, timing=False,
-            device: Optional[bool] = None, labels_out=None) -> RunResult:
-        """The whole method (Alg. 2 over Alg. 1 phases).
-
-        timing: False, True (device time of every launch, from HIP events
-        filled by the dispatches) or a kernel name as it appears in
-        stats["kernels"] (only its launches are timed)."""
-        dev = g.dev if device is None else device
-        n, _, _ = g.info()
-        out = labels_out if labels_out is not None else _empty_like_kind(dev, n, np.int32, self.torch_device)
-        prm = louvain_params(theta_num, theta_den, max_sweeps, max_levels, 1 if singlet_rule else 0, pass_batch)
-        qi = louvain_i128()
-        q = C.c_double()
+    @staticmethod
+    def _timing_stats(timing) -> louvain_run_stats:
         st = louvain_run_stats()
         if isinstance(timing, str):
             st.timing = 2
             st.timing_only = timing.encode()[:39]
         else:
             st.timing = 1 if timing else 0
+        return st
+
+    def run(self, g: Graph, theta_num: int = 1, theta_den: int = 1_000_000, max_sweeps: int = 1000,
+            max_levels: int = 64, singlet_rule: bool = True, pass_batch: int = 0, timing=False,
+            device: Optional[bool] = None, labels_out=None, dendrogram: bool = False):
+        """The whole method (Alg. 2 over Alg. 1 phases).
+
+        timing: False, True (device time of every launch, from HIP events
+        filled by the dispatches) or a kernel name as it appears in
+        stats["kernels"] (only its launches are timed).
+        dendrogram: also keep the per-level maps and the last level's graph;
+        returns (RunResult, Dendrogram) then."""
+        dev = g.dev if device is None else device
+        n, _, _ = g.info()
+        out = labels_out if labels_out is not None else _empty_like_kind(dev, n, np.int32, self.torch_device)
+        prm = louvain_params(theta_num, theta_den, max_sweeps, max_levels, 1 if singlet_rule else 0, pass_batch)
+        qi = louvain_i128()
+        q = C.c_double()
+        st = self._timing_stats(timing)
+        flags = LOUVAIN_DEVICE_PTRS if dev else 0
+        if dendrogram:
+            h = C.c_void_p()
+            rc = self._check(self.lib.louvain_run_dendro(self.h, g.h, C.byref(prm), _ptr(out), C.byref(qi),
+                                                         C.byref(q), C.byref(st), C.byref(h), flags),
+                             ok=(LOUVAIN_OK, LOUVAIN_ELIMIT))
+            return RunResult(out, qi.value(), q.value, rc, stats_dict(st)), Dendrogram(self, h, dev)
         rc = self._check(self.lib.louvain_run(self.h, g.h, C.byref(prm), _ptr(out), C.byref(qi), C.byref(q),
-                                              C.byref(st), LOUVAIN_DEVICE_PTRS if dev else 0),
+                                              C.byref(st), flags),
+                         ok=(LOUVAIN_OK, LOUVAIN_ELIMIT))
+        return RunResult(out, qi.value(), q.value, rc, stats_dict(st))
+
+    def resume(self, g_level: Graph, levels_done: int, labels_so_far, theta_num: int = 1,
+               theta_den: int = 1_000_000, max_sweeps: int = 1000, max_levels: int = 64, singlet_rule: bool = True,
+               pass_batch: int = 0, timing=False, device: Optional[bool] = None) -> RunResult:
+        """Continue a run from the graph of level `levels_done` and the labels
+        so far (one per original vertex); the result equals one run's."""
+        dev = g_level.dev if device is None else device
+        lab = self._labels(labels_so_far, dev)
+        n0 = int(lab.shape[0])
+        out = _empty_like_kind(dev, n0, np.int32, self.torch_device)
+        prm = louvain_params(theta_num, theta_den, max_sweeps, max_levels, 1 if singlet_rule else 0, pass_batch)
+        qi = louvain_i128()
+        q = C.c_double()
+        st = self._timing_stats(timing)
+        rc = self._check(self.lib.louvain_resume(self.h, g_level.h, C.byref(prm), levels_done, n0, _ptr(lab),
+                                                 _ptr(out), C.byref(qi), C.byref(q), C.byref(st),
+                                                 LOUVAIN_DEVICE_PTRS if dev else 0),
                          ok=(LOUVAIN_OK, LOUVAIN_ELIMIT))
         return RunResult(out, qi.value(), q.value, rc, stats_dict(st))
 

@@ -51,6 +51,17 @@ struct louvain_graph_s {
     }
 };
 
+// A run's dendrogram: the renumbering map of every level and the graph of
+// the last level (until handed to the caller).
+struct louvain_dendro_s {
+    std::shared_ptr<lv::Pool> pool;   // keeps the blocks' pool alive; destroyed last
+    louvain_ctx ctx = nullptr;
+    int device = 0;
+    std::vector<lv::DevBuf<int32_t>> maps;    // maps[l]: n[l] entries
+    std::vector<int64_t> n;                   // vertices of level l's graph, l = 0..levels
+    std::unique_ptr<louvain_graph_s> graph;   // the last level's graph
+};
+
 namespace {
 
 using lv::DevBuf;
@@ -105,9 +116,9 @@ void copy_out(T *dst, const T *src, int64_t count, bool dev, hipStream_t s) {
                           dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
 }
 
-__global__ void k_label_range(const int32_t *__restrict__ lab, int64_t n, int *bad) {
+__global__ void k_label_range(const int32_t *__restrict__ lab, int64_t n, int64_t bound, int *bad) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && (lab[i] < 0 || (int64_t)lab[i] >= n)) atomicOr(bad, 1);
+    if (i < n && (lab[i] < 0 || (int64_t)lab[i] >= bound)) atomicOr(bad, 1);
 }
 
 __global__ void k_widen(const int32_t *__restrict__ in, int64_t *out, int64_t m) {
@@ -115,23 +126,61 @@ __global__ void k_widen(const int32_t *__restrict__ in, int64_t *out, int64_t m)
     if (i < m) out[i] = in[i];
 }
 
-// Labels from the caller, copied to the device and range-checked.
-DevBuf<int32_t> labels_in(louvain_ctx ctx, const int32_t *labels, int64_t n, uint32_t flags) {
+// Labels from the caller, copied to the device and checked to lie in
+// [0, bound) (bound < 0: [0, n)).
+DevBuf<int32_t> labels_in(louvain_ctx ctx, const int32_t *labels, int64_t n, uint32_t flags, int64_t bound = -1) {
+    if (bound < 0) bound = n;
     require(labels != nullptr || n == 0, LOUVAIN_EINVAL, "labels must not be NULL");
     DevBuf<int32_t> d((size_t)n);
     copy_in(d.p, labels, n, device_ptrs(flags), ctx->stream);
     if (n > 0) {
         lv::TempBuf bad(sizeof(int), ctx->stream);
         LV_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), ctx->stream));
-        k_label_range<<<lv::grid_for(n, 256), 256, 0, ctx->stream>>>(d.p, n, bad.as<int>());
+        k_label_range<<<lv::grid_for(n, 256), 256, 0, ctx->stream>>>(d.p, n, bound, bad.as<int>());
         LV_LAUNCHED("k_label_range");
         lv::Readback rb(ctx->stream);
         const int *h = rb.add(bad.as<int>());
         rb.fetch();
-        require(*h == 0, LOUVAIN_EINVAL, "label out of range [0, n)");
+        require(*h == 0, LOUVAIN_EINVAL, "label out of range [0, " + std::to_string(bound) + ")");
     }
     return d;
 }
+
+// Device copy of a graph view as a new handle of ctx.
+std::unique_ptr<louvain_graph_s> copy_graph(louvain_ctx ctx, const lv::GraphView &v, hipStream_t s) {
+    std::unique_ptr<louvain_graph_s> g(new louvain_graph_s());
+    g->ctx = ctx;
+    g->pool = ctx->pool;
+    g->device = ctx->device;
+    g->n = v.n;
+    g->nnz = v.nnz;
+    g->tw = v.tw;
+    g->wbytes = v.wbytes;
+    g->row_ptr.alloc((size_t)v.n + 1);
+    g->col.alloc((size_t)v.nnz);
+    if (v.wbytes == 4) g->w32.alloc((size_t)v.nnz); else g->w64.alloc((size_t)v.nnz);
+    g->delta.alloc((size_t)v.n);
+    copy_in(g->row_ptr.p, v.row_ptr, v.n + 1, true, s);
+    copy_in(g->col.p, v.col, v.nnz, true, s);
+    if (v.wbytes == 4)
+        copy_in(g->w32.p, (const int32_t *)v.w, v.nnz, true, s);
+    else
+        copy_in(g->w64.p, (const int64_t *)v.w, v.nnz, true, s);
+    copy_in(g->delta.p, v.delta, v.n, true, s);
+    return g;
+}
+
+// Collects a run's dendrogram (the per-level maps, the last level's graph).
+struct DendroSink final : lv::LevelSink {
+    louvain_dendro_s *d;
+    explicit DendroSink(louvain_dendro_s *dd) : d(dd) {}
+    void map(const int32_t *newlab, int64_t n, int64_t k, hipStream_t s) override {
+        d->maps.emplace_back((size_t)n);
+        copy_in(d->maps.back().p, newlab, n, true, s);
+        d->n.push_back(k);
+    }
+    void last(const lv::GraphView &v, hipStream_t s) override { d->graph = copy_graph(d->ctx, v, s); }
+};
 
 louvain_i128 to_abi(lv::i128 v) {
     louvain_i128 r;
@@ -216,7 +265,7 @@ namespace lv {
 // Alg. 2 on one graph: phases of sweeps, renumbering and contraction until a
 // phase keeps no sweep.  fin_p (device int32[n]) receives the final labels.
 int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, hipStream_t s, Timer &timer,
-              int timing, int32_t *fin_p, i128 *q_out, louvain_run_stats *stats_out) {
+              int timing, int32_t *fin_p, i128 *q_out, louvain_run_stats *stats_out, LevelSink *sink) {
     int status = LOUVAIN_OK;
     const int batch = prm.pass_batch > 0 ? prm.pass_batch : tn.pass_batch;
     timer.on = timing != 0;
@@ -293,7 +342,9 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
             const int32_t *cfin = sw.slot(st.final_slot);
             const int64_t k = ct.renumber(cfin, v.n, newlab.p);
             ct.compose(fin_p, n0, newlab.p);
-            if (level + 1 >= prm.max_levels) {
+            if (sink) sink->map(newlab.p, v.n, k, s);
+            const bool cut = level + 1 >= prm.max_levels;
+            if (cut && !sink) {
                 status = LOUVAIN_ELIMIT;
                 if (timing == 1) {
                     LV_HIP(hipStreamSynchronize(s));
@@ -312,8 +363,8 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
                 nb.col.alloc((size_t)nnz0);
             }
             void *wout = narrow ? (void *)nb.w32.p : (void *)nb.w64.p;
-            const int64_t m2 = ct.contract(v, newlab.p, k, nb.rp.p, nb.col.p, wout, narrow ? 4 : 8, nb.delta.p, false,
-                                           lv::lds_row_max(k, g0.tw, tn));
+            const int64_t m2 = ct.contract(v, newlab.p, k, nb.rp.p, nb.col.p, wout, narrow ? 4 : 8, nb.delta.p,
+                                           sink != nullptr, lv::lds_row_max(k, g0.tw, tn));
             lv::GraphView v2;
             v2.n = k;
             v2.nnz = m2;
@@ -329,7 +380,14 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
                 LV_HIP(hipStreamSynchronize(s));
                 collect_kernel_stats(timer, nullptr, rec0, timer.recs.size(), &ls.ms_sweep, &ls.ms_contract);
             }
+            if (cut) {
+                status = LOUVAIN_ELIMIT;
+                break;
+            }
         }
+        if (sink) sink->last(v, s);
+    } else if (sink) {
+        sink->last(v, s);
     }
     local.status = status;
     if (timing) {
@@ -347,6 +405,69 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
 }
 
 }  // namespace lv
+
+namespace {
+
+// Timing request of a stats record, installed on the context's timer.
+int timing_of(louvain_ctx ctx, const louvain_run_stats *stats) {
+    const int timing = stats ? stats->timing : 0;
+    require(timing >= 0 && timing <= 2, LOUVAIN_EINVAL, "stats->timing must be 0, 1 or 2");
+    if (timing == 2) {
+        char only[sizeof stats->timing_only + 1];
+        memcpy(only, stats->timing_only, sizeof stats->timing_only);
+        only[sizeof stats->timing_only] = 0;
+        ctx->timer.only = only;
+    }
+    return timing;
+}
+
+void stats_out(louvain_run_stats *stats, louvain_run_stats &local) {
+    if (!stats) return;
+    local.timing = stats->timing;
+    memcpy(local.timing_only, stats->timing_only, sizeof local.timing_only);
+    *stats = local;
+}
+
+// louvain_run, keeping the dendrogram when dendro_out is set.
+int run_graph(louvain_ctx ctx, louvain_graph g, const louvain_params *params, int32_t *labels_out,
+              louvain_i128 *q_int, double *q, louvain_run_stats *stats, louvain_dendro *dendro_out, uint32_t flags) {
+    int status = LOUVAIN_OK;
+    const int rc = guarded(ctx, [&] {
+        require(g != nullptr && g->ctx == ctx, LOUVAIN_EINVAL, "graph missing or from another context");
+        require(labels_out != nullptr || g->n == 0, LOUVAIN_EINVAL, "labels_out must not be NULL");
+        const louvain_params prm = checked_params(params);
+        hipStream_t s = ctx->stream;
+        const int timing = timing_of(ctx, stats);
+        std::unique_ptr<louvain_dendro_s> d;
+        std::unique_ptr<DendroSink> sink;
+        if (dendro_out) {
+            d.reset(new louvain_dendro_s());
+            d->pool = ctx->pool;
+            d->ctx = ctx;
+            d->device = ctx->device;
+            d->n.push_back(g->n);
+            sink.reset(new DendroSink(d.get()));
+        }
+        louvain_run_stats local;
+        DevBuf<int32_t> fin((size_t)g->n);
+        lv::i128 q_final = 0;
+        status = lv::run_plain(g->view(), prm, ctx->tuning, s, ctx->timer, timing, fin.p, &q_final, &local,
+                               sink.get());
+        copy_out(labels_out, fin.p, g->n, device_ptrs(flags), s);
+        LV_HIP(hipStreamSynchronize(s));
+        if (q_int) *q_int = to_abi(q_final);
+        if (q) *q = q_of(q_final, g->tw);
+        stats_out(stats, local);
+        if (dendro_out) *dendro_out = d.release();
+    });
+    if (ctx) {
+        ctx->timer.on = false;
+        ctx->timer.only.clear();
+    }
+    return rc != LOUVAIN_OK ? rc : status;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -527,33 +648,93 @@ int louvain_aggregate(louvain_ctx ctx, louvain_graph g, const int32_t *labels, i
 
 int louvain_run(louvain_ctx ctx, louvain_graph g, const louvain_params *params, int32_t *labels_out,
                 louvain_i128 *q_int, double *q, louvain_run_stats *stats, uint32_t flags) {
+    return run_graph(ctx, g, params, labels_out, q_int, q, stats, nullptr, flags);
+}
+
+int louvain_run_dendro(louvain_ctx ctx, louvain_graph g, const louvain_params *params, int32_t *labels_out,
+                       louvain_i128 *q_int, double *q, louvain_run_stats *stats, louvain_dendro *dendro_out,
+                       uint32_t flags) {
+    if (!dendro_out) {
+        if (ctx) ctx->err = "dendro_out must not be NULL";
+        return LOUVAIN_EINVAL;
+    }
+    return run_graph(ctx, g, params, labels_out, q_int, q, stats, dendro_out, flags);
+}
+
+int louvain_dendro_info(louvain_dendro d, int32_t *levels, int64_t *n) {
+    if (!d) return LOUVAIN_EINVAL;
+    if (levels) *levels = (int32_t)d->maps.size();
+    if (n)
+        for (size_t l = 0; l < d->n.size(); ++l) n[l] = d->n[l];
+    return LOUVAIN_OK;
+}
+
+int louvain_dendro_map(louvain_dendro d, int32_t level, int32_t *map_out, uint32_t flags) {
+    if (!d) return LOUVAIN_EINVAL;
+    louvain_ctx ctx = d->ctx;
+    return guarded(ctx, [&] {
+        require(level >= 0 && (size_t)level < d->maps.size(), LOUVAIN_EINVAL, "no such dendrogram level");
+        const int64_t n = d->n[(size_t)level];
+        require(map_out != nullptr || n == 0, LOUVAIN_EINVAL, "map_out must not be NULL");
+        copy_out(map_out, d->maps[(size_t)level].p, n, device_ptrs(flags), ctx->stream);
+        LV_HIP(hipStreamSynchronize(ctx->stream));
+    });
+}
+
+int louvain_dendro_graph(louvain_dendro d, louvain_graph *out) {
+    if (!d) return LOUVAIN_EINVAL;
+    return guarded(d->ctx, [&] {
+        require(out != nullptr, LOUVAIN_EINVAL, "out must not be NULL");
+        require(d->graph != nullptr, LOUVAIN_EINVAL, "the dendrogram's graph was already handed out");
+        *out = d->graph.release();
+    });
+}
+
+int louvain_dendro_destroy(louvain_dendro d) {
+    if (!d) return LOUVAIN_EINVAL;
+    (void)hipSetDevice(d->device);
+    delete d;
+    return LOUVAIN_OK;
+}
+
+int louvain_resume(louvain_ctx ctx, louvain_graph g, const louvain_params *params, int32_t levels_done, int64_t n0,
+                   const int32_t *labels_so_far, int32_t *labels_out, louvain_i128 *q_int, double *q,
+                   louvain_run_stats *stats, uint32_t flags) {
     int status = LOUVAIN_OK;
     const int rc = guarded(ctx, [&] {
         require(g != nullptr && g->ctx == ctx, LOUVAIN_EINVAL, "graph missing or from another context");
-        require(labels_out != nullptr || g->n == 0, LOUVAIN_EINVAL, "labels_out must not be NULL");
-        const louvain_params prm = checked_params(params);
+        require(n0 >= 0 && n0 < ((int64_t)1 << 31), LOUVAIN_EINVAL, "n0 must be in [0, 2^31)");
+        require(labels_out != nullptr || n0 == 0, LOUVAIN_EINVAL, "labels_out must not be NULL");
+        require(levels_done >= 0, LOUVAIN_EINVAL, "levels_done must be >= 0");
+        louvain_params prm = checked_params(params);
         hipStream_t s = ctx->stream;
-        const int timing = stats ? stats->timing : 0;
-        require(timing >= 0 && timing <= 2, LOUVAIN_EINVAL, "stats->timing must be 0, 1 or 2");
-        if (timing == 2) {
-            char only[sizeof stats->timing_only + 1];
-            memcpy(only, stats->timing_only, sizeof stats->timing_only);
-            only[sizeof stats->timing_only] = 0;
-            ctx->timer.only = only;
-        }
+        const int timing = timing_of(ctx, stats);
+        lv::Timer *t = timing ? &ctx->timer : nullptr;
+        DevBuf<int32_t> fin = labels_in(ctx, labels_so_far, n0, flags, g->n);
         louvain_run_stats local;
-        DevBuf<int32_t> fin((size_t)g->n);
+        memset(&local, 0, sizeof local);
         lv::i128 q_final = 0;
-        status = lv::run_plain(g->view(), prm, ctx->tuning, s, ctx->timer, timing, fin.p, &q_final, &local);
-        copy_out(labels_out, fin.p, g->n, device_ptrs(flags), s);
+        if (levels_done >= prm.max_levels) {
+            // no phase left: the partition so far, whose Q_int on g is that of g's singletons
+            status = LOUVAIN_ELIMIT;
+            local.status = status;
+            if (g->tw > 0) {
+                DevBuf<int32_t> iota((size_t)g->n);
+                lv::iota_i32(iota.p, g->n, s);
+                q_final = lv::modularity_int(g->view(), iota.p, s, nullptr);
+            }
+        } else {
+            prm.max_levels -= levels_done;
+            DevBuf<int32_t> lvl((size_t)g->n);
+            status = lv::run_plain(g->view(), prm, ctx->tuning, s, ctx->timer, timing, lvl.p, &q_final, &local);
+            lv::Contractor ct(s, t);
+            ct.compose(fin.p, n0, lvl.p);
+        }
+        copy_out(labels_out, fin.p, n0, device_ptrs(flags), s);
         LV_HIP(hipStreamSynchronize(s));
         if (q_int) *q_int = to_abi(q_final);
         if (q) *q = q_of(q_final, g->tw);
-        if (stats) {
-            local.timing = stats->timing;
-            memcpy(local.timing_only, stats->timing_only, sizeof local.timing_only);
-            *stats = local;
-        }
+        stats_out(stats, local);
     });
     if (ctx) {
         ctx->timer.on = false;

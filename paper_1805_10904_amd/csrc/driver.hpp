@@ -7,13 +7,29 @@
 
 namespace lv {
 
+// Receiver of a run's dendrogram.  With a sink the run contracts into the
+// canonical form (ascending columns), and a run cut by max_levels still
+// contracts its last phase, so that the graph handed to last() is the one
+// the next phase would run on.
+struct LevelSink {
+    virtual ~LevelSink() = default;
+    // One level: newlab (device int32[n], valid during the call) sends every
+    // vertex of the level's graph to its vertex in the next level's graph,
+    // which has k vertices.
+    virtual void map(const int32_t *newlab, int64_t n, int64_t k, hipStream_t s) = 0;
+    // The graph of the last level (device arrays valid during the call).
+    virtual void last(const GraphView &v, hipStream_t s) = 0;
+};
+
 // Phases of sweeps, renumbering and contraction on g0 until a phase keeps no
 // sweep or a cap is reached.  fin_p (device int32[g0.n]) receives the final
 // labels, *q_out Q_int of them, *stats_out the run record (kernel times when
 // timing).  Returns LOUVAIN_OK or LOUVAIN_ELIMIT; throws Error.
 // timing: 0 off, 1 every launch, 2 only launches named timer.only.
 // tn: launch shapes of compact levels (prm.pass_batch 0 takes tn.pass_batch).
+// sink (optional) receives the dendrogram: see LevelSink.
 int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, hipStream_t s, Timer &timer,
-              int timing, int32_t *fin_p, i128 *q_out, louvain_run_stats *stats_out);
+              int timing, int32_t *fin_p, i128 *q_out, louvain_run_stats *stats_out,
+              struct LevelSink *sink = nullptr);
 
 }  // namespace lv

@@ -20,7 +20,6 @@ struct GraphView {
     int64_t tw = 0;
 };
 
-// Device-resident control block of one phase.
 // Device-resident control block of one phase of one graph.
 struct PhaseState {
     unsigned long long acc_I;   // sum of e_{i->c_i} (loops included) of the labelling read by the pass

@@ -277,3 +277,78 @@ def test_sweeps_strictly_increase_q():
     assert r.levels[0]["sweeps_accepted"] == kept
     assert r.labels.tolist() == oracle.renumber(lab)[0][lab].tolist()
     assert r.status == oracle.ORC_ELIMIT
+
+
+# --- the dendrogram and resuming a run from a level state ---------------------
+
+def _dendro_cases():
+    out = [gg.config("sbm1k")]
+    for s in range(6):
+        out.append(gg.random_small(9 + s, 0.35, 5, seed=900 + s, loop_prob=0.2 if s % 2 else 0.0,
+                                   isolated=1 if s == 3 else 0))
+    return out
+
+
+def _compose(maps, n):
+    lab = np.arange(n, dtype=np.int32)
+    for m in maps:
+        lab = m[lab]
+    return lab
+
+
+@pytest.mark.parametrize("g", _dendro_cases(), ids=lambda g: f"n{g.n}m{g.nnz}")
+def test_dendrogram_levels_and_resume(g):
+    r = oracle.louvain(g.row_ptr, g.col, g.w)
+    d = oracle.dendrogram(g.row_ptr, g.col, g.w)
+    # the level-by-level form is the whole run: same labels, Q and records
+    assert np.array_equal(d.labels, r.labels) and np.array_equal(_compose(d.maps, g.n), r.labels)
+    assert d.q_int == r.q_int and d.levels == r.levels and d.status == r.status
+    assert len(d.graphs) == len(d.maps) + 1
+    _, tw = oracle.degrees(g.row_ptr, g.col, g.w)
+    for lvl, m in enumerate(d.maps):
+        rp, cl, w = d.graphs[lvl]
+        n_l = rp.shape[0] - 1
+        k = d.graphs[lvl + 1][0].shape[0] - 1
+        # a map is dense: onto [0, k)
+        assert m.shape[0] == n_l and sorted(set(m.tolist())) == list(range(k))
+        # the next level's graph is P^T A P of this one, stored with ascending columns
+        M = contract_dense(dense(rp, cl, w, n_l), m.tolist(), k)
+        rp2, cl2, w2 = d.graphs[lvl + 1]
+        got = np.zeros((k, k), np.int64)
+        for a in range(k):
+            seg = cl2[rp2[a]:rp2[a + 1]]
+            assert np.all(np.diff(seg) > 0)
+            got[a, seg] = w2[rp2[a]:rp2[a + 1]]
+        assert np.array_equal(got, M)
+        assert oracle.degrees(rp2, cl2, w2)[1] == tw
+    # the last graph carries the result: its singletons have the run's Q, and a
+    # phase on it keeps no sweep
+    last = d.graphs[-1]
+    kl = last[0].shape[0] - 1
+    if tw > 0:
+        assert oracle.modularity(*last, np.arange(kl, dtype=np.int32))[0] == r.q_int
+        assert oracle.louvain(*last).labels.tolist() == list(range(kl))
+    # resuming from every level state gives the whole run's result, also under a level cap
+    for cap in (64, len(d.maps) + 1, max(1, len(d.maps))):
+        full = oracle.louvain(g.row_ptr, g.col, g.w, max_levels=cap)
+        for lvl in range(min(len(d.maps), cap) + 1):
+            part = oracle.dendrogram(g.row_ptr, g.col, g.w, max_levels=lvl) if lvl else None
+            so_far = part.labels if part else np.arange(g.n, dtype=np.int32)
+            if part:
+                assert [m.tolist() for m in part.maps] == [m.tolist() for m in d.maps[:lvl]]
+                assert all(np.array_equal(x, y) for x, y in zip(part.graphs[-1], d.graphs[lvl]))
+            if lvl >= cap:
+                continue
+            rest = oracle.louvain(*d.graphs[lvl], max_levels=cap - lvl)
+            assert np.array_equal(rest.labels[so_far], full.labels)
+            assert rest.q_int == full.q_int
+
+
+def test_dendrogram_worked_example():
+    ex = {e["name"]: e for e in _examples()}["two_triangles_bridge"]
+    g = gg.from_edge_list(ex["n"], ex["edges"])
+    d = oracle.dendrogram(g.row_ptr, g.col, g.w)
+    assert [m.tolist() for m in d.maps] == [ex["final_labels"]]
+    c = ex["contracted"]
+    rp2, cl2, w2 = d.graphs[1]
+    assert rp2.tolist() == c["row_ptr"] and cl2.tolist() == c["col"] and w2.tolist() == c["w"]
