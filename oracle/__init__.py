@@ -59,8 +59,9 @@ def _load():
         lib.orc_renumber.restype = i64
         lib.orc_contract.argtypes = [i64, p, p, p, p, i64, p, p, p]
         lib.orc_contract.restype = i64
-        lib.orc_louvain.argtypes = [i64, p, p, p, i64, i64, C.c_int32, C.c_int32, C.c_int,
+        lib.orc_louvain.argtypes = [i64, p, p, p, i64, i64, C.c_int32, C.c_int32, C.c_int, C.c_int,
                                     p, p, p, p, p]
+        lib.orc_merge.argtypes = [i64, p, p, p, p, C.c_int, p]
         _lib = lib
     return _lib
 
@@ -182,9 +183,24 @@ class RunResult(NamedTuple):
     status: int            # ORC_OK or ORC_ELIMIT
 
 
+def merge(row_ptr, col, w, labels, singlet_rule: bool = True) -> np.ndarray:
+    """The final merge of a phase alone (Section 5.1): vertices alone in
+    their community whose neighbours all carry one label join it when that
+    beats staying (as a sweep decides, singlet rule included)."""
+    n, rp, cl, wt = _csr(row_ptr, col, w)
+    lab = np.ascontiguousarray(labels, dtype=np.int32)
+    out = np.zeros(max(n, 1), np.int32)
+    rc = _load().orc_merge(n, _ptr(rp), _ptr(cl), _ptr(wt), _ptr(lab), int(bool(singlet_rule)), _ptr(out))
+    if rc != ORC_OK:
+        raise ValueError(f"orc_merge failed ({rc})")
+    return out[:n]
+
+
 def louvain(row_ptr, col, w, theta_num: int = 1, theta_den: int = 1_000_000,
-            max_sweeps: int = 1000, max_levels: int = 64, singlet_rule: bool = True) -> RunResult:
-    """The whole method (Alg. 2 over Alg. 1 phases), single-threaded."""
+            max_sweeps: int = 1000, max_levels: int = 64, singlet_rule: bool = True,
+            merge: bool = False) -> RunResult:
+    """The whole method (Alg. 2 over Alg. 1 phases), single-threaded; merge:
+    apply the final merge after every phase that kept a sweep."""
     n, rp, cl, wt = _csr(row_ptr, col, w)
     lab = np.zeros(max(n, 1), np.int32)
     q2 = np.zeros(2, np.int64)
@@ -192,7 +208,7 @@ def louvain(row_ptr, col, w, theta_num: int = 1, theta_den: int = 1_000_000,
     stats = (_LevelStats * max(1, max_levels))()
     levels = C.c_int32(0)
     rc = _load().orc_louvain(n, _ptr(rp), _ptr(cl), _ptr(wt), theta_num, theta_den,
-                             max_sweeps, max_levels, int(bool(singlet_rule)), _ptr(lab),
+                             max_sweeps, max_levels, int(bool(singlet_rule)), int(bool(merge)), _ptr(lab),
                              _ptr(q2), C.byref(q), C.cast(stats, C.c_void_p), C.byref(levels))
     if rc not in (ORC_OK, ORC_ELIMIT):
         raise RuntimeError(f"orc_louvain failed ({rc})")
@@ -212,7 +228,8 @@ class Dendro(NamedTuple):
 
 
 def dendrogram(row_ptr, col, w, theta_num: int = 1, theta_den: int = 1_000_000,
-               max_sweeps: int = 1000, max_levels: int = 64, singlet_rule: bool = True) -> Dendro:
+               max_sweeps: int = 1000, max_levels: int = 64, singlet_rule: bool = True,
+               merge: bool = False) -> Dendro:
     """Alg. 2 taken level by level, keeping every level of the dendrogram:
     a phase (Alg. 1 from singletons on the level's graph) and its
     renumbering give the level's map; the graph rebuilt from that map is the
@@ -230,7 +247,7 @@ def dendrogram(row_ptr, col, w, theta_num: int = 1, theta_den: int = 1_000_000,
         g = graphs[-1]
         # one phase and its renumbering: louvain() cut after one level
         r = louvain(*g, theta_num=theta_num, theta_den=theta_den, max_sweeps=max_sweeps, max_levels=1,
-                    singlet_rule=singlet_rule)
+                    singlet_rule=singlet_rule, merge=merge)
         rec = r.levels[0]
         levels.append(rec)
         if rec["sweeps_accepted"] >= max_sweeps:

@@ -33,6 +33,14 @@
  *     previous sweep's labels, degrees and sizes.  A sweep is kept iff
  *     theta_den * (Q_new - Q_prev) > theta_num * |Q_prev| (exact); otherwise
  *     it is discarded and the phase ends.
+ *   - Final merge (optional; Section 5.1, end of "Generating one level":
+ *     after the last iteration, vertices with a single neighbouring
+ *     community are pushed into it).  Read here as one more synchronous
+ *     decision, made from the phase's final labels, for vertices alone in
+ *     their community whose neighbours (loops aside) all carry one label C:
+ *     such a vertex joins C iff s(C) beats s_own strictly and the singlet
+ *     rule allows it, as in a sweep.  It is applied without the acceptance
+ *     test, only after a phase that kept a sweep, and Q is recomputed.
  *   - Phases (Alg. 2): after a phase that kept at least one sweep, the
  *     labels are renumbered densely in ascending label order and the graph
  *     is contracted: A'_ab = sum of A_ij over i in a, j in b (a loop of a
@@ -198,6 +206,46 @@ static void sweep(int64_t n, const int64_t *row_ptr, const int32_t *col, const i
     }
 }
 
+/* The final merge (see the conventions above): from the snapshot (c, degc,
+ * size), a vertex alone in its community whose neighbours other than
+ * itself all carry one label C moves to C iff TW * e_{i->C} - delta_i *
+ * deg_C beats its own score (zero for a vertex alone) and the singlet rule
+ * allows it; every other vertex keeps its label.  Writes c_out. */
+static void merge_one_neighbour(int64_t n, const int64_t *row_ptr, const int32_t *col, const int64_t *w,
+                                const int64_t *delta, int64_t tw, const int32_t *c, const int64_t *degc,
+                                const int32_t *size, int singlet_rule, int32_t *c_out)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t ci = c[i];
+        c_out[i] = ci;
+        if (size[ci] != 1)
+            continue;
+        int32_t target = -1;
+        int single = 1;
+        int64_t e_target = 0;
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            int32_t j = col[e];
+            if (j == i)
+                continue;            /* loops take no part in moves */
+            if (target < 0)
+                target = c[j];
+            else if (c[j] != target)
+                single = 0;
+            e_target += w[e];
+        }
+        if (target < 0 || !single)
+            continue;
+        /* i is alone, so e_{i->C(i)\{i}} = 0 and deg_{C(i)} - delta_i = 0 */
+        i128 s_own = (i128)tw * 0 - (i128)delta[i] * (i128)(degc[ci] - delta[i]);
+        i128 s = (i128)tw * e_target - (i128)delta[i] * (i128)degc[target];
+        if (s <= s_own)
+            continue;
+        if (singlet_rule && size[target] == 1 && target > ci)
+            continue;                /* singlet minimum label heuristic */
+        c_out[i] = target;
+    }
+}
+
 /* deg_C (eq. 2) and community sizes of labelling c. */
 static void community_state(int64_t n, const int32_t *c, const int64_t *delta,
                             int64_t *degc, int32_t *size)
@@ -239,6 +287,27 @@ int orc_local_move(int64_t n, const int64_t *row_ptr, const int32_t *col, const 
     }
 out:
     free(delta); free(degc); free(acc); free(size); free(list); free(c);
+    return rc;
+}
+
+/* The final merge alone, from labels_in (in [0, n)): labels_out. */
+int orc_merge(int64_t n, const int64_t *row_ptr, const int32_t *col, const int64_t *w,
+              const int32_t *labels_in, int singlet_rule, int32_t *labels_out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (labels_in[i] < 0 || labels_in[i] >= n)
+            return ORC_EINVAL;
+    size_t nn = (size_t)(n ? n : 1);
+    int64_t *delta = malloc(sizeof(int64_t) * nn), *degc = malloc(sizeof(int64_t) * nn);
+    int32_t *size = malloc(sizeof(int32_t) * nn);
+    int rc = ORC_OK;
+    if (!delta || !degc || !size) { rc = ORC_ENOMEM; goto out; }
+    int64_t tw;
+    orc_degrees(n, row_ptr, w, delta, &tw);
+    community_state(n, labels_in, delta, degc, size);
+    merge_one_neighbour(n, row_ptr, col, w, delta, tw, labels_in, degc, size, singlet_rule, labels_out);
+out:
+    free(delta); free(degc); free(size);
     return rc;
 }
 
@@ -336,7 +405,7 @@ typedef struct {
  */
 int orc_louvain(int64_t n, const int64_t *row_ptr, const int32_t *col, const int64_t *w,
                 int64_t theta_num, int64_t theta_den, int32_t max_sweeps, int32_t max_levels,
-                int singlet_rule, int32_t *labels_out, int64_t q_int[2], double *q,
+                int singlet_rule, int merge, int32_t *labels_out, int64_t q_int[2], double *q,
                 orc_level_stats *stats, int32_t *levels_out)
 {
     size_t nn = (size_t)(n ? n : 1);
@@ -397,6 +466,13 @@ int orc_louvain(int64_t n, const int64_t *row_ptr, const int32_t *col, const int
             community_state(ln, c, delta, degc, size);
             q_prev = q_new;
             ++accepted;
+        }
+        if (merge && accepted > 0) {
+            /* the final merge on the phase's labels, then Q once more */
+            merge_one_neighbour(ln, rp, cl, wt, delta, tw, c, degc, size, singlet_rule, c_new);
+            memcpy(c, c_new, sizeof(int32_t) * (size_t)ln);
+            community_state(ln, c, delta, degc, size);
+            q_prev = modularity_int(ln, rp, cl, wt, c, delta, tw, qscratch);
         }
         if (stats) {
             stats[levels].n = ln;

@@ -114,3 +114,29 @@ def contract_dense(A, new_labels, k):
         P[i, a] = 1
     M = np.array(A, dtype=np.int64)
     return P.T @ M @ P
+
+
+def expected_merge(A, labels, i, singlet_rule=True):
+    """Decision of vertex i in the final merge, by brute force: only a vertex
+    alone in its community whose neighbours j != i all carry one label C is
+    considered; it joins C iff recomputing Q with i moved there gains
+    strictly, unless the singlet minimum-label rule (sizes before the merge)
+    blocks it."""
+    n = len(A)
+    ci = labels[i]
+    size = {}
+    for x in labels:
+        size[x] = size.get(x, 0) + 1
+    if size[ci] != 1:
+        return ci
+    nbr = {labels[j] for j in range(n) if j != i and A[i][j] > 0}
+    if len(nbr) != 1:
+        return ci
+    (C,) = nbr
+    moved = list(labels)
+    moved[i] = C
+    if q_pair_form(A, moved) - q_pair_form(A, labels) <= 0:
+        return ci
+    if singlet_rule and size[C] == 1 and C > ci:
+        return ci
+    return C

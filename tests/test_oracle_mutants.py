@@ -25,6 +25,14 @@ MUTANTS = {
     "accept_non_strict": ("(lh == rh && ll > rl)", "(lh == rh && ll >= rl)"),
     "contract_unmapped_row": ("int32_t b = newc[col[e]];", "int32_t b = newc[i];"),
     "renumber_off_by_one": ("map[v] = present ? (int32_t)k : -1;", "map[v] = present ? (int32_t)(k > 0 ? k - 1 : 0) : -1;"),
+    "merge_non_alone": ("        if (size[ci] != 1)\n            continue;\n        int32_t target = -1;",
+                        "        if (size[ci] < 1)\n            continue;\n        int32_t target = -1;"),
+    "merge_on_equal_gain": ("        if (s <= s_own)\n            continue;", "        if (s < s_own)\n            continue;"),
+    "merge_two_communities": ("            else if (c[j] != target)\n                single = 0;",
+                              "            else if (c[j] != target)\n                single = 1;"),
+    "merge_singlet_direction": ("size[target] == 1 && target > ci", "size[target] == 1 && target < ci"),
+    "merge_keeps_old_q": ("            community_state(ln, c, delta, degc, size);\n            q_prev = modularity_int(ln, rp, cl, wt, c, delta, tw, qscratch);\n",
+                          "            community_state(ln, c, delta, degc, size);\n"),
     "degree_skips_first": ("for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)\n            s += w[e];",
                            "for (int64_t e = row_ptr[i] + 1; e < row_ptr[i + 1]; ++e)\n            s += w[e];"),
 }

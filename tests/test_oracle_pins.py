@@ -17,7 +17,7 @@ import pytest
 
 import graphgen as gg
 import oracle
-from mathpins import (contract_dense, dense, expected_move, max_modularity,
+from mathpins import (contract_dense, dense, expected_merge, expected_move, max_modularity,
                       q_int_pair_form, q_pair_form)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "worked_examples.json")
@@ -205,6 +205,16 @@ def test_worked_examples(ex):
         rp2, cl2, w2 = oracle.contract(g.row_ptr, g.col, g.w, m[lab], k)
         assert k == c["n"] and rp2.tolist() == c["row_ptr"]
         assert cl2.tolist() == c["col"] and w2.tolist() == c["w"]
+    if "merge" in ex:
+        mg = ex["merge"]
+        got = oracle.merge(g.row_ptr, g.col, g.w, np.array(mg["phase_labels"], np.int32))
+        assert got.tolist() == mg["merged"]
+        r = oracle.louvain(g.row_ptr, g.col, g.w, merge=True)
+        assert r.labels.tolist() == mg["final_labels"] and r.q_int == mg["q_int"]
+        assert len(r.levels) == len(mg["levels"])
+        for got_lv, want in zip(r.levels, mg["levels"]):
+            for key, v in want.items():
+                assert got_lv[key] == v
     if "singlet_off" in ex:
         s = ex["singlet_off"]
         lm = oracle.local_move(g.row_ptr, g.col, g.w, None, singlet_rule=False)
@@ -352,3 +362,89 @@ def test_dendrogram_worked_example():
     c = ex["contracted"]
     rp2, cl2, w2 = d.graphs[1]
     assert rp2.tolist() == c["row_ptr"] and cl2.tolist() == c["col"] and w2.tolist() == c["w"]
+
+
+# --- the final merge of a phase -----------------------------------------------
+
+@pytest.mark.parametrize("singlet", [True, False])
+@pytest.mark.parametrize("g", _small_graphs(), ids=lambda g: f"n{g.n}m{g.nnz}")
+def test_merge_decisions_by_brute_force(g, singlet):
+    A = dense(g.row_ptr, g.col, g.w, g.n)
+    labs = list(_labelings(g.n, g.nnz + 11))
+    # labellings where the merge has work: the end of a phase, and a sweep's result
+    labs.append(oracle.louvain(g.row_ptr, g.col, g.w, max_levels=1).labels)
+    labs.append(oracle.local_move(g.row_ptr, g.col, g.w).labels)
+    for lab in labs:
+        got = oracle.merge(g.row_ptr, g.col, g.w, lab, singlet_rule=singlet)
+        want = [expected_merge(A, lab.tolist(), i, singlet) for i in range(g.n)]
+        assert got.tolist() == want
+
+
+def test_merge_zero_gain_stays():
+    """Labellings (found by search) where a lone vertex's only neighbouring
+    community scores exactly its own score: it must stay."""
+    for seed, lab in ((50103, [2, 1, 0, 0]), (50295, [0, 0, 1, 0]), (50307, [3, 2, 1, 2])):
+        g = gg.random_small(4, 0.5, 3, seed=seed, loop_prob=0.3)
+        A = dense(g.row_ptr, g.col, g.w, g.n)
+        lab = np.array(lab, np.int32)
+        want = [expected_merge(A, lab.tolist(), i) for i in range(g.n)]
+        assert oracle.merge(g.row_ptr, g.col, g.w, lab).tolist() == want
+
+
+def _merge_run_by_hand(g, singlet=True):
+    """Alg. 2 with the final merge, assembled from one-level runs (whose
+    labels are the phase's, renumbered in ascending order, which keeps the
+    sizes and the label order the merge reads), the brute-force merge, numpy
+    renumbering and dense contraction."""
+    A = np.array(dense(g.row_ptr, g.col, g.w, g.n), dtype=np.int64)
+    final = np.arange(g.n)
+    while A.sum() > 0:
+        n = len(A)
+        rows, cols = np.nonzero(A)
+        rp = np.concatenate([[0], np.cumsum(np.bincount(rows, minlength=n))]).astype(np.int64)
+        r = oracle.louvain(rp, cols.astype(np.int32), A[rows, cols], max_levels=1, singlet_rule=singlet)
+        if r.levels[0]["sweeps_accepted"] == 0:
+            break
+        lab = r.labels.tolist()
+        merged = [expected_merge(A.tolist(), lab, i, singlet) for i in range(n)]
+        uniq, new = np.unique(merged, return_inverse=True)
+        final = new[final]
+        A = contract_dense(A.tolist(), new.tolist(), len(uniq))
+    return final
+
+
+def _merge_cases():
+    # random graphs on which the final merge changes the run (found by search)
+    out = [gg.random_small(4 + s % 6, 0.35, 1, seed=7000 + s) for s in (243, 467, 592, 717, 1444, 1665, 2200)]
+    return out + _dendro_cases()[1:] + _small_graphs()[::3]
+
+
+@pytest.mark.parametrize("g", _merge_cases(), ids=lambda g: f"n{g.n}m{g.nnz}")
+def test_run_with_merge(g):
+    r = oracle.louvain(g.row_ptr, g.col, g.w, merge=True)
+    assert r.labels.tolist() == _merge_run_by_hand(g).tolist()
+    A = dense(g.row_ptr, g.col, g.w, g.n)
+    if sum(map(sum, A)):
+        assert r.q_int == q_int_pair_form(A, r.labels.tolist())
+    # each level's record holds Q after its merge, which the next level's
+    # singletons reproduce (contraction keeps Q)
+    qs = [lv["q_int"] for lv in r.levels]
+    assert all(lv["sweeps_accepted"] > 0 for lv in r.levels[:-1])
+    d = oracle.dendrogram(g.row_ptr, g.col, g.w, merge=True)
+    assert np.array_equal(d.labels, r.labels) and d.levels == r.levels
+    for lvl in range(1, len(d.graphs)):
+        kl = d.graphs[lvl][0].shape[0] - 1
+        assert oracle.modularity(*d.graphs[lvl], np.arange(kl, dtype=np.int32))[0] == qs[lvl - 1]
+    # the merge is inert without the flag
+    assert oracle.louvain(g.row_ptr, g.col, g.w).levels == oracle.louvain(g.row_ptr, g.col, g.w, merge=False).levels
+
+
+def test_merge_changes_runs():
+    """Guard against vacuous merge pins: on the search-found graphs the
+    merged run differs from the plain one."""
+    changed = 0
+    for g in _merge_cases()[:7]:
+        a = oracle.louvain(g.row_ptr, g.col, g.w)
+        b = oracle.louvain(g.row_ptr, g.col, g.w, merge=True)
+        changed += (a.levels != b.levels) or not np.array_equal(a.labels, b.labels)
+    assert changed >= 5
