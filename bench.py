@@ -17,9 +17,11 @@ events add a few microseconds around each timed kernel, so the other timed
 steps carry none).
 
 Beside the plain run, the line reports the run that keeps the dendrogram
-(per-level maps and the last level's graph) and a run checkpointed after its
+(per-level maps and the last level's graph), a run checkpointed after its
 first level and resumed, with their wall times and whether their labels
-equal the plain run's (skip with --no-dendro).
+equal the plain run's, and the run with the optional final merge after
+every phase (time, Q, merge kernels' device time); skip these with
+--no-dendro.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -262,6 +264,29 @@ def bench_dendro(torch, ctx, rp, col, w, ref_labels, plain_ms: float, runs: int 
             "identical_outputs": same}
 
 
+def bench_merge(torch, ctx, rp, col, w, plain_ms: float, plain_q: float, runs: int = 3) -> dict:
+    """The run with the final merge after every phase against the plain run:
+    wall time per run, Q, and the merge kernels' device time (one timed run)."""
+    def one(timing=False):
+        G = ctx.graph_create(rp, col, w)
+        r = ctx.run(G, merge=True, timing=timing)
+        G.destroy()
+        return r
+
+    one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(runs):
+        r = one()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1000.0 / runs
+    k = one(timing=True).stats["kernels"]
+    merge_ms = sum(v["ms"] for n, v in k.items() if n in ("k_comm_state", "k_merge_lone"))
+    return {"ms_per_run": round(ms, 3), "plain_ms_per_run": round(plain_ms, 3), "overhead": round(ms / plain_ms, 3),
+            "q": r.q, "q_plain": plain_q, "levels": len(r.stats["levels"]),
+            "merge_kernels_ms": round(merge_ms, 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -287,7 +312,7 @@ def main():
     ap.add_argument("--served-requests", type=int, default=0, help="trace length (default 4x the graphs)")
     ap.add_argument("--served-load", type=float, default=0.7, help="trace QPS as a fraction of plain capacity")
     ap.add_argument("--no-dendro", action="store_true",
-                    help="skip the dendrogram-keeping and resumed runs beside the plain one")
+                    help="skip the dendrogram-keeping, resumed and merged runs beside the plain one")
     ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (for scaling the "
@@ -444,7 +469,7 @@ def main():
         parity = bool(np.array_equal(labels, ref.labels) and r.q_int == ref.q_int)
         log(f"oracle {spent / runs:.2f} s per run, parity {parity}")
 
-    dendro = None
+    dendro = merged = None
     if not args.no_dendro:
         log("dendrogram and resume vs plain")
         try:
@@ -452,6 +477,12 @@ def main():
         except Exception as e:  # the main measurement stands on its own
             dendro = {"error": f"{type(e).__name__}: {e}"}
         log(f"dendrogram: {dendro}")
+        log("final merge vs plain")
+        try:
+            merged = bench_merge(torch, ctx, rp, col, w, ms_per_step, r.q)
+        except Exception as e:
+            merged = {"error": f"{type(e).__name__}: {e}"}
+        log(f"merge: {merged}")
 
     batched = served = None
     if batch_graphs is not None:
@@ -487,6 +518,8 @@ def main():
     }
     if dendro is not None:
         line["dendrogram"] = dendro
+    if merged is not None:
+        line["final_merge"] = merged
     if batched is not None:
         line["batched"] = batched
     if served is not None:

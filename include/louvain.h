@@ -73,6 +73,15 @@ typedef struct {
     int32_t pass_batch;    /* sweep passes enqueued between host checks of the
                               device's convergence flag (0 = library default);
                               passes past the end of a phase exit at once      */
+    int32_t merge;         /* 1 = final merge after every phase that kept a sweep
+                              (Section 5.1, end of "Generating one level"): from
+                              the phase's labels, a vertex alone in its community
+                              whose neighbours (loops aside) all carry one label C
+                              joins C iff its score there beats staying and the
+                              singlet rule allows it; Q is recomputed.  Default 0.
+                              louvain_run, louvain_run_dendro and louvain_resume
+                              only (EINVAL in the batched and served forms).   */
+    int32_t reserved;      /* must be 0                                            */
 } louvain_params;
 
 /* Per-level record filled by louvain_run. */

@@ -43,7 +43,8 @@ class louvain_i128(C.Structure):
 
 class louvain_params(C.Structure):
     _fields_ = [("theta_num", C.c_int64), ("theta_den", C.c_int64), ("max_sweeps", C.c_int32),
-                ("max_levels", C.c_int32), ("singlet_rule", C.c_int32), ("pass_batch", C.c_int32)]
+                ("max_levels", C.c_int32), ("singlet_rule", C.c_int32), ("pass_batch", C.c_int32),
+                ("merge", C.c_int32), ("reserved", C.c_int32)]
 
 
 class louvain_level_stats(C.Structure):
@@ -457,18 +458,20 @@ class Context:
 
     def run(self, g: Graph, theta_num: int = 1, theta_den: int = 1_000_000, max_sweeps: int = 1000,
             max_levels: int = 64, singlet_rule: bool = True, pass_batch: int = 0, timing=False,
-            device: Optional[bool] = None, labels_out=None, dendrogram: bool = False):
+            device: Optional[bool] = None, labels_out=None, dendrogram: bool = False, merge: bool = False):
         """The whole method (Alg. 2 over Alg. 1 phases).
 
         timing: False, True (device time of every launch, from HIP events
         filled by the dispatches) or a kernel name as it appears in
         stats["kernels"] (only its launches are timed).
         dendrogram: also keep the per-level maps and the last level's graph;
-        returns (RunResult, Dendrogram) then."""
+        returns (RunResult, Dendrogram) then.
+        merge: apply the final merge after every phase that kept a sweep."""
         dev = g.dev if device is None else device
         n, _, _ = g.info()
         out = labels_out if labels_out is not None else _empty_like_kind(dev, n, np.int32, self.torch_device)
-        prm = louvain_params(theta_num, theta_den, max_sweeps, max_levels, 1 if singlet_rule else 0, pass_batch)
+        prm = louvain_params(theta_num, theta_den, max_sweeps, max_levels, 1 if singlet_rule else 0, pass_batch,
+                             1 if merge else 0)
         qi = louvain_i128()
         q = C.c_double()
         st = self._timing_stats(timing)
@@ -486,14 +489,15 @@ class Context:
 
     def resume(self, g_level: Graph, levels_done: int, labels_so_far, theta_num: int = 1,
                theta_den: int = 1_000_000, max_sweeps: int = 1000, max_levels: int = 64, singlet_rule: bool = True,
-               pass_batch: int = 0, timing=False, device: Optional[bool] = None) -> RunResult:
+               pass_batch: int = 0, timing=False, device: Optional[bool] = None, merge: bool = False) -> RunResult:
         """Continue a run from the graph of level `levels_done` and the labels
         so far (one per original vertex); the result equals one run's."""
         dev = g_level.dev if device is None else device
         lab = self._labels(labels_so_far, dev)
         n0 = int(lab.shape[0])
         out = _empty_like_kind(dev, n0, np.int32, self.torch_device)
-        prm = louvain_params(theta_num, theta_den, max_sweeps, max_levels, 1 if singlet_rule else 0, pass_batch)
+        prm = louvain_params(theta_num, theta_den, max_sweeps, max_levels, 1 if singlet_rule else 0, pass_batch,
+                             1 if merge else 0)
         qi = louvain_i128()
         q = C.c_double()
         st = self._timing_stats(timing)
@@ -506,7 +510,7 @@ class Context:
 
     def run_batch(self, graphs, theta_num: int = 1, theta_den: int = 1_000_000, max_sweeps: int = 1000,
                   max_levels: int = 64, singlet_rule: bool = True, pass_batch: int = 0, timing: bool = False,
-                  stats: bool = True, device: Optional[bool] = None, labels_out=None):
+                  stats: bool = True, device: Optional[bool] = None, labels_out=None, merge: bool = False):
         """The whole method on many graphs in one call (one RunResult per graph).
 
         stats=False skips the per-graph statistics records (about 9 KB each).
@@ -523,7 +527,8 @@ class Context:
             else:
                 n, _, _ = g.info()
                 outs.append(_empty_like_kind(dev, n, np.int32, self.torch_device))
-        prm = louvain_params(theta_num, theta_den, max_sweeps, max_levels, 1 if singlet_rule else 0, pass_batch)
+        prm = louvain_params(theta_num, theta_den, max_sweeps, max_levels, 1 if singlet_rule else 0, pass_batch,
+                             1 if merge else 0)
         handles = (C.c_void_p * k)(*[g.h for g in graphs])
         ptrs = (C.c_void_p * k)(*[_ptr(o) for o in outs])
         qi = (louvain_i128 * k)()

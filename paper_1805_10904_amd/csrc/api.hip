@@ -194,11 +194,13 @@ double q_of(lv::i128 q_int, int64_t tw) {
 }
 
 louvain_params checked_params(const louvain_params *params) {
-    louvain_params prm{1, 1000000, 1000, 64, 1, 0};
+    louvain_params prm{1, 1000000, 1000, 64, 1, 0, 0, 0};
     if (params) prm = *params;
     require(prm.theta_num >= 0 && prm.theta_den > 0, LOUVAIN_EINVAL, "theta must be num >= 0, den > 0");
     require(prm.max_sweeps >= 0 && prm.max_levels >= 1 && prm.max_levels <= 64, LOUVAIN_EINVAL,
             "max_sweeps must be >= 0 and max_levels in [1, 64]");
+    require(prm.merge == 0 || prm.merge == 1, LOUVAIN_EINVAL, "merge must be 0 or 1");
+    require(prm.reserved == 0, LOUVAIN_EINVAL, "reserved must be 0");
     return prm;
 }
 
@@ -299,6 +301,7 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
         sw.reserve(n0, nnz0);
         ct.reserve(n0, nnz0);
         DevBuf<int32_t> newlab((size_t)n0);
+        DevBuf<int32_t> merged;   // labels after the final merge (allocated when used)
         // levels below 2^31 total weight keep int32 weights (every weight
         // of a contracted graph is at most 2W)
         const bool narrow = g0.tw < lv::kCompactTwMax;
@@ -340,6 +343,15 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
                 break;
             }
             const int32_t *cfin = sw.slot(st.final_slot);
+            if (prm.merge) {
+                // the final merge on the phase's labels, then Q once more
+                if (!merged.p) merged.alloc((size_t)n0);
+                lv::merge_lone(v, cfin, sp.singlet, merged.p, s, t);
+                cfin = merged.p;
+                q_final = lv::modularity_int(v, cfin, s, t);
+                ls.q_int.lo = (uint64_t)q_final;
+                ls.q_int.hi = (int64_t)(q_final >> 64);
+            }
             const int64_t k = ct.renumber(cfin, v.n, newlab.p);
             ct.compose(fin_p, n0, newlab.p);
             if (sink) sink->map(newlab.p, v.n, k, s);
@@ -866,9 +878,10 @@ int louvain_submit(louvain_ctx ctx, int64_t n, int64_t nnz, const int64_t *row_p
         (n == 0 && nnz > 0))
         return LOUVAIN_EINVAL;
     if (n >= ((int64_t)1 << 31) || nnz >= ((int64_t)1 << 40)) return LOUVAIN_EOVERFLOW;
-    louvain_params prm{1, 1000000, 1000, 64, 1, 0};
+    louvain_params prm{1, 1000000, 1000, 64, 1, 0, 0, 0};
     if (params) prm = *params;
-    if (prm.theta_num < 0 || prm.theta_den <= 0 || prm.max_sweeps < 0 || prm.max_levels < 1 || prm.max_levels > 64)
+    if (prm.theta_num < 0 || prm.theta_den <= 0 || prm.max_sweeps < 0 || prm.max_levels < 1 || prm.max_levels > 64 ||
+        prm.merge != 0 || prm.reserved != 0)
         return LOUVAIN_EINVAL;
     try {
         std::unique_ptr<lv::ServeRequest> r(new lv::ServeRequest());
@@ -961,6 +974,7 @@ int louvain_run_batch(louvain_ctx ctx, int64_t ngraphs, const louvain_graph *gra
                     "labels_out[" + std::to_string(i) + "] must not be NULL");
         }
         const louvain_params prm = checked_params(params);
+        require(prm.merge == 0, LOUVAIN_EINVAL, "the final merge is not available in the batched form");
         hipStream_t s = ctx->stream;
         const bool dev = device_ptrs(flags);
         const int32_t timing = stats ? stats[0].timing : 0;

@@ -63,6 +63,14 @@ class Contractor {
     DevBuf<int64_t> tw_;        // nnz: grouped entries: weight
 };
 
+// The final merge of a phase (Section 5.1, end of "Generating one level"),
+// one synchronous decision from labels (device int32[n] in [0, n)): a
+// vertex alone in its community whose neighbours other than itself all
+// carry one label C moves to C iff TW*e_{i->C} - delta_i*deg_C beats its own
+// score (zero when alone) and, with singlet set, the singlet rule allows it;
+// out (device int32[n], not aliasing labels) receives every vertex's label.
+void merge_lone(const GraphView &g, const int32_t *labels, int singlet, int32_t *out, hipStream_t s, Timer *t);
+
 // Q_int = TW*I - sum_C deg_C^2 of labels (device int32[n] in [0, n)).
 i128 modularity_int(const GraphView &g, const int32_t *labels, hipStream_t s, Timer *t);
 
