@@ -323,9 +323,9 @@ int louvain_resume(louvain_ctx ctx, louvain_graph g_level, const louvain_params 
 
 /* ---- launch shapes -------------------------------------------------------- */
 
-/* Launch-shape settings of levels whose 2W is below 2^31.  They change which
- * kernel sweeps which rows, never the results (every setting gives the same
- * labels, Q and level records). */
+/* Launch-shape settings (of levels whose 2W is below 2^31, except reorder).
+ * They change which kernel sweeps which rows, never the results (every
+ * setting gives the same labels, Q and level records). */
 typedef struct {
     int32_t small_max;   /* rows of at most this many entries are swept one thread per
                             vertex (1..8; default 4)                                     */
@@ -339,6 +339,14 @@ typedef struct {
                             side (1 or 2; 0 = 1): more independent work per lane      */
     int32_t overlap;     /* 1: the rows of 342..block_max entries and the hub rows are swept
                             on two extra streams beside the shorter rows (0 or 1)      */
+    int32_t reorder;     /* level 0 of louvain_run / _dendro / _resume (any 2W): 1 sweeps
+                            the graph rebuilt with its vertices in descending order of
+                            floor(log2(row length)) (gather locality; the paper's
+                            suggestion of placing vertices of similar degree side by
+                            side), 2 as given, 0 auto = 1 for graphs with 2W >= 2^31
+                            and at least 2^20 vertices, else 2.  Results never change:
+                            labels stay the given vertex IDs                          */
+    int32_t reserved;    /* must be 0                                                  */
     double ms;           /* louvain_autotune: device time of one run with this setting */
 } louvain_tuning;
 

@@ -311,10 +311,22 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
         } lg[2];
         int which = 0;
         const lv::SweepParams sp = sweep_params(prm);
+        // level 0 in row-length order (results unchanged): v is the rebuilt
+        // graph, vertex p starts alone in community order[p], and the final
+        // labels start as every vertex's position
+        lv::ReorderedGraph rg;
+        bool permuted = lv::reorder_applies(g0, tn);
+        if (permuted) {
+            v = rg.build(g0, s, t);
+            LV_HIP(hipMemcpyAsync(fin_p, rg.pos.p, (size_t)n0 * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        }
         for (int level = 0; level < prm.max_levels; ++level) {
             const size_t rec0 = timer.recs.size();
             sw.plan(v);
-            sw.init_singletons(v);
+            if (permuted)
+                sw.init_singletons(v, rg.order.p);
+            else
+                sw.init_singletons(v);
             lv::PhaseState st;
             int p = 0;
             for (;;) {
@@ -336,6 +348,8 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
             q_final = lv::make_i128(st.q_ref[0], (int64_t)st.q_ref[1]);
             if (st.limit) status = LOUVAIN_ELIMIT;
             if (st.accepted == 0) {
+                // nothing renumbered: the final labels are the identity, not the level-0 positions
+                if (permuted) lv::iota_i32(fin_p, n0, s);
                 if (timing == 1) {
                     LV_HIP(hipStreamSynchronize(s));
                     collect_kernel_stats(timer, nullptr, rec0, timer.recs.size(), &ls.ms_sweep, &ls.ms_contract);
@@ -354,7 +368,8 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
             }
             const int64_t k = ct.renumber(cfin, v.n, newlab.p);
             ct.compose(fin_p, n0, newlab.p);
-            if (sink) sink->map(newlab.p, v.n, k, s);
+            // after composing, fin_p holds level 0's map in the given vertex order
+            if (sink) sink->map(permuted ? fin_p : newlab.p, v.n, k, s);
             const bool cut = level + 1 >= prm.max_levels;
             if (cut && !sink) {
                 status = LOUVAIN_ELIMIT;
@@ -387,6 +402,7 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
             v2.delta = nb.delta.p;
             v2.tw = g0.tw;
             v = v2;
+            permuted = false;
             which = 1 - which;
             if (timing == 1) {
                 LV_HIP(hipStreamSynchronize(s));
@@ -397,7 +413,7 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
                 break;
             }
         }
-        if (sink) sink->last(v, s);
+        if (sink) sink->last(permuted ? g0 : v, s);
     } else if (sink) {
         sink->last(v, s);
     }
@@ -773,9 +789,12 @@ int louvain_set_tuning(louvain_ctx ctx, const louvain_tuning *tuning) {
             require(tuning->group_vertices >= 0 && tuning->group_vertices <= 2, LOUVAIN_EINVAL,
                     "group_vertices must be 0, 1 or 2");
             require(tuning->overlap == 0 || tuning->overlap == 1, LOUVAIN_EINVAL, "overlap must be 0 or 1");
+            require(tuning->reorder >= 0 && tuning->reorder <= 2, LOUVAIN_EINVAL, "reorder must be 0, 1 or 2");
+            require(tuning->reserved == 0, LOUVAIN_EINVAL, "reserved must be 0");
             tn.group_slots = tuning->group_slots == 0 ? 4 : tuning->group_slots;
             tn.group_vertices = tuning->group_vertices == 0 ? 1 : tuning->group_vertices;
             tn.overlap = tuning->overlap;
+            tn.reorder = tuning->reorder;
         }
         ctx->tuning = tn;
     });
@@ -790,6 +809,7 @@ int louvain_get_tuning(louvain_ctx ctx, louvain_tuning *tuning) {
     tuning->group_slots = ctx->tuning.group_slots;
     tuning->group_vertices = ctx->tuning.group_vertices;
     tuning->overlap = ctx->tuning.overlap;
+    tuning->reorder = ctx->tuning.reorder;
     return LOUVAIN_OK;
 }
 
@@ -843,6 +863,7 @@ int louvain_autotune(louvain_ctx ctx, louvain_graph g, const louvain_params *par
                         tn.pass_batch = pb;
                         tn.group_vertices = gv;
                         tn.overlap = cur.overlap;
+                        tn.reorder = cur.reorder;
                         const double ms = std::min(time_run(tn), time_run(tn));
                         if (ms < pick_ms && ms < 0.98 * cur_ms) {
                             pick_ms = ms;

@@ -21,6 +21,19 @@ struct LevelSink {
     virtual void last(const GraphView &v, hipStream_t s) = 0;
 };
 
+// Level-0 vertex order by row length (gather locality): order[p] is the
+// given ID of the vertex at position p, pos its inverse, and the CSR is g's
+// rebuilt in that order with columns remapped to positions.
+struct ReorderedGraph {
+    DevBuf<int32_t> order, pos, col, w32;
+    DevBuf<int64_t> rp, delta, w64;
+    // Build from g (n >= 2) and return the view of the rebuilt graph.
+    GraphView build(const GraphView &g, hipStream_t s, Timer *t);
+};
+// Whether the tuning asks for the level-0 order on g (auto: 2W >= 2^31 and
+// at least 2^20 vertices, where the measured sweeps gained from it).
+bool reorder_applies(const GraphView &g, const Tuning &tn);
+
 // Phases of sweeps, renumbering and contraction on g0 until a phase keeps no
 // sweep or a cap is reached.  fin_p (device int32[g0.n]) receives the final
 // labels, *q_out Q_int of them, *stats_out the run record (kernel times when

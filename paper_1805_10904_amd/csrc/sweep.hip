@@ -1253,6 +1253,11 @@ void Sweeper::init_singletons(const GraphView &g) {
     LV_HIP(hipMemsetAsync(st_.p, 0, sizeof(PhaseState), s_));
 }
 
+void Sweeper::init_singletons(const GraphView &g, const int32_t *ids) {
+    init_from_labels(g, ids);
+    singleton_start_ = true;   // a permutation: every community holds one vertex
+}
+
 void Sweeper::init_from_labels(const GraphView &g, const int32_t *labels) {
     singleton_start_ = false;
     if (compact_) {

@@ -72,6 +72,7 @@ struct Tuning {
     int group_slots = 4;                // LDS slots per lane of the packed-class sweep (2, 4 or 8)
     int group_vertices = 1;             // vertices per lane group of the packed-class sweep (1 or 2)
     int overlap = 0;                    // 1: row families on side streams, side by side
+    int reorder = 0;                    // level-0 vertex order by row length: 0 auto, 1 on, 2 off
 };
 // log2 of the LDS hash table size of a packed row of d >= 1 entries: the
 // smallest b >= 1 with 2^b >= ceil(3d/2) (load at most 2/3).
@@ -174,6 +175,9 @@ class Sweeper {
     void set_tuning(const Tuning &tn) { tuning_ = tn; }
     // Singleton communities (a2): every ring slot = identity, deg = delta, size = 1.
     void init_singletons(const GraphView &g);
+    // Singleton communities labelled ids[i] (device int32[n], a permutation
+    // of [0, n)): vertex i alone in community ids[i].
+    void init_singletons(const GraphView &g, const int32_t *ids);
     // Communities from labels (device int32[n]): ring slots = labels, deg/size recomputed.
     void init_from_labels(const GraphView &g, const int32_t *labels);
     // Enqueue sweep pass p >= 1: reads ring slot (p-1)%3, writes slot p%3,

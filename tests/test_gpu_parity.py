@@ -306,10 +306,11 @@ def test_launch_shapes_do_not_change_results(ctx):
     refs = [oracle.louvain(g.row_ptr, g.col, g.w) for g in graphs]
     Gs = [ctx.graph_create(g.row_ptr, g.col, g.w) for g in graphs]
     try:
-        for shp in [(1, 341, 1, 4, 1, 0), (4, 1024, 2, 8, 2, 1), (8, 1365, 1, 2, 2, 0), (2, 2730, 3, 4, 1, 1),
-                    (4, 10922, 2, 8, 1, 0), (3, 700, 1, 2, 1, 1), (4, 5000, 2, 4, 2, 1), (4, 10922, 2, 4, 1, 1)]:
+        for shp in [(1, 341, 1, 4, 1, 0, 1), (4, 1024, 2, 8, 2, 1, 2), (8, 1365, 1, 2, 2, 0, 0),
+                    (2, 2730, 3, 4, 1, 1, 1), (4, 10922, 2, 8, 1, 0, 2), (3, 700, 1, 2, 1, 1, 1),
+                    (4, 5000, 2, 4, 2, 1, 0), (4, 10922, 2, 4, 1, 1, 1)]:
             ctx.set_tuning(*shp)
-            keys = ("small_max", "block_max", "pass_batch", "group_slots", "group_vertices", "overlap")
+            keys = ("small_max", "block_max", "pass_batch", "group_slots", "group_vertices", "overlap", "reorder")
             assert ctx.get_tuning() == dict(zip(keys, shp))
             for k, (G, ref) in enumerate(zip(Gs, refs)):
                 r = ctx.run(G)
@@ -331,9 +332,9 @@ def test_autotune(ctx, L):
         best = ctx.autotune(G)
         assert best["small_max"] in (4, 8) and best["block_max"] in (1365, 2730, 10922)
         assert best["pass_batch"] in (1, 2) and best["group_slots"] == 4 and best["ms"] > 0
-        assert best["group_vertices"] in (1, 2) and best["overlap"] == 0
+        assert best["group_vertices"] in (1, 2) and best["overlap"] == 0 and best["reorder"] == 0
         assert ctx.get_tuning() == {k: best[k] for k in ("small_max", "block_max", "pass_batch", "group_slots",
-                                                         "group_vertices", "overlap")}
+                                                         "group_vertices", "overlap", "reorder")}
         r = ctx.run(G)
         ref = oracle.louvain(g.row_ptr, g.col, g.w)
         assert np.array_equal(r.labels, ref.labels) and r.q_int == ref.q_int
@@ -347,6 +348,8 @@ def test_autotune(ctx, L):
             ctx.set_tuning(group_vertices=3)
         with pytest.raises(L.LouvainError):
             ctx.set_tuning(overlap=2)
+        with pytest.raises(L.LouvainError):
+            ctx.set_tuning(reorder=3)
     finally:
         ctx.set_tuning()
         G.destroy()
