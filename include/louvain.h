@@ -78,9 +78,8 @@ typedef struct {
                               the phase's labels, a vertex alone in its community
                               whose neighbours (loops aside) all carry one label C
                               joins C iff its score there beats staying and the
-                              singlet rule allows it; Q is recomputed.  Default 0.
-                              louvain_run, louvain_run_dendro and louvain_resume
-                              only (EINVAL in the batched and served forms).   */
+                              singlet rule allows it; Q is recomputed.  Default 0
+                              (every form: plain, batched, served).            */
     int32_t reserved;      /* must be 0                                            */
 } louvain_params;
 

@@ -367,6 +367,7 @@ class Context:
 
     def submit(self, row_ptr, col, w, theta_num: int = 1, theta_den: int = 1_000_000, max_sweeps: int = 1000,
                max_levels: int = 64, singlet_rule: bool = True, pass_batch: int = 0, labels_out=None,
+               merge: bool = False,
                check_symmetry: bool = False) -> int:
         """Queue one graph for the request loop; returns a ticket for poll().
 
@@ -387,7 +388,8 @@ class Context:
         out = labels_out if labels_out is not None else _empty_like_kind(dev, n, np.int32, self.torch_device)
         flags = (LOUVAIN_DEVICE_PTRS if dev else 0) | (LOUVAIN_CHECK_SYMMETRY if check_symmetry else 0) \
             | (LOUVAIN_WEIGHTS_I64 if wide else 0)
-        prm = louvain_params(theta_num, theta_den, max_sweeps, max_levels, 1 if singlet_rule else 0, pass_batch)
+        prm = louvain_params(theta_num, theta_den, max_sweeps, max_levels, 1 if singlet_rule else 0, pass_batch,
+                             1 if merge else 0)
         t = C.c_uint64()
         rc = self.lib.louvain_submit(self.h, n, nnz, _ptr(row_ptr), _ptr(col), _ptr(w), C.byref(prm), _ptr(out),
                                      flags, C.byref(t))

@@ -210,6 +210,7 @@ lv::SweepParams sweep_params(const louvain_params &prm) {
     sp.theta_den = prm.theta_den;
     sp.max_sweeps = prm.max_sweeps;
     sp.singlet = prm.singlet_rule ? 1 : 0;
+    sp.merge = prm.merge;
     return sp;
 }
 
@@ -902,7 +903,7 @@ int louvain_submit(louvain_ctx ctx, int64_t n, int64_t nnz, const int64_t *row_p
     louvain_params prm{1, 1000000, 1000, 64, 1, 0, 0, 0};
     if (params) prm = *params;
     if (prm.theta_num < 0 || prm.theta_den <= 0 || prm.max_sweeps < 0 || prm.max_levels < 1 || prm.max_levels > 64 ||
-        prm.merge != 0 || prm.reserved != 0)
+        (prm.merge != 0 && prm.merge != 1) || prm.reserved != 0)
         return LOUVAIN_EINVAL;
     try {
         std::unique_ptr<lv::ServeRequest> r(new lv::ServeRequest());
@@ -995,7 +996,6 @@ int louvain_run_batch(louvain_ctx ctx, int64_t ngraphs, const louvain_graph *gra
                     "labels_out[" + std::to_string(i) + "] must not be NULL");
         }
         const louvain_params prm = checked_params(params);
-        require(prm.merge == 0, LOUVAIN_EINVAL, "the final merge is not available in the batched form");
         hipStream_t s = ctx->stream;
         const bool dev = device_ptrs(flags);
         const int32_t timing = stats ? stats[0].timing : 0;

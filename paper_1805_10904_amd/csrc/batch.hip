@@ -355,7 +355,21 @@ std::vector<BatchMember *> BatchEngine::step() {
         newoff_.reserve((size_t)ns + 1);
         sw_.final_labels(labf_.p);
         to_device(keep_, kc, s_);
-        k = ct_.renumber_kept(labf_.p, N, gid_.p, keep_.p, loff_.p, ns, newlab_.p, newoff_.p);
+        const int32_t *lab = labf_.p;
+        if (sp_.merge) {
+            // the final merge of the graphs that kept a sweep, then their Q once more
+            merged_.reserve((size_t)N);
+            merge_lone_batch(v, labf_.p, sp_.singlet, gid_.p, tw_.p, keep_.p, merged_.p, s_, t_);
+            lab = merged_.p;
+            const std::vector<i128> qm = modularity_by_graph(v, lab, gid_.p, ns, htw, s_, t_);
+            for (int64_t s = 0; s < ns; ++s) {
+                if (!kc[(size_t)s]) continue;
+                BatchMember *m = sl[(size_t)s];
+                m->levels.back().q = qm[(size_t)s];
+                m->q = qm[(size_t)s];
+            }
+        }
+        k = ct_.renumber_kept(lab, N, gid_.p, keep_.p, loff_.p, ns, newlab_.p, newoff_.p);
         std::vector<VertSeg> cs;
         std::vector<int64_t> cb0;
         int64_t b = 0, nv = 0;
@@ -376,7 +390,7 @@ std::vector<BatchMember *> BatchEngine::step() {
         }
         if (any_k && !same) {
             to_device(keep_, kk, s_);
-            k = ct_.renumber_kept(labf_.p, N, gid_.p, keep_.p, loff_.p, ns, newlab_.p, newoff_.p);
+            k = ct_.renumber_kept(lab, N, gid_.p, keep_.p, loff_.p, ns, newlab_.p, newoff_.p);
         }
     }
     std::vector<BatchMember *> next;

@@ -80,7 +80,7 @@ class BatchEngine {
     UBuf ub_[2];
     int cur_ = 0;
     int64_t un_ = 0, um_ = 0;              // size of the contracted part in ub_[cur_]
-    DevBuf<int32_t> gid_, newlab_, labf_, keep_;
+    DevBuf<int32_t> gid_, newlab_, labf_, keep_, merged_;
     DevBuf<int64_t> tw_, loff_, newoff_;
 };
 

@@ -1,6 +1,8 @@
 // Renumbering, graph contraction and modularity on the device.
 #pragma once
 
+#include <vector>
+
 #include "common.hpp"
 #include "sweep.hpp"
 
@@ -70,6 +72,16 @@ class Contractor {
 // score (zero when alone) and, with singlet set, the singlet rule allows it;
 // out (device int32[n], not aliasing labels) receives every vertex's label.
 void merge_lone(const GraphView &g, const int32_t *labels, int singlet, int32_t *out, hipStream_t s, Timer *t);
+// The same over a batch's block-diagonal union u: vertex i belongs to graph
+// gid[i] (device), whose total weight is tw_of[gid[i]] (device); only graphs
+// with keep[g] != 0 (device) merge, the others keep their labels.
+void merge_lone_batch(const GraphView &u, const int32_t *labels, int singlet, const int32_t *gid, const int64_t *tw_of,
+                      const int32_t *keep, int32_t *out, hipStream_t s, Timer *t);
+// Q_int of every graph of a batch's union under labels: TW_g * I_g - sum of
+// deg_C^2 over graph g's communities (tw: host, one per graph; every graph
+// of a batch has 2W < 2^31, so the sums fit 64 bits).  Synchronises.
+std::vector<i128> modularity_by_graph(const GraphView &u, const int32_t *labels, const int32_t *gid, int64_t ns,
+                                      const std::vector<int64_t> &tw, hipStream_t s, Timer *t);
 
 // Q_int = TW*I - sum_C deg_C^2 of labels (device int32[n] in [0, n)).
 i128 modularity_int(const GraphView &g, const int32_t *labels, hipStream_t s, Timer *t);

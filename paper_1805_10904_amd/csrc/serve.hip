@@ -13,7 +13,7 @@ namespace {
 bool same_params(const louvain_params &a, const louvain_params &b) {
     return a.theta_num == b.theta_num && a.theta_den == b.theta_den && a.max_sweeps == b.max_sweeps &&
            a.max_levels == b.max_levels && (a.singlet_rule != 0) == (b.singlet_rule != 0) &&
-           a.pass_batch == b.pass_batch;
+           a.pass_batch == b.pass_batch && a.merge == b.merge;
 }
 
 SweepParams to_sweep(const louvain_params &p) {
@@ -22,6 +22,7 @@ SweepParams to_sweep(const louvain_params &p) {
     sp.theta_den = p.theta_den;
     sp.max_sweeps = p.max_sweeps;
     sp.singlet = p.singlet_rule ? 1 : 0;
+    sp.merge = p.merge;
     return sp;
 }
 

@@ -113,6 +113,7 @@ struct SweepParams {
     int64_t theta_num = 1, theta_den = 1000000;
     int32_t max_sweeps = 1000;
     int singlet = 1;
+    int merge = 0;   // the final merge after a phase that kept a sweep (level drivers)
 };
 
 // Device state of a compact pass (one graph or a block-diagonal batch).

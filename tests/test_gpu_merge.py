@@ -111,12 +111,48 @@ def test_merge_dendrogram_and_resume(ctx):
         G.destroy()
 
 
-def test_merge_rejected_where_unsupported(ctx, L):
-    g = gg.config("sbm1k")
+def test_merge_batched(ctx):
+    """Batched calls with the merge: every graph's result equals the oracle's
+    (graphs end their phases at different passes; a heavy graph runs alone)."""
+    graphs = search_graphs() + [gg.from_edge_list(4, [(0, 2), (0, 3), (1, 2), (1, 3)], name="c4"),
+                                gg.config("sbm1k"), gg.config("chunglu_n65536"), gg.config("rmat_s14"), hub_graph(),
+                                heavy_graph()]
+    graphs += [gg.random_small(3 + 7 * s, 0.3, 1 + s % 5, seed=9100 + s, isolated=s % 2) for s in range(12)]
+    Gs = [ctx.graph_create(g.row_ptr, g.col, g.w) for g in graphs]
+    for kw in (dict(), dict(singlet_rule=False), dict(max_levels=2)):
+        res = ctx.run_batch(Gs, merge=True, **kw)
+        for g, r in zip(graphs, res):
+            ref = oracle.louvain(g.row_ptr, g.col, g.w, merge=True, **kw)
+            assert np.array_equal(r.labels, ref.labels), f"batched labels differ on {g.name} {kw}"
+            assert r.q_int == ref.q_int, f"batched Q differs on {g.name} {kw}"
+            assert _levels(r.stats["levels"]) == _levels(ref.levels), f"batched records differ on {g.name} {kw}"
+    for G in Gs:
+        G.destroy()
+
+
+def test_merge_served(ctx):
+    import time
+    graphs = search_graphs() + [gg.config("sbm1k"), gg.config("rmat_s14"), heavy_graph()]
+    tickets = []
+    for k, g in enumerate(graphs):
+        tickets.append((g, ctx.submit(g.row_ptr, g.col, g.w, merge=(k % 2 == 0))))
+    t_end = time.time() + 120
+    for g, t in tickets:
+        r = None
+        while r is None:
+            assert time.time() < t_end, "served requests did not finish in time"
+            r = ctx.poll(t, wait_us=2000)
+        k = [x[1] for x in tickets].index(t)
+        ref = oracle.louvain(g.row_ptr, g.col, g.w, merge=(k % 2 == 0))
+        assert np.array_equal(r.labels, ref.labels), f"served labels differ on {g.name}"
+        assert r.q_int == ref.q_int
+        assert _levels(r.levels) == _levels(ref.levels)
+
+
+def test_merge_off_is_the_default(ctx):
+    g = gg.config("rmat_s14")
     G = ctx.graph_create(g.row_ptr, g.col, g.w)
-    with pytest.raises(L.LouvainError):
-        ctx.run_batch([G], merge=True)
-    # without the flag the default run is unchanged
     ref = oracle.louvain(g.row_ptr, g.col, g.w)
     assert np.array_equal(ctx.run(G).labels, ref.labels)
+    assert np.array_equal(ctx.run_batch([G])[0].labels, ref.labels)
     G.destroy()
