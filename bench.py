@@ -145,8 +145,10 @@ def bench_batched(L, torch, graphs, warmup: int, profile: bool = False, tuning=N
 def bench_served(L, torch, pool, requests: int, load: float, seed: int = 1005, tuning=None):
     """Request loop on a Poisson trace against the plain path on the same trace.
 
-    The plain path's per-graph times are measured alone; its latencies on the
-    trace follow from a first-come-first-served queue over those times."""
+    The plain path's per-graph times (graph_create from the device CSR, run,
+    destroy: what a served request covers) are measured alone; its latencies
+    on the trace follow from a first-come-first-served queue over those
+    times."""
     import numpy as np
     ctx = L.Context(0)
     if tuning:
@@ -159,12 +161,16 @@ def bench_served(L, torch, pool, requests: int, load: float, seed: int = 1005, t
     torch.cuda.synchronize()
     for G, o in zip(Gs, outs):           # warm-up
         ctx.run(G, labels_out=o)
+    # a plain request is what a served one does: take the device CSR in
+    # (copy, validation, degrees) and run the method
     svc = []
     ref_q = []
-    for G, o in zip(Gs, outs):
+    for t, o in zip(res_in, outs):
         torch.cuda.synchronize()
         a = time.perf_counter()
+        G = ctx.graph_create(*t)
         r = ctx.run(G, labels_out=o)
+        G.destroy()
         torch.cuda.synchronize()
         svc.append(time.perf_counter() - a)
         ref_q.append(r.q_int)
