@@ -21,7 +21,9 @@ Beside the plain run, the line reports the run that keeps the dendrogram
 first level and resumed, with their wall times and whether their labels
 equal the plain run's, and the run with the optional final merge after
 every phase (time, Q, merge kernels' device time); skip these with
---no-dendro.
+--no-dendro.  --shards N (default 8) times one GPU's share of the workload
+split into N entry-balanced vertex ranges (sweep kernels per pass, ghosts
+read in place; no exchange) against the whole graph.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -226,6 +228,59 @@ def bench_served(L, torch, pool, requests: int, load: float, seed: int = 1005, t
             "identical_outputs": bool(ok and ok_sat)}
 
 
+def bench_shards(torch, ctx, g, nshards: int) -> dict:
+    """One GPU's share of a sharded run, at its real shape: the vertices are
+    split into nshards contiguous ranges balanced by entries; shard k holds
+    the rows of its range (renumbered from 0) plus one empty row per ghost
+    (a neighbour outside the range, numbered after the local vertices), so
+    its per-vertex state covers local vertices and ghost copies, as a GPU's
+    would.  Each shard's level-0 phase runs alone; its sweep kernels' device
+    time per pass is compared with the whole graph's (the exchange of ghost
+    labels and community deltas between GPUs is not part of it).  The labels
+    of a shard alone mean nothing: only the timing is reported."""
+    import numpy as np
+    dev = torch.device("cuda", 0)
+    rp, col, w = g.row_ptr, g.col, g.w
+    n, nnz = g.n, g.nnz
+    bounds = np.searchsorted(rp, np.linspace(0, nnz, nshards + 1).astype(np.int64), side="left")
+    bounds[0], bounds[-1] = 0, n
+
+    def per_pass(rpk, colk, wk):
+        G = ctx.graph_create(torch.from_numpy(rpk).to(dev), torch.from_numpy(colk).to(dev),
+                             torch.from_numpy(wk).to(dev))
+        ctx.run(G, max_levels=1)   # warm-up
+        r = ctx.run(G, max_levels=1, timing=True)
+        G.destroy()
+        lv = r.stats["levels"][0]
+        sweep_ms = sum(v["ms"] for k, v in r.stats["kernels"].items()
+                       if k.startswith(("k_cpt_", "k_sweep", "k_hub", "k_commit", "k_qsum", "k_finalize")))
+        return sweep_ms / max(1, lv["gpu_passes"]), lv["gpu_passes"]
+
+    full_ms, full_passes = per_pass(rp, col, w)
+    shards = []
+    for k in range(nshards):
+        lo, hi = int(bounds[k]), int(bounds[k + 1])
+        a, b = int(rp[lo]), int(rp[hi])
+        c = col[a:b].astype(np.int64)
+        outside = (c < lo) | (c >= hi)
+        ghost_ids = np.unique(c[outside])
+        nl, ng = hi - lo, int(ghost_ids.shape[0])
+        colk = np.where(outside, nl + np.searchsorted(ghost_ids, c), c - lo)
+        rpk = np.full(nl + ng + 1, b - a, np.int64)
+        rpk[:nl + 1] = rp[lo:hi + 1] - a
+        # columns ascend inside every row again after renumbering
+        rows = np.repeat(np.arange(nl, dtype=np.int64), np.diff(rpk[:nl + 1]))
+        order = np.argsort(rows * (nl + ng) + colk, kind="stable")
+        ms, passes = per_pass(rpk, colk[order].astype(np.int32), w[a:b][order])
+        shards.append({"vertices": nl, "ghosts": ng, "entries": b - a,
+                       "ghost_entry_fraction": round(float(outside.mean()) if b > a else 0.0, 4),
+                       "sweep_ms_per_pass": round(ms, 4), "passes": passes})
+    worst = max(x["sweep_ms_per_pass"] for x in shards)
+    return {"shards": nshards, "whole_graph_sweep_ms_per_pass": round(full_ms, 4),
+            "max_shard_sweep_ms_per_pass": round(worst, 4), "speedup_per_pass": round(full_ms / worst, 3),
+            "per_shard": shards}
+
+
 def bench_dendro(torch, ctx, rp, col, w, ref_labels, plain_ms: float, runs: int = 3) -> dict:
     """The run that keeps the dendrogram (per-level maps and the last level's
     graph), and a run resumed from the first level's state, against the
@@ -319,6 +374,9 @@ def main():
     ap.add_argument("--served-load", type=float, default=0.7, help="trace QPS as a fraction of plain capacity")
     ap.add_argument("--no-dendro", action="store_true",
                     help="skip the dendrogram-keeping, resumed and merged runs beside the plain one")
+    ap.add_argument("--shards", type=int, default=8,
+                    help="also time one GPU's share of the workload split into this many vertex ranges "
+                         "(sweep kernels per pass; 0 = skip)")
     ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (for scaling the "
@@ -490,6 +548,15 @@ def main():
             merged = {"error": f"{type(e).__name__}: {e}"}
         log(f"merge: {merged}")
 
+    shards = None
+    if args.shards > 1:
+        log(f"one GPU's share of {args.shards} shards")
+        try:
+            shards = bench_shards(torch, ctx, g, args.shards)
+        except Exception as e:  # the main measurement stands on its own
+            shards = {"error": f"{type(e).__name__}: {e}"}
+        log(f"shards: {shards}")
+
     batched = served = None
     if batch_graphs is not None:
         log("batched vs plain")
@@ -526,6 +593,8 @@ def main():
         line["dendrogram"] = dendro
     if merged is not None:
         line["final_merge"] = merged
+    if shards is not None:
+        line["one_gpu_share"] = shards
     if batched is not None:
         line["batched"] = batched
     if served is not None:
