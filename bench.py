@@ -228,6 +228,36 @@ def bench_served(L, torch, pool, requests: int, load: float, seed: int = 1005, t
             "identical_outputs": bool(ok and ok_sat)}
 
 
+def shard_bounds(row_ptr, nshards: int):
+    """nshards + 1 vertex bounds of contiguous ranges balanced by entries."""
+    import numpy as np
+    n, nnz = row_ptr.shape[0] - 1, int(row_ptr[-1])
+    b = np.searchsorted(row_ptr, np.linspace(0, nnz, nshards + 1).astype(np.int64), side="left")
+    b[0], b[-1] = 0, n
+    return b
+
+
+def shard_csr(row_ptr, col, w, lo: int, hi: int):
+    """One GPU's share of vertices [lo, hi): its rows renumbered from 0 (columns
+    ascending), then one empty row per ghost (a neighbour outside the range,
+    numbered after the local vertices in ascending ID order).  Returns
+    (row_ptr, col, w, ghost IDs, fraction of entries to ghosts)."""
+    import numpy as np
+    a, b = int(row_ptr[lo]), int(row_ptr[hi])
+    c = col[a:b].astype(np.int64)
+    outside = (c < lo) | (c >= hi)
+    ghost_ids = np.unique(c[outside])
+    nl, ng = hi - lo, int(ghost_ids.shape[0])
+    colk = np.where(outside, nl + np.searchsorted(ghost_ids, c), c - lo)
+    rpk = np.full(nl + ng + 1, b - a, np.int64)
+    rpk[:nl + 1] = row_ptr[lo:hi + 1] - a
+    # columns ascend inside every row again after renumbering
+    rows = np.repeat(np.arange(nl, dtype=np.int64), np.diff(rpk[:nl + 1]))
+    order = np.argsort(rows * (nl + ng) + colk, kind="stable")
+    frac = float(outside.mean()) if b > a else 0.0
+    return rpk, colk[order].astype(np.int32), w[a:b][order], ghost_ids, frac
+
+
 def bench_shards(torch, ctx, g, nshards: int) -> dict:
     """One GPU's share of a sharded run, at its real shape: the vertices are
     split into nshards contiguous ranges balanced by entries; shard k holds
@@ -241,9 +271,7 @@ def bench_shards(torch, ctx, g, nshards: int) -> dict:
     import numpy as np
     dev = torch.device("cuda", 0)
     rp, col, w = g.row_ptr, g.col, g.w
-    n, nnz = g.n, g.nnz
-    bounds = np.searchsorted(rp, np.linspace(0, nnz, nshards + 1).astype(np.int64), side="left")
-    bounds[0], bounds[-1] = 0, n
+    bounds = shard_bounds(rp, nshards)
 
     def per_pass(rpk, colk, wk):
         G = ctx.graph_create(torch.from_numpy(rpk).to(dev), torch.from_numpy(colk).to(dev),
@@ -260,21 +288,11 @@ def bench_shards(torch, ctx, g, nshards: int) -> dict:
     shards = []
     for k in range(nshards):
         lo, hi = int(bounds[k]), int(bounds[k + 1])
-        a, b = int(rp[lo]), int(rp[hi])
-        c = col[a:b].astype(np.int64)
-        outside = (c < lo) | (c >= hi)
-        ghost_ids = np.unique(c[outside])
-        nl, ng = hi - lo, int(ghost_ids.shape[0])
-        colk = np.where(outside, nl + np.searchsorted(ghost_ids, c), c - lo)
-        rpk = np.full(nl + ng + 1, b - a, np.int64)
-        rpk[:nl + 1] = rp[lo:hi + 1] - a
-        # columns ascend inside every row again after renumbering
-        rows = np.repeat(np.arange(nl, dtype=np.int64), np.diff(rpk[:nl + 1]))
-        order = np.argsort(rows * (nl + ng) + colk, kind="stable")
-        ms, passes = per_pass(rpk, colk[order].astype(np.int32), w[a:b][order])
-        shards.append({"vertices": nl, "ghosts": ng, "entries": b - a,
-                       "ghost_entry_fraction": round(float(outside.mean()) if b > a else 0.0, 4),
-                       "sweep_ms_per_pass": round(ms, 4), "passes": passes})
+        rpk, colk, wk, ghost_ids, frac = shard_csr(rp, col, w, lo, hi)
+        ms, passes = per_pass(rpk, colk, wk)
+        shards.append({"vertices": hi - lo, "ghosts": int(ghost_ids.shape[0]), "entries": int(rpk[-1]),
+                       "ghost_entry_fraction": round(frac, 4), "sweep_ms_per_pass": round(ms, 4),
+                       "passes": passes})
     worst = max(x["sweep_ms_per_pass"] for x in shards)
     return {"shards": nshards, "whole_graph_sweep_ms_per_pass": round(full_ms, 4),
             "max_shard_sweep_ms_per_pass": round(worst, 4), "speedup_per_pass": round(full_ms / worst, 3),

@@ -86,3 +86,34 @@ def test_recorded_traffic_lookup():
     assert got is None or got > 0
     assert bench.recorded_traffic("chunglu1m", "no_such_kernel") is None
     assert bench.recorded_traffic("no_such_workload", "k_cpt_groups<4,1,int>") is None
+
+
+def test_shard_csr_reassembles_the_graph():
+    """The bench's one-GPU share: every shard's local rows map back to the
+    graph's rows (columns ascending, ghosts renumbered after the local
+    vertices), and the shards together hold every entry once."""
+    import numpy as np
+
+    import bench
+    import graphgen as gg
+    g = gg.config("chunglu_n20000")
+    b = bench.shard_bounds(g.row_ptr, 8)
+    assert b[0] == 0 and b[-1] == g.n and np.all(np.diff(b) > 0)
+    total = 0
+    for k in range(8):
+        lo, hi = int(b[k]), int(b[k + 1])
+        rp, col, w, ghosts, frac = bench.shard_csr(g.row_ptr, g.col, g.w, lo, hi)
+        nl = hi - lo
+        assert rp.shape[0] == nl + ghosts.shape[0] + 1 and rp[0] == 0 and np.all(np.diff(rp) >= 0)
+        assert np.all(rp[nl:] == rp[nl])                      # ghost rows are empty
+        assert np.all((ghosts < lo) | (ghosts >= hi)) and np.all(np.diff(ghosts) > 0)
+        back = np.where(col < nl, col.astype(np.int64) + lo, ghosts[np.maximum(col.astype(np.int64) - nl, 0)])
+        for v in range(lo, hi):
+            seg = slice(rp[v - lo], rp[v - lo + 1])
+            assert np.all(np.diff(col[seg]) > 0)
+            order = np.argsort(back[seg])
+            assert np.array_equal(back[seg][order], g.col[g.row_ptr[v]:g.row_ptr[v + 1]])
+            assert np.array_equal(w[seg][order], g.w[g.row_ptr[v]:g.row_ptr[v + 1]])
+        assert 0.0 <= frac <= 1.0
+        total += int(rp[-1])
+    assert total == g.nnz
