@@ -330,12 +330,35 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
                 sw.init_singletons(v);
             lv::PhaseState st;
             int p = 0;
+            std::vector<size_t> pass_rec;   // timer records before each enqueued pass
+            auto enqueue = [&](int count) {
+                for (int b = 0; b < count; ++b) {
+                    pass_rec.push_back(timer.recs.size());
+                    sw.pass(v, ++p, sp, nullptr);
+                }
+            };
+            // batch passes per host check of the phase state; one pass is
+            // enqueued ahead of each check, so the device does not idle on
+            // the round trip (passes after the phase's end return at once)
+            enqueue(batch);
+            std::unique_ptr<lv::Readback> rb(new lv::Readback(s));
+            const lv::PhaseState *hst = rb->add(sw.states());
+            rb->issue();
             for (;;) {
-                for (int b = 0; b < batch; ++b) sw.pass(v, ++p, sp, nullptr);
-                st = sw.read_state();
+                enqueue(1);
+                rb->wait();
+                st = *hst;
                 if (st.done) break;
-                require(p <= prm.max_sweeps + 4 + batch, LOUVAIN_EDEVICE, "sweep loop did not converge");
+                require(p <= prm.max_sweeps + 4 + 2 * batch, LOUVAIN_EDEVICE, "sweep loop did not converge");
+                enqueue(batch - 1);
+                rb.reset(new lv::Readback(s));
+                hst = rb->add(sw.states());
+                rb->issue();
             }
+            // the launches of passes past the phase's end returned at once:
+            // they do none of the method's work and stay out of the statistics
+            if (timing && st.pass >= 0 && (size_t)st.pass < pass_rec.size())
+                for (size_t r = pass_rec[(size_t)st.pass]; r < timer.recs.size(); ++r) timer.recs[r].launched = false;
             auto &ls = local.level[level];
             ls.n = v.n;
             ls.nnz = v.nnz;

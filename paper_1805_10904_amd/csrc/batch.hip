@@ -10,6 +10,8 @@
 #include <algorithm>
 #include <cstring>
 
+#include <memory>
+
 #include "batch.hpp"
 #include "prims.hpp"
 
@@ -307,16 +309,30 @@ std::vector<BatchMember *> BatchEngine::step() {
     sw_.init_singletons(v);
     int p = 0;
     unsigned int planned = (unsigned int)ns;   // graphs the current bucket lists cover
+    // pass_batch passes per host check of the count of graphs still in
+    // their phase; one pass is enqueued ahead of each check, so the device
+    // does not idle on the round trip (finished graphs' passes return at
+    // once; a replan covers the graphs active at the count, a superset of
+    // those active when it runs)
+    for (int b = 0; b < pass_batch_; ++b) sw_.pass(v, ++p, sp_, nullptr);
+    std::unique_ptr<Readback> rb(new Readback(s_));
+    const unsigned int *hact = rb->add(sw_.active_counter(p));
+    rb->issue();
     for (;;) {
-        for (int b = 0; b < pass_batch_; ++b) sw_.pass(v, ++p, sp_, nullptr);
-        const unsigned int act = sw_.active_after(p);
+        sw_.pass(v, ++p, sp_, nullptr);
+        rb->wait();
+        const unsigned int act = *hact;
         if (act == 0) break;
-        require(p <= sp_.max_sweeps + 4 + pass_batch_, LOUVAIN_EDEVICE, "batched sweep loop did not converge");
+        require(p <= sp_.max_sweeps + 4 + 2 * pass_batch_, LOUVAIN_EDEVICE, "batched sweep loop did not converge");
         if (2 * act <= planned) {
             // most graphs have ended their phase: sweep only the others
             sw_.replan_active(v);
             planned = act;
         }
+        for (int b = 1; b < pass_batch_; ++b) sw_.pass(v, ++p, sp_, nullptr);
+        rb.reset(new Readback(s_));
+        hact = rb->add(sw_.active_counter(p));
+        rb->issue();
     }
     std::vector<PhaseState> st((size_t)ns);
     LV_HIP(hipMemcpyAsync(st.data(), sw_.states(), sizeof(PhaseState) * (size_t)ns, hipMemcpyDeviceToHost, s_));

@@ -346,7 +346,11 @@ __global__ __launch_bounds__(256) void k_readback(GatherRanges r, uint32_t *dst)
 }
 
 std::mutex g_rb_mu;
-std::vector<uint32_t *> g_rb_free;
+struct RbBlock {
+    uint32_t *host;
+    hipEvent_t ev;
+};
+std::vector<RbBlock> g_rb_free;
 
 }  // namespace
 
@@ -354,17 +358,23 @@ Readback::Readback(hipStream_t s) : s_(s) {
     {
         std::lock_guard<std::mutex> lk(g_rb_mu);
         if (!g_rb_free.empty()) {
-            host_ = g_rb_free.back();
+            host_ = g_rb_free.back().host;
+            ev_ = g_rb_free.back().ev;
             g_rb_free.pop_back();
         }
     }
-    if (!host_) LV_HIP(hipHostMalloc((void **)&host_, kReadbackWords * sizeof(uint32_t), hipHostMallocCoherent));
+    if (!host_) {
+        LV_HIP(hipHostMalloc((void **)&host_, kReadbackWords * sizeof(uint32_t), hipHostMallocCoherent));
+        LV_HIP(hipEventCreateWithFlags(&ev_, hipEventDisableTiming));
+    }
     LV_HIP(hipHostGetDevicePointer((void **)&dev_, host_, 0));
 }
 
 Readback::~Readback() {
+    // a gather still in flight writes into the block: let it land first
+    if (pending_) (void)hipEventSynchronize(ev_);
     std::lock_guard<std::mutex> lk(g_rb_mu);
-    g_rb_free.push_back(host_);
+    g_rb_free.push_back(RbBlock{host_, ev_});
 }
 
 void *Readback::add_words(const void *src, int64_t words) {
@@ -391,9 +401,16 @@ void Readback::issue() {
         LV_LAUNCHED("k_readback");
     }
     n_ = 0;
+    LV_HIP(hipEventRecord(ev_, s_));
+    pending_ = true;
 }
 
-void Readback::wait() { LV_HIP(hipStreamSynchronize(s_)); }
+// Waits for the gather only: work enqueued after issue() keeps running.
+void Readback::wait() {
+    if (!pending_) issue();
+    LV_HIP(hipEventSynchronize(ev_));
+    pending_ = false;
+}
 
 // ---------------------------------------------------------- side streams --
 

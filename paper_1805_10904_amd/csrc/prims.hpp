@@ -65,7 +65,7 @@ class Readback {
         return (T *)add_words(src, count * (int64_t)(sizeof(T) / 4));
     }
     void issue();   // launch the gather of the queued ranges
-    void wait();    // wait for the stream (after issue, the values are in place)
+    void wait();    // wait for the gather (then the values are in place); later work may still run
     void fetch() {
         issue();
         wait();
@@ -75,6 +75,8 @@ class Readback {
     void *add_words(const void *src, int64_t words);
     hipStream_t s_;
     uint32_t *host_ = nullptr, *dev_ = nullptr;
+    hipEvent_t ev_ = nullptr;   // recorded after the gather
+    bool pending_ = false;      // issued and not waited for
     int n_ = 0;
     int used_ = 0;
     const uint32_t *src_[kMaxRanges];

@@ -189,6 +189,9 @@ class Sweeper {
     PhaseState read_state();
     // Number of graphs still in their phase after pass p (synchronises).
     unsigned int active_after(int p);
+    // Device address of that count after pass p (for a read-back enqueued
+    // right after the pass).
+    const unsigned int *active_counter(int p) const { return active_.p + (p & 1); }
     // Control blocks of every graph (device; compact levels).
     PhaseState *states() { return st_.p; }
     bool compact() const { return compact_; }
