@@ -348,20 +348,24 @@ __global__ __launch_bounds__(256) void k_readback(GatherRanges r, uint32_t *dst)
 std::mutex g_rb_mu;
 struct RbBlock {
     uint32_t *host;
-    hipEvent_t ev;
+    hipEvent_t ev;   // belongs to the device it was created on
+    int device;
 };
 std::vector<RbBlock> g_rb_free;
 
 }  // namespace
 
 Readback::Readback(hipStream_t s) : s_(s) {
+    LV_HIP(hipGetDevice(&device_));
     {
         std::lock_guard<std::mutex> lk(g_rb_mu);
-        if (!g_rb_free.empty()) {
-            host_ = g_rb_free.back().host;
-            ev_ = g_rb_free.back().ev;
-            g_rb_free.pop_back();
-        }
+        for (size_t k = g_rb_free.size(); k-- > 0;)
+            if (g_rb_free[k].device == device_) {
+                host_ = g_rb_free[k].host;
+                ev_ = g_rb_free[k].ev;
+                g_rb_free.erase(g_rb_free.begin() + (std::ptrdiff_t)k);
+                break;
+            }
     }
     if (!host_) {
         LV_HIP(hipHostMalloc((void **)&host_, kReadbackWords * sizeof(uint32_t), hipHostMallocCoherent));
@@ -374,7 +378,7 @@ Readback::~Readback() {
     // a gather still in flight writes into the block: let it land first
     if (pending_) (void)hipEventSynchronize(ev_);
     std::lock_guard<std::mutex> lk(g_rb_mu);
-    g_rb_free.push_back(RbBlock{host_, ev_});
+    g_rb_free.push_back(RbBlock{host_, ev_, device_});
 }
 
 void *Readback::add_words(const void *src, int64_t words) {

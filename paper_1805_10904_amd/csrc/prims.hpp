@@ -76,6 +76,7 @@ class Readback {
     hipStream_t s_;
     uint32_t *host_ = nullptr, *dev_ = nullptr;
     hipEvent_t ev_ = nullptr;   // recorded after the gather
+    int device_ = 0;            // device current at construction (the stream's)
     bool pending_ = false;      // issued and not waited for
     int n_ = 0;
     int used_ = 0;
