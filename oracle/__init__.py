@@ -1,7 +1,8 @@
 """CPU oracle of synchronous parallel Louvain -- TEST INFRASTRUCTURE ONLY.
 
-Python access to ``louvain_oracle.c``, a plain single-threaded C
-implementation written from the paper (R. Forster, "Parallel Louvain
+Python access to ``louvain_oracle.c``, a plain C implementation (single
+threaded, with an OpenMP variant over vertices that gives the same
+results) written from the paper (R. Forster, "Parallel Louvain
 Community Detection Optimized for GPUs", arXiv 1805.10904; Section 2
 eqs. 1-5, Section 3.1 heuristics, Alg. 1 and Alg. 2, and the renumbering
 and graph-rebuilding processes of Section 5.1).  Only ``tests/``, the
@@ -33,7 +34,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc into ``oracle/liblouvain_oracle.so``."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-Wall", "-Wextra", "-shared", "-fPIC",
                                "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
@@ -62,6 +63,8 @@ def _load():
         lib.orc_louvain.argtypes = [i64, p, p, p, i64, i64, C.c_int32, C.c_int32, C.c_int, C.c_int,
                                     p, p, p, p, p]
         lib.orc_merge.argtypes = [i64, p, p, p, p, C.c_int, p]
+        lib.orc_set_threads.argtypes = [C.c_int]
+        lib.orc_get_threads.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -93,6 +96,17 @@ def i128_to_pair(v: int) -> np.ndarray:
     hi = u >> 64
     to_s = lambda x: x - (1 << 64) if x >= (1 << 63) else x
     return np.array([to_s(lo), to_s(hi)], dtype=np.int64)
+
+
+def set_threads(threads: int) -> None:
+    """Threads of the OpenMP variant (the sweep's vertex loop and the inner
+    weight of eq. 3); 1 = the plain single-threaded oracle.  Results do not
+    depend on it."""
+    _load().orc_set_threads(int(threads))
+
+
+def get_threads() -> int:
+    return int(_load().orc_get_threads())
 
 
 def degrees(row_ptr, col, w):

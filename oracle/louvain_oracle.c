@@ -54,11 +54,33 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#define THREAD_ID() omp_get_thread_num()
+#else
+#define THREAD_ID() 0
+#endif
 
 typedef __int128 i128;
 typedef unsigned __int128 u128;
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2, ORC_ELIMIT = -6 };
+
+/* Threads of the OpenMP variant: the sweep's vertex loop and the inner
+ * weight of eq. 3 run over this many threads (1 = the plain single-threaded
+ * oracle).  Every vertex decides from the same snapshot and the sums are of
+ * integers, so results do not depend on the count. */
+static int g_threads = 1;
+
+void orc_set_threads(int threads)
+{
+    g_threads = threads < 1 ? 1 : threads;
+}
+
+int orc_get_threads(void)
+{
+    return g_threads;
+}
 
 /* Weighted degrees delta_i and TW = sum_i delta_i (Section 2). */
 int orc_degrees(int64_t n, const int64_t *row_ptr, const int64_t *w,
@@ -96,6 +118,7 @@ static i128 modularity_int(int64_t n, const int64_t *row_ptr, const int32_t *col
                            int64_t tw, int64_t *degc /* scratch n */)
 {
     int64_t inner = 0;
+#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : inner) num_threads(g_threads) if (g_threads > 1)
     for (int64_t i = 0; i < n; ++i)
         for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
             if (c[col[e]] == c[i])
@@ -157,14 +180,17 @@ int orc_accept(const int64_t q_new[2], const int64_t q_prev[2], int64_t theta_nu
 
 /* One synchronous sweep (the parallel loop of Alg. 1).  Reads the snapshot
  * (c, degc, size) and writes every vertex's decision to c_out; e_self_out
- * (optional) gets e_{i->c_i} including i's loop.  acc (n, zeroed) and list (n)
- * are scratch. */
+ * (optional) gets e_{i->c_i} including i's loop.  acc (n per thread, zeroed)
+ * and list (n per thread) are scratch. */
 static void sweep(int64_t n, const int64_t *row_ptr, const int32_t *col, const int64_t *w,
                   const int64_t *delta, int64_t tw, const int32_t *c, const int64_t *degc,
                   const int32_t *size, int singlet_rule, int32_t *c_out, int64_t *e_self_out,
-                  int64_t *acc, int32_t *list)
+                  int64_t *acc_all, int32_t *list_all)
 {
+#pragma omp parallel for schedule(dynamic, 1024) num_threads(g_threads) if (g_threads > 1)
     for (int64_t i = 0; i < n; ++i) {
+        int64_t *acc = acc_all + (size_t)THREAD_ID() * (size_t)n;
+        int32_t *list = list_all + (size_t)THREAD_ID() * (size_t)n;
         int32_t ci = c[i];
         int64_t loop = 0;
         int64_t nl = 0;
@@ -270,8 +296,9 @@ int orc_local_move(int64_t n, const int64_t *row_ptr, const int32_t *col, const 
                 return ORC_EINVAL;
     size_t nn = (size_t)(n ? n : 1);
     int64_t *delta = malloc(sizeof(int64_t) * nn), *degc = malloc(sizeof(int64_t) * nn);
-    int64_t *acc = calloc(nn, sizeof(int64_t));
-    int32_t *size = malloc(sizeof(int32_t) * nn), *list = malloc(sizeof(int32_t) * nn);
+    size_t nt = (size_t)g_threads;   /* scratch of the sweep: one row per thread */
+    int64_t *acc = calloc(nn * nt, sizeof(int64_t));
+    int32_t *size = malloc(sizeof(int32_t) * nn), *list = malloc(sizeof(int32_t) * nn * nt);
     int32_t *c = malloc(sizeof(int32_t) * nn);
     int rc = ORC_OK;
     if (!delta || !degc || !acc || !size || !list || !c) { rc = ORC_ENOMEM; goto out; }
@@ -421,8 +448,9 @@ int orc_louvain(int64_t n, const int64_t *row_ptr, const int32_t *col, const int
     int64_t *wt2 = malloc(sizeof(int64_t) * mm);
     int64_t *delta = malloc(sizeof(int64_t) * nn), *degc = malloc(sizeof(int64_t) * nn);
     int64_t *qscratch = malloc(sizeof(int64_t) * nn);
-    int64_t *acc = calloc(nn, sizeof(int64_t));
-    int32_t *size = malloc(sizeof(int32_t) * nn), *list = malloc(sizeof(int32_t) * nn);
+    size_t nt = (size_t)g_threads;   /* scratch of the sweep: one row per thread */
+    int64_t *acc = calloc(nn * nt, sizeof(int64_t));
+    int32_t *size = malloc(sizeof(int32_t) * nn), *list = malloc(sizeof(int32_t) * nn * nt);
     int32_t *c = malloc(sizeof(int32_t) * nn), *c_new = malloc(sizeof(int32_t) * nn);
     int32_t *map = malloc(sizeof(int32_t) * nn);
     if (!rp || !cl || !wt || !rp2 || !cl2 || !wt2 || !delta || !degc || !qscratch || !acc ||

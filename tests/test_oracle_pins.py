@@ -448,3 +448,33 @@ def test_merge_changes_runs():
         b = oracle.louvain(g.row_ptr, g.col, g.w, merge=True)
         changed += (a.levels != b.levels) or not np.array_equal(a.labels, b.labels)
     assert changed >= 5
+
+
+# --- the OpenMP variant of the oracle ----------------------------------------
+
+@pytest.mark.parametrize("threads", [2, 5])
+def test_openmp_variant_equals_single_thread(threads):
+    """Every vertex decides from the same snapshot and the sums are of
+    integers, so the multi-threaded oracle gives the single-threaded one's
+    results exactly."""
+    graphs = [gg.config("sbm1k"), gg.config("chunglu_n20000"), gg.config("rmat_s14")] + _small_graphs()[::4]
+    ref = []
+    oracle.set_threads(1)
+    try:
+        for g in graphs:
+            lab = gg.random_labels(g.n, max(1, g.n // 7), 5)
+            ref.append((oracle.louvain(g.row_ptr, g.col, g.w), oracle.louvain(g.row_ptr, g.col, g.w, merge=True),
+                        oracle.local_move(g.row_ptr, g.col, g.w, lab), oracle.modularity(g.row_ptr, g.col, g.w, lab)))
+        oracle.set_threads(threads)
+        assert oracle.get_threads() == threads
+        for g, (a, am, lm, q) in zip(graphs, ref):
+            lab = gg.random_labels(g.n, max(1, g.n // 7), 5)
+            b = oracle.louvain(g.row_ptr, g.col, g.w)
+            assert np.array_equal(a.labels, b.labels) and a.q_int == b.q_int and a.levels == b.levels
+            bm = oracle.louvain(g.row_ptr, g.col, g.w, merge=True)
+            assert np.array_equal(am.labels, bm.labels) and am.q_int == bm.q_int and am.levels == bm.levels
+            lm2 = oracle.local_move(g.row_ptr, g.col, g.w, lab)
+            assert all(np.array_equal(x, y) for x, y in zip(lm, lm2))
+            assert oracle.modularity(g.row_ptr, g.col, g.w, lab) == q
+    finally:
+        oracle.set_threads(1)
