@@ -470,12 +470,14 @@ def main():
     # (the last warm-up step, at least the second, is the one timed in full)
     dominant = None
     table = None
+    table_levels = None
     nwarm = max(2, args.warmup) if timing else args.warmup
     for k in range(nwarm):
         full = timing and k == nwarm - 1
         r0 = step(full)
         if full:
             table = r0.stats["kernels"]
+            table_levels = r0.stats["levels"]
             dominant = max(table.items(), key=lambda kv: kv[1]["ms"])[0]
         log(f"warmup {k + 1}/{nwarm} done")
     torch.cuda.synchronize()
@@ -498,6 +500,7 @@ def main():
 
     roofline = None
     sweep_gteps = None
+    level0_gteps = None
     kernel_ms = None
     if timing:
         # the dominant kernel, timed live in the last timed step
@@ -514,6 +517,10 @@ def main():
         sweep_ms = sum(v["ms"] for n, v in table.items() if n.startswith(("k_cpt_", "k_sweep", "k_hub", "k_commit",
                                                                              "k_qsum", "k_finalize")))
         sweep_gteps = edges / (sweep_ms / 1000.0) / 1e9 if sweep_ms > 0 else None
+        # level 0 alone: its executed sweeps over its entries / its sweep kernels' time
+        lv0 = table_levels[0] if table_levels else None
+        level0_gteps = (lv0["sweeps_executed"] * lv0["nnz"] / (lv0["ms_sweep"] / 1000.0) / 1e9
+                        if lv0 and lv0["ms_sweep"] > 0 else None)
         # measured HBM bytes per launch (counters), against the algorithmic ones
         traffic = recorded_traffic(args.workload, dom_name)
         alg_per_launch = dom["alg_bytes"] / max(1, dom["launches"])
@@ -615,6 +622,7 @@ def main():
                    "edges_swept": edges, "parallelism": "single GPU", "launch_shapes": tuning},
         "full_louvain_s": round(ms_per_step / 1000.0, 6),
         "sweep_gteps": None if sweep_gteps is None else round(sweep_gteps, 3),
+        "level0_sweep_gteps": None if level0_gteps is None else round(level0_gteps, 3),
         "kernel_ms_per_step": None if kernel_ms is None else round(kernel_ms, 4),
         "q": r.q,
         "roofline": roofline,
