@@ -265,8 +265,9 @@ def bench_shards(torch, ctx, g, nshards: int) -> dict:
     (a neighbour outside the range, numbered after the local vertices), so
     its per-vertex state covers local vertices and ghost copies, as a GPU's
     would.  Each shard's level-0 phase runs alone; its sweep kernels' device
-    time per pass is compared with the whole graph's (the exchange of ghost
-    labels and community deltas between GPUs is not part of it).  The labels
+    time per pass and its renumbering and contraction time are compared with
+    the whole graph's (the exchange of ghost labels and community deltas
+    between GPUs, and of contracted entries, is not part of it).  The labels
     of a shard alone mean nothing: only the timing is reported."""
     import numpy as np
     dev = torch.device("cuda", 0)
@@ -274,28 +275,30 @@ def bench_shards(torch, ctx, g, nshards: int) -> dict:
     bounds = shard_bounds(rp, nshards)
 
     def per_pass(rpk, colk, wk):
+        # level 0's phase, then its renumbering and contraction (a second
+        # level is started so that the first one is contracted)
         G = ctx.graph_create(torch.from_numpy(rpk).to(dev), torch.from_numpy(colk).to(dev),
                              torch.from_numpy(wk).to(dev))
-        ctx.run(G, max_levels=1)   # warm-up
-        r = ctx.run(G, max_levels=1, timing=True)
+        ctx.run(G, max_levels=2)   # warm-up
+        r = ctx.run(G, max_levels=2, timing=True)
         G.destroy()
         lv = r.stats["levels"][0]
-        sweep_ms = sum(v["ms"] for k, v in r.stats["kernels"].items()
-                       if k.startswith(("k_cpt_", "k_sweep", "k_hub", "k_commit", "k_qsum", "k_finalize")))
-        return sweep_ms / max(1, lv["gpu_passes"]), lv["gpu_passes"]
+        return lv["ms_sweep"] / max(1, lv["gpu_passes"]), lv["gpu_passes"], lv["ms_contract"]
 
-    full_ms, full_passes = per_pass(rp, col, w)
+    full_ms, full_passes, full_contract = per_pass(rp, col, w)
     shards = []
     for k in range(nshards):
         lo, hi = int(bounds[k]), int(bounds[k + 1])
         rpk, colk, wk, ghost_ids, frac = shard_csr(rp, col, w, lo, hi)
-        ms, passes = per_pass(rpk, colk, wk)
+        ms, passes, contract_ms = per_pass(rpk, colk, wk)
         shards.append({"vertices": hi - lo, "ghosts": int(ghost_ids.shape[0]), "entries": int(rpk[-1]),
                        "ghost_entry_fraction": round(frac, 4), "sweep_ms_per_pass": round(ms, 4),
-                       "passes": passes})
+                       "passes": passes, "contract_ms": round(contract_ms, 4)})
     worst = max(x["sweep_ms_per_pass"] for x in shards)
+    worst_c = max(x["contract_ms"] for x in shards)
     return {"shards": nshards, "whole_graph_sweep_ms_per_pass": round(full_ms, 4),
             "max_shard_sweep_ms_per_pass": round(worst, 4), "speedup_per_pass": round(full_ms / worst, 3),
+            "whole_graph_contract_ms": round(full_contract, 4), "max_shard_contract_ms": round(worst_c, 4),
             "per_shard": shards}
 
 
