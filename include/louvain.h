@@ -276,8 +276,8 @@ typedef struct louvain_dendro_s *louvain_dendro;
  *     columns: the graph of the phase that kept no sweep when the run ended
  *     that way, or the contraction by the last map when max_levels cut the
  *     run short (for a graph with TW = 0: a copy of g).
- * The contractions of such a run sort every row, which costs some time
- * over louvain_run; every other output equals louvain_run's.  Arguments
+ * The last graph is put in that form by one more contraction (by the
+ * identity); every other output equals louvain_run's.  Arguments
  * and the return value are as for louvain_run; on error *dendro_out is
  * untouched.
  */

@@ -146,30 +146,6 @@ DevBuf<int32_t> labels_in(louvain_ctx ctx, const int32_t *labels, int64_t n, uin
     return d;
 }
 
-// Device copy of a graph view as a new handle of ctx.
-std::unique_ptr<louvain_graph_s> copy_graph(louvain_ctx ctx, const lv::GraphView &v, hipStream_t s) {
-    std::unique_ptr<louvain_graph_s> g(new louvain_graph_s());
-    g->ctx = ctx;
-    g->pool = ctx->pool;
-    g->device = ctx->device;
-    g->n = v.n;
-    g->nnz = v.nnz;
-    g->tw = v.tw;
-    g->wbytes = v.wbytes;
-    g->row_ptr.alloc((size_t)v.n + 1);
-    g->col.alloc((size_t)v.nnz);
-    if (v.wbytes == 4) g->w32.alloc((size_t)v.nnz); else g->w64.alloc((size_t)v.nnz);
-    g->delta.alloc((size_t)v.n);
-    copy_in(g->row_ptr.p, v.row_ptr, v.n + 1, true, s);
-    copy_in(g->col.p, v.col, v.nnz, true, s);
-    if (v.wbytes == 4)
-        copy_in(g->w32.p, (const int32_t *)v.w, v.nnz, true, s);
-    else
-        copy_in(g->w64.p, (const int64_t *)v.w, v.nnz, true, s);
-    copy_in(g->delta.p, v.delta, v.n, true, s);
-    return g;
-}
-
 // Collects a run's dendrogram (the per-level maps, the last level's graph).
 struct DendroSink final : lv::LevelSink {
     louvain_dendro_s *d;
@@ -179,7 +155,41 @@ struct DendroSink final : lv::LevelSink {
         copy_in(d->maps.back().p, newlab, n, true, s);
         d->n.push_back(k);
     }
-    void last(const lv::GraphView &v, hipStream_t s) override { d->graph = copy_graph(d->ctx, v, s); }
+    // The last level's graph in canonical form: copied when its rows are
+    // sorted, else contracted by the identity (every vertex its own
+    // super-vertex), which sorts every row and keeps the entries, weights
+    // and degrees.
+    void last(const lv::GraphView &v, bool sorted, hipStream_t s) override {
+        std::unique_ptr<louvain_graph_s> g(new louvain_graph_s());
+        g->ctx = d->ctx;
+        g->pool = d->ctx->pool;
+        g->device = d->ctx->device;
+        g->n = v.n;
+        g->tw = v.tw;
+        g->wbytes = v.wbytes;
+        g->row_ptr.alloc((size_t)v.n + 1);
+        g->col.alloc((size_t)v.nnz);
+        if (v.wbytes == 4) g->w32.alloc((size_t)v.nnz); else g->w64.alloc((size_t)v.nnz);
+        g->delta.alloc((size_t)v.n);
+        if (sorted || v.n == 0 || v.nnz == 0) {
+            g->nnz = v.nnz;
+            copy_in(g->row_ptr.p, v.row_ptr, v.n + 1, true, s);
+            copy_in(g->col.p, v.col, v.nnz, true, s);
+            if (v.wbytes == 4)
+                copy_in(g->w32.p, (const int32_t *)v.w, v.nnz, true, s);
+            else
+                copy_in(g->w64.p, (const int64_t *)v.w, v.nnz, true, s);
+            copy_in(g->delta.p, v.delta, v.n, true, s);
+        } else {
+            DevBuf<int32_t> ident((size_t)v.n);
+            lv::iota_i32(ident.p, v.n, s);
+            lv::Contractor ct(s, nullptr);
+            ct.reserve(v.n, v.nnz);
+            void *w = v.wbytes == 4 ? (void *)g->w32.p : (void *)g->w64.p;
+            g->nnz = ct.contract(v, ident.p, v.n, g->row_ptr.p, g->col.p, w, v.wbytes, g->delta.p, true);
+        }
+        d->graph = std::move(g);
+    }
 };
 
 louvain_i128 to_abi(lv::i128 v) {
@@ -321,6 +331,7 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
             v = rg.build(g0, s, t);
             LV_HIP(hipMemcpyAsync(fin_p, rg.pos.p, (size_t)n0 * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
         }
+        bool cut_sorted = false;   // the last contraction (a cut run's) sorted its rows
         for (int level = 0; level < prm.max_levels; ++level) {
             const size_t rec0 = timer.recs.size();
             sw.plan(v);
@@ -415,7 +426,7 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
             }
             void *wout = narrow ? (void *)nb.w32.p : (void *)nb.w64.p;
             const int64_t m2 = ct.contract(v, newlab.p, k, nb.rp.p, nb.col.p, wout, narrow ? 4 : 8, nb.delta.p,
-                                           sink != nullptr, lv::lds_row_max(k, g0.tw, tn));
+                                           sink != nullptr && cut, lv::lds_row_max(k, g0.tw, tn));
             lv::GraphView v2;
             v2.n = k;
             v2.nnz = m2;
@@ -434,12 +445,15 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
             }
             if (cut) {
                 status = LOUVAIN_ELIMIT;
+                cut_sorted = sink != nullptr;
                 break;
             }
         }
-        if (sink) sink->last(permuted ? g0 : v, s);
+        // the caller's graph has ascending columns (checked when it was
+        // created); a contraction's are ascending only when it was the cut one
+        if (sink) sink->last(permuted ? g0 : v, permuted || v.row_ptr == g0.row_ptr || cut_sorted, s);
     } else if (sink) {
-        sink->last(v, s);
+        sink->last(v, true, s);
     }
     local.status = status;
     if (timing) {

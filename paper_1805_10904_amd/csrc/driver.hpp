@@ -7,18 +7,18 @@
 
 namespace lv {
 
-// Receiver of a run's dendrogram.  With a sink the run contracts into the
-// canonical form (ascending columns), and a run cut by max_levels still
-// contracts its last phase, so that the graph handed to last() is the one
-// the next phase would run on.
+// Receiver of a run's dendrogram.  With a sink, a run cut by max_levels
+// still contracts its last phase, so that the graph handed to last() is the
+// one the next phase would run on (its rows in any order).
 struct LevelSink {
     virtual ~LevelSink() = default;
     // One level: newlab (device int32[n], valid during the call) sends every
     // vertex of the level's graph to its vertex in the next level's graph,
     // which has k vertices.
     virtual void map(const int32_t *newlab, int64_t n, int64_t k, hipStream_t s) = 0;
-    // The graph of the last level (device arrays valid during the call).
-    virtual void last(const GraphView &v, hipStream_t s) = 0;
+    // The graph of the last level (device arrays valid during the call);
+    // sorted: its columns already ascend in every row.
+    virtual void last(const GraphView &v, bool sorted, hipStream_t s) = 0;
 };
 
 // Level-0 vertex order by row length (gather locality): order[p] is the
