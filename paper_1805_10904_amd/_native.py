@@ -149,6 +149,9 @@ class LouvainError(RuntimeError):
 
 # ------------------------------------------------------------- marshalling --
 
+_NP_OF = {"int32": np.int32, "int64": np.int64}
+
+
 def _is_torch(x) -> bool:
     return type(x).__module__.startswith("torch")
 
@@ -161,8 +164,68 @@ def _ptr(x):
     return x.ctypes.data_as(C.c_void_p)
 
 
-def _host(x, dtype):
-    return np.ascontiguousarray(x, dtype=dtype)
+def _bad(msg: str):
+    raise LouvainError(LOUVAIN_EINVAL, msg)
+
+
+def _is_dev(x) -> bool:
+    return _is_torch(x) and x.is_cuda
+
+
+def _arg(x, name: str, dtype: str, length: Optional[int], dev: bool, device: int, output: bool = False):
+    """Check one array argument before it reaches the library and return the
+    object whose memory the library is given.
+
+    dev=True: x must be a 1-D contiguous torch CUDA tensor on `device` of
+    dtype `dtype` with `length` elements.  dev=False: host memory; inputs
+    are coerced to a contiguous numpy array of `dtype` (integer values only,
+    none outside the dtype's range), outputs must already be a writable
+    contiguous numpy array of that dtype.  Anything else raises
+    LouvainError(EINVAL) without calling the library."""
+    if dev:
+        import torch
+        if not _is_dev(x):
+            _bad(f"{name}: expected a torch CUDA tensor (device pointers), got {type(x).__name__}")
+        if x.device.index != device:
+            _bad(f"{name}: tensor on cuda:{x.device.index}, the context is on device {device}")
+        if x.dtype != getattr(torch, dtype):
+            _bad(f"{name}: dtype {x.dtype}, expected torch.{dtype}")
+        if x.dim() != 1 or not x.is_contiguous():
+            _bad(f"{name}: expected a contiguous 1-D tensor")
+        if length is not None and x.numel() != length:
+            _bad(f"{name}: {x.numel()} elements, expected {length}")
+        return x
+    if _is_dev(x):
+        _bad(f"{name}: a CUDA tensor where host arrays are expected (all arrays of a call are of one kind)")
+    if _is_torch(x):
+        x = x.numpy()
+    want = np.dtype(_NP_OF[dtype])
+    if output:
+        if not isinstance(x, np.ndarray) or x.dtype != want or x.ndim != 1 or not x.flags.c_contiguous \
+                or not x.flags.writeable:
+            _bad(f"{name}: expected a writable contiguous 1-D numpy array of {dtype}")
+    else:
+        a = np.asarray(x)
+        if a.size and a.dtype.kind not in "iu":
+            _bad(f"{name}: expected integers, got dtype {a.dtype}")
+        if a.ndim != 1:
+            _bad(f"{name}: expected a 1-D array")
+        if a.dtype != want and a.size:
+            info = np.iinfo(want)
+            if int(a.min()) < info.min or int(a.max()) > info.max:
+                _bad(f"{name}: values outside the range of {dtype}")
+        x = np.ascontiguousarray(a, dtype=want)
+    if length is not None and x.shape[0] != length:
+        _bad(f"{name}: {x.shape[0]} elements, expected {length}")
+    return x
+
+
+def _weights_wide(w) -> bool:
+    """int64 weights are passed as they are (LOUVAIN_WEIGHTS_I64); anything
+    else as int32."""
+    if _is_torch(w):
+        return str(w.dtype) == "torch.int64"
+    return np.asarray(w).dtype == np.int64
 
 
 def _empty_like_kind(ref_is_dev, n, dtype_np, device=None):
@@ -315,26 +378,30 @@ class Context:
 
     # -- calls ---------------------------------------------------------------
 
+    def _csr(self, row_ptr, col, w):
+        """Checked CSR arguments: (dev, n, nnz, wide, row_ptr, col, w)."""
+        dev = _is_dev(row_ptr)
+        if row_ptr is None or col is None or w is None:
+            _bad("row_ptr, col and w must be given")
+        n = int(row_ptr.shape[0]) - 1 if hasattr(row_ptr, "shape") else len(row_ptr) - 1
+        if n < 0:
+            _bad("row_ptr needs at least one element")
+        nnz = int(col.shape[0]) if hasattr(col, "shape") else len(col)
+        wide = _weights_wide(w)
+        row_ptr = _arg(row_ptr, "row_ptr", "int64", n + 1, dev, self.device)
+        col = _arg(col, "col", "int32", nnz, dev, self.device)
+        w = _arg(w, "w", "int64" if wide else "int32", nnz, dev, self.device)
+        return dev, n, nnz, wide, row_ptr, col, w
+
     def graph_create(self, row_ptr, col, w, check_symmetry: bool = False) -> Graph:
-        dev = _is_torch(row_ptr) and row_ptr.is_cuda
-        if dev:
-            n = row_ptr.shape[0] - 1
-            nnz = col.shape[0]
-            wide = str(w.dtype) == "torch.int64"
-            keep = (row_ptr, col, w)
-        else:
-            row_ptr = _host(row_ptr, np.int64)
-            col = _host(col, np.int32)
-            wide = np.asarray(w).dtype == np.int64
-            w = _host(w, np.int64 if wide else np.int32)
-            n = row_ptr.shape[0] - 1
-            nnz = col.shape[0]
-            keep = (row_ptr, col, w)
+        """Copy a symmetric CSR graph (numpy arrays or torch CUDA tensors, all
+        of one kind) into the library."""
+        dev, n, nnz, wide, row_ptr, col, w = self._csr(row_ptr, col, w)
         flags = (LOUVAIN_DEVICE_PTRS if dev else 0) | (LOUVAIN_CHECK_SYMMETRY if check_symmetry else 0) \
             | (LOUVAIN_WEIGHTS_I64 if wide else 0)
         h = C.c_void_p()
-        self._check(self.lib.louvain_graph_create(self.h, n, nnz, _ptr(keep[0]), _ptr(keep[1]),
-                                                  _ptr(keep[2]), flags, C.byref(h)))
+        self._check(self.lib.louvain_graph_create(self.h, n, nnz, _ptr(row_ptr), _ptr(col),
+                                                  _ptr(w), flags, C.byref(h)))
         return Graph(self, h, dev)
 
     def set_tuning(self, small_max: int = 4, block_max: int = 2730, pass_batch: int = 2, group_slots: int = 4,
@@ -373,19 +440,11 @@ class Context:
 
         The arrays are kept referenced until the result is polled.  Device
         (torch) inputs must be complete on their streams before the call."""
-        dev = _is_torch(row_ptr) and row_ptr.is_cuda
-        if dev:
-            n = row_ptr.shape[0] - 1
-            nnz = col.shape[0]
-            wide = str(w.dtype) == "torch.int64"
+        dev, n, nnz, wide, row_ptr, col, w = self._csr(row_ptr, col, w)
+        if labels_out is None:
+            out = _empty_like_kind(dev, n, np.int32, self.torch_device)
         else:
-            row_ptr = _host(row_ptr, np.int64)
-            col = _host(col, np.int32)
-            wide = np.asarray(w).dtype == np.int64
-            w = _host(w, np.int64 if wide else np.int32)
-            n = row_ptr.shape[0] - 1
-            nnz = col.shape[0]
-        out = labels_out if labels_out is not None else _empty_like_kind(dev, n, np.int32, self.torch_device)
+            out = _arg(labels_out, "labels_out", "int32", n, dev, self.device, output=True)
         flags = (LOUVAIN_DEVICE_PTRS if dev else 0) | (LOUVAIN_CHECK_SYMMETRY if check_symmetry else 0) \
             | (LOUVAIN_WEIGHTS_I64 if wide else 0)
         prm = louvain_params(theta_num, theta_den, max_sweeps, max_levels, 1 if singlet_rule else 0, pass_batch,
@@ -413,16 +472,16 @@ class Context:
         return ServeResult(keep[3], res.q_int.value(), res.q, rc, levels, res.total_edges_swept,
                            res.t_submit_us, res.t_admit_us, res.t_done_us, res.error.decode(errors="replace"))
 
-    def _labels(self, labels, dev):
+    def _labels(self, labels, dev, n, name="labels"):
         if labels is None:
             return None
-        return labels if dev else _host(labels, np.int32)
+        return _arg(labels, name, "int32", n, dev, self.device)
 
     def local_move(self, g: Graph, labels=None, singlet_rule: bool = True, device: Optional[bool] = None):
         """One synchronous sweep: (labels_out, deg_C of labels_out, e_own)."""
         dev = g.dev if device is None else device
         n, _, _ = g.info()
-        lab = self._labels(labels, dev)
+        lab = self._labels(labels, dev, n)
         out = _empty_like_kind(dev, n, np.int32, self.torch_device)
         deg = _empty_like_kind(dev, n, np.int64, self.torch_device)
         eown = _empty_like_kind(dev, n, np.int64, self.torch_device)
@@ -433,7 +492,10 @@ class Context:
     def modularity(self, g: Graph, labels, device: Optional[bool] = None):
         """(Q_int, Q) of a labelling (eq. 3)."""
         dev = g.dev if device is None else device
-        lab = self._labels(labels, dev)
+        n, _, _ = g.info()
+        if labels is None:
+            _bad("labels must be given")
+        lab = self._labels(labels, dev, n)
         qi = louvain_i128()
         q = C.c_double()
         self._check(self.lib.louvain_modularity(self.h, g.h, _ptr(lab), C.byref(qi), C.byref(q),
@@ -444,7 +506,9 @@ class Context:
         """(contracted Graph, renumbered community of every vertex)."""
         dev = g.dev if device is None else device
         n, _, _ = g.info()
-        lab = self._labels(labels, dev)
+        if labels is None:
+            _bad("labels must be given")
+        lab = self._labels(labels, dev, n)
         ren = _empty_like_kind(dev, n, np.int32, self.torch_device)
         h = C.c_void_p()
         self._check(self.lib.louvain_aggregate(self.h, g.h, _ptr(lab), _ptr(ren), C.byref(h),
@@ -474,7 +538,10 @@ class Context:
         merge: apply the final merge after every phase that kept a sweep."""
         dev = g.dev if device is None else device
         n, _, _ = g.info()
-        out = labels_out if labels_out is not None else _empty_like_kind(dev, n, np.int32, self.torch_device)
+        if labels_out is None:
+            out = _empty_like_kind(dev, n, np.int32, self.torch_device)
+        else:
+            out = _arg(labels_out, "labels_out", "int32", n, dev, self.device, output=True)
         prm = louvain_params(theta_num, theta_den, max_sweeps, max_levels, 1 if singlet_rule else 0, pass_batch,
                              1 if merge else 0)
         qi = louvain_i128()
@@ -498,7 +565,9 @@ class Context:
         """Continue a run from the graph of level `levels_done` and the labels
         so far (one per original vertex); the result equals one run's."""
         dev = g_level.dev if device is None else device
-        lab = self._labels(labels_so_far, dev)
+        if labels_so_far is None:
+            _bad("labels_so_far must be given")
+        lab = self._labels(labels_so_far, dev, None, "labels_so_far")
         n0 = int(lab.shape[0])
         out = _empty_like_kind(dev, n0, np.int32, self.torch_device)
         prm = louvain_params(theta_num, theta_den, max_sweeps, max_levels, 1 if singlet_rule else 0, pass_batch,
@@ -526,11 +595,15 @@ class Context:
             return []
         dev = graphs[0].dev if device is None else device
         outs = []
+        if labels_out is not None and len(labels_out) != k:
+            _bad(f"labels_out has {len(labels_out)} arrays for {k} graphs")
         for i, g in enumerate(graphs):
+            if not isinstance(g, Graph) or g.ctx is not self or not g.h:
+                _bad(f"graphs[{i}] is not a live graph of this context")
+            n, _, _ = g.info()
             if labels_out is not None:
-                outs.append(labels_out[i])
+                outs.append(_arg(labels_out[i], f"labels_out[{i}]", "int32", n, dev, self.device, output=True))
             else:
-                n, _, _ = g.info()
                 outs.append(_empty_like_kind(dev, n, np.int32, self.torch_device))
         prm = louvain_params(theta_num, theta_den, max_sweeps, max_levels, 1 if singlet_rule else 0, pass_batch,
                              1 if merge else 0)

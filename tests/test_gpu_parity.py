@@ -214,6 +214,39 @@ def test_device_pointers(ctx):
     G.destroy()
 
 
+def test_binding_checks_device_tensors(ctx, L):
+    """Device arrays of the wrong dtype, length, layout or kind are refused
+    by the binding (EINVAL) before the library reads them."""
+    import torch
+    g = gg.config("sbm1k")
+    dev = torch.device("cuda", 0)
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    cl = torch.from_numpy(g.col).to(dev)
+    w = torch.from_numpy(g.w).to(dev)
+    bad = [
+        lambda: ctx.graph_create(rp.to(torch.int32), cl, w),                      # int32 row_ptr
+        lambda: ctx.graph_create(rp, cl.cpu(), w),                                # mixed kinds
+        lambda: ctx.graph_create(rp, torch.stack([cl, cl], 1)[:, 0], w),          # strided col
+        lambda: ctx.graph_create(rp, cl, w[:-1]),                                 # short weights
+    ]
+    for k, f in enumerate(bad):
+        with pytest.raises(L.LouvainError) as e:
+            f()
+        assert e.value.code == L.LOUVAIN_EINVAL, k
+    G = ctx.graph_create(rp, cl, w)
+    for labels in (torch.zeros(g.n - 1, dtype=torch.int32, device=dev),           # short
+                   torch.zeros(g.n, dtype=torch.int64, device=dev),               # int64
+                   np.zeros(g.n, np.int32)):                                      # host memory
+        with pytest.raises(L.LouvainError) as e:
+            ctx.modularity(G, labels)
+        assert e.value.code == L.LOUVAIN_EINVAL
+    with pytest.raises(L.LouvainError):
+        ctx.run(G, labels_out=torch.empty(g.n, dtype=torch.int32))                # CPU tensor as device output
+    r = ctx.run(G)   # the graph is unharmed
+    assert np.array_equal(r.labels.cpu().numpy(), oracle.louvain(g.row_ptr, g.col, g.w).labels)
+    G.destroy()
+
+
 def test_int64_weights(ctx):
     g = heavy_graph(seed=9)
     w64 = g.w.astype(np.int64) * 4096      # beyond int32
