@@ -25,7 +25,20 @@
  *   - All device work is enqueued on the context's HIP stream; a call
  *     returns after its outputs are complete (host outputs copied back,
  *     device outputs written, stream synchronised).
- *   - A context is not thread-safe: use one context per host thread.
+ *   - A context serves one host thread at a time: a call made while
+ *     another thread is inside a call on the same context returns
+ *     LOUVAIN_EBUSY and does nothing (louvain_submit / louvain_poll are
+ *     the exception: thread-safe).
+ *   - Device memory: every device allocation of a context comes from the
+ *     region given to louvain_ctx_create (sub-allocated, cached per stream),
+ *     or from hipMalloc when none was given.  With a region the library
+ *     allocates no device memory of its own: a call that needs more than
+ *     the region holds fails with LOUVAIN_ENOMEM and the context stays
+ *     usable.  Pinned host memory for read-backs is allocated separately.
+ *   - Fault injection: if the environment variable LOUVAIN_FAULT_ALLOC_AT
+ *     holds k > 0 when a context is created, the k-th device allocation
+ *     request of that context fails once with LOUVAIN_ENOMEM (tests of
+ *     the error paths).
  */
 #ifndef LOUVAIN_H
 #define LOUVAIN_H
@@ -43,6 +56,7 @@ extern "C" {
 #define LOUVAIN_ENOMEM    (-2)  /* device or host allocation failed             */
 #define LOUVAIN_EDEVICE   (-3)  /* HIP runtime error                            */
 #define LOUVAIN_EAGAIN    (-4)  /* poll: the request is still pending            */
+#define LOUVAIN_EBUSY     (-5)  /* another thread is inside a call on the context */
 #define LOUVAIN_ELIMIT    (-6)  /* max_sweeps / max_levels reached; result valid */
 #define LOUVAIN_EOVERFLOW (-7)  /* n >= 2^31 or TW >= 2^62                      */
 
@@ -126,10 +140,43 @@ typedef struct {
 /* ---- context ------------------------------------------------------------ */
 
 /* Create a context on HIP device `device` that enqueues its work on
- * `hip_stream` (a hipStream_t; NULL = the null stream).  The stream must
- * outlive the context.  *out receives the handle. */
-int louvain_ctx_create(int device, void *hip_stream, louvain_ctx *out);
+ * `hip_stream` (a hipStream_t; NULL = the null stream).
+ *   pool, pool_bytes: NULL and 0, or a region of device memory of `device`
+ *               (e.g. a torch tensor's storage) from which the context
+ *               sub-allocates every device buffer it uses: its graphs,
+ *               level state, temporaries and its request loop's buffers.
+ *               The caller keeps ownership; the region and the stream must
+ *               outlive the context and every graph or dendrogram handle
+ *               made on it.  Only pool_bytes rounded down to 256-byte
+ *               blocks are used.
+ *   tuning_path: NULL, or a file of launch shapes: read here when it
+ *               exists and was written for this device's architecture
+ *               (else the defaults apply), and rewritten by
+ *               louvain_autotune.
+ *   out:        receives the handle.
+ * Errors: EINVAL (NULL out, negative device, a pool that is not device
+ * memory of `device`, pool and pool_bytes not both set or both unset, a
+ * malformed tuning file), EDEVICE (no such device), ENOMEM. */
+int louvain_ctx_create(int device, void *hip_stream, void *pool, size_t pool_bytes, const char *tuning_path,
+                       louvain_ctx *out);
+/* Stops the context's request loop and frees the context.  EBUSY while
+ * another thread is inside a call on it. */
 int louvain_ctx_destroy(louvain_ctx ctx);
+
+/* Device-memory accounting of a context. */
+typedef struct {
+    uint64_t pool_bytes;       /* usable bytes of the caller's region (0: hipMalloc)       */
+    uint64_t pool_in_use;      /* region bytes handed to the context's caches              */
+    uint64_t pool_high_water;  /* largest pool_in_use since creation or the last reset     */
+    uint64_t live_bytes;       /* blocks of the context's own cache held by graphs, runs   */
+    uint64_t cached_bytes;     /* blocks of the context's own cache kept for reuse         */
+} louvain_memory;
+
+/* Read the accounting (the request loop's workers have caches of their
+ * own; their blocks count in pool_in_use only). */
+int louvain_memory_stats(louvain_ctx ctx, louvain_memory *out);
+/* Restart pool_high_water from the current pool_in_use. */
+int louvain_memory_reset_peak(louvain_ctx ctx);
 
 /* Message of the last failed call on ctx (never NULL; "" if none).  The
  * string is owned by ctx and valid until the next call on it. */
@@ -361,10 +408,11 @@ int louvain_get_tuning(louvain_ctx ctx, louvain_tuning *tuning);
  * (small_max in {4, 8}, block_max in {1365, 2730, 10922}, pass_batch in
  * {1, 2}, group_vertices in {1, 2}; group_slots 4, overlap as set), best
  * of two runs each; a candidate replaces the current setting only when it
- * is more than 2% faster, so that timing noise does not flip the setting
- * each, and makes the fastest the context's setting.  *best (optional)
- * receives it with its time.  Graphs with 2W >= 2^31 do not use these
- * shapes; the setting is left as it is and best->ms is -1.
+ * is more than 2% faster, so that timing noise does not flip the setting,
+ * and the pick becomes the context's setting.  *best (optional) receives
+ * it with its time.  When the context has a tuning file, the pick is
+ * written to it (replacing it atomically).  Graphs with 2W >= 2^31 do not
+ * use these shapes; the setting is left as it is and best->ms is -1.
  */
 int louvain_autotune(louvain_ctx ctx, louvain_graph g, const louvain_params *params, louvain_tuning *best);
 

@@ -12,7 +12,7 @@ from __future__ import annotations
 
 from ._native import (  # noqa: F401
     LOUVAIN_DEVICE_PTRS, LOUVAIN_CHECK_SYMMETRY, LOUVAIN_NO_SINGLET, LOUVAIN_WEIGHTS_I64,
-    LOUVAIN_OK, LOUVAIN_EINVAL, LOUVAIN_ENOMEM, LOUVAIN_EDEVICE, LOUVAIN_EAGAIN, LOUVAIN_ELIMIT, LOUVAIN_EOVERFLOW,
+    LOUVAIN_OK, LOUVAIN_EINVAL, LOUVAIN_ENOMEM, LOUVAIN_EDEVICE, LOUVAIN_EAGAIN, LOUVAIN_EBUSY, LOUVAIN_ELIMIT, LOUVAIN_EOVERFLOW,
     LIB_PATH, LouvainError, Context, Graph, Dendrogram, RunResult, ServeResult, load_library, exported_symbols,
     workspace_bytes,
 )

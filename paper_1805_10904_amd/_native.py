@@ -14,6 +14,7 @@ LOUVAIN_EINVAL = -1
 LOUVAIN_ENOMEM = -2
 LOUVAIN_EDEVICE = -3
 LOUVAIN_EAGAIN = -4
+LOUVAIN_EBUSY = -5
 LOUVAIN_ELIMIT = -6
 LOUVAIN_EOVERFLOW = -7
 
@@ -24,7 +25,8 @@ LOUVAIN_WEIGHTS_I64 = 0x8
 
 # Every symbol the header declares (checked by the CPU test-suite).
 ABI_SYMBOLS = (
-    "louvain_ctx_create", "louvain_ctx_destroy", "louvain_last_error",
+    "louvain_ctx_create", "louvain_ctx_destroy", "louvain_last_error", "louvain_memory_stats",
+    "louvain_memory_reset_peak",
     "louvain_graph_create", "louvain_graph_destroy", "louvain_graph_info", "louvain_graph_export",
     "louvain_local_move", "louvain_modularity", "louvain_aggregate", "louvain_run", "louvain_run_batch",
     "louvain_workspace_bytes", "louvain_serve_budget", "louvain_submit", "louvain_poll",
@@ -39,6 +41,11 @@ class louvain_i128(C.Structure):
 
     def value(self) -> int:
         return (int(self.hi) << 64) | int(self.lo)
+
+
+class louvain_memory(C.Structure):
+    _fields_ = [("pool_bytes", C.c_uint64), ("pool_in_use", C.c_uint64), ("pool_high_water", C.c_uint64),
+                ("live_bytes", C.c_uint64), ("cached_bytes", C.c_uint64)]
 
 
 class louvain_params(C.Structure):
@@ -97,7 +104,9 @@ def load_library(path: str = LIB_PATH):
         pass
     lib = C.CDLL(path)
     p, i64, u32, i32 = C.c_void_p, C.c_int64, C.c_uint32, C.c_int
-    lib.louvain_ctx_create.argtypes = [i32, p, C.POINTER(p)]
+    lib.louvain_ctx_create.argtypes = [i32, p, p, C.c_size_t, C.c_char_p, C.POINTER(p)]
+    lib.louvain_memory_stats.argtypes = [p, C.POINTER(louvain_memory)]
+    lib.louvain_memory_reset_peak.argtypes = [p]
     lib.louvain_ctx_destroy.argtypes = [p]
     lib.louvain_last_error.argtypes = [p]
     lib.louvain_last_error.restype = C.c_char_p
@@ -339,12 +348,21 @@ class Dendrogram:
 class Context:
     """A louvain_ctx on one HIP device, enqueuing on the given stream handle
     (default: torch's current stream on that device when torch has a GPU,
-    else the null stream)."""
+    else the null stream).
 
-    def __init__(self, device: int = 0, stream: Optional[int] = None):
+    pool_bytes: when given, a torch uint8 tensor of that many bytes is
+    allocated on the device and handed to the library, which then takes
+    every device buffer from it (LOUVAIN_ENOMEM when it runs out) and
+    allocates no device memory itself; the tensor lives as long as the
+    context.  tuning_path: a file of launch shapes, read when it exists and
+    rewritten by autotune()."""
+
+    def __init__(self, device: int = 0, stream: Optional[int] = None, pool_bytes: Optional[int] = None,
+                 tuning_path: Optional[str] = None):
         self.lib = load_library()
         self.device = device
         self.torch_device = None
+        self.pool = None
         try:
             import torch
             self.torch_device = torch.device("cuda", device)
@@ -352,12 +370,31 @@ class Context:
                 stream = torch.cuda.current_stream(self.torch_device).cuda_stream
         except ImportError:
             pass
+        pool_ptr = None
+        if pool_bytes is not None:
+            if int(pool_bytes) <= 0:
+                _bad("pool_bytes must be positive")
+            import torch
+            self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=self.torch_device)
+            torch.cuda.synchronize(self.torch_device)
+            pool_ptr = self.pool.data_ptr()
         h = C.c_void_p()
-        rc = self.lib.louvain_ctx_create(device, C.c_void_p(stream or 0), C.byref(h))
+        path = tuning_path.encode() if tuning_path else None
+        rc = self.lib.louvain_ctx_create(device, C.c_void_p(stream or 0), C.c_void_p(pool_ptr),
+                                         int(pool_bytes or 0), path, C.byref(h))
         if rc != LOUVAIN_OK:
             raise LouvainError(rc, "louvain_ctx_create failed")
         self.h = h
         self._inflight = {}
+
+    def memory(self) -> dict:
+        """Device-memory accounting (louvain_memory_stats)."""
+        m = louvain_memory()
+        self._check(self.lib.louvain_memory_stats(self.h, C.byref(m)))
+        return {k: int(getattr(m, k)) for k, _ in m._fields_}
+
+    def reset_peak(self):
+        self._check(self.lib.louvain_memory_reset_peak(self.h))
 
     def _check(self, rc: int, ok=(LOUVAIN_OK,)):
         if rc not in ok:
@@ -367,8 +404,10 @@ class Context:
 
     def close(self):
         if getattr(self, "h", None):
-            self.lib.louvain_ctx_destroy(self.h)
+            self._check(self.lib.louvain_ctx_destroy(self.h))
             self.h = None
+        # self.pool stays referenced: graphs made on the context (which keep
+        # the context object alive) may still hold blocks of it
 
     def __del__(self):
         try:

@@ -1,6 +1,9 @@
 // The C ABI (include/louvain.h): contexts, graphs, and the method's calls.
 #include <algorithm>
+#include <atomic>
 #include <cstdlib>
+#include <fstream>
+#include <sstream>
 #include <cstring>
 #include <memory>
 #include <mutex>
@@ -14,7 +17,11 @@
 #include "sweep.hpp"
 
 struct louvain_ctx_s {
-    std::shared_ptr<lv::Pool> pool = std::make_shared<lv::Pool>();   // destroyed last
+    std::shared_ptr<lv::Arena> arena;      // the caller's device region (nullptr: hipMalloc)
+    std::shared_ptr<lv::Pool> pool;        // destroyed last
+    std::string tuning_path;               // launch shapes persisted by louvain_autotune
+    std::atomic<long> owner{0};            // thread inside a call on the context (0: none)
+    int depth = 0;                         // nesting of the owner's calls
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
@@ -75,9 +82,36 @@ struct PoolScope {
     ~PoolScope() { lv::current_pool() = saved; }
 };
 
+// A small id per host thread (0 is never used).
+long thread_id() {
+    static std::atomic<long> next{1};
+    static thread_local long id = next++;
+    return id;
+}
+
+// Marks the calling thread as inside a call on ctx; a call from another
+// thread meanwhile is refused (LOUVAIN_EBUSY), one nested in it is not.
+struct CallScope {
+    louvain_ctx ctx;
+    bool entered = false;
+    explicit CallScope(louvain_ctx c) : ctx(c) {
+        const long me = thread_id();
+        long cur = 0;
+        if (ctx->owner.compare_exchange_strong(cur, me) || cur == me) {
+            ctx->depth++;
+            entered = true;
+        }
+    }
+    ~CallScope() {
+        if (entered && --ctx->depth == 0) ctx->owner.store(0);
+    }
+};
+
 template <typename F>
 int guarded(louvain_ctx ctx, F &&f) {
     if (!ctx) return LOUVAIN_EINVAL;
+    CallScope call(ctx);
+    if (!call.entered) return LOUVAIN_EBUSY;   // ctx->err belongs to the other thread's call
     PoolScope scope(ctx->pool.get());
     try {
         LV_HIP(hipSetDevice(ctx->device));
@@ -97,6 +131,108 @@ int guarded(louvain_ctx ctx, F &&f) {
         ctx->err = "unknown failure";
         return LOUVAIN_EDEVICE;
     }
+}
+
+// Launch shapes from the ABI's form, checked.
+lv::Tuning tuning_from(const louvain_tuning &t) {
+    require(t.small_max >= 1 && t.small_max <= 8, LOUVAIN_EINVAL, "small_max must be in [1, 8]");
+    require(t.block_max >= lv::kPackMaxDeg && t.block_max <= lv::kCompactBlockMax, LOUVAIN_EINVAL,
+            "block_max must be in [341, 10922]");
+    require(t.pass_batch >= 1 && t.pass_batch <= 64, LOUVAIN_EINVAL, "pass_batch must be in [1, 64]");
+    require(t.group_slots == 0 || t.group_slots == 2 || t.group_slots == 4 || t.group_slots == 8, LOUVAIN_EINVAL,
+            "group_slots must be 0, 2, 4 or 8");
+    require(t.group_vertices >= 0 && t.group_vertices <= 2, LOUVAIN_EINVAL, "group_vertices must be 0, 1 or 2");
+    require(t.overlap == 0 || t.overlap == 1, LOUVAIN_EINVAL, "overlap must be 0 or 1");
+    require(t.reorder >= 0 && t.reorder <= 2, LOUVAIN_EINVAL, "reorder must be 0, 1 or 2");
+    require(t.reserved == 0, LOUVAIN_EINVAL, "reserved must be 0");
+    lv::Tuning tn;
+    tn.small_max = t.small_max;
+    tn.block_max = t.block_max;
+    tn.pass_batch = t.pass_batch;
+    tn.group_slots = t.group_slots == 0 ? 4 : t.group_slots;
+    tn.group_vertices = t.group_vertices == 0 ? 1 : t.group_vertices;
+    tn.overlap = t.overlap;
+    tn.reorder = t.reorder;
+    return tn;
+}
+
+louvain_tuning tuning_to(const lv::Tuning &tn) {
+    louvain_tuning t;
+    memset(&t, 0, sizeof t);
+    t.small_max = tn.small_max;
+    t.block_max = (int32_t)tn.block_max;
+    t.pass_batch = tn.pass_batch;
+    t.group_slots = tn.group_slots;
+    t.group_vertices = tn.group_vertices;
+    t.overlap = tn.overlap;
+    t.reorder = tn.reorder;
+    return t;
+}
+
+// Architecture name of a device (the key of a tuning file).
+std::string device_arch(int device) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        (void)hipGetLastError();
+        return "unknown";
+    }
+    std::string a = prop.gcnArchName;
+    return a.empty() ? "unknown" : a;
+}
+
+// Tuning file: text lines "key value" -- "arch <name>" and one line per
+// launch-shape field.  Returns false when the file does not exist or was
+// written for another architecture (the defaults then stay); throws EINVAL
+// for a malformed file or values out of range.
+bool load_tuning(const std::string &path, const std::string &arch, lv::Tuning *out) {
+    std::ifstream f(path);
+    if (!f) return false;
+    louvain_tuning t = tuning_to(lv::Tuning());
+    std::string line, file_arch;
+    int line_no = 0;
+    while (std::getline(f, line)) {
+        ++line_no;
+        if (line.empty() || line[0] == '#') continue;
+        std::istringstream is(line);
+        std::string key;
+        is >> key;
+        if (key == "arch") {
+            is >> file_arch;
+            continue;
+        }
+        long long v = 0;
+        require((bool)(is >> v), LOUVAIN_EINVAL, path + ":" + std::to_string(line_no) + ": expected 'key value'");
+        if (key == "small_max") t.small_max = (int32_t)v;
+        else if (key == "block_max") t.block_max = (int32_t)v;
+        else if (key == "pass_batch") t.pass_batch = (int32_t)v;
+        else if (key == "group_slots") t.group_slots = (int32_t)v;
+        else if (key == "group_vertices") t.group_vertices = (int32_t)v;
+        else if (key == "overlap") t.overlap = (int32_t)v;
+        else if (key == "reorder") t.reorder = (int32_t)v;
+        else require(false, LOUVAIN_EINVAL, path + ":" + std::to_string(line_no) + ": unknown key '" + key + "'");
+    }
+    if (file_arch != arch) return false;
+    *out = tuning_from(t);
+    return true;
+}
+
+void save_tuning(const std::string &path, const std::string &arch, const lv::Tuning &tn, double ms) {
+    const std::string tmp = path + ".tmp";
+    {
+        std::ofstream f(tmp, std::ios::trunc);
+        require((bool)f, LOUVAIN_EINVAL, "cannot write the tuning file " + path);
+        f << "# launch shapes chosen by louvain_autotune (" << ms << " ms per run)\n";
+        f << "arch " << arch << "\n";
+        f << "small_max " << tn.small_max << "\n";
+        f << "block_max " << tn.block_max << "\n";
+        f << "pass_batch " << tn.pass_batch << "\n";
+        f << "group_slots " << tn.group_slots << "\n";
+        f << "group_vertices " << tn.group_vertices << "\n";
+        f << "overlap " << tn.overlap << "\n";
+        f << "reorder " << tn.reorder << "\n";
+        require((bool)f, LOUVAIN_EINVAL, "cannot write the tuning file " + path);
+    }
+    require(std::rename(tmp.c_str(), path.c_str()) == 0, LOUVAIN_EINVAL, "cannot replace the tuning file " + path);
 }
 
 bool device_ptrs(uint32_t flags) { return (flags & LOUVAIN_DEVICE_PTRS) != 0; }
@@ -537,28 +673,80 @@ int run_graph(louvain_ctx ctx, louvain_graph g, const louvain_params *params, in
 
 extern "C" {
 
-int louvain_ctx_create(int device, void *hip_stream, louvain_ctx *out) {
-    if (!out) return LOUVAIN_EINVAL;
-    louvain_ctx c = new (std::nothrow) louvain_ctx_s();
-    if (!c) return LOUVAIN_ENOMEM;
+int louvain_ctx_create(int device, void *hip_stream, void *pool, size_t pool_bytes, const char *tuning_path,
+                       louvain_ctx *out) {
+    if (!out || device < 0) return LOUVAIN_EINVAL;
+    if ((pool == nullptr) != (pool_bytes == 0)) return LOUVAIN_EINVAL;
     int count = 0;
-    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+    if (hipGetDeviceCount(&count) != hipSuccess || device >= count) {
         (void)hipGetLastError();
-        delete c;
-        return device < 0 ? LOUVAIN_EINVAL : LOUVAIN_EDEVICE;
+        return LOUVAIN_EDEVICE;
     }
-    c->device = device;
-    c->stream = (hipStream_t)hip_stream;
-    c->timer.stream = c->stream;
-    *out = c;
-    return LOUVAIN_OK;
+    try {
+        std::unique_ptr<louvain_ctx_s> c(new louvain_ctx_s());
+        c->device = device;
+        c->stream = (hipStream_t)hip_stream;
+        c->timer.stream = c->stream;
+        if (pool) {
+            // the region must be device memory of this device
+            hipPointerAttribute_t attr;
+            if (hipPointerGetAttributes(&attr, pool) != hipSuccess || attr.type != hipMemoryTypeDevice ||
+                attr.device != device) {
+                (void)hipGetLastError();
+                return LOUVAIN_EINVAL;
+            }
+            c->arena = std::make_shared<lv::Arena>(pool, pool_bytes);
+        }
+        c->pool = std::make_shared<lv::Pool>(c->arena);
+        if (const char *f = getenv("LOUVAIN_FAULT_ALLOC_AT")) c->pool->fault_at = atol(f);
+        if (tuning_path && *tuning_path) {
+            c->tuning_path = tuning_path;
+            lv::Tuning tn;
+            if (load_tuning(c->tuning_path, device_arch(device), &tn)) c->tuning = tn;
+        }
+        *out = c.release();
+        return LOUVAIN_OK;
+    } catch (const Error &e) {
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        return LOUVAIN_ENOMEM;
+    } catch (...) {
+        return LOUVAIN_EDEVICE;
+    }
 }
 
 int louvain_ctx_destroy(louvain_ctx ctx) {
     if (!ctx) return LOUVAIN_EINVAL;
+    if (ctx->owner.load() != 0) return LOUVAIN_EBUSY;
     (void)hipSetDevice(ctx->device);
     ctx->server.reset();   // stops the request loop first
     delete ctx;
+    return LOUVAIN_OK;
+}
+
+int louvain_memory_stats(louvain_ctx ctx, louvain_memory *out) {
+    if (!ctx || !out) return LOUVAIN_EINVAL;
+    memset(out, 0, sizeof *out);
+    {
+        std::lock_guard<std::mutex> lk(ctx->pool->mu);
+        out->live_bytes = ctx->pool->in_use;
+        out->cached_bytes = ctx->pool->cached;
+    }
+    if (ctx->arena) {
+        std::lock_guard<std::mutex> lk(ctx->arena->mu);
+        out->pool_bytes = ctx->arena->bytes;
+        out->pool_in_use = ctx->arena->in_use;
+        out->pool_high_water = ctx->arena->high;
+    }
+    return LOUVAIN_OK;
+}
+
+int louvain_memory_reset_peak(louvain_ctx ctx) {
+    if (!ctx) return LOUVAIN_EINVAL;
+    if (ctx->arena) {
+        std::lock_guard<std::mutex> lk(ctx->arena->mu);
+        ctx->arena->high = ctx->arena->in_use;
+    }
     return LOUVAIN_OK;
 }
 
@@ -810,44 +998,12 @@ int louvain_resume(louvain_ctx ctx, louvain_graph g, const louvain_params *param
 }
 
 int louvain_set_tuning(louvain_ctx ctx, const louvain_tuning *tuning) {
-    return guarded(ctx, [&] {
-        lv::Tuning tn;
-        if (tuning) {
-            require(tuning->small_max >= 1 && tuning->small_max <= 8, LOUVAIN_EINVAL, "small_max must be in [1, 8]");
-            require(tuning->block_max >= lv::kPackMaxDeg && tuning->block_max <= lv::kCompactBlockMax, LOUVAIN_EINVAL,
-                    "block_max must be in [341, 10922]");
-            require(tuning->pass_batch >= 1 && tuning->pass_batch <= 64, LOUVAIN_EINVAL,
-                    "pass_batch must be in [1, 64]");
-            require(tuning->group_slots == 0 || tuning->group_slots == 2 || tuning->group_slots == 4 ||
-                        tuning->group_slots == 8,
-                    LOUVAIN_EINVAL, "group_slots must be 0, 2, 4 or 8");
-            tn.small_max = tuning->small_max;
-            tn.block_max = tuning->block_max;
-            tn.pass_batch = tuning->pass_batch;
-            require(tuning->group_vertices >= 0 && tuning->group_vertices <= 2, LOUVAIN_EINVAL,
-                    "group_vertices must be 0, 1 or 2");
-            require(tuning->overlap == 0 || tuning->overlap == 1, LOUVAIN_EINVAL, "overlap must be 0 or 1");
-            require(tuning->reorder >= 0 && tuning->reorder <= 2, LOUVAIN_EINVAL, "reorder must be 0, 1 or 2");
-            require(tuning->reserved == 0, LOUVAIN_EINVAL, "reserved must be 0");
-            tn.group_slots = tuning->group_slots == 0 ? 4 : tuning->group_slots;
-            tn.group_vertices = tuning->group_vertices == 0 ? 1 : tuning->group_vertices;
-            tn.overlap = tuning->overlap;
-            tn.reorder = tuning->reorder;
-        }
-        ctx->tuning = tn;
-    });
+    return guarded(ctx, [&] { ctx->tuning = tuning ? tuning_from(*tuning) : lv::Tuning(); });
 }
 
 int louvain_get_tuning(louvain_ctx ctx, louvain_tuning *tuning) {
     if (!ctx || !tuning) return LOUVAIN_EINVAL;
-    memset(tuning, 0, sizeof *tuning);
-    tuning->small_max = ctx->tuning.small_max;
-    tuning->block_max = (int32_t)ctx->tuning.block_max;
-    tuning->pass_batch = ctx->tuning.pass_batch;
-    tuning->group_slots = ctx->tuning.group_slots;
-    tuning->group_vertices = ctx->tuning.group_vertices;
-    tuning->overlap = ctx->tuning.overlap;
-    tuning->reorder = ctx->tuning.reorder;
+    *tuning = tuning_to(ctx->tuning);
     return LOUVAIN_OK;
 }
 
@@ -858,7 +1014,7 @@ int louvain_autotune(louvain_ctx ctx, louvain_graph g, const louvain_params *par
         prm.pass_batch = 0;   // the candidates' pass batching applies
         if (g->tw >= lv::kCompactTwMax || g->n == 0) {
             if (best) {
-                louvain_get_tuning(ctx, best);
+                *best = tuning_to(ctx->tuning);
                 best->ms = -1.0;
             }
             return;
@@ -909,8 +1065,9 @@ int louvain_autotune(louvain_ctx ctx, louvain_graph g, const louvain_params *par
                         }
                     }
         ctx->tuning = pick;
+        if (!ctx->tuning_path.empty()) save_tuning(ctx->tuning_path, device_arch(ctx->device), pick, pick_ms);
         if (best) {
-            louvain_get_tuning(ctx, best);
+            *best = tuning_to(pick);
             best->ms = pick_ms;
         }
     });
@@ -959,6 +1116,10 @@ int louvain_submit(louvain_ctx ctx, int64_t n, int64_t nnz, const int64_t *row_p
             std::lock_guard<std::mutex> lk(ctx->serve_mu);
             if (!ctx->server) {
                 size_t budget = ctx->serve_budget;
+                if (budget == 0 && ctx->arena) {
+                    std::lock_guard<std::mutex> alk(ctx->arena->mu);
+                    budget = (ctx->arena->bytes - ctx->arena->in_use) / 10 * 8;
+                }
                 if (budget == 0) {
                     size_t free_b = 0, total_b = 0;
                     if (hipSetDevice(ctx->device) != hipSuccess || hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
@@ -967,7 +1128,7 @@ int louvain_submit(louvain_ctx ctx, int64_t n, int64_t nnz, const int64_t *row_p
                     }
                     budget = free_b / 10 * 8;
                 }
-                ctx->server.reset(new lv::Server(ctx->device, budget, ctx->tuning));
+                ctx->server.reset(new lv::Server(ctx->device, budget, ctx->tuning, ctx->arena));
             }
             srv = ctx->server.get();
         }

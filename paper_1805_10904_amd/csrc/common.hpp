@@ -7,12 +7,15 @@
 
 #include <cstdio>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <tuple>
 #include <type_traits>
 #include <vector>
 
+#include "arena.hpp"
 #include "louvain.h"
 
 namespace lv {
@@ -43,15 +46,29 @@ inline void require(bool ok, int code, const std::string &msg) {
 
 // ---------------------------------------------------------- device memory --
 
-// Caching device allocator of one context.  Blocks are rounded to size
-// classes (powers of two up to 1 MiB, multiples of 2 MiB above) and kept
-// for reuse until the pool dies.  All users enqueue on the context's single
-// stream, so a block handed back while kernels still use it is only reused
-// by work ordered after them.
+// Caching device allocator of one stream (a context's, or a request-loop
+// worker's).  Blocks are rounded to size classes (powers of two up to 1 MiB,
+// multiples of 2 MiB above) and kept for reuse until the pool dies.  All
+// users of a pool enqueue on its one stream, so a block handed back while
+// kernels still use it is only reused by work ordered after them; a block
+// goes back to the backing store only after a device-wide wait.  The lock
+// lets another thread release a block (the request loop's plain worker
+// releases requests ingested by the batched workers).
 struct Pool {
+    std::mutex mu;
+    std::shared_ptr<Arena> arena;   // nullptr: hipMalloc / hipFree
     std::multimap<size_t, void *> free_;
     std::map<void *, size_t> live_;
     size_t cached = 0, in_use = 0;
+    // fault injection: when > 0, the fault_at-th allocation request of this
+    // pool (counted from when it was set) fails with ENOMEM, once
+    long fault_at = 0, requests = 0;
+
+    explicit Pool(std::shared_ptr<Arena> a = nullptr) : arena(std::move(a)) {
+        if (arena) arena->attach(this);
+    }
+    Pool(const Pool &) = delete;
+    Pool &operator=(const Pool &) = delete;
 
     static size_t round(size_t b) {
         if (b <= 512) return 512;
@@ -63,31 +80,56 @@ struct Pool {
         const size_t g = (size_t)2 << 20;
         return (b + g - 1) / g * g;
     }
+    void *raw_get(size_t r) {
+        if (arena) return arena->get(r);
+        void *p = nullptr;
+        if (hipMalloc(&p, r) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return p;
+    }
+    void raw_put(void *p) {
+        if (arena) arena->put(p); else (void)hipFree(p);
+    }
     void *get(size_t bytes) {
         const size_t r = round(bytes);
-        auto it = free_.find(r);
-        void *p = nullptr;
-        if (it != free_.end()) {
-            p = it->second;
-            free_.erase(it);
-            cached -= r;
-        } else {
-            hipError_t e = hipMalloc(&p, r);
-            if (e != hipSuccess) {
-                (void)hipGetLastError();
-                trim();
-                e = hipMalloc(&p, r);
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            if (fault_at > 0 && ++requests == fault_at) {
+                fault_at = 0;
+                throw Error(LOUVAIN_ENOMEM, "injected failure of device allocation request " +
+                                                std::to_string(requests) + " (LOUVAIN_FAULT_ALLOC_AT)");
             }
-            if (e != hipSuccess) {
-                (void)hipGetLastError();
-                throw Error(LOUVAIN_ENOMEM, "device allocation of " + std::to_string(r) + " bytes failed");
+            auto it = free_.find(r);
+            if (it != free_.end()) {
+                void *p = it->second;
+                free_.erase(it);
+                cached -= r;
+                live_[p] = r;
+                in_use += r;
+                return p;
             }
         }
+        void *p = raw_get(r);
+        if (!p) {
+            trim();
+            p = raw_get(r);
+        }
+        if (!p && arena) {
+            arena->reclaim(this);
+            p = raw_get(r);
+        }
+        if (!p)
+            throw Error(LOUVAIN_ENOMEM, "device allocation of " + std::to_string(r) + " bytes failed" +
+                                            (arena ? " (the caller's pool is exhausted)" : ""));
+        std::lock_guard<std::mutex> lk(mu);
         live_[p] = r;
         in_use += r;
         return p;
     }
     void put(void *p) {
+        std::lock_guard<std::mutex> lk(mu);
         auto it = live_.find(p);
         if (it == live_.end()) return;
         free_.emplace(it->second, p);
@@ -95,20 +137,32 @@ struct Pool {
         in_use -= it->second;
         live_.erase(it);
     }
-    // Release every cached block (waits for the device first).
+    // Release every cached block to the backing store (waits for the device first).
     void trim() {
+        std::lock_guard<std::mutex> lk(mu);
         if (free_.empty()) return;
         (void)hipDeviceSynchronize();
-        for (auto &kv : free_) (void)hipFree(kv.second);
+        for (auto &kv : free_) raw_put(kv.second);
         free_.clear();
         cached = 0;
     }
     ~Pool() {
         (void)hipDeviceSynchronize();
-        for (auto &kv : free_) (void)hipFree(kv.second);
-        for (auto &kv : live_) (void)hipFree(kv.first);
+        for (auto &kv : free_) raw_put(kv.second);
+        for (auto &kv : live_) raw_put(kv.first);
+        if (arena) arena->detach(this);
     }
 };
+
+inline void Arena::reclaim(Pool *self) {
+    std::vector<Pool *> ps;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        ps = pools;
+    }
+    for (Pool *p : ps)
+        if (p != self) p->trim();
+}
 
 // The pool of the context whose call is running on this thread (set at the
 // C ABI boundary); nullptr means plain hipMalloc / hipFree.

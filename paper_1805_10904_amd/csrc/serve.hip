@@ -96,12 +96,15 @@ size_t Server::workspace_bytes(int64_t n, int64_t nnz) {
     return (size_t)b;
 }
 
-Server::Server(int device, size_t budget, const Tuning &tn) : device_(device), tuning_(tn), budget_(budget) {
-    for (int k = 0; k < 2; ++k) workers_.emplace_back(new Worker());
-    for (auto &w : workers_) {
-        Worker *wp = w.get();
-        w->th = std::thread([this, wp] { loop(wp); });
+Server::Server(int device, size_t budget, const Tuning &tn, std::shared_ptr<Arena> arena)
+    : device_(device), tuning_(tn), budget_(budget) {
+    for (int k = 0; k < kWorkers; ++k) {
+        pools_.emplace_back(new Pool(arena));
+        workers_.emplace_back(new Worker());
     }
+    for (int k = 0; k < kWorkers; ++k)
+        workers_[(size_t)k]->th = k == kPlain ? std::thread([this] { loop_plain(); })
+                                              : std::thread([this, k] { loop(k); });
 }
 
 Server::~Server() {
@@ -112,6 +115,8 @@ Server::~Server() {
     cv_work_.notify_all();
     for (auto &w : workers_)
         if (w->th.joinable()) w->th.join();
+    // requests still held release their blocks into the pools, which go last
+    all_.clear();
 }
 
 uint64_t Server::submit(std::unique_ptr<ServeRequest> r) {
@@ -122,7 +127,7 @@ uint64_t Server::submit(std::unique_ptr<ServeRequest> r) {
         std::lock_guard<std::mutex> lk(mu_);
         t = next_++;
         r->ticket = t;
-        workers_[r->nnz <= kSmallEntries ? 0 : 1]->incoming.push_back(r.get());
+        workers_[r->nnz <= kSmallEntries ? kSmall : kLarge]->incoming.push_back(r.get());
         all_[t] = std::move(r);
     }
     cv_work_.notify_all();
@@ -174,9 +179,68 @@ void Server::finish(ServeRequest *r) {
     cv_work_.notify_all();   // memory freed: the other worker may admit
 }
 
-void Server::loop(Worker *w) {
-    Pool pool;
-    current_pool() = &pool;
+void Server::fail(ServeRequest *r, int code, const std::string &msg) {
+    r->status = code;
+    r->err = msg;
+    finish(r);
+}
+
+// Graphs with 2W >= 2^31, ingested by a batched worker: the plain path, one
+// at a time, on this worker's stream.
+void Server::loop_plain() {
+    Worker *w = workers_[kPlain].get();
+    current_pool() = pools_[kPlain].get();
+    hipStream_t s = nullptr;
+    const bool ok =
+        hipSetDevice(device_) == hipSuccess && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+    Timer timer;
+    for (;;) {
+        ServeRequest *r = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(mu_);
+            cv_work_.wait(lk, [&] { return stop_ || !w->incoming.empty(); });
+            if (stop_) break;
+            r = w->incoming.front();
+            w->incoming.pop_front();
+        }
+        if (!ok) {
+            fail(r, LOUVAIN_EDEVICE, "the request loop could not set up its device stream");
+            continue;
+        }
+        try {
+            louvain_run_stats st;
+            r->status = run_plain(r->member.g0, r->prm, tuning_, s, timer, 0, r->d_fin.p, &r->q, &st);
+            for (int l = 0; l < st.levels; ++l) {
+                LevelRec rec;
+                rec.n = st.level[l].n;
+                rec.nnz = st.level[l].nnz;
+                rec.executed = st.level[l].sweeps_executed;
+                rec.accepted = st.level[l].sweeps_accepted;
+                rec.passes = st.level[l].gpu_passes;
+                rec.q = make_i128(st.level[l].q_int.lo, st.level[l].q_int.hi);
+                r->levels.push_back(rec);
+            }
+            r->edges_swept = st.total_edges_swept;
+            deliver(r, s);
+            finish(r);
+        } catch (const Error &e) {
+            (void)hipStreamSynchronize(s);
+            fail(r, e.code, e.what());
+        } catch (const std::exception &e) {
+            (void)hipStreamSynchronize(s);
+            fail(r, LOUVAIN_EDEVICE, e.what());
+        }
+    }
+    if (s) (void)hipStreamSynchronize(s);
+    for (ServeRequest *r : w->incoming) release_device(r);
+    w->incoming.clear();
+    if (s) (void)hipStreamDestroy(s);
+    current_pool() = nullptr;
+}
+
+void Server::loop(int k) {
+    Worker *w = workers_[(size_t)k].get();
+    current_pool() = pools_[(size_t)k].get();
     hipStream_t s = nullptr;
     bool ok = hipSetDevice(device_) == hipSuccess && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
     struct Lane {
@@ -187,11 +251,6 @@ void Server::loop(Worker *w) {
     std::vector<std::unique_ptr<Lane>> lanes;
     std::deque<ServeRequest *> queue;
     Timer timer;
-    auto fail = [&](ServeRequest *r, int code, const std::string &msg) {
-        r->status = code;
-        r->err = msg;
-        finish(r);
-    };
     auto busy = [&] {
         for (auto &l : lanes)
             if (!l->eng->idle()) return true;
@@ -242,22 +301,13 @@ void Server::loop(Worker *w) {
             try {
                 ingest(r, s);
                 if (r->tw >= kCompactTwMax) {
-                    // too heavy for the batch's compact words: the plain path, alone
-                    louvain_run_stats st;
-                    r->status = run_plain(r->member.g0, r->prm, tuning_, s, timer, 0, r->d_fin.p, &r->q, &st);
-                    for (int l = 0; l < st.levels; ++l) {
-                        LevelRec rec;
-                        rec.n = st.level[l].n;
-                        rec.nnz = st.level[l].nnz;
-                        rec.executed = st.level[l].sweeps_executed;
-                        rec.accepted = st.level[l].sweeps_accepted;
-                        rec.passes = st.level[l].gpu_passes;
-                        rec.q = make_i128(st.level[l].q_int.lo, st.level[l].q_int.hi);
-                        r->levels.push_back(rec);
+                    // too heavy for the batch's compact words: ingested (its stream
+                    // work is complete), handed to the plain worker
+                    {
+                        std::lock_guard<std::mutex> lk(mu_);
+                        workers_[kPlain]->incoming.push_back(r);
                     }
-                    r->edges_swept = st.total_edges_swept;
-                    deliver(r, s);
-                    finish(r);
+                    cv_work_.notify_all();
                     continue;
                 }
                 Lane *lane = nullptr;

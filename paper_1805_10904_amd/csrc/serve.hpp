@@ -6,8 +6,11 @@
 // footprints fit the shared memory budget, and every admitted graph joins
 // the worker's running batch at the next level boundary (continuous
 // batching: newcomers at level 0 are swept in the same launches as members
-// at deeper levels).  Results are identical to louvain_run on each graph
-// alone.
+// at deeper levels).  A graph whose total weight 2W reaches 2^31 cannot use
+// the batch's compact words; after its ingest it is handed to a third
+// worker that runs it on the plain path on its own stream, so the worker
+// that admitted it keeps stepping its batch meanwhile.  Results are
+// identical to louvain_run on each graph alone.
 #pragma once
 
 #include <condition_variable>
@@ -53,7 +56,8 @@ struct ServeRequest {
 
 class Server {
   public:
-    Server(int device, size_t budget, const Tuning &tn);
+    // arena: the context's backing store of device memory (nullptr: hipMalloc)
+    Server(int device, size_t budget, const Tuning &tn, std::shared_ptr<Arena> arena);
     ~Server();
     // Queue a request (thread-safe); returns its ticket.
     uint64_t submit(std::unique_ptr<ServeRequest> r);
@@ -76,11 +80,20 @@ class Server {
         std::thread th;
         std::deque<ServeRequest *> incoming;
     };
-    void loop(Worker *w);
+    void loop(int k);
+    void loop_plain();
     void finish(ServeRequest *r);
+    void fail(ServeRequest *r, int code, const std::string &msg);
+
+    // worker k: 0 small graphs, 1 large graphs (both batched), 2 graphs with
+    // 2W >= 2^31 (plain path, after their ingest by worker 0 or 1)
+    enum { kSmall = 0, kLarge = 1, kPlain = 2, kWorkers = 3 };
 
     int device_;
     Tuning tuning_;
+    // device pools of the workers; they outlive the threads and the requests
+    // (a request ingested by one worker may be released by the plain worker)
+    std::vector<std::unique_ptr<Pool>> pools_;
     std::mutex mu_;
     std::condition_variable cv_work_, cv_done_;
     std::unordered_map<uint64_t, std::unique_ptr<ServeRequest>> all_;

@@ -158,3 +158,63 @@ def test_served_failures_are_isolated(L):
     with pytest.raises(L.LouvainError):
         ctx.poll(tickets[0])          # retired
     ctx.close()
+
+
+def test_served_c5_sizes_mixed_with_small(L):
+    """Requests shaped like the served workload (Chung-Lu, 2e6..3.4e6 entries:
+    the large-graph worker), one of them reweighted so that 2W >= 2^31 (the
+    plain path), interleaved with small SBM requests (the small-graph
+    worker).  Every result equals the oracle's; both batched workers and the
+    plain worker hold requests at the same time; a request joins a worker
+    whose batch is already running; and the heavy request does not hold back
+    the large-graph worker."""
+    import os
+    oracle.set_threads(min(16, os.cpu_count() or 1))
+    large = gg.served_chunglu(3, first=0, n_lo=60_000, n_hi=250_000)    # 3.4e6, 1.0e6, 3.1e6 entries
+    large = [g for g in large if g.nnz > (1 << 20)] + gg.served_chunglu(1, first=5, n_lo=60_000, n_hi=250_000)
+    heavy = gg.served_chunglu(1, first=6, n_lo=60_000, n_hi=250_000)[0]
+    heavy = gg.Graph(heavy.n, heavy.row_ptr, heavy.col, (heavy.w.astype(np.int64) * 100).astype(np.int32),
+                     heavy.planted, "served_6_x100")
+    assert int(heavy.w.astype(np.int64).sum()) >= (1 << 31)
+    assert all(g.nnz > (1 << 20) for g in large + [heavy])
+    small = gg.batch_sbm(10, n_hi=20_000, first=700)
+    assert all(g.nnz <= (1 << 20) for g in small)
+    order = [("heavy", heavy), ("large", large[0])] + [("small", g) for g in small[:3]] + \
+        [("large", large[1])] + [("small", g) for g in small[3:6]] + [("large", large[2])] + \
+        [("small", g) for g in small[6:]]
+    ctx = L.Context(0)
+    tickets = []
+    for k, (kind, g) in enumerate(order):
+        tickets.append(ctx.submit(g.row_ptr, g.col, g.w))
+        if k % 2 == 1:
+            time.sleep(0.002)
+    _say(f"submitted {len(tickets)} requests ({sum(g.nnz for _, g in order)} entries)")
+    res = _drain(ctx, tickets, timeout_s=180.0)
+    for k, ((kind, g), t) in enumerate(zip(order, tickets)):
+        _check(g, res[t], f"request {k} ({kind} {g.name}, nnz {g.nnz})")
+        assert res[t].t_submit_us <= res[t].t_admit_us <= res[t].t_done_us
+    _say("every served result equals the oracle's")
+    span = {t: (res[t].t_admit_us, res[t].t_done_us) for t in tickets}
+    kinds = [kind for kind, _ in order]
+    by = {kd: [t for t, k2 in zip(tickets, kinds) if k2 == kd] for kd in ("heavy", "large", "small")}
+
+    def inside(a, b):   # request a admitted while request b was resident
+        return span[b][0] < span[a][0] < span[b][1]
+
+    # the large-graph worker admitted the next request while the heavy one ran
+    assert inside(by["large"][0], by["heavy"][0]), "the heavy request blocked the large-graph worker"
+    # the two batched workers held requests at the same time
+    assert any(inside(s, lg) for s in by["small"] for lg in by["large"]), "workers never overlapped"
+    # a request joined a worker whose batch was already running (a later
+    # arrival admitted while an earlier request of the same worker was resident)
+    joined = [(a, b) for kd in ("large", "small") for i, b in enumerate(by[kd]) for a in by[kd][i + 1:]
+              if inside(a, b) and span[a][0] > span[b][0] + 500.0]
+    assert joined, "no request joined a running batch"
+    # the same graphs through the plain call
+    for kind, g in (order[0], order[1]):
+        G = ctx.graph_create(g.row_ptr, g.col, g.w)
+        a = ctx.run(G)
+        t = tickets[[x for x, _ in order].index(kind)]
+        assert np.array_equal(a.labels, res[t].labels) and a.q_int == res[t].q_int
+        G.destroy()
+    ctx.close()
