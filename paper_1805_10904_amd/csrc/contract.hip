@@ -142,33 +142,53 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint64_t *__restrict__
     hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter of one 8-bit digit: the block's keys keep their order
-// inside each digit (items visited in index order: k, then wave, then lane).
+// Stable scatter of one 8-bit digit of a tile of kRadixTile items.  Wave w
+// ranks the tile's items [w * 1024, (w + 1) * 1024) in rounds of 64
+// consecutive items: lanes with equal digits find each other by ballots,
+// and the group's first lane takes the wave's running count of that digit
+// from LDS, so every item's rank among the wave's items of its digit keeps
+// index order.  The tile is then laid out in digit order in LDS (digit
+// offsets of the tile, then of the wave), and thread t writes positions t,
+// t + 256, ... of that layout: consecutive threads write consecutive
+// entries of one digit's output run, so the global writes coalesce.  Keys
+// and values pass through the same LDS buffer one after the other.
+constexpr int kRadixWaveItems = kRadixTile / 4;
+
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t *__restrict__ kin,
                                                        const int64_t *__restrict__ vin, uint64_t *kout,
                                                        int64_t *vout, int64_t m, int shift,
                                                        const int64_t *__restrict__ offs, int64_t nblocks) {
-    __shared__ int64_t s_base[256];
-    __shared__ int32_t s_run[256];
-    __shared__ int32_t s_wc[4][256];
+    __shared__ int64_t s_base[256];        // output position of the tile's first item of digit d
+    __shared__ int32_t s_cnt[4][256];      // wave w's items of digit d, then their offset in the digit's run
+    __shared__ int32_t s_off[256];         // first position of digit d in the tile's digit-ordered layout
+    __shared__ int32_t s_wsum[4];
+    __shared__ uint64_t s_stage[kRadixTile];
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     s_base[t] = offs[(int64_t)t * nblocks + blockIdx.x];
-    s_run[t] = 0;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) s_wc[w][t] = 0;
+    for (int w = 0; w < 4; ++w) s_cnt[w][t] = 0;
     __syncthreads();
+    const int64_t tile0 = (int64_t)blockIdx.x * kRadixTile;
+    const int64_t base = tile0 + (int64_t)wid * kRadixWaveItems;
+    const int tile_count = (int)(m - tile0 < kRadixTile ? m - tile0 : kRadixTile);
     const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    uint64_t key[kRadixItems];
+    int64_t val[kRadixItems];
+    int32_t rank[kRadixItems];
+#pragma unroll
     for (int k = 0; k < kRadixItems; ++k) {
-        const int64_t e = base + k * 256 + t;
-        const bool valid = e < m;
-        uint64_t key = 0;
-        int64_t val = 0;
-        if (valid) {
-            key = kin[e];
-            val = vin[e];
+        const int64_t e = base + k * 64 + lane;
+        key[k] = 0;
+        val[k] = 0;
+        if (e < m) {
+            key[k] = kin[e];
+            val[k] = vin[e];
         }
-        const int d = (int)((key >> shift) & 255);
+    }
+#pragma unroll
+    for (int k = 0; k < kRadixItems; ++k) {
+        const bool valid = base + k * 64 + lane < m;
+        const int d = (int)((key[k] >> shift) & 255);
         unsigned long long peers = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -176,30 +196,68 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t *__restric
             const unsigned long long mb = __ballot(bit);
             peers &= bit ? mb : ~mb;
         }
-        const int rank = __popcll(peers & lt);
-        if (valid && rank == 0) s_wc[wid][d] = __popcll(peers);
-        __syncthreads();
-        {
-            int run = s_run[t];
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                const int c = s_wc[w][t];
-                s_wc[w][t] = run;
-                run += c;
-            }
-            s_run[t] = run;
+        const int before = __popcll(peers & lt);
+        int run = 0;
+        if (valid && before == 0) {   // the group's first lane: the wave's count of digit d so far
+            run = s_cnt[wid][d];
+            s_cnt[wid][d] = run + __popcll(peers);
         }
-        __syncthreads();
-        if (valid) {
-            const int64_t pos = s_base[d] + s_wc[wid][d] + rank;
-            kout[pos] = key;
-            vout[pos] = val;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int w = 0; w < 4; ++w) s_wc[w][t] = 0;
-        __syncthreads();
+        const int leader = valid ? __ffsll((long long)peers) - 1 : lane;
+        run = __shfl(run, leader);
+        rank[k] = run + before;
     }
+    __syncthreads();
+    // digit t: the waves' offsets inside the tile's run of t, and the run's start
+    int total = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const int c = s_cnt[w][t];
+        s_cnt[w][t] = total;
+        total += c;
+    }
+    int x = total;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) s_wsum[wid] = x;
+    __syncthreads();
+    int wbase = 0;
+    for (int w = 0; w < wid; ++w) wbase += s_wsum[w];
+    s_off[t] = wbase + x - total;
+    __syncthreads();
+    int32_t lpos[kRadixItems];
+#pragma unroll
+    for (int k = 0; k < kRadixItems; ++k) {
+        lpos[k] = -1;
+        if (base + k * 64 + lane < m) {
+            const int d = (int)((key[k] >> shift) & 255);
+            lpos[k] = s_off[d] + s_cnt[wid][d] + rank[k];
+            s_stage[lpos[k]] = key[k];
+        }
+    }
+    __syncthreads();
+    int64_t gpos[kRadixItems];
+#pragma unroll
+    for (int j = 0; j < kRadixItems; ++j) {
+        const int p = j * 256 + t;
+        gpos[j] = -1;
+        if (p < tile_count) {
+            const uint64_t kk = s_stage[p];
+            const int d = (int)((kk >> shift) & 255);
+            gpos[j] = s_base[d] + (p - s_off[d]);
+            kout[gpos[j]] = kk;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kRadixItems; ++k)
+        if (lpos[k] >= 0) s_stage[lpos[k]] = (uint64_t)val[k];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kRadixItems; ++j)
+        if (gpos[j] >= 0) vout[gpos[j]] = (int64_t)s_stage[j * 256 + t];
 }
 
 __global__ void k_heads(const uint64_t *__restrict__ keys, int64_t m, int32_t *head) {
@@ -1108,17 +1166,33 @@ __global__ __launch_bounds__(256) void k_sq_partials(const int64_t *__restrict__
     }
 }
 
-i128 modularity_int(const GraphView &g, const int32_t *labels, hipStream_t s, Timer *t) {
+size_t modularity_ws_bytes(int64_t n) {
+    const int64_t nb = (n + 2047) / 2048;
+    return (size_t)n * sizeof(int64_t) + (size_t)(2 * nb + 4) * sizeof(uint64_t);
+}
+
+i128 modularity_int(const GraphView &g, const int32_t *labels, hipStream_t s, Timer *t, void *ws) {
     if (g.n == 0 || g.tw == 0) return 0;
     const int64_t nb = (g.n + 2047) / 2048;
-    TempBuf deg((size_t)g.n * sizeof(int64_t), s);
-    TempBuf part((size_t)(2 * nb + 4) * sizeof(uint64_t), s);
-    uint64_t *acc = part.as<uint64_t>() + 2 * nb;      // I
-    uint64_t *tot = acc + 2;                           // sum deg^2
-    fill<int64_t>(deg.as<int64_t>(), 0, g.n, s);
+    TempBuf deg_buf, part_buf;
+    int64_t *deg_p;
+    uint64_t *part_p;
+    if (ws) {
+        // the caller's workspace: deg_C (n words), then the partial sums
+        deg_p = (int64_t *)ws;
+        part_p = (uint64_t *)(deg_p + g.n);
+    } else {
+        deg_buf = TempBuf((size_t)g.n * sizeof(int64_t), s);
+        part_buf = TempBuf((size_t)(2 * nb + 4) * sizeof(uint64_t), s);
+        deg_p = deg_buf.as<int64_t>();
+        part_p = part_buf.as<uint64_t>();
+    }
+    uint64_t *acc = part_p + 2 * nb;      // I
+    uint64_t *tot = acc + 2;              // sum deg^2
+    fill<int64_t>(deg_p, 0, g.n, s);
     fill<uint64_t>(acc, 0, 1, s);
     TimedLaunch tl(t, TG_OTHER, "modularity", (double)g.nnz * 16 + (double)g.n * 24);
-    tl.launch(k_label_degrees, grid_for(g.n, 256), 256, 0, s, labels, g.delta, g.n, deg.as<int64_t>());
+    tl.launch(k_label_degrees, grid_for(g.n, 256), 256, 0, s, labels, g.delta, g.n, deg_p);
     LV_LAUNCHED("k_label_degrees");
     if (g.nnz > 0) {
         const int64_t eb = (g.nnz + kEntriesPerBlock - 1) / kEntriesPerBlock;
@@ -1130,9 +1204,9 @@ i128 modularity_int(const GraphView &g, const int32_t *labels, hipStream_t s, Ti
                       (const int64_t *)g.w, labels, (unsigned long long *)acc);
         LV_LAUNCHED("k_inner_weight");
     }
-    tl.launch(k_sq_partials, (unsigned)nb, 256, 0, s, deg.as<int64_t>(), g.n, part.as<uint64_t>());
+    tl.launch(k_sq_partials, (unsigned)nb, 256, 0, s, deg_p, g.n, part_p);
     LV_LAUNCHED("k_sq_partials");
-    sum_i128_partials(part.as<uint64_t>(), nb, tot, s);
+    sum_i128_partials(part_p, nb, tot, s);
     uint64_t h[4];
     LV_HIP(hipMemcpyAsync(h, acc, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     LV_HIP(hipStreamSynchronize(s));

@@ -84,6 +84,10 @@ std::vector<i128> modularity_by_graph(const GraphView &u, const int32_t *labels,
                                       const std::vector<int64_t> &tw, hipStream_t s, Timer *t);
 
 // Q_int = TW*I - sum_C deg_C^2 of labels (device int32[n] in [0, n)).
-i128 modularity_int(const GraphView &g, const int32_t *labels, hipStream_t s, Timer *t);
+// Q_int of a labelling (eq. 3).  ws: optional device workspace of
+// modularity_ws_bytes(n) bytes (256-byte aligned) used instead of pool
+// temporaries.
+i128 modularity_int(const GraphView &g, const int32_t *labels, hipStream_t s, Timer *t, void *ws = nullptr);
+size_t modularity_ws_bytes(int64_t n);
 
 }  // namespace lv
