@@ -1137,6 +1137,7 @@ void Sweeper::replan_active(const GraphView &g) { plan_impl(g, true); }
 void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     n_ = g.n;
     compact_ = batch_ || g.tw < kCompactTwMax;   // before anything that depends on the level's kind
+    general_classes_ = false;
     const int small_max = compact_ ? tuning_.small_max : (int)kBucketMax[B_T8];
     const int64_t block_max = compact_ ? tuning_.block_max : lds_row_max(g.n, g.tw, tuning_);
     const int32_t *skip_gid = active_only && batch_ ? gid_ : nullptr;
@@ -1189,6 +1190,13 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
         glist_.reserve((size_t)(nl > 0 ? nl : 1));
         ginfo_.reserve((size_t)(nl > 0 ? nl : 1));
         compact_classes(g.row_ptr, list_.p + bstart_[B_T16], nl, glist_.p, ginfo_.p, cstart_, cnnz_, s_, t_);
+    } else if (g.tw > kTwFastMax) {
+        // 128-bit scores: rows small_max + 1 .. block_max swept by table-size class
+        const int64_t nl = bstart_[B_HUB] - bstart_[B_T16];
+        glist_.reserve((size_t)(nl > 0 ? nl : 1));
+        ginfo_.reserve((size_t)(nl > 0 ? nl : 1));
+        compact_classes(g.row_ptr, list_.p + bstart_[B_T16], nl, glist_.p, ginfo_.p, cstart_, cnnz_, s_, t_);
+        general_classes_ = true;
     } else if (pack_count_ > 0 && g.tw <= kTwFastMax) {
         TempBuf cost((size_t)pack_count_ * sizeof(int32_t), s_);
         k_pack_cost<<<grid_for(pack_count_, 256), 256, 0, s_>>>(g.row_ptr, list_.p + bstart_[B_T16], pack_count_,
@@ -1389,12 +1397,23 @@ __global__ __launch_bounds__(kWideThreads) void k_sweep_wide(SweepArgs a, const 
     }
 }
 
+// Rows swept from LDS on levels with 128-bit scores, sorted by table size
+// (the classes of the compact levels: S = 16 << c slots for c < 6, then
+// 2,048, 4,096 and 16,384): class c goes to k_sweep_group with 4 slots per
+// lane (8 for c = 5), so a row's table and lane group fit its length.
+struct ClassLists {
+    const int32_t *list = nullptr;              // nullptr: sweep by degree buckets
+    const int64_t *cstart = nullptr;            // kLdsClasses + 1 offsets into list
+    const int64_t *cnnz = nullptr;              // entries of every class
+};
+
 template <typename W, typename S>
 static void launch_pass(const SweepArgs &a, const int32_t *list, const int64_t *bstart,
                         const int64_t *bnnz, const int64_t *pack_pos, const int64_t *pack_first,
                         int64_t pack_blocks, HubMeta hm,
                         int64_t hub_chunks, int64_t hub_scans, int32_t *hkey, unsigned long long *hval,
-                        unsigned long long *hloop, uint64_t *hpart, hipStream_t s, Timer *t) {
+                        unsigned long long *hloop, uint64_t *hpart, hipStream_t s, Timer *t,
+                        const ClassLists &cl = ClassLists()) {
     const std::string sfx = t ? std::string(type_name<W>()) + "," + type_name<S>() + ">" : std::string();
     const std::string wsfx = t ? std::string(type_name<W>()) + ">" : std::string();
     const std::string ssfx = t ? std::string(type_name<S>()) + ">" : std::string();
@@ -1419,6 +1438,34 @@ static void launch_pass(const SweepArgs &a, const int32_t *list, const int64_t *
             tl.launch(k_sweep_group<256, 11, W, S>, (unsigned)cnt(B_BLOCK), 256, 0, s, a, list + bstart[B_BLOCK],
                       cnt(B_BLOCK));
             LV_LAUNCHED("k_sweep_group<256>");
+        }
+    } else if (cl.list) {
+        if (cnt(B_T8) > 0) {
+            TimedLaunch tl(t, TG_SWEEP, "k_sweep_group<4,4,", bytes(B_T8), sfx.c_str());
+            tl.launch(k_sweep_group<4, 4, W, S>, grid_for(cnt(B_T8), 64), 256, 0, s, a, list + bstart[B_T8], cnt(B_T8));
+            LV_LAUNCHED("k_sweep_group<4>");
+        }
+        auto ccount = [&](int c) { return cl.cstart[c + 1] - cl.cstart[c]; };
+        auto cbytes = [&](int c) { return (double)ccount(c) * vb + (double)cl.cnnz[c] * eb; };
+        auto group = [&](auto kernel, int c, int per_block, const char *name) {
+            if (ccount(c) <= 0) return;
+            TimedLaunch tl(t, TG_SWEEP, name, cbytes(c), sfx.c_str());
+            tl.launch(kernel, grid_for(ccount(c), per_block), 256, 0, s, a, cl.list + cl.cstart[c], ccount(c));
+            LV_LAUNCHED(name);
+        };
+        group(k_sweep_group<4, 4, W, S>, 0, 64, "k_sweep_group<4,4,");
+        group(k_sweep_group<8, 5, W, S>, 1, 32, "k_sweep_group<8,5,");
+        group(k_sweep_group<16, 6, W, S>, 2, 16, "k_sweep_group<16,6,");
+        group(k_sweep_group<32, 7, W, S>, 3, 8, "k_sweep_group<32,7,");
+        group(k_sweep_group<64, 8, W, S>, 4, 4, "k_sweep_group<64,8,");
+        group(k_sweep_group<64, 9, W, S>, 5, 4, "k_sweep_group<64,9,");
+        group(k_sweep_group<256, 11, W, S>, 6, 1, "k_sweep_group<256,11,");
+        group(k_sweep_group<256, 12, W, S>, 7, 1, "k_sweep_group<256,12,");
+        const int c8 = kLdsClasses - 1;
+        if (ccount(c8) > 0) {   // rows up to kBucketMax[B_WIDE]: only when a.hub_shift > 0
+            TimedLaunch tl(t, TG_SWEEP, "k_sweep_wide<", cbytes(c8), sfx.c_str());
+            tl.launch(k_sweep_wide<W, S>, (unsigned)ccount(c8), kWideThreads, 0, s, a, cl.list + cl.cstart[c8]);
+            LV_LAUNCHED("k_sweep_wide");
         }
     } else {
         if (cnt(B_T8) > 0) {
@@ -1445,7 +1492,7 @@ static void launch_pass(const SweepArgs &a, const int32_t *list, const int64_t *
             LV_LAUNCHED("k_sweep_group<256>");
         }
     }
-    if (cnt(B_WIDE) > 0) {   // only bucketed when a.hub_shift > 0
+    if (!cl.list && cnt(B_WIDE) > 0) {   // only bucketed when a.hub_shift > 0
         TimedLaunch tl(t, TG_SWEEP, "k_sweep_wide<", bytes(B_WIDE), sfx.c_str());
         tl.launch(k_sweep_wide<W, S>, (unsigned)cnt(B_WIDE), kWideThreads, 0, s, a, list + bstart[B_WIDE]);
         LV_LAUNCHED("k_sweep_wide");
@@ -1548,20 +1595,26 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
     HubMeta hm{list_.p + bstart_[B_HUB], tab_off, tab_off + (hubs_ + 1), tab_off + 2 * (hubs_ + 1),
                tab_off + 3 * (hubs_ + 1), hub_of_chunk_.p, hub_of_scan_.p, hubs_};
     const bool fast = g.tw <= kTwFastMax;
+    ClassLists cls;
+    if (general_classes_) {
+        cls.list = glist_.p;
+        cls.cstart = cstart_;
+        cls.cnnz = cnnz_;
+    }
     if (g.wbytes == 4) {
         if (fast)
             launch_pass<int32_t, int64_t>(a, list_.p, bstart_, bucket_nnz_, pack_pos_.p, pack_first_.p, pack_blocks_, hm, hub_chunks_, hub_scans_,
                                           hub_key_.p, hub_val_.p, hub_loop_.p, hub_part_.p, s_, t_);
         else
             launch_pass<int32_t, i128>(a, list_.p, bstart_, bucket_nnz_, pack_pos_.p, pack_first_.p, pack_blocks_, hm, hub_chunks_, hub_scans_,
-                                       hub_key_.p, hub_val_.p, hub_loop_.p, hub_part_.p, s_, t_);
+                                       hub_key_.p, hub_val_.p, hub_loop_.p, hub_part_.p, s_, t_, cls);
     } else {
         if (fast)
             launch_pass<int64_t, int64_t>(a, list_.p, bstart_, bucket_nnz_, pack_pos_.p, pack_first_.p, pack_blocks_, hm, hub_chunks_, hub_scans_,
                                           hub_key_.p, hub_val_.p, hub_loop_.p, hub_part_.p, s_, t_);
         else
             launch_pass<int64_t, i128>(a, list_.p, bstart_, bucket_nnz_, pack_pos_.p, pack_first_.p, pack_blocks_, hm, hub_chunks_, hub_scans_,
-                                       hub_key_.p, hub_val_.p, hub_loop_.p, hub_part_.p, s_, t_);
+                                       hub_key_.p, hub_val_.p, hub_loop_.p, hub_part_.p, s_, t_, cls);
     }
     if (g.n > 0) {
         TimedLaunch tl(t_, TG_SWEEP, "k_commit", (double)g.n * 8);

@@ -233,6 +233,7 @@ class Sweeper {
     DevBuf<uint64_t> ginfo_;        // compact: their row start << 12 | length
     int64_t cstart_[kLdsClasses + 1] = {0};
     int64_t cnnz_[kLdsClasses] = {0};
+    bool general_classes_ = false;  // a level with 128-bit scores swept by table-size class
     DevBuf<int32_t> bcount_;        // bucketing scratch (per-block counts / offsets)
     DevBuf<PhaseState> st_;
     DevBuf<uint64_t> qpart_;        // per-block partial sums of deg^2 (lo, hi)
