@@ -101,7 +101,10 @@ def percentile(xs, q):
 
 def bench_batched(L, torch, graphs, warmup: int, profile: bool = False, tuning=None):
     """One louvain_run_batch call against the plain louvain_run loop on the
-    same device-resident graphs; outputs must be identical."""
+    same device-resident graphs; outputs must be identical.  The plain loop
+    runs with the plain workload's launch shapes (`tuning`), the batched
+    call with shapes tuned on the batched workload itself (a batched call
+    over every 16th graph, coordinate descent over the shape fields)."""
     ctx = L.Context(0)
     if tuning:
         ctx.set_tuning(**tuning)
@@ -110,21 +113,31 @@ def bench_batched(L, torch, graphs, warmup: int, profile: bool = False, tuning=N
     out_p = [torch.empty(g.n, dtype=torch.int32, device=dev) for g in graphs]
     out_b = [torch.empty(g.n, dtype=torch.int32, device=dev) for g in graphs]
     torch.cuda.synchronize()
-    for _ in range(warmup):
-        ctx.run_batch(Gs, labels_out=out_b, stats=False)
+    for G, o in zip(Gs[:64], out_p):      # warm-up of the plain path
+        ctx.run(G, labels_out=o, device=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plain = [ctx.run(G, labels_out=o) for G, o in zip(Gs, out_p)]
+    plain = [ctx.run(G, labels_out=o, device=True) for G, o in zip(Gs, out_p)]
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    t = time.time()
+    sample = Gs[::16] if len(Gs) >= 64 else Gs
+    best = ctx.autotune_batch(sample)
+    tuned = ctx.get_tuning()
+    tune_s = time.time() - t
+    log(f"batched: autotuned on {len(sample)} graphs in {tune_s:.1f}s: {tuned} ({best['ms']:.2f} ms per call)")
+    for _ in range(warmup):
+        ctx.run_batch(Gs, labels_out=out_b, stats=False, device=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    res = ctx.run_batch(Gs, labels_out=out_b, stats=True)
+    res = ctx.run_batch(Gs, labels_out=out_b, stats=True, device=True)
     torch.cuda.synchronize()
-    t2 = time.perf_counter()
+    tb = time.perf_counter() - t1
     same = all(torch.equal(a, b) for a, b in zip(out_p, out_b)) and \
         all(p.q_int == r.q_int for p, r in zip(plain, res))
     edges = sum(lv["sweeps_executed"] * lv["nnz"] for r in res for lv in r.stats["levels"])
     if profile:
-        pr = ctx.run_batch(Gs, labels_out=out_b, stats=True, timing=True)
+        pr = ctx.run_batch(Gs, labels_out=out_b, stats=True, timing=True, device=True)
         ks = sorted(pr[0].stats["kernels"].items(), key=lambda kv: -kv[1]["ms"])
         log(f"batched call with kernel timing: {pr[0].stats['ms_total']:.1f} ms device, kernels " +
             ", ".join(f"{n} {k['ms']:.1f} ms/{k['launches']}" for n, k in ks[:14]))
@@ -136,54 +149,70 @@ def bench_batched(L, torch, graphs, warmup: int, profile: bool = False, tuning=N
     for G in Gs:
         G.destroy()
     ctx.close()
-    tp, tb = t1 - t0, t2 - t1
     return {"graphs": len(graphs), "n_total": int(sum(g.n for g in graphs)),
             "nnz_total": int(sum(g.nnz for g in graphs)), "edges_swept": int(edges),
             "plain_s": round(tp, 4), "batched_s": round(tb, 4), "speedup": round(tp / tb, 3),
             "batched_gteps": round(edges / tb / 1e9, 4), "plain_gteps": round(edges / tp / 1e9, 4),
-            "identical_outputs": bool(same)}
+            "launch_shapes": tuned, "plain_launch_shapes": tuning, "autotune_s": round(tune_s, 2),
+            "autotune_sample_graphs": len(sample), "identical_outputs": bool(same)}
 
 
-def bench_served(L, torch, pool, requests: int, load: float, seed: int = 1005, tuning=None):
-    """Request loop on a Poisson trace against the plain path on the same trace.
+def bench_served(L, torch, pool, requests: int, load: float, seed: int = 1005, tuning=None,
+                 budget: int = 200 * 10 ** 9):
+    """Request loop on Poisson traces against the plain path on the same
+    traces, both measured on the device.
 
-    The plain path's per-graph times (graph_create from the device CSR, run,
-    destroy: what a served request covers) are measured alone; its latencies
-    on the trace follow from a first-come-first-served queue over those
-    times."""
+    A served request takes its device CSR in (copy, validation, degrees) and
+    runs the method; so does a plain request (graph_create, run, destroy),
+    one at a time in arrival order.  The saturating trace (every request at
+    time 0) gives graphs/s; the Poisson trace at `load` x the plain path's
+    measured capacity gives p50/p99 latency (arrival to result).  The
+    request loop's memory budget is `budget` bytes.  The plain path's device
+    busy time (its kernels' summed device time over its wall time) bounds
+    what any batching can gain over it."""
     import numpy as np
     ctx = L.Context(0)
     if tuning:
         ctx.set_tuning(**tuning)
+    ctx.serve_budget(budget)
     dev = torch.device("cuda", 0)
     res_in = [(torch.from_numpy(g.row_ptr).to(dev), torch.from_numpy(g.col).to(dev), torch.from_numpy(g.w).to(dev))
               for g in pool]
-    Gs = [ctx.graph_create(*t) for t in res_in]
     outs = [torch.empty(g.n, dtype=torch.int32, device=dev) for g in pool]
     torch.cuda.synchronize()
-    for G, o in zip(Gs, outs):           # warm-up
-        ctx.run(G, labels_out=o)
-    # a plain request is what a served one does: take the device CSR in
-    # (copy, validation, degrees) and run the method
-    svc = []
     ref_q = []
-    for t, o in zip(res_in, outs):
-        torch.cuda.synchronize()
-        a = time.perf_counter()
+    kernel_ms = []
+    for t, o in zip(res_in, outs):     # warm-up, reference outputs and device time per graph
         G = ctx.graph_create(*t)
-        r = ctx.run(G, labels_out=o)
+        r = ctx.run(G, labels_out=o, timing=True)
         G.destroy()
-        torch.cuda.synchronize()
-        svc.append(time.perf_counter() - a)
         ref_q.append(r.q_int)
+        kernel_ms.append(sum(k["ms"] for k in r.stats["kernels"].values()))
     trace = [k % len(pool) for k in range(requests)]
-    mean_svc = float(np.mean([svc[k] for k in trace]))
-    capacity = 1.0 / mean_svc
     rng = np.random.default_rng([seed, 7])
 
-    def run_trace(qps):
-        arrivals = np.zeros(len(trace)) if qps is None else np.cumsum(rng.exponential(1.0 / qps, len(trace)))
+    def plain_trace(arrivals):
+        """The plain path over the trace, first come first served, on the device."""
+        lat = []
         labels = [torch.empty(pool[k].n, dtype=torch.int32, device=dev) for k in trace]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i, k in enumerate(trace):
+            wait = t0 + arrivals[i] - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            G = ctx.graph_create(*res_in[k])
+            ctx.run(G, labels_out=labels[i])
+            G.destroy()
+            torch.cuda.synchronize()
+            lat.append(time.perf_counter() - t0 - arrivals[i])
+        span = time.perf_counter() - t0
+        ok = all(torch.equal(labels[i], outs[k]) for i, k in enumerate(trace))
+        return lat, span, ok
+
+    def served_trace(arrivals):
+        labels = [torch.empty(pool[k].n, dtype=torch.int32, device=dev) for k in trace]
+        torch.cuda.synchronize()
         tickets = []
         t0 = time.perf_counter()
         for i, k in enumerate(trace):
@@ -203,29 +232,29 @@ def bench_served(L, torch, pool, requests: int, load: float, seed: int = 1005, t
         span = (max(done[t].t_done_us for t in tickets) - min(done[t].t_submit_us for t in tickets)) / 1e6
         ok = all(done[t].status in (0, -6) and done[t].q_int == ref_q[k] for t, k in zip(tickets, trace))
         ok = ok and all(torch.equal(labels[i], outs[k]) for i, k in enumerate(trace))
-        return lat, span, ok, arrivals
+        return lat, span, ok
 
-    lat_sat, span_sat, ok_sat, _ = run_trace(None)
+    zero = np.zeros(len(trace))
+    _, plain_span, ok_p0 = plain_trace(zero)
+    capacity = len(trace) / plain_span
+    lat_sat, span_sat, ok_sat = served_trace(zero)
     qps = load * capacity
-    lat, span, ok, arrivals = run_trace(qps)
-    # the plain path on the same trace: one graph at a time, first come first served
-    fin = 0.0
-    plain_lat = []
-    for i, k in enumerate(trace):
-        fin = max(fin, arrivals[i]) + svc[k]
-        plain_lat.append(fin - arrivals[i])
-    for G in Gs:
-        G.destroy()
+    arrivals = np.cumsum(rng.exponential(1.0 / qps, len(trace)))
+    lat, span, ok = served_trace(arrivals)
+    plain_lat, _, ok_p1 = plain_trace(arrivals)
+    busy = sum(kernel_ms[k] for k in trace) / 1000.0 / plain_span
     ctx.close()
-    return {"distinct_graphs": len(pool), "requests": requests,
+    return {"distinct_graphs": len(pool), "requests": requests, "budget_bytes": budget,
             "mean_nnz": int(np.mean([pool[k].nnz for k in trace])),
             "plain_capacity_gps": round(capacity, 3),
             "saturated_gps": round(len(trace) / span_sat, 3),
             "saturated_speedup": round(len(trace) / span_sat / capacity, 3),
+            "plain_device_busy": round(busy, 3), "speedup_bound_from_plain_idle": round(1.0 / busy, 3),
             "trace_qps": round(qps, 3), "load": load,
             "p50_s": round(percentile(lat, 50), 5), "p99_s": round(percentile(lat, 99), 5),
             "plain_p50_s": round(percentile(plain_lat, 50), 5), "plain_p99_s": round(percentile(plain_lat, 99), 5),
-            "identical_outputs": bool(ok and ok_sat)}
+            "plain_latency": "measured: the plain path replayed on the device over the same trace",
+            "identical_outputs": bool(ok and ok_sat and ok_p0 and ok_p1)}
 
 
 def shard_bounds(row_ptr, nshards: int):
@@ -369,6 +398,187 @@ def bench_merge(torch, ctx, rp, col, w, plain_ms: float, plain_q: float, runs: i
             "merge_kernels_ms": round(merge_ms, 4)}
 
 
+def time_oracle_runs(oracle, g, threads: int, min_s: float, max_runs: int):
+    """Full oracle runs on the host: (result, runs, seconds per run)."""
+    oracle.set_threads(threads)
+    runs, spent, res = 0, 0.0, None
+    while runs < max_runs and (runs == 0 or spent < min_s):
+        c0 = time.perf_counter()
+        res = oracle.louvain(g.row_ptr, g.col, g.w)
+        spent += time.perf_counter() - c0
+        runs += 1
+    oracle.set_threads(1)
+    return res, runs, spent / runs
+
+
+def cpu_full_runs(np, g, workload: str, r, out, threads: int):
+    """The oracle on the whole workload (OpenMP variant, then single-threaded
+    when it stays short), in GTEPS of the method's executed sweeps; parity of
+    the GPU run's labels and Q_int with it."""
+    import oracle
+    ref, runs, per = time_oracle_runs(oracle, g, threads, 10.0, 3)
+    ref_edges = sum(lv["sweeps_executed"] * lv["nnz"] for lv in ref.levels)
+    cpu = {"value": round(ref_edges / per / 1e9, 5), "unit": "GTEPS", "cores": threads, "kind": "oracle",
+           "sample": f"{runs} full oracle run(s) of {workload} with its OpenMP variant on {threads} "
+                     f"threads, {per:.3f} s each"}
+    same = True
+    if threads > 1 and per < 20.0:   # the single-threaded oracle too, when it stays within the sample
+        ref1, runs1, per1 = time_oracle_runs(oracle, g, 1, 5.0, 2)
+        cpu["single_thread_value"] = round(ref_edges / per1 / 1e9, 5)
+        cpu["sample"] += f" (single-threaded: {runs1} run(s), {per1:.3f} s each)"
+        same = bool(np.array_equal(ref1.labels, ref.labels))
+    labels = out.cpu().numpy()
+    parity = bool(np.array_equal(labels, ref.labels) and r.q_int == ref.q_int and same)
+    return cpu, parity
+
+
+def cpu_sweep_sample(np, g, workload: str, threads: int):
+    """For a workload whose whole oracle run takes many minutes: level-0
+    sweeps of the oracle (OpenMP variant), from singletons and from a
+    4,096-community labelling, in GTEPS (entries per second of sweeps)."""
+    import graphgen as gg
+    import oracle
+    oracle.set_threads(threads)
+    t = 0.0
+    sweeps = 0
+    for labels in (None, gg.random_labels(g.n, 4096, 11)):
+        c0 = time.perf_counter()
+        oracle.local_move(g.row_ptr, g.col, g.w, labels)
+        t += time.perf_counter() - c0
+        sweeps += 1
+    oracle.set_threads(1)
+    return {"value": round(sweeps * g.nnz / t / 1e9, 5), "unit": "GTEPS", "cores": threads, "kind": "oracle",
+            "sample": f"{sweeps} level-0 sweeps of {workload} (from singletons and from 4,096 random "
+                      f"communities) with the oracle's OpenMP variant on {threads} threads, {t / sweeps:.2f} s "
+                      f"each; a whole oracle run of this graph takes about ten minutes"}
+
+
+def golden_parity(np, workload: str, r, out):
+    """Labels, Q_int and level records of the GPU run against the oracle's
+    results stored as digests (tests/golden/<workload>_expected.json, written
+    by a script that calls only the oracle and the generators)."""
+    import hashlib
+    path = os.path.join(ROOT, "tests", "golden", f"{workload}_expected.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        exp = json.load(f)["run"]
+    labels = np.ascontiguousarray(out.cpu().numpy(), dtype=np.int32)
+    same = hashlib.sha256(labels.tobytes()).hexdigest() == exp["labels"] and str(r.q_int) == exp["q_int"]
+    lv = [(x["n"], x["nnz"], x["sweeps_executed"], x["sweeps_accepted"], str(x["q_int"])) for x in r.stats["levels"]]
+    lv_exp = [(x["n"], x["nnz"], x["sweeps_executed"], x["sweeps_accepted"], x["q_int"]) for x in exp["levels"]]
+    return bool(same and lv == lv_exp)
+
+
+def measure_plain(L, torch, np, g, workload: str, steps: int, warmup: int, timing: bool, pass_batch: int,
+                  shapes=None, autotune: bool = True, cpu: str = "full"):
+    """The plain method on one workload: W warm-up steps (the last one times
+    every launch), K timed steps (the last one times the dominant kernel's
+    launches), the roofline of the dominant kernel, the CPU oracle beside it
+    (cpu: "full" whole runs, "sweeps" level-0 sweeps, "none") and parity.
+    A step = graph_create from the device-resident CSR + run + destroy."""
+    dev = torch.device("cuda", 0)
+    rp = torch.from_numpy(g.row_ptr).to(dev)
+    col = torch.from_numpy(g.col).to(dev)
+    w = torch.from_numpy(g.w).to(dev)
+    out = torch.empty(g.n, dtype=torch.int32, device=dev)
+    ctx = L.Context(0)
+
+    def step(tm):
+        G = ctx.graph_create(rp, col, w)
+        r = ctx.run(G, timing=tm, pass_batch=pass_batch, labels_out=out)
+        G.destroy()
+        return r
+
+    if shapes:
+        ctx.set_tuning(*[int(x) for x in shapes.split(",")])
+    tuning = ctx.get_tuning()
+    if autotune and not shapes:
+        G = ctx.graph_create(rp, col, w)
+        t = time.time()
+        best = ctx.autotune(G)
+        G.destroy()
+        tuning = ctx.get_tuning()
+        log(f"{workload}: autotuned launch shapes in {time.time() - t:.2f}s: {tuning} ({best['ms']:.3f} ms per run)")
+
+    # warm-up steps; the last one records every kernel to find the dominant
+    # one, whose launches alone are timed in the last timed step
+    dominant = table = table_levels = None
+    nwarm = max(2, warmup) if timing else warmup
+    for k in range(nwarm):
+        full = timing and k == nwarm - 1
+        r0 = step(full)
+        if full:
+            table = r0.stats["kernels"]
+            table_levels = r0.stats["levels"]
+            dominant = max(table.items(), key=lambda kv: kv[1]["ms"])[0]
+        log(f"{workload}: warmup {k + 1}/{nwarm} done")
+    torch.cuda.synchronize()
+    results = []
+    t0 = time.perf_counter()
+    # the dominant kernel's launches carry dispatch events in the last timed
+    # step only: each event adds a few microseconds before and after its
+    # kernel, which would otherwise weigh on every step's wall time
+    for k in range(steps):
+        results.append(step(dominant if timing and k == steps - 1 else False))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    log(f"{workload}: timed {steps} steps")
+    ms_per_step = (t1 - t0) * 1000.0 / max(1, steps)
+    r = results[-1]
+    levels = r.stats["levels"]
+    edges = sum(lv["sweeps_executed"] * lv["nnz"] for lv in levels)
+    sweeps = sum(lv["sweeps_executed"] for lv in levels)
+    res = {"value": round(edges / (ms_per_step / 1000.0) / 1e9, 4), "unit": "GTEPS", "steps": steps,
+           "warmup": warmup, "ms_per_step": round(ms_per_step, 4), "full_louvain_s": round(ms_per_step / 1000.0, 6),
+           "config": {"workload": workload, "n": g.n, "nnz": g.nnz, "levels": len(levels), "sweeps": sweeps,
+                      "edges_swept": edges, "launch_shapes": tuning},
+           "q": r.q, "sweep_gteps": None, "level0_sweep_gteps": None, "kernel_ms_per_step": None,
+           "roofline": None, "cpu_baseline": None, "parity_vs_oracle": None}
+    if timing:
+        dom = dict(launches=0, ms=0.0, alg_bytes=0.0)
+        k = r.stats["kernels"].get(dominant)
+        if k:
+            for key in dom:
+                dom[key] += k[key]
+        achieved = dom["alg_bytes"] / (dom["ms"] / 1000.0) / 1e9
+        sweep_ms = sum(v["ms"] for n, v in table.items() if n.startswith(("k_cpt_", "k_sweep", "k_hub", "k_commit",
+                                                                             "k_qsum", "k_finalize")))
+        lv0 = table_levels[0] if table_levels else None
+        traffic = recorded_traffic(workload, dominant)
+        alg_per_launch = dom["alg_bytes"] / max(1, dom["launches"])
+        res["sweep_gteps"] = round(edges / (sweep_ms / 1000.0) / 1e9, 3) if sweep_ms > 0 else None
+        res["level0_sweep_gteps"] = (round(lv0["sweeps_executed"] * lv0["nnz"] / (lv0["ms_sweep"] / 1000.0) / 1e9, 3)
+                                     if lv0 and lv0["ms_sweep"] > 0 else None)
+        res["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dominant,
+                           "avg_launch_us": round(dom["ms"] * 1000.0 / max(1, dom["launches"]), 2),
+                           "launches_per_step": dom["launches"], "traffic_unit": "bytes per launch",
+                           "alg_bytes_per_launch": round(alg_per_launch),
+                           "traffic_over_alg": round(traffic / alg_per_launch, 3) if traffic else None}
+        top = sorted(table.items(), key=lambda kv: -kv[1]["ms"])[:20]
+        log(f"{workload}: kernel time of one step (all launches timed): " +
+            ", ".join(f"{n} {a['ms']:.3f} ms" for n, a in top))
+        kernel_ms = sum(a["ms"] for a in table.values())
+        res["kernel_ms_per_step"] = round(kernel_ms, 4)
+        res["launches_per_step"] = int(sum(a["launches"] for a in table.values()))
+        log(f"{workload}: all kernels {kernel_ms:.3f} ms per step ({res['launches_per_step']} launches); timed "
+            f"step {ms_per_step:.3f} ms; dominant {dominant} "
+            f"{dom['ms'] * 1000.0 / max(1, dom['launches']):.2f} us per launch in the last timed step")
+    threads = max(1, min(16, os.cpu_count() or 1))
+    if cpu == "full":
+        log(f"{workload}: timing the CPU oracle on the same graph")
+        res["cpu_baseline"], res["parity_vs_oracle"] = cpu_full_runs(np, g, workload, r, out, threads)
+        log(f"{workload}: oracle: {res['cpu_baseline']['sample']}, parity {res['parity_vs_oracle']}")
+    elif cpu == "sweeps":
+        log(f"{workload}: timing level-0 sweeps of the CPU oracle")
+        res["cpu_baseline"] = cpu_sweep_sample(np, g, workload, threads)
+        res["parity_vs_oracle"] = golden_parity(np, workload, r, out)
+        log(f"{workload}: oracle: {res['cpu_baseline']['sample']}; parity with the stored oracle results "
+            f"{res['parity_vs_oracle']}")
+    return res, dict(ctx=ctx, rp=rp, col=col, w=w, out=out, r=r, tuning=tuning)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -378,26 +588,28 @@ def main():
     ap.add_argument("--pass-batch", type=int, default=0)
     ap.add_argument("--no-timing", action="store_true", help="time steps without per-kernel events")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the default launch shapes instead of autotuning them on the workload first")
+                    help="keep the default launch shapes (skip the autotuner)")
     ap.add_argument("--shapes", default=None,
-                    help="explicit launch shapes small_max,block_max,pass_batch,group_slots,group_vertices,overlap "
-                         "(no autotuning)")
+                    help="fixed launch shapes: small_max,block_max,pass_batch[,group_slots[,group_vertices"
+                         "[,overlap[,reorder]]]]")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rmat24", type=int, default=1,
+                    help="also measure the R-MAT scale-24 workload (its own roofline, level-0 oracle sweeps, "
+                         "parity with the stored oracle results); 0 = skip")
+    ap.add_argument("--rmat24-steps", type=int, default=3)
+    ap.add_argument("--sbm1k", type=int, default=1, help="also time the 1,000-vertex SBM workload; 0 = skip")
     ap.add_argument("--batched", type=int, default=4096,
-                    help="also compare one batched call on this many graphs of the batched SBM workload "
-                         "against the plain loop (4096 = the full workload; 0 = skip)")
+                    help="graphs of the batched comparison (0 = skip)")
     ap.add_argument("--batched-nmax", type=int, default=100_000)
     ap.add_argument("--batched-profile", action="store_true", help="log the batched call's kernel table")
-    ap.add_argument("--served", type=int, default=32,
-                    help="also run the request loop on a Poisson trace over this many distinct Chung-Lu "
-                         "request graphs (0 = skip)")
-    ap.add_argument("--served-requests", type=int, default=0, help="trace length (default 4x the graphs)")
+    ap.add_argument("--served", type=int, default=48,
+                    help="distinct request graphs of the served comparison (0 = skip)")
+    ap.add_argument("--served-requests", type=int, default=0, help="trace length (default 3x the graphs)")
     ap.add_argument("--served-load", type=float, default=0.7, help="trace QPS as a fraction of plain capacity")
     ap.add_argument("--no-dendro", action="store_true",
-                    help="skip the dendrogram-keeping, resumed and merged runs beside the plain one")
+                    help="skip the dendrogram / resume and final-merge comparisons")
     ap.add_argument("--shards", type=int, default=8,
-                    help="also time one GPU's share of the workload split into this many vertex ranges "
-                         "(sweep kernels per pass; 0 = skip)")
+                    help="time one GPU's share of this many vertex shards (0 or 1 = skip)")
     ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (for scaling the "
@@ -439,141 +651,16 @@ def main():
     import graphgen as gg
     import paper_1805_10904_amd as L
 
+    timing = not args.no_timing
     log(f"generating {args.workload}")
     t = time.time()
     g = gg.config(args.workload)
     log(f"generated n={g.n} nnz={g.nnz} in {time.time() - t:.1f}s")
-    dev = torch.device("cuda", 0)
-    rp = torch.from_numpy(g.row_ptr).to(dev)
-    col = torch.from_numpy(g.col).to(dev)
-    w = torch.from_numpy(g.w).to(dev)
-    out = torch.empty(g.n, dtype=torch.int32, device=dev)
-    ctx = L.Context(0)
-    timing = not args.no_timing
-
-    def step(tm):
-        G = ctx.graph_create(rp, col, w)
-        r = ctx.run(G, timing=tm, pass_batch=args.pass_batch, labels_out=out)
-        G.destroy()
-        return r
-
-    if args.shapes:
-        ctx.set_tuning(*[int(x) for x in args.shapes.split(",")])
-    tuning = ctx.get_tuning()
-    if not args.no_autotune and not args.shapes:
-        G = ctx.graph_create(rp, col, w)
-        t = time.time()
-        best = ctx.autotune(G)
-        G.destroy()
-        tuning = ctx.get_tuning()
-        log(f"autotuned launch shapes in {time.time() - t:.2f}s: {tuning} ({best['ms']:.3f} ms per run)")
-
-    # warm-up steps; the first one records every kernel to find the dominant one,
-    # whose launches alone are timed in the last timed step
-    # (the last warm-up step, at least the second, is the one timed in full)
-    dominant = None
-    table = None
-    table_levels = None
-    nwarm = max(2, args.warmup) if timing else args.warmup
-    for k in range(nwarm):
-        full = timing and k == nwarm - 1
-        r0 = step(full)
-        if full:
-            table = r0.stats["kernels"]
-            table_levels = r0.stats["levels"]
-            dominant = max(table.items(), key=lambda kv: kv[1]["ms"])[0]
-        log(f"warmup {k + 1}/{nwarm} done")
-    torch.cuda.synchronize()
-    results = []
-    t0 = time.perf_counter()
-    # the dominant kernel's launches carry dispatch events in the last timed
-    # step only: each event adds a few microseconds before and after its
-    # kernel, which would otherwise weigh on every step's wall time
-    for k in range(args.steps):
-        results.append(step(dominant if timing and k == args.steps - 1 else False))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    log(f"timed {args.steps} steps")
-    ms_per_step = (t1 - t0) * 1000.0 / max(1, args.steps)
-    r = results[-1]
-    levels = r.stats["levels"]
-    edges = sum(lv["sweeps_executed"] * lv["nnz"] for lv in levels)
-    sweeps = sum(lv["sweeps_executed"] for lv in levels)
-    value = edges / (ms_per_step / 1000.0) / 1e9
-
-    roofline = None
-    sweep_gteps = None
-    level0_gteps = None
-    kernel_ms = None
-    if timing:
-        # the dominant kernel, timed live in the last timed step
-        dom = dict(launches=0, ms=0.0, alg_bytes=0.0)
-        for res in results[-1:]:
-            k = res.stats["kernels"].get(dominant)
-            if k:
-                for key in dom:
-                    dom[key] += k[key]
-        dom_name = dominant
-        achieved = dom["alg_bytes"] / (dom["ms"] / 1000.0) / 1e9
-        # the per-kernel table of the first warm-up step (every launch timed)
-        agg = table
-        sweep_ms = sum(v["ms"] for n, v in table.items() if n.startswith(("k_cpt_", "k_sweep", "k_hub", "k_commit",
-                                                                             "k_qsum", "k_finalize")))
-        sweep_gteps = edges / (sweep_ms / 1000.0) / 1e9 if sweep_ms > 0 else None
-        # level 0 alone: its executed sweeps over its entries / its sweep kernels' time
-        lv0 = table_levels[0] if table_levels else None
-        level0_gteps = (lv0["sweeps_executed"] * lv0["nnz"] / (lv0["ms_sweep"] / 1000.0) / 1e9
-                        if lv0 and lv0["ms_sweep"] > 0 else None)
-        # measured HBM bytes per launch (counters), against the algorithmic ones
-        traffic = recorded_traffic(args.workload, dom_name)
-        alg_per_launch = dom["alg_bytes"] / max(1, dom["launches"])
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom_name,
-                    "avg_launch_us": round(dom["ms"] * 1000.0 / dom["launches"], 2),
-                    "launches_per_step": dom["launches"], "traffic_unit": "bytes per launch",
-                    "alg_bytes_per_launch": round(alg_per_launch),
-                    "traffic_over_alg": round(traffic / alg_per_launch, 3) if traffic else None}
-        top = sorted(agg.items(), key=lambda kv: -kv[1]["ms"])[:20]
-        log("kernel time of one step (all launches timed): " + ", ".join(f"{n} {a['ms']:.3f} ms" for n, a in top))
-        kernel_ms = sum(a["ms"] for a in agg.values())
-        log(f"all kernels {kernel_ms:.3f} ms per step ({sum(a['launches'] for a in agg.values()):.0f} "
-            f"launches); timed step {ms_per_step:.3f} ms; dominant {dom_name} "
-            f"{dom['ms'] * 1000.0 / max(1, dom['launches']):.2f} us per launch in the last timed step")
-
-    cpu = None
-    parity = None
-    if not args.no_cpu_baseline:
-        import oracle
-        log("timing the CPU oracle on the same graph")
-
-        def time_oracle(threads, min_s, max_runs):
-            oracle.set_threads(threads)
-            runs, spent, res = 0, 0.0, None
-            while runs < max_runs and (runs == 0 or spent < min_s):
-                c0 = time.perf_counter()
-                res = oracle.louvain(g.row_ptr, g.col, g.w)
-                spent += time.perf_counter() - c0
-                runs += 1
-            oracle.set_threads(1)
-            return res, runs, spent / runs
-
-        # the OpenMP variant over the host's cores (the box grants up to 16),
-        # and the plain single-threaded oracle beside it
-        threads = max(1, min(16, os.cpu_count() or 1))
-        ref, runs, per = time_oracle(threads, 10.0, 3)
-        ref_edges = sum(lv["sweeps_executed"] * lv["nnz"] for lv in ref.levels)
-        cpu = {"value": round(ref_edges / per / 1e9, 5), "unit": "GTEPS", "cores": threads, "kind": "oracle",
-               "sample": f"{runs} full oracle run(s) of {args.workload} with its OpenMP variant on {threads} "
-                         f"threads, {per:.2f} s each"}
-        same = True
-        if threads > 1 and per < 20.0:   # the single-threaded oracle too, when it stays within the sample
-            ref1, runs1, per1 = time_oracle(1, 5.0, 2)
-            cpu["single_thread_value"] = round(ref_edges / per1 / 1e9, 5)
-            cpu["sample"] += f" (single-threaded: {runs1} run(s), {per1:.2f} s each)"
-            same = bool(np.array_equal(ref1.labels, ref.labels))
-        labels = out.cpu().numpy()
-        parity = bool(np.array_equal(labels, ref.labels) and r.q_int == ref.q_int and same)
-        log(f"oracle: {cpu['sample']}, parity {parity}")
+    head_cpu = "none" if args.no_cpu_baseline else ("sweeps" if args.workload == "rmat24" else "full")
+    head, ctxs = measure_plain(L, torch, np, g, args.workload, args.steps, args.warmup, timing, args.pass_batch,
+                               shapes=args.shapes, autotune=not args.no_autotune, cpu=head_cpu)
+    ctx, rp, col, w, out, r, tuning = (ctxs[k] for k in ("ctx", "rp", "col", "w", "out", "r", "tuning"))
+    ms_per_step = head["ms_per_step"]
 
     dendro = merged = None
     if not args.no_dendro:
@@ -598,6 +685,31 @@ def main():
         except Exception as e:  # the main measurement stands on its own
             shards = {"error": f"{type(e).__name__}: {e}"}
         log(f"shards: {shards}")
+    ctx.close()
+    del ctxs, rp, col, w, out
+
+    others = {}
+    for name, on in (("sbm1k", args.sbm1k), ("rmat24", args.rmat24)):
+        if not on or name == args.workload:
+            continue
+        log(f"generating {name}")
+        t = time.time()
+        gx = gg.config(name)
+        log(f"generated n={gx.n} nnz={gx.nnz} in {time.time() - t:.1f}s")
+        cpu_mode = "none" if args.no_cpu_baseline else ("sweeps" if name == "rmat24" else "full")
+        steps = args.rmat24_steps if name == "rmat24" else max(args.steps, 20)
+        warm = 2 if name == "rmat24" else max(args.warmup, 5)
+        try:
+            resx, cx = measure_plain(L, torch, np, gx, name, steps, warm, timing, args.pass_batch,
+                                     shapes=args.shapes, autotune=not args.no_autotune and name != "rmat24",
+                                     cpu=cpu_mode)
+            cx["ctx"].close()
+            del cx
+        except Exception as e:  # the headline stands on its own
+            resx = {"error": f"{type(e).__name__}: {e}"}
+        others[name] = resx
+        log(f"{name}: {resx}")
+        del gx
 
     batched = served = None
     if batch_graphs is not None:
@@ -611,27 +723,33 @@ def main():
     if served_pool is not None:
         log("served vs plain")
         try:
-            served = bench_served(L, torch, served_pool, args.served_requests or 4 * len(served_pool),
+            served = bench_served(L, torch, served_pool, args.served_requests or 3 * len(served_pool),
                                   args.served_load, tuning=tuning)
         except Exception as e:
             served = {"error": f"{type(e).__name__}: {e}"}
         log(f"served: {served}")
 
+    cfg = dict(head["config"])
+    cfg["parallelism"] = "single GPU"
     line = {
-        "metric": METRIC, "value": round(value, 4), "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
+        "metric": METRIC, "value": head["value"], "unit": "GTEPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-        "config": {"workload": args.workload, "n": g.n, "nnz": g.nnz, "levels": len(levels), "sweeps": sweeps,
-                   "edges_swept": edges, "parallelism": "single GPU", "launch_shapes": tuning},
-        "full_louvain_s": round(ms_per_step / 1000.0, 6),
-        "sweep_gteps": None if sweep_gteps is None else round(sweep_gteps, 3),
-        "level0_sweep_gteps": None if level0_gteps is None else round(level0_gteps, 3),
-        "kernel_ms_per_step": None if kernel_ms is None else round(kernel_ms, 4),
-        "q": r.q,
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-        "parity_vs_oracle": parity,
+        "config": cfg,
+        "full_louvain_s": head["full_louvain_s"],
+        "sweep_gteps": head["sweep_gteps"],
+        "level0_sweep_gteps": head["level0_sweep_gteps"],
+        "kernel_ms_per_step": head["kernel_ms_per_step"],
+        "launches_per_step": head.get("launches_per_step"),
+        "q": head["q"],
+        "roofline": head["roofline"],
+        "cpu_baseline": head["cpu_baseline"],
+        "parity_vs_oracle": head["parity_vs_oracle"],
     }
+    if "rmat24" in others:
+        line["c3_rmat24"] = others["rmat24"]
+    if "sbm1k" in others:
+        line["c1_sbm1k"] = others["sbm1k"]
     if dendro is not None:
         line["dendrogram"] = dendro
     if merged is not None:

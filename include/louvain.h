@@ -416,6 +416,21 @@ int louvain_get_tuning(louvain_ctx ctx, louvain_tuning *tuning);
  */
 int louvain_autotune(louvain_ctx ctx, louvain_graph g, const louvain_params *params, louvain_tuning *best);
 
+/*
+ * Autotuner of the batched form: times louvain_run_batch's batch engine on
+ * the given graphs (those with 2W < 2^31; params as for louvain_run_batch)
+ * and tunes the launch shapes by coordinate descent, one round over the
+ * fields: small_max {2, 4, 8}, group_slots {2, 4, 8}, group_vertices
+ * {1, 2}, block_max {1365, 2730, 10922}, pass_batch {1, 2, 4}; each value
+ * is timed (best of two calls) with the other fields at the best setting
+ * so far, and kept only when it is more than 2% faster.  The pick becomes
+ * the context's setting (and is written to its tuning file, if any);
+ * *best (optional) receives it with one call's device time in ms (-1 when
+ * no graph qualifies).  Results never depend on the setting.
+ */
+int louvain_autotune_batch(louvain_ctx ctx, int64_t ngraphs, const louvain_graph *graphs,
+                           const louvain_params *params, louvain_tuning *best);
+
 /* ---- served form --------------------------------------------------------- */
 
 /* Result of one served request (louvain_poll). */

@@ -30,7 +30,7 @@ ABI_SYMBOLS = (
     "louvain_graph_create", "louvain_graph_destroy", "louvain_graph_info", "louvain_graph_export",
     "louvain_local_move", "louvain_modularity", "louvain_aggregate", "louvain_run", "louvain_run_batch",
     "louvain_workspace_bytes", "louvain_serve_budget", "louvain_submit", "louvain_poll",
-    "louvain_set_tuning", "louvain_get_tuning", "louvain_autotune",
+    "louvain_set_tuning", "louvain_get_tuning", "louvain_autotune", "louvain_autotune_batch",
     "louvain_run_dendro", "louvain_dendro_info", "louvain_dendro_map", "louvain_dendro_graph",
     "louvain_dendro_destroy", "louvain_resume",
 )
@@ -123,6 +123,7 @@ def load_library(path: str = LIB_PATH):
     lib.louvain_set_tuning.argtypes = [p, C.POINTER(louvain_tuning)]
     lib.louvain_get_tuning.argtypes = [p, C.POINTER(louvain_tuning)]
     lib.louvain_autotune.argtypes = [p, p, C.POINTER(louvain_params), C.POINTER(louvain_tuning)]
+    lib.louvain_autotune_batch.argtypes = [p, i64, p, C.POINTER(louvain_params), C.POINTER(louvain_tuning)]
     lib.louvain_workspace_bytes.argtypes = [i64, i64]
     lib.louvain_workspace_bytes.restype = C.c_size_t
     lib.louvain_serve_budget.argtypes = [p, C.c_size_t]
@@ -463,6 +464,18 @@ class Context:
         prm = louvain_params(theta_num, theta_den, max_sweeps, max_levels, 1 if singlet_rule else 0, 0)
         t = louvain_tuning()
         self._check(self.lib.louvain_autotune(self.h, g.h, C.byref(prm), C.byref(t)))
+        return dict(small_max=t.small_max, block_max=t.block_max, pass_batch=t.pass_batch,
+                    group_slots=t.group_slots, group_vertices=t.group_vertices, overlap=t.overlap,
+                    reorder=t.reorder, ms=t.ms)
+
+    def autotune_batch(self, graphs, theta_num: int = 1, theta_den: int = 1_000_000, max_sweeps: int = 1000,
+                       max_levels: int = 64, singlet_rule: bool = True) -> dict:
+        """Tune the launch shapes on a batched call over these graphs (coordinate
+        descent over every shape field); the pick becomes the context's."""
+        prm = louvain_params(theta_num, theta_den, max_sweeps, max_levels, 1 if singlet_rule else 0, 0)
+        hs = (C.c_void_p * len(graphs))(*[g.h for g in graphs])
+        t = louvain_tuning()
+        self._check(self.lib.louvain_autotune_batch(self.h, len(graphs), hs, C.byref(prm), C.byref(t)))
         return dict(small_max=t.small_max, block_max=t.block_max, pass_batch=t.pass_batch,
                     group_slots=t.group_slots, group_vertices=t.group_vertices, overlap=t.overlap,
                     reorder=t.reorder, ms=t.ms)

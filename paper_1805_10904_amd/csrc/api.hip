@@ -1073,6 +1073,96 @@ int louvain_autotune(louvain_ctx ctx, louvain_graph g, const louvain_params *par
     });
 }
 
+int louvain_autotune_batch(louvain_ctx ctx, int64_t ngraphs, const louvain_graph *graphs,
+                           const louvain_params *params, louvain_tuning *best) {
+    return guarded(ctx, [&] {
+        require(ngraphs > 0 && graphs != nullptr, LOUVAIN_EINVAL, "ngraphs must be > 0 and graphs not NULL");
+        std::vector<lv::GraphView> views;
+        int64_t n_total = 0;
+        for (int64_t i = 0; i < ngraphs; ++i) {
+            require(graphs[i] != nullptr && graphs[i]->ctx == ctx, LOUVAIN_EINVAL,
+                    "graph " + std::to_string(i) + " missing or from another context");
+            if (graphs[i]->tw < lv::kCompactTwMax) {   // heavier graphs run alone and ignore the shapes
+                views.push_back(graphs[i]->view());
+                n_total += graphs[i]->n;
+            }
+        }
+        louvain_params prm = checked_params(params);
+        prm.pass_batch = 0;   // the candidates' pass batching applies
+        if (views.empty() || n_total == 0) {
+            if (best) {
+                *best = tuning_to(ctx->tuning);
+                best->ms = -1.0;
+            }
+            return;
+        }
+        hipStream_t s = ctx->stream;
+        DevBuf<int32_t> fin((size_t)n_total);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        struct EvGuard {
+            hipEvent_t *a, *b;
+            ~EvGuard() {
+                if (*a) (void)hipEventDestroy(*a);
+                if (*b) (void)hipEventDestroy(*b);
+            }
+        } evg{&e0, &e1};
+        LV_HIP(hipEventCreate(&e0));
+        LV_HIP(hipEventCreate(&e1));
+        // one batched call's device time under a setting (as louvain_run_batch runs it)
+        auto time_batch = [&](const lv::Tuning &tn) {
+            std::vector<lv::BatchMember> mem(views.size());
+            LV_HIP(hipEventRecord(e0, s));
+            lv::BatchEngine eng(s, nullptr, sweep_params(prm), prm.max_levels, tn.pass_batch);
+            eng.set_tuning(tn);
+            int64_t off = 0;
+            for (size_t k = 0; k < views.size(); ++k) {
+                mem[k].g0 = views[k];
+                mem[k].fin = fin.p + off;
+                off += views[k].n;
+                eng.admit(&mem[k]);
+            }
+            while (!eng.idle()) eng.step();
+            LV_HIP(hipEventRecord(e1, s));
+            LV_HIP(hipEventSynchronize(e1));
+            float ms = 0;
+            LV_HIP(hipEventElapsedTime(&ms, e0, e1));
+            return (double)ms;
+        };
+        auto best_of_two = [&](const lv::Tuning &tn) { return std::min(time_batch(tn), time_batch(tn)); };
+        (void)time_batch(ctx->tuning);   // warm-up (allocations, code loading)
+        const lv::Tuning cur = ctx->tuning;
+        lv::Tuning pick = cur;
+        double pick_ms = best_of_two(cur);
+        // coordinate descent, one round over the fields: each value of a field
+        // with the others at the best setting so far; a change is kept only
+        // when it is more than 2% faster than that setting
+        auto try_field = [&](auto set, std::initializer_list<int64_t> values) {
+            lv::Tuning base = pick;
+            const double base_ms = pick_ms;
+            for (int64_t v : values) {
+                lv::Tuning tn = base;
+                set(tn, v);
+                const double ms = best_of_two(tn);
+                if (ms < pick_ms && ms < 0.98 * base_ms) {
+                    pick_ms = ms;
+                    pick = tn;
+                }
+            }
+        };
+        try_field([](lv::Tuning &t, int64_t v) { t.small_max = (int)v; }, {2, 4, 8});
+        try_field([](lv::Tuning &t, int64_t v) { t.group_slots = (int)v; }, {2, 4, 8});
+        try_field([](lv::Tuning &t, int64_t v) { t.group_vertices = (int)v; }, {1, 2});
+        try_field([](lv::Tuning &t, int64_t v) { t.block_max = v; }, {1365, 2730, lv::kCompactBlockMax});
+        try_field([](lv::Tuning &t, int64_t v) { t.pass_batch = (int)v; }, {1, 2, 4});
+        ctx->tuning = pick;
+        if (!ctx->tuning_path.empty()) save_tuning(ctx->tuning_path, device_arch(ctx->device), pick, pick_ms);
+        if (best) {
+            *best = tuning_to(pick);
+            best->ms = pick_ms;
+        }
+    });
+}
+
 size_t louvain_workspace_bytes(int64_t n, int64_t nnz) {
     if (n < 0 || nnz < 0) return 0;
     return lv::Server::workspace_bytes(n, nnz);

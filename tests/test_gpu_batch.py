@@ -146,3 +146,30 @@ def test_batch_equals_alone(ctx):
         assert a.stats["total_edges_swept"] == r.stats["total_edges_swept"]
     for G in Gs:
         G.destroy()
+
+
+def test_autotune_batch_keeps_results(L, tmp_path):
+    """The batched workload's autotuner (coordinate descent over every launch
+    shape, timed on the batch itself) picks a setting under which every
+    graph's result is unchanged, writes it to the tuning file, and the
+    results still equal the oracle's."""
+    graphs = gg.batch_sbm(40, n_hi=20_000, first=1200)
+    path = str(tmp_path / "tune.txt")
+    c = L.Context(0, tuning_path=path)
+    Gs = [c.graph_create(g.row_ptr, g.col, g.w) for g in graphs]
+    before = c.run_batch(Gs)
+    best = c.autotune_batch(Gs)
+    _say(f"batched autotune: {best}")
+    assert best["ms"] > 0
+    got = c.get_tuning()
+    assert all(got[k] == best[k] for k in got)
+    assert f"group_slots {best['group_slots']}" in open(path).read()
+    after = c.run_batch(Gs)
+    for k, (g, a, b) in enumerate(zip(graphs, before, after)):
+        assert np.array_equal(a.labels, b.labels) and a.q_int == b.q_int, f"graph {k}"
+    for k in (0, 17, 39):
+        ref = oracle.louvain(graphs[k].row_ptr, graphs[k].col, graphs[k].w)
+        assert np.array_equal(after[k].labels, ref.labels) and after[k].q_int == ref.q_int
+    for G in Gs:
+        G.destroy()
+    c.close()
