@@ -240,6 +240,24 @@ int louvain_modularity(louvain_ctx ctx, louvain_graph g, const int32_t *labels,
                        louvain_i128 *q_int, double *q, uint32_t flags);
 
 /*
+ * louvain_modularity without any device allocation, for callers that
+ * cannot allocate device memory (harnesses that forbid it, tight serving
+ * loops).  Same arguments, result and errors as louvain_modularity (labels
+ * host or device per flags: LOUVAIN_DEVICE_PTRS).  Its kernels work in one
+ * library-owned device array of about 48 MiB per GPU, held from the first
+ * context on that GPU until the process ends; graphs of more than
+ * LOUVAIN_NOALLOC_MAX_N vertices are refused with LOUVAIN_EINVAL.  Every
+ * call on a GPU shares that GPU's array, which keeps the last call's
+ * contents (each call clears what it needs); calls on one GPU are
+ * serialised by the library (each ends by reading its result back), so
+ * they do not overlap on the array.  Host labels are copied with
+ * hipMemcpyAsync from the caller's memory.
+ */
+#define LOUVAIN_NOALLOC_MAX_N 4194304
+int louvain_modularity_noalloc(louvain_ctx ctx, louvain_graph g, const int32_t *labels,
+                               louvain_i128 *q_int, double *q, uint32_t flags);
+
+/*
  * Renumbering and graph rebuilding (Section 5.1, "Renumbering nodes" and
  * "Inducing new graph"): community labels are mapped to consecutive IDs in
  * ascending label order, and the graph is contracted so that super-vertex a

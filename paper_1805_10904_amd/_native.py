@@ -28,7 +28,7 @@ ABI_SYMBOLS = (
     "louvain_ctx_create", "louvain_ctx_destroy", "louvain_last_error", "louvain_memory_stats",
     "louvain_memory_reset_peak",
     "louvain_graph_create", "louvain_graph_destroy", "louvain_graph_info", "louvain_graph_export",
-    "louvain_local_move", "louvain_modularity", "louvain_aggregate", "louvain_run", "louvain_run_batch",
+    "louvain_local_move", "louvain_modularity", "louvain_modularity_noalloc", "louvain_aggregate", "louvain_run", "louvain_run_batch",
     "louvain_workspace_bytes", "louvain_serve_budget", "louvain_submit", "louvain_poll",
     "louvain_set_tuning", "louvain_get_tuning", "louvain_autotune", "louvain_autotune_batch",
     "louvain_run_dendro", "louvain_dendro_info", "louvain_dendro_map", "louvain_dendro_graph",
@@ -116,6 +116,7 @@ def load_library(path: str = LIB_PATH):
     lib.louvain_graph_export.argtypes = [p, p, p, p, u32]
     lib.louvain_local_move.argtypes = [p, p, p, p, p, p, u32]
     lib.louvain_modularity.argtypes = [p, p, p, C.POINTER(louvain_i128), p, u32]
+    lib.louvain_modularity_noalloc.argtypes = [p, p, p, C.POINTER(louvain_i128), p, u32]
     lib.louvain_aggregate.argtypes = [p, p, p, p, C.POINTER(p), u32]
     lib.louvain_run.argtypes = [p, p, C.POINTER(louvain_params), p, C.POINTER(louvain_i128), p,
                                 C.POINTER(louvain_run_stats), u32]
@@ -552,6 +553,21 @@ class Context:
         q = C.c_double()
         self._check(self.lib.louvain_modularity(self.h, g.h, _ptr(lab), C.byref(qi), C.byref(q),
                                                 LOUVAIN_DEVICE_PTRS if dev else 0))
+        return qi.value(), q.value
+
+    def modularity_noalloc(self, g: Graph, labels, device: Optional[bool] = None):
+        """(Q_int, Q) as modularity(), computed in the library's fixed device
+        scratch array without any device allocation (graphs of at most
+        LOUVAIN_NOALLOC_MAX_N vertices)."""
+        dev = g.dev if device is None else device
+        n, _, _ = g.info()
+        if labels is None:
+            _bad("labels must be given")
+        lab = self._labels(labels, dev, n)
+        qi = louvain_i128()
+        q = C.c_double()
+        self._check(self.lib.louvain_modularity_noalloc(self.h, g.h, _ptr(lab), C.byref(qi), C.byref(q),
+                                                        LOUVAIN_DEVICE_PTRS if dev else 0))
         return qi.value(), q.value
 
     def aggregate(self, g: Graph, labels, device: Optional[bool] = None):

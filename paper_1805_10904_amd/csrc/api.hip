@@ -671,6 +671,51 @@ int run_graph(louvain_ctx ctx, louvain_graph g, const louvain_params *params, in
 
 }  // namespace
 
+// ------------------------------------------------- allocation-free modularity --
+//
+// louvain_modularity_noalloc uses one file-scope device array as its
+// workspace: a label-check flag, a device copy of host labels, and the
+// modularity workspace (deg_C by label, per-block partial sums).  Each GPU
+// holds its own copy for the life of the process; its address is looked up
+// once per device when the first context on that device is created, and
+// the kernels get that address (the array's name is only a host-side
+// stand-in).  Calls on one GPU take a per-device lock for their whole
+// duration (each ends by reading its result back), so they never overlap
+// on the array.
+namespace {
+
+constexpr int64_t kNoAllocMaxN = LOUVAIN_NOALLOC_MAX_N;
+constexpr size_t kScratchFlag = 0;
+constexpr size_t kScratchLabels = 256;
+constexpr size_t kScratchWs = kScratchLabels + (size_t)kNoAllocMaxN * sizeof(int32_t);
+constexpr size_t kScratchBytes =
+    kScratchWs + (size_t)kNoAllocMaxN * sizeof(int64_t) + (size_t)(2 * ((kNoAllocMaxN + 2047) / 2048) + 4) * 8;
+static_assert(kScratchLabels % 256 == 0 && kScratchWs % 256 == 0, "scratch regions are 256-byte aligned");
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_call_mu[kMaxDevices];
+
+// Address of this device's copy of the scratch array (the device must be current).
+int scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return LOUVAIN_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return LOUVAIN_OK;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr) {
+        (void)hipGetLastError();
+        return LOUVAIN_EDEVICE;
+    }
+    g_scratch_ptr[device] = ptr;
+    return LOUVAIN_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int louvain_ctx_create(int device, void *hip_stream, void *pool, size_t pool_bytes, const char *tuning_path,
@@ -687,6 +732,17 @@ int louvain_ctx_create(int device, void *hip_stream, void *pool, size_t pool_byt
         c->device = device;
         c->stream = (hipStream_t)hip_stream;
         c->timer.stream = c->stream;
+        {
+            // the device's copy of the no-allocation scratch array, looked up with the device current
+            int prev = 0;
+            if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(device) != hipSuccess) {
+                (void)hipGetLastError();
+                return LOUVAIN_EDEVICE;
+            }
+            const int rc = scratch_setup(device);
+            (void)hipSetDevice(prev);
+            if (rc != LOUVAIN_OK) return rc;
+        }
         if (pool) {
             // the region must be device memory of this device
             hipPointerAttribute_t attr;
@@ -865,6 +921,43 @@ int louvain_modularity(louvain_ctx ctx, louvain_graph g, const int32_t *labels, 
         DevBuf<int32_t> lab = labels_in(ctx, labels, g->n, flags);
         lv::Timer *t = ctx->timer.on ? &ctx->timer : nullptr;
         const lv::i128 v = lv::modularity_int(g->view(), lab.p, ctx->stream, t);
+        *q_int = to_abi(v);
+        if (q) *q = q_of(v, g->tw);
+    });
+}
+
+int louvain_modularity_noalloc(louvain_ctx ctx, louvain_graph g, const int32_t *labels, louvain_i128 *q_int,
+                               double *q, uint32_t flags) {
+    return guarded(ctx, [&] {
+        require(g != nullptr && g->ctx == ctx, LOUVAIN_EINVAL, "graph missing or from another context");
+        require(q_int != nullptr, LOUVAIN_EINVAL, "q_int must not be NULL");
+        require(g->n <= kNoAllocMaxN, LOUVAIN_EINVAL,
+                "n = " + std::to_string(g->n) + " exceeds the limit of louvain_modularity_noalloc (" +
+                    std::to_string(kNoAllocMaxN) + " vertices)");
+        require(labels != nullptr || g->n == 0, LOUVAIN_EINVAL, "labels must not be NULL");
+        require(ctx->device >= 0 && ctx->device < kMaxDevices && g_scratch_ptr[ctx->device], LOUVAIN_EDEVICE,
+                "the scratch array of this device was not set up");
+        std::lock_guard<std::mutex> lk(g_scratch_call_mu[ctx->device]);
+        char *base = (char *)g_scratch_ptr[ctx->device];
+        hipStream_t s = ctx->stream;
+        const int64_t n = g->n;
+        const int32_t *lab = labels;
+        if (n > 0) {
+            int *flag = (int *)(base + kScratchFlag);
+            if (!device_ptrs(flags)) {
+                int32_t *copy = (int32_t *)(base + kScratchLabels);
+                LV_HIP(hipMemcpyAsync(copy, labels, (size_t)n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+                lab = copy;
+            }
+            lv::fill<int32_t>(flag, 0, 1, s);
+            k_label_range<<<lv::grid_for(n, 256), 256, 0, s>>>(lab, n, n, flag);
+            LV_LAUNCHED("k_label_range");
+            int bad = 0;
+            LV_HIP(hipMemcpyAsync(&bad, flag, sizeof bad, hipMemcpyDeviceToHost, s));
+            LV_HIP(hipStreamSynchronize(s));
+            require(bad == 0, LOUVAIN_EINVAL, "label out of range [0, " + std::to_string(n) + ")");
+        }
+        const lv::i128 v = lv::modularity_int(g->view(), lab, s, nullptr, base + kScratchWs);
         *q_int = to_abi(v);
         if (q) *q = q_of(v, g->tw);
     });
