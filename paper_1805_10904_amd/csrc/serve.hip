@@ -127,7 +127,8 @@ uint64_t Server::submit(std::unique_ptr<ServeRequest> r) {
         std::lock_guard<std::mutex> lk(mu_);
         t = next_++;
         r->ticket = t;
-        workers_[r->nnz <= kSmallEntries ? kSmall : kLarge]->incoming.push_back(r.get());
+        const int k = r->nnz <= kSmallEntries ? kSmall : r->nnz <= kMediumEntries ? kMedium : kLarge;
+        workers_[(size_t)k]->incoming.push_back(r.get());
         all_[t] = std::move(r);
     }
     cv_work_.notify_all();
@@ -176,7 +177,7 @@ void Server::finish(ServeRequest *r) {
         r->done = true;
     }
     cv_done_.notify_all();
-    cv_work_.notify_all();   // memory freed: the other worker may admit
+    cv_work_.notify_all();   // memory freed: another worker may admit
 }
 
 void Server::fail(ServeRequest *r, int code, const std::string &msg) {

@@ -1,7 +1,9 @@
 // Request loop of the served form: graphs are submitted from any thread and
-// routed by size to one of two workers (each a thread with its own stream,
-// device pool and batch engines, so small graphs are not held back by the
-// level steps of large ones and the two streams overlap on the device).  A
+// routed by size to one of three batched workers (each a thread with its own
+// stream, device pool and batch engines, so a graph is not held back by the
+// level steps of much larger ones: a batch's members advance one level per
+// step together, and a step lasts as long as its largest member's level; the
+// streams overlap on the device).  A
 // worker admits its requests in arrival order while their estimated device
 // footprints fit the shared memory budget, and every admitted graph joins
 // the worker's running batch at the next level boundary (continuous
@@ -72,8 +74,10 @@ class Server {
     static size_t workspace_bytes(int64_t n, int64_t nnz);
     static double now_us();
 
-    // Requests with at most this many entries go to the small-graph worker.
+    // Requests with at most kSmallEntries entries go to the small-graph
+    // worker, up to kMediumEntries to the medium one, larger to the large one.
     static constexpr int64_t kSmallEntries = (int64_t)1 << 20;
+    static constexpr int64_t kMediumEntries = (int64_t)1 << 23;
 
   private:
     struct Worker {
@@ -85,9 +89,9 @@ class Server {
     void finish(ServeRequest *r);
     void fail(ServeRequest *r, int code, const std::string &msg);
 
-    // worker k: 0 small graphs, 1 large graphs (both batched), 2 graphs with
-    // 2W >= 2^31 (plain path, after their ingest by worker 0 or 1)
-    enum { kSmall = 0, kLarge = 1, kPlain = 2, kWorkers = 3 };
+    // worker k: 0 small, 1 medium, 2 large graphs (batched), 3 graphs with
+    // 2W >= 2^31 (plain path, after their ingest by a batched worker)
+    enum { kSmall = 0, kMedium = 1, kLarge = 2, kPlain = 3, kWorkers = 4 };
 
     int device_;
     Tuning tuning_;
