@@ -642,30 +642,45 @@ constexpr int kPiece = 16384;
 constexpr int kPieceBits = 13;
 constexpr int kPieceProbe = 32;
 constexpr int kPieceThreads = 1024;
+// Segments of kChunkMax + 1 .. kMidMax entries take one 256-thread
+// workgroup each with a 2^12-slot table (a quarter of the long pieces' LDS,
+// so three workgroups share a CU instead of one): their distinct columns
+// always fit the table's claimable 3/4.
+constexpr int kMidMax = 2730;
+constexpr int kMidBits = 12;
+constexpr int kMidThreads = 256;
 
-// Pieces of every segment (0 for segments of at most kChunkMax entries).
-__global__ __launch_bounds__(256) void k_big_pieces(const int64_t *__restrict__ off, int64_t k, int64_t *pieces) {
+// Pieces of every segment longer than kMidMax (0 otherwise), and a flag for
+// every segment of kChunkMax + 1 .. kMidMax entries; tot[0] / tot[1]
+// receive their entry counts.
+__global__ __launch_bounds__(256) void k_big_pieces(const int64_t *__restrict__ off, int64_t k, int64_t *pieces,
+                                                    int64_t *mids, unsigned long long *tot, int64_t piece) {
     const int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (a >= k) return;
     const int64_t sz = off[a + 1] - off[a];
-    pieces[a] = sz > kChunkMax ? (sz + kPiece - 1) / kPiece : 0;
+    pieces[a] = sz > kMidMax ? (sz + piece - 1) / piece : 0;
+    mids[a] = sz > kChunkMax && sz <= kMidMax ? 1 : 0;
+    if (sz > kMidMax) atomicAdd(&tot[0], (unsigned long long)sz);
+    else if (sz > kChunkMax) atomicAdd(&tot[1], (unsigned long long)sz);
 }
 
-// One workgroup per piece; poff: exclusive scan of the pieces (k + 1).
-__global__ __launch_bounds__(kPieceThreads) void k_big_piece(const int64_t *__restrict__ off, int64_t k,
-                                                             const int64_t *__restrict__ poff, int32_t *tcol,
-                                                             int64_t *tw, int64_t *mcount, uint64_t *pkey,
-                                                             int64_t *pval, unsigned long long *pcount, int bits,
-                                                             int64_t direct_max) {
-    constexpr int T = 1 << kPieceBits;
-    constexpr int Q = T / kPieceThreads;
+// One workgroup per piece of PIECE entries (THREADS threads, a table of
+// 2^TBITS slots); poff: exclusive scan of the pieces of every segment (k + 1).
+template <int THREADS, int TBITS, int PIECE>
+__global__ __launch_bounds__(THREADS) void k_big_piece(const int64_t *__restrict__ off, int64_t k,
+                                                       const int64_t *__restrict__ poff, int32_t *tcol,
+                                                       int64_t *tw, int64_t *mcount, uint64_t *pkey,
+                                                       int64_t *pval, unsigned long long *pcount, int bits,
+                                                       int64_t direct_max) {
+    constexpr int T = 1 << TBITS;
+    constexpr int Q = T / THREADS;
     __shared__ int32_t s_k[T];
     __shared__ long long s_v[T];
     __shared__ int64_t s_seg, s_idx;
     __shared__ int s_n, s_over, s_used;
     __shared__ unsigned long long s_base, s_obase;
     const int t = threadIdx.x;
-    for (int x = t; x < T; x += kPieceThreads) {
+    for (int x = t; x < T; x += THREADS) {
         s_k[x] = kEmpty;
         s_v[x] = 0;
     }
@@ -681,20 +696,20 @@ __global__ __launch_bounds__(kPieceThreads) void k_big_piece(const int64_t *__re
     }
     __syncthreads();
     const int64_t a = s_seg;
-    const int64_t lo = off[a] + s_idx * kPiece;
-    const int64_t end = off[a + 1] < lo + kPiece ? off[a + 1] : lo + kPiece;
+    const int64_t lo = off[a] + s_idx * PIECE;
+    const int64_t end = off[a + 1] < lo + PIECE ? off[a + 1] : lo + PIECE;
     // New columns claim slots only while the table is at most 3/4 full, so
     // probes stay short; a column that finds neither its slot nor room is
     // an overflow pair (marked here, written after one reservation).
     constexpr int kClaimMax = 3 * T / 4;
     uint32_t over = 0;   // entry q of this thread overflowed
     int n_over = 0;
-    static_assert(kPiece / kPieceThreads <= 32, "one mask bit per entry of a thread");
-    for (int q = 0; lo + t + (int64_t)q * kPieceThreads < end; ++q) {
-        const int64_t e = lo + t + (int64_t)q * kPieceThreads;
+    static_assert(PIECE / THREADS <= 32, "one mask bit per entry of a thread");
+    for (int q = 0; lo + t + (int64_t)q * THREADS < end; ++q) {
+        const int64_t e = lo + t + (int64_t)q * THREADS;
         const int32_t c = tcol[e];
         const int64_t w = tw[e];
-        uint32_t h = ((uint32_t)c * 0x9E3779B1u) >> (32 - kPieceBits);
+        uint32_t h = ((uint32_t)c * 0x9E3779B1u) >> (32 - TBITS);
         bool placed = false;
         for (int p = 0; p < kPieceProbe; ++p) {
             const int32_t cur = s_k[h];
@@ -728,7 +743,7 @@ __global__ __launch_bounds__(kPieceThreads) void k_big_piece(const int64_t *__re
         unsigned long long qpos = s_obase + (unsigned long long)my_over;
         for (int q = 0; over; ++q, over >>= 1) {
             if (!(over & 1u)) continue;
-            const int64_t e = lo + t + (int64_t)q * kPieceThreads;
+            const int64_t e = lo + t + (int64_t)q * THREADS;
             pkey[qpos] = ((uint64_t)a << bits) | (uint32_t)tcol[e];
             pval[qpos] = tw[e];
             ++qpos;
@@ -737,7 +752,7 @@ __global__ __launch_bounds__(kPieceThreads) void k_big_piece(const int64_t *__re
     int pos[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const int x = t + q * kPieceThreads;
+        const int x = t + q * THREADS;
         pos[q] = s_k[x] != kEmpty ? atomicAdd(&s_n, 1) : -1;
     }
     __syncthreads();
@@ -747,7 +762,7 @@ __global__ __launch_bounds__(kPieceThreads) void k_big_piece(const int64_t *__re
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             if (pos[q] < 0) continue;
-            const int x = t + q * kPieceThreads;
+            const int x = t + q * THREADS;
             tcol[off[a] + pos[q]] = s_k[x];
             tw[off[a] + pos[q]] = s_v[x];
         }
@@ -760,9 +775,134 @@ __global__ __launch_bounds__(kPieceThreads) void k_big_piece(const int64_t *__re
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         if (pos[q] < 0) continue;
-        const int x = t + q * kPieceThreads;
+        const int x = t + q * THREADS;
         pkey[base + pos[q]] = ((uint64_t)a << bits) | (uint32_t)s_k[x];
         pval[base + pos[q]] = s_v[x];
+    }
+}
+
+// As k_big_piece with a table of single words, (column + 1) << shift | the
+// weight sum, when every column + 1 fits the 64 - shift high bits and every
+// weight sum (at most 2W) the low ones: half the LDS per slot, so a piece of
+// kPieceW entries gets a 16,384-slot table (128 KB) whose claimable 3/4
+// hold every column of a piece even when all are distinct, and the middle
+// tier's 4,096-slot table takes 32 KB.  A claim is one compare-and-swap of
+// the whole word; an add to a claimed slot never carries into the column.
+constexpr int kPieceW = 12288;
+constexpr int kPieceWBits = 14;
+
+template <int THREADS, int TBITS, int PIECE>
+__global__ __launch_bounds__(THREADS) void k_piece_word(const int64_t *__restrict__ off, int64_t k,
+                                                        const int64_t *__restrict__ poff, int32_t *tcol,
+                                                        int64_t *tw, int64_t *mcount, uint64_t *pkey,
+                                                        int64_t *pval, unsigned long long *pcount, int bits,
+                                                        int64_t direct_max, int shift) {
+    constexpr int T = 1 << TBITS;
+    constexpr int Q = T / THREADS;
+    __shared__ unsigned long long s_t[T];
+    __shared__ int64_t s_seg, s_idx;
+    __shared__ int s_n, s_over, s_used;
+    __shared__ unsigned long long s_base, s_obase;
+    const int t = threadIdx.x;
+    for (int x = t; x < T; x += THREADS) s_t[x] = 0;
+    if (t < 64) {
+        const int64_t a = wave_find_le(poff, k, (int64_t)blockIdx.x);   // the segment holding this piece
+        if (t == 0) {
+            s_seg = a;
+            s_idx = (int64_t)blockIdx.x - poff[a];
+            s_n = 0;
+            s_over = 0;
+            s_used = 0;
+        }
+    }
+    __syncthreads();
+    const int64_t a = s_seg;
+    const int64_t lo = off[a] + s_idx * PIECE;
+    const int64_t end = off[a + 1] < lo + PIECE ? off[a + 1] : lo + PIECE;
+    const unsigned long long tmask = ~0ull << shift;
+    constexpr int kClaimMax = 3 * T / 4;
+    uint32_t over = 0;   // entry q of this thread overflowed
+    int n_over = 0;
+    static_assert(PIECE / THREADS <= 32, "one mask bit per entry of a thread");
+    for (int q = 0; lo + t + (int64_t)q * THREADS < end; ++q) {
+        const int64_t e = lo + t + (int64_t)q * THREADS;
+        const int32_t c = tcol[e];
+        const unsigned long long w = (unsigned long long)tw[e];
+        const unsigned long long tag = (unsigned long long)(uint32_t)(c + 1) << shift;
+        uint32_t h = ((uint32_t)c * 0x9E3779B1u) >> (32 - TBITS);
+        bool placed = false;
+        for (int p = 0; p < kPieceProbe; ++p) {
+            const unsigned long long cur = ((volatile unsigned long long *)s_t)[h];
+            if ((cur & tmask) == tag) {
+                atomicAdd(&s_t[h], w);
+                placed = true;
+                break;
+            }
+            if (cur == 0) {
+                if (s_used >= kClaimMax) break;
+                const unsigned long long prev = atomicCAS(&s_t[h], 0ull, tag | w);
+                if (prev == 0) {
+                    atomicAdd(&s_used, 1);
+                    placed = true;
+                    break;
+                }
+                if ((prev & tmask) == tag) {
+                    atomicAdd(&s_t[h], w);
+                    placed = true;
+                    break;
+                }
+            }
+            h = (h + 1) & (T - 1);
+        }
+        if (!placed) {
+            over |= 1u << q;
+            ++n_over;
+        }
+    }
+    const int my_over = n_over ? atomicAdd(&s_over, n_over) : 0;
+    __syncthreads();
+    if (t == 0 && s_over) s_obase = atomicAdd(pcount, (unsigned long long)s_over);
+    __syncthreads();
+    if (n_over) {
+        unsigned long long qpos = s_obase + (unsigned long long)my_over;
+        for (int q = 0; over; ++q, over >>= 1) {
+            if (!(over & 1u)) continue;
+            const int64_t e = lo + t + (int64_t)q * THREADS;
+            pkey[qpos] = ((uint64_t)a << bits) | (uint32_t)tcol[e];
+            pval[qpos] = tw[e];
+            ++qpos;
+        }
+    }
+    int pos[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int x = t + q * THREADS;
+        pos[q] = s_t[x] != 0 ? atomicAdd(&s_n, 1) : -1;
+    }
+    __syncthreads();
+    const bool direct = poff[a + 1] - poff[a] == 1 && s_over == 0 && s_n <= direct_max;
+    unsigned long long base = 0;
+    if (!direct) {
+        if (t == 0) s_base = atomicAdd(pcount, (unsigned long long)s_n);
+        __syncthreads();
+        base = s_base;
+    } else if (t == 0) {
+        mcount[a] = s_n;
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        if (pos[q] < 0) continue;
+        const unsigned long long wd = s_t[t + q * THREADS];
+        const int32_t c = (int32_t)(wd >> shift) - 1;
+        const int64_t w = (int64_t)(wd & ~tmask);
+        if (direct) {
+            // the whole segment was read above; its pairs go in place
+            tcol[off[a] + pos[q]] = c;
+            tw[off[a] + pos[q]] = w;
+        } else {
+            pkey[base + pos[q]] = ((uint64_t)a << bits) | (uint32_t)c;
+            pval[base + pos[q]] = w;
+        }
     }
 }
 
@@ -1019,18 +1159,29 @@ int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t 
         tl.launch(k_seg_start, vb, 256, 0, s_, g.row_ptr, newlab, n, off, cursor, seg_start_.p);
         LV_LAUNCHED("k_seg_start");
     }
-    // pieces of the segments longer than kChunkMax (unsorted contraction)
-    TempBuf pieces(sorted ? 16 : (size_t)(k + 1) * sizeof(int64_t), s_);
+    // unsorted contraction: pieces of the segments longer than kMidMax, and
+    // the segments of kChunkMax + 1 .. kMidMax entries
+    TempBuf pieces(sorted ? 16 : (size_t)(2 * (k + 1) + 2) * sizeof(int64_t), s_);
     int64_t *poff = pieces.as<int64_t>();
+    int64_t *moff = poff + (k + 1);
+    unsigned long long *ptot = (unsigned long long *)(moff + (k + 1));
+    // single-word piece tables when column + 1 and a weight sum (<= 2W) fit 64 bits together
+    int pshift = 64 - bits_for(k + 1);
+    if (pshift > 62 || (uint64_t)g.tw >= (1ull << pshift)) pshift = 0;
+    const int64_t piece = pshift ? kPieceW : kPiece;
     if (!sorted) {
-        TimedLaunch tl(t_, TG_CONTRACT, "k_big_pieces", (double)k * 24);
-        tl.launch(k_big_pieces, grid_for(k, 256), 256, 0, s_, off, k, poff);
+        fill<uint64_t>((uint64_t *)ptot, 0, 2, s_);
+        TimedLaunch tl(t_, TG_CONTRACT, "k_big_pieces", (double)k * 32);
+        tl.launch(k_big_pieces, grid_for(k, 256), 256, 0, s_, off, k, poff, moff, ptot, piece);
         LV_LAUNCHED("k_big_pieces");
+        scan_exclusive<int64_t, int64_t>(poff, poff, k, poff + k, s_, t_);
+        scan_exclusive<int64_t, int64_t>(moff, moff, k, moff + k, s_, t_);
     }
-    if (!sorted) scan_exclusive<int64_t, int64_t>(poff, poff, k, poff + k, s_, t_);
     Readback rb(s_);
     const int64_t *mr = rb.add(off + k);
     const int64_t *npc = sorted ? nullptr : rb.add(poff + k);
+    const int64_t *nmid = sorted ? nullptr : rb.add(moff + k);
+    const unsigned long long *ntot = sorted ? nullptr : rb.add(ptot, 2);
     rb.issue();   // read while the scatter runs
     {
         const int64_t eb = (g.nnz + kEntriesPerBlock - 1) / kEntriesPerBlock;
@@ -1067,11 +1218,29 @@ int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t 
         LV_LAUNCHED("k_seg_chunk");
     }
     if (npc && *npc > 0) {
-        // at most kPiece entries (column, weight) read per piece
-        TimedLaunch tl(t_, TG_CONTRACT, "k_big_piece", (double)*npc * kPiece * 12);
-        tl.launch(k_big_piece, (unsigned)*npc, kPieceThreads, 0, s_, off, k, (const int64_t *)poff, tcol_.p, tw_.p,
-                  mcount, key_[0].p, val_[0].p, pc.as<unsigned long long>(), bits, direct_max);
+        // per entry: column and weight read, one pair (column, weight) written at most
+        TimedLaunch tl(t_, TG_CONTRACT, "k_big_piece", (double)ntot[0] * 24);
+        if (pshift)
+            tl.launch(k_piece_word<kPieceThreads, kPieceWBits, kPieceW>, (unsigned)*npc, kPieceThreads, 0, s_, off,
+                      k, (const int64_t *)poff, tcol_.p, tw_.p, mcount, key_[0].p, val_[0].p,
+                      pc.as<unsigned long long>(), bits, direct_max, pshift);
+        else
+            tl.launch(k_big_piece<kPieceThreads, kPieceBits, kPiece>, (unsigned)*npc, kPieceThreads, 0, s_, off, k,
+                      (const int64_t *)poff, tcol_.p, tw_.p, mcount, key_[0].p, val_[0].p,
+                      pc.as<unsigned long long>(), bits, direct_max);
         LV_LAUNCHED("k_big_piece");
+    }
+    if (nmid && *nmid > 0) {
+        TimedLaunch tl(t_, TG_CONTRACT, "k_mid_seg", (double)ntot[1] * 24);
+        if (pshift)
+            tl.launch(k_piece_word<kMidThreads, kMidBits, 4096>, (unsigned)*nmid, kMidThreads, 0, s_, off, k,
+                      (const int64_t *)moff, tcol_.p, tw_.p, mcount, key_[0].p, val_[0].p,
+                      pc.as<unsigned long long>(), bits, direct_max, pshift);
+        else
+            tl.launch(k_big_piece<kMidThreads, kMidBits, 4096>, (unsigned)*nmid, kMidThreads, 0, s_, off, k,
+                      (const int64_t *)moff, tcol_.p, tw_.p, mcount, key_[0].p, val_[0].p,
+                      pc.as<unsigned long long>(), bits, direct_max);
+        LV_LAUNCHED("k_mid_seg");
     }
     const uint64_t *npp = rb.add(pc.as<uint64_t>());
     rb.fetch();
