@@ -591,7 +591,7 @@ def main():
                     help="keep the default launch shapes (skip the autotuner)")
     ap.add_argument("--shapes", default=None,
                     help="fixed launch shapes: small_max,block_max,pass_batch[,group_slots[,group_vertices"
-                         "[,overlap[,reorder]]]]")
+                         "[,overlap[,reorder[,group_tiles]]]]]")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rmat24", type=int, default=1,
                     help="also measure the R-MAT scale-24 workload (its own roofline, level-0 oracle sweeps, "

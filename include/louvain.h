@@ -410,7 +410,10 @@ typedef struct {
                             side), 2 as given, 0 auto = 1 for graphs with 2W >= 2^31
                             and at least 2^20 vertices, else 2.  Results never change:
                             labels stay the given vertex IDs                          */
-    int32_t reserved;    /* must be 0                                                  */
+    int32_t group_tiles; /* tiles (one vertex per lane group each) every workgroup of the
+                            packed-class sweep takes, 1..8 (0 = 1): with more than one,
+                            the loads of the next tiles are issued while a tile is
+                            swept (software pipelining; needs group_vertices 1)       */
     double ms;           /* louvain_autotune: device time of one run with this setting */
 } louvain_tuning;
 
@@ -424,7 +427,8 @@ int louvain_get_tuning(louvain_ctx ctx, louvain_tuning *tuning);
  * Autotuner: times one whole run of the method on g (params as for
  * louvain_run) under the context's current setting and each candidate
  * (small_max in {4, 8}, block_max in {1365, 2730, 10922}, pass_batch in
- * {1, 2}, group_vertices in {1, 2}; group_slots 4, overlap as set), best
+ * {1, 2}, group_vertices in {1, 2}, group_tiles in {1, 4} with one vertex
+ * per group; group_slots 4, overlap as set), best
  * of two runs each; a candidate replaces the current setting only when it
  * is more than 2% faster, so that timing noise does not flip the setting,
  * and the pick becomes the context's setting.  *best (optional) receives
@@ -439,7 +443,8 @@ int louvain_autotune(louvain_ctx ctx, louvain_graph g, const louvain_params *par
  * the given graphs (those with 2W < 2^31; params as for louvain_run_batch)
  * and tunes the launch shapes by coordinate descent, one round over the
  * fields: small_max {2, 4, 8}, group_slots {2, 4, 8}, group_vertices
- * {1, 2}, block_max {1365, 2730, 10922}, pass_batch {1, 2, 4}; each value
+ * {1, 2}, group_tiles {1, 2, 4}, block_max {1365, 2730, 10922},
+ * pass_batch {1, 2, 4}; each value
  * is timed (best of two calls) with the other fields at the best setting
  * so far, and kept only when it is more than 2% faster.  The pick becomes
  * the context's setting (and is written to its tuning file, if any);

@@ -75,7 +75,7 @@ class louvain_request_result(C.Structure):
 class louvain_tuning(C.Structure):
     _fields_ = [("small_max", C.c_int32), ("block_max", C.c_int32), ("pass_batch", C.c_int32),
                 ("group_slots", C.c_int32), ("group_vertices", C.c_int32), ("overlap", C.c_int32),
-                ("reorder", C.c_int32), ("reserved", C.c_int32), ("ms", C.c_double)]
+                ("reorder", C.c_int32), ("group_tiles", C.c_int32), ("ms", C.c_double)]
 
 
 class louvain_run_stats(C.Structure):
@@ -446,10 +446,11 @@ class Context:
         return Graph(self, h, dev)
 
     def set_tuning(self, small_max: int = 4, block_max: int = 2730, pass_batch: int = 2, group_slots: int = 4,
-                   group_vertices: int = 1, overlap: int = 0, reorder: int = 0):
+                   group_vertices: int = 1, overlap: int = 0, reorder: int = 0, group_tiles: int = 1):
         """Launch shapes of compact levels and the level-0 vertex order
         (0 auto, 1 by row length, 2 as given); results do not depend on them."""
-        t = louvain_tuning(small_max, block_max, pass_batch, group_slots, group_vertices, overlap, reorder, 0, 0.0)
+        t = louvain_tuning(small_max, block_max, pass_batch, group_slots, group_vertices, overlap, reorder,
+                           group_tiles, 0.0)
         self._check(self.lib.louvain_set_tuning(self.h, C.byref(t)))
 
     def get_tuning(self) -> dict:
@@ -457,7 +458,7 @@ class Context:
         self._check(self.lib.louvain_get_tuning(self.h, C.byref(t)))
         return dict(small_max=t.small_max, block_max=t.block_max, pass_batch=t.pass_batch,
                     group_slots=t.group_slots, group_vertices=t.group_vertices, overlap=t.overlap,
-                    reorder=t.reorder)
+                    reorder=t.reorder, group_tiles=t.group_tiles)
 
     def autotune(self, g: "Graph", theta_num: int = 1, theta_den: int = 1_000_000, max_sweeps: int = 1000,
                  max_levels: int = 64, singlet_rule: bool = True) -> dict:
@@ -467,7 +468,7 @@ class Context:
         self._check(self.lib.louvain_autotune(self.h, g.h, C.byref(prm), C.byref(t)))
         return dict(small_max=t.small_max, block_max=t.block_max, pass_batch=t.pass_batch,
                     group_slots=t.group_slots, group_vertices=t.group_vertices, overlap=t.overlap,
-                    reorder=t.reorder, ms=t.ms)
+                    reorder=t.reorder, group_tiles=t.group_tiles, ms=t.ms)
 
     def autotune_batch(self, graphs, theta_num: int = 1, theta_den: int = 1_000_000, max_sweeps: int = 1000,
                        max_levels: int = 64, singlet_rule: bool = True) -> dict:
@@ -479,7 +480,7 @@ class Context:
         self._check(self.lib.louvain_autotune_batch(self.h, len(graphs), hs, C.byref(prm), C.byref(t)))
         return dict(small_max=t.small_max, block_max=t.block_max, pass_batch=t.pass_batch,
                     group_slots=t.group_slots, group_vertices=t.group_vertices, overlap=t.overlap,
-                    reorder=t.reorder, ms=t.ms)
+                    reorder=t.reorder, group_tiles=t.group_tiles, ms=t.ms)
 
     def serve_budget(self, nbytes: int):
         """Device-memory budget of the request loop (0: 80% of free memory at start)."""

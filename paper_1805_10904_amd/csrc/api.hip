@@ -144,7 +144,7 @@ lv::Tuning tuning_from(const louvain_tuning &t) {
     require(t.group_vertices >= 0 && t.group_vertices <= 2, LOUVAIN_EINVAL, "group_vertices must be 0, 1 or 2");
     require(t.overlap == 0 || t.overlap == 1, LOUVAIN_EINVAL, "overlap must be 0 or 1");
     require(t.reorder >= 0 && t.reorder <= 2, LOUVAIN_EINVAL, "reorder must be 0, 1 or 2");
-    require(t.reserved == 0, LOUVAIN_EINVAL, "reserved must be 0");
+    require(t.group_tiles >= 0 && t.group_tiles <= 8, LOUVAIN_EINVAL, "group_tiles must be in [0, 8]");
     lv::Tuning tn;
     tn.small_max = t.small_max;
     tn.block_max = t.block_max;
@@ -153,6 +153,7 @@ lv::Tuning tuning_from(const louvain_tuning &t) {
     tn.group_vertices = t.group_vertices == 0 ? 1 : t.group_vertices;
     tn.overlap = t.overlap;
     tn.reorder = t.reorder;
+    tn.group_tiles = t.group_tiles == 0 ? 1 : t.group_tiles;
     return tn;
 }
 
@@ -166,6 +167,7 @@ louvain_tuning tuning_to(const lv::Tuning &tn) {
     t.group_vertices = tn.group_vertices;
     t.overlap = tn.overlap;
     t.reorder = tn.reorder;
+    t.group_tiles = tn.group_tiles;
     return t;
 }
 
@@ -209,6 +211,7 @@ bool load_tuning(const std::string &path, const std::string &arch, lv::Tuning *o
         else if (key == "group_vertices") t.group_vertices = (int32_t)v;
         else if (key == "overlap") t.overlap = (int32_t)v;
         else if (key == "reorder") t.reorder = (int32_t)v;
+        else if (key == "group_tiles") t.group_tiles = (int32_t)v;
         else require(false, LOUVAIN_EINVAL, path + ":" + std::to_string(line_no) + ": unknown key '" + key + "'");
     }
     if (file_arch != arch) return false;
@@ -230,6 +233,7 @@ void save_tuning(const std::string &path, const std::string &arch, const lv::Tun
         f << "group_vertices " << tn.group_vertices << "\n";
         f << "overlap " << tn.overlap << "\n";
         f << "reorder " << tn.reorder << "\n";
+        f << "group_tiles " << tn.group_tiles << "\n";
         require((bool)f, LOUVAIN_EINVAL, "cannot write the tuning file " + path);
     }
     require(std::rename(tmp.c_str(), path.c_str()) == 0, LOUVAIN_EINVAL, "cannot replace the tuning file " + path);
@@ -470,6 +474,9 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
         bool cut_sorted = false;   // the last contraction (a cut run's) sorted its rows
         for (int level = 0; level < prm.max_levels; ++level) {
             const size_t rec0 = timer.recs.size();
+            char rname[48];
+            snprintf(rname, sizeof rname, "louvain level %d: sweeps", level);
+            std::unique_ptr<lv::Range> range(new lv::Range(rname));
             sw.plan(v);
             if (permuted)
                 sw.init_singletons(v, rg.order.p);
@@ -506,6 +513,10 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
             // they do none of the method's work and stay out of the statistics
             if (timing && st.pass >= 0 && (size_t)st.pass < pass_rec.size())
                 for (size_t r = pass_rec[(size_t)st.pass]; r < timer.recs.size(); ++r) timer.recs[r].launched = false;
+            range.reset();
+            if (lv::log_on())
+                fprintf(stderr, "[louvain] level %d: n %lld, nnz %lld, passes %d, sweeps kept %d%s\n", level,
+                        (long long)v.n, (long long)v.nnz, st.pass, st.accepted, st.limit ? " (max_sweeps)" : "");
             auto &ls = local.level[level];
             ls.n = v.n;
             ls.nnz = v.nnz;
@@ -537,6 +548,8 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
                 ls.q_int.lo = (uint64_t)q_final;
                 ls.q_int.hi = (int64_t)(q_final >> 64);
             }
+            snprintf(rname, sizeof rname, "louvain level %d: contraction", level);
+            lv::Range crange(rname);
             const int64_t k = ct.renumber(cfin, v.n, newlab.p);
             ct.compose(fin_p, n0, newlab.p);
             // after composing, fin_p holds level 0's map in the given vertex order
@@ -1143,20 +1156,23 @@ int louvain_autotune(louvain_ctx ctx, louvain_graph g, const louvain_params *par
         for (int sm : {4, 8})
             for (int64_t bm : {(int64_t)1365, (int64_t)2730, lv::kCompactBlockMax})
                 for (int pb : {1, 2})
-                    for (int gv : {1, 2}) {
-                        lv::Tuning tn;
-                        tn.small_max = sm;
-                        tn.block_max = bm;
-                        tn.pass_batch = pb;
-                        tn.group_vertices = gv;
-                        tn.overlap = cur.overlap;
-                        tn.reorder = cur.reorder;
-                        const double ms = std::min(time_run(tn), time_run(tn));
-                        if (ms < pick_ms && ms < 0.98 * cur_ms) {
-                            pick_ms = ms;
-                            pick = tn;
+                    for (int gv : {1, 2})
+                        for (int gt : {1, 4}) {
+                            if (gv == 2 && gt > 1) continue;   // pipelining takes one vertex per group
+                            lv::Tuning tn;
+                            tn.small_max = sm;
+                            tn.block_max = bm;
+                            tn.pass_batch = pb;
+                            tn.group_vertices = gv;
+                            tn.group_tiles = gt;
+                            tn.overlap = cur.overlap;
+                            tn.reorder = cur.reorder;
+                            const double ms = std::min(time_run(tn), time_run(tn));
+                            if (ms < pick_ms && ms < 0.98 * cur_ms) {
+                                pick_ms = ms;
+                                pick = tn;
+                            }
                         }
-                    }
         ctx->tuning = pick;
         if (!ctx->tuning_path.empty()) save_tuning(ctx->tuning_path, device_arch(ctx->device), pick, pick_ms);
         if (best) {
@@ -1245,6 +1261,7 @@ int louvain_autotune_batch(louvain_ctx ctx, int64_t ngraphs, const louvain_graph
         try_field([](lv::Tuning &t, int64_t v) { t.small_max = (int)v; }, {2, 4, 8});
         try_field([](lv::Tuning &t, int64_t v) { t.group_slots = (int)v; }, {2, 4, 8});
         try_field([](lv::Tuning &t, int64_t v) { t.group_vertices = (int)v; }, {1, 2});
+        try_field([](lv::Tuning &t, int64_t v) { t.group_tiles = (int)v; }, {1, 2, 4});
         try_field([](lv::Tuning &t, int64_t v) { t.block_max = v; }, {1365, 2730, lv::kCompactBlockMax});
         try_field([](lv::Tuning &t, int64_t v) { t.pass_batch = (int)v; }, {1, 2, 4});
         ctx->tuning = pick;

@@ -202,6 +202,7 @@ void BatchEngine::ensure(UBuf &u, int64_t n, int64_t m, int64_t keep_n, int64_t 
 }
 
 std::vector<BatchMember *> BatchEngine::step() {
+    Range range("louvain batched step");
     std::vector<BatchMember *> out;
     out.swap(finished_);
     // newcomers that keep the union's vertex count within int32 labels

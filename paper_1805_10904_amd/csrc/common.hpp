@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -14,6 +15,8 @@
 #include <tuple>
 #include <type_traits>
 #include <vector>
+
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "arena.hpp"
 #include "louvain.h"
@@ -216,6 +219,28 @@ struct DevBuf {
     }
     T *get() const { return p; }
 };
+
+// ------------------------------------------------------------ diagnostics --
+
+// A named range around host-side phases (a level's sweeps, its
+// contraction, a batched step), visible to profilers that trace roctx
+// markers (rocprofv3 --marker-trace); free when none is attached.
+struct Range {
+    explicit Range(const char *name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range &) = delete;
+    Range &operator=(const Range &) = delete;
+};
+
+// LOUVAIN_LOG set to a non-empty value other than 0: per-level progress on
+// stderr (read once per process).
+inline bool log_on() {
+    static const bool on = [] {
+        const char *e = getenv("LOUVAIN_LOG");
+        return e && *e && !(e[0] == '0' && e[1] == 0);
+    }();
+    return on;
+}
 
 // -------------------------------------------------------------- timing --
 

@@ -37,7 +37,27 @@ struct SweepArgs {
     int64_t *e_self;   // optional per-vertex e_{i->c_i} incl. loop
     int hub_shift;     // > 0: hub tables hold one word (label + 1) << hub_shift | e per slot
     int first;         // the labelling read is the singletons: score entries directly, no tables
+    // Published words of the labelling read, one per vertex (nullptr: read
+    // c_cur and deg): label c_j in the low pw_bits bits, deg of c_j in bits
+    // pw_bits .. 62, bit 63 set iff c_j is a singleton.  Written at the start
+    // of each pass when pw_bits + the bits of TW fit 63.
+    const uint64_t *pw;
+    int pw_bits;
 };
+
+__device__ __forceinline__ int32_t pw_label(uint64_t w, int bits) { return (int32_t)(w & ((1ull << bits) - 1)); }
+__device__ __forceinline__ int64_t pw_deg(uint64_t w, int bits) { return (int64_t)((w << 1) >> (bits + 1)); }
+
+// Community of neighbour j (and, with published words, its degree).
+__device__ __forceinline__ int32_t nb_label(const SweepArgs &a, int32_t j, int64_t *deg) {
+    if (a.pw) {
+        const uint64_t w = a.pw[j];
+        *deg = pw_deg(w, a.pw_bits);
+        return pw_label(w, a.pw_bits);
+    }
+    *deg = -1;
+    return a.c_cur[j];
+}
 
 template <typename W>
 __device__ __forceinline__ int64_t wload(const void *w, int64_t e) {
@@ -49,14 +69,14 @@ __device__ __forceinline__ int64_t wload(const void *w, int64_t e) {
 // Add weight w under label k in an LDS table of 2^BITS slots (open
 // addressing, linear probing).  The table is never more than half full.
 template <int BITS>
-__device__ __forceinline__ void lds_insert(int32_t *key, unsigned long long *val, int32_t k, int64_t w) {
+__device__ __forceinline__ int lds_insert(int32_t *key, unsigned long long *val, int32_t k, int64_t w) {
     constexpr uint32_t kMask = (1u << BITS) - 1;
     uint32_t h = hash_pow2(k, BITS);
     while (true) {
         const int32_t prev = atomicCAS(&key[h], kEmpty, k);   // claims, or returns the slot's key
         if (prev == kEmpty || prev == k) {
             atomicAdd(&val[h], (unsigned long long)w);
-            return;
+            return (int)h;
         }
         h = (h + 1) & kMask;
     }
@@ -193,12 +213,18 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a, const int32_t 
     constexpr int NG = 256 / G;
     __shared__ int32_t s_key[NG * T];
     __shared__ unsigned long long s_val[NG * T];
+    // candidates' deg_C beside their e in LDS (with published words), for
+    // the small tables only: the larger ones would lose occupancy to it and
+    // gather deg_C when they score
+    constexpr bool DEG_LDS = NG * T <= 1024;
+    __shared__ int64_t s_deg[DEG_LDS ? NG * T : 1];
     __shared__ unsigned long long s_I;
     if (a.st->done) return;
     const int tid = threadIdx.x;
     const int g = tid / G, lane = tid % G;
     int32_t *key = s_key + g * T;
     unsigned long long *val = s_val + g * T;
+    int64_t *tdeg = s_deg + (DEG_LDS ? g * T : 0);
     if (!a.first) {   // the first pass from singletons uses no table
 #pragma unroll
         for (int x = lane; x < T; x += G) {
@@ -227,7 +253,7 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a, const int32_t 
     constexpr int U = 4;
     for (int64_t e0 = rs + lane; e0 < re; e0 += (int64_t)U * G) {
         int32_t jq[U], lq[U];
-        int64_t wq[U];
+        int64_t wq[U], dq[U];
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             const int64_t e = e0 + (int64_t)q * G;
@@ -239,19 +265,25 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a, const int32_t 
             }
         }
 #pragma unroll
-        for (int q = 0; q < U; ++q) lq[q] = (jq[q] >= 0 && jq[q] != i) ? a.c_cur[jq[q]] : -1;
+        for (int q = 0; q < U; ++q) {
+            lq[q] = -1;
+            dq[q] = -1;
+            if (jq[q] >= 0 && jq[q] != i) lq[q] = nb_label(a, jq[q], &dq[q]);
+        }
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             if (jq[q] == i) loop += wq[q];
             if (lq[q] < 0) continue;
             if (a.first) {   // every neighbour is its own community
-                const S sc = score_mul<S>(a.tw, wq[q]) - score_mul<S>(di, a.deg[lq[q]]);
+                const int64_t dg = dq[q] >= 0 ? dq[q] : a.deg[lq[q]];
+                const S sc = score_mul<S>(a.tw, wq[q]) - score_mul<S>(di, dg);
                 if (better<S>(sc, lq[q], bs, bl)) {
                     bs = sc;
                     bl = lq[q];
                 }
             } else {
-                lds_insert<BITS>(key, val, lq[q], wq[q]);
+                const int h = lds_insert<BITS>(key, val, lq[q], wq[q]);
+                if (DEG_LDS && a.pw) tdeg[h] = dq[q];   // every inserter of a label writes the same degree
             }
         }
     }
@@ -267,7 +299,7 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a, const int32_t 
                 e_own = ev;
                 continue;
             }
-            const S sc = score_mul<S>(a.tw, ev) - score_mul<S>(di, a.deg[k]);
+            const S sc = score_mul<S>(a.tw, ev) - score_mul<S>(di, DEG_LDS && a.pw ? tdeg[x] : a.deg[k]);
             if (better<S>(sc, k, bs, bl)) {
                 bs = sc;
                 bl = k;
@@ -678,8 +710,13 @@ __global__ __launch_bounds__(256) void k_hub_accum(SweepArgs a, HubMeta hm, int3
             wq[q] = wload<W>(a.w, e);
         }
     }
+    int64_t dq[U];
 #pragma unroll
-    for (int q = 0; q < U; ++q) lq[q] = (jq[q] >= 0 && jq[q] != v) ? a.c_cur[jq[q]] : -1;
+    for (int q = 0; q < U; ++q) {
+        lq[q] = -1;
+        dq[q] = -1;
+        if (jq[q] >= 0 && jq[q] != v) lq[q] = nb_label(a, jq[q], &dq[q]);
+    }
     int64_t loop = 0;
 #pragma unroll
     for (int q = 0; q < U; ++q)
@@ -694,7 +731,7 @@ __global__ __launch_bounds__(256) void k_hub_accum(SweepArgs a, HubMeta hm, int3
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             if (lq[q] < 0) continue;
-            const S sc = score_mul<S>(a.tw, wq[q]) - score_mul<S>(di, a.deg[lq[q]]);
+            const S sc = score_mul<S>(a.tw, wq[q]) - score_mul<S>(di, dq[q] >= 0 ? dq[q] : a.deg[lq[q]]);
             if (better<S>(sc, lq[q], bs, bl)) {
                 bs = sc;
                 bl = lq[q];
@@ -850,9 +887,11 @@ __global__ __launch_bounds__(256) void k_commit(const int32_t *__restrict__ c_cu
     if (threadIdx.x == 0 && s_m) atomicAdd(&st->moved, s_m);
 }
 
-// Per-block partial sums of deg_C^2 (128-bit) of the labelling a pass reads.
+// Per-block partial sums of deg_C^2 (128-bit) of the labelling a pass reads;
+// with pw, also every vertex's published word of that labelling.
 __global__ __launch_bounds__(256) void k_qsum(const int64_t *__restrict__ deg, int64_t n, uint64_t *part,
-                                              const PhaseState *st) {
+                                              const PhaseState *st, const int32_t *__restrict__ c,
+                                              const int32_t *__restrict__ size, uint64_t *pw, int pw_bits) {
     __shared__ uint64_t slo[4];
     __shared__ int64_t shi[4];
     if (st->done) return;
@@ -864,6 +903,11 @@ __global__ __launch_bounds__(256) void k_qsum(const int64_t *__restrict__ deg, i
         if (v < n) {
             const int64_t d = deg[v];
             s += mul_wide(d, d);
+            if (pw) {
+                const int32_t cv = c[v];
+                pw[v] = (uint64_t)(uint32_t)cv | ((uint64_t)deg[cv] << pw_bits) |
+                        (size[cv] == 1 ? (1ull << 63) : 0ull);
+            }
         }
     }
 #pragma unroll
@@ -1331,14 +1375,19 @@ __global__ __launch_bounds__(kWideThreads) void k_sweep_wide(SweepArgs a, const 
                 wq[q] = wload<W>(a.w, e);
             }
         }
+        int64_t dq[U];
 #pragma unroll
-        for (int q = 0; q < U; ++q) lq[q] = (jq[q] >= 0 && jq[q] != i) ? a.c_cur[jq[q]] : -1;
+        for (int q = 0; q < U; ++q) {
+            lq[q] = -1;
+            dq[q] = -1;
+            if (jq[q] >= 0 && jq[q] != i) lq[q] = nb_label(a, jq[q], &dq[q]);
+        }
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             if (jq[q] == i) s_loop = wq[q];   // a row has at most one loop
             if (lq[q] < 0) continue;
             if (a.first) {   // every neighbour is its own community
-                const S sc = score_mul<S>(a.tw, wq[q]) - score_mul<S>(di, a.deg[lq[q]]);
+                const S sc = score_mul<S>(a.tw, wq[q]) - score_mul<S>(di, dq[q] >= 0 ? dq[q] : a.deg[lq[q]]);
                 if (better<S>(sc, lq[q], bs, bl)) {
                     bs = sc;
                     bl = lq[q];
@@ -1417,7 +1466,8 @@ static void launch_pass(const SweepArgs &a, const int32_t *list, const int64_t *
     const std::string sfx = t ? std::string(type_name<W>()) + "," + type_name<S>() + ">" : std::string();
     const std::string wsfx = t ? std::string(type_name<W>()) + ">" : std::string();
     const std::string ssfx = t ? std::string(type_name<S>()) + ">" : std::string();
-    const double eb = 8.0 + sizeof(W);   // col + weight + label gather per entry
+    // per entry: column, weight and the neighbour's label (4 bytes) or published word (8)
+    const double eb = (a.pw ? 12.0 : 8.0) + sizeof(W);
     const double vb = 40.0;              // per evaluated vertex
     auto cnt = [&](int b) { return bstart[b + 1] - bstart[b]; };
     auto bytes = [&](int b) { return (double)cnt(b) * vb + (double)bnnz[b] * eb; };
@@ -1548,6 +1598,7 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
         cp.small_max = tuning_.small_max;
         cp.group_slots = tuning_.group_slots;
         cp.group_vertices = tuning_.group_vertices;
+        cp.group_tiles = tuning_.group_tiles;
         cp.first = singleton_start_ && p == 1 ? 1 : 0;
         cp.overlap = tuning_.overlap;
         for (int c = 0; c <= kLdsClasses; ++c) cp.cstart[c] = cstart_[c];
@@ -1581,16 +1632,23 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
         compact_pass(g, cp, cs, p, prm, s_, t_);
         return;
     }
+    // published words (label, deg_C, singleton flag) on levels with 128-bit
+    // scores, when the label bits and the bits of TW fit 63 together
+    int pw_bits = 1;
+    while (pw_bits < 31 && ((int64_t)1 << pw_bits) < g.n) ++pw_bits;
+    const bool publish = g.tw > kTwFastMax && pw_bits + 64 - __builtin_clzll((unsigned long long)g.tw) <= 63;
     if (g.n > 0) {
-        TimedLaunch tl(t_, TG_SWEEP, "k_qsum", (double)g.n * 8);
-        tl.launch(k_qsum, (unsigned)qblocks_, 256, 0, s_, deg_.p, g.n, qpart_.p, st_.p);
+        TimedLaunch tl(t_, TG_SWEEP, "k_qsum", (double)g.n * (publish ? 32 : 8));
+        tl.launch(k_qsum, (unsigned)qblocks_, 256, 0, s_, deg_.p, g.n, qpart_.p, st_.p, (const int32_t *)c_[cur].p,
+                  (const int32_t *)size_.p, publish ? vw_.p : (uint64_t *)nullptr, pw_bits);
         LV_LAUNCHED("k_qsum");
     }
     // hub and wide-row tables as single words when label + 1 and e (<= 2W)
     // fit 64 bits together
     const int hub_shift = word_shift(g.n, g.tw);
     SweepArgs a{g.row_ptr, g.col, g.w, c_[cur].p, c_[nxt].p, g.delta, deg_.p, size_.p,
-                g.tw, prm.singlet, st_.p, e_self_out, hub_shift, singleton_start_ && p == 1 ? 1 : 0};
+                g.tw, prm.singlet, st_.p, e_self_out, hub_shift, singleton_start_ && p == 1 ? 1 : 0,
+                publish ? vw_.p : nullptr, pw_bits};
     int64_t *tab_off = hub_meta_.p;
     HubMeta hm{list_.p + bstart_[B_HUB], tab_off, tab_off + (hubs_ + 1), tab_off + 2 * (hubs_ + 1),
                tab_off + 3 * (hubs_ + 1), hub_of_chunk_.p, hub_of_scan_.p, hubs_};

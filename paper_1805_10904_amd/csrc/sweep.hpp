@@ -71,6 +71,7 @@ struct Tuning {
     int pass_batch = 2;                 // sweep passes between host checks
     int group_slots = 4;                // LDS slots per lane of the packed-class sweep (2, 4 or 8)
     int group_vertices = 1;             // vertices per lane group of the packed-class sweep (1 or 2)
+    int group_tiles = 1;                // tiles per workgroup of the packed-class sweep (1..8; > 1 pipelined)
     int overlap = 0;                    // 1: row families on side streams, side by side
     int reorder = 0;                    // level-0 vertex order by row length: 0 auto, 1 on, 2 off
 };
@@ -98,6 +99,7 @@ struct CompactPass {
     int small_max = 8;                         // rows swept one thread per vertex
     int group_slots = 4;                       // slots per lane of the packed classes
     int group_vertices = 1;                    // vertices per lane group of the packed classes
+    int group_tiles = 1;                       // tiles per workgroup of the packed classes
     int first = 0;                             // the labelling read is the singletons (every
                                                // neighbour its own community): no tables
     int overlap = 0;                           // row families side by side on side streams

@@ -912,6 +912,221 @@ __global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__re
     }
 }
 
+// The packed classes with software pipelining across tiles: workgroup w of
+// class c sweeps tiles [w * TPW, (w + 1) * TPW) of the class (a tile = one
+// lane group per vertex, NV vertices, as in k_cpt_groups with one vertex
+// per group).  While tile j's neighbours' published words are gathered, the
+// columns and weights of tile j + 1 and the class-list words of tile j + 2
+// are already in flight, so the three dependent loads of a tile overlap
+// with the work of the tiles before it.  Every vertex is decided exactly as
+// in k_cpt_groups.
+struct PipeBlocks {
+    int64_t bo[kGroupClasses + 1];     // first workgroup of every class
+    int64_t cstart[kGroupClasses + 1]; // first row of every class in the class list
+    int tpw;                           // tiles per workgroup
+};
+
+template <int SPL, typename W>
+__global__ __launch_bounds__(256) void k_cpt_groups_pipe(CArgs a, const int32_t *__restrict__ list,
+                                                         const uint64_t *__restrict__ info, PipeBlocks pb) {
+    if (single_done(a.gid, a.st)) return;
+    static_assert(SPL == 2 || SPL == 4 || SPL == 8, "2, 4 or 8 slots per lane");
+    constexpr int LB = SPL == 2 ? 1 : SPL == 4 ? 2 : 3;   // log2 SPL
+    constexpr int U = (2 * SPL + 2) / 3;     // entries per lane at most
+    __shared__ int32_t s_key[256 * SPL];
+    __shared__ uint32_t s_e[256 * SPL], s_hi[256 * SPL];
+    __shared__ unsigned long long r_ok[4];
+    __shared__ uint32_t r_lf[4];
+    __shared__ uint32_t s_eown[128], s_loop[128];
+    const int t = threadIdx.x;
+    int c = 0;
+    while (c < kGroupClasses - 1 && (int64_t)blockIdx.x >= pb.bo[c + 1]) ++c;
+    const int bits = 4 + c;
+    const int G = (16 >> LB) << c;
+    const int NV = (16 * SPL) >> c;
+    const int kv = t >> (4 - LB + c), li = t & (G - 1);
+    const int S = 16 << c;
+    int32_t *key = s_key + kv * S;
+    uint32_t *es = s_e + kv * S, *hs = s_hi + kv * S;
+    const int64_t cend = pb.cstart[c + 1];
+    const int64_t tile0 = ((int64_t)blockIdx.x - pb.bo[c]) * pb.tpw;
+    const int64_t ntile = (cend - pb.cstart[c] + NV - 1) / NV;
+    const int64_t tiles = ntile - tile0 < pb.tpw ? ntile - tile0 : pb.tpw;
+    // pipeline registers: row k of the class list for tiles j + 1 (entries
+    // loaded) and j + 2 (list words loaded)
+    auto row_of = [&](int64_t j) { return pb.cstart[c] + j * NV + kv; };
+    int32_t v1 = 0, v2 = 0;
+    uint64_t ri1 = 0, ri2 = 0;
+    {
+        const int64_t k = row_of(tile0);
+        if (k < cend) {
+            v1 = list[k];
+            ri1 = info[k];
+        } else {
+            ri1 = 0;
+        }
+        const int64_t k2 = row_of(tile0 + 1);
+        if (tiles > 1 && k2 < cend) {
+            v2 = list[k2];
+            ri2 = info[k2];
+        }
+    }
+    int32_t jn[U];
+    uint32_t wn[U];
+    // entries of the first tile
+    {
+        const int64_t rs = info_start(ri1), d = info_len(ri1);
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            const int64_t x = li + (int64_t)q * G;
+            jn[q] = v1;
+            wn[q] = 0;
+            if (x < d) {
+                jn[q] = a.col[rs + x];
+                wn[q] = cw<W>(a.w, rs + x);
+            }
+        }
+    }
+    for (int64_t j = 0; j < tiles; ++j) {
+        // this tile: vertex v, its row (entries in jq / wq)
+        const int64_t k = row_of(tile0 + j);
+        const int32_t v = v1;
+        const uint64_t ri = ri1;
+        int32_t jq[U];
+        uint32_t wq[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            jq[q] = jn[q];
+            wq[q] = wn[q];
+        }
+        bool live = false;
+        int g = 0;
+        int64_t d = 0;
+        if (k < cend) {
+            g = graph_of(a.gid, v);
+            live = !a.st[g].done;
+            d = live ? info_len(ri) : 0;
+        }
+        // gathers of this tile
+        uint64_t nq[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            nq[q] = 0;
+            if ((int64_t)(li + q * G) < d && jq[q] != v) nq[q] = a.vw[jq[q]];
+        }
+        int32_t ci = -1;
+        uint32_t own_hi = 0, di = 0, tw = 0;
+        if (live) {
+            const uint64_t own = a.vw[v];
+            ci = vw_label(own);
+            own_hi = (uint32_t)(own >> 32);
+            di = (uint32_t)a.delta[v];
+            tw = (uint32_t)a.tw[g];
+        }
+        // entries of the next tile, list words of the one after
+        v1 = v2;
+        ri1 = ri2;
+        if (j + 1 < tiles) {
+            const int64_t rs = info_start(ri1), dn = info_len(ri1);
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int64_t x = li + (int64_t)q * G;
+                jn[q] = v1;
+                wn[q] = 0;
+                if (x < dn) {
+                    jn[q] = a.col[rs + x];
+                    wn[q] = cw<W>(a.w, rs + x);
+                }
+            }
+            const int64_t k2 = row_of(tile0 + j + 2);
+            ri2 = 0;
+            if (j + 2 < tiles && k2 < cend) {
+                v2 = list[k2];
+                ri2 = info[k2];
+            }
+        }
+        // the previous tile's scoring is finished: the tables may be reused
+        __syncthreads();
+        if (!a.first) {
+#pragma unroll
+            for (int q = 0; q < SPL; ++q) {
+                key[li + q * G] = kEmpty;
+                es[li + q * G] = 0;
+            }
+        }
+        if (li == 0) {
+            s_eown[kv] = 0;
+            s_loop[kv] = 0;
+        }
+        __syncthreads();
+        unsigned long long bok = 0;
+        uint32_t blf = 0xffffffffu;
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            if ((int64_t)(li + q * G) >= d) continue;
+            if (jq[q] == v) {
+                if (wq[q]) s_loop[kv] = wq[q];
+                continue;
+            }
+            const uint32_t hi = (uint32_t)(nq[q] >> 32);
+            if (a.first) {
+                const unsigned long long ok =
+                    ((uint64_t)tw * wq[q] - (uint64_t)di * hi_deg(hi)) ^ 0x8000000000000000ull;
+                best_take(bok, blf, (uint32_t)ok, (uint32_t)(ok >> 32),
+                          ((uint32_t)vw_label(nq[q]) << 1) | (hi_single(hi) ? 1u : 0u));
+            } else {
+                grp_insert(key, es, hs, bits, vw_label(nq[q]), wq[q], hi);
+            }
+        }
+        __syncthreads();
+        if (!a.first) {
+#pragma unroll
+            for (int q = 0; q < SPL; ++q) {
+                const int x = li + q * G;
+                const int32_t kk = key[x];
+                if (kk == kEmpty) continue;
+                const uint32_t e = es[x];
+                if (kk == ci) {
+                    s_eown[kv] = e;
+                    continue;
+                }
+                const uint32_t hi = hs[x];
+                const unsigned long long ok =
+                    ((uint64_t)tw * e - (uint64_t)di * hi_deg(hi)) ^ 0x8000000000000000ull;
+                best_take(bok, blf, (uint32_t)ok, (uint32_t)(ok >> 32), ((uint32_t)kk << 1) | (hi_single(hi) ? 1u : 0u));
+            }
+        }
+        const int GW = G < 64 ? G : 64;
+        group_best(bok, blf, GW);
+        if (G > 64) {   // uniform over the workgroup: the class is
+            const int wid = t >> 6;
+            if ((t & 63) == 0) {
+                r_ok[wid] = bok;
+                r_lf[wid] = blf;
+            }
+            __syncthreads();
+            if (li == 0)
+                for (int w2 = wid + 1; w2 < wid + G / 64; ++w2)
+                    if (r_ok[w2] > bok || (r_ok[w2] == bok && r_lf[w2] < blf)) {
+                        bok = r_ok[w2];
+                        blf = r_lf[w2];
+                    }
+        } else {
+            // the group's lanes are in one wavefront: its LDS accesses complete
+            // in order, so the cells written above are visible to lane 0
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (li == 0 && live) {
+            const uint32_t e_own = s_eown[kv];
+            a.c_nxt[v] = cpt_decide(a.singlet, (int64_t)tw, ci, own_hi, (int64_t)di, (int64_t)e_own, bok != 0,
+                                    (int64_t)(bok ^ 0x8000000000000000ull), (int32_t)(blf >> 1), (blf & 1u) != 0);
+            a.e_self[v] = e_own + s_loop[kv];
+        }
+    }
+}
+
 // Table-size class of a row swept from LDS: the smallest packed class c
 // with 3d <= 2 * (16 << c), else 2048, 4096 or 16384 slots.
 __device__ __forceinline__ int size_class(int64_t d) {
@@ -1481,7 +1696,27 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
             gbytes += (double)cnt * vb + (double)cp.cnnz[c] * eb;
         }
         for (int c = 0; c <= kGroupClasses; ++c) gb.cstart[c] = cp.cstart[c];
-        if (gb.bo[kGroupClasses] > 0) {
+        if (gb.bo[kGroupClasses] > 0 && cp.group_tiles > 1 && vpg == 1) {
+            // several tiles per workgroup, software-pipelined
+            PipeBlocks pbk;
+            pbk.tpw = cp.group_tiles;
+            pbk.bo[0] = 0;
+            for (int c = 0; c < kGroupClasses; ++c) {
+                const int64_t tiles = gb.bo[c + 1] - gb.bo[c];
+                pbk.bo[c + 1] = pbk.bo[c] + (tiles + pbk.tpw - 1) / pbk.tpw;
+            }
+            for (int c = 0; c <= kGroupClasses; ++c) pbk.cstart[c] = cp.cstart[c];
+            const std::string name = "k_cpt_groups_pipe<" + std::to_string(spl) + ",";
+            TimedLaunch tl(t, TG_SWEEP, name.c_str(), gbytes, sfx.c_str());
+            const unsigned nb = (unsigned)pbk.bo[kGroupClasses];
+            if (spl == 8)
+                tl.launch(k_cpt_groups_pipe<8, W>, nb, 256, 0, s, a, cp.glist, cp.ginfo, pbk);
+            else if (spl == 2)
+                tl.launch(k_cpt_groups_pipe<2, W>, nb, 256, 0, s, a, cp.glist, cp.ginfo, pbk);
+            else
+                tl.launch(k_cpt_groups_pipe<4, W>, nb, 256, 0, s, a, cp.glist, cp.ginfo, pbk);
+            LV_LAUNCHED("k_cpt_groups_pipe");
+        } else if (gb.bo[kGroupClasses] > 0) {
             const std::string name = "k_cpt_groups<" + std::to_string(spl) + "," + std::to_string(vpg) + ",";
             TimedLaunch tl(t, TG_SWEEP, name.c_str(), gbytes, sfx.c_str());
             const unsigned nb = (unsigned)gb.bo[kGroupClasses];

@@ -184,6 +184,12 @@ def test_run_full_chunglu1m(ctx):
     g = gg.config("chunglu1m")
     r = check_run(ctx, g, tag="chunglu1m")
     _say(f"chunglu1m: levels {len(r.stats['levels'])}, Q = {r.q:.6f}")
+    # the packed classes software-pipelined over four tiles per workgroup
+    ctx.set_tuning(group_tiles=4)
+    try:
+        check_run(ctx, g, tag="chunglu1m, group_tiles 4")
+    finally:
+        ctx.set_tuning()
 
 
 def test_determinism_and_batching(ctx):
@@ -339,11 +345,12 @@ def test_launch_shapes_do_not_change_results(ctx):
     refs = [oracle.louvain(g.row_ptr, g.col, g.w) for g in graphs]
     Gs = [ctx.graph_create(g.row_ptr, g.col, g.w) for g in graphs]
     try:
-        for shp in [(1, 341, 1, 4, 1, 0, 1), (4, 1024, 2, 8, 2, 1, 2), (8, 1365, 1, 2, 2, 0, 0),
-                    (2, 2730, 3, 4, 1, 1, 1), (4, 10922, 2, 8, 1, 0, 2), (3, 700, 1, 2, 1, 1, 1),
-                    (4, 5000, 2, 4, 2, 1, 0), (4, 10922, 2, 4, 1, 1, 1)]:
+        for shp in [(1, 341, 1, 4, 1, 0, 1, 1), (4, 1024, 2, 8, 2, 1, 2, 1), (8, 1365, 1, 2, 2, 0, 0, 1),
+                    (2, 2730, 3, 4, 1, 1, 1, 4), (4, 10922, 2, 8, 1, 0, 2, 3), (3, 700, 1, 2, 1, 1, 1, 2),
+                    (4, 5000, 2, 4, 2, 1, 0, 1), (4, 10922, 2, 4, 1, 1, 1, 8), (4, 2730, 2, 4, 1, 0, 2, 4)]:
             ctx.set_tuning(*shp)
-            keys = ("small_max", "block_max", "pass_batch", "group_slots", "group_vertices", "overlap", "reorder")
+            keys = ("small_max", "block_max", "pass_batch", "group_slots", "group_vertices", "overlap", "reorder",
+                    "group_tiles")
             assert ctx.get_tuning() == dict(zip(keys, shp))
             for k, (G, ref) in enumerate(zip(Gs, refs)):
                 r = ctx.run(G)
@@ -366,8 +373,9 @@ def test_autotune(ctx, L):
         assert best["small_max"] in (4, 8) and best["block_max"] in (1365, 2730, 10922)
         assert best["pass_batch"] in (1, 2) and best["group_slots"] == 4 and best["ms"] > 0
         assert best["group_vertices"] in (1, 2) and best["overlap"] == 0 and best["reorder"] == 0
+        assert best["group_tiles"] in (1, 4)
         assert ctx.get_tuning() == {k: best[k] for k in ("small_max", "block_max", "pass_batch", "group_slots",
-                                                         "group_vertices", "overlap", "reorder")}
+                                                         "group_vertices", "overlap", "reorder", "group_tiles")}
         r = ctx.run(G)
         ref = oracle.louvain(g.row_ptr, g.col, g.w)
         assert np.array_equal(r.labels, ref.labels) and r.q_int == ref.q_int
@@ -383,6 +391,8 @@ def test_autotune(ctx, L):
             ctx.set_tuning(overlap=2)
         with pytest.raises(L.LouvainError):
             ctx.set_tuning(reorder=3)
+        with pytest.raises(L.LouvainError):
+            ctx.set_tuning(group_tiles=9)
     finally:
         ctx.set_tuning()
         G.destroy()
