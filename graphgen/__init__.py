@@ -398,6 +398,13 @@ def batch_sbm(count: int = 4096, seed: int = 1004, n_lo: int = 100, n_hi: int = 
     return out
 
 
+def batch_sbm_sizes(count: int = 4096, seed: int = 1004, n_lo: int = 100, n_hi: int = 100_000) -> np.ndarray:
+    """Vertex counts of ``batch_sbm``'s graphs 0..count-1 without building
+    them (the first draw of each graph's stream)."""
+    return np.array([int(round(_log_uniform(np.random.default_rng([seed, g]), n_lo, n_hi)))
+                     for g in range(count)], dtype=np.int64)
+
+
 def served_chunglu(count: int, seed: int = 1005, first: int = 0, n_lo: int = 1000,
                    n_hi: int = 2_000_000) -> list:
     """Requests of the served workload: Chung-Lu graphs with exponent uniform

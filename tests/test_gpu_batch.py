@@ -102,6 +102,27 @@ def test_batch_sbm_sample(ctx):
     check_batch(ctx, graphs, tag="batch_sbm", device=True)
 
 
+def test_batch_sbm_full_size_range():
+    """The batched workload's own graphs across its whole size range: its 8
+    largest (n near 100,000) and 24 more spread over the sizes, in one batch,
+    each against the oracle."""
+    import os
+    sizes = gg.batch_sbm_sizes()
+    order = np.argsort(sizes, kind="stable")
+    picks = list(order[-8:]) + list(order[np.linspace(0, len(order) - 9, 24).astype(int)])
+    graphs = [gg.batch_sbm(1, first=int(i))[0] for i in picks]
+    assert max(g.n for g in graphs) > 90_000
+    oracle.set_threads(min(16, os.cpu_count() or 1))
+    import paper_1805_10904_amd as L
+    c = L.Context(0)
+    try:
+        _say(f"batch of {len(graphs)} workload graphs, n {min(g.n for g in graphs)}..{max(g.n for g in graphs)}, "
+             f"{sum(g.nnz for g in graphs)} entries")
+        check_batch(c, graphs, tag="batch_sbm full range", device=True)
+    finally:
+        c.close()
+
+
 def test_batch_caps_and_params(ctx):
     graphs = [gg.config("sbm1k")] + mixed_graphs(12, 2)
     for kw in (dict(max_levels=1), dict(max_levels=2), dict(max_sweeps=1), dict(max_sweeps=0),

@@ -51,6 +51,9 @@ def test_batch_sbm_size_mix_is_log_uniform():
     g = gg.batch_sbm(1, first=3)[0]
     rng = np.random.default_rng([1004, 3])
     assert g.n == int(round(math.exp(rng.uniform(math.log(100), math.log(100_000)))))
+    sizes = gg.batch_sbm_sizes(40)
+    assert sizes[3] == g.n
+    assert [x.n for x in gg.batch_sbm(6, n_hi=100_000, first=30)] == sizes[30:36].tolist()
 
 
 def test_served_chunglu_small_requests():
