@@ -82,6 +82,29 @@ __device__ __forceinline__ int lds_insert(int32_t *key, unsigned long long *val,
     }
 }
 
+// Tables keyed by the neighbour's whole published word (label, deg_C and
+// singleton flag, all functions of the label within a pass), so scoring
+// reads deg_C from the key instead of gathering it.  No inserted word is
+// all ones: that would be a singleton community holding all of 2W (deg_C
+// needs every bit above the label, and the publish condition keeps 2W below
+// that), whose only vertex is then nobody's neighbour but its own.
+constexpr unsigned long long kEmptyWord = ~0ull;
+
+template <int BITS>
+__device__ __forceinline__ void lds_insert_word(unsigned long long *key, unsigned long long *val, uint64_t word,
+                                                int32_t k, int64_t w) {
+    constexpr uint32_t kMask = (1u << BITS) - 1;
+    uint32_t h = hash_pow2(k, BITS);
+    while (true) {
+        const unsigned long long prev = atomicCAS(&key[h], kEmptyWord, (unsigned long long)word);
+        if (prev == kEmptyWord || prev == word) {
+            atomicAdd(&val[h], (unsigned long long)w);
+            return;
+        }
+        h = (h + 1) & kMask;
+    }
+}
+
 // Same in an HBM table of `size` slots.
 __device__ __forceinline__ void hbm_insert(int32_t *key, unsigned long long *val, int64_t size, int32_t k,
                                            unsigned long long w) {
@@ -205,30 +228,33 @@ __device__ __forceinline__ void group_reduce_block(S &bs, int32_t &bl, int64_t &
 
 // G lanes per vertex (G in {4, 16, 64}: several vertices per wavefront; G =
 // 256: one workgroup per vertex).  Each group owns an LDS table of 2^BITS
-// slots, at least twice the largest row of its bucket.
-template <int G, int BITS, typename W, typename S>
+// slots, at least twice the largest row of its bucket.  KW (levels with
+// published words): slots are keyed by the neighbour's published word.
+template <int G, int BITS, typename W, typename S, bool KW = false>
 __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a, const int32_t *__restrict__ list,
                                                      int64_t count) {
     constexpr int T = 1 << BITS;
     constexpr int NG = 256 / G;
-    __shared__ int32_t s_key[NG * T];
+    using K = typename std::conditional<KW, unsigned long long, int32_t>::type;
+    constexpr K kNone = KW ? (K)kEmptyWord : (K)kEmpty;
+    __shared__ K s_key[NG * T];
     __shared__ unsigned long long s_val[NG * T];
     // candidates' deg_C beside their e in LDS (with published words), for
-    // the small tables only: the larger ones would lose occupancy to it and
-    // gather deg_C when they score
-    constexpr bool DEG_LDS = NG * T <= 1024;
+    // the small tables only: the larger ones key their slots by the whole
+    // published word instead (8 bytes per slot more, not 12)
+    constexpr bool DEG_LDS = !KW && NG * T <= 1024;
     __shared__ int64_t s_deg[DEG_LDS ? NG * T : 1];
     __shared__ unsigned long long s_I;
     if (a.st->done) return;
     const int tid = threadIdx.x;
     const int g = tid / G, lane = tid % G;
-    int32_t *key = s_key + g * T;
+    K *key = s_key + g * T;
     unsigned long long *val = s_val + g * T;
     int64_t *tdeg = s_deg + (DEG_LDS ? g * T : 0);
     if (!a.first) {   // the first pass from singletons uses no table
 #pragma unroll
         for (int x = lane; x < T; x += G) {
-            key[x] = kEmpty;
+            key[x] = kNone;
             val[x] = 0;
         }
     }
@@ -254,6 +280,7 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a, const int32_t 
     for (int64_t e0 = rs + lane; e0 < re; e0 += (int64_t)U * G) {
         int32_t jq[U], lq[U];
         int64_t wq[U], dq[U];
+        uint64_t uq[U];
 #pragma unroll
         for (int q = 0; q < U; ++q) {
             const int64_t e = e0 + (int64_t)q * G;
@@ -268,7 +295,16 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a, const int32_t 
         for (int q = 0; q < U; ++q) {
             lq[q] = -1;
             dq[q] = -1;
-            if (jq[q] >= 0 && jq[q] != i) lq[q] = nb_label(a, jq[q], &dq[q]);
+            uq[q] = 0;
+            if (jq[q] >= 0 && jq[q] != i) {
+                if constexpr (KW) {
+                    uq[q] = a.pw[jq[q]];
+                    lq[q] = pw_label(uq[q], a.pw_bits);
+                    dq[q] = pw_deg(uq[q], a.pw_bits);
+                } else {
+                    lq[q] = nb_label(a, jq[q], &dq[q]);
+                }
+            }
         }
 #pragma unroll
         for (int q = 0; q < U; ++q) {
@@ -281,8 +317,10 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a, const int32_t 
                     bs = sc;
                     bl = lq[q];
                 }
+            } else if constexpr (KW) {
+                lds_insert_word<BITS>(key, val, uq[q], lq[q], wq[q]);
             } else {
-                const int h = lds_insert<BITS>(key, val, lq[q], wq[q]);
+                const int h = lds_insert<BITS>((int32_t *)key, val, lq[q], wq[q]);
                 if (DEG_LDS && a.pw) tdeg[h] = dq[q];   // every inserter of a label writes the same degree
             }
         }
@@ -292,14 +330,16 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a, const int32_t 
     if (active && !a.first) {
 #pragma unroll
         for (int x = lane; x < T; x += G) {
-            const int32_t k = key[x];
-            if (k == kEmpty) continue;
+            const K kx = key[x];
+            if (kx == kNone) continue;
+            const int32_t k = KW ? pw_label((uint64_t)kx, a.pw_bits) : (int32_t)kx;
             const int64_t ev = (int64_t)val[x];
             if (k == ci) {
                 e_own = ev;
                 continue;
             }
-            const S sc = score_mul<S>(a.tw, ev) - score_mul<S>(di, DEG_LDS && a.pw ? tdeg[x] : a.deg[k]);
+            const int64_t dk = KW ? pw_deg((uint64_t)kx, a.pw_bits) : DEG_LDS && a.pw ? tdeg[x] : a.deg[k];
+            const S sc = score_mul<S>(a.tw, ev) - score_mul<S>(di, dk);
             if (better<S>(sc, k, bs, bl)) {
                 bs = sc;
                 bl = k;
@@ -1149,7 +1189,8 @@ void Sweeper::reserve(int64_t n, int64_t nnz) {
     ds_.alloc((size_t)n);
     vw_.alloc((size_t)n);
     es_.alloc((size_t)n);
-    active_.alloc(2);
+    active_.alloc(3);   // graphs still in their phase (by pass parity), commit arrivals
+    fill<int32_t>((int32_t *)active_.p, 0, 3, s_);
     tw_one_.alloc(1);
     list_.alloc((size_t)n);
     const int64_t nblk = (n + kBucketTile - 1) / kBucketTile;
@@ -1508,9 +1549,15 @@ static void launch_pass(const SweepArgs &a, const int32_t *list, const int64_t *
         group(k_sweep_group<16, 6, W, S>, 2, 16, "k_sweep_group<16,6,");
         group(k_sweep_group<32, 7, W, S>, 3, 8, "k_sweep_group<32,7,");
         group(k_sweep_group<64, 8, W, S>, 4, 4, "k_sweep_group<64,8,");
-        group(k_sweep_group<64, 9, W, S>, 5, 4, "k_sweep_group<64,9,");
-        group(k_sweep_group<256, 11, W, S>, 6, 1, "k_sweep_group<256,11,");
-        group(k_sweep_group<256, 12, W, S>, 7, 1, "k_sweep_group<256,12,");
+        if (a.pw) {   // tables keyed by published words: no deg_C gathers when scoring
+            group(k_sweep_group<64, 9, W, S, true>, 5, 4, "k_sweep_group<64,9,");
+            group(k_sweep_group<256, 11, W, S, true>, 6, 1, "k_sweep_group<256,11,");
+            group(k_sweep_group<256, 12, W, S, true>, 7, 1, "k_sweep_group<256,12,");
+        } else {
+            group(k_sweep_group<64, 9, W, S>, 5, 4, "k_sweep_group<64,9,");
+            group(k_sweep_group<256, 11, W, S>, 6, 1, "k_sweep_group<256,11,");
+            group(k_sweep_group<256, 12, W, S>, 7, 1, "k_sweep_group<256,12,");
+        }
         const int c8 = kLdsClasses - 1;
         if (ccount(c8) > 0) {   // rows up to kBucketMax[B_WIDE]: only when a.hub_shift > 0
             TimedLaunch tl(t, TG_SWEEP, "k_sweep_wide<", cbytes(c8), sfx.c_str());
