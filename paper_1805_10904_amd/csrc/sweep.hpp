@@ -127,7 +127,8 @@ struct CompactState {
     const int32_t *gid = nullptr;  // graph of every vertex (nullptr: one graph)
     const int64_t *tw = nullptr;   // TW of every graph
     PhaseState *st = nullptr;      // phase state of every graph
-    unsigned int *active = nullptr;// two counters of graphs still in their phase (pass parity)
+    unsigned int *active = nullptr;// two counters of graphs still in their phase (pass parity), then
+                                   // the commit's workgroup arrivals (0 between launches)
     int64_t ngraphs = 1;
     SideStreams *side = nullptr;   // optional: streams for the one-workgroup rows and the hubs
 };

@@ -215,6 +215,80 @@ __global__ __launch_bounds__(256) void k_cpt_publish(const uint64_t *__restrict_
     span_flush(sp, acc, st, -1, 2);
 }
 
+// ------------------------------------------------------------- acceptance --
+
+__device__ __forceinline__ void cpt_mul_u128_u64(u128 a, uint64_t b, uint64_t &hi, u128 &lo) {
+    const u128 p0 = (u128)(uint64_t)a * b;
+    const u128 p1 = (u128)(uint64_t)(a >> 64) * b;
+    const u128 l = p0 + (p1 << 64);
+    hi = (uint64_t)(p1 >> 64) + (l < p0 ? 1 : 0);
+    lo = l;
+}
+
+// theta_den * (qn - qp) > theta_num * |qp|, exactly.
+__device__ __forceinline__ bool cpt_gain_passes(i128 qn, i128 qp, int64_t num, int64_t den) {
+    if (qn <= qp) return false;
+    const u128 gain = (u128)(qn - qp);
+    const u128 mag = (u128)(qp < 0 ? -qp : qp);
+    uint64_t lh, rh;
+    u128 ll, rl;
+    cpt_mul_u128_u64(gain, (uint64_t)den, lh, ll);
+    cpt_mul_u128_u64(mag, (uint64_t)num, rh, rl);
+    return lh > rh || (lh == rh && ll > rl);
+}
+
+// Graph g: Q_int of the labelling the pass read (slot p-1) and the
+// acceptance test of sweep p-1 against the last kept labelling.  acc_I and
+// moved are read with agent-scope atomic loads: the commit's workgroups on
+// other XCDs added to them in the same launch.
+__device__ __forceinline__ void cpt_finalize_graph(PhaseState *st, const int64_t *__restrict__ tw, int64_t g,
+                                                   int64_t theta_num, int64_t theta_den, int32_t max_sweeps,
+                                                   int32_t p, unsigned int *active) {
+    PhaseState &s = st[g];
+    if (s.done) return;
+    const unsigned long long acc_i = __hip_atomic_load(&s.acc_I, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long moved = __hip_atomic_load(&s.moved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const i128 q = (i128)tw[g] * (i128)acc_i - (i128)s.s_acc;
+    s.pass = p;
+    s.q_last[0] = (uint64_t)q;
+    s.q_last[1] = (uint64_t)(int64_t)(q >> 64);
+    const i128 qref = make_i128(s.q_ref[0], (int64_t)s.q_ref[1]);
+    bool keep = true;
+    if (p == 1) {
+        s.q_ref[0] = (uint64_t)q;
+        s.q_ref[1] = (uint64_t)(int64_t)(q >> 64);
+    } else if (cpt_gain_passes(q, qref, theta_num, theta_den)) {
+        s.q_ref[0] = (uint64_t)q;
+        s.q_ref[1] = (uint64_t)(int64_t)(q >> 64);
+        s.accepted += 1;
+    } else {
+        keep = false;
+        s.done = 1;
+        s.final_slot = (p - 2) % 3;
+    }
+    if (keep) {
+        if (s.accepted >= max_sweeps) {
+            s.done = 1;
+            s.limit = 1;
+            s.final_slot = (p - 1) % 3;
+        } else if (moved == 0) {
+            s.done = 1;   // the next sweep cannot change Q, so it would be discarded
+            s.final_slot = (p - 1) % 3;
+        }
+    }
+    s.acc_I = 0;
+    s.moved = 0;
+    s.s_acc = 0;
+    if (!s.done) atomicAdd(active, 1u);
+}
+
+// One thread per graph (passes over levels without vertices).
+__global__ void k_cpt_finalize(PhaseState *st, const int64_t *__restrict__ tw, int64_t ngraphs, int64_t theta_num,
+                               int64_t theta_den, int32_t max_sweeps, int32_t p, unsigned int *active) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < ngraphs) cpt_finalize_graph(st, tw, g, theta_num, theta_den, max_sweeps, p, active);
+}
+
 // ------------------------------------------------------------------ commit --
 
 constexpr int kCommitTile = 2048;
@@ -245,10 +319,20 @@ __device__ __forceinline__ bool commit_insert(int32_t *key, unsigned long long *
 // one per tile.  Updates that find no LDS slot (tiles where most vertices
 // move between distinct communities) go to HBM directly.  The sums are
 // integers modulo 2^64, so the result does not depend on the order.
+// The last workgroup to finish (counted on `arrive`, which it leaves at 0)
+// then runs the pass's acceptance test for every graph: no launch of its
+// own.  A launch over a finished single graph returns in every workgroup.
+struct FinalizeArgs {
+    const int64_t *tw;
+    int64_t ngraphs, theta_num, theta_den;
+    int32_t max_sweeps, p;
+    unsigned int *active, *arrive;
+};
+
 __global__ __launch_bounds__(256) void k_cpt_commit(const int32_t *__restrict__ c_cur, const int32_t *__restrict__ c_nxt,
                                                     const int64_t *__restrict__ delta, const uint32_t *__restrict__ es,
                                                     uint64_t *ds, const int32_t *__restrict__ gid, PhaseState *st,
-                                                    int64_t n) {
+                                                    int64_t n, FinalizeArgs fa) {
     if (single_done(gid, st)) return;
     constexpr int T = 1 << kCommitBits;
     __shared__ unsigned long long acc[kSpan][2];
@@ -295,76 +379,24 @@ __global__ __launch_bounds__(256) void k_cpt_commit(const int32_t *__restrict__ 
         span_add(sp, acc, 0, gcur, sum_e, st, 0);
         span_add(sp, acc, 1, gcur, sum_m, st, 1);
     }
+    // the pass's sums go out first (after a barrier: the table is complete
+    // too), so a workgroup's arrival waits for them and not for the degree
+    // updates, which only the next pass reads
+    span_flush(sp, acc, st, 0, 1);
+    __shared__ int s_last;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) s_last = atomicAdd(fa.arrive, 1u) == gridDim.x - 1;
     __syncthreads();
     for (int x = threadIdx.x; x < T; x += 256) {
         const int32_t key = s_key[x];
         if (key != kEmpty && s_val[x] != 0) atomicAdd((unsigned long long *)&ds[key], s_val[x]);
     }
-    span_flush(sp, acc, st, 0, 1);
-}
-
-// ------------------------------------------------------------- acceptance --
-
-__device__ __forceinline__ void cpt_mul_u128_u64(u128 a, uint64_t b, uint64_t &hi, u128 &lo) {
-    const u128 p0 = (u128)(uint64_t)a * b;
-    const u128 p1 = (u128)(uint64_t)(a >> 64) * b;
-    const u128 l = p0 + (p1 << 64);
-    hi = (uint64_t)(p1 >> 64) + (l < p0 ? 1 : 0);
-    lo = l;
-}
-
-// theta_den * (qn - qp) > theta_num * |qp|, exactly.
-__device__ __forceinline__ bool cpt_gain_passes(i128 qn, i128 qp, int64_t num, int64_t den) {
-    if (qn <= qp) return false;
-    const u128 gain = (u128)(qn - qp);
-    const u128 mag = (u128)(qp < 0 ? -qp : qp);
-    uint64_t lh, rh;
-    u128 ll, rl;
-    cpt_mul_u128_u64(gain, (uint64_t)den, lh, ll);
-    cpt_mul_u128_u64(mag, (uint64_t)num, rh, rl);
-    return lh > rh || (lh == rh && ll > rl);
-}
-
-// One thread per graph: Q_int of the labelling the pass read (slot p-1) and
-// the acceptance test of sweep p-1 against the last kept labelling.
-__global__ void k_cpt_finalize(PhaseState *st, const int64_t *__restrict__ tw, int64_t ngraphs, int64_t theta_num,
-                               int64_t theta_den, int32_t max_sweeps, int32_t p, unsigned int *active) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ngraphs) return;
-    PhaseState &s = st[g];
-    if (s.done) return;
-    const i128 q = (i128)tw[g] * (i128)s.acc_I - (i128)s.s_acc;
-    s.pass = p;
-    s.q_last[0] = (uint64_t)q;
-    s.q_last[1] = (uint64_t)(int64_t)(q >> 64);
-    const i128 qref = make_i128(s.q_ref[0], (int64_t)s.q_ref[1]);
-    bool keep = true;
-    if (p == 1) {
-        s.q_ref[0] = (uint64_t)q;
-        s.q_ref[1] = (uint64_t)(int64_t)(q >> 64);
-    } else if (cpt_gain_passes(q, qref, theta_num, theta_den)) {
-        s.q_ref[0] = (uint64_t)q;
-        s.q_ref[1] = (uint64_t)(int64_t)(q >> 64);
-        s.accepted += 1;
-    } else {
-        keep = false;
-        s.done = 1;
-        s.final_slot = (p - 2) % 3;
-    }
-    if (keep) {
-        if (s.accepted >= max_sweeps) {
-            s.done = 1;
-            s.limit = 1;
-            s.final_slot = (p - 1) % 3;
-        } else if (s.moved == 0) {
-            s.done = 1;   // the next sweep cannot change Q, so it would be discarded
-            s.final_slot = (p - 1) % 3;
-        }
-    }
-    s.acc_I = 0;
-    s.moved = 0;
-    s.s_acc = 0;
-    if (!s.done) atomicAdd(active, 1u);
+    if (!s_last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    for (int64_t g = threadIdx.x; g < fa.ngraphs; g += 256)
+        cpt_finalize_graph(st, fa.tw, g, fa.theta_num, fa.theta_den, fa.max_sweeps, fa.p, fa.active);
+    if (threadIdx.x == 0) atomicExch(fa.arrive, 0u);
 }
 
 // ---------------------------------------------- rows of <= small_max entries --
@@ -1799,12 +1831,14 @@ void compact_pass(const GraphView &g, const CompactPass &cp, const CompactState 
     else
         compact_sweeps<int64_t>(a, cp, s, side, t);
     if (g.n > 0) {
+        // the acceptance test runs in the last workgroup to finish
+        const FinalizeArgs fa{cs.tw, cs.ngraphs, prm.theta_num, prm.theta_den, prm.max_sweeps, p,
+                              cs.active + (p & 1), cs.active + 2};
         TimedLaunch tl(t, TG_SWEEP, "k_cpt_commit", (double)g.n * 12);
         tl.launch(k_cpt_commit, grid_for(g.n, kCommitTile), 256, 0, s, cs.c_cur, cs.c_nxt, g.delta, cs.es, cs.ds,
-                  cs.gid, cs.st, g.n);
+                  cs.gid, cs.st, g.n, fa);
         LV_LAUNCHED("k_cpt_commit");
-    }
-    {
+    } else {
         TimedLaunch tl(t, TG_SWEEP, "k_cpt_finalize", 0.0);
         tl.launch(k_cpt_finalize, grid_for(cs.ngraphs, 256), 256, 0, s, cs.st, cs.tw, cs.ngraphs, prm.theta_num,
                   prm.theta_den, prm.max_sweeps, p, cs.active + (p & 1));
