@@ -319,9 +319,9 @@ static int bits_for(int64_t k) {
 constexpr int kSegTile = 512;     // vertices per workgroup in the grouping kernels
 constexpr int kSegBits = 11;      // their LDS tables: 2^11 slots for at most 512 keys
 constexpr int kChunk = 1024;      // grouped entries per aggregation workgroup (nominal)
-constexpr int kChunkSnap = 256;   // a chunk starts at the first segment start within this many entries
-constexpr int kChunkMax = kChunk + kChunkSnap;
-constexpr int kChunkBits = 11;    // its LDS hash table: 2^11 slots (load <= 0.625)
+constexpr int kChunkSeg = 512;    // segments of at most this many entries never cross a chunk boundary
+constexpr int kChunkLen = kChunk + kChunkSeg;   // longest chunk
+constexpr int kChunkBits = 11;    // its LDS hash table: 2^11 slots (load < 0.75)
 constexpr unsigned long long kNoKey = ~0ull;
 
 __device__ __forceinline__ int lds_slot(int32_t *key, int32_t k) {
@@ -433,10 +433,10 @@ __global__ __launch_bounds__(256) void k_seg_scatter(const int64_t *__restrict__
     }
 }
 
-// Inclusive max-scan of s[0, kChunkMax) in place (256 threads, R items each).
+// Inclusive max-scan of s[0, kChunkLen) in place (256 threads, R items each).
 __device__ __forceinline__ void block_max_scan_chunk(int32_t *s, int32_t *s_wave) {
-    constexpr int R = kChunkMax / 256;
-    static_assert(kChunkMax % 256 == 0, "scan tiling");
+    constexpr int R = kChunkLen / 256;
+    static_assert(kChunkLen % 256 == 0, "scan tiling");
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     int32_t v[R];
 #pragma unroll
@@ -459,17 +459,20 @@ __device__ __forceinline__ void block_max_scan_chunk(int32_t *s, int32_t *s_wave
     __syncthreads();
 }
 
-// Start of chunk b: b * kChunk moved forward to the first segment start
-// within kChunkSnap entries, if there is one, so that segments shorter than
-// kChunkSnap rarely cross a chunk boundary.  Called by one full wavefront.
+// Start of chunk b: b * kChunk moved back to the start of the segment
+// holding it when that segment has at most kChunkSeg entries, so such a
+// segment never crosses a chunk boundary and its pairs are always final in
+// its chunk (longer segments are aggregated by the middle tier and the
+// pieces, or, in the exported contraction, merged).  Starts increase with b
+// and a chunk has fewer than kChunkLen entries.  Called by one full
+// wavefront.
 __device__ __forceinline__ int64_t chunk_start(const int64_t *__restrict__ off, int64_t k, int64_t m_raw, int64_t b) {
     const int64_t x = b * kChunk;
     if (x <= 0) return 0;
     if (x >= m_raw) return m_raw;
     const int64_t s = wave_find_le(off, k, x);   // segment holding entry x
-    if (off[s] == x) return x;
-    const int64_t nxt = off[s + 1];              // the next segment start (off[k] = m_raw)
-    return nxt - x <= kChunkSnap ? nxt : x;
+    const int64_t st = off[s];
+    return off[s + 1] - st <= kChunkSeg ? st : x;
 }
 
 // Shared first half of the chunk kernels: the chunk's first and last
@@ -486,7 +489,7 @@ __device__ __forceinline__ void chunk_aggregate(const int64_t *__restrict__ off,
         s_hk[x] = kNoKey;
         s_hv[x] = 0;
     }
-    for (int x = t; x < kChunkMax; x += 256) s_mark[x] = -1;
+    for (int x = t; x < kChunkLen; x += 256) s_mark[x] = -1;
     if (t < 64) {   // segments of the chunk's first and last entry (64-way search)
         const int64_t a0 = wave_find_le(off, k, cb);
         const int64_t a1 = wave_find_le(off, k, cb + len - 1);
@@ -497,7 +500,7 @@ __device__ __forceinline__ void chunk_aggregate(const int64_t *__restrict__ off,
     }
     __syncthreads();
     const int64_t slo = s_range[0], shi = s_range[1];
-    if (shi - slo <= kChunkMax) {
+    if (shi - slo <= kChunkLen) {
         // segment of every entry: markers at segment starts, then a max-scan
         for (int64_t sg = slo + 1 + t; sg <= shi; sg += 256) atomicMax(&s_mark[off[sg] - cb], (int32_t)(sg - slo));
         if (t == 0) s_mark[0] = 0;   // markers never land on position 0
@@ -516,14 +519,12 @@ __device__ __forceinline__ void chunk_aggregate(const int64_t *__restrict__ off,
         }
         __syncthreads();
     }
-    // with skip_big, entries of segments longer than kChunkMax (only the
-    // chunk's first and last segment can be) are left to k_big_piece
-    const int32_t last_local = (int32_t)(shi - slo);
-    const bool first_big = skip_big && off[slo + 1] - off[slo] > kChunkMax;
-    const bool last_big = skip_big && off[shi + 1] - off[shi] > kChunkMax;
+    // with skip_big, entries of segments longer than kChunkSeg are left to
+    // the middle tier and the pieces (such a segment can lie anywhere in a
+    // chunk, not only first or last)
     for (int x = t; x < len; x += 256) {
         const int32_t ls = s_mark[x];
-        if ((ls == 0 && first_big) || (ls == last_local && last_big)) continue;
+        if (skip_big && off[slo + ls + 1] - off[slo + ls] > kChunkSeg) continue;
         const unsigned long long key = ((unsigned long long)(uint32_t)ls << 32) | (uint32_t)tcol[cb + x];
         const long long val = (long long)tw[cb + x];
         uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - kChunkBits));
@@ -547,9 +548,9 @@ __global__ __launch_bounds__(256) void k_seg_chunk_any(const int64_t *__restrict
     constexpr int T = 1 << kChunkBits;
     __shared__ unsigned long long s_hk[T];
     __shared__ long long s_hv[T];
-    __shared__ int32_t s_mark[kChunkMax];
-    __shared__ int32_t s_cnt[kChunkMax];   // pairs per segment, at the segment's first position
-    __shared__ int32_t s_cur[kChunkMax];
+    __shared__ int32_t s_mark[kChunkLen];
+    __shared__ int32_t s_cnt[kChunkLen];   // pairs per segment, at the segment's first position
+    __shared__ int32_t s_cur[kChunkLen];
     __shared__ int32_t s_wave[4];
     __shared__ int64_t s_range[2];
     __shared__ int64_t s_bounds[2];
@@ -563,7 +564,7 @@ __global__ __launch_bounds__(256) void k_seg_chunk_any(const int64_t *__restrict
             s_bounds[1] = b1;
         }
     }
-    for (int x = t; x < kChunkMax; x += 256) {
+    for (int x = t; x < kChunkLen; x += 256) {
         s_cnt[x] = 0;
         s_cur[x] = 0;
     }
@@ -628,7 +629,7 @@ __global__ __launch_bounds__(256) void k_seg_chunk_any(const int64_t *__restrict
     }
 }
 
-// Segments longer than kChunkMax entries (the communities with the most
+// Segments longer than kMidMax entries (the communities with the most
 // member entries) are cut into pieces of kPiece entries, one 1,024-thread
 // workgroup each with a 2^13-slot LDS table keyed by column.  A segment of
 // one piece whose columns all found a slot and that has at most direct_max
@@ -642,7 +643,7 @@ constexpr int kPiece = 16384;
 constexpr int kPieceBits = 13;
 constexpr int kPieceProbe = 32;
 constexpr int kPieceThreads = 1024;
-// Segments of kChunkMax + 1 .. kMidMax entries take one 256-thread
+// Segments of kChunkSeg + 1 .. kMidMax entries take one 256-thread
 // workgroup each with a 2^12-slot table (a quarter of the long pieces' LDS,
 // so three workgroups share a CU instead of one): their distinct columns
 // always fit the table's claimable 3/4.
@@ -651,17 +652,37 @@ constexpr int kMidBits = 12;
 constexpr int kMidThreads = 256;
 
 // Pieces of every segment longer than kMidMax (0 otherwise), and a flag for
-// every segment of kChunkMax + 1 .. kMidMax entries; tot[0] / tot[1]
+// every segment of kChunkSeg + 1 .. kMidMax entries; tot[0] / tot[1]
 // receive their entry counts.
 __global__ __launch_bounds__(256) void k_big_pieces(const int64_t *__restrict__ off, int64_t k, int64_t *pieces,
                                                     int64_t *mids, unsigned long long *tot, int64_t piece) {
-    const int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (a >= k) return;
-    const int64_t sz = off[a + 1] - off[a];
-    pieces[a] = sz > kMidMax ? (sz + piece - 1) / piece : 0;
-    mids[a] = sz > kChunkMax && sz <= kMidMax ? 1 : 0;
-    if (sz > kMidMax) atomicAdd(&tot[0], (unsigned long long)sz);
-    else if (sz > kChunkMax) atomicAdd(&tot[1], (unsigned long long)sz);
+    __shared__ unsigned long long s_tot[4][2];
+    unsigned long long big = 0, mid = 0;
+    for (int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x; a < k; a += (int64_t)gridDim.x * 256) {
+        const int64_t sz = off[a + 1] - off[a];
+        pieces[a] = sz > kMidMax ? (sz + piece - 1) / piece : 0;
+        mids[a] = sz > kChunkSeg && sz <= kMidMax ? 1 : 0;
+        if (sz > kMidMax) big += (unsigned long long)sz;
+        else if (sz > kChunkSeg) mid += (unsigned long long)sz;
+    }
+    // one atomic per workgroup and total (the grid is at most a few
+    // thousand workgroups)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        big += __shfl_xor(big, o);
+        mid += __shfl_xor(mid, o);
+    }
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        s_tot[wid][0] = big;
+        s_tot[wid][1] = mid;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        const unsigned long long x = s_tot[0][threadIdx.x] + s_tot[1][threadIdx.x] + s_tot[2][threadIdx.x] +
+                                     s_tot[3][threadIdx.x];
+        if (x) atomicAdd(&tot[threadIdx.x], x);
+    }
 }
 
 // One workgroup per piece of PIECE entries (THREADS threads, a table of
@@ -916,7 +937,8 @@ __global__ __launch_bounds__(256) void k_seg_chunk(const int64_t *__restrict__ o
     __shared__ long long s_hv[T];
     __shared__ unsigned long long s_sk[2 * kChunk];   // sorted pairs (padded to a power of two)
     __shared__ long long s_sv[2 * kChunk];
-    __shared__ int32_t s_mark[kChunkMax];
+    __shared__ int32_t s_mark[kChunkLen];
+    static_assert(kChunkLen <= 2 * kChunk, "a chunk's distinct pairs fit the sort buffer");
     __shared__ int32_t s_wave[4];
     __shared__ int s_nd;
     __shared__ int64_t s_range[2];
@@ -1160,7 +1182,7 @@ int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t 
         LV_LAUNCHED("k_seg_start");
     }
     // unsorted contraction: pieces of the segments longer than kMidMax, and
-    // the segments of kChunkMax + 1 .. kMidMax entries
+    // the segments of kChunkSeg + 1 .. kMidMax entries
     TempBuf pieces(sorted ? 16 : (size_t)(2 * (k + 1) + 2) * sizeof(int64_t), s_);
     int64_t *poff = pieces.as<int64_t>();
     int64_t *moff = poff + (k + 1);
@@ -1172,7 +1194,8 @@ int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t 
     if (!sorted) {
         fill<uint64_t>((uint64_t *)ptot, 0, 2, s_);
         TimedLaunch tl(t_, TG_CONTRACT, "k_big_pieces", (double)k * 32);
-        tl.launch(k_big_pieces, grid_for(k, 256), 256, 0, s_, off, k, poff, moff, ptot, piece);
+        const unsigned pb = grid_for(k, 256) < 2048u ? grid_for(k, 256) : 2048u;
+        tl.launch(k_big_pieces, pb, 256, 0, s_, off, k, poff, moff, ptot, piece);
         LV_LAUNCHED("k_big_pieces");
         scan_exclusive<int64_t, int64_t>(poff, poff, k, poff + k, s_, t_);
         scan_exclusive<int64_t, int64_t>(moff, moff, k, moff + k, s_, t_);
@@ -1217,6 +1240,10 @@ int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t 
                       val_[0].p, pc.as<unsigned long long>(), bits);
         LV_LAUNCHED("k_seg_chunk");
     }
+    const bool log = log_on();
+    TempBuf pc_chunks(log ? sizeof(unsigned long long) : 8, s_);
+    if (log)   // the pairs the chunks left to the sort
+        LV_HIP(hipMemcpyAsync(pc_chunks.p, pc.p, sizeof(unsigned long long), hipMemcpyDeviceToDevice, s_));
     if (npc && *npc > 0) {
         // per entry: column and weight read, one pair (column, weight) written at most
         TimedLaunch tl(t_, TG_CONTRACT, "k_big_piece", (double)ntot[0] * 24);
@@ -1243,8 +1270,16 @@ int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t 
         LV_LAUNCHED("k_mid_seg");
     }
     const uint64_t *npp = rb.add(pc.as<uint64_t>());
+    const uint64_t *npc0 = log ? rb.add(pc_chunks.as<uint64_t>()) : nullptr;
     rb.fetch();
     const uint64_t np = *npp;
+    if (log)
+        fprintf(stderr,
+                "[louvain] contraction: n %lld -> %lld, entries %lld, pieces %lld (%llu entries), middle segments %lld "
+                "(%llu entries), pairs merged by sorting %llu (%llu from chunks)\n",
+                (long long)n, (long long)k, (long long)m_raw, (long long)(npc ? *npc : 0),
+                (unsigned long long)(ntot ? ntot[0] : 0), (long long)(nmid ? *nmid : 0),
+                (unsigned long long)(ntot ? ntot[1] : 0), (unsigned long long)np, (unsigned long long)*npc0);
     if (np > 0) {
         const uint64_t *ukey;
         const int64_t *usum;

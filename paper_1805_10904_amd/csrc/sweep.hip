@@ -122,26 +122,21 @@ __device__ __forceinline__ void hbm_insert(int32_t *key, unsigned long long *val
 // Insert or add x for a label into an HBM hub table of one word per slot,
 // (label + 1) << shift | e, 0 = empty: used when every label + 1 fits the
 // 64 - shift high bits and every e (at most 2W) the low shift bits, so the
-// add never carries into the label.  One atomic per insert instead of a key
-// compare-and-swap plus a value add.
+// add never carries into the label.  The compare-and-swap comes first: on
+// these levels nearly every label a hub's chunk inserts is new to the table
+// (R-MAT scale 24, level 0: 98% of a hub row's neighbour labels are
+// distinct), so a claim costs one memory-side atomic and no line fetch.
 __device__ __forceinline__ void packed_insert(unsigned long long *tab, uint64_t size, int32_t label,
                                               unsigned long long x, int shift) {
     const unsigned long long tag = (unsigned long long)(uint32_t)(label + 1) << shift;
     const unsigned long long tmask = ~0ull << shift;
     uint64_t h = hash_range(label, size);
     while (true) {
-        const unsigned long long cur = ((volatile unsigned long long *)tab)[h];
-        if ((cur & tmask) == tag) {
+        const unsigned long long prev = atomicCAS(&tab[h], 0ull, tag | x);
+        if (prev == 0) return;
+        if ((prev & tmask) == tag) {
             atomicAdd(&tab[h], x);
             return;
-        }
-        if (cur == 0) {
-            const unsigned long long prev = atomicCAS(&tab[h], 0ull, tag | x);
-            if (prev == 0) return;
-            if ((prev & tmask) == tag) {
-                atomicAdd(&tab[h], x);
-                return;
-            }
         }
         h = (h + 1 == size) ? 0 : h + 1;
     }
