@@ -319,9 +319,11 @@ __device__ __forceinline__ bool commit_insert(int32_t *key, unsigned long long *
 // one per tile.  Updates that find no LDS slot (tiles where most vertices
 // move between distinct communities) go to HBM directly.  The sums are
 // integers modulo 2^64, so the result does not depend on the order.
-// The last workgroup to finish (counted on `arrive`, which it leaves at 0)
-// then runs the pass's acceptance test for every graph: no launch of its
-// own.  A launch over a finished single graph returns in every workgroup.
+// With `arrive` (a single graph), the last workgroup to finish (counted on
+// `arrive`, which it leaves at 0) then runs the pass's acceptance test: no
+// launch of its own.  A batch's thousands of graphs keep their own launch,
+// one thread per graph.  A launch over a finished single graph returns in
+// every workgroup.
 struct FinalizeArgs {
     const int64_t *tw;
     int64_t ngraphs, theta_num, theta_den;
@@ -384,9 +386,13 @@ __global__ __launch_bounds__(256) void k_cpt_commit(const int32_t *__restrict__ 
     // updates, which only the next pass reads
     span_flush(sp, acc, st, 0, 1);
     __shared__ int s_last;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (threadIdx.x == 0) s_last = atomicAdd(fa.arrive, 1u) == gridDim.x - 1;
+    if (fa.arrive) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0) s_last = atomicAdd(fa.arrive, 1u) == gridDim.x - 1;
+    } else if (threadIdx.x == 0) {
+        s_last = 0;
+    }
     __syncthreads();
     for (int x = threadIdx.x; x < T; x += 256) {
         const int32_t key = s_key[x];
@@ -1830,15 +1836,17 @@ void compact_pass(const GraphView &g, const CompactPass &cp, const CompactState 
         compact_sweeps<int32_t>(a, cp, s, side, t);
     else
         compact_sweeps<int64_t>(a, cp, s, side, t);
+    const bool fused = g.n > 0 && cs.ngraphs == 1;
     if (g.n > 0) {
-        // the acceptance test runs in the last workgroup to finish
+        // a single graph's acceptance test runs in the last workgroup to finish
         const FinalizeArgs fa{cs.tw, cs.ngraphs, prm.theta_num, prm.theta_den, prm.max_sweeps, p,
-                              cs.active + (p & 1), cs.active + 2};
+                              cs.active + (p & 1), fused ? cs.active + 2 : nullptr};
         TimedLaunch tl(t, TG_SWEEP, "k_cpt_commit", (double)g.n * 12);
         tl.launch(k_cpt_commit, grid_for(g.n, kCommitTile), 256, 0, s, cs.c_cur, cs.c_nxt, g.delta, cs.es, cs.ds,
                   cs.gid, cs.st, g.n, fa);
         LV_LAUNCHED("k_cpt_commit");
-    } else {
+    }
+    if (!fused) {
         TimedLaunch tl(t, TG_SWEEP, "k_cpt_finalize", 0.0);
         tl.launch(k_cpt_finalize, grid_for(cs.ngraphs, 256), 256, 0, s, cs.st, cs.tw, cs.ngraphs, prm.theta_num,
                   prm.theta_den, prm.max_sweeps, p, cs.active + (p & 1));
