@@ -180,8 +180,8 @@ __global__ void k_cpt_expand(const uint64_t *__restrict__ ds, const uint32_t *__
 
 // ---------------------------------------------------- publish + sum deg^2 --
 
-constexpr int kPubTile = 2048;
-
+// TILE vertices per workgroup (512..2048, see compact_tile)
+template <int TILE>
 __global__ __launch_bounds__(256) void k_cpt_publish(const uint64_t *__restrict__ ds, const int32_t *__restrict__ c,
                                                      uint64_t *vw, const int32_t *__restrict__ gid, PhaseState *st,
                                                      int64_t n, unsigned int *active_zero) {
@@ -189,14 +189,14 @@ __global__ __launch_bounds__(256) void k_cpt_publish(const uint64_t *__restrict_
     __shared__ int s_glo, s_span;
     if (active_zero && blockIdx.x == 0 && threadIdx.x == 0) *active_zero = 0;
     if (single_done(gid, st)) return;
-    const int64_t base = (int64_t)blockIdx.x * kPubTile;
-    const int64_t last = base + kPubTile - 1 < n - 1 ? base + kPubTile - 1 : n - 1;
+    const int64_t base = (int64_t)blockIdx.x * TILE;
+    const int64_t last = base + TILE - 1 < n - 1 ? base + TILE - 1 : n - 1;
     const SpanSums sp = span_begin(gid, base, last, &s_glo, &s_span, acc);
     // per-thread sums while consecutive vertices share a graph
     int gcur = -1;
     unsigned long long sum = 0;
 #pragma unroll
-    for (int k = 0; k < kPubTile / 256; ++k) {
+    for (int k = 0; k < TILE / 256; ++k) {
         const int64_t v = base + k * 256 + threadIdx.x;
         if (v > last) continue;
         const int g = graph_of(gid, v);
@@ -291,16 +291,20 @@ __global__ void k_cpt_finalize(PhaseState *st, const int64_t *__restrict__ tw, i
 
 // ------------------------------------------------------------------ commit --
 
-constexpr int kCommitTile = 2048;
-constexpr int kCommitBits = 12;    // LDS table of 2^12 slots
+// Vertices per workgroup of the publish and commit kernels: 2,048 when the
+// level has enough vertices for 1,024 such workgroups, down to 512 so that
+// small levels (the later levels of a run, whose passes are many) still
+// spread over the CUs instead of running a few long workgroups.
+static int compact_tile(int64_t n) { return n >= ((int64_t)2048 << 10) ? 2048 : n >= ((int64_t)1024 << 10) ? 1024 : 512; }
 constexpr int kCommitProbe = 32;   // probes before an update goes straight to HBM
 
-// Add x to community k's pending update in the workgroup's LDS table;
-// false if no slot was found within kCommitProbe probes.
+// Add x to community k's pending update in the workgroup's LDS table of
+// 2^BITS slots; false if no slot was found within kCommitProbe probes.
+template <int BITS>
 __device__ __forceinline__ bool commit_insert(int32_t *key, unsigned long long *val, int32_t k,
                                               unsigned long long x) {
-    constexpr uint32_t mask = (1u << kCommitBits) - 1;
-    uint32_t h = ((uint32_t)k * 0x9E3779B1u) >> (32 - kCommitBits);
+    constexpr uint32_t mask = (1u << BITS) - 1;
+    uint32_t h = ((uint32_t)k * 0x9E3779B1u) >> (32 - BITS);
     for (int probe = 0; probe < kCommitProbe; ++probe) {
         const int32_t prev = atomicCAS(&key[h], kEmpty, k);   // claims, or returns the slot's key
         if (prev == kEmpty || prev == k) {
@@ -331,12 +335,14 @@ struct FinalizeArgs {
     unsigned int *active, *arrive;
 };
 
+template <int TILE>
 __global__ __launch_bounds__(256) void k_cpt_commit(const int32_t *__restrict__ c_cur, const int32_t *__restrict__ c_nxt,
                                                     const int64_t *__restrict__ delta, const uint32_t *__restrict__ es,
                                                     uint64_t *ds, const int32_t *__restrict__ gid, PhaseState *st,
                                                     int64_t n, FinalizeArgs fa) {
     if (single_done(gid, st)) return;
-    constexpr int T = 1 << kCommitBits;
+    constexpr int BITS = TILE == 2048 ? 12 : TILE == 1024 ? 11 : 10;   // two slots per vertex
+    constexpr int T = 1 << BITS;
     __shared__ unsigned long long acc[kSpan][2];
     __shared__ int s_glo, s_span;
     __shared__ int32_t s_key[T];
@@ -345,14 +351,14 @@ __global__ __launch_bounds__(256) void k_cpt_commit(const int32_t *__restrict__ 
         s_key[x] = kEmpty;
         s_val[x] = 0;
     }
-    const int64_t base = (int64_t)blockIdx.x * kCommitTile;
-    const int64_t last = base + kCommitTile - 1 < n - 1 ? base + kCommitTile - 1 : n - 1;
+    const int64_t base = (int64_t)blockIdx.x * TILE;
+    const int64_t last = base + TILE - 1 < n - 1 ? base + TILE - 1 : n - 1;
     const SpanSums sp = span_begin(gid, base, last, &s_glo, &s_span, acc);
     // per-thread sums while consecutive vertices share a graph
     int gcur = -1;
     unsigned long long sum_e = 0, sum_m = 0;
 #pragma unroll 2
-    for (int k = 0; k < kCommitTile / 256; ++k) {
+    for (int k = 0; k < TILE / 256; ++k) {
         const int64_t v = base + k * 256 + threadIdx.x;
         if (v > last) continue;
         const int g = graph_of(gid, v);
@@ -369,9 +375,9 @@ __global__ __launch_bounds__(256) void k_cpt_commit(const int32_t *__restrict__ 
         const int32_t from = c_cur[v], to = c_nxt[v];
         if (from != to) {
             const uint64_t inc = kSizeOne + (uint64_t)delta[v];
-            if (!commit_insert(s_key, s_val, to, (unsigned long long)inc))
+            if (!commit_insert<BITS>(s_key, s_val, to, (unsigned long long)inc))
                 atomicAdd((unsigned long long *)&ds[to], (unsigned long long)inc);
-            if (!commit_insert(s_key, s_val, from, (unsigned long long)(0 - inc)))
+            if (!commit_insert<BITS>(s_key, s_val, from, (unsigned long long)(0 - inc)))
                 atomicAdd((unsigned long long *)&ds[from], (unsigned long long)(0 - inc));
             sum_m += 1;
         }
@@ -1823,10 +1829,16 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
 
 void compact_pass(const GraphView &g, const CompactPass &cp, const CompactState &cs, int p,
                   const SweepParams &prm, hipStream_t s, Timer *t) {
+    const int tile = compact_tile(g.n);
     if (g.n > 0) {
         TimedLaunch tl(t, TG_SWEEP, "k_cpt_publish", (double)g.n * 28);
-        tl.launch(k_cpt_publish, grid_for(g.n, kPubTile), 256, 0, s, cs.ds, cs.c_cur, cs.vw, cs.gid, cs.st, g.n,
-                  cs.active + (p & 1));
+        const unsigned gb = grid_for(g.n, tile);
+        if (tile == 2048)
+            tl.launch(k_cpt_publish<2048>, gb, 256, 0, s, cs.ds, cs.c_cur, cs.vw, cs.gid, cs.st, g.n, cs.active + (p & 1));
+        else if (tile == 1024)
+            tl.launch(k_cpt_publish<1024>, gb, 256, 0, s, cs.ds, cs.c_cur, cs.vw, cs.gid, cs.st, g.n, cs.active + (p & 1));
+        else
+            tl.launch(k_cpt_publish<512>, gb, 256, 0, s, cs.ds, cs.c_cur, cs.vw, cs.gid, cs.st, g.n, cs.active + (p & 1));
         LV_LAUNCHED("k_cpt_publish");
     }
     CArgs a{g.row_ptr, g.col, g.w, cs.c_cur, cs.c_nxt, g.delta, cs.vw, cs.ds, cs.gid, cs.tw, cs.st, cs.es, prm.singlet,
@@ -1842,8 +1854,13 @@ void compact_pass(const GraphView &g, const CompactPass &cp, const CompactState 
         const FinalizeArgs fa{cs.tw, cs.ngraphs, prm.theta_num, prm.theta_den, prm.max_sweeps, p,
                               cs.active + (p & 1), fused ? cs.active + 2 : nullptr};
         TimedLaunch tl(t, TG_SWEEP, "k_cpt_commit", (double)g.n * 12);
-        tl.launch(k_cpt_commit, grid_for(g.n, kCommitTile), 256, 0, s, cs.c_cur, cs.c_nxt, g.delta, cs.es, cs.ds,
-                  cs.gid, cs.st, g.n, fa);
+        const unsigned gb = grid_for(g.n, tile);
+        if (tile == 2048)
+            tl.launch(k_cpt_commit<2048>, gb, 256, 0, s, cs.c_cur, cs.c_nxt, g.delta, cs.es, cs.ds, cs.gid, cs.st, g.n, fa);
+        else if (tile == 1024)
+            tl.launch(k_cpt_commit<1024>, gb, 256, 0, s, cs.c_cur, cs.c_nxt, g.delta, cs.es, cs.ds, cs.gid, cs.st, g.n, fa);
+        else
+            tl.launch(k_cpt_commit<512>, gb, 256, 0, s, cs.c_cur, cs.c_nxt, g.delta, cs.es, cs.ds, cs.gid, cs.st, g.n, fa);
         LV_LAUNCHED("k_cpt_commit");
     }
     if (!fused) {
