@@ -99,13 +99,25 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const TI *__restrict__ in, 
 }
 
 // Down-sweep of one tile: out = exclusive prefix + the tile's offset.  The
-// last block writes the grand total to *total (if non-null).
+// last block writes the grand total to *total (if non-null).  With sums,
+// block_off holds the blocks' sums and every block adds up those before its
+// own (at most kScanFlat of them), so a mid-size scan takes two launches.
+constexpr int kScanFlat = 4096;
+
 template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void k_scan_down(const TI *in, TO *out, int64_t m,
-                                                   const TO *__restrict__ block_off, TO *total) {
+                                                   const TO *__restrict__ block_off, TO *total, int sums) {
     __shared__ TO tile[kScanTile];
     const int t = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    TO off = 0;
+    if (block_off && sums) {
+        TO p = 0;
+        for (int b = t; b < (int)blockIdx.x; b += 256) p += block_off[b];
+        off = block_sum_256<TO>(p);
+    } else if (block_off) {
+        off = block_off[blockIdx.x];
+    }
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
         int64_t i = base + k * 256 + t;
@@ -121,7 +133,6 @@ __global__ __launch_bounds__(256) void k_scan_down(const TI *in, TO *out, int64_
     }
     TO tot;
     TO run = block_excl_scan_256<TO>(sum, tot);
-    const TO off = block_off ? block_off[blockIdx.x] : (TO)0;
     run += off;
 #pragma unroll
     for (int k = 0; k < kScanItems; ++k) {
@@ -146,7 +157,7 @@ void scan_exclusive(const TI *in, TO *out, int64_t m, TO *total_dev, hipStream_t
     const int64_t nb = (m + kScanTile - 1) / kScanTile;
     if (nb == 1) {
         TimedLaunch tl(t, TG_OTHER, "k_scan_down", (double)m * (sizeof(TI) + sizeof(TO)));
-        tl.launch(k_scan_down<TI, TO>, 1, 256, 0, s, in, out, m, nullptr, total_dev);
+        tl.launch(k_scan_down<TI, TO>, 1, 256, 0, s, in, out, m, nullptr, total_dev, 0);
         LV_LAUNCHED("k_scan_down");
         return;
     }
@@ -156,10 +167,11 @@ void scan_exclusive(const TI *in, TO *out, int64_t m, TO *total_dev, hipStream_t
         tl.launch(k_scan_reduce<TI, TO>, (unsigned)nb, 256, 0, s, in, m, bs.as<TO>());
         LV_LAUNCHED("k_scan_reduce");
     }
-    scan_exclusive<TO, TO>(bs.as<TO>(), bs.as<TO>(), nb, (TO *)nullptr, s, t);
+    const int sums = nb <= kScanFlat ? 1 : 0;   // else the block sums are scanned first
+    if (!sums) scan_exclusive<TO, TO>(bs.as<TO>(), bs.as<TO>(), nb, (TO *)nullptr, s, t);
     {
         TimedLaunch tl(t, TG_OTHER, "k_scan_down", (double)m * (sizeof(TI) + sizeof(TO)));
-        tl.launch(k_scan_down<TI, TO>, (unsigned)nb, 256, 0, s, in, out, m, bs.as<TO>(), total_dev);
+        tl.launch(k_scan_down<TI, TO>, (unsigned)nb, 256, 0, s, in, out, m, bs.as<TO>(), total_dev, sums);
         LV_LAUNCHED("k_scan_down");
     }
 }
