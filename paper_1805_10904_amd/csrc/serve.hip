@@ -91,8 +91,9 @@ double Server::now_us() {
 size_t Server::workspace_bytes(int64_t n, int64_t nnz) {
     // resident CSR and labels ~ 20 B/vertex + 12 B/entry; two union buffers
     // with growth slack ~ 40 B/vertex + 30 B/entry; sweep state ~ 80 B/vertex
-    // and hub tables up to 24 B/entry; contraction sort ~ 45 B/entry
-    const double b = 160.0 * (double)n + 128.0 * (double)nnz + (double)(1 << 20);
+    // and hub tables up to 24 B/entry, with the hub buckets of levels with
+    // 2W >= 2^31 up to 32 B/entry more; contraction sort ~ 45 B/entry
+    const double b = 160.0 * (double)n + 160.0 * (double)nnz + (double)(1 << 20);
     return (size_t)b;
 }
 

@@ -153,6 +153,32 @@ static int word_shift(int64_t n, int64_t tw) {
     return (shift < 63 && (uint64_t)tw < (1ull << shift)) ? shift : 0;
 }
 
+// LOUVAIN_HUB_BUCKET_SHRINK=s (1..4096, read once per process): hub bucket
+// regions and tables s times smaller, so that tests reach the spills to the
+// hub tables on small graphs.  Results do not depend on it.
+static int hub_bucket_shrink() {
+    static const int v = [] {
+        const char *e = getenv("LOUVAIN_HUB_BUCKET_SHRINK");
+        const int x = e ? atoi(e) : 1;
+        return x >= 1 && x <= 4096 ? x : 1;
+    }();
+    return v;
+}
+
+// Label bits of the published words of a level of n vertices.
+static int pw_label_bits(int64_t n) {
+    int bits = 1;
+    while (bits < 31 && ((int64_t)1 << bits) < n) ++bits;
+    return bits;
+}
+
+// Published words (label, deg_C, singleton flag) on levels with 128-bit
+// scores, when the label bits and the bits of TW fit 63 together.
+static bool publishes(const GraphView &g) {
+    return g.tw > kTwFastMax && g.n > 0 &&
+           pw_label_bits(g.n) + 64 - __builtin_clzll((unsigned long long)g.tw) <= 63;
+}
+
 int64_t lds_row_max(int64_t n, int64_t tw, const Tuning &tn) {
     if (tw < kCompactTwMax) return tn.block_max;
     return word_shift(n, tw) ? kBucketMax[B_WIDE] : kBucketMax[B_BLOCK];
@@ -701,7 +727,42 @@ struct HubMeta {
     const int32_t *chunk_hub;// hub of each accumulation workgroup
     const int32_t *scan_hub; // hub of each scan workgroup
     int64_t hubs;
+    const int64_t *bkt_off;  // first bucket of each hub (no buckets: the hub uses its table only)
+    const int64_t *reg_off;  // first pair slot of each hub's bucket regions
+    const int32_t *bkt_hub;  // hub of each bucket
+    int shrink;              // bucket regions and tables divided by this (1; more only to test the spills)
 };
+
+// Hub rows on levels with published words and single-word tables are swept
+// by partition.  Each accumulation workgroup sums its chunk in LDS, keyed by
+// the neighbour's published word, then appends every distinct (word, e) to
+// one of the hub's buckets, chosen by a hash of the label, with one cursor
+// add per bucket and workgroup; one workgroup per bucket then sums its pairs
+// in an LDS table and scores them (deg_C is in the key).  On R-MAT scale 24
+// nearly every label a hub's chunk meets is new to it, so the table path
+// cost one memory-side atomic per entry, most of the hubs' time.  The table
+// stays the path of hubs with more than kBktMax buckets, and of a bucket
+// whose pairs overflow its region or its LDS table: all that bucket's pairs
+// then go to the table (the spill flag makes the scan read it), so a label
+// is never split between a bucket and the table.
+constexpr int kBktPairs = 2048;                 // a hub has one bucket per kBktPairs entries
+constexpr int kBktMax = 256;                    // buckets of a hub at most
+constexpr int kBktBits = 12;                    // bucket table: 4,096 word-keyed slots (64 KB)
+constexpr int kBktClaim = 3 * (1 << kBktBits) / 4;
+
+__device__ __forceinline__ int64_t bkt_count(int64_t d) {
+    const int64_t P = (d + kBktPairs - 1) / kBktPairs;
+    return P <= kBktMax ? P : 0;
+}
+// Pair slots of each bucket of a hub of d entries in P buckets: twice the
+// mean (divided by the test shrink factor).
+__device__ __forceinline__ int64_t bkt_cap(int64_t d, int64_t P, int shrink) {
+    const int64_t c = 2 * ((d + P - 1) / P) / shrink;
+    return c > 0 ? c : 1;
+}
+__device__ __forceinline__ int64_t bkt_of(int32_t label, int64_t P) {
+    return (int64_t)(((uint64_t)((uint32_t)label * 0x85EBCA6Bu) * (uint64_t)P) >> 32);
+}
 
 constexpr int kHubLdsBits = 11;  // 2048 slots for a chunk of kHubChunk = 1024 entries
 
@@ -710,17 +771,20 @@ constexpr int kHubLdsBits = 11;  // 2048 slots for a chunk of kHubChunk = 1024 e
 template <typename W, typename S>
 __global__ __launch_bounds__(256) void k_hub_accum(SweepArgs a, HubMeta hm, int32_t *gkey,
                                                    unsigned long long *gval, unsigned long long *hub_loop,
-                                                   uint64_t *part) {
+                                                   uint64_t *part, uint64_t *bkey, uint64_t *bval,
+                                                   unsigned int *bcur, unsigned int *spill) {
     constexpr int T = 1 << kHubLdsBits;
-    __shared__ int32_t s_key[T];
+    // keyed by the neighbour's published word, or by its label without words
+    __shared__ unsigned long long s_key[T];
     __shared__ unsigned long long s_val[T];
+    __shared__ unsigned int s_cnt[kBktMax], s_base[kBktMax];
     __shared__ int64_t s_h;
     if (a.st->done) return;
     const int t = threadIdx.x;
     if (t == 0) s_h = hm.chunk_hub[blockIdx.x];
     if (!a.first)
         for (int x = t; x < T; x += 256) {
-            s_key[x] = kEmpty;
+            s_key[x] = kEmptyWord;
             s_val[x] = 0;
         }
     __syncthreads();
@@ -746,11 +810,22 @@ __global__ __launch_bounds__(256) void k_hub_accum(SweepArgs a, HubMeta hm, int3
         }
     }
     int64_t dq[U];
+    uint64_t uq[U];
 #pragma unroll
     for (int q = 0; q < U; ++q) {
         lq[q] = -1;
         dq[q] = -1;
-        if (jq[q] >= 0 && jq[q] != v) lq[q] = nb_label(a, jq[q], &dq[q]);
+        uq[q] = 0;
+        if (jq[q] >= 0 && jq[q] != v) {
+            if (a.pw) {
+                uq[q] = a.pw[jq[q]];
+                lq[q] = pw_label(uq[q], a.pw_bits);
+                dq[q] = pw_deg(uq[q], a.pw_bits);
+            } else {
+                lq[q] = nb_label(a, jq[q], &dq[q]);
+                uq[q] = (uint32_t)lq[q];
+            }
+        }
     }
     int64_t loop = 0;
 #pragma unroll
@@ -786,16 +861,168 @@ __global__ __launch_bounds__(256) void k_hub_accum(SweepArgs a, HubMeta hm, int3
     }
 #pragma unroll
     for (int q = 0; q < U; ++q)
-        if (lq[q] >= 0) lds_insert<kHubLdsBits>(s_key, s_val, lq[q], wq[q]);
+        if (lq[q] >= 0) lds_insert_word<kHubLdsBits>(s_key, s_val, uq[q], lq[q], wq[q]);
     __syncthreads();
     const int64_t base = hm.tab_off[h], size = hm.tab_size[h];
+    const int64_t b0 = hm.bkt_off[h], P = hm.bkt_off[h + 1] - b0;
+    auto label_of = [&](unsigned long long key) {
+        return a.pw ? pw_label(key, a.pw_bits) : (int32_t)(uint32_t)key;
+    };
+    if (P == 0) {   // the hub's table
+        for (int x = t; x < T; x += 256) {
+            const unsigned long long key = s_key[x];
+            if (key == kEmptyWord) continue;
+            if (a.hub_shift)
+                packed_insert(gval + base, (uint64_t)size, label_of(key), s_val[x], a.hub_shift);
+            else
+                hbm_insert(gkey + base, gval + base, size, label_of(key), s_val[x]);
+        }
+        return;
+    }
+    // buckets: every distinct pair's rank among the workgroup's pairs of its
+    // bucket, then one cursor add per bucket
+    for (int b = t; b < P; b += 256) s_cnt[b] = 0;
+    __syncthreads();
+    constexpr int Q = T / 256;
+    int32_t bq[Q];
+    uint32_t rq[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const unsigned long long key = s_key[t + q * 256];
+        bq[q] = -1;
+        rq[q] = 0;
+        if (key != kEmptyWord) {
+            bq[q] = (int32_t)bkt_of(label_of(key), P);
+            rq[q] = atomicAdd(&s_cnt[bq[q]], 1u);
+        }
+    }
+    __syncthreads();
+    for (int b = t; b < P; b += 256) s_base[b] = s_cnt[b] ? atomicAdd(&bcur[b0 + b], s_cnt[b]) : 0u;
+    __syncthreads();
+    const int64_t cap = bkt_cap(row_end - a.row_ptr[v], P, hm.shrink);
+    bool over = false;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        if (bq[q] < 0) continue;
+        const int x = t + q * 256;
+        const int64_t pos = (int64_t)s_base[bq[q]] + rq[q];
+        if (pos < cap) {
+            const int64_t at = hm.reg_off[h] + (int64_t)bq[q] * cap + pos;
+            bkey[at] = s_key[x];
+            bval[at] = s_val[x];
+        } else {   // the bucket's region is full: the bucket goes to the table
+            packed_insert(gval + base, (uint64_t)size, label_of(s_key[x]), s_val[x], a.hub_shift);
+            over = true;
+        }
+    }
+    if (over) spill[h] = 1u;
+}
+
+// One workgroup per bucket of a hub: sum its pairs in LDS and score them
+// (best candidate and own e as a partial for k_hub_decide), or, when its
+// pairs overflowed its region or its table, add all of them to the hub's
+// table instead.  Leaves the bucket's cursor at 0.
+template <typename S>
+__global__ __launch_bounds__(256) void k_hub_bucket(SweepArgs a, HubMeta hm, unsigned long long *gval,
+                                                    const uint64_t *__restrict__ bkey,
+                                                    const uint64_t *__restrict__ bval, unsigned int *bcur,
+                                                    unsigned int *spill, uint64_t *bpart) {
+    constexpr int T = 1 << kBktBits;
+    __shared__ unsigned long long s_key[T], s_val[T];
+    __shared__ int64_t s_h;
+    __shared__ unsigned int s_n;
+    __shared__ int s_used, s_over;
+    if (a.st->done) return;
+    const int t = threadIdx.x;
+    const int64_t bk = blockIdx.x;
+    if (t == 0) {
+        s_h = hm.bkt_hub[bk];
+        s_n = bcur[bk];
+        s_used = 0;
+        s_over = 0;
+    }
     for (int x = t; x < T; x += 256) {
-        const int32_t key = s_key[x];
-        if (key == kEmpty) continue;
-        if (a.hub_shift)
-            packed_insert(gval + base, (uint64_t)size, key, s_val[x], a.hub_shift);
-        else
-            hbm_insert(gkey + base, gval + base, size, key, s_val[x]);
+        s_key[x] = kEmptyWord;
+        s_val[x] = 0;
+    }
+    __syncthreads();
+    const int64_t h = s_h;
+    const int32_t v = hm.v[h];
+    const int64_t b0 = hm.bkt_off[h], P = hm.bkt_off[h + 1] - b0;
+    const int64_t cap = bkt_cap(a.row_ptr[v + 1] - a.row_ptr[v], P, hm.shrink);
+    const int64_t reg = hm.reg_off[h] + (bk - b0) * cap;
+    const int claim = kBktClaim / hm.shrink > 0 ? kBktClaim / hm.shrink : 1;
+    const int64_t n = s_n;
+    bool spill_all = n > cap;
+    if (!spill_all) {
+        bool over = false;
+        for (int64_t i = t; i < n; i += 256) {
+            const uint64_t word = bkey[reg + i];
+            const unsigned long long e = bval[reg + i];
+            uint32_t x = hash_pow2(pw_label(word, a.pw_bits), kBktBits);
+            while (true) {
+                const unsigned long long cur = s_key[x];
+                if (cur == word) {
+                    atomicAdd(&s_val[x], e);
+                    break;
+                }
+                if (cur == kEmptyWord) {
+                    if (s_used >= claim) {
+                        over = true;
+                        break;
+                    }
+                    const unsigned long long prev = atomicCAS(&s_key[x], kEmptyWord, (unsigned long long)word);
+                    if (prev == kEmptyWord) atomicAdd(&s_used, 1);
+                    if (prev == kEmptyWord || prev == word) {
+                        atomicAdd(&s_val[x], e);
+                        break;
+                    }
+                }
+                x = (x + 1) & (T - 1);
+            }
+        }
+        if (over) s_over = 1;
+        __syncthreads();
+        spill_all = s_over != 0;
+    }
+    S bs = 0;
+    int32_t bl = -1;
+    int64_t e_own = 0, unused = 0;
+    if (spill_all) {
+        const int64_t m = n < cap ? n : cap;
+        const int64_t base = hm.tab_off[h], size = hm.tab_size[h];
+        for (int64_t i = t; i < m; i += 256)
+            packed_insert(gval + base, (uint64_t)size, pw_label(bkey[reg + i], a.pw_bits), bval[reg + i],
+                          a.hub_shift);
+        if (t == 0) spill[h] = 1u;
+    } else {
+        const int32_t ci = a.c_cur[v];
+        const int64_t di = a.delta[v];
+        for (int x = t; x < T; x += 256) {
+            const unsigned long long key = s_key[x];
+            if (key == kEmptyWord) continue;
+            const int32_t k = pw_label(key, a.pw_bits);
+            const int64_t ev = (int64_t)s_val[x];
+            if (k == ci) {
+                e_own += ev;
+                continue;
+            }
+            const S sc = score_mul<S>(a.tw, ev) - score_mul<S>(di, pw_deg(key, a.pw_bits));
+            if (better<S>(sc, k, bs, bl)) {
+                bs = sc;
+                bl = k;
+            }
+        }
+    }
+    group_reduce_block<S>(bs, bl, e_own, unused);
+    if (t == 0) {
+        const i128 w = (i128)bs;
+        uint64_t *p = bpart + 4 * bk;
+        p[0] = (uint64_t)w;
+        p[1] = (uint64_t)(int64_t)(w >> 64);
+        p[2] = (uint64_t)(int64_t)bl;
+        p[3] = (uint64_t)e_own;
+        bcur[bk] = 0u;
     }
 }
 
@@ -803,12 +1030,26 @@ __global__ __launch_bounds__(256) void k_hub_accum(SweepArgs a, HubMeta hm, int3
 // e over its slots (partial), clearing the slots for the next pass.
 template <typename S>
 __global__ __launch_bounds__(256) void k_hub_scan(SweepArgs a, HubMeta hm, int32_t *gkey,
-                                                  unsigned long long *gval, uint64_t *part) {
+                                                  unsigned long long *gval, uint64_t *part,
+                                                  const unsigned int *spill) {
     __shared__ int64_t s_h;
+    __shared__ int s_skip;
     if (a.st->done) return;
     const int t = threadIdx.x;
-    if (t == 0) s_h = hm.scan_hub[blockIdx.x];
+    if (t == 0) {
+        s_h = hm.scan_hub[blockIdx.x];
+        // a hub swept by buckets has nothing in its table unless one spilled
+        s_skip = hm.bkt_off[s_h + 1] > hm.bkt_off[s_h] && spill[s_h] == 0u;
+        if (s_skip) {
+            uint64_t *p = part + 4 * (int64_t)blockIdx.x;
+            p[0] = 0;
+            p[1] = 0;
+            p[2] = (uint64_t)(int64_t)-1;
+            p[3] = 0;
+        }
+    }
     __syncthreads();
+    if (s_skip) return;
     const int64_t h = s_h;
     const int32_t v = hm.v[h];
     const int32_t ci = a.c_cur[v];
@@ -860,7 +1101,8 @@ __global__ __launch_bounds__(256) void k_hub_scan(SweepArgs a, HubMeta hm, int32
 // One wavefront per hub: combine the scan partials and decide.
 template <typename S>
 __global__ __launch_bounds__(256) void k_hub_decide(SweepArgs a, HubMeta hm, const uint64_t *part,
-                                                    unsigned long long *hub_loop) {
+                                                    unsigned long long *hub_loop, const uint64_t *bpart,
+                                                    unsigned int *spill) {
     if (a.st->done) return;
     const int lane = threadIdx.x & 63;
     const int64_t h = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -871,8 +1113,7 @@ __global__ __launch_bounds__(256) void k_hub_decide(SweepArgs a, HubMeta hm, con
     // partials: one per scan workgroup, or one per chunk on the first pass
     // from singletons
     const int64_t *range = a.first ? hm.chunk_off : hm.scan_off;
-    for (int64_t b = range[h] + lane; b < range[h + 1]; b += 64) {
-        const uint64_t *p = part + 4 * b;
+    auto take = [&](const uint64_t *p) {
         const int32_t l = (int32_t)(int64_t)p[2];
         const S sc = (S)make_i128(p[0], (int64_t)p[1]);
         if (better<S>(sc, l, bs, bl)) {
@@ -880,9 +1121,13 @@ __global__ __launch_bounds__(256) void k_hub_decide(SweepArgs a, HubMeta hm, con
             bl = l;
         }
         e_own += (int64_t)p[3];
-    }
+    };
+    for (int64_t b = range[h] + lane; b < range[h + 1]; b += 64) take(part + 4 * b);
+    if (!a.first)   // and the buckets' partials
+        for (int64_t b = hm.bkt_off[h] + lane; b < hm.bkt_off[h + 1]; b += 64) take(bpart + 4 * b);
     group_reduce_wave<64, S>(bs, bl, e_own, unused);
     if (lane == 0) {
+        spill[h] = 0u;
         const int32_t v = hm.v[h];
         const int32_t ci = a.c_cur[v];
         a.c_nxt[v] = decide<S>(a, v, ci, bs, bl, e_own);
@@ -1162,7 +1407,8 @@ __global__ void k_hub_map(const int64_t *__restrict__ off, int64_t hubs, int32_t
 }
 
 __global__ void k_hub_sizes(const int64_t *__restrict__ rp, const int32_t *__restrict__ hubv, int64_t hubs,
-                            int64_t *tab_off, int64_t *chunk_off, int64_t *scan_off, int64_t *tab_size) {
+                            int64_t *tab_off, int64_t *chunk_off, int64_t *scan_off, int64_t *tab_size,
+                            int64_t *bkt_off, int64_t *reg_off, int bucketed, int shrink) {
     const int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (h >= hubs) return;
     const int32_t v = hubv[h];
@@ -1172,6 +1418,9 @@ __global__ void k_hub_sizes(const int64_t *__restrict__ rp, const int32_t *__res
     tab_off[h] = T;
     chunk_off[h] = (d + kHubChunk - 1) / kHubChunk;
     scan_off[h] = T / kHubScan;
+    const int64_t P = bucketed ? bkt_count(d) : 0;
+    bkt_off[h] = P;
+    reg_off[h] = P ? P * bkt_cap(d, P, shrink) : 0;
 }
 
 // ------------------------------------------------------------------- host --
@@ -1196,7 +1445,7 @@ void Sweeper::reserve(int64_t n, int64_t nnz) {
     // kPackMaxDeg + 1 entries whatever the tuning
     const int64_t max_hubs = nnz / (kPackMaxDeg + 1) + 1;
     hub_cap_ = max_hubs;
-    hub_meta_.alloc((size_t)(4 * (max_hubs + 1)));
+    hub_meta_.alloc((size_t)(6 * (max_hubs + 1)));
     pack_pos_.alloc((size_t)n + 1);
     hub_loop_.alloc((size_t)max_hubs);
     cap_n_ = n;
@@ -1233,7 +1482,7 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     if ((int64_t)st_.n < ngraphs_) st_.alloc((size_t)ngraphs_);
     const int64_t nblk = (g.n + kBucketTile - 1) / kBucketTile;
     for (int b = 0; b <= NBUCKET; ++b) bstart_[b] = 0;
-    hubs_ = hub_chunks_ = hub_scans_ = hub_slots_ = 0;
+    hubs_ = hub_chunks_ = hub_scans_ = hub_slots_ = hub_buckets_ = 0;
     pack_count_ = pack_blocks_ = 0;
     qblocks_ = (g.n + kQsumTile - 1) / kQsumTile;
     if (g.n == 0) return;
@@ -1298,17 +1547,42 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     require(hubs_ <= hub_cap_, LOUVAIN_EDEVICE, "hub count exceeds the reserved hub tables");
     int64_t *tab_off = hub_meta_.p, *chunk_off = tab_off + (hubs_ + 1), *scan_off = chunk_off + (hubs_ + 1),
             *tab_size = scan_off + (hubs_ + 1);
+    int64_t *bkt_off = tab_size + (hubs_ + 1), *reg_off = bkt_off + (hubs_ + 1);
     const int32_t *hubv = list_.p + bstart_[B_HUB];
-    k_hub_sizes<<<grid_for(hubs_, 256), 256, 0, s_>>>(g.row_ptr, hubv, hubs_, tab_off, chunk_off, scan_off, tab_size);
+    // general levels with published words and single-word tables sweep their hubs by buckets
+    const int bucketed = !compact_ && publishes(g) && word_shift(g.n, g.tw) > 0 ? 1 : 0;
+    k_hub_sizes<<<grid_for(hubs_, 256), 256, 0, s_>>>(g.row_ptr, hubv, hubs_, tab_off, chunk_off, scan_off, tab_size,
+                                                      bkt_off, reg_off, bucketed, hub_bucket_shrink());
     LV_LAUNCHED("k_hub_sizes");
     scan_exclusive<int64_t, int64_t>(tab_off, tab_off, hubs_, tab_off + hubs_, s_, t_);
     scan_exclusive<int64_t, int64_t>(chunk_off, chunk_off, hubs_, chunk_off + hubs_, s_, t_);
     scan_exclusive<int64_t, int64_t>(scan_off, scan_off, hubs_, scan_off + hubs_, s_, t_);
+    if (!compact_) {
+        scan_exclusive<int64_t, int64_t>(bkt_off, bkt_off, hubs_, bkt_off + hubs_, s_, t_);
+        scan_exclusive<int64_t, int64_t>(reg_off, reg_off, hubs_, reg_off + hubs_, s_, t_);
+    }
     const int64_t *tot[3] = {rb.add(tab_off + hubs_), rb.add(chunk_off + hubs_), rb.add(scan_off + hubs_)};
+    const int64_t *btot[2] = {compact_ ? nullptr : rb.add(bkt_off + hubs_), compact_ ? nullptr : rb.add(reg_off + hubs_)};
     rb.fetch();
     hub_slots_ = *tot[0];
     hub_chunks_ = *tot[1];
     hub_scans_ = *tot[2];
+    hub_buckets_ = btot[0] ? *btot[0] : 0;
+    if (hub_buckets_ > 0) {
+        const int64_t pairs = *btot[1];
+        bkt_key_.reserve((size_t)pairs);
+        bkt_val_.reserve((size_t)pairs);
+        bkt_cur_.reserve((size_t)hub_buckets_);
+        bkt_part_.reserve((size_t)(4 * hub_buckets_));
+        hub_of_bkt_.reserve((size_t)hub_buckets_);
+        fill<int32_t>((int32_t *)bkt_cur_.p, 0, hub_buckets_, s_);
+        k_hub_map<<<(unsigned)hubs_, 256, 0, s_>>>(bkt_off, hubs_, hub_of_bkt_.p);
+        LV_LAUNCHED("k_hub_map");
+    }
+    if (!compact_) {
+        hub_spill_.reserve((size_t)hubs_);
+        fill<int32_t>((int32_t *)hub_spill_.p, 0, hubs_, s_);
+    }
     if (hub_slots_ > hub_slot_cap_) {
         hub_key_.alloc((size_t)hub_slots_);
         hub_val_.alloc((size_t)hub_slots_);
@@ -1492,10 +1766,19 @@ struct ClassLists {
     const int64_t *cnnz = nullptr;              // entries of every class
 };
 
+// Buffers of the hubs swept by buckets.
+struct HubBuckets {
+    int64_t buckets;
+    uint64_t *key, *val;   // pair regions
+    unsigned int *cur;     // pairs appended to each bucket
+    uint64_t *part;        // per bucket: score lo, score hi, label, e_own
+    unsigned int *spill;   // per hub: some bucket went to the table
+};
+
 template <typename W, typename S>
 static void launch_pass(const SweepArgs &a, const int32_t *list, const int64_t *bstart,
                         const int64_t *bnnz, const int64_t *pack_pos, const int64_t *pack_first,
-                        int64_t pack_blocks, HubMeta hm,
+                        int64_t pack_blocks, HubMeta hm, const HubBuckets &hb,
                         int64_t hub_chunks, int64_t hub_scans, int32_t *hkey, unsigned long long *hval,
                         unsigned long long *hloop, uint64_t *hpart, hipStream_t s, Timer *t,
                         const ClassLists &cl = ClassLists()) {
@@ -1592,17 +1875,25 @@ static void launch_pass(const SweepArgs &a, const int32_t *list, const int64_t *
     if (hm.hubs > 0) {
         {
             TimedLaunch tl(t, TG_SWEEP, "k_hub_accum<", (double)bnnz[B_HUB] * eb, wsfx.c_str());
-            tl.launch(k_hub_accum<W, S>, (unsigned)hub_chunks, 256, 0, s, a, hm, hkey, hval, hloop, hpart);
+            tl.launch(k_hub_accum<W, S>, (unsigned)hub_chunks, 256, 0, s, a, hm, hkey, hval, hloop, hpart, hb.key,
+                      hb.val, hb.cur, hb.spill);
             LV_LAUNCHED("k_hub_accum");
+        }
+        if (!a.first && hb.buckets > 0) {
+            // per pair (at most one per hub entry): word and e read
+            TimedLaunch tl(t, TG_SWEEP, "k_hub_bucket<", (double)bnnz[B_HUB] * 16.0, ssfx.c_str());
+            tl.launch(k_hub_bucket<S>, (unsigned)hb.buckets, 256, 0, s, a, hm, hval, hb.key, hb.val, hb.cur, hb.spill,
+                      hb.part);
+            LV_LAUNCHED("k_hub_bucket");
         }
         if (!a.first) {
             TimedLaunch tl(t, TG_SWEEP, "k_hub_scan<", (double)hub_scans * kHubScan * 24.0, ssfx.c_str());
-            tl.launch(k_hub_scan<S>, (unsigned)hub_scans, 256, 0, s, a, hm, hkey, hval, hpart);
+            tl.launch(k_hub_scan<S>, (unsigned)hub_scans, 256, 0, s, a, hm, hkey, hval, hpart, hb.spill);
             LV_LAUNCHED("k_hub_scan");
         }
         {
             TimedLaunch tl(t, TG_SWEEP, "k_hub_decide<", (double)hm.hubs * vb + (double)hub_scans * 32.0, ssfx.c_str());
-            tl.launch(k_hub_decide<S>, grid_for(hm.hubs, 4), 256, 0, s, a, hm, hpart, hloop);
+            tl.launch(k_hub_decide<S>, grid_for(hm.hubs, 4), 256, 0, s, a, hm, hpart, hloop, hb.part, hb.spill);
             LV_LAUNCHED("k_hub_decide");
         }
     }
@@ -1674,11 +1965,8 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
         compact_pass(g, cp, cs, p, prm, s_, t_);
         return;
     }
-    // published words (label, deg_C, singleton flag) on levels with 128-bit
-    // scores, when the label bits and the bits of TW fit 63 together
-    int pw_bits = 1;
-    while (pw_bits < 31 && ((int64_t)1 << pw_bits) < g.n) ++pw_bits;
-    const bool publish = g.tw > kTwFastMax && pw_bits + 64 - __builtin_clzll((unsigned long long)g.tw) <= 63;
+    const int pw_bits = pw_label_bits(g.n);
+    const bool publish = publishes(g);
     if (g.n > 0) {
         TimedLaunch tl(t_, TG_SWEEP, "k_qsum", (double)g.n * (publish ? 32 : 8));
         tl.launch(k_qsum, (unsigned)qblocks_, 256, 0, s_, deg_.p, g.n, qpart_.p, st_.p, (const int32_t *)c_[cur].p,
@@ -1693,7 +1981,9 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
                 publish ? vw_.p : nullptr, pw_bits};
     int64_t *tab_off = hub_meta_.p;
     HubMeta hm{list_.p + bstart_[B_HUB], tab_off, tab_off + (hubs_ + 1), tab_off + 2 * (hubs_ + 1),
-               tab_off + 3 * (hubs_ + 1), hub_of_chunk_.p, hub_of_scan_.p, hubs_};
+               tab_off + 3 * (hubs_ + 1), hub_of_chunk_.p, hub_of_scan_.p, hubs_, tab_off + 4 * (hubs_ + 1),
+               tab_off + 5 * (hubs_ + 1), hub_of_bkt_.p, hub_bucket_shrink()};
+    HubBuckets hb{hub_buckets_, bkt_key_.p, bkt_val_.p, bkt_cur_.p, bkt_part_.p, hub_spill_.p};
     const bool fast = g.tw <= kTwFastMax;
     ClassLists cls;
     if (general_classes_) {
@@ -1703,17 +1993,17 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
     }
     if (g.wbytes == 4) {
         if (fast)
-            launch_pass<int32_t, int64_t>(a, list_.p, bstart_, bucket_nnz_, pack_pos_.p, pack_first_.p, pack_blocks_, hm, hub_chunks_, hub_scans_,
+            launch_pass<int32_t, int64_t>(a, list_.p, bstart_, bucket_nnz_, pack_pos_.p, pack_first_.p, pack_blocks_, hm, hb, hub_chunks_, hub_scans_,
                                           hub_key_.p, hub_val_.p, hub_loop_.p, hub_part_.p, s_, t_);
         else
-            launch_pass<int32_t, i128>(a, list_.p, bstart_, bucket_nnz_, pack_pos_.p, pack_first_.p, pack_blocks_, hm, hub_chunks_, hub_scans_,
+            launch_pass<int32_t, i128>(a, list_.p, bstart_, bucket_nnz_, pack_pos_.p, pack_first_.p, pack_blocks_, hm, hb, hub_chunks_, hub_scans_,
                                        hub_key_.p, hub_val_.p, hub_loop_.p, hub_part_.p, s_, t_, cls);
     } else {
         if (fast)
-            launch_pass<int64_t, int64_t>(a, list_.p, bstart_, bucket_nnz_, pack_pos_.p, pack_first_.p, pack_blocks_, hm, hub_chunks_, hub_scans_,
+            launch_pass<int64_t, int64_t>(a, list_.p, bstart_, bucket_nnz_, pack_pos_.p, pack_first_.p, pack_blocks_, hm, hb, hub_chunks_, hub_scans_,
                                           hub_key_.p, hub_val_.p, hub_loop_.p, hub_part_.p, s_, t_);
         else
-            launch_pass<int64_t, i128>(a, list_.p, bstart_, bucket_nnz_, pack_pos_.p, pack_first_.p, pack_blocks_, hm, hub_chunks_, hub_scans_,
+            launch_pass<int64_t, i128>(a, list_.p, bstart_, bucket_nnz_, pack_pos_.p, pack_first_.p, pack_blocks_, hm, hb, hub_chunks_, hub_scans_,
                                        hub_key_.p, hub_val_.p, hub_loop_.p, hub_part_.p, s_, t_, cls);
     }
     if (g.n > 0) {

@@ -241,7 +241,8 @@ class Sweeper {
     DevBuf<PhaseState> st_;
     DevBuf<uint64_t> qpart_;        // per-block partial sums of deg^2 (lo, hi)
     // hubs
-    DevBuf<int64_t> hub_meta_;      // 4 arrays of (hubs+1): table offset, chunk offset, scan offset, table size
+    DevBuf<int64_t> hub_meta_;      // 6 arrays of (hubs+1): table offset, chunk offset, scan offset, table size,
+                                    // first bucket, first bucket pair slot
     DevBuf<int32_t> hub_key_;
     DevBuf<unsigned long long> hub_val_;
     DevBuf<unsigned long long> hub_loop_;
@@ -250,6 +251,13 @@ class Sweeper {
     DevBuf<int64_t> pack_first_;    // first packed vertex of every packed workgroup (+ end)
     DevBuf<int32_t> hub_of_chunk_;  // hub of every accumulation workgroup
     DevBuf<int32_t> hub_of_scan_;   // hub of every scan workgroup
+    // hubs swept by buckets (levels with 128-bit scores and published words)
+    DevBuf<uint64_t> bkt_key_, bkt_val_;   // pair regions: published word, e
+    DevBuf<unsigned int> bkt_cur_;         // pairs appended to each bucket
+    DevBuf<uint64_t> bkt_part_;            // per bucket: score lo, score hi, label, e_own
+    DevBuf<int32_t> hub_of_bkt_;           // hub of every bucket
+    DevBuf<unsigned int> hub_spill_;       // per hub: a bucket went to the table
+    int64_t hub_buckets_ = 0;
     int64_t pack_count_ = 0, pack_blocks_ = 0;
     int64_t bstart_[NBUCKET + 1] = {0};
     int64_t bucket_nnz_[NBUCKET] = {0};
