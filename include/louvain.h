@@ -39,6 +39,11 @@
  *     holds k > 0 when a context is created, the k-th device allocation
  *     request of that context fails once with LOUVAIN_ENOMEM (tests of
  *     the error paths).
+ *   - LOUVAIN_LOG=1 prints one line per level (and per contraction) on
+ *     stderr.  LOUVAIN_HUB_BUCKET_SHRINK=s (1..4096) makes the hub buckets
+ *     of levels with 2W >= 2^31 s times smaller, so that tests reach their
+ *     spills to the hub tables.  Both are read once per process and change
+ *     no result.
  */
 #ifndef LOUVAIN_H
 #define LOUVAIN_H
