@@ -745,9 +745,9 @@ struct HubMeta {
 // whose pairs overflow its region or its LDS table: all that bucket's pairs
 // then go to the table (the spill flag makes the scan read it), so a label
 // is never split between a bucket and the table.
-constexpr int kBktPairs = 2048;                 // a hub has one bucket per kBktPairs entries
-constexpr int kBktMax = 256;                    // buckets of a hub at most
-constexpr int kBktBits = 12;                    // bucket table: 4,096 word-keyed slots (64 KB)
+constexpr int kBktPairs = 1024;                 // a hub has one bucket per kBktPairs entries
+constexpr int kBktMax = 512;                    // buckets of a hub at most
+constexpr int kBktBits = 11;                    // bucket table: 2,048 word-keyed slots (32 KB)
 constexpr int kBktClaim = 3 * (1 << kBktBits) / 4;
 
 __device__ __forceinline__ int64_t bkt_count(int64_t d) {
