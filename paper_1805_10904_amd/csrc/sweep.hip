@@ -745,24 +745,6 @@ struct HubMeta {
 // whose pairs overflow its region or its LDS table: all that bucket's pairs
 // then go to the table (the spill flag makes the scan read it), so a label
 // is never split between a bucket and the table.
-constexpr int kBktPairs = 1024;                 // a hub has one bucket per kBktPairs entries
-constexpr int kBktMax = 512;                    // buckets of a hub at most
-constexpr int kBktBits = 11;                    // bucket table: 2,048 word-keyed slots (32 KB)
-constexpr int kBktClaim = 3 * (1 << kBktBits) / 4;
-
-__device__ __forceinline__ int64_t bkt_count(int64_t d) {
-    const int64_t P = (d + kBktPairs - 1) / kBktPairs;
-    return P <= kBktMax ? P : 0;
-}
-// Pair slots of each bucket of a hub of d entries in P buckets: twice the
-// mean (divided by the test shrink factor).
-__device__ __forceinline__ int64_t bkt_cap(int64_t d, int64_t P, int shrink) {
-    const int64_t c = 2 * ((d + P - 1) / P) / shrink;
-    return c > 0 ? c : 1;
-}
-__device__ __forceinline__ int64_t bkt_of(int32_t label, int64_t P) {
-    return (int64_t)(((uint64_t)((uint32_t)label * 0x85EBCA6Bu) * (uint64_t)P) >> 32);
-}
 
 constexpr int kHubLdsBits = 11;  // 2048 slots for a chunk of kHubChunk = 1024 entries
 
@@ -1549,29 +1531,28 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
             *tab_size = scan_off + (hubs_ + 1);
     int64_t *bkt_off = tab_size + (hubs_ + 1), *reg_off = bkt_off + (hubs_ + 1);
     const int32_t *hubv = list_.p + bstart_[B_HUB];
-    // general levels with published words and single-word tables sweep their hubs by buckets
-    const int bucketed = !compact_ && publishes(g) && word_shift(g.n, g.tw) > 0 ? 1 : 0;
+    // hubs are summed by buckets on compact levels and on general levels with
+    // published words and single-word tables
+    const int bucketed = compact_ || (publishes(g) && word_shift(g.n, g.tw) > 0) ? 1 : 0;
     k_hub_sizes<<<grid_for(hubs_, 256), 256, 0, s_>>>(g.row_ptr, hubv, hubs_, tab_off, chunk_off, scan_off, tab_size,
                                                       bkt_off, reg_off, bucketed, hub_bucket_shrink());
     LV_LAUNCHED("k_hub_sizes");
     scan_exclusive<int64_t, int64_t>(tab_off, tab_off, hubs_, tab_off + hubs_, s_, t_);
     scan_exclusive<int64_t, int64_t>(chunk_off, chunk_off, hubs_, chunk_off + hubs_, s_, t_);
     scan_exclusive<int64_t, int64_t>(scan_off, scan_off, hubs_, scan_off + hubs_, s_, t_);
-    if (!compact_) {
-        scan_exclusive<int64_t, int64_t>(bkt_off, bkt_off, hubs_, bkt_off + hubs_, s_, t_);
-        scan_exclusive<int64_t, int64_t>(reg_off, reg_off, hubs_, reg_off + hubs_, s_, t_);
-    }
+    scan_exclusive<int64_t, int64_t>(bkt_off, bkt_off, hubs_, bkt_off + hubs_, s_, t_);
+    scan_exclusive<int64_t, int64_t>(reg_off, reg_off, hubs_, reg_off + hubs_, s_, t_);
     const int64_t *tot[3] = {rb.add(tab_off + hubs_), rb.add(chunk_off + hubs_), rb.add(scan_off + hubs_)};
-    const int64_t *btot[2] = {compact_ ? nullptr : rb.add(bkt_off + hubs_), compact_ ? nullptr : rb.add(reg_off + hubs_)};
+    const int64_t *btot[2] = {rb.add(bkt_off + hubs_), rb.add(reg_off + hubs_)};
     rb.fetch();
     hub_slots_ = *tot[0];
     hub_chunks_ = *tot[1];
     hub_scans_ = *tot[2];
-    hub_buckets_ = btot[0] ? *btot[0] : 0;
+    hub_buckets_ = *btot[0];
     if (hub_buckets_ > 0) {
         const int64_t pairs = *btot[1];
         bkt_key_.reserve((size_t)pairs);
-        bkt_val_.reserve((size_t)pairs);
+        if (!compact_) bkt_val_.reserve((size_t)pairs);   // compact pairs are single words
         bkt_cur_.reserve((size_t)hub_buckets_);
         bkt_part_.reserve((size_t)(4 * hub_buckets_));
         hub_of_bkt_.reserve((size_t)hub_buckets_);
@@ -1579,10 +1560,8 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
         k_hub_map<<<(unsigned)hubs_, 256, 0, s_>>>(bkt_off, hubs_, hub_of_bkt_.p);
         LV_LAUNCHED("k_hub_map");
     }
-    if (!compact_) {
-        hub_spill_.reserve((size_t)hubs_);
-        fill<int32_t>((int32_t *)hub_spill_.p, 0, hubs_, s_);
-    }
+    hub_spill_.reserve((size_t)hubs_);
+    fill<int32_t>((int32_t *)hub_spill_.p, 0, hubs_, s_);
     if (hub_slots_ > hub_slot_cap_) {
         hub_key_.alloc((size_t)hub_slots_);
         hub_val_.alloc((size_t)hub_slots_);
@@ -1949,6 +1928,15 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
         cp.hval = hub_val_.p;
         cp.hloop = hub_loop_.p;
         cp.hpart = hub_part_.p;
+        cp.hub_buckets = hub_buckets_;
+        cp.bkt_off = hub_meta_.p + 4 * (hubs_ + 1);
+        cp.reg_off = hub_meta_.p + 5 * (hubs_ + 1);
+        cp.bkt_hub = hub_of_bkt_.p;
+        cp.shrink = hub_bucket_shrink();
+        cp.bkey = (unsigned long long *)bkt_key_.p;
+        cp.bcur = bkt_cur_.p;
+        cp.bpart = bkt_part_.p;
+        cp.spill = hub_spill_.p;
         CompactState cs;
         cs.c_cur = c_[cur].p;
         cs.c_nxt = c_[nxt].p;

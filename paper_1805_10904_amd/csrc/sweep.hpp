@@ -109,6 +109,14 @@ struct CompactPass {
     int32_t *hkey = nullptr;
     unsigned long long *hval = nullptr, *hloop = nullptr;
     uint64_t *hpart = nullptr;
+    // hub buckets (see the general levels): offsets, regions, cursors, partials, spill flags
+    int64_t hub_buckets = 0;
+    const int64_t *bkt_off = nullptr, *reg_off = nullptr;
+    const int32_t *bkt_hub = nullptr;
+    int shrink = 1;
+    unsigned long long *bkey = nullptr;
+    unsigned int *bcur = nullptr, *spill = nullptr;
+    uint64_t *bpart = nullptr;
 };
 
 struct SweepParams {
@@ -138,6 +146,29 @@ struct CompactState {
 // levels; on general levels kBucketMax[B_WIDE] when labels and weights fit a
 // single 64-bit table word, else kBucketMax[B_BLOCK].
 int64_t lds_row_max(int64_t n, int64_t tw, const Tuning &tn);
+
+// Hub buckets (both level kinds): a hub of d entries has one bucket per
+// kBktPairs entries (at most kBktMax; longer rows keep their HBM table
+// only), each with a region of twice the mean pairs and a
+// 2^kBktBits-slot LDS table of which kBktClaim slots may be claimed.
+constexpr int kBktPairs = 1024;                 // a hub has one bucket per kBktPairs entries
+constexpr int kBktMax = 512;                    // buckets of a hub at most
+constexpr int kBktBits = 11;                    // bucket table: 2,048 word-keyed slots (32 KB)
+constexpr int kBktClaim = 3 * (1 << kBktBits) / 4;
+
+__device__ __forceinline__ int64_t bkt_count(int64_t d) {
+    const int64_t P = (d + kBktPairs - 1) / kBktPairs;
+    return P <= kBktMax ? P : 0;
+}
+// Pair slots of each bucket of a hub of d entries in P buckets: twice the
+// mean (divided by the test shrink factor).
+__device__ __forceinline__ int64_t bkt_cap(int64_t d, int64_t P, int shrink) {
+    const int64_t c = 2 * ((d + P - 1) / P) / shrink;
+    return c > 0 ? c : 1;
+}
+__device__ __forceinline__ int64_t bkt_of(int32_t label, int64_t P) {
+    return (int64_t)(((uint64_t)((uint32_t)label * 0x85EBCA6Bu) * (uint64_t)P) >> 32);
+}
 
 // Levels whose graphs all have TW < 2^31 run on packed community words
 // (sweep_compact.hip).

@@ -1378,6 +1378,13 @@ struct CHub {
     const int64_t *tab_off, *chunk_off, *scan_off, *tab_size;
     const int32_t *chunk_hub, *scan_hub;
     int64_t hubs;
+    const int64_t *bkt_off, *reg_off;   // first bucket and first pair slot of each hub (no buckets: table only)
+    const int32_t *bkt_hub;             // hub of each bucket
+    int shrink;                         // bucket sizes divided by this (1; more only to test the spills)
+    unsigned long long *bkey;           // bucket regions: table words (label + 1) << 32 | e
+    unsigned int *bcur;                 // words appended to each bucket
+    uint64_t *bpart;                    // per bucket: a partial as the scan's
+    unsigned int *spill;                // per hub: a bucket went to the table
 };
 
 constexpr int kCHubLdsBits = 11;
@@ -1433,6 +1440,7 @@ __global__ __launch_bounds__(256) void k_cpt_hub_accum(CArgs a, CHub hm, unsigne
     if (single_done(a.gid, a.st)) return;
     constexpr int T = 1 << kCHubLdsBits;
     __shared__ unsigned long long s_tab[T];
+    __shared__ unsigned int s_cnt[kBktMax], s_base[kBktMax];
     __shared__ unsigned long long r_ok[4];
     __shared__ uint32_t r_lf[4];
     __shared__ int64_t s_h;
@@ -1512,11 +1520,175 @@ __global__ __launch_bounds__(256) void k_cpt_hub_accum(CArgs a, CHub hm, unsigne
     }
     __syncthreads();
     const int64_t base = hm.tab_off[h], size = hm.tab_size[h];
-    for (int x = t; x < T; x += 256) {
-        const unsigned long long wd = s_tab[x];
-        if (wd == 0) continue;
-        const int32_t l = (int32_t)(wd >> 32) - 1;
-        word_insert_hbm(gtab + base, (uint64_t)size, hash_range(l, (uint64_t)size), l, (uint32_t)wd);
+    const int64_t b0 = hm.bkt_off[h], P = hm.bkt_off[h + 1] - b0;
+    if (P == 0) {   // the hub's table
+        for (int x = t; x < T; x += 256) {
+            const unsigned long long wd = s_tab[x];
+            if (wd == 0) continue;
+            const int32_t l = (int32_t)(wd >> 32) - 1;
+            word_insert_hbm(gtab + base, (uint64_t)size, hash_range(l, (uint64_t)size), l, (uint32_t)wd);
+        }
+        return;
+    }
+    // buckets: every distinct label's rank among the workgroup's labels of
+    // its bucket, then one cursor add per bucket (as on the general levels)
+    for (int b = t; b < P; b += 256) s_cnt[b] = 0;
+    __syncthreads();
+    constexpr int Q = T / 256;
+    int32_t bq[Q];
+    uint32_t rq[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const unsigned long long wd = s_tab[t + q * 256];
+        bq[q] = -1;
+        rq[q] = 0;
+        if (wd != 0) {
+            bq[q] = (int32_t)bkt_of((int32_t)(wd >> 32) - 1, P);
+            rq[q] = atomicAdd(&s_cnt[bq[q]], 1u);
+        }
+    }
+    __syncthreads();
+    for (int b = t; b < P; b += 256) s_base[b] = s_cnt[b] ? atomicAdd(&hm.bcur[b0 + b], s_cnt[b]) : 0u;
+    __syncthreads();
+    const int64_t cap = bkt_cap(row_end - a.row_ptr[v], P, hm.shrink);
+    bool over = false;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        if (bq[q] < 0) continue;
+        const unsigned long long wd = s_tab[t + q * 256];
+        const int64_t pos = (int64_t)s_base[bq[q]] + rq[q];
+        if (pos < cap) {
+            hm.bkey[hm.reg_off[h] + (int64_t)bq[q] * cap + pos] = wd;
+        } else {   // the bucket's region is full: the bucket goes to the table
+            const int32_t l = (int32_t)(wd >> 32) - 1;
+            word_insert_hbm(gtab + base, (uint64_t)size, hash_range(l, (uint64_t)size), l, (uint32_t)wd);
+            over = true;
+        }
+    }
+    if (over) hm.spill[h] = 1u;
+}
+
+// One workgroup per bucket of a hub: sum its words in LDS and score them
+// (a partial in the scan's format), or, when its words overflowed its
+// region or its table, add all of them to the hub's table instead.  Leaves
+// the bucket's cursor at 0.
+__global__ __launch_bounds__(256) void k_cpt_hub_bucket(CArgs a, CHub hm, unsigned long long *gtab) {
+    if (single_done(a.gid, a.st)) return;
+    constexpr int T = 1 << kBktBits;
+    __shared__ unsigned long long s_tab[T];
+    __shared__ unsigned long long r_ok[4];
+    __shared__ uint32_t r_lf[4], r_e[4];
+    __shared__ int64_t s_h;
+    __shared__ unsigned int s_n;
+    __shared__ int s_used, s_over;
+    const int t = threadIdx.x;
+    const int64_t bk = blockIdx.x;
+    if (t == 0) {
+        s_h = hm.bkt_hub[bk];
+        s_n = hm.bcur[bk];
+        s_used = 0;
+        s_over = 0;
+    }
+    for (int x = t; x < T; x += 256) s_tab[x] = 0;
+    __syncthreads();
+    const int64_t h = s_h;
+    const int32_t v = hm.v[h];
+    const int g = graph_of(a.gid, v);
+    const bool live = !a.st[g].done;   // uniform over the workgroup
+    const int64_t b0 = hm.bkt_off[h], P = hm.bkt_off[h + 1] - b0;
+    const int64_t cap = bkt_cap(a.row_ptr[v + 1] - a.row_ptr[v], P, hm.shrink);
+    const int claim = kBktClaim / hm.shrink > 0 ? kBktClaim / hm.shrink : 1;
+    const int64_t reg = hm.reg_off[h] + (bk - b0) * cap;
+    const int64_t n = live ? (int64_t)s_n : 0;
+    bool spill_all = n > cap;
+    if (!spill_all) {
+        bool over = false;
+        for (int64_t i = t; i < n; i += 256) {
+            const unsigned long long wd = hm.bkey[reg + i];
+            const unsigned long long tag = wd & kTagMask;
+            const uint32_t e = (uint32_t)wd;
+            uint32_t x = ((uint32_t)((wd >> 32) - 1) * 0x9E3779B1u) >> (32 - kBktBits);
+            while (true) {
+                const unsigned long long cur = s_tab[x];
+                if ((cur & kTagMask) == tag) {
+                    atomicAdd(&s_tab[x], (unsigned long long)e);
+                    break;
+                }
+                if (cur == 0) {
+                    if (s_used >= claim) {
+                        over = true;
+                        break;
+                    }
+                    const unsigned long long prev = atomicCAS(&s_tab[x], 0ull, wd);
+                    if (prev == 0) {
+                        atomicAdd(&s_used, 1);
+                        break;
+                    }
+                    if ((prev & kTagMask) == tag) {
+                        atomicAdd(&s_tab[x], (unsigned long long)e);
+                        break;
+                    }
+                }
+                x = (x + 1) & (T - 1);
+            }
+        }
+        if (over) s_over = 1;
+        __syncthreads();
+        spill_all = s_over != 0;
+    }
+    unsigned long long bok = 0;
+    uint32_t blf = 0xffffffffu;
+    uint32_t e_own = 0;
+    if (spill_all) {
+        const int64_t m = n < cap ? n : cap;
+        const int64_t base = hm.tab_off[h], size = hm.tab_size[h];
+        for (int64_t i = t; i < m; i += 256) {
+            const unsigned long long wd = hm.bkey[reg + i];
+            const int32_t l = (int32_t)(wd >> 32) - 1;
+            word_insert_hbm(gtab + base, (uint64_t)size, hash_range(l, (uint64_t)size), l, (uint32_t)wd);
+        }
+        if (t == 0) hm.spill[h] = 1u;
+    } else if (live) {
+        const int32_t ci = vw_label(a.vw[v]);
+        // TW, delta_i, deg_C and e_{i->C} are below 2^31: 32-bit operands
+        const uint32_t di = (uint32_t)a.delta[v];
+        const uint32_t tw = (uint32_t)a.tw[g];
+        for (int x = t; x < T; x += 256) {
+            const unsigned long long wd = s_tab[x];
+            if (wd == 0) continue;
+            const int32_t k = (int32_t)(wd >> 32) - 1;
+            const uint32_t e = (uint32_t)wd;
+            if (k == ci) {
+                e_own += e;
+                continue;
+            }
+            const uint64_t dsk = a.ds[k];
+            const unsigned long long ok = ((uint64_t)tw * e - (uint64_t)di * (uint32_t)dsk) ^ 0x8000000000000000ull;
+            const uint32_t lf = ((uint32_t)k << 1) | ((dsk >> 32) == 1 ? 1u : 0u);
+            best_take(bok, blf, (uint32_t)ok, (uint32_t)(ok >> 32), lf);
+        }
+    }
+    group_best(bok, blf, 64);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) e_own += __shfl_xor(e_own, off);
+    const int lane = t & 63, wid = t >> 6;
+    if (lane == 0) {
+        r_ok[wid] = bok;
+        r_lf[wid] = blf;
+        r_e[wid] = e_own;
+    }
+    __syncthreads();
+    if (t == 0) {
+        for (int w = 1; w < 4; ++w) {
+            best_take(bok, blf, (uint32_t)r_ok[w], (uint32_t)(r_ok[w] >> 32), r_lf[w]);
+            e_own += r_e[w];
+        }
+        uint64_t *p = hm.bpart + 4 * bk;
+        p[0] = bok;
+        p[1] = (uint64_t)(blf >> 1) | ((uint64_t)(blf & 1u) << 32);
+        p[2] = e_own;
+        p[3] = 0;
+        hm.bcur[bk] = 0u;
     }
 }
 
@@ -1526,11 +1698,24 @@ __global__ __launch_bounds__(256) void k_cpt_hub_accum(CArgs a, CHub hm, unsigne
 __global__ __launch_bounds__(256) void k_cpt_hub_scan(CArgs a, CHub hm, unsigned long long *gtab, uint64_t *part) {
     if (single_done(a.gid, a.st)) return;
     __shared__ int64_t s_h;
+    __shared__ int s_skip;
     __shared__ unsigned long long r_ok[4];
     __shared__ uint32_t r_lf[4], r_e[4];
     const int t = threadIdx.x;
-    if (t == 0) s_h = hm.scan_hub[blockIdx.x];
+    if (t == 0) {
+        s_h = hm.scan_hub[blockIdx.x];
+        // a hub summed in buckets has nothing in its table unless one spilled
+        s_skip = hm.bkt_off[s_h + 1] > hm.bkt_off[s_h] && hm.spill[s_h] == 0u;
+        if (s_skip) {
+            uint64_t *p = part + 4 * (int64_t)blockIdx.x;
+            p[0] = 0;
+            p[1] = (uint64_t)(0xffffffffu >> 1) | (1ull << 32);
+            p[2] = 0;
+            p[3] = 0;
+        }
+    }
     __syncthreads();
+    if (s_skip) return;
     const int64_t h = s_h;
     const int32_t v = hm.v[h];
     const int g = graph_of(a.gid, v);
@@ -1598,8 +1783,7 @@ __global__ __launch_bounds__(256) void k_cpt_hub_decide(CArgs a, CHub hm, const 
     // partials: one per scan workgroup, or one per chunk on the first pass
     // from singletons
     const int64_t *range = a.first ? hm.chunk_off : hm.scan_off;
-    for (int64_t b = range[h] + lane; b < range[h + 1]; b += 64) {
-        const uint64_t *p = part + 4 * b;
+    auto take = [&](const uint64_t *p) {
         const unsigned long long ok = p[0];
         const int32_t l = (int32_t)(uint32_t)p[1];
         if (ok > bok || (ok == bok && l < bl)) {
@@ -1608,7 +1792,10 @@ __global__ __launch_bounds__(256) void k_cpt_hub_decide(CArgs a, CHub hm, const 
             bf = (int32_t)(p[1] >> 32);
         }
         e_own += p[2];
-    }
+    };
+    for (int64_t b = range[h] + lane; b < range[h + 1]; b += 64) take(part + 4 * b);
+    if (!a.first)   // and the buckets' partials
+        for (int64_t b = hm.bkt_off[h] + lane; b < hm.bkt_off[h + 1]; b += 64) take(hm.bpart + 4 * b);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         const unsigned long long ook = __shfl_xor(bok, off);
@@ -1622,6 +1809,7 @@ __global__ __launch_bounds__(256) void k_cpt_hub_decide(CArgs a, CHub hm, const 
         e_own += __shfl_xor(e_own, off);
     }
     if (lane == 0) {
+        hm.spill[h] = 0u;
         const uint64_t own = a.vw[v];
         const int32_t ci = vw_label(own);
         const int64_t di = a.delta[v];
@@ -1807,11 +1995,18 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
     }
     if (cp.hubs > 0) {
         CHub hm{cp.list + cp.bstart[B_HUB], cp.tab_off, cp.chunk_off, cp.scan_off, cp.tab_size,
-                cp.chunk_hub, cp.scan_hub, cp.hubs};
+                cp.chunk_hub, cp.scan_hub, cp.hubs, cp.bkt_off, cp.reg_off, cp.bkt_hub, cp.shrink, cp.bkey,
+                cp.bcur, cp.bpart, cp.spill};
         {
             TimedLaunch tl(t, TG_SWEEP, "k_cpt_hub_accum<", (double)cp.bnnz[B_HUB] * eb, sfx.c_str());
             tl.launch(k_cpt_hub_accum<W>, (unsigned)cp.hub_chunks, 256, 0, s2, a, hm, cp.hval, cp.hloop, cp.hpart);
             LV_LAUNCHED("k_cpt_hub_accum");
+        }
+        if (!a.first && cp.hub_buckets > 0) {
+            // per word appended (at most one per hub entry): read
+            TimedLaunch tl(t, TG_SWEEP, "k_cpt_hub_bucket", (double)cp.bnnz[B_HUB] * 8.0);
+            tl.launch(k_cpt_hub_bucket, (unsigned)cp.hub_buckets, 256, 0, s2, a, hm, cp.hval);
+            LV_LAUNCHED("k_cpt_hub_bucket");
         }
         if (!a.first) {
             TimedLaunch tl(t, TG_SWEEP, "k_cpt_hub_scan", (double)cp.hub_scans * kHubScan * 16.0);

@@ -283,32 +283,35 @@ def test_heavy_hubs(ctx, scale):
 
 
 @pytest.mark.parametrize("shrink", [8, 64])
-def test_heavy_hub_bucket_spills(shrink):
-    """On levels with 2W >= 2^31 and published words, hubs are summed in
-    buckets; LOUVAIN_HUB_BUCKET_SHRINK (read once per process, so in a child
-    process) makes the bucket regions and tables that many times smaller, so
-    buckets overflow their region (pairs appended past it) and their table
-    (more distinct labels than it may claim) and spill to the hub table.  The
-    results equal the oracle's."""
+def test_hub_bucket_spills(shrink):
+    """Hubs are summed in buckets (compact levels, and levels with 2W >=
+    2^31 and published words); LOUVAIN_HUB_BUCKET_SHRINK (read once per
+    process, so in a child process) makes the bucket regions and tables that
+    many times smaller, so buckets overflow their region (pairs appended past
+    it) and their table (more distinct labels than it may claim) and spill to
+    the hub table.  The results equal the oracle's, with the hub graph's own
+    weights (compact levels) and with weights x 2^26."""
     import os
     import subprocess
     here = os.path.dirname(os.path.abspath(__file__))
     code = ("import sys; sys.path.insert(0, %r); sys.path.insert(0, %r)\n"
             "import numpy as np, oracle, paper_1805_10904_amd as L\n"
             "from test_gpu_parity import hub_graph\n"
-            "g = hub_graph(seed=11); w = g.w.astype(np.int64) << 26\n"
-            "ctx = L.Context(0); G = ctx.graph_create(g.row_ptr, g.col, w)\n"
-            "r = ctx.run(G); ref = oracle.louvain(g.row_ptr, g.col, w)\n"
-            "assert np.array_equal(r.labels, ref.labels) and r.q_int == ref.q_int, 'run'\n"
-            "assert [lv['q_int'] for lv in r.stats['levels']] == [lv['q_int'] for lv in ref.levels], 'levels'\n"
-            "lm = ctx.local_move(G, None); rl = oracle.local_move(g.row_ptr, g.col, w, None)\n"
-            "assert np.array_equal(lm[0], rl.labels) and np.array_equal(lm[2], rl.e_own), 'local move'\n"
-            "lab = r.labels.astype(np.int32)\n"
-            "lm = ctx.local_move(G, lab); rl = oracle.local_move(g.row_ptr, g.col, w, lab)\n"
-            "assert np.array_equal(lm[0], rl.labels) and np.array_equal(lm[2], rl.e_own), 'from labels'\n"
+            "g = hub_graph(seed=11); ctx = L.Context(0)\n"
+            "for w in (g.w, g.w.astype(np.int64) << 26):\n"
+            "  G = ctx.graph_create(g.row_ptr, g.col, w)\n"
+            "  r = ctx.run(G); ref = oracle.louvain(g.row_ptr, g.col, w)\n"
+            "  assert np.array_equal(r.labels, ref.labels) and r.q_int == ref.q_int, 'run'\n"
+            "  assert [lv['q_int'] for lv in r.stats['levels']] == [lv['q_int'] for lv in ref.levels], 'levels'\n"
+            "  lm = ctx.local_move(G, None); rl = oracle.local_move(g.row_ptr, g.col, w, None)\n"
+            "  assert np.array_equal(lm[0], rl.labels) and np.array_equal(lm[2], rl.e_own), 'local move'\n"
+            "  lab = r.labels.astype(np.int32)\n"
+            "  lm = ctx.local_move(G, lab); rl = oracle.local_move(g.row_ptr, g.col, w, lab)\n"
+            "  assert np.array_equal(lm[0], rl.labels) and np.array_equal(lm[2], rl.e_own), 'from labels'\n"
+            "  G.destroy()\n"
             "print('ok')\n") % (os.path.dirname(here), here)
     env = dict(os.environ, LOUVAIN_HUB_BUCKET_SHRINK=str(shrink))
-    _say(f"hub graph, weights x 2^26, bucket shrink {shrink} (child process)")
+    _say(f"hub graph, own weights and x 2^26, bucket shrink {shrink} (child process)")
     p = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=240)
     assert p.returncode == 0, p.stderr[-3000:]
     assert p.stdout.strip().endswith("ok")
