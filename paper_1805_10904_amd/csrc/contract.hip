@@ -478,10 +478,15 @@ __device__ __forceinline__ int64_t chunk_start(const int64_t *__restrict__ off, 
 // Shared first half of the chunk kernels: the chunk's first and last
 // segment (slo, shi), the local segment of every entry (s_mark) and the sum
 // of every (local segment, column) pair in the LDS hash table s_hk / s_hv.
-__device__ __forceinline__ void chunk_aggregate(const int64_t *__restrict__ off, int64_t k, int64_t cb, int len,
+// Chunks cut the space of coff (segment starts of the entries the chunks
+// aggregate: off itself, or the short segments' entries only, where every
+// other segment is empty); entry x of a chunk is then entry
+// off[sg] + (cb + x - coff[sg]) of the grouped arrays.
+__device__ __forceinline__ void chunk_aggregate(const int64_t *__restrict__ coff, const int64_t *__restrict__ off,
+                                                int64_t k, int64_t cb, int len,
                                                 const int32_t *__restrict__ tcol, const int64_t *__restrict__ tw,
                                                 unsigned long long *s_hk, long long *s_hv, int32_t *s_mark,
-                                                int32_t *s_wave, int64_t *s_range, bool skip_big) {
+                                                int32_t *s_wave, int64_t *s_range) {
     constexpr int T = 1 << kChunkBits;
     constexpr uint32_t mask = T - 1;
     const int t = threadIdx.x;
@@ -491,8 +496,8 @@ __device__ __forceinline__ void chunk_aggregate(const int64_t *__restrict__ off,
     }
     for (int x = t; x < kChunkLen; x += 256) s_mark[x] = -1;
     if (t < 64) {   // segments of the chunk's first and last entry (64-way search)
-        const int64_t a0 = wave_find_le(off, k, cb);
-        const int64_t a1 = wave_find_le(off, k, cb + len - 1);
+        const int64_t a0 = wave_find_le(coff, k, cb);
+        const int64_t a1 = wave_find_le(coff, k, cb + len - 1);
         if (t == 0) {
             s_range[0] = a0;
             s_range[1] = a1;
@@ -502,7 +507,7 @@ __device__ __forceinline__ void chunk_aggregate(const int64_t *__restrict__ off,
     const int64_t slo = s_range[0], shi = s_range[1];
     if (shi - slo <= kChunkLen) {
         // segment of every entry: markers at segment starts, then a max-scan
-        for (int64_t sg = slo + 1 + t; sg <= shi; sg += 256) atomicMax(&s_mark[off[sg] - cb], (int32_t)(sg - slo));
+        for (int64_t sg = slo + 1 + t; sg <= shi; sg += 256) atomicMax(&s_mark[coff[sg] - cb], (int32_t)(sg - slo));
         if (t == 0) s_mark[0] = 0;   // markers never land on position 0
         __syncthreads();
         block_max_scan_chunk(s_mark, s_wave);
@@ -513,20 +518,17 @@ __device__ __forceinline__ void chunk_aggregate(const int64_t *__restrict__ off,
             int64_t lo = slo, hi = shi;
             while (lo < hi) {
                 const int64_t mid = (lo + hi + 1) >> 1;
-                if (off[mid] <= cb + x) lo = mid; else hi = mid - 1;
+                if (coff[mid] <= cb + x) lo = mid; else hi = mid - 1;
             }
             s_mark[x] = (int32_t)(lo - slo);
         }
         __syncthreads();
     }
-    // with skip_big, entries of segments longer than kChunkSeg are left to
-    // the middle tier and the pieces (such a segment can lie anywhere in a
-    // chunk, not only first or last)
     for (int x = t; x < len; x += 256) {
         const int32_t ls = s_mark[x];
-        if (skip_big && off[slo + ls + 1] - off[slo + ls] > kChunkSeg) continue;
-        const unsigned long long key = ((unsigned long long)(uint32_t)ls << 32) | (uint32_t)tcol[cb + x];
-        const long long val = (long long)tw[cb + x];
+        const int64_t e = off[slo + ls] + (cb + x - coff[slo + ls]);
+        const unsigned long long key = ((unsigned long long)(uint32_t)ls << 32) | (uint32_t)tcol[e];
+        const long long val = (long long)tw[e];
         uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - kChunkBits));
         while (true) {
             const unsigned long long prev = atomicCAS(&s_hk[h], kNoKey, key);   // claims, or returns the key
@@ -542,9 +544,10 @@ __device__ __forceinline__ void chunk_aggregate(const int64_t *__restrict__ off,
 // method (sweeps and contraction depend on each row's multiset of columns
 // and weights only), so distinct pairs are placed in table order, each
 // segment's through its own LDS counter, without sorting.
-__global__ __launch_bounds__(256) void k_seg_chunk_any(const int64_t *__restrict__ off, int64_t k, int64_t m_raw,
-                                                       int32_t *tcol, int64_t *tw, int64_t *mcount, uint64_t *pkey,
-                                                       int64_t *pval, unsigned long long *pcount, int bits) {
+__global__ __launch_bounds__(256) void k_seg_chunk_any(const int64_t *__restrict__ coff, const int64_t *__restrict__ off,
+                                                       int64_t k, int64_t m_raw, int32_t *tcol, int64_t *tw,
+                                                       int64_t *mcount, uint64_t *pkey, int64_t *pval,
+                                                       unsigned long long *pcount, int bits) {
     constexpr int T = 1 << kChunkBits;
     __shared__ unsigned long long s_hk[T];
     __shared__ long long s_hv[T];
@@ -557,8 +560,8 @@ __global__ __launch_bounds__(256) void k_seg_chunk_any(const int64_t *__restrict
     __shared__ unsigned long long s_pbase;
     const int t = threadIdx.x;
     if (t < 64) {
-        const int64_t b0 = chunk_start(off, k, m_raw, blockIdx.x);
-        const int64_t b1 = chunk_start(off, k, m_raw, (int64_t)blockIdx.x + 1);
+        const int64_t b0 = chunk_start(coff, k, m_raw, blockIdx.x);
+        const int64_t b1 = chunk_start(coff, k, m_raw, (int64_t)blockIdx.x + 1);
         if (t == 0) {
             s_bounds[0] = b0;
             s_bounds[1] = b1;
@@ -572,20 +575,20 @@ __global__ __launch_bounds__(256) void k_seg_chunk_any(const int64_t *__restrict
     const int64_t cb = s_bounds[0], ce = s_bounds[1];
     const int len = (int)(ce - cb);
     if (len <= 0) return;   // uniform: every segment around here was taken by a neighbour
-    chunk_aggregate(off, k, cb, len, tcol, tw, s_hk, s_hv, s_mark, s_wave, s_range, true);
+    chunk_aggregate(coff, off, k, cb, len, tcol, tw, s_hk, s_hv, s_mark, s_wave, s_range);
     const int64_t slo = s_range[0], shi = s_range[1];
-    const bool first_spans = off[slo] < cb;
-    const bool last_spans = off[shi + 1] > ce;
+    const bool first_spans = coff[slo] < cb;
+    const bool last_spans = coff[shi + 1] > ce;
     const uint32_t last_local = (uint32_t)(shi - slo);
     for (int x = t; x < T; x += 256) {
         const unsigned long long key = s_hk[x];
         if (key == kNoKey) continue;
         const uint32_t ls = (uint32_t)(key >> 32);
-        const int p = ls == 0 ? 0 : (int)(off[slo + ls] - cb);
+        const int p = ls == 0 ? 0 : (int)(coff[slo + ls] - cb);
         atomicAdd(&s_cnt[p], 1);
     }
     __syncthreads();
-    const int p_last = last_local == 0 ? 0 : (int)(off[shi] - cb);
+    const int p_last = last_local == 0 ? 0 : (int)(coff[shi] - cb);
     if (t == 0) {
         int np = 0;
         if (last_local == 0) {
@@ -604,7 +607,7 @@ __global__ __launch_bounds__(256) void k_seg_chunk_any(const int64_t *__restrict
         if (key == kNoKey) continue;
         const uint32_t ls = (uint32_t)(key >> 32);
         const int64_t sg = slo + ls;
-        const int p = ls == 0 ? 0 : (int)(off[sg] - cb);
+        const int p = ls == 0 ? 0 : (int)(coff[sg] - cb);
         const int pos = atomicAdd(&s_cur[p], 1);
         const int32_t c = (int32_t)(uint32_t)key;
         const long long val = s_hv[x];
@@ -651,17 +654,20 @@ constexpr int kMidMax = 2730;
 constexpr int kMidBits = 12;
 constexpr int kMidThreads = 256;
 
-// Pieces of every segment longer than kMidMax (0 otherwise), and a flag for
-// every segment of kChunkSeg + 1 .. kMidMax entries; tot[0] / tot[1]
-// receive their entry counts.
+// Pieces of every segment longer than kMidMax (0 otherwise), a flag for
+// every segment of kChunkSeg + 1 .. kMidMax entries, and the entries of
+// every segment the chunks aggregate (0 for the others); tot[0] / tot[1]
+// receive the entry counts of the first two kinds.
 __global__ __launch_bounds__(256) void k_big_pieces(const int64_t *__restrict__ off, int64_t k, int64_t *pieces,
-                                                    int64_t *mids, unsigned long long *tot, int64_t piece) {
+                                                    int64_t *mids, int64_t *shorts, unsigned long long *tot,
+                                                    int64_t piece) {
     __shared__ unsigned long long s_tot[4][2];
     unsigned long long big = 0, mid = 0;
     for (int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x; a < k; a += (int64_t)gridDim.x * 256) {
         const int64_t sz = off[a + 1] - off[a];
         pieces[a] = sz > kMidMax ? (sz + piece - 1) / piece : 0;
         mids[a] = sz > kChunkSeg && sz <= kMidMax ? 1 : 0;
+        shorts[a] = sz <= kChunkSeg ? sz : 0;
         if (sz > kMidMax) big += (unsigned long long)sz;
         else if (sz > kChunkSeg) mid += (unsigned long long)sz;
     }
@@ -959,7 +965,7 @@ __global__ __launch_bounds__(256) void k_seg_chunk(const int64_t *__restrict__ o
     const int64_t cb = s_bounds[0], ce = s_bounds[1];
     const int len = (int)(ce - cb);
     if (len <= 0) return;
-    chunk_aggregate(off, k, cb, len, tcol, tw, s_hk, s_hv, s_mark, s_wave, s_range, false);
+    chunk_aggregate(off, off, k, cb, len, tcol, tw, s_hk, s_hv, s_mark, s_wave, s_range);
     const int64_t slo = s_range[0], shi = s_range[1];
     {   // compaction of the occupied slots: one LDS atomic per wavefront and round
         const int lane = t & 63;
@@ -1183,10 +1189,11 @@ int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t 
     }
     // unsorted contraction: pieces of the segments longer than kMidMax, and
     // the segments of kChunkSeg + 1 .. kMidMax entries
-    TempBuf pieces(sorted ? 16 : (size_t)(2 * (k + 1) + 2) * sizeof(int64_t), s_);
+    TempBuf pieces(sorted ? 16 : (size_t)(3 * (k + 1) + 2) * sizeof(int64_t), s_);
     int64_t *poff = pieces.as<int64_t>();
     int64_t *moff = poff + (k + 1);
-    unsigned long long *ptot = (unsigned long long *)(moff + (k + 1));
+    int64_t *soff = moff + (k + 1);   // chunk space: the short segments' entries only
+    unsigned long long *ptot = (unsigned long long *)(soff + (k + 1));
     // single-word piece tables when column + 1 and a weight sum (<= 2W) fit 64 bits together
     int pshift = 64 - bits_for(k + 1);
     if (pshift > 62 || (uint64_t)g.tw >= (1ull << pshift)) pshift = 0;
@@ -1195,10 +1202,11 @@ int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t 
         fill<uint64_t>((uint64_t *)ptot, 0, 2, s_);
         TimedLaunch tl(t_, TG_CONTRACT, "k_big_pieces", (double)k * 32);
         const unsigned pb = grid_for(k, 256) < 2048u ? grid_for(k, 256) : 2048u;
-        tl.launch(k_big_pieces, pb, 256, 0, s_, off, k, poff, moff, ptot, piece);
+        tl.launch(k_big_pieces, pb, 256, 0, s_, off, k, poff, moff, soff, ptot, piece);
         LV_LAUNCHED("k_big_pieces");
         scan_exclusive<int64_t, int64_t>(poff, poff, k, poff + k, s_, t_);
         scan_exclusive<int64_t, int64_t>(moff, moff, k, moff + k, s_, t_);
+        scan_exclusive<int64_t, int64_t>(soff, soff, k, soff + k, s_, t_);
     }
     Readback rb(s_);
     const int64_t *mr = rb.add(off + k);
@@ -1229,15 +1237,18 @@ int64_t Contractor::contract(const GraphView &g, const int32_t *newlab, int64_t 
     const int bits = bits_for(k + 1);
     TempBuf pc(sizeof(unsigned long long), s_);
     fill<uint64_t>(pc.as<uint64_t>(), 0, 1, s_);
-    {
-        const int64_t cb = (m_raw + kChunk - 1) / kChunk;
-        TimedLaunch tl(t_, TG_CONTRACT, sorted ? "k_seg_chunk" : "k_seg_chunk_any", (double)m_raw * 24);
+    // entries the chunks aggregate: all of them in the exported contraction,
+    // else those of segments of at most kChunkSeg entries
+    const int64_t m_chunks = sorted ? m_raw : m_raw - (int64_t)ntot[0] - (int64_t)ntot[1];
+    if (m_chunks > 0) {
+        const int64_t cb = (m_chunks + kChunk - 1) / kChunk;
+        TimedLaunch tl(t_, TG_CONTRACT, sorted ? "k_seg_chunk" : "k_seg_chunk_any", (double)m_chunks * 24);
         if (sorted)
             tl.launch(k_seg_chunk, (unsigned)cb, 256, 0, s_, off, k, m_raw, tcol_.p, tw_.p, mcount, key_[0].p,
                       val_[0].p, pc.as<unsigned long long>(), bits);
         else
-            tl.launch(k_seg_chunk_any, (unsigned)cb, 256, 0, s_, off, k, m_raw, tcol_.p, tw_.p, mcount, key_[0].p,
-                      val_[0].p, pc.as<unsigned long long>(), bits);
+            tl.launch(k_seg_chunk_any, (unsigned)cb, 256, 0, s_, (const int64_t *)soff, off, k, m_chunks, tcol_.p,
+                      tw_.p, mcount, key_[0].p, val_[0].p, pc.as<unsigned long long>(), bits);
         LV_LAUNCHED("k_seg_chunk");
     }
     const bool log = log_on();
