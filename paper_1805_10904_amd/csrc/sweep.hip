@@ -1624,6 +1624,7 @@ void Sweeper::init_from_labels(const GraphView &g, const int32_t *labels) {
 // 64 bits together), otherwise as k_sweep_group.
 constexpr int kWideThreads = 1024;
 constexpr int kWideBits = 14;
+static_assert(kBucketMax[B_WIDE] <= 3 * 4 * kWideThreads, "a wide row is at most three rounds of its workgroup");
 
 template <typename W, typename S>
 __global__ __launch_bounds__(kWideThreads) void k_sweep_wide(SweepArgs a, const int32_t *__restrict__ list) {
@@ -1651,7 +1652,19 @@ __global__ __launch_bounds__(kWideThreads) void k_sweep_wide(SweepArgs a, const 
     S bs = 0;
     int32_t bl = -1;
     constexpr int U = 4;
-    for (int64_t e0 = rs + t; e0 < re; e0 += (int64_t)U * T) {
+    // With published words the lane that claims a slot scores it after the
+    // inserts, with the candidate's deg_C from its word (no gather of deg_C):
+    // the slot and the degree of every claim stay in registers (a row has at
+    // most R rounds of U entries per lane).
+    constexpr int R = (int)((kBucketMax[B_WIDE] + U * T - 1) / (U * T));
+    int32_t hc[R * U];
+    int64_t dc[R * U];
+#pragma unroll
+    for (int c = 0; c < R * U; ++c) hc[c] = -1;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t e0 = rs + t + (int64_t)r * U * T;
+        if (e0 >= re) break;
         int32_t jq[U], lq[U];
         int64_t wq[U];
 #pragma unroll
@@ -1687,7 +1700,11 @@ __global__ __launch_bounds__(kWideThreads) void k_sweep_wide(SweepArgs a, const 
             uint32_t h = ((uint32_t)lq[q] * 0x9E3779B1u) >> (32 - kWideBits);
             while (true) {
                 const unsigned long long prev = atomicCAS(&tab[h], 0ull, tag | (unsigned long long)wq[q]);
-                if (prev == 0) break;
+                if (prev == 0) {
+                    hc[r * U + q] = (int32_t)h;
+                    dc[r * U + q] = dq[q];
+                    break;
+                }
                 if ((prev & tmask) == tag) {
                     atomicAdd(&tab[h], (unsigned long long)wq[q]);
                     break;
@@ -1697,9 +1714,27 @@ __global__ __launch_bounds__(kWideThreads) void k_sweep_wide(SweepArgs a, const 
         }
     }
     __syncthreads();
+    if (!a.first && a.pw) {
+#pragma unroll
+        for (int c = 0; c < R * U; ++c) {
+            if (hc[c] < 0) continue;
+            const unsigned long long wd = tab[hc[c]];
+            const int32_t k = (int32_t)(wd >> shift) - 1;
+            const int64_t ev = (int64_t)(wd & ~tmask);
+            if (k == ci) {
+                s_eown = ev;
+                continue;
+            }
+            const S sc = score_mul<S>(a.tw, ev) - score_mul<S>(di, dc[c]);
+            if (better<S>(sc, k, bs, bl)) {
+                bs = sc;
+                bl = k;
+            }
+        }
+    }
 #pragma unroll 4
     for (int q = 0; q < SPL; ++q) {
-        if (a.first) break;
+        if (a.first || a.pw) break;
         const unsigned long long wd = tab[t + q * T];
         if (wd == 0) continue;
         const int32_t k = (int32_t)(wd >> shift) - 1;
