@@ -470,6 +470,56 @@ def golden_parity(np, workload: str, r, out):
     return bool(same and lv == lv_exp)
 
 
+def gather_reference(torch, np, g, ctx, rp, col, w, dominant: str, tuning: dict):
+    """The packed-class sweep's launches at level 0 against a plain gather of
+    the same words: every entry of a row that kernel sweeps (small_max < d <=
+    341, loops excluded) reads one 8-byte published word at its column, in a
+    random order over the level's n words.  libgather_ref times a kernel that
+    does those reads and nothing else (same count, same columns, same order
+    of rows), which is what the memory system gives that pattern; the sweep
+    does them plus its table work.  None for other dominant kernels."""
+    if not dominant or not dominant.startswith("k_cpt_groups"):
+        return None
+    import ctypes as C
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "paper_1805_10904_amd", "libgather_ref.so")
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: run paper_1805_10904_amd/build.py")
+    lib = C.CDLL(path)
+    lib.gather_ref_us.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int, C.POINTER(C.c_float)]
+    lib.gather_ref_us.restype = C.c_int
+    d = np.diff(g.row_ptr)
+    rows = np.nonzero((d > tuning["small_max"]) & (3 * d <= 2 * 512) & (d <= tuning["block_max"]))[0]
+    lens = d[rows]
+    first = np.repeat(g.row_ptr[rows] - np.concatenate(([0], np.cumsum(lens)[:-1])), lens)
+    ent = first + np.arange(int(lens.sum()), dtype=np.int64)
+    cols = g.col[ent]
+    cols = cols[cols != np.repeat(rows, lens)].astype(np.int32)
+    if cols.size == 0 or cols.min() < 0 or cols.max() >= g.n:
+        return None
+    G = ctx.graph_create(rp, col, w)
+    r = ctx.run(G, max_levels=1, timing=dominant)
+    G.destroy()
+    k = r.stats["kernels"].get(dominant)
+    if not k or k["launches"] == 0:
+        return None
+    sweep_us = k["ms"] * 1000.0 / k["launches"]
+    dev_cols = torch.from_numpy(cols).to(torch.device("cuda", 0))
+    us = C.c_float(0)
+    rc = lib.gather_ref_us(dev_cols.data_ptr(), int(cols.size), int(g.n), 20, C.byref(us))
+    if rc != 0:
+        raise RuntimeError(f"gather_ref_us failed ({rc})")
+    m = int(cols.size)
+    return {"what": "level-0 launches of the packed-class sweep vs a kernel that only reads the same published "
+                    "words (8 B at each swept entry's column, same rows, same order)",
+            "rows": int(rows.size), "gathers": m, "words": int(g.n),
+            "sweep_launch_us": round(sweep_us, 2), "sweep_launches": int(k["launches"]),
+            "gather_only_us": round(us.value, 2),
+            "sweep_gathers_per_s": round(m / (sweep_us * 1e-6), 1),
+            "gather_only_per_s": round(m / (us.value * 1e-6), 1),
+            "sweep_over_gather_only": round(sweep_us / us.value, 3)}
+
+
 def measure_plain(L, torch, np, g, workload: str, steps: int, warmup: int, timing: bool, pass_batch: int,
                   shapes=None, autotune: bool = True, cpu: str = "full"):
     """The plain method on one workload: W warm-up steps (the last one times
@@ -556,6 +606,9 @@ def measure_plain(L, torch, np, g, workload: str, steps: int, warmup: int, timin
                            "launches_per_step": dom["launches"], "traffic_unit": "bytes per launch",
                            "alg_bytes_per_launch": round(alg_per_launch),
                            "traffic_over_alg": round(traffic / alg_per_launch, 3) if traffic else None}
+        res["roofline"]["gather_ref"] = gather_reference(torch, np, g, ctx, rp, col, w, dominant, tuning)
+        if res["roofline"]["gather_ref"]:
+            log(f"{workload}: level-0 gathers: {res['roofline']['gather_ref']}")
         top = sorted(table.items(), key=lambda kv: -kv[1]["ms"])[:20]
         log(f"{workload}: kernel time of one step (all launches timed): " +
             ", ".join(f"{n} {a['ms']:.3f} ms" for n, a in top))

@@ -1,8 +1,9 @@
 """Build the HIP library ``liblouvain_hip.so`` for gfx950 with hipcc.
 
 Every ``csrc/*.hip`` file is compiled to an object in ``_build/`` (in
-parallel), then linked into a shared library next to this file.  Run as a
-script or call ``build()``.
+parallel), then linked into a shared library next to this file.  The
+measurement harness's reference gather kernel (``gather_ref/``) becomes
+``libgather_ref.so`` beside it.  Run as a script or call ``build()``.
 """
 from __future__ import annotations
 
@@ -19,6 +20,9 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblouvain_hip.so")
+# the measurement harness's reference gather kernel, a library of its own
+GATHER_SRC = os.path.join(HERE, "gather_ref", "gather_ref.hip")
+GATHER_LIB = os.path.join(HERE, "libgather_ref.so")
 ARCH = os.environ.get("LOUVAIN_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
@@ -58,8 +62,13 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, LIB)
+    gtmp = GATHER_LIB + ".tmp"
+    r = subprocess.run([HIPCC, *COMMON, "-shared", "-o", gtmp, GATHER_SRC], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {GATHER_SRC}:\n{r.stderr}")
+    os.replace(gtmp, GATHER_LIB)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LIB} and {GATHER_LIB}")
     return LIB
 
 

@@ -713,6 +713,22 @@ __global__ __launch_bounds__(256) void k_cpt_group(CArgs a, const int32_t *__res
     }
 }
 
+// The LDS cells a lane group writes become visible to the whole group: a
+// workgroup barrier when the group spans several wavefronts (G > 64,
+// uniform over the workgroup), else a wavefront-scope fence, since a
+// wavefront's LDS accesses complete in order and no other wavefront touches
+// its groups' cells.  Wavefronts whose groups are their own then never wait
+// for the workgroup's slowest one.
+__device__ __forceinline__ void group_sync(int G) {
+    if (G > 64) {
+        __syncthreads();
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 // All packed classes in one launch: workgroups [bo[c], bo[c+1]) take class
 // c (S = 16 << c slots per table, G = S/SPL lanes per vertex, 16 SPL >> c
 // vertices per workgroup, 256 SPL table slots in all), otherwise as
@@ -834,7 +850,7 @@ __global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__re
             tw[j] = (uint32_t)a.tw[g[j]];
         }
     }
-    __syncthreads();
+    group_sync(G);
     unsigned long long bok[VPG];
     uint32_t blf[VPG];
 #pragma unroll
@@ -890,7 +906,7 @@ __global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__re
                 grp_insert(key[j], es[j], hs[j], bits, vw_label(nw), w, (uint32_t)(nw >> 32));
             }
         }
-    __syncthreads();
+    group_sync(G);
 #pragma unroll
     for (int j = 0; j < VPG; ++j) {
         if (a.first) break;
@@ -937,11 +953,7 @@ __global__ __launch_bounds__(256) void k_cpt_groups(CArgs a, const int32_t *__re
                 }
         }
     } else {
-        // the group's lanes are in one wavefront: its LDS accesses complete
-        // in order, so the cells written above are visible to lane 0
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        group_sync(G);   // the cells written above, visible to lane 0
     }
     if (li == 0) {
 #pragma unroll
