@@ -2,6 +2,8 @@
 // and row sums.
 #include "prims.hpp"
 
+#include <atomic>
+#include <chrono>
 #include <mutex>
 #include <vector>
 
@@ -351,11 +353,18 @@ struct GatherRanges {
     int n;
 };
 
-__global__ __launch_bounds__(256) void k_readback(GatherRanges r, uint32_t *dst) {
+// Copies the ranges, then (every thread's stores made visible to the host
+// first) stores the epoch in the flag word.
+__global__ __launch_bounds__(256) void k_readback(GatherRanges r, uint32_t *dst, uint32_t epoch) {
     for (int k = 0; k < r.n; ++k)
         for (int i = threadIdx.x; i < r.len[k]; i += 256) dst[r.off[k] + i] = r.src[k][i];
     __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0)
+        __hip_atomic_store(dst + Readback::kFlagWord, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
+
+std::atomic<uint32_t> g_rb_epoch{0};
 
 std::mutex g_rb_mu;
 struct RbBlock {
@@ -394,7 +403,7 @@ Readback::~Readback() {
 }
 
 void *Readback::add_words(const void *src, int64_t words) {
-    require(n_ < kMaxRanges && used_ + words <= kReadbackWords, LOUVAIN_EDEVICE, "read-back block is full");
+    require(n_ < kMaxRanges && used_ + words <= kFlagWord, LOUVAIN_EDEVICE, "read-back block is full");
     src_[n_] = (const uint32_t *)src;
     off_[n_] = used_;
     len_[n_] = (int)words;
@@ -413,8 +422,11 @@ void Readback::issue() {
             r.len[k] = len_[k];
         }
         r.n = n_;
-        k_readback<<<1, 256, 0, s_>>>(r, dev_);
+        epoch_ = g_rb_epoch.fetch_add(1, std::memory_order_relaxed) + 1;
+        if (epoch_ == 0) epoch_ = g_rb_epoch.fetch_add(1, std::memory_order_relaxed) + 1;   // 0: never stored
+        k_readback<<<1, 256, 0, s_>>>(r, dev_, epoch_);
         LV_LAUNCHED("k_readback");
+        flagged_ = true;
     }
     n_ = 0;
     LV_HIP(hipEventRecord(ev_, s_));
@@ -422,10 +434,28 @@ void Readback::issue() {
 }
 
 // Waits for the gather only: work enqueued after issue() keeps running.
+// Polls the flag word for up to kSpinUs, then waits on the event, which
+// also reports a failed stream (whose gather never runs).
 void Readback::wait() {
+    constexpr int64_t kSpinUs = 2000;
     if (!pending_) issue();
-    LV_HIP(hipEventSynchronize(ev_));
+    bool seen = false;
+    if (flagged_) {
+        const uint32_t *flag = host_ + kFlagWord;
+        const auto t0 = std::chrono::steady_clock::now();
+        for (int k = 0;; ++k) {
+            if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) == epoch_) {
+                seen = true;
+                break;
+            }
+            if ((k & 255) == 255 && std::chrono::duration_cast<std::chrono::microseconds>(
+                                        std::chrono::steady_clock::now() - t0).count() > kSpinUs)
+                break;
+        }
+    }
+    if (!seen) LV_HIP(hipEventSynchronize(ev_));
     pending_ = false;
+    flagged_ = false;
 }
 
 // ---------------------------------------------------------- side streams --

@@ -49,13 +49,16 @@ struct TempBuf {
 // Device values the host needs, read in one round trip: each add() queues
 // a device range (4-byte words) and returns where it will land in pinned
 // host memory; fetch() (issue() then wait()) gathers every queued range with
-// one small kernel that writes straight into that memory, then waits for the
-// stream once.  The
-// pinned block (kReadbackWords words) comes from a process-wide free list.
+// one small kernel that writes straight into that memory, then waits for it
+// once.  The pinned block (kReadbackWords words) comes from a process-wide
+// free list; its last word is a completion flag the kernel stores after the
+// values, which the host polls for a while before it falls back to the
+// event (a blocking wait adds its wake-up time to every round trip).
 class Readback {
   public:
     static constexpr int kMaxRanges = 24;
     static constexpr int kReadbackWords = 1024;
+    static constexpr int kFlagWord = kReadbackWords - 2;   // values use the words below it
     explicit Readback(hipStream_t s);
     ~Readback();
     Readback(const Readback &) = delete;
@@ -78,6 +81,8 @@ class Readback {
     hipEvent_t ev_ = nullptr;   // recorded after the gather
     int device_ = 0;            // device current at construction (the stream's)
     bool pending_ = false;      // issued and not waited for
+    bool flagged_ = false;      // the issued gather stores epoch_ in the flag word
+    uint32_t epoch_ = 0;
     int n_ = 0;
     int used_ = 0;
     const uint32_t *src_[kMaxRanges];
