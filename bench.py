@@ -470,16 +470,7 @@ def golden_parity(np, workload: str, r, out):
     return bool(same and lv == lv_exp)
 
 
-def gather_reference(torch, np, g, ctx, rp, col, w, dominant: str, tuning: dict):
-    """The packed-class sweep's launches at level 0 against a plain gather of
-    the same words: every entry of a row that kernel sweeps (small_max < d <=
-    341, loops excluded) reads one 8-byte published word at its column, in a
-    random order over the level's n words.  libgather_ref times a kernel that
-    does those reads and nothing else (same count, same columns, same order
-    of rows), which is what the memory system gives that pattern; the sweep
-    does them plus its table work.  None for other dominant kernels."""
-    if not dominant or not dominant.startswith("k_cpt_groups"):
-        return None
+def _gather_lib():
     import ctypes as C
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "paper_1805_10904_amd", "libgather_ref.so")
@@ -488,36 +479,84 @@ def gather_reference(torch, np, g, ctx, rp, col, w, dominant: str, tuning: dict)
     lib = C.CDLL(path)
     lib.gather_ref_us.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.c_int, C.POINTER(C.c_float)]
     lib.gather_ref_us.restype = C.c_int
-    d = np.diff(g.row_ptr)
-    rows = np.nonzero((d > tuning["small_max"]) & (3 * d <= 2 * 512) & (d <= tuning["block_max"]))[0]
-    lens = d[rows]
-    first = np.repeat(g.row_ptr[rows] - np.concatenate(([0], np.cumsum(lens)[:-1])), lens)
-    ent = first + np.arange(int(lens.sum()), dtype=np.int64)
-    cols = g.col[ent]
-    cols = cols[cols != np.repeat(rows, lens)].astype(np.int32)
-    if cols.size == 0 or cols.min() < 0 or cols.max() >= g.n:
-        return None
-    G = ctx.graph_create(rp, col, w)
-    r = ctx.run(G, max_levels=1, timing=dominant)
-    G.destroy()
-    k = r.stats["kernels"].get(dominant)
-    if not k or k["launches"] == 0:
-        return None
-    sweep_us = k["ms"] * 1000.0 / k["launches"]
-    dev_cols = torch.from_numpy(cols).to(torch.device("cuda", 0))
+    return lib
+
+
+def _gather_only_us(lib, idx_ptr: int, m: int, n: int, reps: int) -> float:
+    import ctypes as C
     us = C.c_float(0)
-    rc = lib.gather_ref_us(dev_cols.data_ptr(), int(cols.size), int(g.n), 20, C.byref(us))
+    rc = lib.gather_ref_us(idx_ptr, int(m), int(n), int(reps), C.byref(us))
     if rc != 0:
         raise RuntimeError(f"gather_ref_us failed ({rc})")
-    m = int(cols.size)
-    return {"what": "level-0 launches of the packed-class sweep vs a kernel that only reads the same published "
-                    "words (8 B at each swept entry's column, same rows, same order)",
-            "rows": int(rows.size), "gathers": m, "words": int(g.n),
-            "sweep_launch_us": round(sweep_us, 2), "sweep_launches": int(k["launches"]),
-            "gather_only_us": round(us.value, 2),
-            "sweep_gathers_per_s": round(m / (sweep_us * 1e-6), 1),
-            "gather_only_per_s": round(m / (us.value * 1e-6), 1),
-            "sweep_over_gather_only": round(sweep_us / us.value, 3)}
+    return float(us.value)
+
+
+def gather_reference(torch, np, g, ctx, rp, col, w, dominant: str, tuning: dict):
+    """The sweep at level 0 against a plain gather of the same words: every
+    swept entry reads one 8-byte published word at its column, in a random
+    order over the level's n words.  libgather_ref times a kernel that does
+    those reads and nothing else (same count, same columns, same order of
+    rows, one store per 4 or 16 reads), which is what the memory system gives
+    that pattern; the sweep does them plus its table work.
+    Compact levels (dominant kernel k_cpt_groups): that kernel's level-0
+    launches against the reads of the rows it sweeps (small_max < d <= 341,
+    loops excluded).  General levels: the level-0 passes (every sweep
+    kernel, level 0 in input order) against the reads of every entry (the
+    workloads have no loops).  None for other dominant kernels."""
+    if not dominant:
+        return None
+    lib = _gather_lib()
+    if dominant.startswith("k_cpt_groups"):
+        d = np.diff(g.row_ptr)
+        rows = np.nonzero((d > tuning["small_max"]) & (3 * d <= 2 * 512) & (d <= tuning["block_max"]))[0]
+        lens = d[rows]
+        first = np.repeat(g.row_ptr[rows] - np.concatenate(([0], np.cumsum(lens)[:-1])), lens)
+        ent = first + np.arange(int(lens.sum()), dtype=np.int64)
+        cols = g.col[ent]
+        cols = cols[cols != np.repeat(rows, lens)].astype(np.int32)
+        if cols.size == 0 or cols.min() < 0 or cols.max() >= g.n:
+            return None
+        G = ctx.graph_create(rp, col, w)
+        r = ctx.run(G, max_levels=1, timing=dominant)
+        G.destroy()
+        k = r.stats["kernels"].get(dominant)
+        if not k or k["launches"] == 0:
+            return None
+        sweep_us = k["ms"] * 1000.0 / k["launches"]
+        dev_cols = torch.from_numpy(cols).to(torch.device("cuda", 0))
+        us = _gather_only_us(lib, dev_cols.data_ptr(), cols.size, g.n, 20)
+        m = int(cols.size)
+        return {"what": "level-0 launches of the packed-class sweep vs a kernel that only reads the same published "
+                        "words (8 B at each swept entry's column, same rows, same order)",
+                "rows": int(rows.size), "gathers": m, "words": int(g.n),
+                "sweep_launch_us": round(sweep_us, 2), "sweep_launches": int(k["launches"]),
+                "gather_only_us": round(us, 2),
+                "sweep_gathers_per_s": round(m / (sweep_us * 1e-6), 1),
+                "gather_only_per_s": round(m / (us * 1e-6), 1),
+                "sweep_over_gather_only": round(sweep_us / us, 3)}
+    if not dominant.startswith("k_sweep") or g.nnz == 0:
+        return None
+    keys = ("small_max", "block_max", "pass_batch", "group_slots", "group_vertices", "overlap", "reorder",
+            "group_tiles")
+    ctx.set_tuning(*[2 if k == "reorder" else int(tuning[k]) for k in keys])   # level 0 in input order
+    try:
+        G = ctx.graph_create(rp, col, w)
+        r = ctx.run(G, max_levels=1, timing=True)
+        G.destroy()
+    finally:
+        ctx.set_tuning(*[int(tuning[k]) for k in keys])
+    lv0 = r.stats["levels"][0]
+    if lv0["gpu_passes"] <= 0 or lv0["ms_sweep"] <= 0:
+        return None
+    pass_us = lv0["ms_sweep"] * 1000.0 / lv0["gpu_passes"]
+    us = _gather_only_us(lib, col.data_ptr(), g.nnz, g.n, 5)
+    return {"what": "level-0 sweep passes (every sweep kernel, level 0 in input order) vs a kernel that only reads "
+                    "one 8-byte word at every entry's column (the passes' neighbour reads, same order)",
+            "gathers": int(g.nnz), "words": int(g.n), "passes": int(lv0["gpu_passes"]),
+            "pass_us": round(pass_us, 1), "gather_only_us": round(us, 1),
+            "pass_gathers_per_s": round(g.nnz / (pass_us * 1e-6), 1),
+            "gather_only_per_s": round(g.nnz / (us * 1e-6), 1),
+            "pass_over_gather_only": round(pass_us / us, 3)}
 
 
 def measure_plain(L, torch, np, g, workload: str, steps: int, warmup: int, timing: bool, pass_batch: int,
