@@ -1124,28 +1124,76 @@ __global__ __launch_bounds__(256) void k_hub_decide(SweepArgs a, HubMeta hm, con
 
 constexpr int kQsumTile = 2048;
 
-// Community degrees and sizes follow the movers (integer atomics, so the
-// result does not depend on their order).
+// Community degrees and sizes follow the movers.  A workgroup takes
+// kCommitTile vertices and sums its movers' updates per community in an LDS
+// table first (a community that many of the tile's vertices join or leave,
+// such as a hub's, then takes one global atomic per array instead of one per
+// mover); an update that finds no slot within kGenCommitProbe probes goes to
+// HBM directly.  Integer sums (modulo 2^64 for the degrees), so the result
+// does not depend on their order.
+constexpr int kCommitTile = 1024;
+constexpr int kCommitBits = 11;       // 2 slots per vertex of the tile
+constexpr int kGenCommitProbe = 32;
+
+__device__ __forceinline__ bool gen_commit_insert(int32_t *key, unsigned long long *dsum, int *ssum, int32_t k,
+                                                  unsigned long long d, int s) {
+    constexpr uint32_t mask = (1u << kCommitBits) - 1;
+    uint32_t h = ((uint32_t)k * 0x9E3779B1u) >> (32 - kCommitBits);
+    for (int probe = 0; probe < kGenCommitProbe; ++probe) {
+        const int32_t prev = atomicCAS(&key[h], kEmpty, k);   // claims, or returns the slot's key
+        if (prev == kEmpty || prev == k) {
+            atomicAdd(&dsum[h], d);
+            atomicAdd(&ssum[h], s);
+            return true;
+        }
+        h = (h + 1) & mask;
+    }
+    return false;
+}
+
 __global__ __launch_bounds__(256) void k_commit(const int32_t *__restrict__ c_cur, const int32_t *__restrict__ c_nxt,
                                                 const int64_t *__restrict__ delta, int64_t *deg, int32_t *size,
                                                 int64_t n, PhaseState *st) {
+    constexpr int T = 1 << kCommitBits;
+    __shared__ int32_t s_key[T];
+    __shared__ unsigned long long s_deg[T];
+    __shared__ int s_size[T];
     __shared__ unsigned long long s_m;
     if (st->done) return;
+    for (int x = threadIdx.x; x < T; x += 256) {
+        s_key[x] = kEmpty;
+        s_deg[x] = 0;
+        s_size[x] = 0;
+    }
     if (threadIdx.x == 0) s_m = 0;
     __syncthreads();
-    const int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (v < n) {
+    const int64_t base = (int64_t)blockIdx.x * kCommitTile;
+    unsigned long long moved = 0;
+#pragma unroll 2
+    for (int k = 0; k < kCommitTile / 256; ++k) {
+        const int64_t v = base + k * 256 + threadIdx.x;
+        if (v >= n) break;
         const int32_t a = c_cur[v], b = c_nxt[v];
-        if (a != b) {
-            const int64_t d = delta[v];
-            atomicAdd((unsigned long long *)&deg[b], (unsigned long long)d);
-            atomicAdd((unsigned long long *)&deg[a], (unsigned long long)(-d));
+        if (a == b) continue;
+        const unsigned long long d = (unsigned long long)delta[v];
+        if (!gen_commit_insert(s_key, s_deg, s_size, b, d, 1)) {
+            atomicAdd((unsigned long long *)&deg[b], d);
             atomicAdd(&size[b], 1);
-            atomicAdd(&size[a], -1);
-            atomicAdd(&s_m, 1ull);
         }
+        if (!gen_commit_insert(s_key, s_deg, s_size, a, 0 - d, -1)) {
+            atomicAdd((unsigned long long *)&deg[a], 0 - d);
+            atomicAdd(&size[a], -1);
+        }
+        ++moved;
     }
+    if (moved) atomicAdd(&s_m, moved);
     __syncthreads();
+    for (int x = threadIdx.x; x < T; x += 256) {
+        const int32_t key = s_key[x];
+        if (key == kEmpty) continue;
+        if (s_deg[x] != 0) atomicAdd((unsigned long long *)&deg[key], s_deg[x]);
+        if (s_size[x] != 0) atomicAdd(&size[key], s_size[x]);
+    }
     if (threadIdx.x == 0 && s_m) atomicAdd(&st->moved, s_m);
 }
 
@@ -2031,7 +2079,8 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
     }
     if (g.n > 0) {
         TimedLaunch tl(t_, TG_SWEEP, "k_commit", (double)g.n * 8);
-        tl.launch(k_commit, grid_for(g.n, 256), 256, 0, s_, c_[cur].p, c_[nxt].p, g.delta, deg_.p, size_.p, g.n, st_.p);
+        tl.launch(k_commit, grid_for(g.n, kCommitTile), 256, 0, s_, c_[cur].p, c_[nxt].p, g.delta, deg_.p, size_.p,
+                  g.n, st_.p);
         LV_LAUNCHED("k_commit");
     }
     {
