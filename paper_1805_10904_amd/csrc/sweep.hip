@@ -1360,6 +1360,23 @@ __device__ __forceinline__ int bucket_of_vertex(const int64_t *__restrict__ rp, 
     return bucket_of(d, small_max, block_max);
 }
 
+// Largest delta_i of a level: per-thread maxima, a wavefront reduction and
+// one atomic per wavefront.
+constexpr int kDeltaMaxItems = 8;
+__global__ __launch_bounds__(256) void k_delta_max(const int64_t *__restrict__ delta, int64_t n,
+                                                   unsigned long long *out) {
+    const int64_t base = (int64_t)blockIdx.x * 256 * kDeltaMaxItems + threadIdx.x;
+    unsigned long long m = 0;
+#pragma unroll
+    for (int k = 0; k < kDeltaMaxItems; ++k) {
+        const int64_t v = base + (int64_t)k * 256;
+        if (v < n) m = max(m, (unsigned long long)delta[v]);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (unsigned long long)__shfl_xor((long long)m, off));
+    if ((threadIdx.x & 63) == 0 && m) atomicMax(out, m);
+}
+
 __global__ __launch_bounds__(256) void k_bucket_count(const int64_t *__restrict__ rp, int64_t n, int32_t *counts,
                                                       int64_t nblocks, unsigned long long *bucket_nnz,
                                                       const int32_t *__restrict__ gid,
@@ -1497,6 +1514,7 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     n_ = g.n;
     compact_ = batch_ || g.tw < kCompactTwMax;   // before anything that depends on the level's kind
     general_classes_ = false;
+    score64_ = g.tw <= kTwFastMax;
     const int small_max = compact_ ? tuning_.small_max : (int)kBucketMax[B_T8];
     const int64_t block_max = compact_ ? tuning_.block_max : lds_row_max(g.n, g.tw, tuning_);
     const int32_t *skip_gid = active_only && batch_ ? gid_ : nullptr;
@@ -1538,7 +1556,20 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     for (int b = 0; b < NBUCKET; ++b) hs[b] = rb.add(counts + (int64_t)b * nblk);
     hs[NBUCKET] = rb.add(counts + m);
     const unsigned long long *hn = rb.add(bnnz.as<unsigned long long>(), NBUCKET);
+    // 64-bit scores whenever every product of a score fits: TW e and
+    // delta_i deg_C are at most TW max_i delta_i (e_{i->C} <= delta_i and
+    // deg_C <= TW), so TW max delta < 2^62 keeps scores and their
+    // differences inside int64 (always so when TW <= kTwFastMax)
+    const unsigned long long *hdmax = nullptr;
+    if (!compact_ && g.tw > kTwFastMax) {
+        dmax_.reserve(1);
+        fill<uint64_t>((uint64_t *)dmax_.p, 0, 1, s_);
+        k_delta_max<<<grid_for(g.n, 256 * kDeltaMaxItems), 256, 0, s_>>>(g.delta, g.n, dmax_.p);
+        LV_LAUNCHED("k_delta_max");
+        hdmax = rb.add(dmax_.p);
+    }
     rb.fetch();
+    score64_ = g.tw <= kTwFastMax || (hdmax && (i128)g.tw * (i128)*hdmax < ((i128)1 << 62));
     for (int b = 0; b <= NBUCKET; ++b) bstart_[b] = *hs[b];
     for (int b = 0; b < NBUCKET; ++b) bucket_nnz_[b] = (int64_t)hn[b];
     // line positions of the packed vertices (buckets B_T16 to B_MID, contiguous in the list)
@@ -1852,25 +1883,7 @@ static void launch_pass(const SweepArgs &a, const int32_t *list, const int64_t *
     const double vb = 40.0;              // per evaluated vertex
     auto cnt = [&](int b) { return bstart[b + 1] - bstart[b]; };
     auto bytes = [&](int b) { return (double)cnt(b) * vb + (double)bnnz[b] * eb; };
-    if constexpr (std::is_same<S, int64_t>::value) {
-        if (cnt(B_T8) > 0) {
-            TimedLaunch tl(t, TG_SWEEP, "k_sweep_thread<8,", bytes(B_T8), wsfx.c_str());
-            tl.launch(k_sweep_thread<8, W>, grid_for(cnt(B_T8), 256), 256, 0, s, a, list + bstart[B_T8], cnt(B_T8));
-            LV_LAUNCHED("k_sweep_thread<8>");
-        }
-        const int64_t np = bstart[B_BLOCK] - bstart[B_T16];
-        if (np > 0) {
-            TimedLaunch tl(t, TG_SWEEP, "k_sweep_pack<", bytes(B_T16) + bytes(B_G64) + bytes(B_MID), wsfx.c_str());
-            tl.launch(k_sweep_pack<W>, (unsigned)pack_blocks, 256, 0, s, a, list + bstart[B_T16], pack_pos, pack_first);
-            LV_LAUNCHED("k_sweep_pack");
-        }
-        if (cnt(B_BLOCK) > 0) {
-            TimedLaunch tl(t, TG_SWEEP, "k_sweep_group<256,11,", bytes(B_BLOCK), sfx.c_str());
-            tl.launch(k_sweep_group<256, 11, W, S>, (unsigned)cnt(B_BLOCK), 256, 0, s, a, list + bstart[B_BLOCK],
-                      cnt(B_BLOCK));
-            LV_LAUNCHED("k_sweep_group<256>");
-        }
-    } else if (cl.list) {
+    if (cl.list) {
         if (cnt(B_T8) > 0) {
             TimedLaunch tl(t, TG_SWEEP, "k_sweep_group<4,4,", bytes(B_T8), sfx.c_str());
             tl.launch(k_sweep_group<4, 4, W, S>, grid_for(cnt(B_T8), 64), 256, 0, s, a, list + bstart[B_T8], cnt(B_T8));
@@ -1903,6 +1916,24 @@ static void launch_pass(const SweepArgs &a, const int32_t *list, const int64_t *
             TimedLaunch tl(t, TG_SWEEP, "k_sweep_wide<", cbytes(c8), sfx.c_str());
             tl.launch(k_sweep_wide<W, S>, (unsigned)ccount(c8), kWideThreads, 0, s, a, cl.list + cl.cstart[c8]);
             LV_LAUNCHED("k_sweep_wide");
+        }
+    } else if constexpr (std::is_same<S, int64_t>::value) {
+        if (cnt(B_T8) > 0) {
+            TimedLaunch tl(t, TG_SWEEP, "k_sweep_thread<8,", bytes(B_T8), wsfx.c_str());
+            tl.launch(k_sweep_thread<8, W>, grid_for(cnt(B_T8), 256), 256, 0, s, a, list + bstart[B_T8], cnt(B_T8));
+            LV_LAUNCHED("k_sweep_thread<8>");
+        }
+        const int64_t np = bstart[B_BLOCK] - bstart[B_T16];
+        if (np > 0) {
+            TimedLaunch tl(t, TG_SWEEP, "k_sweep_pack<", bytes(B_T16) + bytes(B_G64) + bytes(B_MID), wsfx.c_str());
+            tl.launch(k_sweep_pack<W>, (unsigned)pack_blocks, 256, 0, s, a, list + bstart[B_T16], pack_pos, pack_first);
+            LV_LAUNCHED("k_sweep_pack");
+        }
+        if (cnt(B_BLOCK) > 0) {
+            TimedLaunch tl(t, TG_SWEEP, "k_sweep_group<256,11,", bytes(B_BLOCK), sfx.c_str());
+            tl.launch(k_sweep_group<256, 11, W, S>, (unsigned)cnt(B_BLOCK), 256, 0, s, a, list + bstart[B_BLOCK],
+                      cnt(B_BLOCK));
+            LV_LAUNCHED("k_sweep_group<256>");
         }
     } else {
         if (cnt(B_T8) > 0) {
@@ -2055,7 +2086,7 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
                tab_off + 3 * (hubs_ + 1), hub_of_chunk_.p, hub_of_scan_.p, hubs_, tab_off + 4 * (hubs_ + 1),
                tab_off + 5 * (hubs_ + 1), hub_of_bkt_.p, hub_bucket_shrink()};
     HubBuckets hb{hub_buckets_, bkt_key_.p, bkt_val_.p, bkt_cur_.p, bkt_part_.p, hub_spill_.p};
-    const bool fast = g.tw <= kTwFastMax;
+    const bool fast = score64_;
     ClassLists cls;
     if (general_classes_) {
         cls.list = glist_.p;
@@ -2065,14 +2096,14 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
     if (g.wbytes == 4) {
         if (fast)
             launch_pass<int32_t, int64_t>(a, list_.p, bstart_, bucket_nnz_, pack_pos_.p, pack_first_.p, pack_blocks_, hm, hb, hub_chunks_, hub_scans_,
-                                          hub_key_.p, hub_val_.p, hub_loop_.p, hub_part_.p, s_, t_);
+                                          hub_key_.p, hub_val_.p, hub_loop_.p, hub_part_.p, s_, t_, cls);
         else
             launch_pass<int32_t, i128>(a, list_.p, bstart_, bucket_nnz_, pack_pos_.p, pack_first_.p, pack_blocks_, hm, hb, hub_chunks_, hub_scans_,
                                        hub_key_.p, hub_val_.p, hub_loop_.p, hub_part_.p, s_, t_, cls);
     } else {
         if (fast)
             launch_pass<int64_t, int64_t>(a, list_.p, bstart_, bucket_nnz_, pack_pos_.p, pack_first_.p, pack_blocks_, hm, hb, hub_chunks_, hub_scans_,
-                                          hub_key_.p, hub_val_.p, hub_loop_.p, hub_part_.p, s_, t_);
+                                          hub_key_.p, hub_val_.p, hub_loop_.p, hub_part_.p, s_, t_, cls);
         else
             launch_pass<int64_t, i128>(a, list_.p, bstart_, bucket_nnz_, pack_pos_.p, pack_first_.p, pack_blocks_, hm, hb, hub_chunks_, hub_scans_,
                                        hub_key_.p, hub_val_.p, hub_loop_.p, hub_part_.p, s_, t_, cls);

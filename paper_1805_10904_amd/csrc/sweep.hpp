@@ -267,7 +267,9 @@ class Sweeper {
     DevBuf<uint64_t> ginfo_;        // compact: their row start << 12 | length
     int64_t cstart_[kLdsClasses + 1] = {0};
     int64_t cnnz_[kLdsClasses] = {0};
-    bool general_classes_ = false;  // a level with 128-bit scores swept by table-size class
+    bool general_classes_ = false;  // a general level (TW > kTwFastMax) swept by table-size class
+    bool score64_ = true;           // the level's scores fit int64 (TW max delta < 2^62)
+    DevBuf<unsigned long long> dmax_;   // largest delta of the level
     DevBuf<int32_t> bcount_;        // bucketing scratch (per-block counts / offsets)
     DevBuf<PhaseState> st_;
     DevBuf<uint64_t> qpart_;        // per-block partial sums of deg^2 (lo, hi)
