@@ -515,8 +515,9 @@ int run_plain(const GraphView &g0, const louvain_params &prm, const Tuning &tn, 
                 for (size_t r = pass_rec[(size_t)st.pass]; r < timer.recs.size(); ++r) timer.recs[r].launched = false;
             range.reset();
             if (lv::log_on())
-                fprintf(stderr, "[louvain] level %d: n %lld, nnz %lld, passes %d, sweeps kept %d%s\n", level,
-                        (long long)v.n, (long long)v.nnz, st.pass, st.accepted, st.limit ? " (max_sweeps)" : "");
+                fprintf(stderr, "[louvain] level %d: n %lld, nnz %lld, %s, passes %d, sweeps kept %d%s\n", level,
+                        (long long)v.n, (long long)v.nnz, sw.score_kind(), st.pass, st.accepted,
+                        st.limit ? " (max_sweeps)" : "");
             auto &ls = local.level[level];
             ls.n = v.n;
             ls.nnz = v.nnz;

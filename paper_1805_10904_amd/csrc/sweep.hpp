@@ -228,6 +228,8 @@ class Sweeper {
     const unsigned int *active_counter(int p) const { return active_.p + (p & 1); }
     // Control blocks of every graph (device; compact levels).
     PhaseState *states() { return st_.p; }
+    // the planned level: compact words, or general levels' score width
+    const char *score_kind() const { return compact_ ? "compact" : score64_ ? "64-bit scores" : "128-bit scores"; }
     bool compact() const { return compact_; }
     int64_t ngraphs() const { return ngraphs_; }
     // e_{i->labels_in[i]} incl. loop of the last pass (compact levels, int64 copy)
