@@ -500,9 +500,10 @@ def gather_reference(torch, np, g, ctx, rp, col, w, dominant: str, tuning: dict)
     that pattern; the sweep does them plus its table work.
     Compact levels (dominant kernel k_cpt_groups): that kernel's level-0
     launches against the reads of the rows it sweeps (small_max < d <= 341,
-    loops excluded).  General levels: the level-0 passes (every sweep
-    kernel, level 0 in input order) against the reads of every entry (the
-    workloads have no loops).  None for other dominant kernels."""
+    loops excluded).  General levels (2W >= 2^31, whatever kernel
+    dominates): the level-0 passes (every sweep kernel, level 0 in input
+    order) against the reads of every entry (the workloads have no loops).
+    None otherwise."""
     if not dominant:
         return None
     lib = _gather_lib()
@@ -534,8 +535,8 @@ def gather_reference(torch, np, g, ctx, rp, col, w, dominant: str, tuning: dict)
                 "sweep_gathers_per_s": round(m / (sweep_us * 1e-6), 1),
                 "gather_only_per_s": round(m / (us * 1e-6), 1),
                 "sweep_over_gather_only": round(sweep_us / us, 3)}
-    if not dominant.startswith("k_sweep") or g.nnz == 0:
-        return None
+    if g.nnz == 0 or int(g.w.sum(dtype=np.int64)) < (1 << 31):
+        return None   # compact levels: only the packed-class comparison above
     keys = ("small_max", "block_max", "pass_batch", "group_slots", "group_vertices", "overlap", "reorder",
             "group_tiles")
     ctx.set_tuning(*[2 if k == "reorder" else int(tuning[k]) for k in keys])   # level 0 in input order
