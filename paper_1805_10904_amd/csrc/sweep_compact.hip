@@ -2062,7 +2062,7 @@ void compact_pass(const GraphView &g, const CompactPass &cp, const CompactState 
         compact_sweeps<int64_t>(a, cp, s, side, t);
     const bool fused = g.n > 0 && cs.ngraphs == 1 && g.n <= kFuseMaxN;
     if (g.n > 0) {
-        // a single graph's acceptance test runs in the last workgroup to finish
+        // a small single graph's acceptance test runs in the last workgroup to finish
         const FinalizeArgs fa{cs.tw, cs.ngraphs, prm.theta_num, prm.theta_den, prm.max_sweeps, p,
                               cs.active + (p & 1), fused ? cs.active + 2 : nullptr};
         TimedLaunch tl(t, TG_SWEEP, "k_cpt_commit", (double)g.n * 12);
