@@ -43,7 +43,17 @@ struct SweepArgs {
     // of each pass when pw_bits + the bits of TW fit 63.
     const uint64_t *pw;
     int pw_bits;
+    // the pass's sums (I, then the mover count) spread over kAccSlots
+    // counters a 128-byte line apart: the kernels' thousands of workgroups
+    // would otherwise queue their atomics on one address
+    unsigned long long *acc;
 };
+
+constexpr int kAccSlots = 256;
+constexpr int kAccStride = 16;   // 64-bit words per slot (one 128-byte line)
+__device__ __forceinline__ void acc_add(unsigned long long *acc, uint64_t slot, int field, unsigned long long x) {
+    atomicAdd(&acc[(slot & (kAccSlots - 1)) * kAccStride + field], x);
+}
 
 __device__ __forceinline__ int32_t pw_label(uint64_t w, int bits) { return (int32_t)(w & ((1ull << bits) - 1)); }
 __device__ __forceinline__ int64_t pw_deg(uint64_t w, int bits) { return (int64_t)((w << 1) >> (bits + 1)); }
@@ -378,7 +388,7 @@ __global__ __launch_bounds__(256) void k_sweep_group(SweepArgs a, const int32_t 
         if (self) atomicAdd(&s_I, (unsigned long long)self);
     }
     __syncthreads();
-    if (tid == 0 && s_I) atomicAdd(&a.st->acc_I, s_I);
+    if (tid == 0 && s_I) acc_add(a.acc, blockIdx.x, 0, s_I);
 }
 
 // ---------------------------------------------------- thread-per-vertex kernel --
@@ -470,7 +480,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) self += __shfl_xor(self, off);
-    if ((threadIdx.x & 63) == 0 && self) atomicAdd(&a.st->acc_I, (unsigned long long)self);
+    if ((threadIdx.x & 63) == 0 && self) acc_add(a.acc, (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6), 0, (unsigned long long)self);
 }
 
 // ------------------------------------------------------- packed sweep kernel --
@@ -712,7 +722,7 @@ __global__ __launch_bounds__(256) void k_sweep_pack(SweepArgs a, const int32_t *
         if (self) atomicAdd(&s_I, (unsigned long long)self);
     }
     __syncthreads();
-    if (t == 0 && s_I) atomicAdd(&a.st->acc_I, s_I);
+    if (t == 0 && s_I) acc_add(a.acc, blockIdx.x, 0, s_I);
 }
 
 // ------------------------------------------------------------- hub kernels --
@@ -1116,7 +1126,7 @@ __global__ __launch_bounds__(256) void k_hub_decide(SweepArgs a, HubMeta hm, con
         const int64_t self = e_own + (int64_t)hub_loop[h];
         hub_loop[h] = 0;
         if (a.e_self) a.e_self[v] = self;
-        if (self) atomicAdd(&a.st->acc_I, (unsigned long long)self);
+        if (self) acc_add(a.acc, (uint64_t)h, 0, (unsigned long long)self);
     }
 }
 
@@ -1153,7 +1163,7 @@ __device__ __forceinline__ bool gen_commit_insert(int32_t *key, unsigned long lo
 
 __global__ __launch_bounds__(256) void k_commit(const int32_t *__restrict__ c_cur, const int32_t *__restrict__ c_nxt,
                                                 const int64_t *__restrict__ delta, int64_t *deg, int32_t *size,
-                                                int64_t n, PhaseState *st) {
+                                                int64_t n, PhaseState *st, unsigned long long *acc) {
     constexpr int T = 1 << kCommitBits;
     __shared__ int32_t s_key[T];
     __shared__ unsigned long long s_deg[T];
@@ -1194,7 +1204,7 @@ __global__ __launch_bounds__(256) void k_commit(const int32_t *__restrict__ c_cu
         if (s_deg[x] != 0) atomicAdd((unsigned long long *)&deg[key], s_deg[x]);
         if (s_size[x] != 0) atomicAdd(&size[key], s_size[x]);
     }
-    if (threadIdx.x == 0 && s_m) atomicAdd(&st->moved, s_m);
+    if (threadIdx.x == 0 && s_m) acc_add(acc, blockIdx.x, 1, s_m);
 }
 
 // Per-block partial sums of deg_C^2 (128-bit) of the labelling a pass reads;
@@ -1261,10 +1271,26 @@ __device__ __forceinline__ bool relative_gain_passes(i128 qn, i128 qp, int64_t n
 // sweep p-1 against the last kept labelling.
 __global__ __launch_bounds__(256) void k_finalize(PhaseState *st, const uint64_t *__restrict__ part,
                                                   int64_t nparts, int64_t tw, int64_t theta_num,
-                                                  int64_t theta_den, int32_t max_sweeps, int32_t p) {
+                                                  int64_t theta_den, int32_t max_sweeps, int32_t p,
+                                                  unsigned long long *acc) {
+    static_assert(kAccSlots == 256, "one slot of the pass's sums per thread");
     __shared__ uint64_t slo[256];
     __shared__ int64_t shi[256];
+    __shared__ unsigned long long s_I[4], s_m[4];
     if (st->done) return;
+    // the pass's I and mover count: one slot per thread, then cleared for the next pass
+    unsigned long long vi = acc[threadIdx.x * kAccStride], vm = acc[threadIdx.x * kAccStride + 1];
+    acc[threadIdx.x * kAccStride] = 0;
+    acc[threadIdx.x * kAccStride + 1] = 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        vi += (unsigned long long)__shfl_xor((long long)vi, off);
+        vm += (unsigned long long)__shfl_xor((long long)vm, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_I[threadIdx.x >> 6] = vi;
+        s_m[threadIdx.x >> 6] = vm;
+    }
     i128 s = 0;
     for (int64_t b = threadIdx.x; b < nparts; b += 256) s += make_i128(part[2 * b], (int64_t)part[2 * b + 1]);
     slo[threadIdx.x] = (uint64_t)s;
@@ -1279,8 +1305,10 @@ __global__ __launch_bounds__(256) void k_finalize(PhaseState *st, const uint64_t
         __syncthreads();
     }
     if (threadIdx.x != 0) return;
+    const unsigned long long acc_I = s_I[0] + s_I[1] + s_I[2] + s_I[3];
+    const unsigned long long moved = s_m[0] + s_m[1] + s_m[2] + s_m[3];
     const i128 S = make_i128(slo[0], shi[0]);
-    const i128 q = mul_wide(tw, (int64_t)st->acc_I) - S;
+    const i128 q = mul_wide(tw, (int64_t)acc_I) - S;
     st->pass = p;
     st->q_last[0] = (uint64_t)q;
     st->q_last[1] = (uint64_t)(int64_t)(q >> 64);
@@ -1303,7 +1331,7 @@ __global__ __launch_bounds__(256) void k_finalize(PhaseState *st, const uint64_t
             st->done = 1;
             st->limit = 1;
             st->final_slot = (p - 1) % 3;
-        } else if (st->moved == 0) {
+        } else if (moved == 0) {
             st->done = 1;   // the next sweep cannot change Q, so it would be discarded
             st->final_slot = (p - 1) % 3;
         }
@@ -1480,6 +1508,8 @@ void Sweeper::reserve(int64_t n, int64_t nnz) {
     ds_.alloc((size_t)n);
     vw_.alloc((size_t)n);
     es_.alloc((size_t)n);
+    acc_.alloc((size_t)kAccSlots * kAccStride);   // general levels: the pass's sums, by slot
+    fill<uint64_t>((uint64_t *)acc_.p, 0, (int64_t)kAccSlots * kAccStride, s_);
     active_.alloc(3);   // graphs still in their phase (by pass parity), commit arrivals
     fill<int32_t>((int32_t *)active_.p, 0, 3, s_);
     tw_one_.alloc(1);
@@ -1515,6 +1545,7 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     compact_ = batch_ || g.tw < kCompactTwMax;   // before anything that depends on the level's kind
     general_classes_ = false;
     score64_ = g.tw <= kTwFastMax;
+    if (!compact_) fill<uint64_t>((uint64_t *)acc_.p, 0, (int64_t)kAccSlots * kAccStride, s_);   // a phase starts from zero sums
     const int small_max = compact_ ? tuning_.small_max : (int)kBucketMax[B_T8];
     const int64_t block_max = compact_ ? tuning_.block_max : lds_row_max(g.n, g.tw, tuning_);
     const int32_t *skip_gid = active_only && batch_ ? gid_ : nullptr;
@@ -1845,7 +1876,7 @@ __global__ __launch_bounds__(kWideThreads) void k_sweep_wide(SweepArgs a, const 
         a.c_nxt[i] = decide<S>(a, i, ci, bs, bl, s_eown);
         const int64_t self = s_eown + s_loop;
         if (a.e_self) a.e_self[i] = self;
-        if (self) atomicAdd(&a.st->acc_I, (unsigned long long)self);
+        if (self) acc_add(a.acc, blockIdx.x, 0, (unsigned long long)self);
     }
 }
 
@@ -2080,7 +2111,7 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
     const int hub_shift = word_shift(g.n, g.tw);
     SweepArgs a{g.row_ptr, g.col, g.w, c_[cur].p, c_[nxt].p, g.delta, deg_.p, size_.p,
                 g.tw, prm.singlet, st_.p, e_self_out, hub_shift, singleton_start_ && p == 1 ? 1 : 0,
-                publish ? vw_.p : nullptr, pw_bits};
+                publish ? vw_.p : nullptr, pw_bits, acc_.p};
     int64_t *tab_off = hub_meta_.p;
     HubMeta hm{list_.p + bstart_[B_HUB], tab_off, tab_off + (hubs_ + 1), tab_off + 2 * (hubs_ + 1),
                tab_off + 3 * (hubs_ + 1), hub_of_chunk_.p, hub_of_scan_.p, hubs_, tab_off + 4 * (hubs_ + 1),
@@ -2111,13 +2142,13 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
     if (g.n > 0) {
         TimedLaunch tl(t_, TG_SWEEP, "k_commit", (double)g.n * 8);
         tl.launch(k_commit, grid_for(g.n, kCommitTile), 256, 0, s_, c_[cur].p, c_[nxt].p, g.delta, deg_.p, size_.p,
-                  g.n, st_.p);
+                  g.n, st_.p, acc_.p);
         LV_LAUNCHED("k_commit");
     }
     {
         TimedLaunch tl(t_, TG_SWEEP, "k_finalize", 0.0);
         tl.launch(k_finalize, 1, 256, 0, s_, st_.p, qpart_.p, qblocks_, g.tw, prm.theta_num, prm.theta_den,
-                  prm.max_sweeps, p);
+                  prm.max_sweeps, p, acc_.p);
         LV_LAUNCHED("k_finalize");
     }
 }

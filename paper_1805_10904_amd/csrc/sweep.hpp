@@ -272,6 +272,7 @@ class Sweeper {
     bool general_classes_ = false;  // a general level (TW > kTwFastMax) swept by table-size class
     bool score64_ = true;           // the level's scores fit int64 (TW max delta < 2^62)
     DevBuf<unsigned long long> dmax_;   // largest delta of the level
+    DevBuf<unsigned long long> acc_;    // general levels: the pass's I and mover count, by slot
     DevBuf<int32_t> bcount_;        // bucketing scratch (per-block counts / offsets)
     DevBuf<PhaseState> st_;
     DevBuf<uint64_t> qpart_;        // per-block partial sums of deg^2 (lo, hi)
