@@ -49,8 +49,6 @@ struct SweepArgs {
     unsigned long long *acc;
 };
 
-constexpr int kAccSlots = 256;
-constexpr int kAccStride = 16;   // 64-bit words per slot (one 128-byte line)
 __device__ __forceinline__ void acc_add(unsigned long long *acc, uint64_t slot, int field, unsigned long long x) {
     atomicAdd(&acc[(slot & (kAccSlots - 1)) * kAccStride + field], x);
 }
@@ -1545,7 +1543,7 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     compact_ = batch_ || g.tw < kCompactTwMax;   // before anything that depends on the level's kind
     general_classes_ = false;
     score64_ = g.tw <= kTwFastMax;
-    if (!compact_) fill<uint64_t>((uint64_t *)acc_.p, 0, (int64_t)kAccSlots * kAccStride, s_);   // a phase starts from zero sums
+    fill<uint64_t>((uint64_t *)acc_.p, 0, (int64_t)kAccSlots * kAccStride, s_);   // a phase starts from zero sums
     const int small_max = compact_ ? tuning_.small_max : (int)kBucketMax[B_T8];
     const int64_t block_max = compact_ ? tuning_.block_max : lds_row_max(g.n, g.tw, tuning_);
     const int32_t *skip_gid = active_only && batch_ ? gid_ : nullptr;
@@ -2093,6 +2091,7 @@ void Sweeper::pass(const GraphView &g, int p, const SweepParams &prm, int64_t *e
         cs.st = st_.p;
         cs.active = active_.p;
         cs.ngraphs = ngraphs_;
+        cs.slots = gid_ ? nullptr : acc_.p;
         if (tuning_.overlap && !side_) side_.reset(new SideStreams());
         cs.side = side_.get();
         compact_pass(g, cp, cs, p, prm, s_, t_);

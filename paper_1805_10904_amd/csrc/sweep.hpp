@@ -20,6 +20,13 @@ struct GraphView {
     int64_t tw = 0;
 };
 
+// A single graph's per-pass sums (I, movers, sum deg_C^2) are added by
+// thousands of workgroups; they go to kAccSlots counters a 128-byte line
+// apart (slot = workgroup index mod kAccSlots) instead of one address, where
+// device-scope atomics would queue, and the acceptance test sums the slots.
+constexpr int kAccSlots = 256;
+constexpr int kAccStride = 16;   // 64-bit words per slot
+
 // Device-resident control block of one phase of one graph.
 struct PhaseState {
     unsigned long long acc_I;   // sum of e_{i->c_i} (loops included) of the labelling read by the pass
@@ -139,6 +146,7 @@ struct CompactState {
                                    // the commit's workgroup arrivals (0 between launches)
     int64_t ngraphs = 1;
     SideStreams *side = nullptr;   // optional: streams for the one-workgroup rows and the hubs
+    unsigned long long *slots = nullptr;   // one graph: the pass's sums by slot (zero between passes)
 };
 
 // Longest row a level of n vertices and total weight tw sweeps from LDS

@@ -124,8 +124,16 @@ __device__ __forceinline__ void span_add(const SpanSums &sp, unsigned long long 
 }
 
 __device__ __forceinline__ void span_flush(const SpanSums &sp, unsigned long long (*acc)[2], PhaseState *st,
-                                           int field0, int field1) {
+                                           int field0, int field1, unsigned long long *slots) {
     __syncthreads();
+    if (slots) {   // one graph: the workgroup's slot (fields 0, 1, 2 as in PhaseState)
+        if (threadIdx.x == 0) {
+            unsigned long long *sl = slots + (blockIdx.x & (kAccSlots - 1)) * kAccStride;
+            if (field0 >= 0 && acc[0][0]) atomicAdd(sl + field0, acc[0][0]);
+            if (field1 >= 0 && acc[0][1]) atomicAdd(sl + field1, acc[0][1]);
+        }
+        return;
+    }
     if (sp.span <= kSpan && (int)threadIdx.x < sp.span) {
         const int g = sp.g_lo + threadIdx.x;
         const int fs[2] = {field0, field1};
@@ -184,7 +192,7 @@ __global__ void k_cpt_expand(const uint64_t *__restrict__ ds, const uint32_t *__
 template <int TILE>
 __global__ __launch_bounds__(256) void k_cpt_publish(const uint64_t *__restrict__ ds, const int32_t *__restrict__ c,
                                                      uint64_t *vw, const int32_t *__restrict__ gid, PhaseState *st,
-                                                     int64_t n, unsigned int *active_zero) {
+                                                     int64_t n, unsigned int *active_zero, unsigned long long *slots) {
     __shared__ unsigned long long acc[kSpan][2];
     __shared__ int s_glo, s_span;
     if (active_zero && blockIdx.x == 0 && threadIdx.x == 0) *active_zero = 0;
@@ -212,7 +220,7 @@ __global__ __launch_bounds__(256) void k_cpt_publish(const uint64_t *__restrict_
         vw[v] = vw_make(cv, ds[cv]);
     }
     if (gcur >= 0) span_add(sp, acc, 1, gcur, sum, st, 2);
-    span_flush(sp, acc, st, -1, 2);
+    span_flush(sp, acc, st, -1, 2, slots);
 }
 
 // ------------------------------------------------------------- acceptance --
@@ -241,14 +249,12 @@ __device__ __forceinline__ bool cpt_gain_passes(i128 qn, i128 qp, int64_t num, i
 // acceptance test of sweep p-1 against the last kept labelling.  acc_I and
 // moved are read with agent-scope atomic loads: the commit's workgroups on
 // other XCDs added to them in the same launch.
-__device__ __forceinline__ void cpt_finalize_graph(PhaseState *st, const int64_t *__restrict__ tw, int64_t g,
-                                                   int64_t theta_num, int64_t theta_den, int32_t max_sweeps,
-                                                   int32_t p, unsigned int *active) {
+__device__ __forceinline__ void cpt_finalize_sums(PhaseState *st, const int64_t *__restrict__ tw, int64_t g,
+                                                  unsigned long long acc_i, unsigned long long moved,
+                                                  unsigned long long s_acc, int64_t theta_num, int64_t theta_den,
+                                                  int32_t max_sweeps, int32_t p, unsigned int *active) {
     PhaseState &s = st[g];
-    if (s.done) return;
-    const unsigned long long acc_i = __hip_atomic_load(&s.acc_I, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned long long moved = __hip_atomic_load(&s.moved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const i128 q = (i128)tw[g] * (i128)acc_i - (i128)s.s_acc;
+    const i128 q = (i128)tw[g] * (i128)acc_i - (i128)s_acc;
     s.pass = p;
     s.q_last[0] = (uint64_t)q;
     s.q_last[1] = (uint64_t)(int64_t)(q >> 64);
@@ -282,9 +288,51 @@ __device__ __forceinline__ void cpt_finalize_graph(PhaseState *st, const int64_t
     if (!s.done) atomicAdd(active, 1u);
 }
 
-// One thread per graph (passes over levels without vertices).
+__device__ __forceinline__ void cpt_finalize_graph(PhaseState *st, const int64_t *__restrict__ tw, int64_t g,
+                                                   int64_t theta_num, int64_t theta_den, int32_t max_sweeps,
+                                                   int32_t p, unsigned int *active) {
+    PhaseState &s = st[g];
+    if (s.done) return;
+    const unsigned long long acc_i = __hip_atomic_load(&s.acc_I, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long moved = __hip_atomic_load(&s.moved, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    cpt_finalize_sums(st, tw, g, acc_i, moved, s.s_acc, theta_num, theta_den, max_sweeps, p, active);
+}
+
+// One graph's sums from its slots (called by all 256 threads of a
+// workgroup): thread t reads slot t with agent-scope atomic loads (the
+// commit's workgroups on other XCDs added to them in the same launch) and
+// clears it for the next pass; thread 0 then runs the test.
+__device__ __forceinline__ void cpt_finalize_slots(PhaseState *st, const int64_t *__restrict__ tw,
+                                                   unsigned long long *slots, int64_t theta_num,
+                                                   int64_t theta_den, int32_t max_sweeps, int32_t p,
+                                                   unsigned int *active) {
+    static_assert(kAccSlots == 256, "one slot per thread");
+    __shared__ unsigned long long r[4][3];
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    unsigned long long v[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        v[k] = __hip_atomic_load(slots + t * kAccStride + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        slots[t * kAccStride + k] = 0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[k] += (unsigned long long)__shfl_xor((long long)v[k], off);
+        if (lane == 0) r[wid][k] = v[k];
+    }
+    __syncthreads();
+    if (t != 0 || st[0].done) return;
+    cpt_finalize_sums(st, tw, 0, r[0][0] + r[1][0] + r[2][0] + r[3][0], r[0][1] + r[1][1] + r[2][1] + r[3][1],
+                      r[0][2] + r[1][2] + r[2][2] + r[3][2], theta_num, theta_den, max_sweeps, p, active);
+}
+
+// One thread per graph (passes over levels without vertices), or, for one
+// graph with slots, one workgroup summing them.
 __global__ void k_cpt_finalize(PhaseState *st, const int64_t *__restrict__ tw, int64_t ngraphs, int64_t theta_num,
-                               int64_t theta_den, int32_t max_sweeps, int32_t p, unsigned int *active) {
+                               int64_t theta_den, int32_t max_sweeps, int32_t p, unsigned int *active,
+                               unsigned long long *slots) {
+    if (slots) {
+        cpt_finalize_slots(st, tw, slots, theta_num, theta_den, max_sweeps, p, active);
+        return;
+    }
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g < ngraphs) cpt_finalize_graph(st, tw, g, theta_num, theta_den, max_sweeps, p, active);
 }
@@ -338,6 +386,7 @@ struct FinalizeArgs {
     int64_t ngraphs, theta_num, theta_den;
     int32_t max_sweeps, p;
     unsigned int *active, *arrive;
+    unsigned long long *slots;   // one graph: the pass's sums by slot
 };
 
 template <int TILE>
@@ -395,7 +444,7 @@ __global__ __launch_bounds__(256) void k_cpt_commit(const int32_t *__restrict__ 
     // the pass's sums go out first (after a barrier: the table is complete
     // too), so a workgroup's arrival waits for them and not for the degree
     // updates, which only the next pass reads
-    span_flush(sp, acc, st, 0, 1);
+    span_flush(sp, acc, st, 0, 1, fa.slots);
     __shared__ int s_last;
     if (fa.arrive) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -411,8 +460,11 @@ __global__ __launch_bounds__(256) void k_cpt_commit(const int32_t *__restrict__ 
     }
     if (!s_last) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    for (int64_t g = threadIdx.x; g < fa.ngraphs; g += 256)
-        cpt_finalize_graph(st, fa.tw, g, fa.theta_num, fa.theta_den, fa.max_sweeps, fa.p, fa.active);
+    if (fa.slots)
+        cpt_finalize_slots(st, fa.tw, fa.slots, fa.theta_num, fa.theta_den, fa.max_sweeps, fa.p, fa.active);
+    else
+        for (int64_t g = threadIdx.x; g < fa.ngraphs; g += 256)
+            cpt_finalize_graph(st, fa.tw, g, fa.theta_num, fa.theta_den, fa.max_sweeps, fa.p, fa.active);
     if (threadIdx.x == 0) atomicExch(fa.arrive, 0u);
 }
 
@@ -2046,11 +2098,14 @@ void compact_pass(const GraphView &g, const CompactPass &cp, const CompactState 
         TimedLaunch tl(t, TG_SWEEP, "k_cpt_publish", (double)g.n * 28);
         const unsigned gb = grid_for(g.n, tile);
         if (tile == 2048)
-            tl.launch(k_cpt_publish<2048>, gb, 256, 0, s, cs.ds, cs.c_cur, cs.vw, cs.gid, cs.st, g.n, cs.active + (p & 1));
+            tl.launch(k_cpt_publish<2048>, gb, 256, 0, s, cs.ds, cs.c_cur, cs.vw, cs.gid, cs.st, g.n, cs.active + (p & 1),
+                      cs.slots);
         else if (tile == 1024)
-            tl.launch(k_cpt_publish<1024>, gb, 256, 0, s, cs.ds, cs.c_cur, cs.vw, cs.gid, cs.st, g.n, cs.active + (p & 1));
+            tl.launch(k_cpt_publish<1024>, gb, 256, 0, s, cs.ds, cs.c_cur, cs.vw, cs.gid, cs.st, g.n, cs.active + (p & 1),
+                      cs.slots);
         else
-            tl.launch(k_cpt_publish<512>, gb, 256, 0, s, cs.ds, cs.c_cur, cs.vw, cs.gid, cs.st, g.n, cs.active + (p & 1));
+            tl.launch(k_cpt_publish<512>, gb, 256, 0, s, cs.ds, cs.c_cur, cs.vw, cs.gid, cs.st, g.n, cs.active + (p & 1),
+                      cs.slots);
         LV_LAUNCHED("k_cpt_publish");
     }
     CArgs a{g.row_ptr, g.col, g.w, cs.c_cur, cs.c_nxt, g.delta, cs.vw, cs.ds, cs.gid, cs.tw, cs.st, cs.es, prm.singlet,
@@ -2064,7 +2119,7 @@ void compact_pass(const GraphView &g, const CompactPass &cp, const CompactState 
     if (g.n > 0) {
         // a small single graph's acceptance test runs in the last workgroup to finish
         const FinalizeArgs fa{cs.tw, cs.ngraphs, prm.theta_num, prm.theta_den, prm.max_sweeps, p,
-                              cs.active + (p & 1), fused ? cs.active + 2 : nullptr};
+                              cs.active + (p & 1), fused ? cs.active + 2 : nullptr, cs.slots};
         TimedLaunch tl(t, TG_SWEEP, "k_cpt_commit", (double)g.n * 12);
         const unsigned gb = grid_for(g.n, tile);
         if (tile == 2048)
@@ -2077,8 +2132,8 @@ void compact_pass(const GraphView &g, const CompactPass &cp, const CompactState 
     }
     if (!fused) {
         TimedLaunch tl(t, TG_SWEEP, "k_cpt_finalize", 0.0);
-        tl.launch(k_cpt_finalize, grid_for(cs.ngraphs, 256), 256, 0, s, cs.st, cs.tw, cs.ngraphs, prm.theta_num,
-                  prm.theta_den, prm.max_sweeps, p, cs.active + (p & 1));
+        tl.launch(k_cpt_finalize, cs.slots ? 1u : grid_for(cs.ngraphs, 256), 256, 0, s, cs.st, cs.tw, cs.ngraphs,
+                  prm.theta_num, prm.theta_den, prm.max_sweeps, p, cs.active + (p & 1), cs.slots);
         LV_LAUNCHED("k_cpt_finalize");
     }
 }
