@@ -282,6 +282,39 @@ def test_heavy_hubs(ctx, scale):
     G.destroy()
 
 
+@pytest.mark.parametrize("scale,kind", [(3676, "64-bit scores"), (8000, "128-bit scores")])
+def test_general_score_width(scale, kind):
+    """Levels with 2W above the 64-bit range of TW^2 score in 64 bits while
+    TW times the level's largest delta stays below 2^62 (every product of a
+    score is at most that), else in 128 bits.  The hub graph with weights x
+    3676 has TW = 3.10e9 and TW max delta = 0.39 * 2^62; x 8000 puts it past
+    2^62.  The level log (LOUVAIN_LOG, read once per process, so in a child
+    process) names the width, and the results equal the oracle's."""
+    import os
+    import subprocess
+    here = os.path.dirname(os.path.abspath(__file__))
+    code = ("import sys; sys.path.insert(0, %r); sys.path.insert(0, %r)\n"
+            "import numpy as np, oracle, paper_1805_10904_amd as L\n"
+            "from test_gpu_parity import hub_graph\n"
+            "g = hub_graph(seed=11); ctx = L.Context(0)\n"
+            "w = g.w.astype(np.int64) * %d\n"
+            "G = ctx.graph_create(g.row_ptr, g.col, w)\n"
+            "r = ctx.run(G)\n"
+            "ref = oracle.louvain(g.row_ptr, g.col, w)\n"
+            "assert np.array_equal(r.labels, ref.labels) and r.q_int == ref.q_int\n"
+            "lm = ctx.local_move(G, None)\n"
+            "ref_lm = oracle.local_move(g.row_ptr, g.col, w, None)\n"
+            "assert np.array_equal(lm[0], ref_lm.labels) and np.array_equal(lm[1], ref_lm.deg)\n"
+            "assert np.array_equal(lm[2], ref_lm.e_own)\n"
+            "print('OK', flush=True)\n") % (os.path.dirname(here), here, scale)
+    _say(f"hub graph with weights x {scale} in a child process")
+    env = dict(os.environ, LOUVAIN_LOG="1")
+    p = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=240)
+    assert p.returncode == 0 and "OK" in p.stdout, p.stderr[-2000:]
+    lines = [ln for ln in p.stderr.splitlines() if ln.startswith("[louvain] level 0: ")]
+    assert lines and all(kind in ln for ln in lines), lines
+
+
 @pytest.mark.parametrize("shrink", [8, 64])
 def test_hub_bucket_spills(shrink):
     """Hubs are summed in buckets (compact levels, and levels with 2W >=
