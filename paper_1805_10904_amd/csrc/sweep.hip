@@ -1386,21 +1386,25 @@ __device__ __forceinline__ int bucket_of_vertex(const int64_t *__restrict__ rp, 
     return bucket_of(d, small_max, block_max);
 }
 
-// Largest delta_i of a level: per-thread maxima, a wavefront reduction and
-// one atomic per wavefront.
-constexpr int kDeltaMaxItems = 8;
+// Largest delta_i of a level: a grid of at most kDeltaMaxBlocks workgroups
+// strides over the vertices, each reduces its maxima (wavefront, then LDS)
+// and makes one atomic (one per wavefront queued about 30,000 atomics on the
+// one address at 2^24 vertices).
+constexpr int kDeltaMaxBlocks = 512;
 __global__ __launch_bounds__(256) void k_delta_max(const int64_t *__restrict__ delta, int64_t n,
                                                    unsigned long long *out) {
-    const int64_t base = (int64_t)blockIdx.x * 256 * kDeltaMaxItems + threadIdx.x;
+    __shared__ unsigned long long s_m[4];
     unsigned long long m = 0;
-#pragma unroll
-    for (int k = 0; k < kDeltaMaxItems; ++k) {
-        const int64_t v = base + (int64_t)k * 256;
-        if (v < n) m = max(m, (unsigned long long)delta[v]);
-    }
+    for (int64_t v = (int64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += (int64_t)gridDim.x * 256)
+        m = max(m, (unsigned long long)delta[v]);
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) m = max(m, (unsigned long long)__shfl_xor((long long)m, off));
-    if ((threadIdx.x & 63) == 0 && m) atomicMax(out, m);
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = max(max(s_m[0], s_m[1]), max(s_m[2], s_m[3]));
+        if (m) atomicMax(out, m);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_bucket_count(const int64_t *__restrict__ rp, int64_t n, int32_t *counts,
@@ -1593,7 +1597,8 @@ void Sweeper::plan_impl(const GraphView &g, bool active_only) {
     if (!compact_ && g.tw > kTwFastMax) {
         dmax_.reserve(1);
         fill<uint64_t>((uint64_t *)dmax_.p, 0, 1, s_);
-        k_delta_max<<<grid_for(g.n, 256 * kDeltaMaxItems), 256, 0, s_>>>(g.delta, g.n, dmax_.p);
+        const unsigned db = grid_for(g.n, 256) < (unsigned)kDeltaMaxBlocks ? grid_for(g.n, 256) : (unsigned)kDeltaMaxBlocks;
+        k_delta_max<<<db, 256, 0, s_>>>(g.delta, g.n, dmax_.p);
         LV_LAUNCHED("k_delta_max");
         hdmax = rb.add(dmax_.p);
     }
