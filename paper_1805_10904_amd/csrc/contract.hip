@@ -316,8 +316,9 @@ static int bits_for(int64_t k) {
 // 4. row pointers are the scan of the distinct counts, and a last pass packs
 //    the segments into the output CSR.
 
-constexpr int kSegTile = 512;     // vertices per workgroup in the grouping kernels
-constexpr int kSegBits = 11;      // their LDS tables: 2^11 slots for at most 512 keys
+constexpr int kSegTile = 2048;    // vertices per workgroup in the grouping kernels (a community spread over
+                                  // the level takes one atomic per tile: larger tiles, fewer on its address)
+constexpr int kSegBits = 12;      // their LDS tables: 2^12 slots for at most 2,048 keys
 constexpr int kChunk = 1024;      // grouped entries per aggregation workgroup (nominal)
 constexpr int kChunkSeg = 512;    // segments of at most this many entries never cross a chunk boundary
 constexpr int kChunkLen = kChunk + kChunkSeg;   // longest chunk
