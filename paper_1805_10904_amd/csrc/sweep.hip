@@ -1139,8 +1139,8 @@ constexpr int kQsumTile = 2048;
 // mover); an update that finds no slot within kGenCommitProbe probes goes to
 // HBM directly.  Integer sums (modulo 2^64 for the degrees), so the result
 // does not depend on their order.
-constexpr int kCommitTile = 1024;
-constexpr int kCommitBits = 11;       // 2 slots per vertex of the tile
+constexpr int kCommitTile = 2048;
+constexpr int kCommitBits = 12;       // 2 slots per vertex of the tile
 constexpr int kGenCommitProbe = 32;
 
 __device__ __forceinline__ bool gen_commit_insert(int32_t *key, unsigned long long *dsum, int *ssum, int32_t k,
