@@ -1761,84 +1761,13 @@ __global__ __launch_bounds__(256) void k_cpt_hub_bucket(CArgs a, CHub hm, unsign
     }
 }
 
-// Workgroup per kHubScan table slots: partial best (order key, label,
-// singleton flag) and own e; clears the slots for the next pass.  The
-// community's degree and size come from its community word.
-__global__ __launch_bounds__(256) void k_cpt_hub_scan(CArgs a, CHub hm, unsigned long long *gtab, uint64_t *part) {
-    if (single_done(a.gid, a.st)) return;
-    __shared__ int64_t s_h;
-    __shared__ int s_skip;
-    __shared__ unsigned long long r_ok[4];
-    __shared__ uint32_t r_lf[4], r_e[4];
-    const int t = threadIdx.x;
-    if (t == 0) {
-        s_h = hm.scan_hub[blockIdx.x];
-        // a hub summed in buckets has nothing in its table unless one spilled
-        s_skip = hm.bkt_off[s_h + 1] > hm.bkt_off[s_h] && hm.spill[s_h] == 0u;
-        if (s_skip) {
-            uint64_t *p = part + 4 * (int64_t)blockIdx.x;
-            p[0] = 0;
-            p[1] = (uint64_t)(0xffffffffu >> 1) | (1ull << 32);
-            p[2] = 0;
-            p[3] = 0;
-        }
-    }
-    __syncthreads();
-    if (s_skip) return;
-    const int64_t h = s_h;
-    const int32_t v = hm.v[h];
-    const int g = graph_of(a.gid, v);
-    const int32_t ci = vw_label(a.vw[v]);
-    // TW, delta_i, deg_C and e_{i->C} are below 2^31: 32-bit operands
-    const uint32_t di = (uint32_t)a.delta[v];
-    const uint32_t tw = (uint32_t)a.tw[g];
-    const int64_t base = hm.tab_off[h] + ((int64_t)blockIdx.x - hm.scan_off[h]) * kHubScan;
-    unsigned long long bok = 0;
-    uint32_t blf = 0xffffffffu;
-    uint32_t e_own = 0;
-#pragma unroll
-    for (int q = 0; q < kHubScan / 256; ++q) {
-        const int64_t x = base + q * 256 + t;
-        const unsigned long long wd = gtab[x];
-        if (wd == 0) continue;
-        gtab[x] = 0;
-        const int32_t k = (int32_t)(wd >> 32) - 1;
-        const uint32_t e = (uint32_t)wd;
-        if (k == ci) {
-            e_own += e;
-            continue;
-        }
-        const uint64_t dsk = a.ds[k];
-        const unsigned long long ok = ((uint64_t)tw * e - (uint64_t)di * (uint32_t)dsk) ^ 0x8000000000000000ull;
-        const uint32_t lf = ((uint32_t)k << 1) | ((dsk >> 32) == 1 ? 1u : 0u);
-        best_take(bok, blf, (uint32_t)ok, (uint32_t)(ok >> 32), lf);
-    }
-    group_best(bok, blf, 64);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) e_own += __shfl_xor(e_own, off);
-    const int lane = t & 63, wid = t >> 6;
-    if (lane == 0) {
-        r_ok[wid] = bok;
-        r_lf[wid] = blf;
-        r_e[wid] = e_own;
-    }
-    __syncthreads();
-    if (t == 0) {
-        for (int w = 1; w < 4; ++w) {
-            best_take(bok, blf, (uint32_t)r_ok[w], (uint32_t)(r_ok[w] >> 32), r_lf[w]);
-            e_own += r_e[w];
-        }
-        uint64_t *p = part + 4 * (int64_t)blockIdx.x;
-        p[0] = bok;
-        p[1] = (uint64_t)(blf >> 1) | ((uint64_t)(blf & 1u) << 32);
-        p[2] = e_own;
-        p[3] = 0;
-    }
-}
-
-// Wavefront per hub: combine the scan partials and decide.
+// Wavefront per hub: combine the partials and decide.  On the first pass
+// from singletons the partials are the chunks'; later they are the
+// buckets', and a hub whose bucket spilled (or that has no bucket) also
+// has pairs in its HBM table, which the wavefront scans and clears here
+// (spills are rare, so no launch is spent on the tables of the others).
 __global__ __launch_bounds__(256) void k_cpt_hub_decide(CArgs a, CHub hm, const uint64_t *part,
-                                                        unsigned long long *hub_loop) {
+                                                        unsigned long long *hub_loop, unsigned long long *gtab) {
     if (single_done(a.gid, a.st)) return;
     const int lane = threadIdx.x & 63;
     const int64_t h = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -1849,9 +1778,6 @@ __global__ __launch_bounds__(256) void k_cpt_hub_decide(CArgs a, CHub hm, const 
     unsigned long long bok = 0;
     int32_t bl = 0x7fffffff, bf = 0;
     uint64_t e_own = 0;
-    // partials: one per scan workgroup, or one per chunk on the first pass
-    // from singletons
-    const int64_t *range = a.first ? hm.chunk_off : hm.scan_off;
     auto take = [&](const uint64_t *p) {
         const unsigned long long ok = p[0];
         const int32_t l = (int32_t)(uint32_t)p[1];
@@ -1862,9 +1788,37 @@ __global__ __launch_bounds__(256) void k_cpt_hub_decide(CArgs a, CHub hm, const 
         }
         e_own += p[2];
     };
-    for (int64_t b = range[h] + lane; b < range[h + 1]; b += 64) take(part + 4 * b);
-    if (!a.first)   // and the buckets' partials
+    if (a.first) {
+        for (int64_t b = hm.chunk_off[h] + lane; b < hm.chunk_off[h + 1]; b += 64) take(part + 4 * b);
+    } else {
         for (int64_t b = hm.bkt_off[h] + lane; b < hm.bkt_off[h + 1]; b += 64) take(hm.bpart + 4 * b);
+        if (hm.bkt_off[h + 1] == hm.bkt_off[h] || hm.spill[h] != 0u) {
+            // the table's pairs: (label + 1) << 32 | e per slot, 0 = empty;
+            // TW, delta_i, deg_C and e_{i->C} are below 2^31 (32-bit operands)
+            const int32_t ci = vw_label(a.vw[v]);
+            const uint32_t di = (uint32_t)a.delta[v];
+            const uint32_t tw = (uint32_t)a.tw[g];
+            const int64_t t0 = hm.tab_off[h], t1 = t0 + hm.tab_size[h];
+            for (int64_t x = t0 + lane; x < t1; x += 64) {
+                const unsigned long long wd = gtab[x];
+                if (wd == 0) continue;
+                gtab[x] = 0;
+                const int32_t k = (int32_t)(wd >> 32) - 1;
+                const uint32_t e = (uint32_t)wd;
+                if (k == ci) {
+                    e_own += e;
+                    continue;
+                }
+                const uint64_t dsk = a.ds[k];
+                const unsigned long long ok = ((uint64_t)tw * e - (uint64_t)di * (uint32_t)dsk) ^ 0x8000000000000000ull;
+                if (ok > bok || (ok == bok && k < bl)) {
+                    bok = ok;
+                    bl = k;
+                    bf = (dsk >> 32) == 1 ? 1 : 0;
+                }
+            }
+        }
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
         const unsigned long long ook = __shfl_xor(bok, off);
@@ -2077,14 +2031,9 @@ static void compact_sweeps(const CArgs &a, const CompactPass &cp, hipStream_t s,
             tl.launch(k_cpt_hub_bucket, (unsigned)cp.hub_buckets, 256, 0, s2, a, hm, cp.hval);
             LV_LAUNCHED("k_cpt_hub_bucket");
         }
-        if (!a.first) {
-            TimedLaunch tl(t, TG_SWEEP, "k_cpt_hub_scan", (double)cp.hub_scans * kHubScan * 16.0);
-            tl.launch(k_cpt_hub_scan, (unsigned)cp.hub_scans, 256, 0, s2, a, hm, cp.hval, cp.hpart);
-            LV_LAUNCHED("k_cpt_hub_scan");
-        }
         {
-            TimedLaunch tl(t, TG_SWEEP, "k_cpt_hub_decide", (double)cp.hubs * vb + (double)cp.hub_scans * 32.0);
-            tl.launch(k_cpt_hub_decide, grid_for(cp.hubs, 4), 256, 0, s2, a, hm, cp.hpart, cp.hloop);
+            TimedLaunch tl(t, TG_SWEEP, "k_cpt_hub_decide", (double)cp.hubs * vb + (double)cp.hub_buckets * 32.0);
+            tl.launch(k_cpt_hub_decide, grid_for(cp.hubs, 4), 256, 0, s2, a, hm, cp.hpart, cp.hloop, cp.hval);
             LV_LAUNCHED("k_cpt_hub_decide");
         }
     }
