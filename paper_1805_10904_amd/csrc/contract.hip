@@ -418,17 +418,27 @@ __global__ __launch_bounds__(256) void k_seg_scatter(const int64_t *__restrict__
                                                      const int32_t *__restrict__ newlab,
                                                      const int64_t *__restrict__ start, int32_t *tcol, int64_t *tw) {
     __shared__ int64_t srange[2];
+    __shared__ int64_t s_rp[kRowStage];
     const int64_t base = (int64_t)blockIdx.x * kEntriesPerBlock;
     block_row_range(rp, n, nnz, base, kEntriesPerBlock, srange);
     const int64_t rlo = srange[0], rhi = srange[1];
+    const bool staged = stage_rows(rp, rlo, rhi, s_rp);
 #pragma unroll 1
     for (int k = 0; k < kEntryItems; ++k) {
         const int64_t e = base + k * 256 + threadIdx.x;
         if (e >= nnz) break;
-        const int64_t r = row_of_entry(rp, rlo, rhi, e);
+        int64_t r, r0;   // the entry's row and its first entry
+        if (staged) {
+            const int i = row_of_entry_lds(s_rp, (int)(rhi - rlo), e);
+            r = rlo + i;
+            r0 = s_rp[i];
+        } else {
+            r = row_of_entry(rp, rlo, rhi, e);
+            r0 = rp[r];
+        }
         const int32_t a = newlab[r];
         if (a < 0) continue;
-        const int64_t dst = start[r] + (e - rp[r]);
+        const int64_t dst = start[r] + (e - r0);
         tcol[dst] = newlab[col[e]];
         tw[dst] = (int64_t)w[e];
     }
@@ -1102,12 +1112,22 @@ __global__ __launch_bounds__(256) void k_seg_pack(const int64_t *__restrict__ rp
     if (base >= m_new) return;   // uniform over the workgroup
     block_row_range(rp, n_new, m_new, base, kEntriesPerBlock, srange);
     const int64_t rlo = srange[0], rhi = srange[1];
+    __shared__ int64_t s_rp[kRowStage];
+    const bool staged = stage_rows(rp, rlo, rhi, s_rp);
 #pragma unroll 1
     for (int k = 0; k < kEntryItems; ++k) {
         const int64_t u = base + k * 256 + threadIdx.x;
         if (u >= m_new) break;
-        const int64_t a = row_of_entry(rp, rlo, rhi, u);
-        const int64_t src = off[a] + (u - rp[a]);
+        int64_t a, a0;   // the entry's row and its first entry
+        if (staged) {
+            const int i = row_of_entry_lds(s_rp, (int)(rhi - rlo), u);
+            a = rlo + i;
+            a0 = s_rp[i];
+        } else {
+            a = row_of_entry(rp, rlo, rhi, u);
+            a0 = rp[a];
+        }
+        const int64_t src = off[a] + (u - a0);
         col_out[u] = tcol[src];
         w_out[u] = (WO)tw[src];
     }

@@ -255,10 +255,12 @@ __global__ __launch_bounds__(256) void k_ingest_entries(const int64_t *__restric
                                                         const W *__restrict__ w, int64_t *delta,
                                                         uint64_t *tw_partials, int *bad, int check_sym) {
     __shared__ int64_t srange[2];
+    __shared__ int64_t s_rp[kRowStage];
     const int t = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * kEntriesPerBlock;
     block_row_range(rp, n, nnz, base, kEntriesPerBlock, srange);
     const int64_t rlo = srange[0], rhi = srange[1];
+    const bool staged = stage_rows(rp, rlo, rhi, s_rp);
     int errs = 0;
     i128 tw = 0;
 #pragma unroll 1
@@ -267,12 +269,20 @@ __global__ __launch_bounds__(256) void k_ingest_entries(const int64_t *__restric
         const bool valid = e < nnz;
         int64_t r = 0, wv = 0;
         if (valid) {
-            r = row_of_entry(rp, rlo, rhi, e);
+            int64_t r_end;   // row_ptr[r + 1]
+            if (staged) {
+                const int i = row_of_entry_lds(s_rp, (int)(rhi - rlo), e);
+                r = rlo + i;
+                r_end = s_rp[i + 1];
+            } else {
+                r = row_of_entry(rp, rlo, rhi, e);
+                r_end = rp[r + 1];
+            }
             const int32_t j = col[e];
             const int64_t x = (int64_t)w[e];
             if (j < 0 || (int64_t)j >= n) errs |= BAD_COL;
             if (x < 1) errs |= BAD_WEIGHT;
-            if (e + 1 < rp[r + 1] && col[e + 1] <= j) errs |= BAD_ORDER;
+            if (e + 1 < r_end && col[e + 1] <= j) errs |= BAD_ORDER;
             wv = x;
             tw += (i128)x;
             if (check_sym && j >= 0 && (int64_t)j < n) {

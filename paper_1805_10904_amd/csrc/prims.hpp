@@ -143,6 +143,33 @@ __device__ __forceinline__ int64_t row_of_entry(const int64_t *__restrict__ row_
     return lo;
 }
 
+// The same search over a block's slice of row_ptr staged in LDS: s_rp[i] =
+// row_ptr[rlo + i] for i <= hi; returns the index i (row rlo + i).
+__device__ __forceinline__ int row_of_entry_lds(const int64_t *s_rp, int hi, int64_t e) {
+    int lo = 0;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_rp[mid] <= e) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Entry-parallel kernels find each entry's row in LDS: row_ptr[rlo .. rhi + 1]
+// of the workgroup's rows is staged into s_rp (kRowStage words) when it fits
+// (a workgroup's entries span at most kEntriesPerBlock non-empty rows; long
+// runs of empty rows do not fit and keep the search in memory, which the
+// caller does when this returns false).  rhi + 1 <= n, so every word read
+// exists.  Ends with a workgroup barrier; all threads must call it.
+constexpr int kRowStage = 256 * 8 + 2;
+__device__ __forceinline__ bool stage_rows(const int64_t *__restrict__ row_ptr, int64_t rlo, int64_t rhi,
+                                           int64_t *s_rp) {
+    const bool fits = rhi - rlo + 2 <= kRowStage;
+    if (fits)
+        for (int64_t i = threadIdx.x; i <= rhi - rlo + 1; i += blockDim.x) s_rp[i] = row_ptr[rlo + i];
+    __syncthreads();
+    return fits;
+}
+
 // Largest r in [0, n) with a[r] <= x, for a nondecreasing with a[0] <= x,
 // searched by all 64 lanes of a converged wavefront (each round probes 64
 // positions at once, so about log64(n) dependent loads); every lane gets r.
@@ -201,5 +228,6 @@ __device__ __forceinline__ void seg_add_wave(int64_t *out, int64_t r, int64_t v,
 // CSR entries, item k of thread t is entry base + k*256 + t.
 constexpr int kEntryItems = 8;
 constexpr int kEntriesPerBlock = 256 * kEntryItems;
+static_assert(kRowStage == kEntriesPerBlock + 2, "row_ptr slice of one entry-parallel workgroup");
 
 }  // namespace lv
